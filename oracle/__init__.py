@@ -1,0 +1,158 @@
+"""Plain FP64 CPU oracle for the modified-Helmholtz layer-potential path.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke entry point and the
+CPU-baseline leg of the benchmark may import this package.  The HIP library
+never imports, links or calls it, and the two share no code.
+
+The arithmetic lives in ``mhlp_oracle.c`` (header comment there gives the
+definitions and the paper passages they follow); this module is the ctypes
+marshalling around it plus a small numpy MLP reference.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mhlp_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_D = ctypes.POINTER(ctypes.c_double)
+_I64 = ctypes.POINTER(ctypes.c_int64)
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99", "-D_GNU_SOURCE",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        L.orc_bessel_k01.argtypes = [ctypes.c_double, _D, _D]
+        L.orc_gauss_legendre.argtypes = [ctypes.c_int, _D, _D]
+        L.orc_panel_weights.argtypes = [_D, _D, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_double, ctypes.c_int, ctypes.c_int, _D]
+        L.orc_eval.argtypes = [_D, _D, ctypes.c_int64, _D, _D, ctypes.c_double, _D, _D, ctypes.c_int64, _I64,
+                               _D, _D, ctypes.c_int]
+        L.orc_assemble_onsurface.argtypes = [_D, _D, ctypes.c_int64, ctypes.c_double, _D, _D, ctypes.c_int]
+        L.orc_gmres.argtypes = [_D, ctypes.c_int64, _D, _D, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                ctypes.POINTER(ctypes.c_int), _D, ctypes.c_int]
+        L.orc_self_cell.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.orc_self_cell.restype = ctypes.c_double
+        L.orc_volume_eval.argtypes = [_D, _D, _D, _D, ctypes.c_int64, ctypes.c_double, ctypes.c_double, _I64,
+                                      ctypes.c_int64, _D, ctypes.c_int]
+        L.orc_max_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(_D)
+
+
+def _c(a, dt=np.float64):
+    return None if a is None else np.ascontiguousarray(a, dtype=dt)
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
+
+
+def bessel_k01(z):
+    """K0(z), K1(z) for z > 0 (scalar or array)."""
+    z = np.atleast_1d(np.asarray(z, dtype=np.float64))
+    k0 = np.empty_like(z)
+    k1 = np.empty_like(z)
+    a, b = ctypes.c_double(), ctypes.c_double()
+    for i, v in enumerate(z.ravel()):
+        lib().orc_bessel_k01(float(v), ctypes.byref(a), ctypes.byref(b))
+        k0.flat[i] = a.value
+        k1.flat[i] = b.value
+    return k0, k1
+
+
+def gauss_legendre(n):
+    t = np.empty(n)
+    w = np.empty(n)
+    lib().orc_gauss_legendre(n, _p(t), _p(w))
+    return t, w
+
+
+def panel_weights(x, y, panel, tx, ty, alpha, self_node=-1, mode=0):
+    """Exact (mode 1), direct (mode 2) or automatic (0) SLP/DLP weights of one
+    target against one panel: returns (W_slp[16], W_dlp[16])."""
+    x, y = _c(x), _c(y)
+    W = np.empty(32)
+    lib().orc_panel_weights(_p(x), _p(y), int(panel), float(tx), float(ty), float(alpha), int(self_node),
+                            int(mode), _p(W))
+    return W[:16].copy(), W[16:].copy()
+
+
+def eval_potentials(x, y, alpha, tx, ty, sigma=None, mu=None, tgt_node=None, nthreads=0):
+    """SLP of sigma and DLP of mu at the targets (exact near-panel integrals)."""
+    x, y, tx, ty = _c(x), _c(y), _c(tx), _c(ty)
+    sigma, mu = _c(sigma), _c(mu)
+    m = tx.size
+    us = np.zeros(m) if sigma is not None else None
+    ud = np.zeros(m) if mu is not None else None
+    tn = None if tgt_node is None else _c(tgt_node, np.int64)
+    rc = lib().orc_eval(_p(x), _p(y), x.size // 16, _p(sigma), _p(mu), float(alpha), _p(tx), _p(ty), m,
+                        None if tn is None else tn.ctypes.data_as(_I64), _p(us), _p(ud), int(nthreads))
+    if rc != 0:
+        raise RuntimeError(f"orc_eval failed: {rc}")
+    return us, ud
+
+
+def onsurface_matrices(x, y, alpha, want_slp=False, want_dlp=True, nthreads=0):
+    """Dense on-surface SLP and DLP (principal value, no 1/2 I) matrices."""
+    x, y = _c(x), _c(y)
+    n = x.size
+    S = np.empty((n, n)) if want_slp else None
+    D = np.empty((n, n)) if want_dlp else None
+    rc = lib().orc_assemble_onsurface(_p(x), _p(y), n // 16, float(alpha), _p(S), _p(D), int(nthreads))
+    if rc != 0:
+        raise RuntimeError(f"orc_assemble_onsurface failed: {rc}")
+    return S, D
+
+
+def apply_bie(D, mu):
+    """(1/2 I + D) mu with the dense DLP matrix D."""
+    return 0.5 * mu + D @ mu
+
+
+def gmres(A, b, x0=None, tol=1e-10, restart=200, max_iter=1000, nthreads=0):
+    """Dense GMRES (MGS Arnoldi) on A x = b, judged by the true relative residual."""
+    A = _c(A)
+    b = _c(b)
+    n = b.size
+    x = np.zeros(n) if x0 is None else _c(x0).copy()
+    it = ctypes.c_int()
+    rr = ctypes.c_double()
+    rc = lib().orc_gmres(_p(A), n, _p(b), _p(x), float(tol), int(restart), int(max_iter), ctypes.byref(it),
+                         ctypes.byref(rr), int(nthreads))
+    return x, dict(iters=it.value, relres=rr.value, converged=(rc == 0))
+
+
+def self_cell(alpha, h):
+    return float(lib().orc_self_cell(float(alpha), float(h)))
+
+
+def volume_eval(x, y, w, f, alpha, h, idx, nthreads=0):
+    x, y, w, f = _c(x), _c(y), _c(w), _c(f)
+    idx = _c(idx, np.int64)
+    out = np.empty(idx.size)
+    lib().orc_volume_eval(_p(x), _p(y), _p(w), _p(f), x.size, float(alpha), float(h),
+                          idx.ctypes.data_as(_I64), idx.size, _p(out), int(nthreads))
+    return out

@@ -1,0 +1,302 @@
+"""Pins of the CPU oracle to facts the paper and the mathematics fix.
+
+Nothing here compares the oracle with itself: every expected value comes from a
+closed form (Graf's addition theorem on a circle), an identity (Green's
+representation, the jump relation, the Yukawa PDE), a textbook or library
+routine (mpmath Bessel functions, numpy Gauss-Legendre, LAPACK solve) or an
+independent brute-force quadrature.
+"""
+import math
+
+import mpmath as mp
+import numpy as np
+import pytest
+import scipy.integrate as si
+import scipy.special as sp
+
+import oracle
+from paper_1908_07392_amd import workloads as wl
+
+
+# ---------------------------------------------------------------------------
+# Bessel functions (App. C series + integral representation)
+# ---------------------------------------------------------------------------
+def test_bessel_k01_vs_mpmath():
+    mp.mp.dps = 40
+    zs = np.concatenate([np.logspace(-10, np.log10(700.0), 160), [1.999999, 2.0, 2.000001, 2.5]])
+    k0, k1 = oracle.bessel_k01(zs)
+    for z, a, b in zip(zs, k0, k1):
+        assert abs(a / float(mp.besselk(0, z)) - 1.0) < 2e-15, z
+        assert abs(b / float(mp.besselk(1, z)) - 1.0) < 2e-15, z
+
+
+def test_bessel_wronskian():
+    # DLMF 10.28.2: I0 K1 + I1 K0 = 1/z  (I from scipy, K from the oracle)
+    z = np.logspace(-6, 2, 200)
+    k0, k1 = oracle.bessel_k01(z)
+    w = sp.ive(0, z) * np.exp(z) * k1 + sp.ive(1, z) * np.exp(z) * k0
+    assert np.max(np.abs(w * z - 1.0)) < 5e-14
+
+
+def test_gauss_legendre_vs_numpy():
+    for n in (16, 32):
+        t, w = oracle.gauss_legendre(n)
+        T, W = np.polynomial.legendre.leggauss(n)
+        assert np.max(np.abs(t - T)) < 1e-15
+        assert np.max(np.abs(w - W)) < 2e-15
+
+
+# ---------------------------------------------------------------------------
+# Circle closed forms (Graf's addition theorem, DLMF 10.44.3)
+#   SLP of e^{in theta}:  R I_n(alpha r) K_n(alpha R) e^{in theta}, r <= R
+#   DLP (inward normal): -alpha R I_n(alpha r) K_n'(alpha R) e^{in theta}, r < R
+# ---------------------------------------------------------------------------
+def _circle_closed(coeffs, alpha, R, tx, ty):
+    r = np.hypot(tx, ty)
+    th = np.arctan2(ty, tx)
+    n = np.arange(len(coeffs))
+    E = np.exp(1j * np.outer(th, n))
+    In = sp.iv(n[None, :], alpha * r[:, None])
+    slp = np.real((E * R * In * sp.kv(n, alpha * R)) @ coeffs)
+    dlp = np.real((E * (-alpha * R) * In * sp.kvp(n, alpha * R)) @ coeffs)
+    return slp, dlp
+
+
+def test_circle_config1_closed_form():
+    c = wl.config1()
+    g = c["geom"]
+    us, ud = oracle.eval_potentials(g.x, g.y, c["alpha"], c["tx"], c["ty"], sigma=c["sigma"], mu=c["sigma"])
+    slp, dlp = _circle_closed(c["coeffs"], c["alpha"], 1.0, c["tx"], c["ty"])
+    assert np.max(np.abs(us - slp)) / np.max(np.abs(slp)) < 5e-14
+    assert np.max(np.abs(ud - dlp)) / np.max(np.abs(dlp)) < 5e-14
+
+
+def test_circle_very_near_targets_closed_form():
+    # targets 1e-3 .. 1e-9 inside the circle, at nodes and between nodes
+    R, alpha = 1.0, 10.0
+    g = wl.discretize(wl.Curve("circle", R=R), 24)
+    rng = np.random.default_rng(7)
+    coeffs = wl.random_fourier_coeffs(rng, 6)
+    sigma = wl.fourier_density(g.theta, coeffs)
+    th = np.concatenate([g.theta[[5, 40, 200]], [0.1234, 2.5, 4.4]])
+    tx, ty = [], []
+    for d in (1e-3, 1e-6, 1e-9):
+        tx.append((R - d) * np.cos(th))
+        ty.append((R - d) * np.sin(th))
+    tx, ty = np.concatenate(tx), np.concatenate(ty)
+    us, ud = oracle.eval_potentials(g.x, g.y, alpha, tx, ty, sigma=sigma, mu=sigma)
+    slp, dlp = _circle_closed(coeffs, alpha, R, tx, ty)
+    scale_s, scale_d = np.max(np.abs(slp)), np.max(np.abs(dlp))
+    assert np.max(np.abs(us - slp)) / scale_s < 1e-13
+    assert np.max(np.abs(ud - dlp)) / scale_d < 1e-12
+
+
+@pytest.mark.parametrize("alpha", [10.0, 300.0])
+def test_circle_onsurface_eigenvalues(alpha):
+    # (1/2 I + D) e^{in theta} = lambda_n e^{in theta}, lambda_n = -alpha R I_n K_n'(alpha R);
+    # S e^{in theta} = R I_n(alpha R) K_n(alpha R) e^{in theta}   (scaled Bessel for large alpha)
+    R = 1.3
+    g = wl.discretize(wl.Curve("circle", R=R), 32)
+    S, D = oracle.onsurface_matrices(g.x, g.y, alpha, want_slp=True, want_dlp=True)
+    x = alpha * R
+    for n in (0, 1, 5, 12):
+        v = np.cos(n * g.theta)
+        lam = x * sp.ive(n, x) * 0.5 * (sp.kve(n - 1, x) + sp.kve(n + 1, x))
+        s = R * sp.ive(n, x) * sp.kve(n, x)
+        assert np.max(np.abs(oracle.apply_bie(D, v) - lam * v)) < 1e-12 * lam
+        assert np.max(np.abs(S @ v - s * v)) < 1e-12 * max(s, 1e-3)
+        assert 0.5 < lam <= 1.0
+
+
+def test_jump_relation_circle():
+    # D[mu](x0 + eps n) -> 1/2 mu(x0) + D_pv[mu](x0) (interior limit, inward normal)
+    R, alpha = 1.0, 7.0
+    g = wl.discretize(wl.Curve("circle", R=R), 16)
+    mu = np.cos(3 * g.theta) + 0.3 * np.sin(g.theta)
+    _, D = oracle.onsurface_matrices(g.x, g.y, alpha)
+    on = oracle.apply_bie(D, mu)
+    nx, ny = g.normals
+    idx = np.array([3, 77, 130])
+    eps = 1e-9
+    _, ud = oracle.eval_potentials(g.x, g.y, alpha, g.x[idx] + eps * nx[idx], g.y[idx] + eps * ny[idx], mu=mu)
+    assert np.max(np.abs(ud - on[idx])) < 1e-7
+    # exterior limit differs by exactly mu
+    _, ue = oracle.eval_potentials(g.x, g.y, alpha, g.x[idx] - eps * nx[idx], g.y[idx] - eps * ny[idx], mu=mu)
+    assert np.max(np.abs((ud - ue) - mu[idx])) < 1e-7
+
+
+# ---------------------------------------------------------------------------
+# Green's representation on the starfish (paper's first test geometry)
+#   u = D[u] - S[du/dn]  in Omega,  0 outside (inward normal), for (Delta - alpha^2) u = 0
+# ---------------------------------------------------------------------------
+def test_green_identity_starfish():
+    alpha = 10.0
+    g = wl.discretize(wl.starfish_curve(), 128)
+    z0 = 2.0 * np.exp(0.3j)
+    dx, dy = g.x - z0.real, g.y - z0.imag
+    d = np.hypot(dx, dy)
+    u = sp.k0(alpha * d)
+    nx, ny = g.normals
+    dudn = -alpha * sp.k1(alpha * d) * (dx * nx + dy * ny) / d
+    # interior targets: deep, near a node, between nodes, very close
+    th = np.array([0.05, 1.0, 2.2, 3.9, 5.5])
+    curve = wl.starfish_curve()
+    zc, dzc, _ = curve.eval(th)
+    nrm = 1j * dzc / np.abs(dzc)
+    pts = [0.2 + 0.1j, -0.3 + 0.4j]
+    for dist in (1e-2, 1e-4, 1e-7):
+        pts.extend(zc + dist * nrm)
+    pts = np.asarray(pts)
+    us, ud = oracle.eval_potentials(g.x, g.y, alpha, pts.real, pts.imag, sigma=dudn, mu=u)
+    exact = sp.k0(alpha * np.abs(pts - z0))
+    assert np.max(np.abs(ud - us - exact)) / np.max(np.abs(u)) < 1e-11
+    # exterior points: the representation vanishes
+    ext = np.concatenate([zc - 1e-3 * nrm, [1.6 + 0.2j]])
+    us, ud = oracle.eval_potentials(g.x, g.y, alpha, ext.real, ext.imag, sigma=dudn, mu=u)
+    assert np.max(np.abs(ud - us)) / np.max(np.abs(u)) < 1e-11
+
+
+def test_yukawa_pde_finite_differences():
+    # (Delta - alpha^2) u = 0 for u = S[sigma] + D[mu] at interior points (4th-order stencil)
+    alpha = 10.0
+    g = wl.discretize(wl.starfish_curve(), 48)
+    rng = np.random.default_rng(3)
+    sigma = wl.fourier_density(g.theta, wl.random_fourier_coeffs(rng, 5))
+    mu = wl.fourier_density(g.theta, wl.random_fourier_coeffs(rng, 5))
+    h = 5e-3
+    pts = np.array([0.1 + 0.2j, -0.5 + 0.1j, 0.3 - 0.6j])
+    offs = [(0, 0)] + [(k * h, 0) for k in (-2, -1, 1, 2)] + [(0, k * h) for k in (-2, -1, 1, 2)]
+    for p in pts:
+        tx = np.array([p.real + o[0] for o in offs])
+        ty = np.array([p.imag + o[1] for o in offs])
+        us, ud = oracle.eval_potentials(g.x, g.y, alpha, tx, ty, sigma=sigma, mu=mu)
+        u = us + ud
+        c = np.array([-1.0, 16.0, 16.0, -1.0]) / (12 * h * h)
+        lap = c @ u[1:5] + c @ u[5:9] - 2 * 30.0 / (12 * h * h) * u[0]
+        assert abs(lap - alpha ** 2 * u[0]) < 1e-6 * alpha ** 2 * np.max(np.abs(u))
+
+
+# ---------------------------------------------------------------------------
+# Brute force on single panels of a non-circular curve
+# ---------------------------------------------------------------------------
+def _bruteforce_panel(x, y, tx, ty, alpha):
+    """Composite 20-point GL on a geometric mesh towards the closest point of the
+    degree-15 polynomial panel (numpy Legendre-basis interpolation; scipy Bessel)."""
+    leg = np.polynomial.legendre
+    t16, _ = leg.leggauss(16)
+    Vinv = np.linalg.inv(leg.legvander(t16, 15))
+    cx, cy = Vinv @ x, Vinv @ y
+    dcx, dcy = leg.legder(cx), leg.legder(cy)
+    tt = np.linspace(-1, 1, 20001)
+    t0 = tt[np.argmin(np.hypot(leg.legval(tt, cx) - tx, leg.legval(tt, cy) - ty))]
+    for _ in range(30):  # Newton on the distance to refine the closest point
+        px, py = leg.legval(t0, cx) - tx, leg.legval(t0, cy) - ty
+        dx, dy = leg.legval(t0, dcx), leg.legval(t0, dcy)
+        ddx, ddy = leg.legval(t0, leg.legder(dcx)), leg.legval(t0, leg.legder(dcy))
+        f = px * dx + py * dy
+        fp = dx * dx + dy * dy + px * ddx + py * ddy
+        t0 = float(np.clip(t0 - f / fp, -1, 1))
+    g = np.unique(np.concatenate([t0 + (1 - t0) * 0.5 ** np.arange(0, 50),
+                                  t0 - (1 + t0) * 0.5 ** np.arange(0, 50), np.linspace(-1, 1, 9)]))
+    g = g[(g >= -1) & (g <= 1)]
+    tg, wg = leg.leggauss(20)
+    Ws = np.zeros(16)
+    Wd = np.zeros(16)
+    for a, b in zip(g[:-1], g[1:]):
+        t = 0.5 * (a + b) + 0.5 * (b - a) * tg
+        w = 0.5 * (b - a) * wg
+        L = leg.legvander(t, 15) @ Vinv
+        px, py = leg.legval(t, cx), leg.legval(t, cy)
+        dx, dy = leg.legval(t, dcx), leg.legval(t, dcy)
+        r = np.hypot(px - tx, py - ty)
+        speed = np.hypot(dx, dy)
+        xmyn = (tx - px) * (-dy) + (ty - py) * dx
+        ks = sp.k0(alpha * r) / (2 * np.pi) * speed
+        kd = alpha * sp.k1(alpha * r) / (2 * np.pi * r) * xmyn
+        Ws += (L * (ks * w)[:, None]).sum(0)
+        Wd += (L * (kd * w)[:, None]).sum(0)
+    return Ws, Wd
+
+
+@pytest.mark.parametrize("dist", [0.3, 1e-2, 1e-4])
+def test_panel_weights_bruteforce(dist):
+    curve = wl.Curve("ellipse", a=1.3, b=0.7)
+    g = wl.discretize(curve, 12)
+    p = 4
+    sl = slice(16 * p, 16 * p + 16)
+    th = 0.5 * (g.theta[sl][6] + g.theta[sl][7])
+    z, dz, _ = curve.eval(th)
+    nrm = 1j * dz / abs(dz)
+    pt = z + dist * nrm
+    for alpha in (3.0, 40.0):
+        Ws, Wd = oracle.panel_weights(g.x, g.y, p, pt.real, pt.imag, alpha, mode=1)
+        Bs, Bd = _bruteforce_panel(g.x[sl], g.y[sl], pt.real, pt.imag, alpha)
+        assert np.max(np.abs(Ws - Bs)) < 1e-13 * max(1.0, np.max(np.abs(Bs)))
+        assert np.max(np.abs(Wd - Bd)) < 1e-12 * max(1.0, np.max(np.abs(Bd)))
+
+
+# ---------------------------------------------------------------------------
+# GMRES: closed-form modal solution on the circle; LAPACK on a starfish
+# ---------------------------------------------------------------------------
+def test_gmres_circle_modal():
+    R, alpha = 1.0, 10.0
+    g = wl.discretize(wl.Curve("circle", R=R), 16)
+    _, D = oracle.onsurface_matrices(g.x, g.y, alpha)
+    A = 0.5 * np.eye(g.n_nodes) + D
+    x = alpha * R
+
+    def lam(n):
+        return x * sp.ive(n, x) * 0.5 * (sp.kve(n - 1, x) + sp.kve(n + 1, x))
+
+    b = np.cos(3 * g.theta) + 0.5 * np.sin(7 * g.theta)
+    mu, info = oracle.gmres(A, b, tol=1e-12)
+    exact = np.cos(3 * g.theta) / lam(3) + 0.5 * np.sin(7 * g.theta) / lam(7)
+    assert info["converged"]
+    assert np.max(np.abs(mu - exact)) < 1e-11
+
+
+def test_gmres_vs_lapack_starfish():
+    alpha = 5.0
+    g = wl.discretize(wl.starfish_curve(), 24)
+    _, D = oracle.onsurface_matrices(g.x, g.y, alpha)
+    A = 0.5 * np.eye(g.n_nodes) + D
+    rng = np.random.default_rng(11)
+    b = rng.standard_normal(g.n_nodes)
+    mu, info = oracle.gmres(A, b, tol=1e-12)
+    ref = np.linalg.solve(A, b)
+    assert info["converged"] and info["relres"] <= 1e-12
+    assert np.max(np.abs(mu - ref)) < 1e-10 * np.max(np.abs(ref))
+
+
+# ---------------------------------------------------------------------------
+# Volume sum: self cell and all-pairs sum
+# ---------------------------------------------------------------------------
+def test_self_cell_vs_cartesian_quadrature():
+    alpha, h = 20.0, 3.0 / 255.0
+
+    def f(yy, xx):
+        return sp.k0(alpha * math.hypot(xx, yy)) / (2 * math.pi)
+
+    # one quadrant, log singularity at its corner
+    q, _ = si.dblquad(f, 0.0, h / 2, 0.0, h / 2, epsabs=1e-22, epsrel=1e-14)
+    assert abs(oracle.self_cell(alpha, h) - 4 * q) < 1e-13 * 4 * q
+
+
+def test_volume_sum_bruteforce():
+    n, alpha = 12, 20.0
+    gx = np.linspace(-1.5, 1.5, n)
+    h = gx[1] - gx[0]
+    X, Y = np.meshgrid(gx, gx)
+    w1 = np.full(n, h)
+    w1[[0, -1]] = h / 2
+    W = np.outer(w1, w1).ravel()
+    f = np.cos(X).ravel() + Y.ravel() ** 2
+    x, y = X.ravel(), Y.ravel()
+    idx = np.array([0, 5, 77, 143])
+    out = oracle.volume_eval(x, y, W, f, alpha, h, idx)
+    wc = oracle.self_cell(alpha, h)
+    for q, i in enumerate(idx):
+        r = np.hypot(x - x[i], y - y[i])
+        m = np.arange(x.size) != i
+        ref = np.sum(sp.k0(alpha * r[m]) / (2 * np.pi) * W[m] * f[m]) + W[i] / h ** 2 * wc * f[i]
+        assert abs(out[q] - ref) < 1e-14 * np.sum(np.abs(W * f))
