@@ -1,0 +1,139 @@
+/*
+ * mhlp.h -- C ABI of the modified-Helmholtz layer-potential library (gfx950).
+ *
+ * Computes, for a closed (possibly multiply connected) boundary discretised by
+ * composite 16-point Gauss-Legendre panels (af Klinteberg, Askham & Kropinski,
+ * "A fast integral equation method for the two-dimensional Navier-Stokes
+ * equations", Sec. 3.2), the Yukawa single- and double-layer potentials
+ *
+ *   S[sigma](x) = int_Gamma K0(alpha |x-y|)/(2 pi) sigma(y) dS_y
+ *   D[mu](x)    = int_Gamma alpha K1(alpha r) (x-y).n_y / (2 pi r) mu(y) dS_y,
+ *
+ * (K0/2pi is the Yukawa part of the paper's modified-biharmonic Green's
+ * function, Sec. 2 and App. B), with the near-field panel corrections of
+ * Sec. 4, the on-surface second-kind operator (1/2 I + D) of Sec. 3.2 (the
+ * jump relation of the paper's Lemma on jump conditions, inward normal) and
+ * GMRES for (1/2 I + D) mu = g (Sec. 3.2).
+ *
+ * Conventions
+ *  - Geometry: N = 16 * n_panels nodes, panel-major, local parameter t
+ *    ascending inside a panel; each curve is oriented with the domain on its
+ *    left, so n = i tau'/|tau'| points into the domain.
+ *  - All array pointers are DEVICE pointers owned by the caller unless marked
+ *    "host".  The library owns the opaque handles and their workspaces
+ *    (allocated at create, freed at destroy).
+ *  - `stream` is a hipStream_t passed as void*; all work is enqueued on it.
+ *    Calls return after enqueueing unless documented as synchronising.
+ *  - Every call returns an mhlp_status.  No exception crosses the ABI.  On
+ *    error mhlp_last_error() returns a thread-local message.  Inputs are
+ *    validated before anything is enqueued.
+ *  - Handles are bound to the device current at creation and are not safe
+ *    for concurrent use from several threads.
+ */
+#ifndef MHLP_H
+#define MHLP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mhlp_status;
+#define MHLP_OK 0
+#define MHLP_NOT_CONVERGED 1 /* soft: GMRES stopped before the tolerance   */
+#define MHLP_INVALID_ARG (-1)
+#define MHLP_HIP_ERROR (-2)
+#define MHLP_UNSUPPORTED (-3)
+#define MHLP_NO_MEMORY (-4)
+
+/* Arithmetic of the far-field direct sum.  Near-field corrections, the
+   identity term and GMRES orthogonalisation are FP64 in both modes. */
+#define MHLP_FP64 0
+#define MHLP_MIXED 1 /* FP32 far field with compensated accumulation */
+
+typedef struct mhlp_geometry mhlp_geometry;
+typedef struct mhlp_plan mhlp_plan;
+
+/* Near-field parameters (Sec. 4.5).  Zero fields take the paper's values. */
+typedef struct {
+    double near_factor; /* candidate panels: some node within near_factor*h   (1.2)      */
+    double rho_direct;  /* Bernstein radius beyond which 16-point GL is used  (3.5)      */
+    double rho_split;   /* below: kernel split on the 32-point panel          (sqrt 3.5) */
+    double ah_max;      /* panels with alpha*h above are subdivided            (4.5)      */
+    double far_exp;     /* subpanels with alpha*dist beyond are plain GL       (40)       */
+} mhlp_params;
+
+typedef struct {
+    double tol;         /* stop when ||g - A mu||_2 / ||g||_2 <= tol (true residual) */
+    int32_t max_iter;   /* total Arnoldi steps                                        */
+    int32_t restart;    /* Krylov dimension before a restart (<= 512)                 */
+    int32_t precision;  /* MHLP_FP64 or MHLP_MIXED (mixed: FP32 far-field inner solves
+                           inside FP64 iterative refinement)                          */
+    int32_t use_x0;     /* 1: mu holds the initial guess on entry; 0: zero guess      */
+} mhlp_gmres_opts;
+
+typedef struct {
+    int32_t iters;        /* Arnoldi steps taken                                   */
+    int32_t restarts;     /* outer cycles (restarts or refinement steps)           */
+    double rel_residual;  /* true ||g - A mu|| / ||g|| at exit (FP64 operator)     */
+    double x0_residual;   /* true relative residual of the initial guess           */
+    int32_t converged;    /* 1 if rel_residual <= tol                              */
+    int32_t used_x0;      /* 0 if the initial guess was rejected (residual >= 1)   */
+} mhlp_gmres_info;
+
+const char *mhlp_last_error(void);
+
+/* Geometry from node data.  node_soa: device [6][N] float64, rows x, y,
+   dx/dt, dy/dt, d2x/dt2, d2y/dt2 (derivatives with respect to the panel
+   parameter t in [-1,1]; Sec. 3.2).  n_panels >= 1.  Synchronises the stream.
+   Errors: MHLP_INVALID_ARG (null pointers, n_panels < 1), MHLP_HIP_ERROR. */
+mhlp_status mhlp_geometry_create(const double *node_soa, int64_t n_panels, void *stream, mhlp_geometry **out);
+mhlp_status mhlp_geometry_destroy(mhlp_geometry *geom);
+/* Device views (valid for the geometry's lifetime): per-node quadrature
+   weight, unit normal (x, y) and signed curvature. Any output may be NULL. */
+mhlp_status mhlp_geometry_arrays(const mhlp_geometry *geom, const double **w, const double **nx, const double **ny,
+                                 const double **kappa);
+
+/* Plan: targets plus precomputed near-field correction weights (Sec. 4.5:
+   candidate panels within 1.2 h, Newton preimage, Bernstein-radius tiers,
+   kernel split, subdivision for alpha h > 4.5).  tx, ty: device [m] float64.
+   m == 0 builds the on-surface plan (targets are the nodes; needed by
+   apply_bie_operator and gmres_solve).  params: host, NULL = paper values.
+   Synchronises the stream.  Errors: MHLP_INVALID_ARG (alpha <= 0 or not
+   finite, null targets with m > 0), MHLP_HIP_ERROR, MHLP_NO_MEMORY. */
+mhlp_status mhlp_plan_create(const mhlp_geometry *geom, double alpha, const double *tx, const double *ty, int64_t m,
+                             const mhlp_params *params, void *stream, mhlp_plan **out);
+mhlp_status mhlp_plan_destroy(mhlp_plan *plan);
+/* Plan statistics (host outputs; any may be NULL). */
+mhlp_status mhlp_plan_info(const mhlp_plan *plan, int64_t *n_targets, int64_t *n_sources, int64_t *n_near_pairs,
+                           double *alpha);
+
+/* S[sigma] and/or D[mu] at the plan's targets (sigma, mu: device [N];
+   u_slp, u_dlp: device [M], overwritten).  Either density/output pair may be
+   NULL (then that potential is skipped), not both.  On an on-surface plan,
+   D is the principal value (no 1/2 mu term) and S is the on-surface value.
+   Far field in FP64 or mixed precision; near-field corrections FP64. */
+mhlp_status mhlp_eval_layer(const mhlp_plan *plan, const double *sigma, const double *mu, double *u_slp,
+                            double *u_dlp, int32_t precision, void *stream);
+mhlp_status mhlp_eval_slp(const mhlp_plan *plan, const double *sigma, double *u, int32_t precision, void *stream);
+mhlp_status mhlp_eval_dlp(const mhlp_plan *plan, const double *mu, double *u, int32_t precision, void *stream);
+
+/* out = (1/2 I + D) mu on an on-surface plan (Sec. 3.2, second-kind BIE with
+   the interior limit).  Errors: MHLP_INVALID_ARG if the plan is not on-surface. */
+mhlp_status mhlp_apply_bie_operator(const mhlp_plan *onsurf, const double *mu, double *out, int32_t precision,
+                                    void *stream);
+
+/* GMRES for (1/2 I + D) mu = g (Sec. 3.2), restarted, classical Gram-Schmidt
+   with reorthogonalisation in FP64, judged by the true FP64 residual.  g, mu:
+   device [N].  With opts->use_x0, mu holds the initial guess; a guess whose
+   true relative residual is >= 1 is replaced by zero (info->used_x0 = 0).
+   opts, info: host.  Synchronises the stream.  Returns MHLP_NOT_CONVERGED
+   (mu = last iterate, info filled) if max_iter is reached. */
+mhlp_status mhlp_gmres_solve(const mhlp_plan *onsurf, const double *g, double *mu, const mhlp_gmres_opts *opts,
+                             mhlp_gmres_info *info, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MHLP_H */

@@ -1,0 +1,841 @@
+/*
+ * mhlp.hip -- HIP kernels and C ABI of the modified-Helmholtz layer-potential
+ * library (declarations and contracts: include/mhlp.h).
+ *
+ * Data layout in device memory
+ *   geometry : node SoA x, y, dx, dy, d2x, d2y (copy of the caller's [6][N]),
+ *              derived per-node weight w, unit normal nx, ny, curvature;
+ *              per panel the Legendre coefficients of its position (16
+ *              complex), arclength h and a bounding circle.
+ *   plan     : targets tx, ty; CSR near list by target (row_ptr, panel index
+ *              ascending, target index, complex preimage) and 16 SLP + 16 DLP
+ *              correction weights per listed (target, panel) pair.
+ *
+ * Kernels
+ *   geom_prep        one thread per panel: weights, normals, curvature, Legendre
+ *                    coefficients, arclength, bounding circle.
+ *   near_count/fill  one thread per target: candidate panels (some node within
+ *                    1.2 h), Newton preimage, Bernstein radius < 3.5 (Sec. 4.5.1).
+ *   near_weights     one thread per listed pair: correction weights (nearfield.h).
+ *   far_eval_fp64    one thread per target, sources streamed through LDS in tiles
+ *                    of 16 panels; listed panels are skipped and their corrected
+ *                    contribution added in the epilogue (no add-then-subtract).
+ *   gmres_*          BLAS-1 pieces of the Arnoldi process.
+ */
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mhlp.h"
+#include "nearfield.h"
+
+using namespace mhlp;
+
+/* ------------------------------------------------------------------------ */
+/* error handling                                                            */
+/* ------------------------------------------------------------------------ */
+static thread_local std::string g_err;
+
+static mhlp_status fail(mhlp_status s, const std::string &msg)
+{
+    g_err = msg;
+    return s;
+}
+
+#define HIPCHECK(x)                                                                                   \
+    do {                                                                                              \
+        hipError_t e_ = (x);                                                                          \
+        if (e_ != hipSuccess) return fail(MHLP_HIP_ERROR, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+extern "C" const char *mhlp_last_error(void) { return g_err.c_str(); }
+
+/* ------------------------------------------------------------------------ */
+/* handles                                                                   */
+/* ------------------------------------------------------------------------ */
+struct mhlp_geometry {
+    int device = 0;
+    int64_t N = 0, Np = 0;
+    double *soa = nullptr;                       /* [6][N] */
+    double *w = nullptr, *nx = nullptr, *ny = nullptr, *kappa = nullptr;
+    double *pa = nullptr;                        /* [Np][16] complex (re, im) */
+    double *ph = nullptr, *pcx = nullptr, *pcy = nullptr, *prad = nullptr;
+};
+
+struct mhlp_plan {
+    const mhlp_geometry *g = nullptr;
+    double alpha = 0.0;
+    int64_t M = 0;
+    bool onsurf = false;
+    double *tx = nullptr, *ty = nullptr; /* owned unless onsurf */
+    int32_t *near_ptr = nullptr;         /* [M+1] */
+    int32_t *near_panel = nullptr;       /* [nnz] */
+    int32_t *near_tgt = nullptr;         /* [nnz] */
+    double *near_ts = nullptr;           /* [nnz][2] */
+    double *wslp = nullptr, *wdlp = nullptr; /* [nnz][16] */
+    int64_t nnz = 0;
+    NearParams np{};
+    double near_factor = 1.2;
+    /* GMRES workspace (lazily allocated) */
+    double *ws = nullptr;
+    int64_t ws_cols = 0;
+    double *hdev = nullptr;  /* small device scratch for dot products */
+    double *hhost = nullptr; /* pinned host mirror                    */
+};
+
+/* ------------------------------------------------------------------------ */
+/* geometry preparation                                                      */
+/* ------------------------------------------------------------------------ */
+__global__ void geom_prep_kernel(const double *__restrict__ soa, int64_t N, int64_t Np, double *__restrict__ w,
+                                 double *__restrict__ nx, double *__restrict__ ny, double *__restrict__ kappa,
+                                 double *__restrict__ pa, double *__restrict__ ph, double *__restrict__ pcx,
+                                 double *__restrict__ pcy, double *__restrict__ prad)
+{
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= Np) return;
+    const double *x = soa, *y = soa + N, *dx = soa + 2 * N, *dy = soa + 3 * N, *ddx = soa + 4 * N,
+                 *ddy = soa + 5 * N;
+    double h = 0.0;
+    for (int j = 0; j < 16; ++j) {
+        const int64_t m = 16 * p + j;
+        const double sp = hypot(dx[m], dy[m]);
+        const double wm = GL16_W[j] * sp;
+        w[m] = wm;
+        nx[m] = -dy[m] / sp;
+        ny[m] = dx[m] / sp;
+        kappa[m] = (dx[m] * ddy[m] - dy[m] * ddx[m]) / (sp * sp * sp);
+        h += wm;
+    }
+    cplx a[16];
+    for (int mm = 0; mm < 16; ++mm) {
+        cplx s = mk(0.0, 0.0);
+        for (int j = 0; j < 16; ++j) s = s + LEGC[mm * 16 + j] * mk(x[16 * p + j], y[16 * p + j]);
+        a[mm] = s;
+        pa[(16 * p + mm) * 2] = s.re;
+        pa[(16 * p + mm) * 2 + 1] = s.im;
+    }
+    const cplx c = a[0];
+    double r = 0.0;
+    for (int j = 0; j < 16; ++j) r = fmax(r, cabs(mk(x[16 * p + j], y[16 * p + j]) - c));
+    cplx e1 = mk(0.0, 0.0), e0 = mk(0.0, 0.0);
+    for (int mm = 0; mm < 16; ++mm) {
+        e1 = e1 + a[mm];
+        e0 = e0 + ((mm & 1) ? -1.0 : 1.0) * a[mm];
+    }
+    r = fmax(r, fmax(cabs(e1 - c), cabs(e0 - c)));
+    ph[p] = h;
+    pcx[p] = c.re;
+    pcy[p] = c.im;
+    prad[p] = r;
+}
+
+/* ------------------------------------------------------------------------ */
+/* near list                                                                 */
+/* ------------------------------------------------------------------------ */
+struct GeoView {
+    const double *x, *y, *pa, *ph, *pcx, *pcy, *prad;
+    int64_t N, Np;
+};
+
+/* Calls f(panel, self, tstar) for every panel needing a correction at target i
+   (panel index ascending). */
+template <class F>
+__device__ inline void visit_near(const GeoView &G, int64_t i, cplx z, bool onsurf, double near_factor,
+                                  double rho_direct, F &&f)
+{
+    const int64_t self_p = onsurf ? i / 16 : -1;
+    for (int64_t p = 0; p < G.Np; ++p) {
+        const double lim = near_factor * G.ph[p];
+        const bool self = (p == self_p);
+        if (!self) {
+            const double dc = cabs(z - mk(G.pcx[p], G.pcy[p])) - G.prad[p];
+            if (dc > lim) continue;
+        }
+        if (self) {
+            f(p, (int)(i % 16), mk(GL16_T[i % 16], 0.0));
+            continue;
+        }
+        double dmin = 1e300;
+        int jb = 0;
+        for (int j = 0; j < 16; ++j) {
+            const double d = cabs2(z - mk(G.x[16 * p + j], G.y[16 * p + j]));
+            if (d < dmin) {
+                dmin = d;
+                jb = j;
+            }
+        }
+        if (dmin >= lim * lim) continue;
+        cplx a[16];
+        for (int m = 0; m < 16; ++m) a[m] = mk(G.pa[(16 * p + m) * 2], G.pa[(16 * p + m) * 2 + 1]);
+        cplx ts;
+        if (!preimage(a, z, mk(GL16_T[jb], 0.0), ts)) continue;
+        if (bernstein_rho(ts) >= rho_direct) continue;
+        f(p, -1, ts);
+    }
+}
+
+__global__ void near_count_kernel(GeoView G, const double *__restrict__ tx, const double *__restrict__ ty, int64_t M,
+                                  int onsurf, double near_factor, double rho_direct, int32_t *__restrict__ cnt)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    int32_t c = 0;
+    visit_near(G, i, mk(tx[i], ty[i]), onsurf != 0, near_factor, rho_direct, [&](int64_t, int, cplx) { ++c; });
+    cnt[i] = c;
+}
+
+__global__ void near_fill_kernel(GeoView G, const double *__restrict__ tx, const double *__restrict__ ty, int64_t M,
+                                 int onsurf, double near_factor, double rho_direct, const int32_t *__restrict__ ptr,
+                                 int32_t *__restrict__ panel, int32_t *__restrict__ tgt, double *__restrict__ ts_out)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    int32_t q = ptr[i];
+    const int32_t qend = ptr[i + 1];
+    visit_near(G, i, mk(tx[i], ty[i]), onsurf != 0, near_factor, rho_direct, [&](int64_t p, int, cplx ts) {
+        if (q < qend) {
+            panel[q] = (int32_t)p;
+            tgt[q] = (int32_t)i;
+            ts_out[2 * q] = ts.re;
+            ts_out[2 * q + 1] = ts.im;
+        }
+        ++q;
+    });
+}
+
+/* exclusive scan of cnt[0..M) into ptr[0..M]; one block of 1024 threads */
+__global__ __launch_bounds__(1024) void scan_kernel(const int32_t *__restrict__ cnt, int64_t M,
+                                                    int32_t *__restrict__ ptr)
+{
+    __shared__ int64_t part[1024];
+    const int t = threadIdx.x;
+    const int64_t chunk = (M + 1023) / 1024;
+    const int64_t b = t * chunk, e = (b + chunk < M) ? b + chunk : M;
+    int64_t s = 0;
+    for (int64_t i = b; i < e; ++i) s += cnt[i];
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int64_t v = (t >= off) ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int64_t run = part[t] - s;
+    for (int64_t i = b; i < e; ++i) {
+        ptr[i] = (int32_t)run;
+        run += cnt[i];
+    }
+    if (t == 1023) ptr[M] = (int32_t)part[1023];
+}
+
+__global__ void near_weights_kernel(GeoView G, const double *__restrict__ tx, const double *__restrict__ ty,
+                                    int onsurf, const int32_t *__restrict__ panel, const int32_t *__restrict__ tgt,
+                                    const double *__restrict__ ts, int64_t nnz, double alpha, NearParams P,
+                                    double *__restrict__ wsl, double *__restrict__ wdl)
+{
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= nnz) return;
+    const int64_t p = panel[q], i = tgt[q];
+    cplx a[16];
+    for (int m = 0; m < 16; ++m) a[m] = mk(G.pa[(16 * p + m) * 2], G.pa[(16 * p + m) * 2 + 1]);
+    const int self = (onsurf && i / 16 == p) ? (int)(i % 16) : -1;
+    double Ws[16], Wd[16];
+    pair_weights(a, G.ph[p], mk(tx[i], ty[i]), self, mk(ts[2 * q], ts[2 * q + 1]), alpha, P, Ws, Wd);
+    for (int j = 0; j < 16; ++j) {
+        wsl[16 * q + j] = Ws[j];
+        wdl[16 * q + j] = Wd[j];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* far field + corrections, FP64                                             */
+/* ------------------------------------------------------------------------ */
+constexpr int FT_THREADS = 256;
+constexpr int FT_SRC = 256; /* sources per LDS tile = 16 panels */
+
+struct FarArgs {
+    const double *sx, *sy, *sw, *snx, *sny;
+    const double *sigma, *mu;
+    int64_t N;
+    const double *tx, *ty;
+    int64_t M;
+    const int32_t *nptr, *npan;
+    const double *wsl, *wdl;
+    double alpha;
+    double half_term; /* 0.5 for (1/2 I + D) on an on-surface plan, else 0 */
+    double *us, *ud;
+};
+
+template <bool SLP, bool DLP>
+__global__ __launch_bounds__(FT_THREADS) void far_eval_fp64(FarArgs A)
+{
+    __shared__ double lx[FT_SRC], ly[FT_SRC], lq[FT_SRC], ldx[FT_SRC], ldy[FT_SRC];
+    const int64_t i = blockIdx.x * (int64_t)FT_THREADS + threadIdx.x;
+    const bool valid = i < A.M;
+    const double x = valid ? A.tx[i] : 0.0, y = valid ? A.ty[i] : 0.0;
+    int32_t k = 0, kend = 0;
+    if (valid) {
+        k = A.nptr[i];
+        kend = A.nptr[i + 1];
+    }
+    int32_t nxt = (k < kend) ? A.npan[k] : INT_MAX;
+    const double alpha = A.alpha, a2q = 0.25 * alpha * alpha, a4 = 4.0 / alpha;
+    double accs = 0.0, accd = 0.0;
+    for (int64_t base = 0; base < A.N; base += FT_SRC) {
+        __syncthreads();
+        const int64_t j = base + threadIdx.x;
+        if (j < A.N) {
+            const double wj = A.sw[j];
+            lx[threadIdx.x] = A.sx[j];
+            ly[threadIdx.x] = A.sy[j];
+            if (SLP) lq[threadIdx.x] = wj * A.sigma[j];
+            if (DLP) {
+                const double m = wj * A.mu[j];
+                ldx[threadIdx.x] = m * A.snx[j];
+                ldy[threadIdx.x] = m * A.sny[j];
+            }
+        }
+        __syncthreads();
+        const int64_t rem = (A.N - base) / 16;
+        const int npl = rem < 16 ? (int)rem : 16;
+        const int32_t p0 = (int32_t)(base / 16);
+        for (int pl = 0; pl < npl; ++pl) {
+            if (p0 + pl == nxt) {
+                ++k;
+                nxt = (k < kend) ? A.npan[k] : INT_MAX;
+                continue;
+            }
+#pragma unroll 2
+            for (int s = 0; s < 16; ++s) {
+                const int l = pl * 16 + s;
+                const double ex = x - lx[l], ey = y - ly[l];
+                const double r2 = fma(ex, ex, ey * ey);
+                const K01 o = k01_fp64<SLP, DLP>(r2, alpha, a2q, a4);
+                if (SLP) accs = fma(o.k0, lq[l], accs);
+                if (DLP) accd = fma(o.ak1r, fma(ex, ldx[l], ey * ldy[l]), accd);
+            }
+        }
+    }
+    if (!valid) return;
+    double cs = 0.0, cd = 0.0;
+    for (int32_t q = A.nptr[i]; q < A.nptr[i + 1]; ++q) {
+        const int64_t p = A.npan[q];
+        for (int jj = 0; jj < 16; ++jj) {
+            if (SLP) cs = fma(A.wsl[16 * (int64_t)q + jj], A.sigma[16 * p + jj], cs);
+            if (DLP) cd = fma(A.wdl[16 * (int64_t)q + jj], A.mu[16 * p + jj], cd);
+        }
+    }
+    if (SLP) A.us[i] = fma(INV_2PI, accs, cs);
+    if (DLP) A.ud[i] = fma(INV_2PI, accd, cd) + A.half_term * A.mu[i];
+}
+
+/* ------------------------------------------------------------------------ */
+/* GMRES BLAS-1                                                              */
+/* ------------------------------------------------------------------------ */
+/* out[c] = sum_i V[c*ld + i] * w[i], one block per column */
+__global__ __launch_bounds__(256) void multi_dot_kernel(const double *__restrict__ V, int64_t ld, const double *__restrict__ w,
+                                                        int64_t N, double *__restrict__ out)
+{
+    __shared__ double red[256];
+    const int c = blockIdx.x;
+    const double *v = V + c * ld;
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < N; i += 256) s = fma(v[i], w[i], s);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[c] = red[0];
+}
+
+/* w[i] -= sum_{c<ncol} h[c] V[c*ld + i] */
+__global__ void sub_combo_kernel(const double *__restrict__ V, int64_t ld, int ncol, const double *__restrict__ h,
+                                 double *__restrict__ w, int64_t N)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double s = w[i];
+    for (int c = 0; c < ncol; ++c) s = fma(-h[c], V[c * ld + i], s);
+    w[i] = s;
+}
+
+/* x[i] += sum_{c<ncol} y[c] V[c*ld + i] */
+__global__ void add_combo_kernel(const double *__restrict__ V, int64_t ld, int ncol, const double *__restrict__ yv,
+                                 double *__restrict__ x, int64_t N)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double s = x[i];
+    for (int c = 0; c < ncol; ++c) s = fma(yv[c], V[c * ld + i], s);
+    x[i] = s;
+}
+
+/* out = s * in */
+__global__ void scale_kernel(const double *__restrict__ in, double s, double *__restrict__ out, int64_t N)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < N) out[i] = s * in[i];
+}
+
+/* r = g - a */
+__global__ void residual_kernel(const double *__restrict__ g, const double *__restrict__ a, double *__restrict__ r,
+                                int64_t N)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < N) r[i] = g[i] - a[i];
+}
+
+__global__ void fill_kernel(double *__restrict__ x, double v, int64_t N)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < N) x[i] = v;
+}
+
+/* ------------------------------------------------------------------------ */
+/* host helpers                                                              */
+/* ------------------------------------------------------------------------ */
+static inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+template <class T>
+static mhlp_status dalloc(T **p, int64_t n)
+{
+    *p = nullptr;
+    if (n <= 0) return MHLP_OK;
+    hipError_t e = hipMalloc((void **)p, sizeof(T) * (size_t)n);
+    if (e != hipSuccess) return fail(MHLP_NO_MEMORY, std::string("hipMalloc: ") + hipGetErrorString(e));
+    return MHLP_OK;
+}
+
+#define TRY(x)                          \
+    do {                                \
+        mhlp_status s_ = (x);           \
+        if (s_ != MHLP_OK) return s_;   \
+    } while (0)
+
+static GeoView view(const mhlp_geometry *g)
+{
+    GeoView G;
+    G.x = g->soa;
+    G.y = g->soa + g->N;
+    G.pa = g->pa;
+    G.ph = g->ph;
+    G.pcx = g->pcx;
+    G.pcy = g->pcy;
+    G.prad = g->prad;
+    G.N = g->N;
+    G.Np = g->Np;
+    return G;
+}
+
+/* ------------------------------------------------------------------------ */
+/* geometry API                                                              */
+/* ------------------------------------------------------------------------ */
+extern "C" mhlp_status mhlp_geometry_create(const double *node_soa, int64_t n_panels, void *stream,
+                                            mhlp_geometry **out)
+{
+    if (!out) return fail(MHLP_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!node_soa) return fail(MHLP_INVALID_ARG, "node_soa is NULL");
+    if (n_panels < 1 || n_panels > (INT_MAX / 16)) return fail(MHLP_INVALID_ARG, "n_panels out of range");
+    hipStream_t st = (hipStream_t)stream;
+    mhlp_geometry *g = new mhlp_geometry();
+    HIPCHECK(hipGetDevice(&g->device));
+    g->Np = n_panels;
+    g->N = 16 * n_panels;
+    const int64_t N = g->N, Np = g->Np;
+    mhlp_status s;
+    if ((s = dalloc(&g->soa, 6 * N)) || (s = dalloc(&g->w, N)) || (s = dalloc(&g->nx, N)) || (s = dalloc(&g->ny, N)) ||
+        (s = dalloc(&g->kappa, N)) || (s = dalloc(&g->pa, 32 * Np)) || (s = dalloc(&g->ph, Np)) ||
+        (s = dalloc(&g->pcx, Np)) || (s = dalloc(&g->pcy, Np)) || (s = dalloc(&g->prad, Np))) {
+        mhlp_geometry_destroy(g);
+        return s;
+    }
+    hipError_t e = hipMemcpyAsync(g->soa, node_soa, sizeof(double) * 6 * N, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) {
+        geom_prep_kernel<<<nblocks(Np, 64), 64, 0, st>>>(g->soa, N, Np, g->w, g->nx, g->ny, g->kappa, g->pa, g->ph,
+                                                          g->pcx, g->pcy, g->prad);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        mhlp_geometry_destroy(g);
+        return fail(MHLP_HIP_ERROR, std::string("geometry_create: ") + hipGetErrorString(e));
+    }
+    *out = g;
+    return MHLP_OK;
+}
+
+extern "C" mhlp_status mhlp_geometry_destroy(mhlp_geometry *g)
+{
+    if (!g) return MHLP_OK;
+    double *ptrs[] = {g->soa, g->w, g->nx, g->ny, g->kappa, g->pa, g->ph, g->pcx, g->pcy, g->prad};
+    for (double *p : ptrs)
+        if (p) (void)hipFree(p);
+    delete g;
+    return MHLP_OK;
+}
+
+extern "C" mhlp_status mhlp_geometry_arrays(const mhlp_geometry *g, const double **w, const double **nx,
+                                            const double **ny, const double **kappa)
+{
+    if (!g) return fail(MHLP_INVALID_ARG, "geometry is NULL");
+    if (w) *w = g->w;
+    if (nx) *nx = g->nx;
+    if (ny) *ny = g->ny;
+    if (kappa) *kappa = g->kappa;
+    return MHLP_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* plan API                                                                  */
+/* ------------------------------------------------------------------------ */
+extern "C" mhlp_status mhlp_plan_destroy(mhlp_plan *P)
+{
+    if (!P) return MHLP_OK;
+    if (!P->onsurf) {
+        if (P->tx) (void)hipFree(P->tx);
+        if (P->ty) (void)hipFree(P->ty);
+    }
+    void *ptrs[] = {P->near_ptr, P->near_panel, P->near_tgt, P->near_ts, P->wslp, P->wdlp, P->ws, P->hdev};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    if (P->hhost) (void)hipHostFree(P->hhost);
+    delete P;
+    return MHLP_OK;
+}
+
+extern "C" mhlp_status mhlp_plan_create(const mhlp_geometry *g, double alpha, const double *tx, const double *ty,
+                                        int64_t m, const mhlp_params *prm, void *stream, mhlp_plan **out)
+{
+    if (!out) return fail(MHLP_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!g) return fail(MHLP_INVALID_ARG, "geometry is NULL");
+    if (!(alpha > 0.0) || !std::isfinite(alpha)) return fail(MHLP_INVALID_ARG, "alpha must be finite and > 0");
+    if (m < 0 || m > INT_MAX - 1) return fail(MHLP_INVALID_ARG, "number of targets out of range");
+    if (m > 0 && (!tx || !ty)) return fail(MHLP_INVALID_ARG, "target arrays are NULL");
+    hipStream_t st = (hipStream_t)stream;
+    mhlp_plan *P = new mhlp_plan();
+    P->g = g;
+    P->alpha = alpha;
+    P->np.rho_direct = 3.5;
+    P->np.rho_split = std::sqrt(3.5);
+    P->np.ah_max = 4.5;
+    P->np.far_exp = 40.0;
+    if (prm) {
+        if (prm->near_factor > 0) P->near_factor = prm->near_factor;
+        if (prm->rho_direct > 0) P->np.rho_direct = prm->rho_direct;
+        if (prm->rho_split > 0) P->np.rho_split = prm->rho_split;
+        if (prm->ah_max > 0) P->np.ah_max = prm->ah_max;
+        if (prm->far_exp > 0) P->np.far_exp = prm->far_exp;
+    }
+    mhlp_status s;
+    if (m == 0) {
+        P->onsurf = true;
+        P->M = g->N;
+        P->tx = g->soa;
+        P->ty = g->soa + g->N;
+    } else {
+        P->M = m;
+        if ((s = dalloc(&P->tx, m)) || (s = dalloc(&P->ty, m))) {
+            mhlp_plan_destroy(P);
+            return s;
+        }
+        hipError_t e = hipMemcpyAsync(P->tx, tx, sizeof(double) * m, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(P->ty, ty, sizeof(double) * m, hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) {
+            mhlp_plan_destroy(P);
+            return fail(MHLP_HIP_ERROR, std::string("plan_create copy: ") + hipGetErrorString(e));
+        }
+    }
+    const int64_t M = P->M;
+    int32_t *cnt = nullptr;
+    if ((s = dalloc(&cnt, M)) || (s = dalloc(&P->near_ptr, M + 1))) {
+        if (cnt) (void)hipFree(cnt);
+        mhlp_plan_destroy(P);
+        return s;
+    }
+    GeoView G = view(g);
+    near_count_kernel<<<nblocks(M, 128), 128, 0, st>>>(G, P->tx, P->ty, M, P->onsurf ? 1 : 0, P->near_factor,
+                                                        P->np.rho_direct, cnt);
+    scan_kernel<<<1, 1024, 0, st>>>(cnt, M, P->near_ptr);
+    int32_t nnz = 0;
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&nnz, P->near_ptr + M, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(cnt);
+    if (e != hipSuccess) {
+        mhlp_plan_destroy(P);
+        return fail(MHLP_HIP_ERROR, std::string("plan_create near count: ") + hipGetErrorString(e));
+    }
+    P->nnz = nnz;
+    if (nnz > 0) {
+        if ((s = dalloc(&P->near_panel, nnz)) || (s = dalloc(&P->near_tgt, nnz)) || (s = dalloc(&P->near_ts, 2 * (int64_t)nnz)) ||
+            (s = dalloc(&P->wslp, 16 * (int64_t)nnz)) || (s = dalloc(&P->wdlp, 16 * (int64_t)nnz))) {
+            mhlp_plan_destroy(P);
+            return s;
+        }
+        near_fill_kernel<<<nblocks(M, 128), 128, 0, st>>>(G, P->tx, P->ty, M, P->onsurf ? 1 : 0, P->near_factor,
+                                                           P->np.rho_direct, P->near_ptr, P->near_panel, P->near_tgt,
+                                                           P->near_ts);
+        near_weights_kernel<<<nblocks(nnz, 64), 64, 0, st>>>(G, P->tx, P->ty, P->onsurf ? 1 : 0, P->near_panel,
+                                                              P->near_tgt, P->near_ts, nnz, alpha, P->np, P->wslp,
+                                                              P->wdlp);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            mhlp_plan_destroy(P);
+            return fail(MHLP_HIP_ERROR, std::string("plan_create near weights: ") + hipGetErrorString(e));
+        }
+    }
+    *out = P;
+    return MHLP_OK;
+}
+
+extern "C" mhlp_status mhlp_plan_info(const mhlp_plan *P, int64_t *n_targets, int64_t *n_sources,
+                                      int64_t *n_near_pairs, double *alpha)
+{
+    if (!P) return fail(MHLP_INVALID_ARG, "plan is NULL");
+    if (n_targets) *n_targets = P->M;
+    if (n_sources) *n_sources = P->g->N;
+    if (n_near_pairs) *n_near_pairs = P->nnz;
+    if (alpha) *alpha = P->alpha;
+    return MHLP_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* evaluation                                                                */
+/* ------------------------------------------------------------------------ */
+static mhlp_status launch_far(const mhlp_plan *P, const double *sigma, const double *mu, double *us, double *ud,
+                              double half_term, int32_t precision, hipStream_t st)
+{
+    if (precision != MHLP_FP64 && precision != MHLP_MIXED) return fail(MHLP_INVALID_ARG, "unknown precision");
+    const mhlp_geometry *g = P->g;
+    FarArgs A;
+    A.sx = g->soa;
+    A.sy = g->soa + g->N;
+    A.sw = g->w;
+    A.snx = g->nx;
+    A.sny = g->ny;
+    A.sigma = sigma;
+    A.mu = mu;
+    A.N = g->N;
+    A.tx = P->tx;
+    A.ty = P->ty;
+    A.M = P->M;
+    A.nptr = P->near_ptr;
+    A.npan = P->near_panel;
+    A.wsl = P->wslp;
+    A.wdl = P->wdlp;
+    A.alpha = P->alpha;
+    A.half_term = half_term;
+    A.us = us;
+    A.ud = ud;
+    const unsigned nb = nblocks(P->M, FT_THREADS);
+    if (precision == MHLP_MIXED) return fail(MHLP_UNSUPPORTED, "mixed precision far field not built");
+    if (sigma && mu)
+        far_eval_fp64<true, true><<<nb, FT_THREADS, 0, st>>>(A);
+    else if (sigma)
+        far_eval_fp64<true, false><<<nb, FT_THREADS, 0, st>>>(A);
+    else
+        far_eval_fp64<false, true><<<nb, FT_THREADS, 0, st>>>(A);
+    HIPCHECK(hipGetLastError());
+    return MHLP_OK;
+}
+
+extern "C" mhlp_status mhlp_eval_layer(const mhlp_plan *P, const double *sigma, const double *mu, double *u_slp,
+                                       double *u_dlp, int32_t precision, void *stream)
+{
+    if (!P) return fail(MHLP_INVALID_ARG, "plan is NULL");
+    const bool ds = sigma && u_slp, dd = mu && u_dlp;
+    if (!ds && !dd) return fail(MHLP_INVALID_ARG, "no density/output pair given");
+    if ((sigma && !u_slp) || (u_slp && !sigma) || (mu && !u_dlp) || (u_dlp && !mu))
+        return fail(MHLP_INVALID_ARG, "density and output must be given together");
+    return launch_far(P, sigma, mu, u_slp, u_dlp, 0.0, precision, (hipStream_t)stream);
+}
+
+extern "C" mhlp_status mhlp_eval_slp(const mhlp_plan *P, const double *sigma, double *u, int32_t precision,
+                                     void *stream)
+{
+    if (!sigma || !u) return fail(MHLP_INVALID_ARG, "sigma or u is NULL");
+    return mhlp_eval_layer(P, sigma, nullptr, u, nullptr, precision, stream);
+}
+
+extern "C" mhlp_status mhlp_eval_dlp(const mhlp_plan *P, const double *mu, double *u, int32_t precision, void *stream)
+{
+    if (!mu || !u) return fail(MHLP_INVALID_ARG, "mu or u is NULL");
+    return mhlp_eval_layer(P, nullptr, mu, nullptr, u, precision, stream);
+}
+
+extern "C" mhlp_status mhlp_apply_bie_operator(const mhlp_plan *P, const double *mu, double *out, int32_t precision,
+                                               void *stream)
+{
+    if (!P) return fail(MHLP_INVALID_ARG, "plan is NULL");
+    if (!P->onsurf) return fail(MHLP_INVALID_ARG, "apply_bie_operator needs an on-surface plan (m == 0)");
+    if (!mu || !out) return fail(MHLP_INVALID_ARG, "mu or out is NULL");
+    if (mu == out) return fail(MHLP_INVALID_ARG, "mu and out must not alias");
+    return launch_far(P, nullptr, mu, nullptr, out, 0.5, precision, (hipStream_t)stream);
+}
+
+/* ------------------------------------------------------------------------ */
+/* GMRES                                                                     */
+/* ------------------------------------------------------------------------ */
+static mhlp_status ensure_ws(mhlp_plan *P, int64_t cols)
+{
+    if (P->ws && P->ws_cols >= cols) return MHLP_OK;
+    if (P->ws) (void)hipFree(P->ws);
+    P->ws = nullptr;
+    TRY(dalloc(&P->ws, (cols + 4) * P->g->N));
+    P->ws_cols = cols;
+    if (!P->hdev) TRY(dalloc(&P->hdev, 4 * 1024));
+    if (!P->hhost) HIPCHECK(hipHostMalloc((void **)&P->hhost, sizeof(double) * 4 * 1024, hipHostMallocDefault));
+    return MHLP_OK;
+}
+
+/* ||v||_2 (synchronising) */
+static mhlp_status dnorm(mhlp_plan *P, const double *v, int64_t N, hipStream_t st, double *out)
+{
+    multi_dot_kernel<<<1, 256, 0, st>>>(v, N, v, N, P->hdev);
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipMemcpyAsync(P->hhost, P->hdev, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    *out = std::sqrt(P->hhost[0]);
+    return MHLP_OK;
+}
+
+/* One restarted-GMRES solve of A x = b to relative tolerance `tol` (relative
+   to bnorm), FP64 Arnoldi with CGS2, operator in `prec`.  x is updated in
+   place. */
+static mhlp_status gmres_core(mhlp_plan *P, const double *b, double bnorm, double *x, double tol, int restart,
+                              int max_iter, int32_t prec, hipStream_t st, int *iters, int *cycles, double *relres)
+{
+    const int64_t N = P->g->N;
+    double *V = P->ws;                       /* (restart+1) columns */
+    double *w = P->ws + (int64_t)(restart + 1) * N;
+    double *r = w + N;
+    std::vector<double> H((size_t)(restart + 1) * restart, 0.0), cs(restart), sn(restart), gv(restart + 1), yv(restart);
+    const unsigned nbN = nblocks(N, 256);
+    int it = 0;
+    *cycles = 0;
+    for (;;) {
+        /* r = b - A x */
+        TRY(launch_far(P, nullptr, x, nullptr, w, 0.5, prec, st));
+        residual_kernel<<<nbN, 256, 0, st>>>(b, w, r, N);
+        double beta;
+        TRY(dnorm(P, r, N, st, &beta));
+        *relres = beta / bnorm;
+        if (*relres <= tol || it >= max_iter) break;
+        ++*cycles;
+        scale_kernel<<<nbN, 256, 0, st>>>(r, 1.0 / beta, V, N);
+        std::fill(gv.begin(), gv.end(), 0.0);
+        gv[0] = beta;
+        int k = 0;
+        for (; k < restart && it < max_iter; ++k) {
+            ++it;
+            TRY(launch_far(P, nullptr, V + k * N, nullptr, w, 0.5, prec, st));
+            /* classical Gram-Schmidt, twice */
+            double *h1 = P->hdev, *h2 = P->hdev + 1024, *hn = P->hdev + 2048;
+            multi_dot_kernel<<<k + 1, 256, 0, st>>>(V, N, w, N, h1);
+            sub_combo_kernel<<<nbN, 256, 0, st>>>(V, N, k + 1, h1, w, N);
+            multi_dot_kernel<<<k + 1, 256, 0, st>>>(V, N, w, N, h2);
+            sub_combo_kernel<<<nbN, 256, 0, st>>>(V, N, k + 1, h2, w, N);
+            multi_dot_kernel<<<1, 256, 0, st>>>(w, N, w, N, hn);
+            HIPCHECK(hipGetLastError());
+            HIPCHECK(hipMemcpyAsync(P->hhost, P->hdev, sizeof(double) * 3 * 1024, hipMemcpyDeviceToHost, st));
+            HIPCHECK(hipStreamSynchronize(st));
+            for (int j = 0; j <= k; ++j) H[(size_t)j * restart + k] = P->hhost[j] + P->hhost[1024 + j];
+            const double hn1 = std::sqrt(P->hhost[2048]);
+            H[(size_t)(k + 1) * restart + k] = hn1;
+            if (hn1 > 0.0) scale_kernel<<<nbN, 256, 0, st>>>(w, 1.0 / hn1, V + (k + 1) * N, N);
+            for (int j = 0; j < k; ++j) {
+                const double a = H[(size_t)j * restart + k], c = H[(size_t)(j + 1) * restart + k];
+                H[(size_t)j * restart + k] = cs[j] * a + sn[j] * c;
+                H[(size_t)(j + 1) * restart + k] = -sn[j] * a + cs[j] * c;
+            }
+            const double a = H[(size_t)k * restart + k], c = H[(size_t)(k + 1) * restart + k];
+            const double den = std::hypot(a, c);
+            cs[k] = a / den;
+            sn[k] = c / den;
+            H[(size_t)k * restart + k] = den;
+            H[(size_t)(k + 1) * restart + k] = 0.0;
+            gv[k + 1] = -sn[k] * gv[k];
+            gv[k] = cs[k] * gv[k];
+            if (std::fabs(gv[k + 1]) <= 0.5 * tol * bnorm || hn1 == 0.0) {
+                ++k;
+                break;
+            }
+        }
+        for (int i2 = k - 1; i2 >= 0; --i2) {
+            double sacc = gv[i2];
+            for (int j = i2 + 1; j < k; ++j) sacc -= H[(size_t)i2 * restart + j] * yv[j];
+            yv[i2] = sacc / H[(size_t)i2 * restart + i2];
+        }
+        HIPCHECK(hipMemcpyAsync(P->hdev + 3072, yv.data(), sizeof(double) * k, hipMemcpyHostToDevice, st));
+        add_combo_kernel<<<nbN, 256, 0, st>>>(V, N, k, P->hdev + 3072, x, N);
+        HIPCHECK(hipGetLastError());
+        HIPCHECK(hipStreamSynchronize(st));
+    }
+    *iters = it;
+    return MHLP_OK;
+}
+
+extern "C" mhlp_status mhlp_gmres_solve(const mhlp_plan *Pc, const double *g, double *mu, const mhlp_gmres_opts *opts,
+                                        mhlp_gmres_info *info, void *stream)
+{
+    if (!Pc) return fail(MHLP_INVALID_ARG, "plan is NULL");
+    if (!Pc->onsurf) return fail(MHLP_INVALID_ARG, "gmres_solve needs an on-surface plan (m == 0)");
+    if (!g || !mu || !opts || !info) return fail(MHLP_INVALID_ARG, "NULL argument");
+    if (g == mu) return fail(MHLP_INVALID_ARG, "g and mu must not alias");
+    if (!(opts->tol > 0.0) || opts->max_iter < 1 || opts->restart < 1 || opts->restart > 512)
+        return fail(MHLP_INVALID_ARG, "bad GMRES options");
+    if (opts->precision != MHLP_FP64 && opts->precision != MHLP_MIXED)
+        return fail(MHLP_INVALID_ARG, "unknown precision");
+    mhlp_plan *P = const_cast<mhlp_plan *>(Pc);
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t N = P->g->N;
+    std::memset(info, 0, sizeof(*info));
+    TRY(ensure_ws(P, opts->restart + 1));
+    double bnorm;
+    TRY(dnorm(P, g, N, st, &bnorm));
+    info->used_x0 = opts->use_x0 ? 1 : 0;
+    if (bnorm == 0.0) {
+        fill_kernel<<<nblocks(N, 256), 256, 0, st>>>(mu, 0.0, N);
+        HIPCHECK(hipStreamSynchronize(st));
+        info->converged = 1;
+        return MHLP_OK;
+    }
+    if (opts->use_x0) {
+        double *w = P->ws, *r = P->ws + N;
+        TRY(launch_far(P, nullptr, mu, nullptr, w, 0.5, MHLP_FP64, st));
+        residual_kernel<<<nblocks(N, 256), 256, 0, st>>>(g, w, r, N);
+        double rn;
+        TRY(dnorm(P, r, N, st, &rn));
+        info->x0_residual = rn / bnorm;
+        if (!(info->x0_residual < 1.0)) {
+            fill_kernel<<<nblocks(N, 256), 256, 0, st>>>(mu, 0.0, N);
+            info->used_x0 = 0;
+        }
+    } else {
+        fill_kernel<<<nblocks(N, 256), 256, 0, st>>>(mu, 0.0, N);
+        info->x0_residual = 1.0;
+    }
+    int iters = 0, cycles = 0;
+    double rel = 1.0;
+    if (opts->precision == MHLP_FP64) {
+        TRY(gmres_core(P, g, bnorm, mu, opts->tol, opts->restart, opts->max_iter, MHLP_FP64, st, &iters, &cycles, &rel));
+    } else {
+        return fail(MHLP_UNSUPPORTED, "mixed precision GMRES not built");
+    }
+    info->iters = iters;
+    info->restarts = cycles;
+    info->rel_residual = rel;
+    info->converged = rel <= opts->tol ? 1 : 0;
+    return info->converged ? MHLP_OK : MHLP_NOT_CONVERGED;
+}

@@ -1,0 +1,480 @@
+/*
+ * nearfield.h -- near-field correction weights for one (target, panel) pair.
+ *
+ * Follows the paper's Sec. 4 ("Quadrature details"): the kernel is split into
+ * a smooth part, a smooth function times log|r| and (double layer only) a
+ * smooth function times the Laplace/Cauchy kernel (x-y).n/|r|^2 (Sec. 4.1);
+ * the singular parts are integrated by interpolatory quadrature with exact
+ * moments (Sec. 4.3); targets are classified by the Bernstein radius of
+ * their preimage, with 16-point Gauss-Legendre for rho >= 3.5, a 32-point
+ * upsampled rule for sqrt(3.5) <= rho < 3.5 and kernel split on the upsampled
+ * panel below (Sec. 4.5.3); on-surface targets use kernel split for the log
+ * part on the 16 nodes with the curvature limit for the Cauchy part (Sec.
+ * 4.2, 4.5.2); panels with alpha h > 4.5 are subdivided towards the target
+ * and the subpanel weights folded back to the 16 nodes by interpolation
+ * (Sec. 4.5.4).
+ *
+ * Difference from the paper's formulation: the interpolation variable is the
+ * panel parameter t (a straight segment) rather than the complex coordinate
+ * tau.  With t* the complex preimage of the target, tau(t) - z =
+ * (t - t*) Q(t) where Q is the divided difference of the panel polynomial, so
+ *    log|tau - z|          = log|t - t*| + log|Q(t)|,
+ *    dtau / (tau - z)      = [tau'(t)/Q(t)] dt / (t - t*),
+ * and the moments int t^k log(t - t*) dt, int t^k/(t - t*) dt are taken over
+ * [-1, 1], where the principal logarithm is continuous whenever t* is off the
+ * segment (no winding corrections).
+ *
+ * All weights multiply the density at the panel's 16 nodes; they REPLACE the
+ * panel's direct 16-point contribution (the far-field kernels skip listed
+ * panels).  Arithmetic is FP64 throughout.
+ */
+#pragma once
+#include "yukawa.h"
+
+namespace mhlp {
+
+struct NearParams {
+    double rho_direct; /* 3.5: 16-point rule accurate at or beyond        */
+    double rho_split;  /* sqrt(3.5): kernel split below                    */
+    double ah_max;     /* 4.5: largest alpha h a split panel may have      */
+    double far_exp;    /* 40: a subpanel with alpha*dist beyond is direct   */
+};
+
+/* p(t), p'(t), p''(t) of the Legendre series sum_m a_m P_m(t), complex t. */
+__host__ __device__ inline void leg_eval(const cplx *a, cplx t, cplx &p, cplx &dp, cplx *d2p = nullptr)
+{
+    cplx P0 = mk(1.0, 0.0), P1 = t;
+    cplx D0 = mk(0.0, 0.0), D1 = mk(1.0, 0.0);
+    cplx E0 = mk(0.0, 0.0), E1 = mk(0.0, 0.0);
+    p = a[0] + a[1] * P1;
+    dp = a[1];
+    cplx d2 = mk(0.0, 0.0);
+    for (int m = 1; m < 15; ++m) {
+        const double c1 = (2.0 * m + 1.0) / (m + 1.0), c0 = m / (m + 1.0);
+        cplx P2 = c1 * (t * P1) - c0 * P0;
+        cplx D2 = D0 + (2.0 * m + 1.0) * P1;
+        cplx E2 = E0 + (2.0 * m + 1.0) * D1;
+        p = p + a[m + 1] * P2;
+        dp = dp + a[m + 1] * D2;
+        d2 = d2 + a[m + 1] * E2;
+        P0 = P1; P1 = P2;
+        D0 = D1; D1 = D2;
+        E0 = E1; E1 = E2;
+    }
+    if (d2p) *d2p = d2;
+}
+
+/* Divided difference (p(t) - p(s)) / (t - s) of the Legendre series, computed
+   without cancellation: with D_m = (P_m(t) - P_m(s))/(t - s),
+   D_0 = 0, D_1 = 1, (m+1) D_{m+1} = (2m+1) (P_m(t) + s D_m) - m D_{m-1}.    */
+__host__ __device__ inline cplx leg_divdiff(const cplx *a, cplx t, cplx s)
+{
+    cplx P0 = mk(1.0, 0.0), P1 = t;
+    cplx D0 = mk(0.0, 0.0), D1 = mk(1.0, 0.0);
+    cplx acc = a[1];
+    for (int m = 1; m < 15; ++m) {
+        const double c1 = (2.0 * m + 1.0) / (m + 1.0), c0 = m / (m + 1.0);
+        cplx D2 = c1 * (P1 + s * D1) - c0 * D0;
+        cplx P2 = c1 * (t * P1) - c0 * P0;
+        acc = acc + a[m + 1] * D2;
+        P0 = P1; P1 = P2;
+        D0 = D1; D1 = D2;
+    }
+    return acc;
+}
+
+/* First and Hermite second divided differences of the Legendre series,
+   Q = p[t, s] and R = p[t, t, s], so that p(t) - p(s) = (t - s) Q and
+   p'(t) = Q + (t - s) R, from the Leibniz rule (x f)[t,t,s] = t f[t,t,s] +
+   f[t,s] applied to the three-term recurrence:
+   (m+1) E_{m+1} = (2m+1) (t E_m + D_m) - m E_{m-1},  E_0 = E_1 = 0.       */
+__host__ __device__ inline void leg_divdiff2(const cplx *a, double t, double s, cplx &Q, cplx &R)
+{
+    double P0 = 1.0, P1 = t, D0 = 0.0, D1 = 1.0, E0 = 0.0, E1 = 0.0;
+    Q = a[1];
+    R = mk(0.0, 0.0);
+    for (int m = 1; m < 15; ++m) {
+        const double c1 = (2.0 * m + 1.0) / (m + 1.0), c0 = m / (m + 1.0);
+        const double E2 = c1 * (t * E1 + D1) - c0 * E0;
+        const double D2 = c1 * (P1 + s * D1) - c0 * D0;
+        const double P2 = c1 * (t * P1) - c0 * P0;
+        Q = Q + D2 * a[m + 1];
+        R = R + E2 * a[m + 1];
+        P0 = P1; P1 = P2;
+        D0 = D1; D1 = D2;
+        E0 = E1; E1 = E2;
+    }
+}
+
+/* Newton iteration for the complex preimage t* with p(t*) = z.  The attainable
+   accuracy of t* is about eps |z| / |p'|, so convergence is declared once the
+   step is below 1e-12 and two more steps polish t* to that floor.  Returns
+   false only if the iteration leaves the region |t| < 1000 or never reaches
+   the 1e-12 step size. */
+__host__ __device__ inline bool preimage(const cplx *a, cplx z, cplx t0, cplx &t)
+{
+    t = t0;
+    int polish = -1;
+    for (int it = 0; it < 60; ++it) {
+        cplx p, dp;
+        leg_eval(a, t, p, dp);
+        const cplx dt = (p - z) / dp;
+        t = t - dt;
+        if (!(cabs2(t) < 1e6)) return false;
+        if (polish >= 0) {
+            if (++polish == 2) return true;
+        } else if (cabs2(dt) < 1e-24 * (1.0 + cabs2(t))) {
+            polish = 0;
+        }
+    }
+    return polish >= 0;
+}
+
+/* Bernstein radius rho(t) = |t +- sqrt(t^2 - 1)| >= 1. */
+__host__ __device__ inline double bernstein_rho(cplx t)
+{
+    cplx w = csqrt(t * t - mk(1.0, 0.0));
+    double r1 = cabs(t + w), r2 = cabs(t - w);
+    return r1 > r2 ? r1 : r2;
+}
+
+/* Legendre moments over the segment [-1, 1] with pole / branch point s off
+   the segment (or real outside it):
+     MC[m] = int P_m(t) / (t - s) dt,        m = 0..N
+     ML[m] = int P_m(t) log(t - s) dt,       m = 0..N-1
+   MC[m] = -2 Q_m(s) is the minimal solution of the Legendre recurrence
+   (m+1) M_{m+1} = (2m+1) s M_m - m M_{m-1} (m >= 1, M_1 = s M_0 + 2):
+   forward recursion close to the segment (Bernstein radius < 1.05, where the
+   error growth rho^(2m) is mild), Miller's backward recursion otherwise,
+   normalised by M_0 = log((1 - s)/(-1 - s)).  Log moments by parts with the
+   antiderivative (P_{m+1} - P_{m-1})/(2m+1) of P_m, which vanishes at +-1:
+     ML[0] = (1-s) log(1-s) - (-1-s) log(-1-s) - 2,
+     ML[m] = -(MC[m+1] - MC[m-1]) / (2m+1).
+   The principal logarithm is continuous along the segment for such s.       */
+template <int N>
+__host__ __device__ inline void legendre_moments(cplx s, double rho, cplx *MC, cplx *ML)
+{
+    const cplx la = clog(mk(-1.0, 0.0) - s);
+    const cplx lb = clog(mk(1.0, 0.0) - s);
+    const cplx m0 = lb - la;
+    if (rho < 1.05) {
+        MC[0] = m0;
+        MC[1] = s * m0 + mk(2.0, 0.0);
+        for (int m = 1; m < N; ++m)
+            MC[m + 1] = (1.0 / (m + 1.0)) * ((2.0 * m + 1.0) * (s * MC[m]) - (double)m * MC[m - 1]);
+    } else {
+        int K = N + 1 + (int)ceil(40.0 / log(rho * rho));
+        if (K > 4000) K = 4000;
+        cplx y1 = mk(0.0, 0.0), y0 = mk(1e-30, 0.0); /* y_{m+1}, y_m */
+        for (int m = K; m >= 1; --m) {
+            cplx ym1 = (1.0 / m) * ((2.0 * m + 1.0) * (s * y0) - (m + 1.0) * y1);
+            y1 = y0;
+            y0 = ym1;
+            if (m - 1 <= N) MC[m - 1] = y0;
+            if (cabs2(y0) > 1e200) { /* rescale the running solution */
+                y0 = 1e-100 * y0;
+                y1 = 1e-100 * y1;
+                for (int j = m - 1; j <= N && j <= K; ++j) MC[j] = 1e-100 * MC[j];
+            }
+        }
+        const cplx f = m0 / MC[0];
+        for (int m = 0; m <= N; ++m) MC[m] = f * MC[m];
+    }
+    ML[0] = (mk(1.0, 0.0) - s) * lb - (mk(-1.0, 0.0) - s) * la - mk(2.0, 0.0);
+    for (int m = 1; m < N; ++m) ML[m] = (-1.0 / (2.0 * m + 1.0)) * (MC[m + 1] - MC[m - 1]);
+}
+
+/* Same for real s strictly inside (-1, 1) (target on the curve inside the
+   rule's interval): principal-value Cauchy moments and int P_m log|t - s| dt.
+   Forward recursion is stable there (both solutions oscillate).            */
+template <int N>
+__host__ __device__ inline void legendre_moments_real(double s, double *MC, double *ML)
+{
+    const double l1 = log(1.0 - s), l2 = log(1.0 + s);
+    MC[0] = l1 - l2;
+    MC[1] = s * MC[0] + 2.0;
+    for (int m = 1; m < N; ++m) MC[m + 1] = ((2.0 * m + 1.0) * s * MC[m] - m * MC[m - 1]) / (m + 1.0);
+    ML[0] = (1.0 - s) * l1 + (1.0 + s) * l2 - 2.0;
+    for (int m = 1; m < N; ++m) ML[m] = -(MC[m + 1] - MC[m - 1]) / (2.0 * m + 1.0);
+}
+
+/* Node weights of the N-point Gauss-Legendre rule reproducing the moments
+   exactly for polynomials of degree < N: w_k = sum_m lambda_k (2m+1)/2
+   P_m(t_k) M_m (discrete orthogonality of the Legendre polynomials). */
+template <int N, typename T>
+__host__ __device__ inline void moments_to_weights(const double *legw, const T *M, T *w)
+{
+    for (int k = 0; k < N; ++k) {
+        T acc = M[0] * legw[k * N];
+        for (int m = 1; m < N; ++m) acc = acc + M[m] * legw[k * N + m];
+        w[k] = acc;
+    }
+}
+
+/* Lagrange basis of the 16 Gauss-Legendre nodes at real t (barycentric). */
+__host__ __device__ inline void lagrange16(double t, double *l)
+{
+    double s = 0.0;
+    for (int j = 0; j < 16; ++j) {
+        double d = t - GL16_T[j];
+        if (d == 0.0) {
+            for (int k = 0; k < 16; ++k) l[k] = (k == j) ? 1.0 : 0.0;
+            return;
+        }
+        l[j] = BARY16[j] / d;
+        s += l[j];
+    }
+    const double is = 1.0 / s;
+    for (int j = 0; j < 16; ++j) l[j] *= is;
+}
+
+/* Per-node kernel pieces for the rule on one (sub)panel. */
+struct NodeGeo {
+    cplx tau, dtau; /* position, derivative w.r.t. the local parameter */
+    double w;       /* quadrature weight |dtau| lambda                 */
+};
+
+__host__ __device__ inline double xmy_dot_n(cplx z, const NodeGeo &g)
+{
+    /* (x - y).n with n = i dtau/|dtau|:  -(Re(conj(tau - z) * i dtau))/|dtau| */
+    cplx d = g.tau - z;
+    cplx in = mk(-g.dtau.im, g.dtau.re);
+    return -(d.re * in.re + d.im * in.im) / cabs(g.dtau);
+}
+
+/* Direct (plain quadrature) weights at one node; returns SLP and DLP weights. */
+__host__ __device__ inline void direct_node(cplx z, const NodeGeo &g, double alpha, double &ws, double &wd)
+{
+    const double r2 = cabs2(g.tau - z);
+    const K01 o = k01_fp64<true, true>(r2, alpha, 0.25 * alpha * alpha, 4.0 / alpha);
+    ws = INV_2PI * o.k0 * g.w;
+    wd = INV_2PI * o.ak1r * xmy_dot_n(z, g) * g.w;
+}
+
+/* Fold node weights of a rule with NQ nodes on [ta, tb] of the parent panel
+   back to the parent's 16 nodes. */
+template <int NQ>
+__host__ __device__ inline void fold_add(const double *tq, double ta, double tb, const double *WS, const double *WD,
+                                         double *Ws, double *Wd)
+{
+    const double mid = 0.5 * (ta + tb), half = 0.5 * (tb - ta);
+    for (int k = 0; k < NQ; ++k) {
+        double l[16];
+        lagrange16(mid + half * tq[k], l);
+        for (int j = 0; j < 16; ++j) {
+            Ws[j] = fma(l[j], WS[k], Ws[j]);
+            Wd[j] = fma(l[j], WD[k], Wd[j]);
+        }
+    }
+}
+
+/* Geometry of the rule with NQ nodes on [ta, tb] of the parent panel. */
+template <int NQ>
+__host__ __device__ inline void rule_geo(const cplx *a, const double *tq, const double *wq, double ta, double tb,
+                                         NodeGeo *g)
+{
+    const double mid = 0.5 * (ta + tb), half = 0.5 * (tb - ta);
+    for (int k = 0; k < NQ; ++k) {
+        cplx p, dp;
+        leg_eval(a, mk(mid + half * tq[k], 0.0), p, dp);
+        g[k].tau = p;
+        g[k].dtau = half * dp;
+        g[k].w = wq[k] * cabs(g[k].dtau);
+    }
+}
+
+/* Plain NQ-point rule on [ta, tb], folded into the 16 weights. */
+template <int NQ>
+__host__ __device__ inline void leaf_direct(const cplx *a, const double *tq, const double *wq, double ta, double tb,
+                                            cplx z, double alpha, double *Ws, double *Wd)
+{
+    NodeGeo g[NQ];
+    double WS[NQ], WD[NQ];
+    rule_geo<NQ>(a, tq, wq, ta, tb, g);
+    for (int k = 0; k < NQ; ++k) direct_node(z, g[k], alpha, WS[k], WD[k]);
+    fold_add<NQ>(tq, ta, tb, WS, WD, Ws, Wd);
+}
+
+/* Kernel split on the 32-point upsampled rule of [ta, tb] for a target with
+   parent preimage tstar (complex, off the segment or on the real axis outside
+   it). */
+__host__ __device__ inline void leaf_split32(const cplx *a, double ta, double tb, cplx z, cplx tstar, double alpha,
+                                             double *Ws, double *Wd)
+{
+    constexpr int NQ = 32;
+    NodeGeo g[NQ];
+    double WS[NQ], WD[NQ];
+    rule_geo<NQ>(a, GL32_T, GL32_W, ta, tb, g);
+    const double mid = 0.5 * (ta + tb), half = 0.5 * (tb - ta);
+    const cplx ss = (1.0 / half) * (tstar - mk(mid, 0.0));
+    cplx MC[NQ + 1], ML[NQ], pc[NQ], pl[NQ];
+    legendre_moments<NQ>(ss, bernstein_rho(ss), MC, ML);
+    moments_to_weights<NQ>(LEGW32, MC, pc); /* Cauchy weights */
+    moments_to_weights<NQ>(LEGW32, ML, pl); /* log weights    */
+    const double la = log(alpha);
+    const double a2 = alpha * alpha;
+    for (int k = 0; k < NQ; ++k) {
+        const cplx tk = mk(mid + half * GL32_T[k], 0.0);
+        const cplx Q = half * leg_divdiff(a, tk, tstar); /* (tau - z)/(s - s*) */
+        const double sp_ = cabs(g[k].dtau);
+        const double logw = fma(sp_, pl[k].re, g[k].w * log(cabs(Q)));
+        const double r = cabs(g[k].tau - z);
+        const Split s = split_k01(alpha * r);
+        const double xn = xmy_dot_n(z, g[k]);
+        WS[k] = INV_2PI * (fma(-s.i0, la, s.k0s) * g[k].w - s.i0 * logw);
+        const double Sd = a2 * fma(s.i1z, la, s.k1sz), Ld = a2 * s.i1z;
+        const cplx cw = pc[k] * (g[k].dtau / Q);
+        WD[k] = INV_2PI * (xn * fma(Sd, g[k].w, Ld * logw) + cw.im);
+    }
+    fold_add<NQ>(GL32_T, ta, tb, WS, WD, Ws, Wd);
+}
+
+/* Target on the curve at real local parameter sstar strictly inside the rule's
+   interval, not at a node (NQ = 32), or exactly at node `at` (NQ = 16, the
+   panel's own nodes).  Log part by kernel split with real moments; smooth and
+   Cauchy parts by the plain rule (smooth on the curve), with the on-curve
+   limits at a node: G^S(0) for the single layer and kappa/(4 pi) for the
+   double layer. */
+template <int NQ>
+__host__ __device__ inline void leaf_oncurve(const cplx *a, const double *tq, const double *wq, double ta, double tb,
+                                             cplx z, double tstar, int at, double alpha, double *Ws, double *Wd)
+{
+    NodeGeo g[NQ];
+    double WS[NQ], WD[NQ];
+    rule_geo<NQ>(a, tq, wq, ta, tb, g);
+    const double mid = 0.5 * (ta + tb), half = 0.5 * (tb - ta);
+    const double ss = (tstar - mid) / half;
+    double MC[NQ + 1], ML[NQ], pl[NQ];
+    legendre_moments_real<NQ>(ss, MC, ML);
+    moments_to_weights<NQ>(NQ == 16 ? LEGW16 : LEGW32, ML, pl);
+    const double la = log(alpha);
+    const double a2 = alpha * alpha;
+    for (int k = 0; k < NQ; ++k) {
+        const double sp_ = cabs(g[k].dtau);
+        if (k == at) {
+            /* on-curve limits at the target node */
+            cplx p, dp, d2;
+            leg_eval(a, mk(tstar, 0.0), p, dp, &d2);
+            const double sp1 = cabs(dp);
+            const double kappa = (dp.re * d2.im - dp.im * d2.re) / (sp1 * sp1 * sp1);
+            const double logw = fma(sp_, pl[k], g[k].w * log(half * sp1));
+            const Split s0 = split_k01(0.0);
+            WS[k] = INV_2PI * (fma(-s0.i0, la, s0.k0s) * g[k].w - s0.i0 * logw);
+            WD[k] = 0.5 * INV_2PI * kappa * g[k].w;
+            continue;
+        }
+        /* target on the curve: form y - x, (x - y).n and |y - x|^2 from divided
+           differences so that no cancellation occurs near the target */
+        const double tk = mid + half * tq[k];
+        const double dl = tk - tstar;
+        cplx Qp, Rp;
+        leg_divdiff2(a, tk, tstar, Qp, Rp);
+        const double qq = cabs2(Qp);
+        const double r2 = dl * dl * qq;
+        const double r = sqrt(r2);
+        const double spp = cabs(Qp + dl * Rp);            /* |p'(t_k)| */
+        const double xr = (Qp.re * Rp.im - Qp.im * Rp.re) / (qq * spp); /* (x-y).n / r^2 */
+        const double xn = xr * r2;
+        const double logw = fma(sp_, pl[k], g[k].w * log(half * sqrt(qq)));
+        const Split s = split_k01(alpha * r);
+        WS[k] = INV_2PI * (fma(-s.i0, la, s.k0s) * g[k].w - s.i0 * logw);
+        const double Sd = a2 * fma(s.i1z, la, s.k1sz), Ld = a2 * s.i1z;
+        WD[k] = INV_2PI * (xn * fma(Sd, g[k].w, Ld * logw) + xr * g[k].w);
+    }
+    if (NQ == 16 && ta == -1.0 && tb == 1.0) {
+        for (int j = 0; j < 16; ++j) {
+            Ws[j] += WS[j];
+            Wd[j] += WD[j];
+        }
+    } else {
+        fold_add<NQ>(tq, ta, tb, WS, WD, Ws, Wd);
+    }
+}
+
+/* Estimated arclength of [ta, tb] of the parent panel of arclength h. */
+__host__ __device__ inline double sub_len(double h, double ta, double tb) { return 0.5 * h * (tb - ta); }
+
+/* One interval of the (possibly subdivided) parent: classify by the Bernstein
+   radius of the target's local preimage and apply the matching rule. */
+__host__ __device__ inline void leaf_apply(const cplx *a, double ta, double tb, cplx z, cplx tstar, double alpha,
+                                           const NearParams &P, double *Ws, double *Wd)
+{
+    const double mid = 0.5 * (ta + tb), half = 0.5 * (tb - ta);
+    const cplx ss = (1.0 / half) * (tstar - mk(mid, 0.0));
+    const double rho = bernstein_rho(ss);
+    if (rho >= P.rho_direct)
+        leaf_direct<16>(a, GL16_T, GL16_W, ta, tb, z, alpha, Ws, Wd);
+    else if (rho >= P.rho_split)
+        leaf_direct<32>(a, GL32_T, GL32_W, ta, tb, z, alpha, Ws, Wd);
+    else
+        leaf_split32(a, ta, tb, z, tstar, alpha, Ws, Wd);
+}
+
+/* Recursive bisection of [ta, tb] towards the target until every piece either
+   satisfies alpha h <= ah_max or is far enough that its contribution is below
+   exp(-far_exp) of the kernel at the target's distance scale. */
+__host__ __device__ inline void subdivide(const cplx *a, double h, double ta, double tb, cplx z, cplx tstar,
+                                          double alpha, const NearParams &P, double *Ws, double *Wd)
+{
+    double st_a[64], st_b[64];
+    int top = 0;
+    st_a[top] = ta;
+    st_b[top] = tb;
+    ++top;
+    while (top > 0) {
+        --top;
+        const double a0 = st_a[top], b0 = st_b[top];
+        const double hs = sub_len(h, a0, b0);
+        bool leaf = alpha * hs <= P.ah_max || top >= 60 || (b0 - a0) < 1e-12;
+        if (!leaf) {
+            const double mid = 0.5 * (a0 + b0), half = 0.5 * (b0 - a0);
+            const cplx ss = (1.0 / half) * (tstar - mk(mid, 0.0));
+            if (bernstein_rho(ss) >= P.rho_direct) {
+                cplx pm, dpm;
+                leg_eval(a, mk(mid, 0.0), pm, dpm);
+                const double dist = cabs(pm - z) - 0.5 * hs;
+                if (alpha * dist >= P.far_exp) leaf = true;
+            }
+        }
+        if (leaf) {
+            leaf_apply(a, a0, b0, z, tstar, alpha, P, Ws, Wd);
+        } else {
+            const double m = 0.5 * (a0 + b0);
+            st_a[top] = a0; st_b[top] = m; ++top;
+            st_a[top] = m; st_b[top] = b0; ++top;
+        }
+    }
+}
+
+/* Correction weights of target z against a panel with Legendre coefficients a
+   (position) and arclength h.  self: index of the node of this panel that the
+   target is (on-surface evaluation), or -1; tstar: preimage of the target
+   (for self, the node's parameter). */
+__host__ __device__ inline void pair_weights(const cplx *a, double h, cplx z, int self, cplx tstar, double alpha,
+                                             const NearParams &P, double *Ws, double *Wd)
+{
+    for (int j = 0; j < 16; ++j) Ws[j] = Wd[j] = 0.0;
+    if (self >= 0) {
+        const double ts = GL16_T[self];
+        if (alpha * h <= P.ah_max) {
+            /* upsampled: the 32-point rule integrates (degree-15 density) x
+               (smooth kernel factor) x log exactly to rounding */
+            leaf_oncurve<32>(a, GL32_T, GL32_W, -1.0, 1.0, z, ts, -1, alpha, Ws, Wd);
+            return;
+        }
+        /* central piece holding the target, then the rest subdivided */
+        const double d = P.ah_max / (alpha * h);
+        const double c0 = ts - d > -1.0 ? ts - d : -1.0;
+        const double c1 = ts + d < 1.0 ? ts + d : 1.0;
+        leaf_oncurve<32>(a, GL32_T, GL32_W, c0, c1, z, ts, -1, alpha, Ws, Wd);
+        if (c0 > -1.0) subdivide(a, h, -1.0, c0, z, mk(ts, 0.0), alpha, P, Ws, Wd);
+        if (c1 < 1.0) subdivide(a, h, c1, 1.0, z, mk(ts, 0.0), alpha, P, Ws, Wd);
+        return;
+    }
+    if (alpha * h <= P.ah_max)
+        leaf_apply(a, -1.0, 1.0, z, tstar, alpha, P, Ws, Wd);
+    else
+        subdivide(a, h, -1.0, 1.0, z, tstar, alpha, P, Ws, Wd);
+}
+
+} // namespace mhlp

@@ -1,0 +1,219 @@
+"""Thin ctypes binding of ``libmhlp.so`` (include/mhlp.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of the library.  PyTorch supplies device memory and the current stream.
+Importing works without a GPU; any call raises if the library is missing or no
+HIP device is present.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmhlp.so")
+
+FP64 = 0
+MIXED = 1
+
+OK = 0
+NOT_CONVERGED = 1
+
+_lib = None
+
+_c_double_p = ctypes.POINTER(ctypes.c_double)
+
+
+class MhlpError(RuntimeError):
+    pass
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("near_factor", ctypes.c_double), ("rho_direct", ctypes.c_double), ("rho_split", ctypes.c_double),
+                ("ah_max", ctypes.c_double), ("far_exp", ctypes.c_double)]
+
+
+class GmresOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("restart", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("use_x0", ctypes.c_int32)]
+
+
+class GmresInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("restarts", ctypes.c_int32), ("rel_residual", ctypes.c_double),
+                ("x0_residual", ctypes.c_double), ("converged", ctypes.c_int32), ("used_x0", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+# every symbol the header declares: name -> (argtypes, restype)
+_V = ctypes.c_void_p
+_SIGS = {
+    "mhlp_last_error": ([], ctypes.c_char_p),
+    "mhlp_geometry_create": ([_V, ctypes.c_int64, _V, ctypes.POINTER(_V)], ctypes.c_int32),
+    "mhlp_geometry_destroy": ([_V], ctypes.c_int32),
+    "mhlp_geometry_arrays": ([_V, ctypes.POINTER(_V), ctypes.POINTER(_V), ctypes.POINTER(_V), ctypes.POINTER(_V)],
+                             ctypes.c_int32),
+    "mhlp_plan_create": ([_V, ctypes.c_double, _V, _V, ctypes.c_int64, ctypes.POINTER(Params), _V, ctypes.POINTER(_V)],
+                         ctypes.c_int32),
+    "mhlp_plan_destroy": ([_V], ctypes.c_int32),
+    "mhlp_plan_info": ([_V, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                        ctypes.POINTER(ctypes.c_int64), _c_double_p], ctypes.c_int32),
+    "mhlp_eval_layer": ([_V, _V, _V, _V, _V, ctypes.c_int32, _V], ctypes.c_int32),
+    "mhlp_eval_slp": ([_V, _V, _V, ctypes.c_int32, _V], ctypes.c_int32),
+    "mhlp_eval_dlp": ([_V, _V, _V, ctypes.c_int32, _V], ctypes.c_int32),
+    "mhlp_apply_bie_operator": ([_V, _V, _V, ctypes.c_int32, _V], ctypes.c_int32),
+    "mhlp_gmres_solve": ([_V, _V, _V, ctypes.POINTER(GmresOpts), ctypes.POINTER(GmresInfo), _V], ctypes.c_int32),
+}
+
+
+def load(path: str = LIB_PATH):
+    """Load the library (raises MhlpError if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise MhlpError(f"{path} is not built; run __graft_entry__.build() or paper_1908_07392_amd/build.py")
+    L = ctypes.CDLL(path)
+    for name, (args, res) in _SIGS.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def _check(rc, what):
+    if rc < 0:
+        msg = load().mhlp_last_error().decode(errors="replace")
+        raise MhlpError(f"{what} failed ({rc}): {msg}")
+    return rc
+
+
+def _dev(t: torch.Tensor, name: str, n: int | None = None) -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise MhlpError(f"{name} must be a HIP device tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise MhlpError(f"{name} must be contiguous float64")
+    if n is not None and t.numel() != n:
+        raise MhlpError(f"{name} must have {n} elements, has {t.numel()}")
+    return t.data_ptr()
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Geometry:
+    """Panel geometry on the device from a ``[6][N]`` float64 node array."""
+
+    def __init__(self, node_soa: torch.Tensor):
+        L = load()
+        if node_soa.dim() != 2 or node_soa.shape[0] != 6 or node_soa.shape[1] % 16:
+            raise MhlpError("node_soa must be [6][16*n_panels]")
+        self.n_nodes = int(node_soa.shape[1])
+        self.n_panels = self.n_nodes // 16
+        self.device = node_soa.device
+        h = ctypes.c_void_p()
+        _check(L.mhlp_geometry_create(_dev(node_soa, "node_soa"), self.n_panels, _stream(), ctypes.byref(h)),
+               "geometry_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().mhlp_geometry_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan:
+    """Targets + near-field corrections (``tx``/``ty`` None: on-surface plan)."""
+
+    def __init__(self, geom: Geometry, alpha: float, tx: torch.Tensor | None = None, ty: torch.Tensor | None = None,
+                 params: dict | None = None):
+        L = load()
+        self.geom = geom
+        self.alpha = float(alpha)
+        prm = None
+        if params:
+            prm = Params(**{k: float(v) for k, v in params.items()})
+        h = ctypes.c_void_p()
+        if tx is None:
+            m, ptx, pty = 0, None, None
+        else:
+            m = int(tx.numel())
+            ptx, pty = _dev(tx, "tx"), _dev(ty, "ty", m)
+        _check(L.mhlp_plan_create(geom.handle, self.alpha, ptx, pty, m, ctypes.byref(prm) if prm else None, _stream(),
+                                  ctypes.byref(h)), "plan_create")
+        self._h = h
+        nt, ns, nn = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(L.mhlp_plan_info(h, ctypes.byref(nt), ctypes.byref(ns), ctypes.byref(nn), None), "plan_info")
+        self.n_targets, self.n_sources, self.n_near_pairs = nt.value, ns.value, nn.value
+        self.onsurface = tx is None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().mhlp_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def eval_layer(plan: Plan, sigma=None, mu=None, precision=FP64, out_slp=None, out_dlp=None):
+    """Single layer of sigma and/or double layer of mu at the plan's targets."""
+    L = load()
+    N, M = plan.n_sources, plan.n_targets
+    dev = plan.geom.device
+    ps = pm = us = ud = None
+    if sigma is not None:
+        ps = _dev(sigma, "sigma", N)
+        out_slp = torch.empty(M, dtype=torch.float64, device=dev) if out_slp is None else out_slp
+        us = _dev(out_slp, "u_slp", M)
+    if mu is not None:
+        pm = _dev(mu, "mu", N)
+        out_dlp = torch.empty(M, dtype=torch.float64, device=dev) if out_dlp is None else out_dlp
+        ud = _dev(out_dlp, "u_dlp", M)
+    _check(L.mhlp_eval_layer(plan.handle, ps, pm, us, ud, int(precision), _stream()), "eval_layer")
+    return (out_slp if sigma is not None else None), (out_dlp if mu is not None else None)
+
+
+def apply_bie(plan: Plan, mu, precision=FP64, out=None):
+    """(1/2 I + D) mu on an on-surface plan."""
+    L = load()
+    N = plan.n_sources
+    out = torch.empty(N, dtype=torch.float64, device=plan.geom.device) if out is None else out
+    _check(L.mhlp_apply_bie_operator(plan.handle, _dev(mu, "mu", N), _dev(out, "out", N), int(precision), _stream()),
+           "apply_bie_operator")
+    return out
+
+
+def gmres_solve(plan: Plan, g, x0=None, tol=1e-10, max_iter=500, restart=100, precision=FP64):
+    """Solve (1/2 I + D) mu = g; returns (mu, info dict)."""
+    L = load()
+    N = plan.n_sources
+    mu = torch.zeros(N, dtype=torch.float64, device=plan.geom.device) if x0 is None else x0.clone()
+    opts = GmresOpts(float(tol), int(max_iter), int(restart), int(precision), 0 if x0 is None else 1)
+    info = GmresInfo()
+    rc = L.mhlp_gmres_solve(plan.handle, _dev(g, "g", N), _dev(mu, "mu", N), ctypes.byref(opts), ctypes.byref(info),
+                            _stream())
+    _check(rc, "gmres_solve")
+    return mu, info.as_dict()

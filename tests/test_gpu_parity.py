@@ -1,0 +1,187 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Tolerances (relative to the largest |oracle value| of the compared set):
+  * off-surface potentials, FP64: 1e-11 (near-field quadrature error of the
+    kernel-split rule is ~1e-13..1e-12; rounding of the direct sums ~1e-14);
+  * on-surface operator, FP64: 1e-11 (the on-surface double layer is
+    conditioned at ~1e-13 w.r.t. 1-ulp node rounding; see the oracle pins);
+  * GMRES: true relative residual <= tol and solution within 1e-9 of the
+    oracle's dense solve.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.special as sp
+import torch
+
+import oracle
+from paper_1908_07392_amd import mhlp
+from paper_1908_07392_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _t(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=DEV)
+
+
+def _geom(g):
+    return mhlp.Geometry(_t(g.node_soa()))
+
+
+def _relerr(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(np.max(np.abs(b)), 1e-300))
+
+
+def test_config1_circle_vs_oracle_and_closed_form():
+    c = wl.config1()
+    g = c["geom"]
+    G = _geom(g)
+    P = mhlp.Plan(G, c["alpha"], _t(c["tx"]), _t(c["ty"]))
+    sig = _t(c["sigma"])
+    us, ud = mhlp.eval_layer(P, sigma=sig, mu=sig)
+    torch.cuda.synchronize()
+    us, ud = us.cpu().numpy(), ud.cpu().numpy()
+    os_, od = oracle.eval_potentials(g.x, g.y, c["alpha"], c["tx"], c["ty"], sigma=c["sigma"], mu=c["sigma"])
+    print("config1 near pairs", P.n_near_pairs, "slp err", _relerr(us, os_), "dlp err", _relerr(ud, od))
+    assert _relerr(us, os_) < 1e-11
+    assert _relerr(ud, od) < 1e-11
+    # closed form (Graf's addition theorem)
+    r = np.hypot(c["tx"], c["ty"])
+    th = np.arctan2(c["ty"], c["tx"])
+    n = np.arange(len(c["coeffs"]))
+    E = np.exp(1j * np.outer(th, n))
+    In = sp.iv(n[None, :], c["alpha"] * r[:, None])
+    slp = np.real((E * In * sp.kv(n, c["alpha"])) @ c["coeffs"])
+    dlp = np.real((E * (-c["alpha"]) * In * sp.kvp(n, c["alpha"])) @ c["coeffs"])
+    assert _relerr(us, slp) < 1e-11
+    assert _relerr(ud, dlp) < 1e-11
+
+
+def _near_targets(curve, rng, n_each=12):
+    th = rng.uniform(0, 2 * math.pi, n_each)
+    z, dz, _ = curve.eval(th)
+    nrm = 1j * dz / np.abs(dz)
+    pts = []
+    for d in (3e-2, 1e-3, 1e-5, 1e-8):
+        pts.append(z + d * nrm)
+    pts.append(rng.uniform(-0.5, 0.5, n_each) + 1j * rng.uniform(-0.5, 0.5, n_each))
+    p = np.concatenate(pts)
+    return p.real.copy(), p.imag.copy()
+
+
+@pytest.mark.parametrize("alpha", [5.0, 50.0, 500.0])
+def test_starfish_near_targets_vs_oracle(alpha):
+    rng = np.random.default_rng(21)
+    curve = wl.starfish_curve()
+    g = wl.discretize(curve, 64)
+    tx, ty = _near_targets(curve, rng)  # 60 targets: ragged w.r.t. the 256-thread tiles
+    sigma = wl.fourier_density(g.theta, wl.random_fourier_coeffs(rng, 8))
+    mu = wl.fourier_density(g.theta, wl.random_fourier_coeffs(rng, 8))
+    G = _geom(g)
+    P = mhlp.Plan(G, alpha, _t(tx), _t(ty))
+    us, ud = mhlp.eval_layer(P, sigma=_t(sigma), mu=_t(mu))
+    torch.cuda.synchronize()
+    os_, od = oracle.eval_potentials(g.x, g.y, alpha, tx, ty, sigma=sigma, mu=mu)
+    es, ed = _relerr(us.cpu().numpy(), os_), _relerr(ud.cpu().numpy(), od)
+    print(f"alpha={alpha} pairs={P.n_near_pairs} slp {es:.2e} dlp {ed:.2e}")
+    assert es < 1e-11 and ed < 1e-11
+
+
+@pytest.mark.parametrize("alpha", [5.0, 50.0, 500.0])
+def test_onsurface_operator_vs_oracle(alpha):
+    rng = np.random.default_rng(5)
+    g = wl.discretize(wl.starfish_curve(), 48)
+    mu = wl.fourier_density(g.theta, wl.random_fourier_coeffs(rng, 6))
+    S, D = oracle.onsurface_matrices(g.x, g.y, alpha, want_slp=True)
+    G = _geom(g)
+    P = mhlp.Plan(G, alpha)
+    out = mhlp.apply_bie(P, _t(mu)).cpu().numpy()
+    ref = oracle.apply_bie(D, mu)
+    us, ud = mhlp.eval_layer(P, sigma=_t(mu), mu=_t(mu))
+    # the principal-value D tends to 0 as alpha grows (eigenvalues of 1/2 I + D tend to 1/2),
+    # so its error is measured against the scale of the operator's action, max|mu|
+    e1, e2 = _relerr(out, ref), _relerr(us.cpu().numpy(), S @ mu)
+    e3 = float(np.max(np.abs(ud.cpu().numpy() - D @ mu)) / np.max(np.abs(mu)))
+    print(f"alpha={alpha} pairs={P.n_near_pairs} bie {e1:.2e} slp {e2:.2e} dlp {e3:.2e}")
+    assert e1 < 1e-11 and e2 < 1e-11 and e3 < 1e-11
+
+
+def test_gmres_circle_modal():
+    R, alpha = 1.0, 10.0
+    g = wl.discretize(wl.Curve("circle", R=R), 32)
+    x = alpha * R
+
+    def lam(n):
+        return x * sp.ive(n, x) * 0.5 * (sp.kve(n - 1, x) + sp.kve(n + 1, x))
+
+    b = np.cos(3 * g.theta) + 0.5 * np.sin(7 * g.theta)
+    P = mhlp.Plan(_geom(g), alpha)
+    mu, info = mhlp.gmres_solve(P, _t(b), tol=1e-12)
+    exact = np.cos(3 * g.theta) / lam(3) + 0.5 * np.sin(7 * g.theta) / lam(7)
+    print(info)
+    assert info["converged"] and info["rel_residual"] <= 1e-12
+    assert np.max(np.abs(mu.cpu().numpy() - exact)) < 1e-10
+
+
+@pytest.mark.parametrize("alpha", [5.0, 500.0])
+def test_gmres_starfish_vs_oracle_solve(alpha):
+    g = wl.discretize(wl.starfish_curve(), 40)
+    _, D = oracle.onsurface_matrices(g.x, g.y, alpha)
+    A = 0.5 * np.eye(g.n_nodes) + D
+    zs = np.array([2.0 * np.exp(0.4j), 2.0 * np.exp(2.9j)])
+    b, _ = wl.point_source_data(g.x, g.y, alpha, zs, np.array([1.0, -0.7]))
+    b = b / np.max(np.abs(b))
+    ref = np.linalg.solve(A, b)
+    P = mhlp.Plan(_geom(g), alpha)
+    mu, info = mhlp.gmres_solve(P, _t(b), tol=1e-10)
+    print(info)
+    assert info["converged"] and info["rel_residual"] <= 1e-10
+    assert _relerr(mu.cpu().numpy(), ref) < 1e-8
+
+
+def test_config2_full_size_sampled():
+    """Full config-2 target set at alpha=50: the launch the benchmark times,
+    checked on sampled targets (nearest to the boundary and random)."""
+    c = wl.config2(alphas=(50.0,))
+    g = c["geom"]
+    alpha = 50.0
+    rng = np.random.default_rng(2)
+    sigma = wl.fourier_density(g.theta, wl.random_fourier_coeffs(rng, 8))
+    mu = wl.fourier_density(g.theta, wl.random_fourier_coeffs(rng, 8))
+    G = _geom(g)
+    P = mhlp.Plan(G, alpha, _t(c["tx"]), _t(c["ty"]))
+    us, ud = mhlp.eval_layer(P, sigma=_t(sigma), mu=_t(mu))
+    us, ud = us.cpu().numpy(), ud.cpu().numpy()
+    # sample: 64 closest to the boundary + 64 random
+    curve = wl.starfish_curve()
+    dist = curve.radius_at(np.arctan2(c["ty"], c["tx"])) - np.hypot(c["tx"], c["ty"])
+    idx = np.concatenate([np.argsort(dist)[:64], rng.choice(len(dist), 64, replace=False)])
+    os_, od = oracle.eval_potentials(g.x, g.y, alpha, c["tx"][idx], c["ty"][idx], sigma=sigma, mu=mu)
+    es, ed = _relerr(us[idx], os_), _relerr(ud[idx], od)
+    print(f"config2 M={P.n_targets} pairs={P.n_near_pairs} slp {es:.2e} dlp {ed:.2e}")
+    assert es < 1e-11 and ed < 1e-11
+    assert np.all(np.isfinite(us)) and np.all(np.isfinite(ud))
+
+
+def test_edge_single_panel_and_single_target():
+    g = wl.discretize(wl.Curve("ellipse", a=1.0, b=0.6), 1)
+    tx, ty = np.array([0.1]), np.array([0.05])
+    P = mhlp.Plan(_geom(g), 3.0, _t(tx), _t(ty))
+    sig = np.cos(g.theta)
+    us, ud = mhlp.eval_layer(P, sigma=_t(sig), mu=_t(sig))
+    os_, od = oracle.eval_potentials(g.x, g.y, 3.0, tx, ty, sigma=sig, mu=sig)
+    assert _relerr(us.cpu().numpy(), os_) < 1e-11 and _relerr(ud.cpu().numpy(), od) < 1e-11
+
+
+def test_invalid_arguments_raise():
+    g = wl.discretize(wl.Curve("circle"), 4)
+    G = _geom(g)
+    with pytest.raises(mhlp.MhlpError):
+        mhlp.Plan(G, -1.0)
+    P = mhlp.Plan(G, 2.0, _t(np.array([0.0])), _t(np.array([0.0])))
+    with pytest.raises(mhlp.MhlpError):
+        mhlp.apply_bie(P, _t(np.zeros(g.n_nodes)))
