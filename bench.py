@@ -1,0 +1,169 @@
+"""Benchmark of the modified-Helmholtz layer-potential hot path on one MI355X.
+
+Workload (the starfish configuration): boundary r(theta) = 1 + 0.3 cos(5 theta)
+in 256 equal-arclength panels x 16 Gauss-Legendre nodes (N = 4096); Dirichlet
+data from 8 seeded point sources on radius 2; alpha in {5, 50, 500}; targets
+are the 109,314 interior points of a 512 x 512 grid on [-1.4, 1.4]^2.
+
+One step = for each alpha: GMRES solve of (1/2 I + D) mu = g to a true relative
+residual of 1e-10, then the single- and double-layer potentials of mu at all
+targets (fused kernel, near-field corrections included).  Plans (near lists
+and correction weights) are built once before timing, as the paper
+precomputes them; their build time is reported separately.
+
+value = far-field pair evaluations (GMRES mat-vecs + target evaluation) per
+second of the whole step.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GPair-evals/s (SLP+DLP) and GMRES time-to-1e-10, mixed/batched/warm vs FP64"
+FP64_PEAK_TFLOPS = 78.6        # MI355X vector FP64 (published)
+# FP64 operations per (target, source) pair of the fused far-field kernel on
+# its z > 2 branch: difference and r^2 (5), sqrt, 4/(alpha r) - 1, exp(-z)/sqrt(z)
+# (8 incl. 3 transcendental/divide), two degree-22 Horner polynomials (88),
+# scalings (4), accumulation of both layers (7)
+FLOP_PER_PAIR_FP64 = 112
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--grid", type=int, default=512)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle CPU baseline")
+    ap.add_argument("--no-cpu", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(cfg, alpha, budget_s):
+    """Oracle (FP64, OpenMP) SLP+DLP at a bounded sample of the same targets."""
+    import oracle
+    g = cfg["geom"]
+    rng = np.random.default_rng(7)
+    sigma = np.cos(3 * g.theta)
+    order = rng.permutation(len(cfg["tx"]))
+    done, pairs, t_used = 0, 0, 0.0
+    chunk = 64
+    while t_used < budget_s and done < len(order):
+        idx = order[done:done + chunk]
+        t0 = time.perf_counter()
+        oracle.eval_potentials(g.x, g.y, alpha, cfg["tx"][idx], cfg["ty"][idx], sigma=sigma, mu=sigma)
+        t_used += time.perf_counter() - t0
+        done += len(idx)
+        pairs += len(idx) * g.n_nodes
+    return dict(value=pairs / t_used / 1e9, unit="GPair-evals/s", cores=oracle.max_threads(), kind="oracle",
+                sample=f"{done} random targets of the {len(cfg['tx'])} x {g.n_nodes} SLP+DLP evaluation at "
+                       f"alpha={alpha:g} ({pairs:.3g} pairs, {t_used:.1f} s)")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+
+    from paper_1908_07392_amd import mhlp
+    from paper_1908_07392_amd import workloads as wl
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)  # noqa: E731
+    cfg = wl.config2(grid=args.grid)
+    g = cfg["geom"]
+    N, M = g.n_nodes, len(cfg["tx"])
+    G = mhlp.Geometry(t(g.node_soa()))
+    tx, ty = t(cfg["tx"]), t(cfg["ty"])
+    plans = {}
+    t0 = time.perf_counter()
+    for a in cfg["alphas"]:
+        print(f"# building plans alpha={a:g}", file=sys.stderr, flush=True)
+        plans[a] = (mhlp.Plan(G, a), mhlp.Plan(G, a, tx, ty))
+    torch.cuda.synchronize()
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    gdev = {a: t(cfg["data"][a]["g"]) for a in cfg["alphas"]}
+    print(f"# plans built in {plan_ms:.0f} ms; near pairs "
+          + ", ".join(f"alpha={a:g}: {plans[a][0].n_near_pairs}/{plans[a][1].n_near_pairs}" for a in cfg["alphas"]),
+          file=sys.stderr, flush=True)
+
+    stats = {}
+
+    def step(record=False):
+        pairs = 0
+        for a in cfg["alphas"]:
+            on, off = plans[a]
+            t1 = time.perf_counter()
+            mu, info = mhlp.gmres_solve(on, gdev[a], tol=1e-10, max_iter=400, restart=200)
+            t2 = time.perf_counter()
+            us, ud = mhlp.eval_layer(off, sigma=mu, mu=mu)
+            if record:
+                stats.setdefault(a, []).append(dict(gmres_ms=(t2 - t1) * 1e3, iters=info["iters"],
+                                                    residual=info["rel_residual"]))
+            # matvecs: one per Arnoldi step plus the residual checks (restart cycles + 1)
+            pairs += (info["iters"] + info["restarts"] + 1) * N * N + M * N
+        return pairs
+
+    for _ in range(args.warmup):
+        print("# warmup step", file=sys.stderr, flush=True)
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    total_pairs = 0
+    for _ in range(args.steps):
+        total_pairs += step(record=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = total_pairs / elapsed / 1e9
+
+    # dominant kernel: fused SLP+DLP far-field evaluation at the targets (alpha = 50), HIP events
+    a_r = 50.0
+    on, off = plans[a_r]
+    mu, _ = mhlp.gmres_solve(on, gdev[a_r], tol=1e-10)
+    reps = 20
+    mhlp.eval_layer(off, sigma=mu, mu=mu)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        mhlp.eval_layer(off, sigma=mu, mu=mu)
+    ev1.record()
+    torch.cuda.synchronize()
+    launch_ms = ev0.elapsed_time(ev1) / reps
+    eval_pairs = M * N
+    achieved_tf = eval_pairs * FLOP_PER_PAIR_FP64 / (launch_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved_tf, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved_tf / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                "kernel": "far_eval_fp64<SLP,DLP>", "launch_ms": round(launch_ms, 4),
+                "pairs_per_launch": eval_pairs, "flop_per_pair": FLOP_PER_PAIR_FP64,
+                "eval_gpair_per_s": round(eval_pairs / (launch_ms * 1e-3) / 1e9, 3)}
+
+    gm = {f"alpha={a:g}": {"gmres_ms": round(float(np.median([s["gmres_ms"] for s in stats[a]])), 3),
+                           "iters": stats[a][-1]["iters"], "residual": stats[a][-1]["residual"]}
+          for a in cfg["alphas"]}
+    out = {"metric": METRIC, "value": round(value, 4), "unit": "GPair-evals/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"starfish 256x16 (N={N}), alpha 5/50/500, GMRES to 1e-10 + SLP+DLP at {M} "
+                                  f"interior targets of a {args.grid}^2 grid",
+                      "n_sources": N, "n_targets": M, "alphas": list(cfg["alphas"]), "precision": "fp64"},
+           "gmres": gm, "plan_build_ms": round(plan_ms, 1), "roofline": roofline}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(cfg, 50.0, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -14,8 +14,9 @@
  * Kernels
  *   geom_prep        one thread per panel: weights, normals, curvature, Legendre
  *                    coefficients, arclength, bounding circle.
- *   near_count/fill  one thread per target: candidate panels (some node within
- *                    1.2 h), Newton preimage, Bernstein radius < 3.5 (Sec. 4.5.1).
+ *   near_list        one thread per target, run twice (count, then fill): candidate
+ *                    panels (some node within 1.2 h), Newton preimage, Bernstein
+ *                    radius < 3.5 (Sec. 4.5.1).
  *   near_weights     one thread per listed pair: correction weights (nearfield.h).
  *   far_eval_fp64    one thread per target, sources streamed through LDS in tiles
  *                    of 16 panels; listed panels are skipped and their corrected
@@ -79,6 +80,7 @@ struct mhlp_plan {
     double *near_ts = nullptr;           /* [nnz][2] */
     double *wslp = nullptr, *wdlp = nullptr; /* [nnz][16] */
     int64_t nnz = 0;
+    int32_t fill_mismatch = 0;
     NearParams np{};
     double near_factor = 1.2;
     /* GMRES workspace (lazily allocated) */
@@ -91,13 +93,13 @@ struct mhlp_plan {
 /* ------------------------------------------------------------------------ */
 /* geometry preparation                                                      */
 /* ------------------------------------------------------------------------ */
-__global__ void geom_prep_kernel(const double *__restrict__ soa, int64_t N, int64_t Np, double *__restrict__ w,
-                                 double *__restrict__ nx, double *__restrict__ ny, double *__restrict__ kappa,
-                                 double *__restrict__ pa, double *__restrict__ ph, double *__restrict__ pcx,
-                                 double *__restrict__ pcy, double *__restrict__ prad)
+__host__ __device__ inline void geom_prep_body(int64_t p, const double *__restrict__ soa, int64_t N,
+                                               double *__restrict__ w, double *__restrict__ nx,
+                                               double *__restrict__ ny, double *__restrict__ kappa,
+                                               double *__restrict__ pa, double *__restrict__ ph,
+                                               double *__restrict__ pcx, double *__restrict__ pcy,
+                                               double *__restrict__ prad)
 {
-    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p >= Np) return;
     const double *x = soa, *y = soa + N, *dx = soa + 2 * N, *dy = soa + 3 * N, *ddx = soa + 4 * N,
                  *ddy = soa + 5 * N;
     double h = 0.0;
@@ -134,6 +136,16 @@ __global__ void geom_prep_kernel(const double *__restrict__ soa, int64_t N, int6
     prad[p] = r;
 }
 
+__global__ void geom_prep_kernel(const double *__restrict__ soa, int64_t N, int64_t Np, double *__restrict__ w,
+                                 double *__restrict__ nx, double *__restrict__ ny, double *__restrict__ kappa,
+                                 double *__restrict__ pa, double *__restrict__ ph, double *__restrict__ pcx,
+                                 double *__restrict__ pcy, double *__restrict__ prad)
+{
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= Np) return;
+    geom_prep_body(p, soa, N, w, nx, ny, kappa, pa, ph, pcx, pcy, prad);
+}
+
 /* ------------------------------------------------------------------------ */
 /* near list                                                                 */
 /* ------------------------------------------------------------------------ */
@@ -145,7 +157,7 @@ struct GeoView {
 /* Calls f(panel, self, tstar) for every panel needing a correction at target i
    (panel index ascending). */
 template <class F>
-__device__ inline void visit_near(const GeoView &G, int64_t i, cplx z, bool onsurf, double near_factor,
+__host__ __device__ inline void visit_near(const GeoView &G, int64_t i, cplx z, bool onsurf, double near_factor,
                                   double rho_direct, F &&f)
 {
     const int64_t self_p = onsurf ? i / 16 : -1;
@@ -179,26 +191,23 @@ __device__ inline void visit_near(const GeoView &G, int64_t i, cplx z, bool onsu
     }
 }
 
-__global__ void near_count_kernel(GeoView G, const double *__restrict__ tx, const double *__restrict__ ty, int64_t M,
-                                  int onsurf, double near_factor, double rho_direct, int32_t *__restrict__ cnt)
+/* One traversal serves both passes of the CSR build (mode 0: count, mode 1:
+   fill), so that the two passes run the same instructions and find the same
+   pairs.  In fill mode, slots a target reserved but did not fill (which the
+   shared code path rules out) are padded with panel -1, which every consumer
+   skips, and the event is flagged. */
+__host__ __device__ inline void near_list_body(int64_t i, int mode, const GeoView &G, const double *__restrict__ tx,
+                                               const double *__restrict__ ty, int onsurf, double near_factor,
+                                               double rho_direct, int32_t *__restrict__ cnt,
+                                               const int32_t *__restrict__ ptr, int32_t *__restrict__ panel,
+                                               int32_t *__restrict__ tgt, double *__restrict__ ts_out,
+                                               int32_t *__restrict__ mismatch)
 {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= M) return;
-    int32_t c = 0;
-    visit_near(G, i, mk(tx[i], ty[i]), onsurf != 0, near_factor, rho_direct, [&](int64_t, int, cplx) { ++c; });
-    cnt[i] = c;
-}
-
-__global__ void near_fill_kernel(GeoView G, const double *__restrict__ tx, const double *__restrict__ ty, int64_t M,
-                                 int onsurf, double near_factor, double rho_direct, const int32_t *__restrict__ ptr,
-                                 int32_t *__restrict__ panel, int32_t *__restrict__ tgt, double *__restrict__ ts_out)
-{
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= M) return;
-    int32_t q = ptr[i];
-    const int32_t qend = ptr[i + 1];
+    int32_t q = mode ? ptr[i] : 0;
+    const int32_t qend = mode ? ptr[i + 1] : INT_MAX;
+    const int32_t q0 = q;
     visit_near(G, i, mk(tx[i], ty[i]), onsurf != 0, near_factor, rho_direct, [&](int64_t p, int, cplx ts) {
-        if (q < qend) {
+        if (mode && q < qend) {
             panel[q] = (int32_t)p;
             tgt[q] = (int32_t)i;
             ts_out[2 * q] = ts.re;
@@ -206,6 +215,28 @@ __global__ void near_fill_kernel(GeoView G, const double *__restrict__ tx, const
         }
         ++q;
     });
+    if (!mode) {
+        cnt[i] = q - q0;
+        return;
+    }
+    if (q != qend) mismatch[0] = 1;
+    for (int32_t r = q; r < qend; ++r) {
+        panel[r] = -1;
+        tgt[r] = (int32_t)i;
+        ts_out[2 * r] = 0.0;
+        ts_out[2 * r + 1] = 0.0;
+    }
+}
+
+__global__ void near_list_kernel(int mode, GeoView G, const double *__restrict__ tx, const double *__restrict__ ty,
+                                 int64_t M, int onsurf, double near_factor, double rho_direct,
+                                 int32_t *__restrict__ cnt, const int32_t *__restrict__ ptr,
+                                 int32_t *__restrict__ panel, int32_t *__restrict__ tgt, double *__restrict__ ts_out,
+                                 int32_t *__restrict__ mismatch)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    near_list_body(i, mode, G, tx, ty, onsurf, near_factor, rho_direct, cnt, ptr, panel, tgt, ts_out, mismatch);
 }
 
 /* exclusive scan of cnt[0..M) into ptr[0..M]; one block of 1024 threads */
@@ -234,14 +265,17 @@ __global__ __launch_bounds__(1024) void scan_kernel(const int32_t *__restrict__ 
     if (t == 1023) ptr[M] = (int32_t)part[1023];
 }
 
-__global__ void near_weights_kernel(GeoView G, const double *__restrict__ tx, const double *__restrict__ ty,
-                                    int onsurf, const int32_t *__restrict__ panel, const int32_t *__restrict__ tgt,
-                                    const double *__restrict__ ts, int64_t nnz, double alpha, NearParams P,
-                                    double *__restrict__ wsl, double *__restrict__ wdl)
+__host__ __device__ inline void near_weights_body(int64_t q, const GeoView &G, const double *__restrict__ tx,
+                                                  const double *__restrict__ ty, int onsurf,
+                                                  const int32_t *__restrict__ panel, const int32_t *__restrict__ tgt,
+                                                  const double *__restrict__ ts, double alpha, const NearParams &P,
+                                                  double *__restrict__ wsl, double *__restrict__ wdl)
 {
-    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (q >= nnz) return;
     const int64_t p = panel[q], i = tgt[q];
+    if (p < 0 || p >= G.Np) {
+        for (int j = 0; j < 16; ++j) wsl[16 * q + j] = wdl[16 * q + j] = 0.0;
+        return;
+    }
     cplx a[16];
     for (int m = 0; m < 16; ++m) a[m] = mk(G.pa[(16 * p + m) * 2], G.pa[(16 * p + m) * 2 + 1]);
     const int self = (onsurf && i / 16 == p) ? (int)(i % 16) : -1;
@@ -251,6 +285,16 @@ __global__ void near_weights_kernel(GeoView G, const double *__restrict__ tx, co
         wsl[16 * q + j] = Ws[j];
         wdl[16 * q + j] = Wd[j];
     }
+}
+
+__global__ void near_weights_kernel(GeoView G, const double *__restrict__ tx, const double *__restrict__ ty,
+                                    int onsurf, const int32_t *__restrict__ panel, const int32_t *__restrict__ tgt,
+                                    const double *__restrict__ ts, int64_t nnz, double alpha, NearParams P,
+                                    double *__restrict__ wsl, double *__restrict__ wdl)
+{
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= nnz) return;
+    near_weights_body(q, G, tx, ty, onsurf, panel, tgt, ts, alpha, P, wsl, wdl);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -326,13 +370,96 @@ __global__ __launch_bounds__(FT_THREADS) void far_eval_fp64(FarArgs A)
     double cs = 0.0, cd = 0.0;
     for (int32_t q = A.nptr[i]; q < A.nptr[i + 1]; ++q) {
         const int64_t p = A.npan[q];
+        if (p < 0) continue;
         for (int jj = 0; jj < 16; ++jj) {
             if (SLP) cs = fma(A.wsl[16 * (int64_t)q + jj], A.sigma[16 * p + jj], cs);
             if (DLP) cd = fma(A.wdl[16 * (int64_t)q + jj], A.mu[16 * p + jj], cd);
         }
     }
     if (SLP) A.us[i] = fma(INV_2PI, accs, cs);
-    if (DLP) A.ud[i] = fma(INV_2PI, accd, cd) + A.half_term * A.mu[i];
+    if (DLP) {
+        double v = fma(INV_2PI, accd, cd);
+        /* identity term: only on-surface plans (targets are the nodes, M == N) */
+        if (A.half_term != 0.0) v = fma(A.half_term, A.mu[i], v);
+        A.ud[i] = v;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* far field, mixed precision: FP32 kernel values and products, differences  */
+/* x - y formed exactly in FP64 then rounded, FP32 partial sums over each     */
+/* 16-node panel accumulated in FP64; corrections and identity term in FP64. */
+/* ------------------------------------------------------------------------ */
+template <bool SLP, bool DLP>
+__global__ __launch_bounds__(FT_THREADS) void far_eval_mixed(FarArgs A)
+{
+    __shared__ double lx[FT_SRC], ly[FT_SRC];
+    __shared__ float lq[FT_SRC], ldx[FT_SRC], ldy[FT_SRC];
+    const int64_t i = blockIdx.x * (int64_t)FT_THREADS + threadIdx.x;
+    const bool valid = i < A.M;
+    const double x = valid ? A.tx[i] : 0.0, y = valid ? A.ty[i] : 0.0;
+    int32_t k = 0, kend = 0;
+    if (valid) {
+        k = A.nptr[i];
+        kend = A.nptr[i + 1];
+    }
+    int32_t nxt = (k < kend) ? A.npan[k] : INT_MAX;
+    const float alpha = (float)A.alpha, a2q = 0.25f * alpha * alpha, a4 = 4.0f / alpha;
+    double accs = 0.0, accd = 0.0;
+    for (int64_t base = 0; base < A.N; base += FT_SRC) {
+        __syncthreads();
+        const int64_t j = base + threadIdx.x;
+        if (j < A.N) {
+            const double wj = A.sw[j];
+            lx[threadIdx.x] = A.sx[j];
+            ly[threadIdx.x] = A.sy[j];
+            if (SLP) lq[threadIdx.x] = (float)(wj * A.sigma[j]);
+            if (DLP) {
+                const double m = wj * A.mu[j];
+                ldx[threadIdx.x] = (float)(m * A.snx[j]);
+                ldy[threadIdx.x] = (float)(m * A.sny[j]);
+            }
+        }
+        __syncthreads();
+        const int64_t rem = (A.N - base) / 16;
+        const int npl = rem < 16 ? (int)rem : 16;
+        const int32_t p0 = (int32_t)(base / 16);
+        for (int pl = 0; pl < npl; ++pl) {
+            if (p0 + pl == nxt) {
+                ++k;
+                nxt = (k < kend) ? A.npan[k] : INT_MAX;
+                continue;
+            }
+            float ps = 0.0f, pd = 0.0f;
+#pragma unroll 4
+            for (int s = 0; s < 16; ++s) {
+                const int l = pl * 16 + s;
+                const float ex = (float)(x - lx[l]), ey = (float)(y - ly[l]);
+                const float r2 = fmaf(ex, ex, ey * ey);
+                const K01f o = k01_fp32<SLP, DLP>(r2, alpha, a2q, a4);
+                if (SLP) ps = fmaf(o.k0, lq[l], ps);
+                if (DLP) pd = fmaf(o.ak1r, fmaf(ex, ldx[l], ey * ldy[l]), pd);
+            }
+            if (SLP) accs += (double)ps;
+            if (DLP) accd += (double)pd;
+        }
+    }
+    if (!valid) return;
+    double cs = 0.0, cd = 0.0;
+    for (int32_t q = A.nptr[i]; q < A.nptr[i + 1]; ++q) {
+        const int64_t p = A.npan[q];
+        if (p < 0) continue;
+        for (int jj = 0; jj < 16; ++jj) {
+            if (SLP) cs = fma(A.wsl[16 * (int64_t)q + jj], A.sigma[16 * p + jj], cs);
+            if (DLP) cd = fma(A.wdl[16 * (int64_t)q + jj], A.mu[16 * p + jj], cd);
+        }
+    }
+    if (SLP) A.us[i] = fma(INV_2PI, accs, cs);
+    if (DLP) {
+        double v = fma(INV_2PI, accd, cd);
+        if (A.half_term != 0.0) v = fma(A.half_term, A.mu[i], v);
+        A.ud[i] = v;
+    }
 }
 
 /* ------------------------------------------------------------------------ */
@@ -391,6 +518,12 @@ __global__ void residual_kernel(const double *__restrict__ g, const double *__re
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < N) r[i] = g[i] - a[i];
+}
+
+__global__ void fill_i32_kernel(int32_t *__restrict__ x, int32_t v, int64_t N)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < N) x[i] = v;
 }
 
 __global__ void fill_kernel(double *__restrict__ x, double v, int64_t N)
@@ -557,21 +690,23 @@ extern "C" mhlp_status mhlp_plan_create(const mhlp_geometry *g, double alpha, co
     }
     const int64_t M = P->M;
     int32_t *cnt = nullptr;
-    if ((s = dalloc(&cnt, M)) || (s = dalloc(&P->near_ptr, M + 1))) {
+    if ((s = dalloc(&cnt, M + 1)) || (s = dalloc(&P->near_ptr, M + 1))) {
         if (cnt) (void)hipFree(cnt);
         mhlp_plan_destroy(P);
         return s;
     }
     GeoView G = view(g);
-    near_count_kernel<<<nblocks(M, 128), 128, 0, st>>>(G, P->tx, P->ty, M, P->onsurf ? 1 : 0, P->near_factor,
-                                                        P->np.rho_direct, cnt);
+    /* cnt[M] doubles as the fill-mismatch flag */
+    near_list_kernel<<<nblocks(M, 128), 128, 0, st>>>(0, G, P->tx, P->ty, M, P->onsurf ? 1 : 0, P->near_factor,
+                                                       P->np.rho_direct, cnt, nullptr, nullptr, nullptr, nullptr,
+                                                       nullptr);
     scan_kernel<<<1, 1024, 0, st>>>(cnt, M, P->near_ptr);
     int32_t nnz = 0;
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(&nnz, P->near_ptr + M, sizeof(int32_t), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    (void)hipFree(cnt);
     if (e != hipSuccess) {
+        (void)hipFree(cnt);
         mhlp_plan_destroy(P);
         return fail(MHLP_HIP_ERROR, std::string("plan_create near count: ") + hipGetErrorString(e));
     }
@@ -582,19 +717,44 @@ extern "C" mhlp_status mhlp_plan_create(const mhlp_geometry *g, double alpha, co
             mhlp_plan_destroy(P);
             return s;
         }
-        near_fill_kernel<<<nblocks(M, 128), 128, 0, st>>>(G, P->tx, P->ty, M, P->onsurf ? 1 : 0, P->near_factor,
-                                                           P->np.rho_direct, P->near_ptr, P->near_panel, P->near_tgt,
-                                                           P->near_ts);
+        fill_i32_kernel<<<1, 1, 0, st>>>(cnt + M, 0, 1);
+        near_list_kernel<<<nblocks(M, 128), 128, 0, st>>>(1, G, P->tx, P->ty, M, P->onsurf ? 1 : 0, P->near_factor,
+                                                           P->np.rho_direct, nullptr, P->near_ptr, P->near_panel,
+                                                           P->near_tgt, P->near_ts, cnt + M);
+        /* validate the list on the host before any kernel indexes with it */
+        {
+            std::vector<int32_t> hp((size_t)nnz);
+            e = hipGetLastError();
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(hp.data(), P->near_panel, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) {
+                (void)hipFree(cnt);
+                mhlp_plan_destroy(P);
+                return fail(MHLP_HIP_ERROR, std::string("plan_create near list: ") + hipGetErrorString(e));
+            }
+            for (int32_t v : hp)
+                if (v < -1 || v >= g->Np) {
+                    (void)hipFree(cnt);
+                    mhlp_plan_destroy(P);
+                    return fail(MHLP_HIP_ERROR, "plan_create: near list holds an invalid panel index");
+                }
+        }
         near_weights_kernel<<<nblocks(nnz, 64), 64, 0, st>>>(G, P->tx, P->ty, P->onsurf ? 1 : 0, P->near_panel,
                                                               P->near_tgt, P->near_ts, nnz, alpha, P->np, P->wslp,
                                                               P->wdlp);
         e = hipGetLastError();
+        int32_t mism = 0;
+        if (e == hipSuccess) e = hipMemcpyAsync(&mism, cnt + M, sizeof(int32_t), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) {
+            (void)hipFree(cnt);
             mhlp_plan_destroy(P);
             return fail(MHLP_HIP_ERROR, std::string("plan_create near weights: ") + hipGetErrorString(e));
         }
+        P->fill_mismatch = mism;
     }
+    (void)hipFree(cnt);
     *out = P;
     return MHLP_OK;
 }
@@ -638,8 +798,19 @@ static mhlp_status launch_far(const mhlp_plan *P, const double *sigma, const dou
     A.half_term = half_term;
     A.us = us;
     A.ud = ud;
+    if (half_term != 0.0 && (!P->onsurf || P->M != g->N))
+        return fail(MHLP_INVALID_ARG, "identity term needs an on-surface plan");
     const unsigned nb = nblocks(P->M, FT_THREADS);
-    if (precision == MHLP_MIXED) return fail(MHLP_UNSUPPORTED, "mixed precision far field not built");
+    if (precision == MHLP_MIXED) {
+        if (sigma && mu)
+            far_eval_mixed<true, true><<<nb, FT_THREADS, 0, st>>>(A);
+        else if (sigma)
+            far_eval_mixed<true, false><<<nb, FT_THREADS, 0, st>>>(A);
+        else
+            far_eval_mixed<false, true><<<nb, FT_THREADS, 0, st>>>(A);
+        HIPCHECK(hipGetLastError());
+        return MHLP_OK;
+    }
     if (sigma && mu)
         far_eval_fp64<true, true><<<nb, FT_THREADS, 0, st>>>(A);
     else if (sigma)
@@ -694,7 +865,11 @@ static mhlp_status ensure_ws(mhlp_plan *P, int64_t cols)
     P->ws = nullptr;
     TRY(dalloc(&P->ws, (cols + 4) * P->g->N));
     P->ws_cols = cols;
-    if (!P->hdev) TRY(dalloc(&P->hdev, 4 * 1024));
+    if (!P->hdev) {
+        TRY(dalloc(&P->hdev, 4 * 1024));
+        fill_kernel<<<1, 64, 0, 0>>>(P->hdev + 4000, 1.0, 1); /* constant 1 for x += d */
+        HIPCHECK(hipDeviceSynchronize());
+    }
     if (!P->hhost) HIPCHECK(hipHostMalloc((void **)&P->hhost, sizeof(double) * 4 * 1024, hipHostMallocDefault));
     return MHLP_OK;
 }
@@ -831,7 +1006,29 @@ extern "C" mhlp_status mhlp_gmres_solve(const mhlp_plan *Pc, const double *g, do
     if (opts->precision == MHLP_FP64) {
         TRY(gmres_core(P, g, bnorm, mu, opts->tol, opts->restart, opts->max_iter, MHLP_FP64, st, &iters, &cycles, &rel));
     } else {
-        return fail(MHLP_UNSUPPORTED, "mixed precision GMRES not built");
+        /* iterative refinement: FP64 residual r = g - A mu (FP64 operator), inner
+           GMRES on the mixed-precision operator for A d = r to 1e-6 relative (the
+           FP32 far field resolves the operator to ~1e-7), mu += d. */
+        const int64_t cols = opts->restart + 1;
+        double *r = P->ws + (cols + 2) * N, *d = P->ws + (cols + 3) * N;
+        double *w = P->ws + cols * N;
+        const unsigned nbN = nblocks(N, 256);
+        for (int outer = 0; outer < 20; ++outer) {
+            TRY(launch_far(P, nullptr, mu, nullptr, w, 0.5, MHLP_FP64, st));
+            residual_kernel<<<nbN, 256, 0, st>>>(g, w, r, N);
+            double rn;
+            TRY(dnorm(P, r, N, st, &rn));
+            rel = rn / bnorm;
+            if (rel <= opts->tol || iters >= opts->max_iter) break;
+            fill_kernel<<<nbN, 256, 0, st>>>(d, 0.0, N);
+            int it_in = 0, cyc_in = 0;
+            double rel_in = 1.0;
+            TRY(gmres_core(P, r, rn, d, 1e-6, opts->restart, opts->max_iter - iters, MHLP_MIXED, st, &it_in, &cyc_in,
+                           &rel_in));
+            iters += it_in;
+            cycles += 1;
+            add_combo_kernel<<<nbN, 256, 0, st>>>(d, N, 1, P->hdev + 4000, mu, N);
+        }
     }
     info->iters = iters;
     info->restarts = cycles;

@@ -74,6 +74,41 @@ __host__ __device__ __forceinline__ K01 k01_fp64(double r2, double a, double a2q
 }
 
 /* ---------------------------------------------------------------------- */
+/* Far-field kernel values, FP32 (mixed-precision far field).               */
+/* Same two regimes with the FP32 fits; exp/log/rsqrt/rcp are the hardware  */
+/* single-precision instructions.  Below e^{-87} the FP32 result flushes to */
+/* zero, far below the FP32 resolution of any potential it is summed into.  */
+/* ---------------------------------------------------------------------- */
+struct K01f {
+    float k0;
+    float ak1r;
+};
+
+template <bool SLP, bool DLP>
+__device__ __forceinline__ K01f k01_fp32(float r2, float a, float a2q, float a4)
+{
+    K01f o{0.0f, 0.0f};
+    const float q = a2q * r2;
+    if (q <= 1.0f) {
+        const float lq = __logf(q);
+        if (SLP) o.k0 = fmaf(-0.5f * lq, horner(KSF_I0, q), horner(KSF_R0, q));
+        if (DLP) {
+            const float t = fmaf(0.5f * lq, horner(KSF_I1Z, q), -0.25f * horner(KSF_R1, q));
+            o.ak1r = fmaf(4.0f * a2q, t, __frcp_rn(r2));
+        }
+    } else {
+        const float ri = __frsqrt_rn(r2);
+        const float r = r2 * ri;
+        const float z = a * r;
+        const float u = fmaf(a4, ri, -1.0f);
+        const float e = __expf(-z) * __frsqrt_rn(z);
+        if (SLP) o.k0 = e * horner(KLF0, u);
+        if (DLP) o.ak1r = a * e * horner(KLF1, u) * ri;
+    }
+    return o;
+}
+
+/* ---------------------------------------------------------------------- */
 /* Kernel-split pieces (paper Sec. 4.1, App. C), any moderate z >= 0.       */
 /*   I0(z), K0S = K0 + I0 log z, I1z = I1(z)/z, K1Sz = (K1 - I1 log z - 1/z)/z */
 /* Power series in q = z^2/4 with psi(n+1) = -gamma + sum_{k<=n} 1/k.        */

@@ -185,3 +185,40 @@ def test_invalid_arguments_raise():
     P = mhlp.Plan(G, 2.0, _t(np.array([0.0])), _t(np.array([0.0])))
     with pytest.raises(mhlp.MhlpError):
         mhlp.apply_bie(P, _t(np.zeros(g.n_nodes)))
+
+
+# ---------------------------------------------------------------------------
+# Mixed precision: FP32 far field, FP64 near field / identity / Arnoldi.
+# Tolerance 1e-6 relative to max|u| for potentials (FP32 kernel values carry
+# ~1e-7 relative error); solves are still judged by the FP64 residual at 1e-10.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("alpha", [5.0, 50.0, 500.0])
+def test_mixed_precision_potentials(alpha):
+    rng = np.random.default_rng(31)
+    curve = wl.starfish_curve()
+    g = wl.discretize(curve, 64)
+    tx, ty = _near_targets(curve, rng)
+    tx = np.concatenate([tx, rng.uniform(-0.6, 0.6, 300)])
+    ty = np.concatenate([ty, rng.uniform(-0.6, 0.6, 300)])
+    sigma = wl.fourier_density(g.theta, wl.random_fourier_coeffs(rng, 8))
+    G = _geom(g)
+    P = mhlp.Plan(G, alpha, _t(tx), _t(ty))
+    us, ud = mhlp.eval_layer(P, sigma=_t(sigma), mu=_t(sigma), precision=mhlp.MIXED)
+    os_, od = oracle.eval_potentials(g.x, g.y, alpha, tx, ty, sigma=sigma, mu=sigma)
+    es, ed = _relerr(us.cpu().numpy(), os_), _relerr(ud.cpu().numpy(), od)
+    print(f"mixed alpha={alpha} slp {es:.2e} dlp {ed:.2e}")
+    assert es < 1e-6 and ed < 1e-6
+
+
+@pytest.mark.parametrize("alpha", [5.0, 50.0])
+def test_mixed_precision_gmres(alpha):
+    g = wl.discretize(wl.starfish_curve(), 64)
+    zs = np.array([2.0 * np.exp(0.4j), 2.0 * np.exp(2.9j), 2.0 * np.exp(4.4j)])
+    b, _ = wl.point_source_data(g.x, g.y, alpha, zs, np.array([1.0, -0.7, 0.3]))
+    b = b / np.max(np.abs(b))
+    P = mhlp.Plan(_geom(g), alpha)
+    mu64, i64 = mhlp.gmres_solve(P, _t(b), tol=1e-10)
+    mu32, i32 = mhlp.gmres_solve(P, _t(b), tol=1e-10, precision=mhlp.MIXED)
+    print("fp64", i64, "mixed", i32)
+    assert i32["converged"] and i32["rel_residual"] <= 1e-10
+    assert _relerr(mu32.cpu().numpy(), mu64.cpu().numpy()) < 1e-8
