@@ -105,6 +105,8 @@ def main():
         pairs = 0
         for a in cfg["alphas"]:
             on, off = plans[a]
+            if record:
+                torch.cuda.synchronize()  # attribute the previous evaluation to its own step
             t1 = time.perf_counter()
             mu, info = mhlp.gmres_solve(on, gdev[a], tol=1e-10, max_iter=400, restart=200)
             t2 = time.perf_counter()

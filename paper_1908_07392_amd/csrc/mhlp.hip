@@ -81,6 +81,9 @@ struct mhlp_plan {
     double *wslp = nullptr, *wdlp = nullptr; /* [nnz][16] */
     int64_t nnz = 0;
     int32_t fill_mismatch = 0;
+    int nsplit = 1;           /* source splits of the far field (small M)   */
+    int32_t pps = 0;          /* panels per split                           */
+    double *part = nullptr;   /* [2][nsplit][M] partial sums                */
     NearParams np{};
     double near_factor = 1.2;
     /* GMRES workspace (lazily allocated) */
@@ -314,59 +317,15 @@ struct FarArgs {
     double alpha;
     double half_term; /* 0.5 for (1/2 I + D) on an on-surface plan, else 0 */
     double *us, *ud;
+    int64_t Np;
+    int32_t pps;      /* panels per source split (blockIdx.y) */
+    double *part_s, *part_d; /* [nsplit][M] partial far sums when split */
 };
 
+/* Near corrections, 1/(2 pi) scaling and identity term for target i. */
 template <bool SLP, bool DLP>
-__global__ __launch_bounds__(FT_THREADS) void far_eval_fp64(FarArgs A)
+__device__ __forceinline__ void far_epilogue(const FarArgs &A, int64_t i, double accs, double accd)
 {
-    __shared__ double lx[FT_SRC], ly[FT_SRC], lq[FT_SRC], ldx[FT_SRC], ldy[FT_SRC];
-    const int64_t i = blockIdx.x * (int64_t)FT_THREADS + threadIdx.x;
-    const bool valid = i < A.M;
-    const double x = valid ? A.tx[i] : 0.0, y = valid ? A.ty[i] : 0.0;
-    int32_t k = 0, kend = 0;
-    if (valid) {
-        k = A.nptr[i];
-        kend = A.nptr[i + 1];
-    }
-    int32_t nxt = (k < kend) ? A.npan[k] : INT_MAX;
-    const double alpha = A.alpha, a2q = 0.25 * alpha * alpha, a4 = 4.0 / alpha;
-    double accs = 0.0, accd = 0.0;
-    for (int64_t base = 0; base < A.N; base += FT_SRC) {
-        __syncthreads();
-        const int64_t j = base + threadIdx.x;
-        if (j < A.N) {
-            const double wj = A.sw[j];
-            lx[threadIdx.x] = A.sx[j];
-            ly[threadIdx.x] = A.sy[j];
-            if (SLP) lq[threadIdx.x] = wj * A.sigma[j];
-            if (DLP) {
-                const double m = wj * A.mu[j];
-                ldx[threadIdx.x] = m * A.snx[j];
-                ldy[threadIdx.x] = m * A.sny[j];
-            }
-        }
-        __syncthreads();
-        const int64_t rem = (A.N - base) / 16;
-        const int npl = rem < 16 ? (int)rem : 16;
-        const int32_t p0 = (int32_t)(base / 16);
-        for (int pl = 0; pl < npl; ++pl) {
-            if (p0 + pl == nxt) {
-                ++k;
-                nxt = (k < kend) ? A.npan[k] : INT_MAX;
-                continue;
-            }
-#pragma unroll 2
-            for (int s = 0; s < 16; ++s) {
-                const int l = pl * 16 + s;
-                const double ex = x - lx[l], ey = y - ly[l];
-                const double r2 = fma(ex, ex, ey * ey);
-                const K01 o = k01_fp64<SLP, DLP>(r2, alpha, a2q, a4);
-                if (SLP) accs = fma(o.k0, lq[l], accs);
-                if (DLP) accd = fma(o.ak1r, fma(ex, ldx[l], ey * ldy[l]), accd);
-            }
-        }
-    }
-    if (!valid) return;
     double cs = 0.0, cd = 0.0;
     for (int32_t q = A.nptr[i]; q < A.nptr[i + 1]; ++q) {
         const int64_t p = A.npan[q];
@@ -385,12 +344,88 @@ __global__ __launch_bounds__(FT_THREADS) void far_eval_fp64(FarArgs A)
     }
 }
 
+/* Sum of the source-split partials in fixed order, then the epilogue. */
+template <bool SLP, bool DLP>
+__global__ void far_finalize(FarArgs A, int nsplit)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= A.M) return;
+    double s_ = 0.0, d_ = 0.0;
+    for (int k = 0; k < nsplit; ++k) {
+        if (SLP) s_ += A.part_s[k * A.M + i];
+        if (DLP) d_ += A.part_d[k * A.M + i];
+    }
+    far_epilogue<SLP, DLP>(A, i, s_, d_);
+}
+
+template <bool SLP, bool DLP, bool SPLIT>
+__global__ __launch_bounds__(FT_THREADS) void far_eval_fp64(FarArgs A)
+{
+    __shared__ double lx[FT_SRC], ly[FT_SRC], lq[FT_SRC], ldx[FT_SRC], ldy[FT_SRC];
+    const int64_t i = blockIdx.x * (int64_t)FT_THREADS + threadIdx.x;
+    const bool valid = i < A.M;
+    const double x = valid ? A.tx[i] : 0.0, y = valid ? A.ty[i] : 0.0;
+    /* this block's panel range */
+    const int64_t pb = SPLIT ? (int64_t)blockIdx.y * A.pps : 0;
+    const int64_t pe = SPLIT ? min(A.Np, pb + A.pps) : A.Np;
+    int32_t k = 0, kend = 0;
+    if (valid) {
+        k = A.nptr[i];
+        kend = A.nptr[i + 1];
+        while (k < kend && A.npan[k] >= 0 && A.npan[k] < pb) ++k;
+    }
+    int32_t nxt = (k < kend) ? A.npan[k] : INT_MAX;
+    const double alpha = A.alpha, a2q = 0.25 * alpha * alpha, a4 = 4.0 / alpha, ia = 1.0 / alpha;
+    double accs = 0.0, accd = 0.0;
+    for (int64_t base = 16 * pb; base < 16 * pe; base += FT_SRC) {
+        __syncthreads();
+        const int64_t j = base + threadIdx.x;
+        if (j < 16 * pe) {
+            const double wj = A.sw[j];
+            lx[threadIdx.x] = A.sx[j];
+            ly[threadIdx.x] = A.sy[j];
+            if (SLP) lq[threadIdx.x] = wj * A.sigma[j];
+            if (DLP) {
+                const double m = wj * A.mu[j];
+                ldx[threadIdx.x] = m * A.snx[j];
+                ldy[threadIdx.x] = m * A.sny[j];
+            }
+        }
+        __syncthreads();
+        const int32_t p0 = (int32_t)(base / 16);
+        const int npl = (pe - p0) < 16 ? (int)(pe - p0) : 16;
+        for (int pl = 0; pl < npl; ++pl) {
+            if (p0 + pl == nxt) {
+                ++k;
+                nxt = (k < kend) ? A.npan[k] : INT_MAX;
+                continue;
+            }
+#pragma unroll 2
+            for (int s = 0; s < 16; ++s) {
+                const int l = pl * 16 + s;
+                const double ex = x - lx[l], ey = y - ly[l];
+                const double r2 = fma(ex, ex, ey * ey);
+                const K01 o = k01_far_fp64<SLP, DLP>(r2, alpha, a2q, a4, ia);
+                if (SLP) accs = fma(o.k0, lq[l], accs);
+                if (DLP) accd = fma(o.ak1r, fma(ex, ldx[l], ey * ldy[l]), accd);
+            }
+        }
+    }
+    if (!valid) return;
+    if (SPLIT) {
+        if (SLP) A.part_s[blockIdx.y * A.M + i] = accs;
+        if (DLP) A.part_d[blockIdx.y * A.M + i] = accd;
+    } else {
+        far_epilogue<SLP, DLP>(A, i, accs, accd);
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* far field, mixed precision: FP32 kernel values and products, differences  */
 /* x - y formed exactly in FP64 then rounded, FP32 partial sums over each     */
 /* 16-node panel accumulated in FP64; corrections and identity term in FP64. */
 /* ------------------------------------------------------------------------ */
-template <bool SLP, bool DLP>
+template <bool SLP, bool DLP, bool SPLIT>
 __global__ __launch_bounds__(FT_THREADS) void far_eval_mixed(FarArgs A)
 {
     __shared__ double lx[FT_SRC], ly[FT_SRC];
@@ -398,18 +433,21 @@ __global__ __launch_bounds__(FT_THREADS) void far_eval_mixed(FarArgs A)
     const int64_t i = blockIdx.x * (int64_t)FT_THREADS + threadIdx.x;
     const bool valid = i < A.M;
     const double x = valid ? A.tx[i] : 0.0, y = valid ? A.ty[i] : 0.0;
+    const int64_t pb = SPLIT ? (int64_t)blockIdx.y * A.pps : 0;
+    const int64_t pe = SPLIT ? min(A.Np, pb + A.pps) : A.Np;
     int32_t k = 0, kend = 0;
     if (valid) {
         k = A.nptr[i];
         kend = A.nptr[i + 1];
+        while (k < kend && A.npan[k] >= 0 && A.npan[k] < pb) ++k;
     }
     int32_t nxt = (k < kend) ? A.npan[k] : INT_MAX;
     const float alpha = (float)A.alpha, a2q = 0.25f * alpha * alpha, a4 = 4.0f / alpha;
     double accs = 0.0, accd = 0.0;
-    for (int64_t base = 0; base < A.N; base += FT_SRC) {
+    for (int64_t base = 16 * pb; base < 16 * pe; base += FT_SRC) {
         __syncthreads();
         const int64_t j = base + threadIdx.x;
-        if (j < A.N) {
+        if (j < 16 * pe) {
             const double wj = A.sw[j];
             lx[threadIdx.x] = A.sx[j];
             ly[threadIdx.x] = A.sy[j];
@@ -421,9 +459,8 @@ __global__ __launch_bounds__(FT_THREADS) void far_eval_mixed(FarArgs A)
             }
         }
         __syncthreads();
-        const int64_t rem = (A.N - base) / 16;
-        const int npl = rem < 16 ? (int)rem : 16;
         const int32_t p0 = (int32_t)(base / 16);
+        const int npl = (pe - p0) < 16 ? (int)(pe - p0) : 16;
         for (int pl = 0; pl < npl; ++pl) {
             if (p0 + pl == nxt) {
                 ++k;
@@ -445,20 +482,11 @@ __global__ __launch_bounds__(FT_THREADS) void far_eval_mixed(FarArgs A)
         }
     }
     if (!valid) return;
-    double cs = 0.0, cd = 0.0;
-    for (int32_t q = A.nptr[i]; q < A.nptr[i + 1]; ++q) {
-        const int64_t p = A.npan[q];
-        if (p < 0) continue;
-        for (int jj = 0; jj < 16; ++jj) {
-            if (SLP) cs = fma(A.wsl[16 * (int64_t)q + jj], A.sigma[16 * p + jj], cs);
-            if (DLP) cd = fma(A.wdl[16 * (int64_t)q + jj], A.mu[16 * p + jj], cd);
-        }
-    }
-    if (SLP) A.us[i] = fma(INV_2PI, accs, cs);
-    if (DLP) {
-        double v = fma(INV_2PI, accd, cd);
-        if (A.half_term != 0.0) v = fma(A.half_term, A.mu[i], v);
-        A.ud[i] = v;
+    if (SPLIT) {
+        if (SLP) A.part_s[blockIdx.y * A.M + i] = accs;
+        if (DLP) A.part_d[blockIdx.y * A.M + i] = accd;
+    } else {
+        far_epilogue<SLP, DLP>(A, i, accs, accd);
     }
 }
 
@@ -637,7 +665,7 @@ extern "C" mhlp_status mhlp_plan_destroy(mhlp_plan *P)
         if (P->tx) (void)hipFree(P->tx);
         if (P->ty) (void)hipFree(P->ty);
     }
-    void *ptrs[] = {P->near_ptr, P->near_panel, P->near_tgt, P->near_ts, P->wslp, P->wdlp, P->ws, P->hdev};
+    void *ptrs[] = {P->near_ptr, P->near_panel, P->near_tgt, P->near_ts, P->wslp, P->wdlp, P->ws, P->hdev, P->part};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (P->hhost) (void)hipHostFree(P->hhost);
@@ -689,6 +717,20 @@ extern "C" mhlp_status mhlp_plan_create(const mhlp_geometry *g, double alpha, co
         }
     }
     const int64_t M = P->M;
+    {
+        /* source splits so that about 1024 blocks of 256 targets cover the GPU;
+           at least 4 panels per split */
+        const int64_t tblocks = (M + FT_THREADS - 1) / FT_THREADS;
+        int64_t ns = (1024 + tblocks - 1) / tblocks;
+        if (ns > g->Np / 4) ns = g->Np / 4;
+        if (ns < 1) ns = 1;
+        P->pps = (int32_t)((g->Np + ns - 1) / ns);
+        P->nsplit = (int)((g->Np + P->pps - 1) / P->pps);
+        if (P->nsplit > 1 && (s = dalloc(&P->part, 2 * (int64_t)P->nsplit * M))) {
+            mhlp_plan_destroy(P);
+            return s;
+        }
+    }
     int32_t *cnt = nullptr;
     if ((s = dalloc(&cnt, M + 1)) || (s = dalloc(&P->near_ptr, M + 1))) {
         if (cnt) (void)hipFree(cnt);
@@ -773,11 +815,32 @@ extern "C" mhlp_status mhlp_plan_info(const mhlp_plan *P, int64_t *n_targets, in
 /* ------------------------------------------------------------------------ */
 /* evaluation                                                                */
 /* ------------------------------------------------------------------------ */
+template <bool SLP, bool DLP>
+static void launch_far_t(const FarArgs &A, int nsplit, int32_t precision, hipStream_t st)
+{
+    const unsigned nb = nblocks(A.M, FT_THREADS);
+    if (nsplit <= 1) {
+        if (precision == MHLP_MIXED)
+            far_eval_mixed<SLP, DLP, false><<<nb, FT_THREADS, 0, st>>>(A);
+        else
+            far_eval_fp64<SLP, DLP, false><<<nb, FT_THREADS, 0, st>>>(A);
+        return;
+    }
+    dim3 grid(nb, nsplit);
+    if (precision == MHLP_MIXED)
+        far_eval_mixed<SLP, DLP, true><<<grid, FT_THREADS, 0, st>>>(A);
+    else
+        far_eval_fp64<SLP, DLP, true><<<grid, FT_THREADS, 0, st>>>(A);
+    far_finalize<SLP, DLP><<<nblocks(A.M, 256), 256, 0, st>>>(A, nsplit);
+}
+
 static mhlp_status launch_far(const mhlp_plan *P, const double *sigma, const double *mu, double *us, double *ud,
                               double half_term, int32_t precision, hipStream_t st)
 {
     if (precision != MHLP_FP64 && precision != MHLP_MIXED) return fail(MHLP_INVALID_ARG, "unknown precision");
     const mhlp_geometry *g = P->g;
+    if (half_term != 0.0 && (!P->onsurf || P->M != g->N))
+        return fail(MHLP_INVALID_ARG, "identity term needs an on-surface plan");
     FarArgs A;
     A.sx = g->soa;
     A.sy = g->soa + g->N;
@@ -798,25 +861,16 @@ static mhlp_status launch_far(const mhlp_plan *P, const double *sigma, const dou
     A.half_term = half_term;
     A.us = us;
     A.ud = ud;
-    if (half_term != 0.0 && (!P->onsurf || P->M != g->N))
-        return fail(MHLP_INVALID_ARG, "identity term needs an on-surface plan");
-    const unsigned nb = nblocks(P->M, FT_THREADS);
-    if (precision == MHLP_MIXED) {
-        if (sigma && mu)
-            far_eval_mixed<true, true><<<nb, FT_THREADS, 0, st>>>(A);
-        else if (sigma)
-            far_eval_mixed<true, false><<<nb, FT_THREADS, 0, st>>>(A);
-        else
-            far_eval_mixed<false, true><<<nb, FT_THREADS, 0, st>>>(A);
-        HIPCHECK(hipGetLastError());
-        return MHLP_OK;
-    }
+    A.Np = g->Np;
+    A.pps = P->pps;
+    A.part_s = P->part;
+    A.part_d = P->part + (int64_t)P->nsplit * P->M;
     if (sigma && mu)
-        far_eval_fp64<true, true><<<nb, FT_THREADS, 0, st>>>(A);
+        launch_far_t<true, true>(A, P->nsplit, precision, st);
     else if (sigma)
-        far_eval_fp64<true, false><<<nb, FT_THREADS, 0, st>>>(A);
+        launch_far_t<true, false>(A, P->nsplit, precision, st);
     else
-        far_eval_fp64<false, true><<<nb, FT_THREADS, 0, st>>>(A);
+        launch_far_t<false, true>(A, P->nsplit, precision, st);
     HIPCHECK(hipGetLastError());
     return MHLP_OK;
 }

@@ -74,6 +74,147 @@ __host__ __device__ __forceinline__ K01 k01_fp64(double r2, double a, double a2q
 }
 
 /* ---------------------------------------------------------------------- */
+/* Far-field kernel values, FP64, device-lean version for the tile kernels.  */
+/* Same regimes and coefficients as k01_fp64 with lean elementary functions: */
+/*  * 1/sqrt and 1/x: hardware v_rsq_f64 / v_rcp_f64 estimates refined by    */
+/*    one Newton-type step (third order for rsq, two steps for rcp);         */
+/*  * e^{-z}: Cody-Waite reduction z = n ln2 - r, |r| <= ln2/2, degree-13    */
+/*    Taylor polynomial (truncation 4e-18), scaling by 2^-n (ldexp);         */
+/*  * log q, 0 < q <= 1: q = m 2^e with m in [sqrt(1/2), sqrt(2)),           */
+/*    log m = 2 atanh(s), s = (m-1)/(m+1), |s| <= 0.1716, series to s^21.     */
+/* ---------------------------------------------------------------------- */
+constexpr double LN2_HI = 6.93147180369123816490e-01; /* ln 2 split: hi has 32 bits */
+constexpr double LN2_LO = 1.90821492927058770002e-10;
+constexpr double LOG2E = 1.44269504088896338700e+00;
+constexpr double SQRT_HALF = 0.707106781186547524401;
+/* 1/k!, k = 0..13 */
+static constexpr double EXP_T[14] = {1.0, 1.0, 0.5, 1.0 / 6.0, 1.0 / 24.0, 1.0 / 120.0, 1.0 / 720.0, 1.0 / 5040.0,
+                                     1.0 / 40320.0, 1.0 / 362880.0, 1.0 / 3628800.0, 1.0 / 39916800.0,
+                                     1.0 / 479001600.0, 1.0 / 6227020800.0};
+/* 1/(2k+1), k = 0..10 */
+static constexpr double ATANH_T[11] = {1.0, 1.0 / 3.0, 1.0 / 5.0, 1.0 / 7.0, 1.0 / 9.0, 1.0 / 11.0,
+                                       1.0 / 13.0, 1.0 / 15.0, 1.0 / 17.0, 1.0 / 19.0, 1.0 / 21.0};
+
+/* Three-operand FP64 FMA.  Written as a one-instruction arithmetic asm so the
+   polynomial steps below stay single v_fma_f64 instructions with the
+   coefficient as addend, instead of a register copy plus the two-address
+   v_fmac_f64 form. */
+__device__ __forceinline__ double fma3(double a, double b, double c)
+{
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+template <int N>
+__device__ __forceinline__ double hornerv(const double (&c)[N], double x)
+{
+    double v = c[N - 1];
+#pragma unroll
+    for (int i = N - 2; i >= 0; --i) v = fma3(v, x, c[i]);
+    return v;
+}
+
+/* value and first derivative of the polynomial */
+template <int N>
+__device__ __forceinline__ double hornerd(const double (&c)[N], double x, double &d)
+{
+    double v = c[N - 1];
+    d = 0.0;
+#pragma unroll
+    for (int i = N - 2; i >= 0; --i) {
+        d = fma3(d, x, v);
+        v = fma3(v, x, c[i]);
+    }
+    return v;
+}
+
+__device__ __forceinline__ double lean_rsq(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    return fma(y * e, fma(0.375, e, 0.5), y);
+}
+
+__device__ __forceinline__ double lean_rcp(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+
+__device__ __forceinline__ double lean_exp_neg(double z)
+{
+    const double n = rint(z * LOG2E);
+    double r = fma(n, LN2_HI, -z);
+    r = fma(n, LN2_LO, r);
+    return ldexp(hornerv(EXP_T, r), -(int)n);
+}
+
+__device__ __forceinline__ double lean_log01(double q)
+{
+    int e;
+    double m = frexp(q, &e);
+    const bool lo = m < SQRT_HALF;
+    m = lo ? 2.0 * m : m;
+    e -= lo ? 1 : 0;
+    const double s = (m - 1.0) * lean_rcp(m + 1.0);
+    const double p = hornerv(ATANH_T, s * s);
+    const double de = (double)e;
+    return fma(de, LN2_HI, fma(de, LN2_LO, 2.0 * s * p));
+}
+
+/* K0(z) and alpha K1(z)/r for the far-field tiles.  When both layers are
+   wanted, K1 is taken from the derivative of the K0 fits (K1 = -K0'):
+     z > 2 : K0 = E P0(u), K1 = E [P0 (1 + 1/(2z)) + (4/z^2) P0'(u)],
+             E = e^{-z}/sqrt(z), u = 4/z - 1;
+     z <= 2: K1 = I0/z + (z/4) log(q) I0'(q) - (z/2) R0'(q), q = z^2/4,
+   which halves the coefficient tables (max rel. error 3e-15 vs 5e-16 for the
+   separate fits; measured against mpmath).  ia = 1/alpha. */
+template <bool SLP, bool DLP>
+__device__ __forceinline__ K01 k01_far_fp64(double r2, double a, double a2q, double a4, double ia)
+{
+    K01 o{0.0, 0.0};
+    const double q = a2q * r2; /* z^2/4 */
+    if (q <= 1.0) {
+        const double lq = lean_log01(q); /* 2 log(z/2) */
+        if (SLP && DLP) {
+            double di0, dr0;
+            const double i0 = hornerd(KS_I0, q, di0);
+            const double r0 = hornerd(KS_R0, q, dr0);
+            o.k0 = fma(-0.5 * lq, i0, r0);
+            /* alpha^2 K1/z = I0/r^2 + alpha^2 (lq I0'/4 - R0'/2) */
+            o.ak1r = fma(4.0 * a2q, fma(0.25 * lq, di0, -0.5 * dr0), i0 * lean_rcp(r2));
+        } else if (SLP) {
+            o.k0 = fma(-0.5 * lq, hornerv(KS_I0, q), hornerv(KS_R0, q));
+        } else {
+            const double t = fma(0.5 * lq, hornerv(KS_I1Z, q), -0.25 * hornerv(KS_R1, q));
+            o.ak1r = fma(4.0 * a2q, t, lean_rcp(r2));
+        }
+    } else {
+        const double ri = lean_rsq(r2);
+        const double z = a * (r2 * ri);
+        const double u = fma(a4, ri, -1.0);
+        const double e = lean_exp_neg(z) * lean_rsq(z);
+        if (SLP && DLP) {
+            double dp;
+            const double p = hornerd(KL0, u, dp);
+            o.k0 = e * p;
+            const double iz = ia * ri; /* 1/z */
+            const double k1 = e * fma(4.0 * iz * iz, dp, p * fma(0.5, iz, 1.0));
+            o.ak1r = a * k1 * ri;
+        } else if (SLP) {
+            o.k0 = e * hornerv(KL0, u);
+        } else {
+            o.ak1r = a * e * hornerv(KL1, u) * ri;
+        }
+    }
+    return o;
+}
+
+/* ---------------------------------------------------------------------- */
 /* Far-field kernel values, FP32 (mixed-precision far field).               */
 /* Same two regimes with the FP32 fits; exp/log/rsqrt/rcp are the hardware  */
 /* single-precision instructions.  Below e^{-87} the FP32 result flushes to */
