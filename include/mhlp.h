@@ -133,6 +133,18 @@ mhlp_status mhlp_apply_bie_operator(const mhlp_plan *onsurf, const double *mu, d
 mhlp_status mhlp_gmres_solve(const mhlp_plan *onsurf, const double *g, double *mu, const mhlp_gmres_opts *opts,
                              mhlp_gmres_info *info, void *stream);
 
+/* Volume-style all-pairs Yukawa sum on a tensor grid (the dense stress case;
+   the paper instead treats volume potentials by FFT, Sec. 3.1):
+     u_i = sum_{j != i} K0(alpha |x_i - x_j|)/(2 pi) w_j f_j + (w_i / h^2) Wcell f_i,
+   Wcell = integral of K0(alpha |x|)/(2 pi) over the h x h cell centred at the
+   point (exact self-cell correction; trapezoid edge/corner cells take their
+   weight fraction w_i/h^2).  x, y, w, f, u: device [n].  self_cell (host, may be
+   NULL) receives Wcell.  Synchronises the stream when the source range is
+   split (n small enough that fewer than 1024 target blocks exist).  Errors:
+   MHLP_INVALID_ARG for NULL arrays, n < 1, alpha or h not > 0. */
+mhlp_status mhlp_volume_eval(const double *x, const double *y, const double *w, const double *f, int64_t n,
+                             double alpha, double h, int32_t precision, double *u, double *self_cell, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

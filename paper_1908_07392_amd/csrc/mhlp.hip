@@ -491,6 +491,114 @@ __global__ __launch_bounds__(FT_THREADS) void far_eval_mixed(FarArgs A)
 }
 
 /* ------------------------------------------------------------------------ */
+/* volume sum over a tensor grid (all pairs) with the self-cell correction   */
+/*   u_i = sum_{j != i} K0(alpha r_ij)/(2 pi) w_j f_j + (w_i/h^2) Wcell f_i    */
+/* Sources are targets; the self pair (r == 0) is skipped in the sum.        */
+/* ------------------------------------------------------------------------ */
+struct VolArgs {
+    const double *x, *y, *w, *f;
+    int64_t n;
+    double alpha;
+    double selfc;   /* Wcell / h^2 */
+    int64_t per_split;
+    double *part;   /* [nsplit][n] */
+    double *u;
+};
+
+template <bool MIXED, bool SPLIT>
+__global__ __launch_bounds__(FT_THREADS) void volume_kernel(VolArgs A)
+{
+    __shared__ double lx[FT_SRC], ly[FT_SRC];
+    __shared__ double lq[FT_SRC];
+    const int64_t i = blockIdx.x * (int64_t)FT_THREADS + threadIdx.x;
+    const bool valid = i < A.n;
+    const double x = valid ? A.x[i] : 0.0, y = valid ? A.y[i] : 0.0;
+    const int64_t jb = SPLIT ? (int64_t)blockIdx.y * A.per_split : 0;
+    const int64_t je = SPLIT ? min(A.n, jb + A.per_split) : A.n;
+    const double alpha = A.alpha, a2q = 0.25 * alpha * alpha, a4 = 4.0 / alpha, ia = 1.0 / alpha;
+    const float af = (float)alpha, a2qf = 0.25f * af * af, a4f = 4.0f / af;
+    double acc = 0.0;
+    for (int64_t base = jb; base < je; base += FT_SRC) {
+        __syncthreads();
+        const int64_t j = base + threadIdx.x;
+        if (j < je) {
+            lx[threadIdx.x] = A.x[j];
+            ly[threadIdx.x] = A.y[j];
+            lq[threadIdx.x] = A.w[j] * A.f[j];
+        } else {
+            lx[threadIdx.x] = 0.0;
+            ly[threadIdx.x] = 0.0;
+            lq[threadIdx.x] = 0.0;
+        }
+        __syncthreads();
+        const int cnt = (je - base) < FT_SRC ? (int)(je - base) : FT_SRC;
+        if (MIXED) {
+            float ps = 0.0f;
+            for (int l = 0; l < cnt; ++l) {
+                const float ex = (float)(x - lx[l]), ey = (float)(y - ly[l]);
+                float r2 = fmaf(ex, ex, ey * ey);
+                const bool self = r2 == 0.0f;
+                r2 = self ? 1.0f : r2;
+                const K01f o = k01_fp32<true, false>(r2, af, a2qf, a4f);
+                ps = fmaf(self ? 0.0f : o.k0, (float)lq[l], ps);
+                if ((l & 15) == 15) {
+                    acc += (double)ps;
+                    ps = 0.0f;
+                }
+            }
+            acc += (double)ps;
+        } else {
+#pragma unroll 2
+            for (int l = 0; l < cnt; ++l) {
+                const double ex = x - lx[l], ey = y - ly[l];
+                double r2 = fma(ex, ex, ey * ey);
+                const bool self = r2 == 0.0;
+                r2 = self ? 1.0 : r2;
+                const K01 o = k01_far_fp64<true, false>(r2, alpha, a2q, a4, ia);
+                acc = fma(self ? 0.0 : o.k0, lq[l], acc);
+            }
+        }
+    }
+    if (!valid) return;
+    if (SPLIT)
+        A.part[blockIdx.y * A.n + i] = acc;
+    else
+        A.u[i] = fma(INV_2PI, acc, A.selfc * A.w[i] * A.f[i]);
+}
+
+__global__ void volume_finalize(VolArgs A, int nsplit)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    double s_ = 0.0;
+    for (int k = 0; k < nsplit; ++k) s_ += A.part[k * A.n + i];
+    A.u[i] = fma(INV_2PI, s_, A.selfc * A.w[i] * A.f[i]);
+}
+
+/* Integral of K0(alpha |x|)/(2 pi) over the h x h cell centred at the origin:
+   (1/2pi) 8 int_0^{pi/4} (1 - a K1(a))/alpha^2 dtheta, a = alpha h/(2 cos theta)
+   (from int_0^R K0(alpha s) s ds = (1 - alpha R K1(alpha R))/alpha^2);
+   composite 32-point Gauss-Legendre on 8 pieces.  One thread. */
+__global__ void self_cell_kernel(double alpha, double h, double *out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double L = 0.25 * PI;
+    double acc = 0.0;
+    for (int qp = 0; qp < 8; ++qp) {
+        const double a0 = L * qp / 8.0, a1 = L * (qp + 1) / 8.0;
+        const double mid = 0.5 * (a0 + a1), half = 0.5 * (a1 - a0);
+        for (int k = 0; k < 32; ++k) {
+            const double th = mid + half * GL32_T[k];
+            const double R = 0.5 * h / cos(th);
+            const K01 o = k01_fp64<false, true>(R * R, alpha, 0.25 * alpha * alpha, 4.0 / alpha);
+            /* o.ak1r = alpha K1(alpha R)/R  =>  alpha R K1 = o.ak1r R^2 */
+            acc += GL32_W[k] * half * (1.0 - o.ak1r * R * R) / (alpha * alpha);
+        }
+    }
+    out[0] = 8.0 * acc * INV_2PI;
+}
+
+/* ------------------------------------------------------------------------ */
 /* GMRES BLAS-1                                                              */
 /* ------------------------------------------------------------------------ */
 /* out[c] = sum_i V[c*ld + i] * w[i], one block per column */
@@ -1089,4 +1197,64 @@ extern "C" mhlp_status mhlp_gmres_solve(const mhlp_plan *Pc, const double *g, do
     info->rel_residual = rel;
     info->converged = rel <= opts->tol ? 1 : 0;
     return info->converged ? MHLP_OK : MHLP_NOT_CONVERGED;
+}
+
+/* ------------------------------------------------------------------------ */
+/* volume API                                                                */
+/* ------------------------------------------------------------------------ */
+extern "C" mhlp_status mhlp_volume_eval(const double *x, const double *y, const double *w, const double *f, int64_t n,
+                                        double alpha, double h, int32_t precision, double *u, double *self_cell,
+                                        void *stream)
+{
+    if (!x || !y || !w || !f || !u) return fail(MHLP_INVALID_ARG, "NULL argument");
+    if (n < 1) return fail(MHLP_INVALID_ARG, "n must be >= 1");
+    if (!(alpha > 0.0) || !std::isfinite(alpha) || !(h > 0.0)) return fail(MHLP_INVALID_ARG, "alpha and h must be > 0");
+    if (precision != MHLP_FP64 && precision != MHLP_MIXED) return fail(MHLP_INVALID_ARG, "unknown precision");
+    hipStream_t st = (hipStream_t)stream;
+    double *dev = nullptr;
+    TRY(dalloc(&dev, 1));
+    self_cell_kernel<<<1, 64, 0, st>>>(alpha, h, dev);
+    double wc = 0.0;
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&wc, dev, sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(dev);
+    if (e != hipSuccess) return fail(MHLP_HIP_ERROR, std::string("volume self cell: ") + hipGetErrorString(e));
+    if (self_cell) *self_cell = wc;
+    VolArgs A;
+    A.x = x;
+    A.y = y;
+    A.w = w;
+    A.f = f;
+    A.n = n;
+    A.alpha = alpha;
+    A.selfc = wc / (h * h);
+    A.u = u;
+    const int64_t tblocks = (n + FT_THREADS - 1) / FT_THREADS;
+    int64_t ns = (1024 + tblocks - 1) / tblocks;
+    if (ns > (n + FT_SRC - 1) / FT_SRC) ns = (n + FT_SRC - 1) / FT_SRC;
+    if (ns < 1) ns = 1;
+    A.per_split = ((n + ns - 1) / ns + FT_SRC - 1) / FT_SRC * FT_SRC;
+    const int nsplit = (int)((n + A.per_split - 1) / A.per_split);
+    A.part = nullptr;
+    if (nsplit > 1) {
+        TRY(dalloc(&A.part, (int64_t)nsplit * n));
+        dim3 grid((unsigned)tblocks, nsplit);
+        if (precision == MHLP_MIXED)
+            volume_kernel<true, true><<<grid, FT_THREADS, 0, st>>>(A);
+        else
+            volume_kernel<false, true><<<grid, FT_THREADS, 0, st>>>(A);
+        volume_finalize<<<nblocks(n, 256), 256, 0, st>>>(A, nsplit);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        (void)hipFree(A.part);
+        if (e != hipSuccess) return fail(MHLP_HIP_ERROR, std::string("volume_eval: ") + hipGetErrorString(e));
+        return MHLP_OK;
+    }
+    if (precision == MHLP_MIXED)
+        volume_kernel<true, false><<<(unsigned)tblocks, FT_THREADS, 0, st>>>(A);
+    else
+        volume_kernel<false, false><<<(unsigned)tblocks, FT_THREADS, 0, st>>>(A);
+    HIPCHECK(hipGetLastError());
+    return MHLP_OK;
 }

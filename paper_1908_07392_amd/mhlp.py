@@ -66,6 +66,8 @@ _SIGS = {
     "mhlp_eval_dlp": ([_V, _V, _V, ctypes.c_int32, _V], ctypes.c_int32),
     "mhlp_apply_bie_operator": ([_V, _V, _V, ctypes.c_int32, _V], ctypes.c_int32),
     "mhlp_gmres_solve": ([_V, _V, _V, ctypes.POINTER(GmresOpts), ctypes.POINTER(GmresInfo), _V], ctypes.c_int32),
+    "mhlp_volume_eval": ([_V, _V, _V, _V, ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_int32, _V,
+                          _c_double_p, _V], ctypes.c_int32),
 }
 
 
@@ -217,3 +219,15 @@ def gmres_solve(plan: Plan, g, x0=None, tol=1e-10, max_iter=500, restart=100, pr
                             _stream())
     _check(rc, "gmres_solve")
     return mu, info.as_dict()
+
+
+def volume_eval(x, y, w, f, alpha, h, precision=FP64, out=None):
+    """All-pairs volume sum with self-cell correction; returns (u, Wcell)."""
+    L = load()
+    n = x.numel()
+    out = torch.empty(n, dtype=torch.float64, device=x.device) if out is None else out
+    wc = ctypes.c_double()
+    _check(L.mhlp_volume_eval(_dev(x, "x", n), _dev(y, "y", n), _dev(w, "w", n), _dev(f, "f", n), n, float(alpha),
+                              float(h), int(precision), _dev(out, "u", n), ctypes.byref(wc), _stream()),
+           "volume_eval")
+    return out, wc.value

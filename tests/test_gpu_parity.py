@@ -222,3 +222,33 @@ def test_mixed_precision_gmres(alpha):
     print("fp64", i64, "mixed", i32)
     assert i32["converged"] and i32["rel_residual"] <= 1e-10
     assert _relerr(mu32.cpu().numpy(), mu64.cpu().numpy()) < 1e-8
+
+
+# ---------------------------------------------------------------------------
+# Volume all-pairs sum with self-cell correction (dense stress case)
+# ---------------------------------------------------------------------------
+def test_volume_small_grid_full():
+    n, alpha = 20, 20.0
+    gx = np.linspace(-1.5, 1.5, n)
+    h = gx[1] - gx[0]
+    X, Y = np.meshgrid(gx, gx)
+    w1 = np.full(n, h)
+    w1[[0, -1]] = h / 2
+    W = np.outer(w1, w1).ravel()
+    f = (np.cos(2 * X) + Y ** 2).ravel()
+    x, y = X.ravel(), Y.ravel()
+    u, wc = mhlp.volume_eval(_t(x), _t(y), _t(W), _t(f), alpha, h)
+    ref = oracle.volume_eval(x, y, W, f, alpha, h, np.arange(n * n))
+    assert abs(wc - oracle.self_cell(alpha, h)) < 1e-14 * abs(wc)
+    assert _relerr(u.cpu().numpy(), ref) < 1e-12
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 1e-6)])
+def test_volume_config3_sampled(precision, tol):
+    c = wl.config3()
+    u, _ = mhlp.volume_eval(_t(c["x"]), _t(c["y"]), _t(c["w"]), _t(c["f"]), c["alpha"], c["h"], precision=precision)
+    idx = c["sample"][:48]
+    ref = oracle.volume_eval(c["x"], c["y"], c["w"], c["f"], c["alpha"], c["h"], idx)
+    err = _relerr(u.cpu().numpy()[idx], ref)
+    print(f"volume precision={precision} sampled rel err {err:.2e}")
+    assert err < tol
