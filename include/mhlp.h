@@ -145,6 +145,30 @@ mhlp_status mhlp_gmres_solve(const mhlp_plan *onsurf, const double *g, double *m
 mhlp_status mhlp_volume_eval(const double *x, const double *y, const double *w, const double *f, int64_t n,
                              double alpha, double h, int32_t precision, double *u, double *self_cell, void *stream);
 
+/* Batched on-surface solves over many geometries (each with its own alpha)
+   and up to 4 right-hand sides per geometry (Sec. 3.2 BIE, one system per
+   geometry and right-hand side).  plans: host array of n_geom on-surface
+   plans (borrowed; they must outlive the batch).  Batched vectors hold, for
+   each geometry in order, its n_rhs right-hand sides of N_g values each;
+   mhlp_batch_info reports the total length and each system's offset and
+   length (host arrays of n_geom*n_rhs entries, may be NULL). */
+typedef struct mhlp_batch mhlp_batch;
+mhlp_status mhlp_batch_create(int32_t n_geom, const mhlp_plan *const *plans, int32_t n_rhs, void *stream,
+                              mhlp_batch **out);
+mhlp_status mhlp_batch_destroy(mhlp_batch *batch);
+mhlp_status mhlp_batch_info(const mhlp_batch *batch, int64_t *total_len, int32_t *n_systems, int64_t *offsets,
+                            int64_t *lengths);
+/* out = (1/2 I + D) mu for every system in one grouped launch (kernel values
+   shared by the right-hand sides of a geometry); FP64. */
+mhlp_status mhlp_batch_apply_bie(const mhlp_batch *batch, const double *mu, double *out, void *stream);
+/* Lockstep restarted GMRES on every system (FP64, CGS2, restart <= 64),
+   converged systems frozen; each judged by its own true residual.  infos:
+   host array of n_geom*n_rhs.  Synchronises the stream.  Returns
+   MHLP_NOT_CONVERGED if any system misses the tolerance within max_iter
+   Arnoldi steps (counted per lockstep iteration). */
+mhlp_status mhlp_batch_gmres_solve(mhlp_batch *batch, const double *g, double *mu, const mhlp_gmres_opts *opts,
+                                   mhlp_gmres_info *infos, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1258,3 +1258,500 @@ extern "C" mhlp_status mhlp_volume_eval(const double *x, const double *y, const 
     HIPCHECK(hipGetLastError());
     return MHLP_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* batched on-surface operator and lockstep GMRES over many geometries and   */
+/* right-hand sides                                                          */
+/*                                                                           */
+/* Batched vector layout: for each geometry g, a block [R][N_g] at offset     */
+/* voff_g (R right-hand sides of the same geometry are contiguous systems).   */
+/* One grouped launch applies (1/2 I + D) to every system: each block owns    */
+/* (geometry, target tile, source split); every kernel value is shared by the */
+/* R right-hand sides of its geometry.                                        */
+/* ------------------------------------------------------------------------ */
+constexpr int BATCH_R_MAX = 4;
+
+struct BatchGeo {
+    const double *x, *y, *w, *nx, *ny;
+    const int32_t *nptr, *npan;
+    const double *wdl;
+    int64_t N, Np;
+    double alpha;
+    int64_t voff; /* offset of the geometry's [R][N] block in batched vectors */
+    int64_t poff; /* offset of its partial sums [nsplit][R][N]                 */
+    int32_t nsplit, pps;
+};
+
+struct BatchWork {
+    int32_t g, tb, split, pad;
+};
+
+template <int R>
+__global__ __launch_bounds__(FT_THREADS) void batch_far_dlp(const BatchGeo *__restrict__ G,
+                                                            const BatchWork *__restrict__ W,
+                                                            const double *__restrict__ mu, double *__restrict__ part)
+{
+    __shared__ double lx[FT_SRC], ly[FT_SRC];
+    __shared__ double ldx[R][FT_SRC], ldy[R][FT_SRC];
+    const BatchWork wk = W[blockIdx.x];
+    const BatchGeo geo = G[wk.g];
+    const int64_t i = (int64_t)wk.tb * FT_THREADS + threadIdx.x;
+    const bool valid = i < geo.N;
+    const double x = valid ? geo.x[i] : 0.0, y = valid ? geo.y[i] : 0.0;
+    const int64_t pb = (int64_t)wk.split * geo.pps;
+    const int64_t pe = min(geo.Np, pb + geo.pps);
+    int32_t k = 0, kend = 0;
+    if (valid) {
+        k = geo.nptr[i];
+        kend = geo.nptr[i + 1];
+        while (k < kend && geo.npan[k] >= 0 && geo.npan[k] < pb) ++k;
+    }
+    int32_t nxt = (k < kend) ? geo.npan[k] : INT_MAX;
+    const double alpha = geo.alpha, a2q = 0.25 * alpha * alpha, a4 = 4.0 / alpha, ia = 1.0 / alpha;
+    const double *mug = mu + geo.voff;
+    double acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = 0.0;
+    for (int64_t base = 16 * pb; base < 16 * pe; base += FT_SRC) {
+        __syncthreads();
+        const int64_t j = base + threadIdx.x;
+        if (j < 16 * pe) {
+            const double wj = geo.w[j];
+            lx[threadIdx.x] = geo.x[j];
+            ly[threadIdx.x] = geo.y[j];
+            const double nxj = geo.nx[j], nyj = geo.ny[j];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const double m = wj * mug[r * geo.N + j];
+                ldx[r][threadIdx.x] = m * nxj;
+                ldy[r][threadIdx.x] = m * nyj;
+            }
+        }
+        __syncthreads();
+        const int32_t p0 = (int32_t)(base / 16);
+        const int npl = (pe - p0) < 16 ? (int)(pe - p0) : 16;
+        for (int pl = 0; pl < npl; ++pl) {
+            if (p0 + pl == nxt) {
+                ++k;
+                nxt = (k < kend) ? geo.npan[k] : INT_MAX;
+                continue;
+            }
+            for (int s = 0; s < 16; ++s) {
+                const int l = pl * 16 + s;
+                const double ex = x - lx[l], ey = y - ly[l];
+                const double r2 = fma(ex, ex, ey * ey);
+                const K01 o = k01_far_fp64<false, true>(r2, alpha, a2q, a4, ia);
+#pragma unroll
+                for (int r = 0; r < R; ++r) acc[r] = fma(o.ak1r, fma(ex, ldx[r][l], ey * ldy[r][l]), acc[r]);
+            }
+        }
+    }
+    if (!valid) return;
+#pragma unroll
+    for (int r = 0; r < R; ++r) part[geo.poff + ((int64_t)wk.split * R + r) * geo.N + i] = acc[r];
+}
+
+/* out = (1/2 I + D) mu for every system: split partials + corrections + identity */
+template <int R>
+__global__ void batch_finalize(const BatchGeo *__restrict__ G, const BatchWork *__restrict__ W,
+                               const double *__restrict__ part, const double *__restrict__ mu,
+                               double *__restrict__ out)
+{
+    const BatchWork wk = W[blockIdx.x];
+    const BatchGeo geo = G[wk.g];
+    const int64_t i = (int64_t)wk.tb * FT_THREADS + threadIdx.x;
+    if (i >= geo.N) return;
+    const double *mug = mu + geo.voff;
+    double v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = 0.0;
+    for (int sp = 0; sp < geo.nsplit; ++sp)
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] += part[geo.poff + ((int64_t)sp * R + r) * geo.N + i];
+    double c[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) c[r] = 0.0;
+    for (int32_t q = geo.nptr[i]; q < geo.nptr[i + 1]; ++q) {
+        const int64_t p = geo.npan[q];
+        if (p < 0) continue;
+        for (int jj = 0; jj < 16; ++jj) {
+            const double wq = geo.wdl[16 * (int64_t)q + jj];
+#pragma unroll
+            for (int r = 0; r < R; ++r) c[r] = fma(wq, mug[r * geo.N + 16 * p + jj], c[r]);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) out[geo.voff + r * geo.N + i] = fma(INV_2PI, v[r], c[r]) + 0.5 * mug[r * geo.N + i];
+}
+
+/* per-system BLAS-1 over batched vectors: system s spans [off[s], off[s] + n[s]) */
+__global__ __launch_bounds__(256) void bdot_kernel(const double *__restrict__ V, int64_t ld,
+                                                   const double *__restrict__ w, const int64_t *__restrict__ off,
+                                                   const int64_t *__restrict__ n, int ldh, double *__restrict__ out)
+{
+    __shared__ double red[256];
+    const int s = blockIdx.x, c = blockIdx.y;
+    const double *v = V + c * ld + off[s];
+    const double *ww = w + off[s];
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < n[s]; i += 256) acc = fma(v[i], ww[i], acc);
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[(int64_t)s * ldh + c] = red[0];
+}
+
+/* w_s -= sum_{c<ncol} h[s][c] V_c  (sign = -1) or x_s += sum_{c<k_s} y[s][c] V_c (sign = +1) */
+__global__ void bcombo_kernel(const double *__restrict__ V, int64_t ld, int ncol, const int32_t *__restrict__ kcol,
+                              const double *__restrict__ h, int ldh, double sign, double *__restrict__ w,
+                              const int64_t *__restrict__ off, const int64_t *__restrict__ n)
+{
+    const int s = blockIdx.y;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n[s]) return;
+    const int nc = kcol ? kcol[s] : ncol;
+    const int64_t e = off[s] + i;
+    double acc = w[e];
+    for (int c = 0; c < nc; ++c) acc = fma(sign * h[(int64_t)s * ldh + c], V[c * ld + e], acc);
+    w[e] = acc;
+}
+
+/* out_s = scale[s] * in_s */
+__global__ void bscale_kernel(const double *__restrict__ in, const double *__restrict__ scale,
+                              double *__restrict__ out, const int64_t *__restrict__ off,
+                              const int64_t *__restrict__ n)
+{
+    const int s = blockIdx.y;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n[s]) return;
+    out[off[s] + i] = scale[s] * in[off[s] + i];
+}
+
+struct mhlp_batch {
+    int n_geom = 0, R = 0, S = 0;
+    int64_t total = 0, max_n = 0;
+    std::vector<int64_t> off, n;
+    BatchGeo *dgeo = nullptr;
+    BatchWork *dwork = nullptr, *dfin = nullptr;
+    int64_t nwork = 0, nfin = 0;
+    double *part = nullptr;
+    int64_t *doff = nullptr, *dn = nullptr;
+    /* GMRES workspace */
+    int m = 0;
+    double *V = nullptr, *w = nullptr, *r = nullptr;
+    double *dh = nullptr, *hh = nullptr; /* [3][S][ldh] device / pinned host */
+    double *dsc = nullptr;               /* per-system scalars */
+    int32_t *dk = nullptr;
+    int ldh = 0;
+};
+
+extern "C" mhlp_status mhlp_batch_destroy(mhlp_batch *B)
+{
+    if (!B) return MHLP_OK;
+    void *ptrs[] = {B->dgeo, B->dwork, B->dfin, B->part, B->doff, B->dn, B->V, B->w, B->r, B->dh, B->dsc, B->dk};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    if (B->hh) (void)hipHostFree(B->hh);
+    delete B;
+    return MHLP_OK;
+}
+
+extern "C" mhlp_status mhlp_batch_create(int32_t n_geom, const mhlp_plan *const *plans, int32_t n_rhs, void *stream,
+                                         mhlp_batch **out)
+{
+    if (!out) return fail(MHLP_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (n_geom < 1 || !plans) return fail(MHLP_INVALID_ARG, "need at least one plan");
+    if (n_rhs < 1 || n_rhs > BATCH_R_MAX) return fail(MHLP_INVALID_ARG, "n_rhs must be 1..4");
+    for (int g = 0; g < n_geom; ++g)
+        if (!plans[g] || !plans[g]->onsurf) return fail(MHLP_INVALID_ARG, "batch needs on-surface plans");
+    hipStream_t st = (hipStream_t)stream;
+    mhlp_batch *B = new mhlp_batch();
+    B->n_geom = n_geom;
+    B->R = n_rhs;
+    B->S = n_geom * n_rhs;
+    std::vector<BatchGeo> hg(n_geom);
+    std::vector<BatchWork> hw, hf;
+    int64_t voff = 0, poff = 0, tblocks_all = 0;
+    for (int g = 0; g < n_geom; ++g) tblocks_all += (plans[g]->M + FT_THREADS - 1) / FT_THREADS;
+    /* source splits: aim at ~2048 blocks in total, split the larger geometries */
+    const double target = 2048.0;
+    const double tot_work = [&] {
+        double t = 0;
+        for (int g = 0; g < n_geom; ++g) t += (double)plans[g]->g->N * plans[g]->M;
+        return t;
+    }();
+    for (int g = 0; g < n_geom; ++g) {
+        const mhlp_plan *P = plans[g];
+        const mhlp_geometry *G = P->g;
+        BatchGeo &b = hg[g];
+        b.x = G->soa;
+        b.y = G->soa + G->N;
+        b.w = G->w;
+        b.nx = G->nx;
+        b.ny = G->ny;
+        b.nptr = P->near_ptr;
+        b.npan = P->near_panel;
+        b.wdl = P->wdlp;
+        b.N = G->N;
+        b.Np = G->Np;
+        b.alpha = P->alpha;
+        b.voff = voff;
+        const int64_t tb = (G->N + FT_THREADS - 1) / FT_THREADS;
+        /* blocks for this geometry proportional to its share of pair work */
+        int64_t want = (int64_t)std::ceil(target * (double)G->N * G->N / tot_work);
+        int64_t ns = (want + tb - 1) / tb;
+        if (ns > G->Np / 4) ns = G->Np / 4;
+        if (ns < 1) ns = 1;
+        b.pps = (int32_t)((G->Np + ns - 1) / ns);
+        b.nsplit = (int32_t)((G->Np + b.pps - 1) / b.pps);
+        b.poff = poff;
+        poff += (int64_t)b.nsplit * n_rhs * G->N;
+        for (int64_t t = 0; t < tb; ++t) {
+            for (int sp = 0; sp < b.nsplit; ++sp) hw.push_back(BatchWork{g, (int32_t)t, sp, 0});
+            hf.push_back(BatchWork{g, (int32_t)t, 0, 0});
+        }
+        for (int r = 0; r < n_rhs; ++r) {
+            B->off.push_back(voff + (int64_t)r * G->N);
+            B->n.push_back(G->N);
+        }
+        B->max_n = std::max<int64_t>(B->max_n, G->N);
+        voff += (int64_t)n_rhs * G->N;
+    }
+    (void)tblocks_all;
+    B->total = voff;
+    B->nwork = (int64_t)hw.size();
+    B->nfin = (int64_t)hf.size();
+    mhlp_status s;
+    if ((s = dalloc(&B->dgeo, n_geom)) || (s = dalloc(&B->dwork, B->nwork)) || (s = dalloc(&B->dfin, B->nfin)) ||
+        (s = dalloc(&B->part, poff)) || (s = dalloc(&B->doff, B->S)) || (s = dalloc(&B->dn, B->S))) {
+        mhlp_batch_destroy(B);
+        return s;
+    }
+    hipError_t e = hipMemcpyAsync(B->dgeo, hg.data(), sizeof(BatchGeo) * n_geom, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(B->dwork, hw.data(), sizeof(BatchWork) * B->nwork, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(B->dfin, hf.data(), sizeof(BatchWork) * B->nfin, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(B->doff, B->off.data(), sizeof(int64_t) * B->S, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(B->dn, B->n.data(), sizeof(int64_t) * B->S, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        mhlp_batch_destroy(B);
+        return fail(MHLP_HIP_ERROR, std::string("batch_create: ") + hipGetErrorString(e));
+    }
+    *out = B;
+    return MHLP_OK;
+}
+
+extern "C" mhlp_status mhlp_batch_info(const mhlp_batch *B, int64_t *total_len, int32_t *n_systems,
+                                       int64_t *offsets, int64_t *lengths)
+{
+    if (!B) return fail(MHLP_INVALID_ARG, "batch is NULL");
+    if (total_len) *total_len = B->total;
+    if (n_systems) *n_systems = B->S;
+    for (int s = 0; s < B->S; ++s) {
+        if (offsets) offsets[s] = B->off[s];
+        if (lengths) lengths[s] = B->n[s];
+    }
+    return MHLP_OK;
+}
+
+static mhlp_status batch_apply_impl(const mhlp_batch *B, const double *mu, double *out, hipStream_t st)
+{
+    switch (B->R) {
+    case 1:
+        batch_far_dlp<1><<<(unsigned)B->nwork, FT_THREADS, 0, st>>>(B->dgeo, B->dwork, mu, B->part);
+        batch_finalize<1><<<(unsigned)B->nfin, FT_THREADS, 0, st>>>(B->dgeo, B->dfin, B->part, mu, out);
+        break;
+    case 2:
+        batch_far_dlp<2><<<(unsigned)B->nwork, FT_THREADS, 0, st>>>(B->dgeo, B->dwork, mu, B->part);
+        batch_finalize<2><<<(unsigned)B->nfin, FT_THREADS, 0, st>>>(B->dgeo, B->dfin, B->part, mu, out);
+        break;
+    case 3:
+        batch_far_dlp<3><<<(unsigned)B->nwork, FT_THREADS, 0, st>>>(B->dgeo, B->dwork, mu, B->part);
+        batch_finalize<3><<<(unsigned)B->nfin, FT_THREADS, 0, st>>>(B->dgeo, B->dfin, B->part, mu, out);
+        break;
+    default:
+        batch_far_dlp<4><<<(unsigned)B->nwork, FT_THREADS, 0, st>>>(B->dgeo, B->dwork, mu, B->part);
+        batch_finalize<4><<<(unsigned)B->nfin, FT_THREADS, 0, st>>>(B->dgeo, B->dfin, B->part, mu, out);
+        break;
+    }
+    HIPCHECK(hipGetLastError());
+    return MHLP_OK;
+}
+
+extern "C" mhlp_status mhlp_batch_apply_bie(const mhlp_batch *B, const double *mu, double *out, void *stream)
+{
+    if (!B || !mu || !out) return fail(MHLP_INVALID_ARG, "NULL argument");
+    if (mu == out) return fail(MHLP_INVALID_ARG, "mu and out must not alias");
+    return batch_apply_impl(B, mu, out, (hipStream_t)stream);
+}
+
+extern "C" mhlp_status mhlp_batch_gmres_solve(mhlp_batch *B, const double *g, double *mu, const mhlp_gmres_opts *opts,
+                                              mhlp_gmres_info *infos, void *stream)
+{
+    if (!B || !g || !mu || !opts || !infos) return fail(MHLP_INVALID_ARG, "NULL argument");
+    if (!(opts->tol > 0.0) || opts->max_iter < 1 || opts->restart < 1) return fail(MHLP_INVALID_ARG, "bad options");
+    if (opts->precision != MHLP_FP64) return fail(MHLP_UNSUPPORTED, "batched GMRES runs in FP64");
+    hipStream_t st = (hipStream_t)stream;
+    const int S = B->S;
+    const int m = std::min(opts->restart, 64);
+    const int64_t T = B->total;
+    if (B->m < m) {
+        void *ptrs[] = {B->V, B->w, B->r, B->dh, B->dsc, B->dk};
+        for (void *p : ptrs)
+            if (p) (void)hipFree(p);
+        if (B->hh) (void)hipHostFree(B->hh);
+        B->V = B->w = B->r = B->dh = B->dsc = nullptr;
+        B->dk = nullptr;
+        B->hh = nullptr;
+        B->ldh = m + 2;
+        TRY(dalloc(&B->V, (int64_t)(m + 1) * T));
+        TRY(dalloc(&B->w, T));
+        TRY(dalloc(&B->r, T));
+        TRY(dalloc(&B->dh, 3 * (int64_t)S * B->ldh));
+        TRY(dalloc(&B->dsc, S));
+        TRY(dalloc(&B->dk, S));
+        HIPCHECK(hipHostMalloc((void **)&B->hh, sizeof(double) * 3 * (size_t)S * B->ldh, hipHostMallocDefault));
+        B->m = m;
+    }
+    const int ldh = B->ldh;
+    const dim3 gS((unsigned)((B->max_n + 255) / 256), (unsigned)S);
+    double *h1 = B->dh, *h2 = B->dh + (int64_t)S * ldh, *hn = B->dh + 2 * (int64_t)S * ldh;
+    std::vector<double> bn(S), rel(S, 1.0), x0res(S, 1.0), H((size_t)S * (m + 1) * m), cs((size_t)S * m),
+        sn((size_t)S * m), gv((size_t)S * (m + 1)), yv((size_t)S * ldh, 0.0), sc(S);
+    std::vector<int32_t> kdone(S), iters(S, 0), cyc(S, 0);
+    std::vector<char> conv(S, 0), active(S, 0);
+    auto norms = [&](const double *v, std::vector<double> &outv) -> mhlp_status {
+        bdot_kernel<<<dim3((unsigned)S, 1), 256, 0, st>>>(v, 0, v, B->doff, B->dn, ldh, hn);
+        HIPCHECK(hipGetLastError());
+        HIPCHECK(hipMemcpyAsync(B->hh, hn, sizeof(double) * (size_t)S * ldh, hipMemcpyDeviceToHost, st));
+        HIPCHECK(hipStreamSynchronize(st));
+        for (int s = 0; s < S; ++s) outv[s] = std::sqrt(B->hh[(size_t)s * ldh]);
+        return MHLP_OK;
+    };
+    TRY(norms(g, bn));
+    /* x0: a guess whose residual is >= 1 (relative) is replaced by zero, per system */
+    std::vector<double> rn(S);
+    if (opts->use_x0) {
+        TRY(batch_apply_impl(B, mu, B->w, st));
+        residual_kernel<<<nblocks(T, 256), 256, 0, st>>>(g, B->w, B->r, T);
+        TRY(norms(B->r, rn));
+        bool any_bad = false;
+        for (int s = 0; s < S; ++s) {
+            x0res[s] = bn[s] > 0 ? rn[s] / bn[s] : 0.0;
+            sc[s] = (x0res[s] < 1.0) ? 1.0 : 0.0;
+            any_bad |= sc[s] == 0.0;
+        }
+        if (any_bad) {
+            HIPCHECK(hipMemcpyAsync(B->dsc, sc.data(), sizeof(double) * S, hipMemcpyHostToDevice, st));
+            bscale_kernel<<<gS, 256, 0, st>>>(mu, B->dsc, mu, B->doff, B->dn);
+        }
+    } else {
+        fill_kernel<<<nblocks(T, 256), 256, 0, st>>>(mu, 0.0, T);
+    }
+    int total_it = 0;
+    for (;;) {
+        TRY(batch_apply_impl(B, mu, B->w, st));
+        residual_kernel<<<nblocks(T, 256), 256, 0, st>>>(g, B->w, B->r, T);
+        TRY(norms(B->r, rn));
+        int nact = 0;
+        for (int s = 0; s < S; ++s) {
+            rel[s] = bn[s] > 0 ? rn[s] / bn[s] : 0.0;
+            conv[s] = rel[s] <= opts->tol;
+            active[s] = !conv[s];
+            nact += active[s];
+            sc[s] = active[s] ? 1.0 / rn[s] : 0.0;
+            kdone[s] = 0;
+            std::fill(&gv[(size_t)s * (m + 1)], &gv[(size_t)s * (m + 1)] + m + 1, 0.0);
+            gv[(size_t)s * (m + 1)] = rn[s];
+        }
+        if (nact == 0 || total_it >= opts->max_iter) break;
+        HIPCHECK(hipMemcpyAsync(B->dsc, sc.data(), sizeof(double) * S, hipMemcpyHostToDevice, st));
+        bscale_kernel<<<gS, 256, 0, st>>>(B->r, B->dsc, B->V, B->doff, B->dn);
+        for (int s = 0; s < S; ++s) cyc[s] += active[s];
+        int k = 0;
+        for (; k < m && total_it < opts->max_iter; ++k) {
+            ++total_it;
+            double *Vk = B->V + (int64_t)k * T;
+            TRY(batch_apply_impl(B, Vk, B->w, st));
+            bdot_kernel<<<dim3((unsigned)S, (unsigned)(k + 1)), 256, 0, st>>>(B->V, T, B->w, B->doff, B->dn, ldh, h1);
+            bcombo_kernel<<<gS, 256, 0, st>>>(B->V, T, k + 1, nullptr, h1, ldh, -1.0, B->w, B->doff, B->dn);
+            bdot_kernel<<<dim3((unsigned)S, (unsigned)(k + 1)), 256, 0, st>>>(B->V, T, B->w, B->doff, B->dn, ldh, h2);
+            bcombo_kernel<<<gS, 256, 0, st>>>(B->V, T, k + 1, nullptr, h2, ldh, -1.0, B->w, B->doff, B->dn);
+            bdot_kernel<<<dim3((unsigned)S, 1), 256, 0, st>>>(B->w, 0, B->w, B->doff, B->dn, ldh, hn);
+            HIPCHECK(hipGetLastError());
+            HIPCHECK(hipMemcpyAsync(B->hh, B->dh, sizeof(double) * 3 * (size_t)S * ldh, hipMemcpyDeviceToHost, st));
+            HIPCHECK(hipStreamSynchronize(st));
+            int still = 0;
+            for (int s = 0; s < S; ++s) {
+                sc[s] = 0.0;
+                if (!active[s]) continue;
+                ++iters[s];
+                double *Hs = &H[(size_t)s * (m + 1) * m];
+                for (int j = 0; j <= k; ++j)
+                    Hs[(size_t)j * m + k] = B->hh[(size_t)s * ldh + j] + B->hh[(size_t)(S + s) * ldh + j];
+                const double hk = std::sqrt(B->hh[(size_t)(2 * S + s) * ldh]);
+                Hs[(size_t)(k + 1) * m + k] = hk;
+                double *c_ = &cs[(size_t)s * m], *s_ = &sn[(size_t)s * m], *g_ = &gv[(size_t)s * (m + 1)];
+                for (int j = 0; j < k; ++j) {
+                    const double a = Hs[(size_t)j * m + k], c = Hs[(size_t)(j + 1) * m + k];
+                    Hs[(size_t)j * m + k] = c_[j] * a + s_[j] * c;
+                    Hs[(size_t)(j + 1) * m + k] = -s_[j] * a + c_[j] * c;
+                }
+                const double a = Hs[(size_t)k * m + k], c = Hs[(size_t)(k + 1) * m + k];
+                const double den = std::hypot(a, c);
+                c_[k] = den > 0 ? a / den : 1.0;
+                s_[k] = den > 0 ? c / den : 0.0;
+                Hs[(size_t)k * m + k] = den;
+                Hs[(size_t)(k + 1) * m + k] = 0.0;
+                g_[k + 1] = -s_[k] * g_[k];
+                g_[k] = c_[k] * g_[k];
+                kdone[s] = k + 1;
+                if (std::fabs(g_[k + 1]) <= 0.5 * opts->tol * bn[s] || hk == 0.0) {
+                    active[s] = 0;
+                } else {
+                    sc[s] = 1.0 / hk;
+                    ++still;
+                }
+            }
+            HIPCHECK(hipMemcpyAsync(B->dsc, sc.data(), sizeof(double) * S, hipMemcpyHostToDevice, st));
+            bscale_kernel<<<gS, 256, 0, st>>>(B->w, B->dsc, B->V + (int64_t)(k + 1) * T, B->doff, B->dn);
+            if (still == 0) {
+                ++k;
+                break;
+            }
+        }
+        /* per-system back substitution and update x += V y */
+        for (int s = 0; s < S; ++s) {
+            const int ks = kdone[s];
+            const double *Hs = &H[(size_t)s * (m + 1) * m];
+            const double *g_ = &gv[(size_t)s * (m + 1)];
+            double *y_ = &yv[(size_t)s * ldh];
+            for (int i2 = ks - 1; i2 >= 0; --i2) {
+                double acc = g_[i2];
+                for (int j = i2 + 1; j < ks; ++j) acc -= Hs[(size_t)i2 * m + j] * y_[j];
+                y_[i2] = Hs[(size_t)i2 * m + i2] != 0.0 ? acc / Hs[(size_t)i2 * m + i2] : 0.0;
+            }
+        }
+        std::vector<int32_t> kk(kdone.begin(), kdone.end());
+        HIPCHECK(hipMemcpyAsync(h1, yv.data(), sizeof(double) * (size_t)S * ldh, hipMemcpyHostToDevice, st));
+        HIPCHECK(hipMemcpyAsync(B->dk, kk.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice, st));
+        bcombo_kernel<<<gS, 256, 0, st>>>(B->V, T, 0, B->dk, h1, ldh, 1.0, mu, B->doff, B->dn);
+        HIPCHECK(hipGetLastError());
+        HIPCHECK(hipStreamSynchronize(st));
+    }
+    bool all = true;
+    for (int s = 0; s < S; ++s) {
+        infos[s].iters = iters[s];
+        infos[s].restarts = cyc[s];
+        infos[s].rel_residual = rel[s];
+        infos[s].x0_residual = opts->use_x0 ? x0res[s] : 1.0;
+        infos[s].converged = conv[s];
+        infos[s].used_x0 = opts->use_x0 ? (x0res[s] < 1.0) : 0;
+        all &= conv[s] != 0;
+    }
+    return all ? MHLP_OK : MHLP_NOT_CONVERGED;
+}

@@ -66,6 +66,14 @@ _SIGS = {
     "mhlp_eval_dlp": ([_V, _V, _V, ctypes.c_int32, _V], ctypes.c_int32),
     "mhlp_apply_bie_operator": ([_V, _V, _V, ctypes.c_int32, _V], ctypes.c_int32),
     "mhlp_gmres_solve": ([_V, _V, _V, ctypes.POINTER(GmresOpts), ctypes.POINTER(GmresInfo), _V], ctypes.c_int32),
+    "mhlp_batch_create": ([ctypes.c_int32, ctypes.POINTER(_V), ctypes.c_int32, _V, ctypes.POINTER(_V)],
+                          ctypes.c_int32),
+    "mhlp_batch_destroy": ([_V], ctypes.c_int32),
+    "mhlp_batch_info": ([_V, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
+                         ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int32),
+    "mhlp_batch_apply_bie": ([_V, _V, _V, _V], ctypes.c_int32),
+    "mhlp_batch_gmres_solve": ([_V, _V, _V, ctypes.POINTER(GmresOpts), ctypes.POINTER(GmresInfo), _V],
+                               ctypes.c_int32),
     "mhlp_volume_eval": ([_V, _V, _V, _V, ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_int32, _V,
                           _c_double_p, _V], ctypes.c_int32),
 }
@@ -231,3 +239,56 @@ def volume_eval(x, y, w, f, alpha, h, precision=FP64, out=None):
                               float(h), int(precision), _dev(out, "u", n), ctypes.byref(wc), _stream()),
            "volume_eval")
     return out, wc.value
+
+
+class Batch:
+    """Many on-surface systems (geometries x right-hand sides) solved together."""
+
+    def __init__(self, plans, n_rhs: int):
+        L = load()
+        self.plans = list(plans)
+        self.n_rhs = int(n_rhs)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
+        h = ctypes.c_void_p()
+        _check(L.mhlp_batch_create(len(self.plans), arr, self.n_rhs, _stream(), ctypes.byref(h)), "batch_create")
+        self._h = h
+        tot, ns = ctypes.c_int64(), ctypes.c_int32()
+        _check(L.mhlp_batch_info(h, ctypes.byref(tot), ctypes.byref(ns), None, None), "batch_info")
+        off = (ctypes.c_int64 * ns.value)()
+        ln = (ctypes.c_int64 * ns.value)()
+        _check(L.mhlp_batch_info(h, None, None, off, ln), "batch_info")
+        self.total, self.n_systems = tot.value, ns.value
+        self.offsets, self.lengths = list(off), list(ln)
+        self.device = self.plans[0].geom.device
+
+    def pack(self, per_system):
+        """Concatenate per-system device vectors into one batched vector."""
+        return torch.cat([v.reshape(-1) for v in per_system]).contiguous()
+
+    def unpack(self, v):
+        return [v[o:o + n] for o, n in zip(self.offsets, self.lengths)]
+
+    def apply(self, mu, out=None):
+        out = torch.empty(self.total, dtype=torch.float64, device=self.device) if out is None else out
+        _check(load().mhlp_batch_apply_bie(self._h, _dev(mu, "mu", self.total), _dev(out, "out", self.total),
+                                           _stream()), "batch_apply_bie")
+        return out
+
+    def gmres(self, g, x0=None, tol=1e-10, max_iter=500, restart=64):
+        mu = torch.zeros(self.total, dtype=torch.float64, device=self.device) if x0 is None else x0.clone()
+        opts = GmresOpts(float(tol), int(max_iter), int(restart), FP64, 0 if x0 is None else 1)
+        infos = (GmresInfo * self.n_systems)()
+        _check(load().mhlp_batch_gmres_solve(self._h, _dev(g, "g", self.total), _dev(mu, "mu", self.total),
+                                             ctypes.byref(opts), infos, _stream()), "batch_gmres_solve")
+        return mu, [i.as_dict() for i in infos]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().mhlp_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
