@@ -45,6 +45,7 @@ def parse():
     ap.add_argument("--grid", type=int, default=512)
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the batched and volume legs")
     return ap.parse_args()
 
 
@@ -162,9 +163,114 @@ def main():
                                   f"interior targets of a {args.grid}^2 grid",
                       "n_sources": N, "n_targets": M, "alphas": list(cfg["alphas"]), "precision": "fp64"},
            "gmres": gm, "plan_build_ms": round(plan_ms, 1), "roofline": roofline}
+    # ---- mixed precision (FP32 far field, FP64 near/identity/Arnoldi, GMRES-IR) on the same step
+    def mixed_step():
+        tm = {}
+        for a in cfg["alphas"]:
+            on, off = plans[a]
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            mu_m, info_m = mhlp.gmres_solve(on, gdev[a], tol=1e-10, max_iter=400, restart=200, precision=mhlp.MIXED)
+            t2 = time.perf_counter()
+            mhlp.eval_layer(off, sigma=mu_m, mu=mu_m, precision=mhlp.MIXED)
+            tm[a] = ((t2 - t1) * 1e3, info_m)
+        return tm
+
+    mixed_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        tm = mixed_step()
+    torch.cuda.synchronize()
+    ms_mixed = (time.perf_counter() - t0) * 1e3 / args.steps
+    mu64, _ = mhlp.gmres_solve(on, gdev[a_r], tol=1e-10)
+    us64, ud64 = mhlp.eval_layer(off, sigma=mu64, mu=mu64)
+    us32, ud32 = mhlp.eval_layer(off, sigma=mu64, mu=mu64, precision=mhlp.MIXED)
+    ev0.record()
+    for _ in range(reps):
+        mhlp.eval_layer(off, sigma=mu64, mu=mu64, precision=mhlp.MIXED)
+    ev1.record()
+    torch.cuda.synchronize()
+    mixed_launch_ms = ev0.elapsed_time(ev1) / reps
+    err_m = max(float((us32 - us64).abs().max() / us64.abs().max()), float((ud32 - ud64).abs().max() / ud64.abs().max()))
+    out["mixed"] = {"ms_per_step": round(ms_mixed, 3), "speedup_vs_fp64": round(ms_per_step / ms_mixed, 3),
+                    "eval_launch_ms": round(mixed_launch_ms, 4),
+                    "eval_speedup_vs_fp64": round(launch_ms / mixed_launch_ms, 3),
+                    "eval_gpair_per_s": round(eval_pairs / (mixed_launch_ms * 1e-3) / 1e9, 3),
+                    "eval_max_rel_err_vs_fp64": err_m,
+                    "gmres": {f"alpha={a:g}": {"gmres_ms": round(tm[a][0], 3), "iters": tm[a][1]["iters"],
+                                               "refinements": tm[a][1]["restarts"],
+                                               "residual": tm[a][1]["rel_residual"]} for a in cfg["alphas"]}}
+
+    if not args.no_extra:
+        out["batched"] = bench_batched(mhlp, wl, t, torch)
+        out["volume"] = bench_volume(mhlp, wl, t, torch)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, 50.0, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def bench_batched(mhlp, wl, t, torch):
+    """64 geometries x 4 right-hand sides, GMRES to 1e-10: one batched solve vs the
+    same 256 solves one by one (FP64 both)."""
+    print("# batched leg", file=sys.stderr, flush=True)
+    items = wl.config4()
+    t0 = time.perf_counter()
+    plans = []
+    for it in items:
+        G = mhlp.Geometry(t(it["geom"].node_soa()))
+        plans.append(mhlp.Plan(G, it["alpha"]))
+    torch.cuda.synchronize()
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    B = mhlp.Batch(plans, 4)
+    rhs = [t(it["rhs"][r]) for it in items for r in range(4)]
+    gb = B.pack(rhs)
+    B.gmres(gb, tol=1e-10)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mu, infos = B.gmres(gb, tol=1e-10)
+    torch.cuda.synchronize()
+    batched_ms = (time.perf_counter() - t0) * 1e3
+    t0 = time.perf_counter()
+    seq_iters = 0
+    k = 0
+    for p in plans:
+        for r in range(4):
+            _, inf = mhlp.gmres_solve(p, rhs[k], tol=1e-10, restart=64)
+            seq_iters += inf["iters"]
+            k += 1
+    torch.cuda.synchronize()
+    seq_ms = (time.perf_counter() - t0) * 1e3
+    n_nodes = sum(it["geom"].n_nodes for it in items)
+    return {"systems": len(infos), "total_nodes": n_nodes, "plan_build_ms": round(plan_ms, 1),
+            "batched_ms": round(batched_ms, 2), "sequential_ms": round(seq_ms, 2),
+            "speedup_vs_sequential": round(seq_ms / batched_ms, 2),
+            "all_converged": all(i["converged"] for i in infos),
+            "max_residual": max(i["rel_residual"] for i in infos),
+            "max_iters": max(i["iters"] for i in infos), "sequential_total_iters": seq_iters}
+
+
+def bench_volume(mhlp, wl, t, torch):
+    """256^2 grid all-pairs K0 sum (4.3e9 pairs) with self-cell correction."""
+    print("# volume leg", file=sys.stderr, flush=True)
+    c = wl.config3()
+    x, y, w, f = t(c["x"]), t(c["y"]), t(c["w"]), t(c["f"])
+    res = {}
+    for name, prec in (("fp64", mhlp.FP64), ("mixed", mhlp.MIXED)):
+        u, _ = mhlp.volume_eval(x, y, w, f, c["alpha"], c["h"], precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 3
+        for _ in range(reps):
+            u, _ = mhlp.volume_eval(x, y, w, f, c["alpha"], c["h"], precision=prec)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        res[name] = {"ms": round(ms, 3), "gpair_per_s": round(len(c["x"]) ** 2 / (ms * 1e-3) / 1e9, 2)}
+        res.setdefault("_u", {})[name] = u
+    d = res.pop("_u")
+    res["mixed_max_rel_err_vs_fp64"] = float((d["mixed"] - d["fp64"]).abs().max() / d["fp64"].abs().max())
+    res["pairs"] = len(c["x"]) ** 2
+    return res
 
 
 if __name__ == "__main__":
