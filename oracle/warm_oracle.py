@@ -1,0 +1,175 @@
+"""FP64 oracle of the learned warm start (test infrastructure only).
+
+Plain numpy, written from the definitions; shares no code with the HIP
+library and is imported only by the tests, the smoke check and the CPU leg of
+the benchmark.
+
+* Fourier features of a density on each closed curve, in the curve parameter
+  theta: c_k = (1/2 pi) int_0^{2 pi} mu(theta) e^{-i k theta} d theta, by the
+  composite panel rule in theta, and the real Fourier series back.
+* The network n_in -> width -> width -> n_out, GELU (tanh form) after the two
+  hidden layers, mean-squared-error loss, back-propagation, Adam.  Weights may
+  be rounded to BF16 (round to nearest even) before use, as the matrix cores
+  see them; everything else is FP64.
+
+Parameter layout (shared convention with the library): for l = 0, 1, 2 the
+weight W_l as a row-major [n_{l+1}][n_l] block followed by the bias b_l.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+SQRT_2_OVER_PI = math.sqrt(2.0 / math.pi)
+GELU_CUBIC = 0.044715
+
+
+# --------------------------------------------------------------------------------------
+# BF16
+# --------------------------------------------------------------------------------------
+def bf16_round(x) -> np.ndarray:
+    """Nearest-even BF16 value (8-bit significand) of each FP32 number, as float64.
+
+    BF16 keeps the top 16 bits of the IEEE binary32 pattern; the 16 dropped bits are
+    rounded half to even."""
+    b = np.ascontiguousarray(np.asarray(x, dtype=np.float32)).view(np.uint32).astype(np.uint64)
+    low = b & 0xFFFF
+    high = b >> 16
+    up = (low > 0x8000) | ((low == 0x8000) & ((high & 1) == 1))
+    high = high + up.astype(np.uint64)
+    return (high << 16).astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+# --------------------------------------------------------------------------------------
+# network
+# --------------------------------------------------------------------------------------
+def gelu(z):
+    """GELU in its tanh form: z/2 (1 + tanh(sqrt(2/pi) (z + 0.044715 z^3)))."""
+    return 0.5 * z * (1.0 + np.tanh(SQRT_2_OVER_PI * (z + GELU_CUBIC * z ** 3)))
+
+
+def gelu_prime(z):
+    u = SQRT_2_OVER_PI * (z + GELU_CUBIC * z ** 3)
+    t = np.tanh(u)
+    du = SQRT_2_OVER_PI * (1.0 + 3.0 * GELU_CUBIC * z ** 2)
+    return 0.5 * (1.0 + t) + 0.5 * z * (1.0 - t * t) * du
+
+
+def layer_slices(sizes):
+    """[(weight slice, bias slice)] of the flat parameter vector."""
+    out, o = [], 0
+    for l in range(3):
+        nw = sizes[l + 1] * sizes[l]
+        out.append((slice(o, o + nw), slice(o + nw, o + nw + sizes[l + 1])))
+        o += nw + sizes[l + 1]
+    return out
+
+
+def n_params(sizes) -> int:
+    return sum(sizes[l + 1] * sizes[l] + sizes[l + 1] for l in range(3))
+
+
+def unpack(params, sizes, round_weights=True):
+    p = np.asarray(params)
+    Ws, bs = [], []
+    for l, (sw, sb) in enumerate(layer_slices(sizes)):
+        w = p[sw].reshape(sizes[l + 1], sizes[l])
+        Ws.append(bf16_round(w) if round_weights else w.astype(np.float64))
+        bs.append(p[sb].astype(np.float64))
+    return Ws, bs
+
+
+def mlp_forward(params, sizes, X, round_weights=True):
+    """Returns (Y, cache) for a batch X [B][n_in]."""
+    Ws, bs = unpack(params, sizes, round_weights)
+    a = np.asarray(X, dtype=np.float64)
+    acts, pre = [a], []
+    for l in range(3):
+        z = a @ Ws[l].T + bs[l]
+        pre.append(z)
+        a = gelu(z) if l < 2 else z
+        acts.append(a)
+    return a, dict(Ws=Ws, acts=acts, pre=pre)
+
+
+def mlp_loss_grad(params, sizes, X, T, round_weights=True):
+    """Loss mean((net(X) - T)^2) over all entries and its gradient (flat, FP64).
+
+    With rounded weights the gradient is taken with respect to the rounded values
+    (the usual mixed-precision convention: it is applied to the FP32 masters)."""
+    Y, c = mlp_forward(params, sizes, X, round_weights)
+    T = np.asarray(T, dtype=np.float64)
+    n = Y.size
+    loss = float(np.sum((Y - T) ** 2) / n)
+    g = np.zeros(n_params(sizes))
+    sl = layer_slices(sizes)
+    dz = 2.0 * (Y - T) / n
+    for l in (2, 1, 0):
+        a_in = c["acts"][l]
+        g[sl[l][0]] = (dz.T @ a_in).ravel()
+        g[sl[l][1]] = dz.sum(axis=0)
+        if l > 0:
+            da = dz @ c["Ws"][l]
+            dz = da * gelu_prime(c["pre"][l - 1])
+    return loss, g
+
+
+def adam_step(p, g, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One bias-corrected Adam update (Kingma & Ba); returns new (p, m, v)."""
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    mh = m / (1.0 - beta1 ** step)
+    vh = v / (1.0 - beta2 ** step)
+    return p - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+# --------------------------------------------------------------------------------------
+# Fourier features
+# --------------------------------------------------------------------------------------
+def fourier_coefficients(theta, omega, curve_ptr, mu, n_modes):
+    """[d][F] with F = 2 n_modes n_curves, ordered [curve][k][Re, Im]."""
+    mu = np.atleast_2d(np.asarray(mu, dtype=np.float64))
+    nc = len(curve_ptr) - 1
+    k = np.arange(n_modes)
+    out = np.zeros((mu.shape[0], nc, n_modes, 2))
+    for c in range(nc):
+        a, b = curve_ptr[c], curve_ptr[c + 1]
+        E = np.exp(-1j * np.outer(theta[a:b], k)) * omega[a:b, None] / (2.0 * math.pi)
+        ck = mu[:, a:b] @ E
+        out[:, c, :, 0] = ck.real
+        out[:, c, :, 1] = ck.imag
+    return out.reshape(mu.shape[0], -1)
+
+
+def fourier_synthesis(theta, curve_ptr, coef, n_modes):
+    """Real Fourier series Re(c_0) + sum_{k>=1} 2 Re(c_k e^{i k theta}) on each curve."""
+    coef = np.atleast_2d(np.asarray(coef, dtype=np.float64))
+    nc = len(curve_ptr) - 1
+    C = coef.reshape(coef.shape[0], nc, n_modes, 2)
+    out = np.zeros((coef.shape[0], int(curve_ptr[-1])))
+    k = np.arange(n_modes)
+    wk = np.where(k == 0, 1.0, 2.0)
+    for c in range(nc):
+        a, b = curve_ptr[c], curve_ptr[c + 1]
+        E = np.exp(1j * np.outer(theta[a:b], k))
+        ck = C[:, c, :, 0] + 1j * C[:, c, :, 1]
+        out[:, a:b] = np.real((ck * wk) @ E.T)
+    return out
+
+
+def warm_scales(coef, n_hist):
+    """{1 / RMS of the input rows 0..n-2, RMS of the increments of rows n_hist..n-1}."""
+    coef = np.asarray(coef, dtype=np.float64)
+    rx = math.sqrt(np.mean(coef[:-1] ** 2))
+    ry = math.sqrt(np.mean((coef[n_hist:] - coef[n_hist - 1:-1]) ** 2))
+    return (1.0 / rx if rx > 0 else 1.0), (ry if ry > 0 else 1.0)
+
+
+def warm_samples(coef, n_hist, scales):
+    """Network inputs [S][n_hist F] and targets [S][F] of a training series."""
+    coef = np.asarray(coef, dtype=np.float64)
+    S = coef.shape[0] - n_hist
+    X = np.stack([coef[j:j + n_hist].ravel() for j in range(S)]) * scales[0]
+    T = (coef[n_hist:] - coef[n_hist - 1:-1]) / scales[1]
+    return X, T

@@ -162,6 +162,7 @@ class Geometry:
     gl_t: np.ndarray           # 16 Gauss-Legendre nodes on [-1, 1]
     gl_w: np.ndarray           # 16 Gauss-Legendre weights
     lengths: np.ndarray        # arclength of each curve
+    theta_w: np.ndarray = None  # quadrature weight in theta (half panel span in theta x GL weight)
 
     @property
     def n_nodes(self) -> int:
@@ -174,6 +175,11 @@ class Geometry:
     @property
     def curve_panel_offsets(self) -> np.ndarray:
         return np.concatenate([[0], np.cumsum(self.panels_per_curve)]).astype(np.int32)
+
+    @property
+    def curve_node_ptr(self) -> np.ndarray:
+        """Node ranges of the curves: curve c owns nodes ptr[c]..ptr[c+1]-1."""
+        return (self.curve_panel_offsets * NODES_PER_PANEL).astype(np.int64)
 
     @property
     def speed(self) -> np.ndarray:
@@ -209,7 +215,7 @@ def discretize(curves, panels_per_curve) -> Geometry:
     if np.isscalar(panels_per_curve):
         panels_per_curve = [int(panels_per_curve)] * len(curves)
     t, lam = _gl(NODES_PER_PANEL)
-    xs, ys, dxs, dys, d2xs, d2ys, ths, cid, lens = [], [], [], [], [], [], [], [], []
+    xs, ys, dxs, dys, d2xs, d2ys, ths, cid, lens, thw = [], [], [], [], [], [], [], [], [], []
     for ci, (c, npan) in enumerate(zip(curves, panels_per_curve)):
         bps, L = _arclength_breakpoints(c, int(npan))
         a, b = bps[:-1], bps[1:]
@@ -222,10 +228,11 @@ def discretize(curves, panels_per_curve) -> Geometry:
         dxs.append(dzt.real.ravel()); dys.append(dzt.imag.ravel())
         d2xs.append(d2zt.real.ravel()); d2ys.append(d2zt.imag.ravel())
         ths.append(th.ravel()); cid.append(np.full(th.size, ci, dtype=np.int32))
+        thw.append((half[:, None] * lam[None, :]).ravel())
         lens.append(L)
     cat = np.concatenate
     return Geometry(list(curves), [int(p) for p in panels_per_curve], cat(xs), cat(ys), cat(dxs), cat(dys),
-                    cat(d2xs), cat(d2ys), cat(ths), cat(cid), t, lam, np.asarray(lens))
+                    cat(d2xs), cat(d2ys), cat(ths), cat(cid), t, lam, np.asarray(lens), cat(thw))
 
 
 # --------------------------------------------------------------------------------------

@@ -1,0 +1,140 @@
+"""Pins of the warm-start oracle (Fourier features, network, Adam).
+
+Expected values come from the BF16 format's definition, the exact GELU
+(z Phi(z) via erf), PyTorch's CPU autograd in float64, central finite
+differences, the Adam paper's update written with torch.optim, and band-limited
+densities whose Fourier coefficients are known by construction.
+"""
+import math
+
+import numpy as np
+import scipy.special as sp
+import torch
+
+from oracle import warm_oracle as wo
+from paper_1908_07392_amd import workloads as wl
+
+
+def test_bf16_round_definition():
+    ulp = 2.0 ** -7  # BF16 spacing on [1, 2)
+    cases = {
+        1.0: 1.0,
+        1.0 + ulp / 2: 1.0,                          # tie -> even (1.0)
+        1.0 + 1.5 * ulp: 1.0 + 2 * ulp,              # tie -> even (1 + 2 ulp)
+        1.0 + ulp / 2 + 2.0 ** -20: 1.0 + ulp,       # just above the tie -> up
+        1.0 + ulp / 2 - 2.0 ** -20: 1.0,             # just below the tie -> down
+        -3.0: -3.0,
+        -(1.0 + 1.5 * ulp): -(1.0 + 2 * ulp),
+        2.0 ** -130: 2.0 ** -130,                    # subnormal with few bits
+        0.0: 0.0,
+    }
+    got = wo.bf16_round(np.array(list(cases.keys()), dtype=np.float32))
+    assert np.array_equal(got, np.array(list(cases.values())))
+    x = np.random.default_rng(0).standard_normal(10000).astype(np.float32)
+    r = wo.bf16_round(x)
+    assert np.all(np.abs(r - x) <= np.abs(x) * 2.0 ** -8 * (1 + 1e-12))
+    assert np.all(r.astype(np.float32).view(np.uint32) & 0xFFFF == 0)
+
+
+def test_gelu_tanh_form_vs_exact_gelu():
+    z = np.linspace(-6, 6, 2001)
+    exact = 0.5 * z * (1.0 + sp.erf(z / math.sqrt(2.0)))
+    assert np.max(np.abs(wo.gelu(z) - exact)) < 5e-4
+    assert wo.gelu(np.array([0.0]))[0] == 0.0
+    assert abs(wo.gelu_prime(np.array([0.0]))[0] - 0.5) < 1e-15
+    h = 1e-5
+    fd = (wo.gelu(z + h) - wo.gelu(z - h)) / (2 * h)
+    assert np.max(np.abs(fd - wo.gelu_prime(z))) < 1e-9
+
+
+def _tiny(seed=0, sizes=(7, 5, 5, 3), B=4):
+    rng = np.random.default_rng(seed)
+    p = rng.standard_normal(wo.n_params(sizes)) * 0.7
+    X = rng.standard_normal((B, sizes[0]))
+    T = rng.standard_normal((B, sizes[3]))
+    return p, X, T, sizes
+
+
+def test_mlp_gradient_central_differences():
+    p, X, T, sizes = _tiny()
+    loss, g = wo.mlp_loss_grad(p, sizes, X, T, round_weights=False)
+    h = 1e-6
+    fd = np.empty_like(g)
+    for i in range(p.size):
+        e = np.zeros_like(p)
+        e[i] = h
+        fd[i] = (wo.mlp_loss_grad(p + e, sizes, X, T, False)[0] - wo.mlp_loss_grad(p - e, sizes, X, T, False)[0]) / (2 * h)
+    assert np.max(np.abs(fd - g)) < 1e-8 * max(1.0, np.max(np.abs(g)))
+
+
+def test_mlp_forward_and_grad_vs_torch_autograd():
+    p, X, T, sizes = _tiny(seed=3, sizes=(11, 9, 9, 6), B=5)
+    for rnd in (False, True):
+        loss, g = wo.mlp_loss_grad(p, sizes, X, T, round_weights=rnd)
+        Ws, bs = [], []
+        for l, (sw, sb) in enumerate(wo.layer_slices(sizes)):
+            w = p[sw].reshape(sizes[l + 1], sizes[l])
+            if rnd:  # BF16 rounding of the weights by torch's own conversion
+                w = torch.tensor(w, dtype=torch.float32).to(torch.bfloat16).double().numpy()
+            Ws.append(torch.tensor(w, dtype=torch.float64, requires_grad=True))
+            bs.append(torch.tensor(p[sb], dtype=torch.float64, requires_grad=True))
+        a = torch.tensor(X)
+        for l in range(3):
+            a = torch.nn.functional.linear(a, Ws[l], bs[l])
+            if l < 2:
+                a = torch.nn.functional.gelu(a, approximate="tanh")
+        Y = wo.mlp_forward(p, sizes, X, rnd)[0]
+        assert np.max(np.abs(a.detach().numpy() - Y)) < 1e-13
+        L = torch.nn.functional.mse_loss(a, torch.tensor(T))
+        L.backward()
+        assert abs(L.item() - loss) < 1e-14
+        gt = np.concatenate([np.concatenate([Ws[l].grad.numpy().ravel(), bs[l].grad.numpy()]) for l in range(3)])
+        assert np.max(np.abs(gt - g)) < 1e-13
+
+
+def test_adam_vs_torch_optim():
+    rng = np.random.default_rng(5)
+    p = rng.standard_normal(50)
+    m = np.zeros(50)
+    v = np.zeros(50)
+    tp = torch.tensor(p.copy(), requires_grad=True)
+    opt = torch.optim.Adam([tp], lr=1e-3, betas=(0.9, 0.999), eps=1e-8)
+    for step in range(1, 6):
+        g = rng.standard_normal(50)
+        p, m, v = wo.adam_step(p, g, m, v, step)
+        tp.grad = torch.tensor(g)
+        opt.step()
+    assert np.max(np.abs(tp.detach().numpy() - p)) < 1e-14
+
+
+def test_fourier_band_limited_exact():
+    geom, _ = wl.config5_geometry()
+    ptr = geom.curve_node_ptr
+    K = 128
+    rng = np.random.default_rng(11)
+    nc = len(ptr) - 1
+    C = np.zeros((nc, K), dtype=complex)
+    C[:, :40] = rng.standard_normal((nc, 40)) + 1j * rng.standard_normal((nc, 40))
+    C[:, 0] = C[:, 0].real
+    mu = np.zeros(geom.n_nodes)
+    for c in range(nc):
+        a, b = ptr[c], ptr[c + 1]
+        th = geom.theta[a:b]
+        mu[a:b] = C[c, 0].real + 2.0 * np.real(np.exp(1j * np.outer(th, np.arange(1, K))) @ C[c, 1:])
+    coef = wo.fourier_coefficients(geom.theta, geom.theta_w, ptr, mu, K)[0].reshape(nc, K, 2)
+    assert np.max(np.abs(coef[..., 0] - C.real)) < 1e-13
+    assert np.max(np.abs(coef[..., 1] - C.imag)) < 1e-13
+    back = wo.fourier_synthesis(geom.theta, ptr, coef.ravel(), K)[0]
+    assert np.max(np.abs(back - mu)) < 1e-11 * np.max(np.abs(mu))
+
+
+def test_warm_samples_shapes_and_scales():
+    rng = np.random.default_rng(2)
+    coef = rng.standard_normal((10, 6))
+    sx, sy = wo.warm_scales(coef, 4)
+    X, T = wo.warm_samples(coef, 4, (sx, sy))
+    assert X.shape == (6, 24) and T.shape == (6, 6)
+    assert np.allclose(X[2], coef[2:6].ravel() * sx)
+    assert np.allclose(T[5] * sy, coef[9] - coef[8])
+    assert abs(sx * math.sqrt(np.mean(coef[:9] ** 2)) - 1.0) < 1e-12  # inputs use rows 0..8
+    assert abs(np.sqrt(np.mean(T ** 2)) - 1.0) < 1e-12
