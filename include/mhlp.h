@@ -169,6 +169,84 @@ mhlp_status mhlp_batch_apply_bie(const mhlp_batch *batch, const double *mu, doub
 mhlp_status mhlp_batch_gmres_solve(mhlp_batch *batch, const double *g, double *mu, const mhlp_gmres_opts *opts,
                                    mhlp_gmres_info *infos, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Learned GMRES warm start.  The paper's implicit time stepping (Sec. 3)
+ * solves one Sec. 3.2 BIE per step with slowly changing data; these entries
+ * predict the next step's density from the last ones, to be passed to
+ * mhlp_gmres_solve with use_x0 = 1 (which falls back to the zero guess when
+ * the prediction's residual is not below ||g||).  Not part of the paper.
+ *
+ * Network (mhlp_mlp): n_in -> width -> width -> n_out, GELU (tanh form)
+ * after both hidden layers, no activation on the output.  Parameters are FP32
+ * master copies laid out per layer l = 0,1,2 as W_l (row-major
+ * [n_{l+1}][n_l]) followed by b_l; every product rounds its operands to BF16
+ * (nearest even) and accumulates in FP32 on the matrix cores.  Default
+ * initialisation: W_l ~ U(-1/sqrt(n_l), 1/sqrt(n_l)) from a counter-based
+ * generator seeded by `seed`, biases 0.  Batched arrays are row-major
+ * [batch][features], FP32, device.
+ * ---------------------------------------------------------------------- */
+typedef struct mhlp_mlp mhlp_mlp;
+mhlp_status mhlp_mlp_create(int32_t n_in, int32_t width, int32_t n_out, uint64_t seed, void *stream,
+                            mhlp_mlp **out);
+mhlp_status mhlp_mlp_destroy(mhlp_mlp *mlp);
+/* parameter count and the four layer widths (host outputs, may be NULL) */
+mhlp_status mhlp_mlp_info(const mhlp_mlp *mlp, int64_t *n_params, int32_t *sizes4);
+/* copy the FP32 parameters out to dst and/or in from src (device, n_params
+   floats each, may be NULL); loading resets the Adam state */
+mhlp_status mhlp_mlp_params(mhlp_mlp *mlp, float *dst, const float *src, void *stream);
+/* Y [batch][n_out] = net(X [batch][n_in]) */
+mhlp_status mhlp_mlp_forward(mhlp_mlp *mlp, const float *X, int32_t batch, float *Y, void *stream);
+/* forward, loss L = mean over batch*n_out entries of (net(X) - T)^2, and the
+   gradient dL/dparams (back-propagation with the same BF16 products) into the
+   network's gradient buffer; loss (device, 1 float) and grad (device,
+   n_params floats) receive copies when non-NULL */
+mhlp_status mhlp_mlp_loss_grad(mhlp_mlp *mlp, const float *X, const float *T, int32_t batch, float *loss,
+                               float *grad, void *stream);
+/* one Adam step (bias-corrected, no weight decay) with the last gradient */
+mhlp_status mhlp_mlp_adam_step(mhlp_mlp *mlp, float lr, float beta1, float beta2, float eps, void *stream);
+/* C[m][n] (row-major, leading dimension ldc >= n) = sum_k A(m,k) B(k,n) with
+   A(m,k) = A[m*sam + k*sak], B(k,n) = B[k*sbk + n*sbn]; FP32 in memory,
+   BF16 operands, FP32 accumulation (the network's product, exposed for tests) */
+mhlp_status mhlp_gemm_bf16(int32_t m, int32_t n, int32_t k, const float *A, int64_t sam, int64_t sak, const float *B,
+                           int64_t sbk, int64_t sbn, float *C, int64_t ldc, void *stream);
+
+/* Warm-start model (mhlp_warm): Fourier features of the density on each
+   closed curve in its parameter theta, c_k = (1/2 pi) int mu e^{-i k theta},
+   k = 0..n_modes-1, by the panel quadrature in theta; F = 2 n_modes n_curves
+   reals per density, ordered [curve][k][Re, Im].  The network maps the
+   coefficients of the last n_hist densities (scaled by one global factor) to
+   the increment of the next density's coefficients (in units of the RMS
+   training increment).
+   theta, omega: device [N] float64, curve parameter and theta-quadrature
+   weight of each node (copied); curve_ptr: host [n_curves+1], node ranges of
+   the curves (0 = curve_ptr[0] < ... < curve_ptr[n_curves] = N).  The network
+   is n_hist*F -> width -> width -> F.  Synchronises the stream. */
+typedef struct mhlp_warm mhlp_warm;
+mhlp_status mhlp_warm_create(const double *theta, const double *omega, const int64_t *curve_ptr, int32_t n_curves,
+                             int32_t n_modes, int32_t n_hist, int32_t width, uint64_t seed, void *stream,
+                             mhlp_warm **out);
+mhlp_status mhlp_warm_destroy(mhlp_warm *warm);
+/* node count, F, the network (borrowed, owned by the model) and the two
+   scales {input factor, output unit} (host [2]; synchronous); any may be NULL */
+mhlp_status mhlp_warm_info(const mhlp_warm *warm, int64_t *n_nodes, int64_t *n_features, mhlp_mlp **net,
+                           double *scales);
+/* coef [n_dens][F] = Fourier coefficients of mu [n_dens][N] (FP64) */
+mhlp_status mhlp_warm_coefficients(const mhlp_warm *warm, const double *mu, int32_t n_dens, double *coef,
+                                   void *stream);
+/* out [n_dens][N] = base + real Fourier series of coef [n_dens][F] at the
+   nodes (base may be NULL = 0) */
+mhlp_status mhlp_warm_synthesize(const mhlp_warm *warm, const double *coef, int32_t n_dens, const double *base,
+                                 double *out, void *stream);
+/* Train on a series of solved densities mus [n_steps][N] (oldest first):
+   samples j = 0..n_steps-n_hist-1, full-batch Adam (beta 0.9/0.999, eps
+   1e-8) for iters steps at learning rate lr; the scales are fixed from this
+   series.  losses: host [iters] (may be NULL).  Synchronises the stream. */
+mhlp_status mhlp_warm_train(mhlp_warm *warm, const double *mus, int32_t n_steps, int32_t iters, float lr,
+                            float *losses, void *stream);
+/* x0 [N] = hist[n_hist-1] + predicted increment, from hist [n_hist][N]
+   (oldest first).  Errors: MHLP_INVALID_ARG before training. */
+mhlp_status mhlp_warm_predict(mhlp_warm *warm, const double *hist, double *x0, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

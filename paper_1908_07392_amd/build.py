@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmhlp.so")
-SOURCES = [os.path.join(CSRC, "mhlp.hip")]
+SOURCES = [os.path.join(CSRC, "mhlp.hip"), os.path.join(CSRC, "mlp.hip")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -56,6 +56,13 @@ static mhlp_status fail(mhlp_status s, const std::string &msg)
 
 extern "C" const char *mhlp_last_error(void) { return g_err.c_str(); }
 
+/* error setter shared with the other translation units of the library */
+__attribute__((visibility("hidden"))) mhlp_status mhlp_set_error(mhlp_status s, const char *msg)
+{
+    g_err = msg;
+    return s;
+}
+
 /* ------------------------------------------------------------------------ */
 /* handles                                                                   */
 /* ------------------------------------------------------------------------ */

@@ -76,6 +76,26 @@ _SIGS = {
                                ctypes.c_int32),
     "mhlp_volume_eval": ([_V, _V, _V, _V, ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_int32, _V,
                           _c_double_p, _V], ctypes.c_int32),
+    "mhlp_mlp_create": ([ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, _V, ctypes.POINTER(_V)],
+                        ctypes.c_int32),
+    "mhlp_mlp_destroy": ([_V], ctypes.c_int32),
+    "mhlp_mlp_info": ([_V, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int32),
+    "mhlp_mlp_params": ([_V, _V, _V, _V], ctypes.c_int32),
+    "mhlp_mlp_forward": ([_V, _V, ctypes.c_int32, _V, _V], ctypes.c_int32),
+    "mhlp_mlp_loss_grad": ([_V, _V, _V, ctypes.c_int32, _V, _V, _V], ctypes.c_int32),
+    "mhlp_mlp_adam_step": ([_V, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _V], ctypes.c_int32),
+    "mhlp_gemm_bf16": ([ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _V, ctypes.c_int64, ctypes.c_int64, _V,
+                        ctypes.c_int64, ctypes.c_int64, _V, ctypes.c_int64, _V], ctypes.c_int32),
+    "mhlp_warm_create": ([_V, _V, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                          ctypes.c_int32, ctypes.c_uint64, _V, ctypes.POINTER(_V)], ctypes.c_int32),
+    "mhlp_warm_destroy": ([_V], ctypes.c_int32),
+    "mhlp_warm_info": ([_V, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_V),
+                        _c_double_p], ctypes.c_int32),
+    "mhlp_warm_coefficients": ([_V, _V, ctypes.c_int32, _V, _V], ctypes.c_int32),
+    "mhlp_warm_synthesize": ([_V, _V, ctypes.c_int32, _V, _V, _V], ctypes.c_int32),
+    "mhlp_warm_train": ([_V, _V, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.POINTER(ctypes.c_float), _V],
+                        ctypes.c_int32),
+    "mhlp_warm_predict": ([_V, _V, _V, _V], ctypes.c_int32),
 }
 
 
@@ -285,6 +305,156 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None):
             load().mhlp_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _devf(t: torch.Tensor, name: str, n: int | None = None) -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise MhlpError(f"{name} must be a HIP device tensor")
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise MhlpError(f"{name} must be contiguous float32")
+    if n is not None and t.numel() != n:
+        raise MhlpError(f"{name} must have {n} elements, has {t.numel()}")
+    return t.data_ptr()
+
+
+def gemm_bf16(A, B, transA=False, transB=False):
+    """C = op(A) op(B) with BF16 operands and FP32 accumulation (2-D float32)."""
+    m, k = (A.shape[1], A.shape[0]) if transA else (A.shape[0], A.shape[1])
+    k2, n = (B.shape[1], B.shape[0]) if transB else (B.shape[0], B.shape[1])
+    if k != k2:
+        raise MhlpError("inner dimensions differ")
+    sam, sak = (1, A.shape[1]) if transA else (A.shape[1], 1)
+    sbk, sbn = (1, B.shape[1]) if transB else (B.shape[1], 1)
+    C = torch.empty(m, n, dtype=torch.float32, device=A.device)
+    _check(load().mhlp_gemm_bf16(m, n, k, _devf(A, "A"), sam, sak, _devf(B, "B"), sbk, sbn, _devf(C, "C"), n,
+                                 _stream()), "gemm_bf16")
+    return C
+
+
+class MLP:
+    """n_in -> width -> width -> n_out network with BF16 matrix-core products."""
+
+    def __init__(self, n_in: int, width: int, n_out: int, seed: int = 0, handle=None, device="cuda"):
+        L = load()
+        self._owned = handle is None
+        if handle is None:
+            h = ctypes.c_void_p()
+            _check(L.mhlp_mlp_create(int(n_in), int(width), int(n_out), int(seed), _stream(), ctypes.byref(h)),
+                   "mlp_create")
+            self._h = h
+        else:
+            self._h = handle
+        npar, sizes = ctypes.c_int64(), (ctypes.c_int32 * 4)()
+        _check(L.mhlp_mlp_info(self._h, ctypes.byref(npar), sizes), "mlp_info")
+        self.n_params, self.sizes = npar.value, list(sizes)
+        self.device = torch.device(device)
+
+    def get_params(self):
+        out = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+        _check(load().mhlp_mlp_params(self._h, _devf(out, "dst"), None, _stream()), "mlp_params")
+        return out
+
+    def set_params(self, p):
+        _check(load().mhlp_mlp_params(self._h, None, _devf(p, "src", self.n_params), _stream()), "mlp_params")
+
+    def forward(self, X):
+        B = X.shape[0]
+        Y = torch.empty(B, self.sizes[3], dtype=torch.float32, device=self.device)
+        _check(load().mhlp_mlp_forward(self._h, _devf(X, "X", B * self.sizes[0]), B, _devf(Y, "Y"), _stream()),
+               "mlp_forward")
+        return Y
+
+    def loss_grad(self, X, T):
+        B = X.shape[0]
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        grad = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+        _check(load().mhlp_mlp_loss_grad(self._h, _devf(X, "X", B * self.sizes[0]), _devf(T, "T", B * self.sizes[3]),
+                                         B, _devf(loss, "loss"), _devf(grad, "grad"), _stream()), "mlp_loss_grad")
+        return loss, grad
+
+    def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        _check(load().mhlp_mlp_adam_step(self._h, lr, beta1, beta2, eps, _stream()), "mlp_adam_step")
+
+    def close(self):
+        if getattr(self, "_h", None) and self._owned:
+            load().mhlp_mlp_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class WarmStart:
+    """Learned GMRES initial guess from the last ``n_hist`` densities."""
+
+    def __init__(self, theta, omega, curve_ptr, n_modes=128, n_hist=4, width=256, seed=0):
+        L = load()
+        self.n_nodes = int(theta.numel())
+        self.n_curves = len(curve_ptr) - 1
+        cp = (ctypes.c_int64 * len(curve_ptr))(*[int(v) for v in curve_ptr])
+        if cp[len(curve_ptr) - 1] != self.n_nodes:
+            raise MhlpError("curve_ptr[-1] must equal the node count")
+        self.n_hist = int(n_hist)
+        self.device = theta.device
+        h = ctypes.c_void_p()
+        _check(L.mhlp_warm_create(_dev(theta, "theta"), _dev(omega, "omega", self.n_nodes), cp, self.n_curves,
+                                  int(n_modes), self.n_hist, int(width), int(seed), _stream(), ctypes.byref(h)),
+               "warm_create")
+        self._h = h
+        nf, net = ctypes.c_int64(), ctypes.c_void_p()
+        _check(L.mhlp_warm_info(h, None, ctypes.byref(nf), ctypes.byref(net), None), "warm_info")
+        self.n_features = nf.value
+        self.mlp = MLP(0, 0, 0, handle=net, device=self.device)
+
+    def scales(self):
+        sc = (ctypes.c_double * 2)()
+        _check(load().mhlp_warm_info(self._h, None, None, None, sc), "warm_info")
+        return sc[0], sc[1]
+
+    def coefficients(self, mu):
+        mu2 = mu.reshape(-1, self.n_nodes)
+        d = mu2.shape[0]
+        coef = torch.empty(d, self.n_features, dtype=torch.float64, device=self.device)
+        _check(load().mhlp_warm_coefficients(self._h, _dev(mu2, "mu"), d, _dev(coef, "coef"), _stream()),
+               "warm_coefficients")
+        return coef
+
+    def synthesize(self, coef, base=None):
+        c2 = coef.reshape(-1, self.n_features)
+        d = c2.shape[0]
+        out = torch.empty(d, self.n_nodes, dtype=torch.float64, device=self.device)
+        pb = None if base is None else _dev(base, "base", d * self.n_nodes)
+        _check(load().mhlp_warm_synthesize(self._h, _dev(c2, "coef"), d, pb, _dev(out, "out"), _stream()),
+               "warm_synthesize")
+        return out
+
+    def train(self, mus, iters=2000, lr=1e-3):
+        n_steps = mus.shape[0]
+        losses = (ctypes.c_float * max(int(iters), 1))()
+        _check(load().mhlp_warm_train(self._h, _dev(mus, "mus", n_steps * self.n_nodes), n_steps, int(iters),
+                                      float(lr), losses, _stream()), "warm_train")
+        return list(losses)[:int(iters)]
+
+    def predict(self, hist, out=None):
+        out = torch.empty(self.n_nodes, dtype=torch.float64, device=self.device) if out is None else out
+        _check(load().mhlp_warm_predict(self._h, _dev(hist, "hist", self.n_hist * self.n_nodes),
+                                        _dev(out, "x0", self.n_nodes), _stream()), "warm_predict")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.mlp._h = None
+            load().mhlp_warm_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -1,0 +1,201 @@
+"""GPU parity of the learned warm start (BF16 matrix-core network, Fourier
+features) against the FP64 oracle, and the measured GMRES gain on the
+multiply connected time series (outer circle R=2 with 512 panels, three
+starfish holes with 128 panels each, alpha = 30, 200 steps)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import warm_oracle as wo
+from paper_1908_07392_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module")
+def M():
+    from paper_1908_07392_amd import mhlp
+    mhlp.load()
+    return mhlp
+
+
+def _t(a, dt=torch.float32):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dt, device=DEV)
+
+
+@pytest.mark.parametrize("m,n,k,ta,tb", [(16, 16, 16, False, False), (37, 29, 50, False, False),
+                                         (1, 300, 257, False, True), (70, 5, 3, True, False),
+                                         (33, 47, 128, True, True), (96, 256, 4096, False, True)])
+def test_gemm_bf16_layout_and_ragged_sizes(M, m, n, k, ta, tb):
+    rng = np.random.default_rng(m * 1000 + n + k)
+    A = rng.standard_normal((k, m) if ta else (m, k)).astype(np.float32)
+    B = rng.standard_normal((n, k) if tb else (k, n)).astype(np.float32)
+    C = M.gemm_bf16(_t(A), _t(B), ta, tb).cpu().numpy().astype(np.float64)
+    Ab = wo.bf16_round(A.T if ta else A)
+    Bb = wo.bf16_round(B.T if tb else B)
+    ref = Ab @ Bb
+    bound = np.abs(Ab) @ np.abs(Bb)
+    assert np.all(np.abs(C - ref) <= 2e-6 * bound + 1e-30)
+
+
+def _mlp_case(sizes, B, seed):
+    rng = np.random.default_rng(seed)
+    parts = []
+    for l in range(3):
+        lim = 1.0 / np.sqrt(sizes[l])
+        parts.append(rng.uniform(-lim, lim, sizes[l + 1] * sizes[l]))
+        parts.append(rng.uniform(-0.1, 0.1, sizes[l + 1]))
+    p = np.concatenate(parts).astype(np.float32)
+    X = rng.standard_normal((B, sizes[0])).astype(np.float32)
+    T = (0.5 * rng.standard_normal((B, sizes[3]))).astype(np.float32)
+    return p, X, T
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("sizes,B", [((96, 64, 64, 40), 10), ((4096, 256, 256, 1024), 96), ((300, 48, 48, 17), 1)])
+def test_mlp_forward_and_gradient_vs_oracle(M, sizes, B):
+    p, X, T = _mlp_case(sizes, B, seed=sizes[0] + B)
+    net = M.MLP(*sizes[:2], sizes[3], seed=1)
+    assert net.n_params == wo.n_params(sizes)
+    net.set_params(_t(p))
+    Y = net.forward(_t(X)).cpu().numpy().astype(np.float64)
+    Yr = wo.mlp_forward(p, sizes, X.astype(np.float64), round_weights=True)[0]
+    assert _rel(Y, Yr) < 1e-2
+    loss, grad = net.loss_grad(_t(X), _t(T))
+    lr_, gr = wo.mlp_loss_grad(p, sizes, X.astype(np.float64), T.astype(np.float64), round_weights=True)
+    assert abs(float(loss.item()) - lr_) <= 2e-2 * lr_
+    g = grad.cpu().numpy().astype(np.float64)
+    for l, (sw, sb) in enumerate(wo.layer_slices(sizes)):
+        for sl, name in ((sw, "W"), (sb, "b")):
+            a, b = g[sl], gr[sl]
+            cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
+            assert _rel(a, b) <= 2e-2, (l, name, _rel(a, b))
+            assert cos >= 0.999, (l, name, cos)
+
+
+def test_adam_step_vs_oracle(M):
+    sizes = (96, 64, 64, 40)
+    p, X, T = _mlp_case(sizes, 12, seed=7)
+    net = M.MLP(96, 64, 40, seed=3)
+    net.set_params(_t(p))
+    net.loss_grad(_t(X), _t(T))
+    net.adam_step(1e-3, 0.9, 0.999, 1e-8)
+    p1 = net.get_params().cpu().numpy().astype(np.float64)
+    _, gr = wo.mlp_loss_grad(p, sizes, X.astype(np.float64), T.astype(np.float64), round_weights=True)
+    ref, _, _ = wo.adam_step(p.astype(np.float64), gr, np.zeros_like(gr), np.zeros_like(gr), 1)
+    big = np.abs(gr) > 1e-2 * np.max(np.abs(gr))  # sign of tiny gradients may flip under BF16 products
+    assert big.sum() > 0.5 * big.size
+    assert np.max(np.abs(p1 - ref)[big]) < 1e-6
+
+
+@pytest.fixture(scope="module")
+def geo5():
+    geom, _ = wl.config5_geometry()
+    return geom
+
+
+def _warm(M, geom, seed=0, n_modes=128, n_hist=4, width=256):
+    return M.WarmStart(_t(geom.theta, torch.float64), _t(geom.theta_w, torch.float64), geom.curve_node_ptr,
+                       n_modes=n_modes, n_hist=n_hist, width=width, seed=seed)
+
+
+def test_fourier_analysis_synthesis_vs_oracle(M, geo5):
+    geom = geo5
+    W = _warm(M, geom)
+    rng = np.random.default_rng(21)
+    mu = rng.standard_normal((3, geom.n_nodes))
+    c = W.coefficients(_t(mu, torch.float64)).cpu().numpy()
+    cr = wo.fourier_coefficients(geom.theta, geom.theta_w, geom.curve_node_ptr, mu, 128)
+    assert np.max(np.abs(c - cr)) < 1e-13 * np.max(np.abs(mu))
+    coef = rng.standard_normal((2, W.n_features)) / (1.0 + np.tile(np.repeat(np.arange(128), 2), 4))
+    base = rng.standard_normal((2, geom.n_nodes))
+    s = W.synthesize(_t(coef, torch.float64), _t(base, torch.float64)).cpu().numpy()
+    sr = base + wo.fourier_synthesis(geom.theta, geom.curve_node_ptr, coef, 128)
+    assert np.max(np.abs(s - sr)) < 1e-12 * np.max(np.abs(sr))
+
+
+def test_warm_predict_vs_oracle(M, geo5):
+    """Scales and prediction with host-set weights on a seeded synthetic series."""
+    geom = geo5
+    W = _warm(M, geom, n_modes=32, n_hist=4, width=64)
+    rng = np.random.default_rng(33)
+    series = np.cumsum(rng.standard_normal((9, geom.n_nodes)) * 0.1, axis=0) + rng.standard_normal(geom.n_nodes)
+    W.train(_t(series, torch.float64), iters=0)
+    sizes = W.mlp.sizes
+    p, _, _ = _mlp_case(sizes, 1, seed=44)
+    W.mlp.set_params(_t(p))
+    coef_r = wo.fourier_coefficients(geom.theta, geom.theta_w, geom.curve_node_ptr, series, 32)
+    sx, sy = wo.warm_scales(coef_r, 4)
+    gsx, gsy = W.scales()
+    assert abs(gsx / sx - 1) < 1e-12 and abs(gsy / sy - 1) < 1e-12
+    hist = series[-4:]
+    x0 = W.predict(_t(hist, torch.float64)).cpu().numpy()
+    Xr = (coef_r[-4:].ravel() * sx)[None, :]
+    Yr = wo.mlp_forward(p, sizes, Xr, round_weights=True)[0] * sy
+    inc = wo.fourier_synthesis(geom.theta, geom.curve_node_ptr, Yr, 32)[0]
+    assert _rel(x0 - hist[-1], inc) < 1e-2
+
+
+def test_warm_requires_training_and_validates(M, geo5):
+    W = _warm(M, geo5, n_modes=8, n_hist=2, width=16)
+    with pytest.raises(M.MhlpError):
+        W.predict(torch.zeros(2 * geo5.n_nodes, dtype=torch.float64, device=DEV))
+    with pytest.raises(M.MhlpError):
+        W.train(torch.zeros(2, geo5.n_nodes, dtype=torch.float64, device=DEV), iters=1)  # needs n_hist + 1 steps
+    with pytest.raises(M.MhlpError):
+        M.WarmStart(_t(geo5.theta, torch.float64), _t(geo5.theta_w, torch.float64), [0, 100, 50, geo5.n_nodes])
+
+
+@pytest.fixture(scope="module")
+def series5(M):
+    cfg = wl.config5()
+    geom = cfg["geom"]
+    G = M.Geometry(_t(geom.node_soa(), torch.float64))
+    plan = M.Plan(G, cfg["alpha"])
+    g = _t(cfg["g"], torch.float64)
+    mus, infos = [], []
+    x0 = None
+    for s in range(100):
+        mu, info = M.gmres_solve(plan, g[s], x0=x0, tol=1e-10, restart=100)
+        assert info["converged"] and info["rel_residual"] <= 1e-10
+        mus.append(mu)
+        x0 = mu
+    return dict(cfg=cfg, geom=geom, G=G, plan=plan, g=g, mus=torch.stack(mus))
+
+
+def test_learned_warm_start_reduces_gmres_iterations(M, series5):
+    d = series5
+    W = _warm(M, d["geom"], seed=5)
+    losses = W.train(d["mus"], iters=2000, lr=1e-3)
+    assert np.isfinite(losses).all() and losses[-1] < 0.05 * losses[0]
+    hist = list(d["mus"][-4:])
+    its = {"zero": [], "previous": [], "learned": []}
+    for s in range(100, 116):
+        g = d["g"][s]
+        mu, iz = M.gmres_solve(d["plan"], g, tol=1e-10, restart=100)
+        _, ip = M.gmres_solve(d["plan"], g, x0=hist[-1], tol=1e-10, restart=100)
+        x0 = W.predict(torch.stack(hist[-4:]).contiguous())
+        _, il = M.gmres_solve(d["plan"], g, x0=x0, tol=1e-10, restart=100)
+        for k, inf in (("zero", iz), ("previous", ip), ("learned", il)):
+            assert inf["converged"] and inf["rel_residual"] <= 1e-10, (s, k, inf)
+            its[k].append(inf["iters"])
+        assert il["used_x0"] == 1
+        hist = hist[1:] + [mu]
+    mean = {k: float(np.mean(v)) for k, v in its.items()}
+    print("mean GMRES iterations to 1e-10:", mean)
+    assert mean["learned"] < mean["zero"]
+
+
+def test_bad_initial_guess_falls_back_to_zero(M, series5):
+    d = series5
+    g = d["g"][100]
+    bad = torch.full_like(g, 1e6)
+    mu, info = M.gmres_solve(d["plan"], g, x0=bad, tol=1e-10, restart=100)
+    _, iz = M.gmres_solve(d["plan"], g, tol=1e-10, restart=100)
+    assert info["used_x0"] == 0 and info["x0_residual"] >= 1.0
+    assert info["converged"] and info["iters"] == iz["iters"]
