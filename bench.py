@@ -205,6 +205,7 @@ def main():
     if not args.no_extra:
         out["batched"] = bench_batched(mhlp, wl, t, torch)
         out["volume"] = bench_volume(mhlp, wl, t, torch)
+        out["warm_start"] = bench_warm(mhlp, wl, t, torch)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, 50.0, args.cpu_seconds)
     print(json.dumps(out), flush=True)
@@ -270,6 +271,77 @@ def bench_volume(mhlp, wl, t, torch):
     d = res.pop("_u")
     res["mixed_max_rel_err_vs_fp64"] = float((d["mixed"] - d["fp64"]).abs().max() / d["fp64"].abs().max())
     res["pairs"] = len(c["x"]) ** 2
+    return res
+
+
+def bench_warm(mhlp, wl, t, torch):
+    """Multiply connected time series (outer circle + 3 starfish holes, 14,336 nodes,
+    alpha 30, 200 steps): train the learned initial guess on the densities of steps
+    1-100, then solve steps 101-200 to 1e-10 from four initial guesses (zero, the
+    previous density, cubic extrapolation of the last four, learned)."""
+    print("# warm-start leg", file=sys.stderr, flush=True)
+    cfg = wl.config5()
+    geom = cfg["geom"]
+    plan = mhlp.Plan(mhlp.Geometry(t(geom.node_soa())), cfg["alpha"])
+    g = t(cfg["g"])
+    kw = dict(tol=1e-10, restart=100, max_iter=400)
+    mus = []
+    x0 = None
+    for s in range(100):
+        mu, _ = mhlp.gmres_solve(plan, g[s], x0=x0, **kw)
+        mus.append(mu)
+        x0 = mu
+    W = mhlp.WarmStart(t(geom.theta), t(geom.theta_w), geom.curve_node_ptr, n_modes=128, n_hist=4, base_order=3,
+                       width=256, seed=5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = W.train(torch.stack(mus).contiguous(), iters=2000, lr=1e-3)
+    train_ms = (time.perf_counter() - t0) * 1e3
+    hist = torch.stack(mus[-4:]).contiguous()
+
+    def guess(kind):
+        if kind == "zero":
+            return None
+        if kind == "previous":
+            return hist[-1]
+        if kind == "cubic":
+            return 4 * hist[-1] - 6 * hist[-2] + 4 * hist[-3] - hist[-4]
+        return W.predict(hist)
+
+    kinds = ("zero", "previous", "cubic", "learned")
+    rec = {k: dict(iters=[], ms=[], res=[], x0res=[], used=[]) for k in kinds}
+    pred_ms = []
+    for s in range(100, 200):
+        mu_true = None
+        for k in kinds:
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            x0 = guess(k)
+            if k == "learned":
+                torch.cuda.synchronize()
+                pred_ms.append((time.perf_counter() - t1) * 1e3)
+            mu, info = mhlp.gmres_solve(plan, g[s], x0=x0, **kw)
+            torch.cuda.synchronize()
+            r = rec[k]
+            r["ms"].append((time.perf_counter() - t1) * 1e3)
+            r["iters"].append(info["iters"])
+            r["res"].append(info["rel_residual"])
+            r["x0res"].append(info["x0_residual"])
+            r["used"].append(info["used_x0"])
+            if k == "zero":
+                mu_true = mu
+        hist = torch.cat([hist[1:], mu_true[None]]).contiguous()
+    z_ms = float(np.mean(rec["zero"]["ms"]))
+    res = {"steps": "101-200", "n_nodes": geom.n_nodes, "train_ms": round(train_ms, 1),
+           "train_loss_first_last": [float(losses[0]), float(losses[-1])],
+           "predict_ms_mean": round(float(np.mean(pred_ms)), 3)}
+    for k in kinds:
+        r = rec[k]
+        res[k] = {"mean_iters": round(float(np.mean(r["iters"])), 3), "mean_ms": round(float(np.mean(r["ms"])), 3),
+                  "speedup_vs_zero": round(z_ms / float(np.mean(r["ms"])), 3),
+                  "max_residual": float(np.max(r["res"])),
+                  "median_x0_residual": float(np.median(r["x0res"])) if k != "zero" else 1.0,
+                  "x0_used": int(np.sum(r["used"])) if k != "zero" else 0}
     return res
 
 

@@ -213,21 +213,28 @@ mhlp_status mhlp_gemm_bf16(int32_t m, int32_t n, int32_t k, const float *A, int6
 /* Warm-start model (mhlp_warm): Fourier features of the density on each
    closed curve in its parameter theta, c_k = (1/2 pi) int mu e^{-i k theta},
    k = 0..n_modes-1, by the panel quadrature in theta; F = 2 n_modes n_curves
-   reals per density, ordered [curve][k][Re, Im].  The network maps the
-   coefficients of the last n_hist densities (scaled by one global factor) to
-   the increment of the next density's coefficients (in units of the RMS
-   training increment).
+   reals per density, ordered [curve][k][Re, Im].  From the coefficients of
+   the last n_hist densities (newest last) the network input is, for
+   h = 0..n_hist-1, the h-th backward difference of the newest coefficients,
+   each group scaled to unit RMS over the training samples.  The network
+   predicts the error of the order-p polynomial extrapolation of the history,
+   sum_{i<=p} (-1)^i C(p+1, i+1) c_{s-i}  (p = base_order; 0 = the last
+   density, 1 = linear, 2 = quadratic, 3 = cubic), in units of its RMS over
+   the training samples; the initial guess is the same extrapolation of the
+   densities plus the synthesis of the predicted correction.
    theta, omega: device [N] float64, curve parameter and theta-quadrature
    weight of each node (copied); curve_ptr: host [n_curves+1], node ranges of
-   the curves (0 = curve_ptr[0] < ... < curve_ptr[n_curves] = N).  The network
-   is n_hist*F -> width -> width -> F.  Synchronises the stream. */
+   the curves (0 = curve_ptr[0] < ... < curve_ptr[n_curves] = N).
+   1 <= n_hist <= 8, 0 <= base_order <= min(3, n_hist - 1).  The network is
+   n_hist*F -> width -> width -> F.  Synchronises the stream. */
 typedef struct mhlp_warm mhlp_warm;
 mhlp_status mhlp_warm_create(const double *theta, const double *omega, const int64_t *curve_ptr, int32_t n_curves,
-                             int32_t n_modes, int32_t n_hist, int32_t width, uint64_t seed, void *stream,
-                             mhlp_warm **out);
+                             int32_t n_modes, int32_t n_hist, int32_t base_order, int32_t width, uint64_t seed,
+                             void *stream, mhlp_warm **out);
 mhlp_status mhlp_warm_destroy(mhlp_warm *warm);
-/* node count, F, the network (borrowed, owned by the model) and the two
-   scales {input factor, output unit} (host [2]; synchronous); any may be NULL */
+/* node count, F, the network (borrowed, owned by the model) and the scales
+   {input group factors 0..n_hist-1, output unit} (host [n_hist+1];
+   synchronous); any may be NULL */
 mhlp_status mhlp_warm_info(const mhlp_warm *warm, int64_t *n_nodes, int64_t *n_features, mhlp_mlp **net,
                            double *scales);
 /* coef [n_dens][F] = Fourier coefficients of mu [n_dens][N] (FP64) */
@@ -243,8 +250,8 @@ mhlp_status mhlp_warm_synthesize(const mhlp_warm *warm, const double *coef, int3
    series.  losses: host [iters] (may be NULL).  Synchronises the stream. */
 mhlp_status mhlp_warm_train(mhlp_warm *warm, const double *mus, int32_t n_steps, int32_t iters, float lr,
                             float *losses, void *stream);
-/* x0 [N] = hist[n_hist-1] + predicted increment, from hist [n_hist][N]
-   (oldest first).  Errors: MHLP_INVALID_ARG before training. */
+/* x0 [N] = extrapolation of hist [n_hist][N] (oldest first) + predicted
+   correction.  Errors: MHLP_INVALID_ARG before training. */
 mhlp_status mhlp_warm_predict(mhlp_warm *warm, const double *hist, double *x0, void *stream);
 
 #ifdef __cplusplus

@@ -11,6 +11,9 @@ the benchmark.
   hidden layers, mean-squared-error loss, back-propagation, Adam.  Weights may
   be rounded to BF16 (round to nearest even) before use, as the matrix cores
   see them; everything else is FP64.
+* The warm-start data: network inputs are the backward differences of a
+  window of coefficient rows, targets the error of polynomial extrapolation
+  of the window one step ahead.
 
 Parameter layout (shared convention with the library): for l = 0, 1, 2 the
 weight W_l as a row-major [n_{l+1}][n_l] block followed by the bias b_l.
@@ -158,18 +161,48 @@ def fourier_synthesis(theta, curve_ptr, coef, n_modes):
     return out
 
 
-def warm_scales(coef, n_hist):
-    """{1 / RMS of the input rows 0..n-2, RMS of the increments of rows n_hist..n-1}."""
-    coef = np.asarray(coef, dtype=np.float64)
-    rx = math.sqrt(np.mean(coef[:-1] ** 2))
-    ry = math.sqrt(np.mean((coef[n_hist:] - coef[n_hist - 1:-1]) ** 2))
-    return (1.0 / rx if rx > 0 else 1.0), (ry if ry > 0 else 1.0)
+def extrapolation_coeffs(p):
+    """b_i, i = 0..p, of the degree-p polynomial through the last p+1 equally
+    spaced values, evaluated one step ahead: next = sum_i b_i x_{s-i}."""
+    return np.array([(-1) ** i * math.comb(p + 1, i + 1) for i in range(p + 1)], dtype=np.float64)
 
 
-def warm_samples(coef, n_hist, scales):
-    """Network inputs [S][n_hist F] and targets [S][F] of a training series."""
+def warm_features(coef, n_hist, order):
+    """Network input groups [S][n_hist][F] (backward differences 0..n_hist-1 of
+    the newest row of each window) and targets [S][F] (next row minus the
+    order-p extrapolation of the window)."""
     coef = np.asarray(coef, dtype=np.float64)
     S = coef.shape[0] - n_hist
-    X = np.stack([coef[j:j + n_hist].ravel() for j in range(S)]) * scales[0]
-    T = (coef[n_hist:] - coef[n_hist - 1:-1]) / scales[1]
-    return X, T
+    grp = np.zeros((S, n_hist, coef.shape[1]))
+    for j in range(S):
+        cur = coef[j:j + n_hist].copy()
+        grp[j, 0] = cur[-1]
+        for h in range(1, n_hist):  # repeated first differences of the window
+            cur = cur[1:] - cur[:-1]
+            grp[j, h] = cur[-1]
+    b = extrapolation_coeffs(order)
+    tgt = np.stack([coef[j + n_hist] - sum(b[i] * coef[j + n_hist - 1 - i] for i in range(order + 1))
+                    for j in range(S)])
+    return grp, tgt
+
+
+def warm_scales(coef, n_hist, order):
+    """(1 / RMS of each input group over the samples, RMS of the targets)."""
+    grp, tgt = warm_features(coef, n_hist, order)
+    gx = [math.sqrt(np.mean(grp[:, h] ** 2)) for h in range(n_hist)]
+    ry = math.sqrt(np.mean(tgt ** 2))
+    return [1.0 / r if r > 0 else 1.0 for r in gx], (ry if ry > 0 else 1.0)
+
+
+def warm_samples(coef, n_hist, order, scales):
+    """Network inputs [S][n_hist F] and targets [S][F] of a training series."""
+    grp, tgt = warm_features(coef, n_hist, order)
+    X = (grp * np.asarray(scales[0])[None, :, None]).reshape(grp.shape[0], -1)
+    return X, tgt / scales[1]
+
+
+def warm_input(hist_coef, scales):
+    """Network input of one window of coefficients [n_hist][F] (newest last)."""
+    h = np.asarray(hist_coef, dtype=np.float64)
+    grp, _ = warm_features(np.vstack([h, h[-1:]]), h.shape[0], 0)
+    return (grp * np.asarray(scales[0])[None, :, None]).reshape(1, -1)

@@ -17,9 +17,13 @@
  * runs on the matrix cores with operands rounded to BF16 and FP32
  * accumulation (v_mfma_f32_16x16x16_bf16).
  *
- * Warm start.  Input: the coefficients of the last H densities, scaled by one
- * global factor; output: the increment c_{s+1} - c_s in units of the RMS
- * training increment; initial guess mu_s + synthesis(increment).
+ * Warm start.  Input: the backward differences 0..H-1 of the coefficients of
+ * the last H densities (an invertible linear map of the history that keeps
+ * small differences at full BF16 relative precision), each group scaled to
+ * unit RMS over the training samples; output: the error of the order-p
+ * polynomial extrapolation of the history (p = 0: the increment over the
+ * last density), in units of its training RMS; initial guess
+ * extrapolation(mu_{s-p..s}) + synthesis(output).
  */
 #include <hip/hip_runtime.h>
 
@@ -545,13 +549,43 @@ __global__ __launch_bounds__(256) void fourier_analysis_kernel(const double *__r
     }
 }
 
-/* out[d][m] = base[d][m] + scale * sum_k s_k (Re c_k cos k theta - Im c_k sin k theta),
+/* History maps of the warm start (all FP64, by value).
+   H rows of history, newest last.  Network input group h (h = 0..H-1) is the
+   h-th backward difference of the newest row, sum_i (-1)^i C(h,i) row[H-1-i];
+   the base prediction is the order-p polynomial extrapolation
+   sum_i b_i row[H-1-i], b_i = (-1)^i C(p+1, i+1) (p = 0: the newest row). */
+constexpr int MAX_HIST = 8;
+struct WarmMap {
+    int H, p;
+    double diff[MAX_HIST][MAX_HIST]; /* diff[h][i] = (-1)^i C(h, i), i <= h */
+    double b[4];
+};
+
+static WarmMap make_map(int H, int p)
+{
+    WarmMap w{};
+    w.H = H;
+    w.p = p;
+    double C[MAX_HIST + 1][MAX_HIST + 1] = {};
+    for (int n = 0; n <= MAX_HIST; ++n) {
+        C[n][0] = 1.0;
+        for (int k = 1; k <= n; ++k) C[n][k] = C[n - 1][k - 1] + (k <= n - 1 ? C[n - 1][k] : 0.0);
+    }
+    for (int h = 0; h < MAX_HIST; ++h)
+        for (int i = 0; i <= h; ++i) w.diff[h][i] = (i % 2 ? -1.0 : 1.0) * C[h][i];
+    for (int i = 0; i <= p; ++i) w.b[i] = (i % 2 ? -1.0 : 1.0) * C[p + 1][i + 1];
+    return w;
+}
+
+/* out[d][m] = base_d(m) + scale * sum_k s_k (Re c_k cos k theta - Im c_k sin k theta),
    s_0 = 1, s_k = 2; coefficients of type T (FP64 or the network's FP32), scale
-   read from device memory (NULL = 1). */
+   read from device memory (NULL = 1); base_d(m) = sum_{i<=p} b_i
+   base[d*dstride + (last - i)*n + m] (base NULL = 0). */
 template <class T>
 __global__ void fourier_synthesis_kernel(const double *__restrict__ theta, const int32_t *__restrict__ cid, int64_t n,
                                          int K, int64_t F, const T *__restrict__ coef,
                                          const double *__restrict__ scale, const double *__restrict__ base,
+                                         int64_t dstride, int last, int p, double b0, double b1, double b2, double b3,
                                          double *__restrict__ out)
 {
     const int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -566,7 +600,13 @@ __global__ void fourier_synthesis_kernel(const double *__restrict__ theta, const
         acc += 2.0 * ((double)cd[2 * k] * co - (double)cd[2 * k + 1] * s);
     }
     if (scale) acc *= scale[0];
-    out[d * n + m] = (base ? base[d * n + m] : 0.0) + acc;
+    double bv = 0.0;
+    if (base) {
+        const double bb[4] = {b0, b1, b2, b3};
+        const double *bd = base + d * dstride + m;
+        for (int i = 0; i <= p; ++i) bv += bb[i] * bd[(int64_t)(last - i) * n];
+    }
+    out[d * n + m] = bv + acc;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -574,13 +614,14 @@ __global__ void fourier_synthesis_kernel(const double *__restrict__ theta, const
 /* ------------------------------------------------------------------------ */
 struct mhlp_warm {
     int64_t n = 0;
-    int n_curves = 0, K = 0, H = 0;
+    int n_curves = 0, K = 0, H = 0, order = 0;
     int64_t F = 0;
+    WarmMap map{};
     double *theta = nullptr, *omega = nullptr;
     int32_t *cid = nullptr;
     int64_t *cptr = nullptr;
     mhlp_mlp *net = nullptr;
-    double *scales = nullptr; /* device [2]: input factor, output unit */
+    double *scales = nullptr; /* device [H+1]: input group factors, output unit */
     double *coef = nullptr;
     int64_t coef_rows = 0;
     float *X = nullptr, *T = nullptr, *Y = nullptr, *losses = nullptr;
@@ -588,54 +629,63 @@ struct mhlp_warm {
     bool trained = false;
 };
 
-/* RMS of the coefficient rows 0..rows-2 (network inputs) and of the
-   increments of rows H..rows-1 (network targets): scales = {1/rms_in, rms_inc} */
-__global__ __launch_bounds__(1024) void warm_scales_kernel(const double *__restrict__ coef, int64_t rows, int64_t F,
-                                                           int H, double *__restrict__ scales)
+/* input groups and target of sample j, feature f (coefficient rows j..j+H) */
+__device__ __forceinline__ void warm_features(const WarmMap &w, const double *__restrict__ coef, int64_t F, int64_t j,
+                                              int64_t f, double *grp, double *tgt, bool with_target)
 {
-    __shared__ double red[2][1024];
-    double sx = 0.0, sy = 0.0;
-    for (int64_t i = threadIdx.x; i < rows * F; i += 1024) {
-        const int64_t r = i / F;
-        const double c = coef[i];
-        if (r <= rows - 2) sx += c * c;
-        if (r >= H) {
-            const double d = c - coef[i - F];
-            sy += d * d;
-        }
+    const double *c = coef + j * F + f; /* c[r*F] = row j + r */
+    for (int h = 0; h < w.H; ++h) {
+        double v = 0.0;
+        for (int i = 0; i <= h; ++i) v += w.diff[h][i] * c[(int64_t)(w.H - 1 - i) * F];
+        grp[h] = v;
     }
-    red[0][threadIdx.x] = sx;
-    red[1][threadIdx.x] = sy;
-    __syncthreads();
-    for (int o = 512; o > 0; o >>= 1) {
-        if (threadIdx.x < o) {
-            red[0][threadIdx.x] += red[0][threadIdx.x + o];
-            red[1][threadIdx.x] += red[1][threadIdx.x + o];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        const double rx = sqrt(red[0][0] / (double)((rows - 1) * F));
-        const double ry = sqrt(red[1][0] / (double)((rows - H) * F));
-        scales[0] = rx > 0.0 ? 1.0 / rx : 1.0;
-        scales[1] = ry > 0.0 ? ry : 1.0;
+    if (with_target) {
+        double e = c[(int64_t)w.H * F];
+        for (int i = 0; i <= w.p; ++i) e -= w.b[i] * c[(int64_t)(w.H - 1 - i) * F];
+        *tgt = e;
     }
 }
 
-/* sample j: X[j] = (coef rows j..j+H-1) * scales[0];
-             T[j] = (coef[j+H] - coef[j+H-1]) / scales[1]  (T optional) */
-__global__ void warm_samples_kernel(const double *__restrict__ coef, int64_t n_samples, int64_t F, int H,
+/* scales[h] = 1 / RMS of input group h, scales[H] = RMS of the target, over
+   all samples j < S and features */
+__global__ __launch_bounds__(256) void warm_scales_kernel(WarmMap w, const double *__restrict__ coef, int64_t S,
+                                                          int64_t F, double *__restrict__ scales)
+{
+    __shared__ double red[MAX_HIST + 1][256];
+    double acc[MAX_HIST + 1];
+    for (int h = 0; h <= MAX_HIST; ++h) acc[h] = 0.0;
+    for (int64_t i = threadIdx.x; i < S * F; i += 256) {
+        double grp[MAX_HIST], tgt;
+        warm_features(w, coef, F, i / F, i % F, grp, &tgt, true);
+        for (int h = 0; h < w.H; ++h) acc[h] += grp[h] * grp[h];
+        acc[w.H] += tgt * tgt;
+    }
+    for (int h = 0; h <= w.H; ++h) red[h][threadIdx.x] = acc[h];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o)
+            for (int h = 0; h <= w.H; ++h) red[h][threadIdx.x] += red[h][threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x <= w.H) {
+        const int h = threadIdx.x;
+        const double r = sqrt(red[h][0] / (double)(S * F));
+        scales[h] = h < w.H ? (r > 0.0 ? 1.0 / r : 1.0) : (r > 0.0 ? r : 1.0);
+    }
+}
+
+/* X[j][h*F + f] = group h * scales[h];  T[j][f] = target / scales[H] (T optional) */
+__global__ void warm_samples_kernel(WarmMap w, const double *__restrict__ coef, int64_t n_samples, int64_t F,
                                     const double *__restrict__ scales, float *__restrict__ X, float *__restrict__ T)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t HF = (int64_t)H * F;
-    if (i >= n_samples * HF) return;
-    const int64_t j = i / HF, q = i % HF;
-    X[i] = (float)(coef[j * F + q] * scales[0]);
-    if (T && q >= HF - F) {
-        const int64_t f = q - (HF - F);
-        T[j * F + f] = (float)((coef[(j + H) * F + f] - coef[(j + H - 1) * F + f]) / scales[1]);
-    }
+    if (i >= n_samples * F) return;
+    const int64_t j = i / F, f = i % F;
+    double grp[MAX_HIST], tgt = 0.0;
+    warm_features(w, coef, F, j, f, grp, &tgt, T != nullptr);
+    float *xj = X + j * (int64_t)w.H * F;
+    for (int h = 0; h < w.H; ++h) xj[(int64_t)h * F + f] = (float)(grp[h] * scales[h]);
+    if (T) T[j * F + f] = (float)(tgt / scales[w.H]);
 }
 
 extern "C" mhlp_status mhlp_warm_destroy(mhlp_warm *W)
@@ -658,14 +708,17 @@ extern "C" mhlp_status mhlp_warm_destroy(mhlp_warm *W)
 }
 
 extern "C" mhlp_status mhlp_warm_create(const double *theta, const double *omega, const int64_t *curve_ptr,
-                                        int32_t n_curves, int32_t n_modes, int32_t n_hist, int32_t width,
-                                        uint64_t seed, void *stream, mhlp_warm **out)
+                                        int32_t n_curves, int32_t n_modes, int32_t n_hist, int32_t base_order,
+                                        int32_t width, uint64_t seed, void *stream, mhlp_warm **out)
 {
     if (!out) return mfail(MHLP_INVALID_ARG, "out is NULL");
     *out = nullptr;
     if (!theta || !omega || !curve_ptr) return mfail(MHLP_INVALID_ARG, "NULL argument");
     if (n_curves < 1 || n_modes < 1 || n_hist < 1 || width < 1)
         return mfail(MHLP_INVALID_ARG, "n_curves, n_modes, n_hist and width must be >= 1");
+    if (n_hist > MAX_HIST) return mfail(MHLP_INVALID_ARG, "n_hist > 8");
+    if (base_order < 0 || base_order > 3 || base_order >= n_hist)
+        return mfail(MHLP_INVALID_ARG, "base_order must be in [0, min(3, n_hist - 1)]");
     if ((int64_t)n_curves * n_modes > 65535) return mfail(MHLP_INVALID_ARG, "n_curves * n_modes > 65535");
     if (curve_ptr[0] != 0) return mfail(MHLP_INVALID_ARG, "curve_ptr[0] must be 0");
     for (int c = 0; c < n_curves; ++c)
@@ -679,13 +732,15 @@ extern "C" mhlp_status mhlp_warm_create(const double *theta, const double *omega
     W->n_curves = n_curves;
     W->K = n_modes;
     W->H = n_hist;
+    W->order = base_order;
+    W->map = make_map(n_hist, base_order);
     W->F = F;
     std::vector<int32_t> cid(n);
     for (int c = 0; c < n_curves; ++c)
         for (int64_t i = curve_ptr[c]; i < curve_ptr[c + 1]; ++i) cid[i] = c;
     mhlp_status s;
     if ((s = malloc_dev(&W->theta, n)) || (s = malloc_dev(&W->omega, n)) || (s = malloc_dev(&W->cid, n)) ||
-        (s = malloc_dev(&W->cptr, n_curves + 1)) || (s = malloc_dev(&W->scales, 2)) ||
+        (s = malloc_dev(&W->cptr, n_curves + 1)) || (s = malloc_dev(&W->scales, n_hist + 1)) ||
         (s = malloc_dev(&W->Y, F))) {
         mhlp_warm_destroy(W);
         return s;
@@ -715,7 +770,7 @@ extern "C" mhlp_status mhlp_warm_info(const mhlp_warm *W, int64_t *n_nodes, int6
     if (n_nodes) *n_nodes = W->n;
     if (n_features) *n_features = W->F;
     if (net) *net = W->net;
-    if (scales) MHIP(hipMemcpy(scales, W->scales, 2 * sizeof(double), hipMemcpyDeviceToHost));
+    if (scales) MHIP(hipMemcpy(scales, W->scales, (W->H + 1) * sizeof(double), hipMemcpyDeviceToHost));
     return MHLP_OK;
 }
 
@@ -752,8 +807,8 @@ extern "C" mhlp_status mhlp_warm_synthesize(const mhlp_warm *W, const double *co
     if (!W || !coef || !out) return mfail(MHLP_INVALID_ARG, "NULL argument");
     if (n_dens < 1 || n_dens > 65535) return mfail(MHLP_INVALID_ARG, "n_dens must be in [1, 65535]");
     dim3 grid(nb(W->n, 256), (unsigned)n_dens);
-    fourier_synthesis_kernel<double><<<grid, 256, 0, (hipStream_t)stream>>>(W->theta, W->cid, W->n, W->K, W->F, coef,
-                                                                            nullptr, base, out);
+    fourier_synthesis_kernel<double><<<grid, 256, 0, (hipStream_t)stream>>>(
+        W->theta, W->cid, W->n, W->K, W->F, coef, nullptr, base, W->n, 0, 0, 1.0, 0.0, 0.0, 0.0, out);
     MHIP(hipGetLastError());
     return MHLP_OK;
 }
@@ -787,8 +842,8 @@ extern "C" mhlp_status mhlp_warm_train(mhlp_warm *W, const double *mus, int32_t 
         W->loss_cap = lc;
     }
     analysis(W, mus, n_steps, W->coef, st);
-    warm_scales_kernel<<<1, 1024, 0, st>>>(W->coef, n_steps, W->F, W->H, W->scales);
-    warm_samples_kernel<<<nb(S * W->H * W->F, 256), 256, 0, st>>>(W->coef, S, W->F, W->H, W->scales, W->X, W->T);
+    warm_scales_kernel<<<1, 256, 0, st>>>(W->map, W->coef, S, W->F, W->scales);
+    warm_samples_kernel<<<nb(S * W->F, 256), 256, 0, st>>>(W->map, W->coef, S, W->F, W->scales, W->X, W->T);
     MHIP(hipGetLastError());
     for (int it = 0; it < iters; ++it) {
         if (mhlp_status s = mhlp_mlp_loss_grad(W->net, W->X, W->T, (int32_t)S, W->losses + it, nullptr, stream))
@@ -809,12 +864,12 @@ extern "C" mhlp_status mhlp_warm_predict(mhlp_warm *W, const double *hist, doubl
     hipStream_t st = (hipStream_t)stream;
     if (mhlp_status s = ensure_coef(W, W->H, st)) return s;
     analysis(W, hist, W->H, W->coef, st);
-    warm_samples_kernel<<<nb((int64_t)W->H * W->F, 256), 256, 0, st>>>(W->coef, 1, W->F, W->H, W->scales, W->X,
-                                                                        nullptr);
+    warm_samples_kernel<<<nb(W->F, 256), 256, 0, st>>>(W->map, W->coef, 1, W->F, W->scales, W->X, nullptr);
     if (mhlp_status s = mhlp_mlp_forward(W->net, W->X, 1, W->Y, stream)) return s;
     dim3 grid(nb(W->n, 256), 1);
-    fourier_synthesis_kernel<float><<<grid, 256, 0, st>>>(W->theta, W->cid, W->n, W->K, W->F, W->Y, W->scales + 1,
-                                                          hist + (int64_t)(W->H - 1) * W->n, x0);
+    const WarmMap &w = W->map;
+    fourier_synthesis_kernel<float><<<grid, 256, 0, st>>>(W->theta, W->cid, W->n, W->K, W->F, W->Y, W->scales + W->H,
+                                                          hist, 0, W->H - 1, w.p, w.b[0], w.b[1], w.b[2], w.b[3], x0);
     MHIP(hipGetLastError());
     return MHLP_OK;
 }

@@ -87,7 +87,7 @@ _SIGS = {
     "mhlp_gemm_bf16": ([ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _V, ctypes.c_int64, ctypes.c_int64, _V,
                         ctypes.c_int64, ctypes.c_int64, _V, ctypes.c_int64, _V], ctypes.c_int32),
     "mhlp_warm_create": ([_V, _V, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
-                          ctypes.c_int32, ctypes.c_uint64, _V, ctypes.POINTER(_V)], ctypes.c_int32),
+                          ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, _V, ctypes.POINTER(_V)], ctypes.c_int32),
     "mhlp_warm_destroy": ([_V], ctypes.c_int32),
     "mhlp_warm_info": ([_V, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_V),
                         _c_double_p], ctypes.c_int32),
@@ -397,7 +397,7 @@ class MLP:
 class WarmStart:
     """Learned GMRES initial guess from the last ``n_hist`` densities."""
 
-    def __init__(self, theta, omega, curve_ptr, n_modes=128, n_hist=4, width=256, seed=0):
+    def __init__(self, theta, omega, curve_ptr, n_modes=128, n_hist=4, base_order=3, width=256, seed=0):
         L = load()
         self.n_nodes = int(theta.numel())
         self.n_curves = len(curve_ptr) - 1
@@ -408,7 +408,8 @@ class WarmStart:
         self.device = theta.device
         h = ctypes.c_void_p()
         _check(L.mhlp_warm_create(_dev(theta, "theta"), _dev(omega, "omega", self.n_nodes), cp, self.n_curves,
-                                  int(n_modes), self.n_hist, int(width), int(seed), _stream(), ctypes.byref(h)),
+                                  int(n_modes), self.n_hist, int(base_order), int(width), int(seed), _stream(),
+                                  ctypes.byref(h)),
                "warm_create")
         self._h = h
         nf, net = ctypes.c_int64(), ctypes.c_void_p()
@@ -417,9 +418,10 @@ class WarmStart:
         self.mlp = MLP(0, 0, 0, handle=net, device=self.device)
 
     def scales(self):
-        sc = (ctypes.c_double * 2)()
+        """(input group factors [n_hist], output unit)."""
+        sc = (ctypes.c_double * (self.n_hist + 1))()
         _check(load().mhlp_warm_info(self._h, None, None, None, sc), "warm_info")
-        return sc[0], sc[1]
+        return list(sc)[:self.n_hist], sc[self.n_hist]
 
     def coefficients(self, mu):
         mu2 = mu.reshape(-1, self.n_nodes)

@@ -88,8 +88,13 @@ def test_adam_step_vs_oracle(M):
     p1 = net.get_params().cpu().numpy().astype(np.float64)
     _, gr = wo.mlp_loss_grad(p, sizes, X.astype(np.float64), T.astype(np.float64), round_weights=True)
     ref, _, _ = wo.adam_step(p.astype(np.float64), gr, np.zeros_like(gr), np.zeros_like(gr), 1)
-    big = np.abs(gr) > 1e-2 * np.max(np.abs(gr))  # sign of tiny gradients may flip under BF16 products
-    assert big.sum() > 0.5 * big.size
+    # the first Adam step moves each weight by lr * sign(gradient); the sign of a
+    # gradient far below its tensor's RMS may flip under BF16 products
+    big = np.zeros(gr.size, dtype=bool)
+    for sw, sb in wo.layer_slices(sizes):
+        for sl in (sw, sb):
+            big[sl] = np.abs(gr[sl]) > 0.2 * np.sqrt(np.mean(gr[sl] ** 2))
+    assert big.sum() > 0.7 * big.size
     assert np.max(np.abs(p1 - ref)[big]) < 1e-6
 
 
@@ -99,9 +104,9 @@ def geo5():
     return geom
 
 
-def _warm(M, geom, seed=0, n_modes=128, n_hist=4, width=256):
+def _warm(M, geom, seed=0, n_modes=128, n_hist=4, base_order=3, width=256):
     return M.WarmStart(_t(geom.theta, torch.float64), _t(geom.theta_w, torch.float64), geom.curve_node_ptr,
-                       n_modes=n_modes, n_hist=n_hist, width=width, seed=seed)
+                       n_modes=n_modes, n_hist=n_hist, base_order=base_order, width=width, seed=seed)
 
 
 def test_fourier_analysis_synthesis_vs_oracle(M, geo5):
@@ -119,36 +124,40 @@ def test_fourier_analysis_synthesis_vs_oracle(M, geo5):
     assert np.max(np.abs(s - sr)) < 1e-12 * np.max(np.abs(sr))
 
 
-def test_warm_predict_vs_oracle(M, geo5):
+@pytest.mark.parametrize("n_hist,order", [(4, 0), (4, 2), (3, 1), (4, 3)])
+def test_warm_predict_vs_oracle(M, geo5, n_hist, order):
     """Scales and prediction with host-set weights on a seeded synthetic series."""
     geom = geo5
-    W = _warm(M, geom, n_modes=32, n_hist=4, width=64)
-    rng = np.random.default_rng(33)
+    W = _warm(M, geom, n_modes=32, n_hist=n_hist, base_order=order, width=64)
+    rng = np.random.default_rng(33 + order)
     series = np.cumsum(rng.standard_normal((9, geom.n_nodes)) * 0.1, axis=0) + rng.standard_normal(geom.n_nodes)
     W.train(_t(series, torch.float64), iters=0)
     sizes = W.mlp.sizes
     p, _, _ = _mlp_case(sizes, 1, seed=44)
     W.mlp.set_params(_t(p))
     coef_r = wo.fourier_coefficients(geom.theta, geom.theta_w, geom.curve_node_ptr, series, 32)
-    sx, sy = wo.warm_scales(coef_r, 4)
+    sx, sy = wo.warm_scales(coef_r, n_hist, order)
     gsx, gsy = W.scales()
-    assert abs(gsx / sx - 1) < 1e-12 and abs(gsy / sy - 1) < 1e-12
-    hist = series[-4:]
+    assert np.max(np.abs(np.array(gsx) / np.array(sx) - 1)) < 1e-12 and abs(gsy / sy - 1) < 1e-12
+    hist = series[-n_hist:]
     x0 = W.predict(_t(hist, torch.float64)).cpu().numpy()
-    Xr = (coef_r[-4:].ravel() * sx)[None, :]
-    Yr = wo.mlp_forward(p, sizes, Xr, round_weights=True)[0] * sy
-    inc = wo.fourier_synthesis(geom.theta, geom.curve_node_ptr, Yr, 32)[0]
-    assert _rel(x0 - hist[-1], inc) < 1e-2
+    Yr = wo.mlp_forward(p, sizes, wo.warm_input(coef_r[-n_hist:], (sx, sy)), round_weights=True)[0] * sy
+    corr = wo.fourier_synthesis(geom.theta, geom.curve_node_ptr, Yr, 32)[0]
+    b = wo.extrapolation_coeffs(order)
+    base = sum(b[i] * hist[-1 - i] for i in range(order + 1))
+    assert _rel(x0 - base, corr) < 1e-2
 
 
 def test_warm_requires_training_and_validates(M, geo5):
-    W = _warm(M, geo5, n_modes=8, n_hist=2, width=16)
+    W = _warm(M, geo5, n_modes=8, n_hist=2, base_order=1, width=16)
     with pytest.raises(M.MhlpError):
         W.predict(torch.zeros(2 * geo5.n_nodes, dtype=torch.float64, device=DEV))
     with pytest.raises(M.MhlpError):
         W.train(torch.zeros(2, geo5.n_nodes, dtype=torch.float64, device=DEV), iters=1)  # needs n_hist + 1 steps
     with pytest.raises(M.MhlpError):
         M.WarmStart(_t(geo5.theta, torch.float64), _t(geo5.theta_w, torch.float64), [0, 100, 50, geo5.n_nodes])
+    with pytest.raises(M.MhlpError):  # extrapolation order needs order + 1 history rows
+        _warm(M, geo5, n_modes=8, n_hist=2, base_order=2, width=16)
 
 
 @pytest.fixture(scope="module")

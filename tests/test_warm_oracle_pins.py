@@ -128,13 +128,51 @@ def test_fourier_band_limited_exact():
     assert np.max(np.abs(back - mu)) < 1e-11 * np.max(np.abs(mu))
 
 
+def test_extrapolation_exact_on_polynomials():
+    # a degree-p polynomial sampled at s-p..s is continued exactly to s+1
+    for p in range(4):
+        b = wo.extrapolation_coeffs(p)
+        assert abs(b.sum() - 1.0) < 1e-15
+        for deg in range(p + 1):
+            for s0 in (0.0, 3.0, -7.5):
+                xs = [(s0 - i) ** deg for i in range(p + 1)]
+                assert abs(sum(bi * x for bi, x in zip(b, xs)) - (s0 + 1) ** deg) < 1e-9 * max(1.0, abs(s0 + 1) ** deg)
+    # and not beyond: the error on t^(p+1) is (p+1)! (one step of size 1)
+    for p in range(4):
+        b = wo.extrapolation_coeffs(p)
+        err = (1.0) ** (p + 1) - sum(b[i] * (-float(i)) ** (p + 1) for i in range(p + 1))
+        assert abs(err - math.factorial(p + 1)) < 1e-9
+
+
+def test_warm_features_backward_differences_and_targets():
+    # rows x_r = r^k (every feature): the h-th backward difference of r^h is h!,
+    # and vanishes for h > k
+    rows = np.arange(10, dtype=np.float64)
+    for k in range(4):
+        coef = np.repeat((rows ** k)[:, None], 3, axis=1)
+        grp, tgt = wo.warm_features(coef, 4, 3)
+        assert grp.shape == (6, 4, 3) and tgt.shape == (6, 3)
+        assert np.allclose(grp[:, k], math.factorial(k))
+        for h in range(k + 1, 4):
+            assert np.allclose(grp[:, h], 0.0)
+        assert np.allclose(tgt, 0.0)  # cubic extrapolation is exact for k <= 3
+        assert np.allclose(grp[:, 0], coef[3:9])
+    coef = np.repeat((rows ** 2)[:, None], 2, axis=1)
+    _, tgt = wo.warm_features(coef, 3, 1)
+    assert np.allclose(tgt, 2.0)  # linear extrapolation misses r^2 by 2
+
+
 def test_warm_samples_shapes_and_scales():
     rng = np.random.default_rng(2)
     coef = rng.standard_normal((10, 6))
-    sx, sy = wo.warm_scales(coef, 4)
-    X, T = wo.warm_samples(coef, 4, (sx, sy))
+    sx, sy = wo.warm_scales(coef, 4, 2)
+    X, T = wo.warm_samples(coef, 4, 2, (sx, sy))
     assert X.shape == (6, 24) and T.shape == (6, 6)
-    assert np.allclose(X[2], coef[2:6].ravel() * sx)
-    assert np.allclose(T[5] * sy, coef[9] - coef[8])
-    assert abs(sx * math.sqrt(np.mean(coef[:9] ** 2)) - 1.0) < 1e-12  # inputs use rows 0..8
+    for h in range(4):
+        assert abs(np.sqrt(np.mean(X.reshape(6, 4, 6)[:, h] ** 2)) - 1.0) < 1e-12
+    assert np.allclose(X.reshape(6, 4, 6)[2, 0], coef[5] * sx[0])
+    assert np.allclose(X.reshape(6, 4, 6)[2, 1], (coef[5] - coef[4]) * sx[1])
+    assert np.allclose(T[5] * sy, coef[9] - (3 * coef[8] - 3 * coef[7] + coef[6]))
     assert abs(np.sqrt(np.mean(T ** 2)) - 1.0) < 1e-12
+    Xi = wo.warm_input(coef[2:6], (sx, sy))
+    assert np.allclose(Xi, X[2:3])
