@@ -382,7 +382,7 @@ __global__ __launch_bounds__(FT_THREADS) void far_eval_fp64(FarArgs A)
         while (k < kend && A.npan[k] >= 0 && A.npan[k] < pb) ++k;
     }
     int32_t nxt = (k < kend) ? A.npan[k] : INT_MAX;
-    const double alpha = A.alpha, a2q = 0.25 * alpha * alpha, a4 = 4.0 / alpha, ia = 1.0 / alpha;
+    const FarConst fc = far_const(A.alpha);
     double accs = 0.0, accd = 0.0;
     for (int64_t base = 16 * pb; base < 16 * pe; base += FT_SRC) {
         __syncthreads();
@@ -407,14 +407,18 @@ __global__ __launch_bounds__(FT_THREADS) void far_eval_fp64(FarArgs A)
                 nxt = (k < kend) ? A.npan[k] : INT_MAX;
                 continue;
             }
-#pragma unroll 2
-            for (int s = 0; s < 16; ++s) {
-                const int l = pl * 16 + s;
-                const double ex = x - lx[l], ey = y - ly[l];
-                const double r2 = fma(ex, ex, ey * ey);
-                const K01 o = k01_far_fp64<SLP, DLP>(r2, alpha, a2q, a4, ia);
-                if (SLP) accs = fma(o.k0, lq[l], accs);
-                if (DLP) accd = fma(o.ak1r, fma(ex, ldx[l], ey * ldy[l]), accd);
+#pragma unroll 1
+            for (int s = 0; s < 16; s += 2) {
+                const FarTab T = far_table();
+                const int l0 = pl * 16 + s, l1 = l0 + 1;
+                const double ex0 = x - lx[l0], ey0 = y - ly[l0];
+                const double ex1 = x - lx[l1], ey1 = y - ly[l1];
+                K01 o0, o1;
+                k01_far2<SLP, DLP>(T, fc, fma(ex0, ex0, ey0 * ey0), fma(ex1, ex1, ey1 * ey1), o0, o1);
+                if (SLP) accs = fma(o1.k0, lq[l1], fma(o0.k0, lq[l0], accs));
+                if (DLP)
+                    accd = fma(o1.ak1r, fma(ex1, ldx[l1], ey1 * ldy[l1]),
+                               fma(o0.ak1r, fma(ex0, ldx[l0], ey0 * ldy[l0]), accd));
             }
         }
     }
@@ -522,8 +526,8 @@ __global__ __launch_bounds__(FT_THREADS) void volume_kernel(VolArgs A)
     const double x = valid ? A.x[i] : 0.0, y = valid ? A.y[i] : 0.0;
     const int64_t jb = SPLIT ? (int64_t)blockIdx.y * A.per_split : 0;
     const int64_t je = SPLIT ? min(A.n, jb + A.per_split) : A.n;
-    const double alpha = A.alpha, a2q = 0.25 * alpha * alpha, a4 = 4.0 / alpha, ia = 1.0 / alpha;
-    const float af = (float)alpha, a2qf = 0.25f * af * af, a4f = 4.0f / af;
+    const FarConst fc = far_const(A.alpha);
+    const float af = (float)A.alpha, a2qf = 0.25f * af * af, a4f = 4.0f / af;
     double acc = 0.0;
     for (int64_t base = jb; base < je; base += FT_SRC) {
         __syncthreads();
@@ -555,14 +559,19 @@ __global__ __launch_bounds__(FT_THREADS) void volume_kernel(VolArgs A)
             }
             acc += (double)ps;
         } else {
-#pragma unroll 2
-            for (int l = 0; l < cnt; ++l) {
-                const double ex = x - lx[l], ey = y - ly[l];
-                double r2 = fma(ex, ex, ey * ey);
-                const bool self = r2 == 0.0;
-                r2 = self ? 1.0 : r2;
-                const K01 o = k01_far_fp64<true, false>(r2, alpha, a2q, a4, ia);
-                acc = fma(self ? 0.0 : o.k0, lq[l], acc);
+            /* pairs of sources; an odd count reads one zero-padded slot (lq = 0) */
+#pragma unroll 1
+            for (int l = 0; l < cnt; l += 2) {
+                const FarTab T = far_table();
+                const double ex0 = x - lx[l], ey0 = y - ly[l];
+                const double ex1 = x - lx[l + 1], ey1 = y - ly[l + 1];
+                double r20 = fma(ex0, ex0, ey0 * ey0), r21 = fma(ex1, ex1, ey1 * ey1);
+                const bool self0 = r20 == 0.0, self1 = r21 == 0.0;
+                r20 = self0 ? 1.0 : r20;
+                r21 = self1 ? 1.0 : r21;
+                K01 o0, o1;
+                k01_far2<true, false>(T, fc, r20, r21, o0, o1);
+                acc = fma(self1 ? 0.0 : o1.k0, lq[l + 1], fma(self0 ? 0.0 : o0.k0, lq[l], acc));
             }
         }
     }
@@ -1314,7 +1323,7 @@ __global__ __launch_bounds__(FT_THREADS) void batch_far_dlp(const BatchGeo *__re
         while (k < kend && geo.npan[k] >= 0 && geo.npan[k] < pb) ++k;
     }
     int32_t nxt = (k < kend) ? geo.npan[k] : INT_MAX;
-    const double alpha = geo.alpha, a2q = 0.25 * alpha * alpha, a4 = 4.0 / alpha, ia = 1.0 / alpha;
+    const FarConst fc = far_const(geo.alpha);
     const double *mug = mu + geo.voff;
     double acc[R];
 #pragma unroll
@@ -1343,13 +1352,18 @@ __global__ __launch_bounds__(FT_THREADS) void batch_far_dlp(const BatchGeo *__re
                 nxt = (k < kend) ? geo.npan[k] : INT_MAX;
                 continue;
             }
-            for (int s = 0; s < 16; ++s) {
-                const int l = pl * 16 + s;
-                const double ex = x - lx[l], ey = y - ly[l];
-                const double r2 = fma(ex, ex, ey * ey);
-                const K01 o = k01_far_fp64<false, true>(r2, alpha, a2q, a4, ia);
+#pragma unroll 1
+            for (int s = 0; s < 16; s += 2) {
+                const FarTab T = far_table();
+                const int l0 = pl * 16 + s, l1 = l0 + 1;
+                const double ex0 = x - lx[l0], ey0 = y - ly[l0];
+                const double ex1 = x - lx[l1], ey1 = y - ly[l1];
+                K01 o0, o1;
+                k01_far2<false, true>(T, fc, fma(ex0, ex0, ey0 * ey0), fma(ex1, ex1, ey1 * ey1), o0, o1);
 #pragma unroll
-                for (int r = 0; r < R; ++r) acc[r] = fma(o.ak1r, fma(ex, ldx[r][l], ey * ldy[r][l]), acc[r]);
+                for (int r = 0; r < R; ++r)
+                    acc[r] = fma(o1.ak1r, fma(ex1, ldx[r][l1], ey1 * ldy[r][l1]),
+                                 fma(o0.ak1r, fma(ex0, ldx[r][l0], ey0 * ldy[r][l0]), acc[r]));
             }
         }
     }

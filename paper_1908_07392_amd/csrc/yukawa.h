@@ -95,36 +95,60 @@ static constexpr double EXP_T[14] = {1.0, 1.0, 0.5, 1.0 / 6.0, 1.0 / 24.0, 1.0 /
 static constexpr double ATANH_T[11] = {1.0, 1.0 / 3.0, 1.0 / 5.0, 1.0 / 7.0, 1.0 / 9.0, 1.0 / 11.0,
                                        1.0 / 13.0, 1.0 / 15.0, 1.0 / 17.0, 1.0 / 19.0, 1.0 / 21.0};
 
-/* Three-operand FP64 FMA.  Written as a one-instruction arithmetic asm so the
-   polynomial steps below stay single v_fma_f64 instructions with the
-   coefficient as addend, instead of a register copy plus the two-address
-   v_fmac_f64 form. */
-__device__ __forceinline__ double fma3(double a, double b, double c)
+/* Coefficient tables of the far-field kernel values, in the constant
+   address space.  The tile kernels fetch the table pointer through
+   far_table() once per pair of sources: the empty asm makes the pointer
+   opaque, so the compiler cannot hoist the (scalar) loads of the
+   coefficients out of the source loop into vector registers.  Each
+   coefficient then reaches its v_fma_f64 as a scalar-register operand, and
+   the vector register file holds only per-lane state (about 110 instead of
+   about 200 registers in the fused kernel: 4 instead of 2 waves per SIMD). */
+#define MHLP_CAS __attribute__((address_space(4)))
+struct FarTable {
+    double kl0[23], kl1[23], expt[14], atanh[11], ks_i0[12], ks_r0[13], ks_i1z[12], ks_r1[13];
+};
+
+constexpr FarTable make_far_table()
 {
-    double r;
-    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
-    return r;
+    FarTable t{};
+    for (int i = 0; i < 23; ++i) t.kl0[i] = KL0[i], t.kl1[i] = KL1[i];
+    for (int i = 0; i < 14; ++i) t.expt[i] = EXP_T[i];
+    for (int i = 0; i < 11; ++i) t.atanh[i] = ATANH_T[i];
+    for (int i = 0; i < 12; ++i) t.ks_i0[i] = KS_I0[i], t.ks_i1z[i] = KS_I1Z[i];
+    for (int i = 0; i < 13; ++i) t.ks_r0[i] = KS_R0[i], t.ks_r1[i] = KS_R1[i];
+    return t;
+}
+
+static __constant__ FarTable FAR_TAB = make_far_table();
+
+typedef const MHLP_CAS FarTable *FarTab;
+
+__device__ __forceinline__ FarTab far_table()
+{
+    FarTab T = (FarTab)&FAR_TAB;
+    asm volatile("" : "+s"(T));
+    return T;
 }
 
 template <int N>
-__device__ __forceinline__ double hornerv(const double (&c)[N], double x)
+__device__ __forceinline__ double hornerc(const MHLP_CAS double *c, double x)
 {
     double v = c[N - 1];
 #pragma unroll
-    for (int i = N - 2; i >= 0; --i) v = fma3(v, x, c[i]);
+    for (int i = N - 2; i >= 0; --i) v = fma(v, x, c[i]);
     return v;
 }
 
 /* value and first derivative of the polynomial */
 template <int N>
-__device__ __forceinline__ double hornerd(const double (&c)[N], double x, double &d)
+__device__ __forceinline__ double hornercd(const MHLP_CAS double *c, double x, double &d)
 {
     double v = c[N - 1];
     d = 0.0;
 #pragma unroll
     for (int i = N - 2; i >= 0; --i) {
-        d = fma3(d, x, v);
-        v = fma3(v, x, c[i]);
+        d = fma(d, x, v);
+        v = fma(v, x, c[i]);
     }
     return v;
 }
@@ -145,15 +169,15 @@ __device__ __forceinline__ double lean_rcp(double x)
     return fma(y, e, y);
 }
 
-__device__ __forceinline__ double lean_exp_neg(double z)
+__device__ __forceinline__ double lean_exp_neg(FarTab T, double z)
 {
     const double n = rint(z * LOG2E);
     double r = fma(n, LN2_HI, -z);
     r = fma(n, LN2_LO, r);
-    return ldexp(hornerv(EXP_T, r), -(int)n);
+    return ldexp(hornerc<14>(T->expt, r), -(int)n);
 }
 
-__device__ __forceinline__ double lean_log01(double q)
+__device__ __forceinline__ double lean_log01(FarTab T, double q)
 {
     int e;
     double m = frexp(q, &e);
@@ -161,7 +185,7 @@ __device__ __forceinline__ double lean_log01(double q)
     m = lo ? 2.0 * m : m;
     e -= lo ? 1 : 0;
     const double s = (m - 1.0) * lean_rcp(m + 1.0);
-    const double p = hornerv(ATANH_T, s * s);
+    const double p = hornerc<11>(T->atanh, s * s);
     const double de = (double)e;
     return fma(de, LN2_HI, fma(de, LN2_LO, 2.0 * s * p));
 }
@@ -172,46 +196,76 @@ __device__ __forceinline__ double lean_log01(double q)
              E = e^{-z}/sqrt(z), u = 4/z - 1;
      z <= 2: K1 = I0/z + (z/4) log(q) I0'(q) - (z/2) R0'(q), q = z^2/4,
    which halves the coefficient tables (max rel. error 3e-15 vs 5e-16 for the
-   separate fits; measured against mpmath).  ia = 1/alpha. */
+   separate fits; measured against mpmath).  ia = 1/alpha.
+   k01_far_big evaluates the z > 2 form for any r2 > 0 (finite or inf/nan
+   garbage when z <= 2); k01_far_small is the z <= 2 form.  k01_far2 takes
+   two pairs: both big forms straight-line (independent instruction streams
+   the scheduler interleaves), then the small form only on lanes that need
+   it, selected over the big values. */
 template <bool SLP, bool DLP>
-__device__ __forceinline__ K01 k01_far_fp64(double r2, double a, double a2q, double a4, double ia)
+__device__ __forceinline__ K01 k01_far_big(FarTab T, double r2, double a, double a4, double ia)
+{
+    K01 o{0.0, 0.0};
+    const double ri = lean_rsq(r2);
+    const double z = a * (r2 * ri);
+    const double u = fma(a4, ri, -1.0);
+    const double e = lean_exp_neg(T, z) * lean_rsq(z);
+    if (SLP && DLP) {
+        double dp;
+        const double p = hornercd<23>(T->kl0, u, dp);
+        o.k0 = e * p;
+        const double iz = ia * ri; /* 1/z */
+        const double k1 = e * fma(4.0 * iz * iz, dp, p * fma(0.5, iz, 1.0));
+        o.ak1r = a * k1 * ri;
+    } else if (SLP) {
+        o.k0 = e * hornerc<23>(T->kl0, u);
+    } else {
+        o.ak1r = a * e * hornerc<23>(T->kl1, u) * ri;
+    }
+    return o;
+}
+
+template <bool SLP, bool DLP>
+__device__ __noinline__ K01 k01_far_small(FarTab T, double r2, double a2q)
 {
     K01 o{0.0, 0.0};
     const double q = a2q * r2; /* z^2/4 */
-    if (q <= 1.0) {
-        const double lq = lean_log01(q); /* 2 log(z/2) */
-        if (SLP && DLP) {
-            double di0, dr0;
-            const double i0 = hornerd(KS_I0, q, di0);
-            const double r0 = hornerd(KS_R0, q, dr0);
-            o.k0 = fma(-0.5 * lq, i0, r0);
-            /* alpha^2 K1/z = I0/r^2 + alpha^2 (lq I0'/4 - R0'/2) */
-            o.ak1r = fma(4.0 * a2q, fma(0.25 * lq, di0, -0.5 * dr0), i0 * lean_rcp(r2));
-        } else if (SLP) {
-            o.k0 = fma(-0.5 * lq, hornerv(KS_I0, q), hornerv(KS_R0, q));
-        } else {
-            const double t = fma(0.5 * lq, hornerv(KS_I1Z, q), -0.25 * hornerv(KS_R1, q));
-            o.ak1r = fma(4.0 * a2q, t, lean_rcp(r2));
-        }
+    const double lq = lean_log01(T, q); /* 2 log(z/2) */
+    if (SLP && DLP) {
+        double di0, dr0;
+        const double i0 = hornercd<12>(T->ks_i0, q, di0);
+        const double r0 = hornercd<13>(T->ks_r0, q, dr0);
+        o.k0 = fma(-0.5 * lq, i0, r0);
+        /* alpha^2 K1/z = I0/r^2 + alpha^2 (lq I0'/4 - R0'/2) */
+        o.ak1r = fma(4.0 * a2q, fma(0.25 * lq, di0, -0.5 * dr0), i0 * lean_rcp(r2));
+    } else if (SLP) {
+        o.k0 = fma(-0.5 * lq, hornerc<12>(T->ks_i0, q), hornerc<13>(T->ks_r0, q));
     } else {
-        const double ri = lean_rsq(r2);
-        const double z = a * (r2 * ri);
-        const double u = fma(a4, ri, -1.0);
-        const double e = lean_exp_neg(z) * lean_rsq(z);
-        if (SLP && DLP) {
-            double dp;
-            const double p = hornerd(KL0, u, dp);
-            o.k0 = e * p;
-            const double iz = ia * ri; /* 1/z */
-            const double k1 = e * fma(4.0 * iz * iz, dp, p * fma(0.5, iz, 1.0));
-            o.ak1r = a * k1 * ri;
-        } else if (SLP) {
-            o.k0 = e * hornerv(KL0, u);
-        } else {
-            o.ak1r = a * e * hornerv(KL1, u) * ri;
-        }
+        const double t = fma(0.5 * lq, hornerc<12>(T->ks_i1z, q), -0.25 * hornerc<13>(T->ks_r1, q));
+        o.ak1r = fma(4.0 * a2q, t, lean_rcp(r2));
     }
     return o;
+}
+
+struct FarConst {
+    double a, a2q, a4, ia; /* alpha, alpha^2/4, 4/alpha, 1/alpha */
+};
+
+__device__ __forceinline__ FarConst far_const(double alpha)
+{
+    return FarConst{alpha, 0.25 * alpha * alpha, 4.0 / alpha, 1.0 / alpha};
+}
+
+template <bool SLP, bool DLP>
+__device__ __forceinline__ void k01_far2(FarTab T, const FarConst &c, double r2a, double r2b, K01 &oa, K01 &ob)
+{
+    oa = k01_far_big<SLP, DLP>(T, r2a, c.a, c.a4, c.ia);
+    ob = k01_far_big<SLP, DLP>(T, r2b, c.a, c.a4, c.ia);
+    const bool sa = c.a2q * r2a <= 1.0, sb = c.a2q * r2b <= 1.0;
+    if (sa || sb) {
+        if (sa) oa = k01_far_small<SLP, DLP>(T, r2a, c.a2q);
+        if (sb) ob = k01_far_small<SLP, DLP>(T, r2b, c.a2q);
+    }
 }
 
 /* ---------------------------------------------------------------------- */
