@@ -200,8 +200,8 @@ __device__ __forceinline__ double lean_log01(FarTab T, double q)
    k01_far_big evaluates the z > 2 form for any r2 > 0 (finite or inf/nan
    garbage when z <= 2); k01_far_small is the z <= 2 form.  k01_far2 takes
    two pairs: both big forms straight-line (independent instruction streams
-   the scheduler interleaves), then the small form only on lanes that need
-   it, selected over the big values. */
+   the scheduler interleaves) on lanes where either pair needs it, then the
+   small form on lanes that need it, overwriting the big values. */
 template <bool SLP, bool DLP>
 __device__ __forceinline__ K01 k01_far_big(FarTab T, double r2, double a, double a4, double ia)
 {
@@ -226,7 +226,7 @@ __device__ __forceinline__ K01 k01_far_big(FarTab T, double r2, double a, double
 }
 
 template <bool SLP, bool DLP>
-__device__ __noinline__ K01 k01_far_small(FarTab T, double r2, double a2q)
+__device__ __forceinline__ K01 k01_far_small(FarTab T, double r2, double a2q)
 {
     K01 o{0.0, 0.0};
     const double q = a2q * r2; /* z^2/4 */
@@ -259,9 +259,11 @@ __device__ __forceinline__ FarConst far_const(double alpha)
 template <bool SLP, bool DLP>
 __device__ __forceinline__ void k01_far2(FarTab T, const FarConst &c, double r2a, double r2b, K01 &oa, K01 &ob)
 {
-    oa = k01_far_big<SLP, DLP>(T, r2a, c.a, c.a4, c.ia);
-    ob = k01_far_big<SLP, DLP>(T, r2b, c.a, c.a4, c.ia);
     const bool sa = c.a2q * r2a <= 1.0, sb = c.a2q * r2b <= 1.0;
+    if (!(sa && sb)) {
+        oa = k01_far_big<SLP, DLP>(T, r2a, c.a, c.a4, c.ia);
+        ob = k01_far_big<SLP, DLP>(T, r2b, c.a, c.a4, c.ia);
+    }
     if (sa || sb) {
         if (sa) oa = k01_far_small<SLP, DLP>(T, r2a, c.a2q);
         if (sb) ob = k01_far_small<SLP, DLP>(T, r2b, c.a2q);
