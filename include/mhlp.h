@@ -109,6 +109,23 @@ mhlp_status mhlp_plan_destroy(mhlp_plan *plan);
 mhlp_status mhlp_plan_info(const mhlp_plan *plan, int64_t *n_targets, int64_t *n_sources, int64_t *n_near_pairs,
                            double *alpha);
 
+/* Far-field launch shape.  The direct sum over sources can be split into
+   nsplit ranges of panels evaluated by separate blocks (partial sums added
+   in fixed order, so results do not depend on nsplit beyond rounding); the
+   default gives about 1024 blocks.  set_split may reallocate the plan's
+   partial-sum buffer (it synchronises the device then).
+   mhlp_plan_autotune times the far evaluation (layers: 1 SLP, 2 DLP, 3 both,
+   4 the on-surface BIE operator) for nsplit = 1, 2, 4, ... (up to Np/4 and
+   256) plus the current value, reps timed launches each after one warm-up,
+   with HIP events on `stream`, keeps the fastest and reports it (host
+   outputs; cand/cand_ms receive up to cap candidates and their ms per launch).
+   Synchronises the stream.  Errors: MHLP_INVALID_ARG. */
+mhlp_status mhlp_plan_set_split(mhlp_plan *plan, int32_t nsplit);
+mhlp_status mhlp_plan_get_split(const mhlp_plan *plan, int32_t *nsplit);
+mhlp_status mhlp_plan_autotune(mhlp_plan *plan, int32_t layers, int32_t precision, int32_t reps, void *stream,
+                               int32_t *best_nsplit, double *best_ms, int32_t *cand, double *cand_ms, int32_t cap,
+                               int32_t *n_cand);
+
 /* S[sigma] and/or D[mu] at the plan's targets (sigma, mu: device [N];
    u_slp, u_dlp: device [M], overwritten).  Either density/output pair may be
    NULL (then that potential is skipped), not both.  On an on-surface plan,
@@ -128,6 +145,10 @@ mhlp_status mhlp_apply_bie_operator(const mhlp_plan *onsurf, const double *mu, d
    with reorthogonalisation in FP64, judged by the true FP64 residual.  g, mu:
    device [N].  With opts->use_x0, mu holds the initial guess; a guess whose
    true relative residual is >= 1 is replaced by zero (info->used_x0 = 0).
+   The Arnoldi steps, Givens rotations and the stopping test run on the
+   device; chunks of steps are replayed from HIP graphs captured on a private
+   stream of the plan (the host reads the state once per chunk).  The plan's
+   GMRES state is shared: concurrent solves on one plan are not allowed.
    opts, info: host.  Synchronises the stream.  Returns MHLP_NOT_CONVERGED
    (mu = last iterate, info filled) if max_iter is reached. */
 mhlp_status mhlp_gmres_solve(const mhlp_plan *onsurf, const double *g, double *mu, const mhlp_gmres_opts *opts,

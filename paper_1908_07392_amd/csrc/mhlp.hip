@@ -27,6 +27,7 @@
 
 #include <climits>
 #include <cmath>
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -75,6 +76,18 @@ struct mhlp_geometry {
     double *ph = nullptr, *pcx = nullptr, *pcy = nullptr, *prad = nullptr;
 };
 
+/* Device state of one GMRES cycle (see the GMRES section). */
+struct GState {
+    int32_t j;     /* current Arnoldi column                               */
+    int32_t kmax;  /* columns allowed in this cycle                        */
+    int32_t done;  /* converged, broken down or kmax reached               */
+    int32_t steps; /* Arnoldi steps taken in this cycle                    */
+    double thresh; /* stop when the residual estimate |g_{j+1}| <= thresh  */
+    double inv;    /* 1 / h_{j+1,j}: scaling of the next basis vector      */
+    double resest; /* |g_{j+1}| after the last step                        */
+    double pad;
+};
+
 struct mhlp_plan {
     const mhlp_geometry *g = nullptr;
     double alpha = 0.0;
@@ -93,11 +106,22 @@ struct mhlp_plan {
     double *part = nullptr;   /* [2][nsplit][M] partial sums                */
     NearParams np{};
     double near_factor = 1.2;
+    int64_t part_cap = 0;     /* capacity of part (doubles)                 */
     /* GMRES workspace (lazily allocated) */
     double *ws = nullptr;
     int64_t ws_cols = 0;
     double *hdev = nullptr;  /* small device scratch for dot products */
     double *hhost = nullptr; /* pinned host mirror                    */
+    /* device-driven GMRES: state + Hessenberg data, captured step graphs */
+    char *gdev = nullptr;       /* GState, H, cs, sn, gv, y, h1, h2, hn   */
+    int gdev_R = 0;
+    GState *gstate_host = nullptr; /* pinned mirror of the state          */
+    hipStream_t cap_stream = nullptr;
+    struct StepGraph {
+        hipGraphExec_t exec = nullptr;
+        const void *ws = nullptr, *part = nullptr, *gdev = nullptr;
+        int R = 0, nsplit = 0, S = 0;
+    } graphs[2][4]; /* [precision][chunk length 1, 2, 4, 8] */
 };
 
 /* ------------------------------------------------------------------------ */
@@ -327,11 +351,29 @@ struct FarArgs {
     int64_t Np;
     int32_t pps;      /* panels per source split (blockIdx.y) */
     double *part_s, *part_d; /* [nsplit][M] partial far sums when split */
+    /* device-driven GMRES: when gs is set the density is column gs->j of the
+       basis (mu + j*jstride) and the launch does nothing once gs->done */
+    const GState *gs;
+    int64_t jstride;
 };
+
+
+/* density of a far launch: fixed, or the current GMRES basis column;
+   false when the launch is a no-op */
+__device__ __forceinline__ bool far_density(const FarArgs &A, const double *&mu)
+{
+    mu = A.mu;
+    if (A.gs) {
+        if (A.gs->done) return false;
+        mu += (int64_t)A.gs->j * A.jstride;
+    }
+    return true;
+}
 
 /* Near corrections, 1/(2 pi) scaling and identity term for target i. */
 template <bool SLP, bool DLP>
-__device__ __forceinline__ void far_epilogue(const FarArgs &A, int64_t i, double accs, double accd)
+__device__ __forceinline__ void far_epilogue(const FarArgs &A, const double *__restrict__ mu, int64_t i, double accs,
+                                             double accd)
 {
     double cs = 0.0, cd = 0.0;
     for (int32_t q = A.nptr[i]; q < A.nptr[i + 1]; ++q) {
@@ -339,14 +381,14 @@ __device__ __forceinline__ void far_epilogue(const FarArgs &A, int64_t i, double
         if (p < 0) continue;
         for (int jj = 0; jj < 16; ++jj) {
             if (SLP) cs = fma(A.wsl[16 * (int64_t)q + jj], A.sigma[16 * p + jj], cs);
-            if (DLP) cd = fma(A.wdl[16 * (int64_t)q + jj], A.mu[16 * p + jj], cd);
+            if (DLP) cd = fma(A.wdl[16 * (int64_t)q + jj], mu[16 * p + jj], cd);
         }
     }
     if (SLP) A.us[i] = fma(INV_2PI, accs, cs);
     if (DLP) {
         double v = fma(INV_2PI, accd, cd);
         /* identity term: only on-surface plans (targets are the nodes, M == N) */
-        if (A.half_term != 0.0) v = fma(A.half_term, A.mu[i], v);
+        if (A.half_term != 0.0) v = fma(A.half_term, mu[i], v);
         A.ud[i] = v;
     }
 }
@@ -356,19 +398,22 @@ template <bool SLP, bool DLP>
 __global__ void far_finalize(FarArgs A, int nsplit)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= A.M) return;
+    const double *mu;
+    if (i >= A.M || !far_density(A, mu)) return;
     double s_ = 0.0, d_ = 0.0;
     for (int k = 0; k < nsplit; ++k) {
         if (SLP) s_ += A.part_s[k * A.M + i];
         if (DLP) d_ += A.part_d[k * A.M + i];
     }
-    far_epilogue<SLP, DLP>(A, i, s_, d_);
+    far_epilogue<SLP, DLP>(A, mu, i, s_, d_);
 }
 
 template <bool SLP, bool DLP, bool SPLIT>
 __global__ __launch_bounds__(FT_THREADS) void far_eval_fp64(FarArgs A)
 {
     __shared__ double lx[FT_SRC], ly[FT_SRC], lq[FT_SRC], ldx[FT_SRC], ldy[FT_SRC];
+    const double *mu;
+    if (!far_density(A, mu)) return;
     const int64_t i = blockIdx.x * (int64_t)FT_THREADS + threadIdx.x;
     const bool valid = i < A.M;
     const double x = valid ? A.tx[i] : 0.0, y = valid ? A.ty[i] : 0.0;
@@ -393,7 +438,7 @@ __global__ __launch_bounds__(FT_THREADS) void far_eval_fp64(FarArgs A)
             ly[threadIdx.x] = A.sy[j];
             if (SLP) lq[threadIdx.x] = wj * A.sigma[j];
             if (DLP) {
-                const double m = wj * A.mu[j];
+                const double m = wj * mu[j];
                 ldx[threadIdx.x] = m * A.snx[j];
                 ldy[threadIdx.x] = m * A.sny[j];
             }
@@ -427,7 +472,7 @@ __global__ __launch_bounds__(FT_THREADS) void far_eval_fp64(FarArgs A)
         if (SLP) A.part_s[blockIdx.y * A.M + i] = accs;
         if (DLP) A.part_d[blockIdx.y * A.M + i] = accd;
     } else {
-        far_epilogue<SLP, DLP>(A, i, accs, accd);
+        far_epilogue<SLP, DLP>(A, mu, i, accs, accd);
     }
 }
 
@@ -441,6 +486,8 @@ __global__ __launch_bounds__(FT_THREADS) void far_eval_mixed(FarArgs A)
 {
     __shared__ double lx[FT_SRC], ly[FT_SRC];
     __shared__ float lq[FT_SRC], ldx[FT_SRC], ldy[FT_SRC];
+    const double *mu;
+    if (!far_density(A, mu)) return;
     const int64_t i = blockIdx.x * (int64_t)FT_THREADS + threadIdx.x;
     const bool valid = i < A.M;
     const double x = valid ? A.tx[i] : 0.0, y = valid ? A.ty[i] : 0.0;
@@ -464,7 +511,7 @@ __global__ __launch_bounds__(FT_THREADS) void far_eval_mixed(FarArgs A)
             ly[threadIdx.x] = A.sy[j];
             if (SLP) lq[threadIdx.x] = (float)(wj * A.sigma[j]);
             if (DLP) {
-                const double m = wj * A.mu[j];
+                const double m = wj * mu[j];
                 ldx[threadIdx.x] = (float)(m * A.snx[j]);
                 ldy[threadIdx.x] = (float)(m * A.sny[j]);
             }
@@ -497,7 +544,7 @@ __global__ __launch_bounds__(FT_THREADS) void far_eval_mixed(FarArgs A)
         if (SLP) A.part_s[blockIdx.y * A.M + i] = accs;
         if (DLP) A.part_d[blockIdx.y * A.M + i] = accd;
     } else {
-        far_epilogue<SLP, DLP>(A, i, accs, accd);
+        far_epilogue<SLP, DLP>(A, mu, i, accs, accd);
     }
 }
 
@@ -672,6 +719,146 @@ __global__ void residual_kernel(const double *__restrict__ g, const double *__re
     if (i < N) r[i] = g[i] - a[i];
 }
 
+/* ---- device-driven GMRES steps (every kernel does nothing once done) ---- */
+/* h[c] = V_c . w for c <= j; one block per column, blocks beyond j exit */
+__global__ __launch_bounds__(256) void gs_dot_kernel(const GState *__restrict__ gs, const double *__restrict__ V,
+                                                     int64_t ld, const double *__restrict__ w, int64_t N,
+                                                     double *__restrict__ h)
+{
+    if (gs->done || (int)blockIdx.x > gs->j) return;
+    __shared__ double red[256];
+    const double *v = V + (int64_t)blockIdx.x * ld;
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < N; i += 256) s = fma(v[i], w[i], s);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) h[blockIdx.x] = red[0];
+}
+
+/* w -= sum_{c<=j} h[c] V_c */
+__global__ void gs_sub_kernel(const GState *__restrict__ gs, const double *__restrict__ V, int64_t ld,
+                              const double *__restrict__ h, double *__restrict__ w, int64_t N)
+{
+    if (gs->done) return;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int ncol = gs->j + 1;
+    double v = w[i];
+    for (int c = 0; c < ncol; ++c) v = fma(-h[c], V[c * ld + i], v);
+    w[i] = v;
+}
+
+/* hn = w . w (one block) */
+__global__ __launch_bounds__(256) void gs_norm_kernel(const GState *__restrict__ gs, const double *__restrict__ w,
+                                                      int64_t N, double *__restrict__ hn)
+{
+    if (gs->done) return;
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < N; i += 256) s = fma(w[i], w[i], s);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) hn[0] = red[0];
+}
+
+/* Column j of the Hessenberg matrix (CGS2 coefficients h1 + h2, subdiagonal
+   ||w||), the earlier Givens rotations applied to it, a new rotation that
+   zeroes the subdiagonal, the rotated right-hand side g and the stopping
+   decision.  H is (R+1) x R row-major.  One thread. */
+__global__ void gs_finish_kernel(GState *__restrict__ gs, double *__restrict__ H, int R, double *__restrict__ cs,
+                                 double *__restrict__ sn, double *__restrict__ gv, const double *__restrict__ h1,
+                                 const double *__restrict__ h2, const double *__restrict__ hn)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0 || gs->done) return;
+    const int k = gs->j;
+    for (int j = 0; j <= k; ++j) H[(int64_t)j * R + k] = h1[j] + h2[j];
+    const double hn1 = sqrt(hn[0]);
+    H[(int64_t)(k + 1) * R + k] = hn1;
+    for (int j = 0; j < k; ++j) {
+        const double a = H[(int64_t)j * R + k], c = H[(int64_t)(j + 1) * R + k];
+        H[(int64_t)j * R + k] = cs[j] * a + sn[j] * c;
+        H[(int64_t)(j + 1) * R + k] = -sn[j] * a + cs[j] * c;
+    }
+    const double a = H[(int64_t)k * R + k], c = H[(int64_t)(k + 1) * R + k];
+    const double den = hypot(a, c);
+    cs[k] = a / den;
+    sn[k] = c / den;
+    H[(int64_t)k * R + k] = den;
+    H[(int64_t)(k + 1) * R + k] = 0.0;
+    gv[k + 1] = -sn[k] * gv[k];
+    gv[k] = cs[k] * gv[k];
+    gs->steps = k + 1;
+    gs->resest = fabs(gv[k + 1]);
+    gs->inv = hn1 > 0.0 ? 1.0 / hn1 : 0.0;
+    if (gs->resest <= gs->thresh || hn1 == 0.0 || k + 1 >= gs->kmax) gs->done = 1;
+}
+
+/* V_{j+1} = w / h_{j+1,j} */
+__global__ void gs_scale_kernel(const GState *__restrict__ gs, const double *__restrict__ w, double *__restrict__ V,
+                                int64_t ld, int64_t N)
+{
+    if (gs->done) return;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < N) V[(int64_t)(gs->j + 1) * ld + i] = gs->inv * w[i];
+}
+
+__global__ void gs_advance_kernel(GState *__restrict__ gs)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0 && !gs->done) gs->j += 1;
+}
+
+/* start of a cycle: state, g = beta e_1 */
+__global__ void gs_init_kernel(GState *__restrict__ gs, double *__restrict__ gv, int R, int kmax, double beta,
+                               double thresh)
+{
+    for (int i = threadIdx.x; i <= R; i += blockDim.x) gv[i] = i == 0 ? beta : 0.0;
+    if (threadIdx.x == 0) {
+        gs->j = 0;
+        gs->kmax = kmax;
+        gs->done = 0;
+        gs->steps = 0;
+        gs->thresh = thresh;
+        gs->inv = 0.0;
+        gs->resest = beta;
+        gs->pad = 0.0;
+    }
+}
+
+/* y = R_k^{-1} g_k for the k = steps leading columns (upper triangular back
+   substitution), one wave: the row sums are split over the 64 lanes */
+__global__ __launch_bounds__(64) void gs_solve_kernel(const GState *__restrict__ gs, const double *__restrict__ H,
+                                                      int R, const double *__restrict__ gv, double *__restrict__ y)
+{
+    const int k = gs->steps;
+    for (int i = k - 1; i >= 0; --i) {
+        double s = 0.0;
+        for (int m = i + 1 + (int)threadIdx.x; m < k; m += 64) s = fma(H[(int64_t)i * R + m], y[m], s);
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        if (threadIdx.x == 0) y[i] = (gv[i] - s) / H[(int64_t)i * R + i];
+        __syncthreads();
+    }
+}
+
+/* x += sum_{c < steps} y[c] V_c */
+__global__ void gs_addcols_kernel(const GState *__restrict__ gs, const double *__restrict__ V, int64_t ld,
+                                  const double *__restrict__ y, double *__restrict__ x, int64_t N)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int k = gs->steps;
+    double v = x[i];
+    for (int c = 0; c < k; ++c) v = fma(y[c], V[c * ld + i], v);
+    x[i] = v;
+}
+
 __global__ void fill_i32_kernel(int32_t *__restrict__ x, int32_t v, int64_t N)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -782,6 +969,31 @@ extern "C" mhlp_status mhlp_geometry_arrays(const mhlp_geometry *g, const double
 /* ------------------------------------------------------------------------ */
 /* plan API                                                                  */
 /* ------------------------------------------------------------------------ */
+/* Source splits of the far field: ns requested splits of the panel range
+   (1 = none); the partial-sum buffer grows as needed. */
+static mhlp_status plan_set_split(mhlp_plan *P, int ns)
+{
+    const int64_t Np = P->g->Np;
+    if (ns < 1) ns = 1;
+    if (ns > Np) ns = (int)Np;
+    const int32_t pps = (int32_t)((Np + ns - 1) / ns);
+    const int nsplit = (int)((Np + pps - 1) / pps);
+    const int64_t need = nsplit > 1 ? 2 * (int64_t)nsplit * P->M : 0;
+    if (need > P->part_cap) {
+        if (P->part) {
+            HIPCHECK(hipDeviceSynchronize()); /* queued launches may still use it */
+            (void)hipFree(P->part);
+            P->part = nullptr;
+            P->part_cap = 0;
+        }
+        TRY(dalloc(&P->part, need));
+        P->part_cap = need;
+    }
+    P->pps = pps;
+    P->nsplit = nsplit;
+    return MHLP_OK;
+}
+
 extern "C" mhlp_status mhlp_plan_destroy(mhlp_plan *P)
 {
     if (!P) return MHLP_OK;
@@ -789,10 +1001,16 @@ extern "C" mhlp_status mhlp_plan_destroy(mhlp_plan *P)
         if (P->tx) (void)hipFree(P->tx);
         if (P->ty) (void)hipFree(P->ty);
     }
-    void *ptrs[] = {P->near_ptr, P->near_panel, P->near_tgt, P->near_ts, P->wslp, P->wdlp, P->ws, P->hdev, P->part};
+    for (auto &gp : P->graphs)
+        for (auto &gr : gp)
+            if (gr.exec) (void)hipGraphExecDestroy(gr.exec);
+    if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
+    void *ptrs[] = {P->near_ptr, P->near_panel, P->near_tgt, P->near_ts, P->wslp, P->wdlp,
+                    P->ws,       P->hdev,       P->part,     P->gdev};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (P->hhost) (void)hipHostFree(P->hhost);
+    if (P->gstate_host) (void)hipHostFree(P->gstate_host);
     delete P;
     return MHLP_OK;
 }
@@ -848,9 +1066,7 @@ extern "C" mhlp_status mhlp_plan_create(const mhlp_geometry *g, double alpha, co
         int64_t ns = (1024 + tblocks - 1) / tblocks;
         if (ns > g->Np / 4) ns = g->Np / 4;
         if (ns < 1) ns = 1;
-        P->pps = (int32_t)((g->Np + ns - 1) / ns);
-        P->nsplit = (int)((g->Np + P->pps - 1) / P->pps);
-        if (P->nsplit > 1 && (s = dalloc(&P->part, 2 * (int64_t)P->nsplit * M))) {
+        if ((s = plan_set_split(P, (int)ns))) {
             mhlp_plan_destroy(P);
             return s;
         }
@@ -959,7 +1175,8 @@ static void launch_far_t(const FarArgs &A, int nsplit, int32_t precision, hipStr
 }
 
 static mhlp_status launch_far(const mhlp_plan *P, const double *sigma, const double *mu, double *us, double *ud,
-                              double half_term, int32_t precision, hipStream_t st)
+                              double half_term, int32_t precision, hipStream_t st, const GState *gs = nullptr,
+                              int64_t jstride = 0)
 {
     if (precision != MHLP_FP64 && precision != MHLP_MIXED) return fail(MHLP_INVALID_ARG, "unknown precision");
     const mhlp_geometry *g = P->g;
@@ -989,6 +1206,8 @@ static mhlp_status launch_far(const mhlp_plan *P, const double *sigma, const dou
     A.pps = P->pps;
     A.part_s = P->part;
     A.part_d = P->part + (int64_t)P->nsplit * P->M;
+    A.gs = gs;
+    A.jstride = jstride;
     if (sigma && mu)
         launch_far_t<true, true>(A, P->nsplit, precision, st);
     else if (sigma)
@@ -1008,6 +1227,94 @@ extern "C" mhlp_status mhlp_eval_layer(const mhlp_plan *P, const double *sigma, 
     if ((sigma && !u_slp) || (u_slp && !sigma) || (mu && !u_dlp) || (u_dlp && !mu))
         return fail(MHLP_INVALID_ARG, "density and output must be given together");
     return launch_far(P, sigma, mu, u_slp, u_dlp, 0.0, precision, (hipStream_t)stream);
+}
+
+/* ------------------------------------------------------------------------ */
+/* far-field launch shape: source splits, and their autotuner               */
+/* ------------------------------------------------------------------------ */
+extern "C" mhlp_status mhlp_plan_set_split(mhlp_plan *P, int32_t nsplit)
+{
+    if (!P) return fail(MHLP_INVALID_ARG, "plan is NULL");
+    if (nsplit < 1) return fail(MHLP_INVALID_ARG, "nsplit must be >= 1");
+    return plan_set_split(P, nsplit);
+}
+
+extern "C" mhlp_status mhlp_plan_get_split(const mhlp_plan *P, int32_t *nsplit)
+{
+    if (!P || !nsplit) return fail(MHLP_INVALID_ARG, "NULL argument");
+    *nsplit = P->nsplit;
+    return MHLP_OK;
+}
+
+extern "C" mhlp_status mhlp_plan_autotune(mhlp_plan *P, int32_t layers, int32_t precision, int32_t reps,
+                                          void *stream, int32_t *best_nsplit, double *best_ms, int32_t *cand,
+                                          double *cand_ms, int32_t cap, int32_t *n_cand)
+{
+    if (!P) return fail(MHLP_INVALID_ARG, "plan is NULL");
+    if (layers < 1 || layers > 4 || layers == 0) return fail(MHLP_INVALID_ARG, "layers must be 1, 2, 3 or 4");
+    if (layers == 4 && !P->onsurf) return fail(MHLP_INVALID_ARG, "layers 4 (BIE operator) needs an on-surface plan");
+    if (precision != MHLP_FP64 && precision != MHLP_MIXED) return fail(MHLP_INVALID_ARG, "unknown precision");
+    if (reps < 1 || reps > 1000) return fail(MHLP_INVALID_ARG, "reps must be in [1, 1000]");
+    if (cap < 0 || (cap > 0 && (!cand || !cand_ms))) return fail(MHLP_INVALID_ARG, "candidate arrays");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t N = P->g->N, M = P->M, Np = P->g->Np;
+    std::vector<int> cs;
+    for (int64_t ns = 1; ns <= std::max<int64_t>(1, Np / 4) && ns <= 256; ns *= 2) cs.push_back((int)ns);
+    if (std::find(cs.begin(), cs.end(), P->nsplit) == cs.end()) cs.push_back(P->nsplit);
+    double *dens = nullptr, *out = nullptr;
+    TRY(dalloc(&dens, N));
+    mhlp_status s = dalloc(&out, 2 * M);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (s == MHLP_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+        s = fail(MHLP_HIP_ERROR, "hipEventCreate");
+    int best = P->nsplit;
+    double bms = 1e300;
+    int nc = 0;
+    if (s == MHLP_OK) fill_kernel<<<nblocks(N, 256), 256, 0, st>>>(dens, 1.0, N);
+    for (size_t c = 0; c < cs.size() && s == MHLP_OK; ++c) {
+        if ((s = plan_set_split(P, cs[c]))) break;
+        auto run = [&]() -> mhlp_status {
+            const double *sg = (layers & 1) ? dens : nullptr, *mu = (layers & 2 || layers == 4) ? dens : nullptr;
+            return launch_far(P, sg, mu, sg ? out : nullptr, mu ? out + M : nullptr, layers == 4 ? 0.5 : 0.0,
+                              precision, st);
+        };
+        if ((s = run())) break;
+        if (hipEventRecord(e0, st) != hipSuccess) {
+            s = fail(MHLP_HIP_ERROR, "hipEventRecord");
+            break;
+        }
+        for (int r = 0; r < reps && s == MHLP_OK; ++r) s = run();
+        if (s) break;
+        float ms = 0.f;
+        hipError_t e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            s = fail(MHLP_HIP_ERROR, std::string("autotune timing: ") + hipGetErrorString(e));
+            break;
+        }
+        const double per = (double)ms / reps;
+        if (nc < cap) {
+            cand[nc] = P->nsplit;
+            cand_ms[nc] = per;
+        }
+        ++nc;
+        if (per < bms) {
+            bms = per;
+            best = P->nsplit;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(dens);
+    if (out) (void)hipFree(out);
+    if (s) return s;
+    TRY(plan_set_split(P, best));
+    if (best_nsplit) *best_nsplit = best;
+    if (best_ms) *best_ms = bms;
+    if (n_cand) *n_cand = std::min(nc, cap);
+    return MHLP_OK;
 }
 
 extern "C" mhlp_status mhlp_eval_slp(const mhlp_plan *P, const double *sigma, double *u, int32_t precision,
@@ -1063,77 +1370,185 @@ static mhlp_status dnorm(mhlp_plan *P, const double *v, int64_t N, hipStream_t s
     return MHLP_OK;
 }
 
-/* One restarted-GMRES solve of A x = b to relative tolerance `tol` (relative
-   to bnorm), FP64 Arnoldi with CGS2, operator in `prec`.  x is updated in
-   place. */
-static mhlp_status gmres_core(mhlp_plan *P, const double *b, double bnorm, double *x, double tol, int restart,
-                              int max_iter, int32_t prec, hipStream_t st, int *iters, int *cycles, double *relres)
+/* Device data of the device-driven GMRES for restart length R. */
+struct GmresDev {
+    GState *gs;
+    double *H, *cs, *sn, *gv, *y, *h1, *h2, *hn;
+};
+
+static GmresDev gdev_view(const mhlp_plan *P)
+{
+    const int R = P->gdev_R;
+    double *d = reinterpret_cast<double *>(P->gdev + 64);
+    GmresDev v;
+    v.gs = reinterpret_cast<GState *>(P->gdev);
+    v.H = d;
+    d += (int64_t)(R + 1) * R;
+    v.cs = d;
+    d += R;
+    v.sn = d;
+    d += R;
+    v.gv = d;
+    d += R + 1;
+    v.y = d;
+    d += R;
+    v.h1 = d;
+    d += R + 1;
+    v.h2 = d;
+    d += R + 1;
+    v.hn = d;
+    return v;
+}
+
+static mhlp_status ensure_gdev(mhlp_plan *P, int R)
+{
+    if (P->gdev && P->gdev_R >= R) return MHLP_OK;
+    if (P->gdev) {
+        HIPCHECK(hipDeviceSynchronize());
+        (void)hipFree(P->gdev);
+        P->gdev = nullptr;
+    }
+    const int64_t nd = (int64_t)(R + 1) * R + 3 * R + 3 * (R + 1) + 1;
+    char *g = nullptr;
+    TRY(dalloc(&g, 64 + 8 * nd));
+    P->gdev = g;
+    P->gdev_R = R;
+    if (!P->gstate_host) HIPCHECK(hipHostMalloc((void **)&P->gstate_host, sizeof(GState), hipHostMallocDefault));
+    return MHLP_OK;
+}
+
+/* One Arnoldi step of the device-driven GMRES, enqueued on st. */
+static mhlp_status enqueue_step(mhlp_plan *P, int32_t prec, hipStream_t st)
 {
     const int64_t N = P->g->N;
-    double *V = P->ws;                       /* (restart+1) columns */
-    double *w = P->ws + (int64_t)(restart + 1) * N;
+    const int R = P->gdev_R;
+    double *V = P->ws, *w = P->ws + (int64_t)(R + 1) * N;
+    const GmresDev d = gdev_view(P);
+    const unsigned nbN = nblocks(N, 256);
+    TRY(launch_far(P, nullptr, V, nullptr, w, 0.5, prec, st, d.gs, N));
+    /* classical Gram-Schmidt, twice */
+    gs_dot_kernel<<<R, 256, 0, st>>>(d.gs, V, N, w, N, d.h1);
+    gs_sub_kernel<<<nbN, 256, 0, st>>>(d.gs, V, N, d.h1, w, N);
+    gs_dot_kernel<<<R, 256, 0, st>>>(d.gs, V, N, w, N, d.h2);
+    gs_sub_kernel<<<nbN, 256, 0, st>>>(d.gs, V, N, d.h2, w, N);
+    gs_norm_kernel<<<1, 256, 0, st>>>(d.gs, w, N, d.hn);
+    gs_finish_kernel<<<1, 64, 0, st>>>(d.gs, d.H, R, d.cs, d.sn, d.gv, d.h1, d.h2, d.hn);
+    gs_scale_kernel<<<nbN, 256, 0, st>>>(d.gs, w, V, N, N);
+    gs_advance_kernel<<<1, 64, 0, st>>>(d.gs);
+    HIPCHECK(hipGetLastError());
+    return MHLP_OK;
+}
+
+/* Executable graph of S consecutive Arnoldi steps (S = 1, 2, 4, 8), captured
+   once per plan state (workspace, split and restart) on a private stream. */
+static mhlp_status step_graph(mhlp_plan *P, int32_t prec, int si, hipGraphExec_t *out)
+{
+    const int S = 1 << si;
+    mhlp_plan::StepGraph &G = P->graphs[prec == MHLP_MIXED ? 1 : 0][si];
+    if (G.exec && G.ws == P->ws && G.part == P->part && G.gdev == P->gdev && G.R == P->gdev_R &&
+        G.nsplit == P->nsplit && G.S == S) {
+        *out = G.exec;
+        return MHLP_OK;
+    }
+    if (G.exec) {
+        (void)hipGraphExecDestroy(G.exec);
+        G.exec = nullptr;
+    }
+    if (!P->cap_stream) HIPCHECK(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
+    HIPCHECK(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
+    mhlp_status s = MHLP_OK;
+    for (int k = 0; k < S && s == MHLP_OK; ++k) s = enqueue_step(P, prec, P->cap_stream);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(P->cap_stream, &graph);
+    if (s != MHLP_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return s;
+    }
+    if (e != hipSuccess) return fail(MHLP_HIP_ERROR, std::string("GMRES step capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        G.exec = nullptr;
+        return fail(MHLP_HIP_ERROR, std::string("GMRES step graph: ") + hipGetErrorString(e));
+    }
+    G.ws = P->ws;
+    G.part = P->part;
+    G.gdev = P->gdev;
+    G.R = P->gdev_R;
+    G.nsplit = P->nsplit;
+    G.S = S;
+    *out = G.exec;
+    return MHLP_OK;
+}
+
+/* One restarted-GMRES solve of A x = b to relative tolerance `tol` (relative
+   to bnorm), FP64 Arnoldi with CGS2, operator in `prec`.  x is updated in
+   place.  The Arnoldi steps, the Givens rotations and the stopping test run
+   on the device; the host replays captured chunks of steps and reads the
+   state once per chunk.  The chunk length follows the observed convergence
+   rate (the steps still needed, rounded up to a power of two, at most 8);
+   steps after the stopping point do nothing. */
+static mhlp_status gmres_core(mhlp_plan *P, const double *b, double bnorm, double *x, double tol, int restart,
+                              int max_iter, int32_t prec, hipStream_t st, int *iters, int *cycles, double *relres,
+                              bool x_zero)
+{
+    const int64_t N = P->g->N;
+    TRY(ensure_gdev(P, restart));
+    const int R = P->gdev_R;
+    double *V = P->ws;
+    double *w = P->ws + (int64_t)(R + 1) * N;
     double *r = w + N;
-    std::vector<double> H((size_t)(restart + 1) * restart, 0.0), cs(restart), sn(restart), gv(restart + 1), yv(restart);
+    const GmresDev d = gdev_view(P);
     const unsigned nbN = nblocks(N, 256);
     int it = 0;
     *cycles = 0;
     for (;;) {
-        /* r = b - A x */
-        TRY(launch_far(P, nullptr, x, nullptr, w, 0.5, prec, st));
-        residual_kernel<<<nbN, 256, 0, st>>>(b, w, r, N);
+        /* r = b - A x (r = b, beta = ||b|| for a zero initial guess) */
         double beta;
-        TRY(dnorm(P, r, N, st, &beta));
+        const double *rr = b;
+        if (x_zero && *cycles == 0) {
+            beta = bnorm;
+        } else {
+            TRY(launch_far(P, nullptr, x, nullptr, w, 0.5, prec, st));
+            residual_kernel<<<nbN, 256, 0, st>>>(b, w, r, N);
+            TRY(dnorm(P, r, N, st, &beta));
+            rr = r;
+        }
         *relres = beta / bnorm;
         if (*relres <= tol || it >= max_iter) break;
         ++*cycles;
-        scale_kernel<<<nbN, 256, 0, st>>>(r, 1.0 / beta, V, N);
-        std::fill(gv.begin(), gv.end(), 0.0);
-        gv[0] = beta;
-        int k = 0;
-        for (; k < restart && it < max_iter; ++k) {
-            ++it;
-            TRY(launch_far(P, nullptr, V + k * N, nullptr, w, 0.5, prec, st));
-            /* classical Gram-Schmidt, twice */
-            double *h1 = P->hdev, *h2 = P->hdev + 1024, *hn = P->hdev + 2048;
-            multi_dot_kernel<<<k + 1, 256, 0, st>>>(V, N, w, N, h1);
-            sub_combo_kernel<<<nbN, 256, 0, st>>>(V, N, k + 1, h1, w, N);
-            multi_dot_kernel<<<k + 1, 256, 0, st>>>(V, N, w, N, h2);
-            sub_combo_kernel<<<nbN, 256, 0, st>>>(V, N, k + 1, h2, w, N);
-            multi_dot_kernel<<<1, 256, 0, st>>>(w, N, w, N, hn);
-            HIPCHECK(hipGetLastError());
-            HIPCHECK(hipMemcpyAsync(P->hhost, P->hdev, sizeof(double) * 3 * 1024, hipMemcpyDeviceToHost, st));
-            HIPCHECK(hipStreamSynchronize(st));
-            for (int j = 0; j <= k; ++j) H[(size_t)j * restart + k] = P->hhost[j] + P->hhost[1024 + j];
-            const double hn1 = std::sqrt(P->hhost[2048]);
-            H[(size_t)(k + 1) * restart + k] = hn1;
-            if (hn1 > 0.0) scale_kernel<<<nbN, 256, 0, st>>>(w, 1.0 / hn1, V + (k + 1) * N, N);
-            for (int j = 0; j < k; ++j) {
-                const double a = H[(size_t)j * restart + k], c = H[(size_t)(j + 1) * restart + k];
-                H[(size_t)j * restart + k] = cs[j] * a + sn[j] * c;
-                H[(size_t)(j + 1) * restart + k] = -sn[j] * a + cs[j] * c;
-            }
-            const double a = H[(size_t)k * restart + k], c = H[(size_t)(k + 1) * restart + k];
-            const double den = std::hypot(a, c);
-            cs[k] = a / den;
-            sn[k] = c / den;
-            H[(size_t)k * restart + k] = den;
-            H[(size_t)(k + 1) * restart + k] = 0.0;
-            gv[k + 1] = -sn[k] * gv[k];
-            gv[k] = cs[k] * gv[k];
-            if (std::fabs(gv[k + 1]) <= 0.5 * tol * bnorm || hn1 == 0.0) {
-                ++k;
-                break;
-            }
-        }
-        for (int i2 = k - 1; i2 >= 0; --i2) {
-            double sacc = gv[i2];
-            for (int j = i2 + 1; j < k; ++j) sacc -= H[(size_t)i2 * restart + j] * yv[j];
-            yv[i2] = sacc / H[(size_t)i2 * restart + i2];
-        }
-        HIPCHECK(hipMemcpyAsync(P->hdev + 3072, yv.data(), sizeof(double) * k, hipMemcpyHostToDevice, st));
-        add_combo_kernel<<<nbN, 256, 0, st>>>(V, N, k, P->hdev + 3072, x, N);
+        scale_kernel<<<nbN, 256, 0, st>>>(rr, 1.0 / beta, V, N);
+        const int kmax = std::min(restart, max_iter - it);
+        const double thresh = 0.5 * tol * bnorm;
+        gs_init_kernel<<<1, 256, 0, st>>>(d.gs, d.gv, R, kmax, beta, thresh);
         HIPCHECK(hipGetLastError());
-        HIPCHECK(hipStreamSynchronize(st));
+        int done_steps = 0, chunk = 2;
+        double last_est = beta;
+        for (;;) {
+            int si = 0;
+            while ((1 << si) < chunk && si < 3) ++si;
+            hipGraphExec_t ex;
+            TRY(step_graph(P, prec, si, &ex));
+            HIPCHECK(hipGraphLaunch(ex, st));
+            HIPCHECK(hipMemcpyAsync(P->gstate_host, d.gs, sizeof(GState), hipMemcpyDeviceToHost, st));
+            HIPCHECK(hipStreamSynchronize(st));
+            const GState gsh = *P->gstate_host;
+            if (gsh.done) break;
+            /* steps still needed at the rate observed over this chunk */
+            const int ran = gsh.steps - done_steps;
+            done_steps = gsh.steps;
+            int need = 8;
+            if (ran > 0 && gsh.resest > 0.0 && gsh.resest < last_est) {
+                const double rate = std::pow(gsh.resest / last_est, 1.0 / ran);
+                need = (int)std::ceil(std::log(thresh / gsh.resest) / std::log(rate));
+            }
+            last_est = gsh.resest;
+            chunk = std::max(1, std::min(need, 8));
+        }
+        it += P->gstate_host->steps;
+        gs_solve_kernel<<<1, 64, 0, st>>>(d.gs, d.H, R, d.gv, d.y);
+        gs_addcols_kernel<<<nbN, 256, 0, st>>>(d.gs, V, N, d.y, x, N);
+        HIPCHECK(hipGetLastError());
     }
     *iters = it;
     return MHLP_OK;
@@ -1154,7 +1569,11 @@ extern "C" mhlp_status mhlp_gmres_solve(const mhlp_plan *Pc, const double *g, do
     hipStream_t st = (hipStream_t)stream;
     const int64_t N = P->g->N;
     std::memset(info, 0, sizeof(*info));
-    TRY(ensure_ws(P, opts->restart + 1));
+    /* workspace columns: basis V_0..V_R, w, r (cycle residual), and the two
+       refinement vectors; R >= restart is the largest restart seen */
+    TRY(ensure_gdev(P, opts->restart));
+    const int R = P->gdev_R;
+    TRY(ensure_ws(P, R + 1));
     double bnorm;
     TRY(dnorm(P, g, N, st, &bnorm));
     info->used_x0 = opts->use_x0 ? 1 : 0;
@@ -1182,14 +1601,14 @@ extern "C" mhlp_status mhlp_gmres_solve(const mhlp_plan *Pc, const double *g, do
     int iters = 0, cycles = 0;
     double rel = 1.0;
     if (opts->precision == MHLP_FP64) {
-        TRY(gmres_core(P, g, bnorm, mu, opts->tol, opts->restart, opts->max_iter, MHLP_FP64, st, &iters, &cycles, &rel));
+        TRY(gmres_core(P, g, bnorm, mu, opts->tol, opts->restart, opts->max_iter, MHLP_FP64, st, &iters, &cycles, &rel,
+                       !info->used_x0));
     } else {
         /* iterative refinement: FP64 residual r = g - A mu (FP64 operator), inner
            GMRES on the mixed-precision operator for A d = r to 1e-6 relative (the
            FP32 far field resolves the operator to ~1e-7), mu += d. */
-        const int64_t cols = opts->restart + 1;
-        double *r = P->ws + (cols + 2) * N, *d = P->ws + (cols + 3) * N;
-        double *w = P->ws + cols * N;
+        double *r = P->ws + (int64_t)(R + 3) * N, *d = P->ws + (int64_t)(R + 4) * N;
+        double *w = P->ws + (int64_t)(R + 1) * N;
         const unsigned nbN = nblocks(N, 256);
         for (int outer = 0; outer < 20; ++outer) {
             TRY(launch_far(P, nullptr, mu, nullptr, w, 0.5, MHLP_FP64, st));
@@ -1202,7 +1621,7 @@ extern "C" mhlp_status mhlp_gmres_solve(const mhlp_plan *Pc, const double *g, do
             int it_in = 0, cyc_in = 0;
             double rel_in = 1.0;
             TRY(gmres_core(P, r, rn, d, 1e-6, opts->restart, opts->max_iter - iters, MHLP_MIXED, st, &it_in, &cyc_in,
-                           &rel_in));
+                           &rel_in, true));
             iters += it_in;
             cycles += 1;
             add_combo_kernel<<<nbN, 256, 0, st>>>(d, N, 1, P->hdev + 4000, mu, N);

@@ -61,6 +61,11 @@ _SIGS = {
     "mhlp_plan_destroy": ([_V], ctypes.c_int32),
     "mhlp_plan_info": ([_V, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                         ctypes.POINTER(ctypes.c_int64), _c_double_p], ctypes.c_int32),
+    "mhlp_plan_set_split": ([_V, ctypes.c_int32], ctypes.c_int32),
+    "mhlp_plan_get_split": ([_V, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int32),
+    "mhlp_plan_autotune": ([_V, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _V, ctypes.POINTER(ctypes.c_int32),
+                            _c_double_p, ctypes.POINTER(ctypes.c_int32), _c_double_p, ctypes.c_int32,
+                            ctypes.POINTER(ctypes.c_int32)], ctypes.c_int32),
     "mhlp_eval_layer": ([_V, _V, _V, _V, _V, ctypes.c_int32, _V], ctypes.c_int32),
     "mhlp_eval_slp": ([_V, _V, _V, ctypes.c_int32, _V], ctypes.c_int32),
     "mhlp_eval_dlp": ([_V, _V, _V, ctypes.c_int32, _V], ctypes.c_int32),
@@ -195,6 +200,25 @@ class Plan:
     @property
     def handle(self):
         return self._h
+
+    @property
+    def nsplit(self) -> int:
+        v = ctypes.c_int32()
+        _check(load().mhlp_plan_get_split(self._h, ctypes.byref(v)), "plan_get_split")
+        return v.value
+
+    def set_split(self, nsplit: int):
+        _check(load().mhlp_plan_set_split(self._h, int(nsplit)), "plan_set_split")
+
+    def autotune(self, layers: int = 3, precision=FP64, reps: int = 5):
+        """Time the far evaluation over source-split counts and keep the fastest.
+        layers: 1 SLP, 2 DLP, 3 both, 4 BIE operator.  Returns (best, best_ms, {nsplit: ms})."""
+        cap = 32
+        cand, cms = (ctypes.c_int32 * cap)(), (ctypes.c_double * cap)()
+        best, bms, nc = ctypes.c_int32(), ctypes.c_double(), ctypes.c_int32()
+        _check(load().mhlp_plan_autotune(self._h, int(layers), int(precision), int(reps), _stream(), ctypes.byref(best),
+                                         ctypes.byref(bms), cand, cms, cap, ctypes.byref(nc)), "plan_autotune")
+        return best.value, bms.value, {cand[i]: cms[i] for i in range(nc.value)}
 
     def close(self):
         if getattr(self, "_h", None):

@@ -1,0 +1,141 @@
+"""Device-driven GMRES (captured step graphs, device-side stopping test) and
+the far-field launch-shape autotuner, through the C ABI.
+
+Graph replays are checked against the oracle's dense solve and against each
+other, with eager library work and synchronisations between the replays; the
+autotuner must not change results beyond rounding.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1908_07392_amd import mhlp
+from paper_1908_07392_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _t(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=DEV)
+
+
+def _relerr(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(np.max(np.abs(b)), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def starfish():
+    alpha = 10.0
+    g = wl.discretize(wl.starfish_curve(), 40)
+    _, D = oracle.onsurface_matrices(g.x, g.y, alpha)
+    A = 0.5 * np.eye(g.n_nodes) + D
+    rng = np.random.default_rng(77)
+    rhs = [wl.fourier_density(g.theta, wl.random_fourier_coeffs(rng, 8)) for _ in range(3)]
+    refs = [np.linalg.solve(A, b) for b in rhs]
+    G = mhlp.Geometry(_t(g.node_soa()))
+    P = mhlp.Plan(G, alpha)
+    return dict(g=g, A=A, rhs=rhs, refs=refs, G=G, P=P, alpha=alpha)
+
+
+def test_replayed_solves_match_oracle_and_each_other(starfish):
+    d = starfish
+    P = d["P"]
+    first = {}
+    for rep in range(3):
+        for k, (b, ref) in enumerate(zip(d["rhs"], d["refs"])):
+            mu, info = mhlp.gmres_solve(P, _t(b), tol=1e-10, restart=50)
+            assert info["converged"] and info["rel_residual"] <= 1e-10, info
+            m = mu.cpu().numpy()
+            assert _relerr(m, ref) < 1e-8
+            # eager library work between replays: the operator and an evaluation
+            out = mhlp.apply_bie(P, mu)
+            torch.cuda.synchronize()
+            r = np.linalg.norm(out.cpu().numpy() - b) / np.linalg.norm(b)
+            assert r <= 1e-10
+            if rep == 0:
+                first[k] = (m, info["iters"])
+            else:
+                assert np.array_equal(m, first[k][0]) and info["iters"] == first[k][1]
+
+
+@pytest.mark.parametrize("restart", [1, 2, 3, 5, 200])
+def test_restarts_and_chunk_boundaries(starfish, restart):
+    d = starfish
+    b, ref = d["rhs"][0], d["refs"][0]
+    mu, info = mhlp.gmres_solve(d["P"], _t(b), tol=1e-10, restart=restart, max_iter=400)
+    assert info["converged"] and info["rel_residual"] <= 1e-10, info
+    assert _relerr(mu.cpu().numpy(), ref) < 1e-8
+    if restart == 200:
+        assert info["restarts"] == 1
+
+
+def test_max_iter_stops_exactly(starfish):
+    d = starfish
+    for cap in (1, 3, 6):
+        mu, info = mhlp.gmres_solve(d["P"], _t(d["rhs"][1]), tol=1e-14, restart=50, max_iter=cap)
+        assert info["iters"] == cap and not info["converged"]
+        # the reported residual is the true one of the returned iterate
+        out = mhlp.apply_bie(d["P"], mu).cpu().numpy()
+        b = d["rhs"][1]
+        assert abs(np.linalg.norm(out - b) / np.linalg.norm(b) - info["rel_residual"]) < 1e-12
+
+
+def test_split_change_invalidates_step_graphs(starfish):
+    d = starfish
+    P = d["P"]
+    b, ref = d["rhs"][2], d["refs"][2]
+    base = P.nsplit
+    try:
+        for ns in (1, 3, 10):
+            P.set_split(ns)
+            mu, info = mhlp.gmres_solve(P, _t(b), tol=1e-10, restart=50)
+            assert info["converged"] and _relerr(mu.cpu().numpy(), ref) < 1e-8
+    finally:
+        P.set_split(base)
+
+
+def test_mixed_refinement_after_larger_restart(starfish):
+    d = starfish
+    P = d["P"]
+    b, ref = d["rhs"][0], d["refs"][0]
+    mhlp.gmres_solve(P, _t(b), tol=1e-10, restart=300)  # grows the workspace
+    mu, info = mhlp.gmres_solve(P, _t(b), tol=1e-10, restart=20, precision=mhlp.MIXED)
+    assert info["converged"] and info["rel_residual"] <= 1e-10
+    assert _relerr(mu.cpu().numpy(), ref) < 1e-8
+
+
+def test_autotune_keeps_results_and_picks_a_candidate():
+    cfg = wl.config1()
+    geom = cfg["geom"]
+    G = mhlp.Geometry(_t(geom.node_soa()))
+    off = mhlp.Plan(G, cfg["alpha"], _t(cfg["tx"]), _t(cfg["ty"]))
+    sig = _t(cfg["sigma"])
+    us0, ud0 = mhlp.eval_layer(off, sigma=sig, mu=sig)
+    ref_s, ref_d = us0.cpu().numpy(), ud0.cpu().numpy()
+    best, ms, table = off.autotune(layers=3, reps=3)
+    assert best in table and ms == min(table.values()) and off.nsplit == best
+    assert 1 in table and len(table) >= 2
+    for ns in sorted(table):
+        off.set_split(ns)
+        us, ud = mhlp.eval_layer(off, sigma=sig, mu=sig)
+        assert _relerr(us.cpu().numpy(), ref_s) < 1e-13
+        assert _relerr(ud.cpu().numpy(), ref_d) < 1e-13
+    with pytest.raises(mhlp.MhlpError):
+        off.set_split(0)
+    with pytest.raises(mhlp.MhlpError):
+        off.autotune(layers=4)  # the BIE operator needs an on-surface plan
+
+
+def test_autotune_json_cache(tmp_path, monkeypatch):
+    from paper_1908_07392_amd import autotune
+    monkeypatch.setenv("MHLP_TUNE_CACHE", str(tmp_path / "tune.json"))
+    g = wl.discretize(wl.starfish_curve(), 64)
+    P = mhlp.Plan(mhlp.Geometry(_t(g.node_soa())), 20.0)
+    r1 = autotune.tune(P, "bie", reps=2)
+    assert not r1["cached"] and P.nsplit == r1["nsplit"]
+    P.set_split(1)
+    r2 = autotune.tune(P, "bie", reps=2)
+    assert r2["cached"] and P.nsplit == r1["nsplit"]
