@@ -30,11 +30,22 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GPair-evals/s (SLP+DLP) and GMRES time-to-1e-10, mixed/batched/warm vs FP64"
 FP64_PEAK_TFLOPS = 78.6        # MI355X vector FP64 (published)
-# FP64 operations per (target, source) pair of the fused far-field kernel on
-# its z > 2 branch: difference and r^2 (5), sqrt, 4/(alpha r) - 1, exp(-z)/sqrt(z)
-# (8 incl. 3 transcendental/divide), two degree-22 Horner polynomials (88),
-# scalings (4), accumulation of both layers (7)
-FLOP_PER_PAIR_FP64 = 112
+# FP64 operations per (target, source) pair of the fused SLP+DLP far-field
+# kernel on its z > 2 branch, counted from the instructions of the built kernel
+# (two pairs per loop trip): 69 v_fma (x2), 18 v_mul, 2 v_add, 2 v_rsq (x1)
+# = 160; not counted: 1 v_rndne, 1 v_ldexp, 1 v_cvt (exponent handling of
+# exp(-z)).  By function: r^2 and differences 5, 1/r 9, exp(-z) 33,
+# 1/sqrt(z) 9, K0 fit with derivative 86-88, K1 and scalings ~14, both
+# accumulations 7.
+FLOP_PER_PAIR_FP64 = 160
+# launch shapes (far-field source splits) chosen by the autotuner on MI355X for
+# the plans of this benchmark; the HBM byte counts below were taken with them
+TUNED_SPLITS = os.path.join(ROOT, "paper_1908_07392_amd", "tuning", "mi355x_far_splits.json")
+# HBM bytes per fused evaluation (FETCH_SIZE + WRITE_SIZE, each scaled by the
+# same counter's reading for a plain 256 MiB copy), averaged over the three
+# alphas, measured with these source splits
+# (profiles/far_eval_fp64_starfish4096_grid512_hbm_bytes.txt)
+PROFILED_TRAFFIC = {"splits": {"alpha=5": 20, "alpha=50": 16, "alpha=500": 16}, "bytes": 36912634}
 
 
 def parse():
@@ -45,7 +56,12 @@ def parse():
     ap.add_argument("--grid", type=int, default=512)
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the batched and volume legs")
+    ap.add_argument("--no-extra", action="store_true", help="skip the batched, volume and warm-start legs")
+    ap.add_argument("--tune-cache", default=TUNED_SPLITS,
+                    help="JSON cache of the autotuned launch shapes (read; plans missing from it are tuned afresh)")
+    ap.add_argument("--tune-write", action="store_true", help="add freshly tuned plans to the cache file")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -96,11 +112,23 @@ def main():
     torch.cuda.synchronize()
     plan_ms = (time.perf_counter() - t0) * 1e3
     gdev = {a: t(cfg["data"][a]["g"]) for a in cfg["alphas"]}
+    # launch shape of every plan from the autotuner (untimed set-up)
+    from paper_1908_07392_amd import autotune
+    tuned = {}
+    for a in cfg["alphas"]:
+        on, off = plans[a]
+        kw = dict(use_cache=True, path=args.tune_cache, write=args.tune_write)
+        r_on = autotune.tune(on, "bie", reps=5, **kw)
+        r_off = autotune.tune(off, "both", reps=5, **kw)
+        tuned[f"alpha={a:g}"] = {"bie_nsplit": r_on["nsplit"], "eval_nsplit": r_off["nsplit"],
+                                 "from_cache": bool(r_on["cached"] and r_off["cached"])}
+    print(f"# autotuned splits {tuned}", file=sys.stderr, flush=True)
     print(f"# plans built in {plan_ms:.0f} ms; near pairs "
           + ", ".join(f"alpha={a:g}: {plans[a][0].n_near_pairs}/{plans[a][1].n_near_pairs}" for a in cfg["alphas"]),
           file=sys.stderr, flush=True)
 
     stats = {}
+    events = []  # (alpha, start, end) around every fused evaluation of the timed region
 
     def step(record=False):
         pairs = 0
@@ -111,8 +139,13 @@ def main():
             t1 = time.perf_counter()
             mu, info = mhlp.gmres_solve(on, gdev[a], tol=1e-10, max_iter=400, restart=200)
             t2 = time.perf_counter()
+            if record:
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
             us, ud = mhlp.eval_layer(off, sigma=mu, mu=mu)
             if record:
+                e1.record()
+                events.append((a, e0, e1))
                 stats.setdefault(a, []).append(dict(gmres_ms=(t2 - t1) * 1e3, iters=info["iters"],
                                                     residual=info["rel_residual"]))
             # matvecs: one per Arnoldi step plus the residual checks (restart cycles + 1)
@@ -132,26 +165,28 @@ def main():
     ms_per_step = elapsed * 1e3 / args.steps
     value = total_pairs / elapsed / 1e9
 
-    # dominant kernel: fused SLP+DLP far-field evaluation at the targets (alpha = 50), HIP events
+    # dominant kernel: fused SLP+DLP far-field evaluation at the targets; HIP events
+    # on the launch stream around each evaluation of the timed region
+    per_a = {}
+    for a, e0, e1 in events:
+        per_a.setdefault(a, []).append(e0.elapsed_time(e1))
+    launch_ms = float(np.mean([v for a in per_a for v in per_a[a]]))
+    eval_pairs = M * N
+    achieved_tf = eval_pairs * FLOP_PER_PAIR_FP64 / (launch_ms * 1e-3) / 1e12
+    split = max(tuned[k]["eval_nsplit"] for k in tuned)
+    same_shape = {k: v["eval_nsplit"] for k, v in tuned.items()} == PROFILED_TRAFFIC["splits"]
+    roofline = {"bound": "alu", "achieved": round(achieved_tf, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved_tf / FP64_PEAK_TFLOPS, 4),
+                "traffic": PROFILED_TRAFFIC["bytes"] if same_shape else None,
+                "kernel": "far_eval_fp64<SLP,DLP>" + ("" if split == 1 else " + far_finalize"),
+                "launch_ms": round(launch_ms, 4),
+                "launch_ms_by_alpha": {f"alpha={a:g}": round(float(np.mean(v)), 4) for a, v in per_a.items()},
+                "pairs_per_launch": eval_pairs, "flop_per_pair": FLOP_PER_PAIR_FP64,
+                "eval_gpair_per_s": round(eval_pairs / (launch_ms * 1e-3) / 1e9, 3)}
     a_r = 50.0
     on, off = plans[a_r]
     mu, _ = mhlp.gmres_solve(on, gdev[a_r], tol=1e-10)
     reps = 20
-    mhlp.eval_layer(off, sigma=mu, mu=mu)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(reps):
-        mhlp.eval_layer(off, sigma=mu, mu=mu)
-    ev1.record()
-    torch.cuda.synchronize()
-    launch_ms = ev0.elapsed_time(ev1) / reps
-    eval_pairs = M * N
-    achieved_tf = eval_pairs * FLOP_PER_PAIR_FP64 / (launch_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "achieved": round(achieved_tf, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved_tf / FP64_PEAK_TFLOPS, 4), "traffic": None,
-                "kernel": "far_eval_fp64<SLP,DLP>", "launch_ms": round(launch_ms, 4),
-                "pairs_per_launch": eval_pairs, "flop_per_pair": FLOP_PER_PAIR_FP64,
-                "eval_gpair_per_s": round(eval_pairs / (launch_ms * 1e-3) / 1e9, 3)}
 
     gm = {f"alpha={a:g}": {"gmres_ms": round(float(np.median([s["gmres_ms"] for s in stats[a]])), 3),
                            "iters": stats[a][-1]["iters"], "residual": stats[a][-1]["residual"]}
@@ -162,7 +197,7 @@ def main():
            "config": {"workload": f"starfish 256x16 (N={N}), alpha 5/50/500, GMRES to 1e-10 + SLP+DLP at {M} "
                                   f"interior targets of a {args.grid}^2 grid",
                       "n_sources": N, "n_targets": M, "alphas": list(cfg["alphas"]), "precision": "fp64"},
-           "gmres": gm, "plan_build_ms": round(plan_ms, 1), "roofline": roofline}
+           "gmres": gm, "plan_build_ms": round(plan_ms, 1), "autotune": tuned, "roofline": roofline}
     # ---- mixed precision (FP32 far field, FP64 near/identity/Arnoldi, GMRES-IR) on the same step
     def mixed_step():
         tm = {}
@@ -186,6 +221,7 @@ def main():
     mu64, _ = mhlp.gmres_solve(on, gdev[a_r], tol=1e-10)
     us64, ud64 = mhlp.eval_layer(off, sigma=mu64, mu=mu64)
     us32, ud32 = mhlp.eval_layer(off, sigma=mu64, mu=mu64, precision=mhlp.MIXED)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record()
     for _ in range(reps):
         mhlp.eval_layer(off, sigma=mu64, mu=mu64, precision=mhlp.MIXED)
@@ -202,6 +238,14 @@ def main():
                                                "refinements": tm[a][1]["restarts"],
                                                "residual": tm[a][1]["rel_residual"]} for a in cfg["alphas"]}}
 
+    if args.copy_calibration:
+        nbytes = 256 << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration"] = {"bytes_read": nbytes, "bytes_written": nbytes, "launches": 3}
     if not args.no_extra:
         out["batched"] = bench_batched(mhlp, wl, t, torch)
         out["volume"] = bench_volume(mhlp, wl, t, torch)

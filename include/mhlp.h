@@ -117,8 +117,9 @@ mhlp_status mhlp_plan_info(const mhlp_plan *plan, int64_t *n_targets, int64_t *n
    mhlp_plan_autotune times the far evaluation (layers: 1 SLP, 2 DLP, 3 both,
    4 the on-surface BIE operator) for nsplit = 1, 2, 4, ... (up to Np/4 and
    256) plus the current value, reps timed launches each after one warm-up,
-   with HIP events on `stream`, keeps the fastest and reports it (host
-   outputs; cand/cand_ms receive up to cap candidates and their ms per launch).
+   with HIP events on `stream`, keeps the fewest splits within 1% of the
+   fastest and reports it with its time (host outputs; cand/cand_ms receive up
+   to cap candidates and their ms per launch).
    Synchronises the stream.  Errors: MHLP_INVALID_ARG. */
 mhlp_status mhlp_plan_set_split(mhlp_plan *plan, int32_t nsplit);
 mhlp_status mhlp_plan_get_split(const mhlp_plan *plan, int32_t *nsplit);

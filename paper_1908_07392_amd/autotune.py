@@ -24,9 +24,11 @@ def cache_path() -> str:
 
 
 def _key(plan: mhlp.Plan, layers: str, precision: int) -> str:
-    dev = torch.cuda.get_device_name(plan.geom.device)
+    # the compute-unit count identifies the part (the marketing name is not
+    # reported reliably, e.g. under a profiler)
+    dev = f"cu{torch.cuda.get_device_properties(plan.geom.device).multi_processor_count}"
     kind = "onsurf" if plan.onsurface else "targets"
-    return f"{dev}|{kind}|M={plan.n_targets}|N={plan.n_sources}|{layers}|prec={precision}"
+    return f"{dev}|{kind}|M={plan.n_targets}|N={plan.n_sources}|alpha={plan.alpha:g}|{layers}|prec={precision}"
 
 
 def _load(path):
@@ -38,9 +40,10 @@ def _load(path):
 
 
 def tune(plan: mhlp.Plan, layers: str = "both", precision: int = mhlp.FP64, reps: int = 5,
-         use_cache: bool = True) -> dict:
-    """Set the plan's split count from the cache or by timing; returns the record."""
-    path = cache_path()
+         use_cache: bool = True, path: str | None = None, write: bool = True) -> dict:
+    """Set the plan's split count from the cache or by timing; returns the record.
+    path: cache file (default cache_path()); write=False never modifies it."""
+    path = path or cache_path()
     key = _key(plan, layers, precision)
     cache = _load(path) if use_cache else {}
     if key in cache:
@@ -48,7 +51,7 @@ def tune(plan: mhlp.Plan, layers: str = "both", precision: int = mhlp.FP64, reps
         return dict(cache[key], cached=True)
     best, ms, table = plan.autotune(LAYERS[layers], precision, reps)
     rec = {"nsplit": best, "ms": ms, "candidates": {str(k): v for k, v in table.items()}}
-    if use_cache:
+    if use_cache and write:
         cache = _load(path)
         cache[key] = rec
         os.makedirs(os.path.dirname(path), exist_ok=True)
