@@ -1499,7 +1499,7 @@ static mhlp_status step_graph(mhlp_plan *P, int32_t prec, int si, hipGraphExec_t
    steps after the stopping point do nothing. */
 static mhlp_status gmres_core(mhlp_plan *P, const double *b, double bnorm, double *x, double tol, int restart,
                               int max_iter, int32_t prec, hipStream_t st, int *iters, int *cycles, double *relres,
-                              bool x_zero)
+                              const double *r_first, double beta_first)
 {
     const int64_t N = P->g->N;
     TRY(ensure_gdev(P, restart));
@@ -1512,11 +1512,12 @@ static mhlp_status gmres_core(mhlp_plan *P, const double *b, double bnorm, doubl
     int it = 0;
     *cycles = 0;
     for (;;) {
-        /* r = b - A x (r = b, beta = ||b|| for a zero initial guess) */
+        /* r = b - A x; the caller may hand over the first cycle's residual and
+           its norm (b itself for a zero initial guess) */
         double beta;
-        const double *rr = b;
-        if (x_zero && *cycles == 0) {
-            beta = bnorm;
+        const double *rr = r_first;
+        if (r_first && *cycles == 0) {
+            beta = beta_first;
         } else {
             TRY(launch_far(P, nullptr, x, nullptr, w, 0.5, prec, st));
             residual_kernel<<<nbN, 256, 0, st>>>(b, w, r, N);
@@ -1592,13 +1593,16 @@ extern "C" mhlp_status mhlp_gmres_solve(const mhlp_plan *Pc, const double *g, do
         info->converged = 1;
         return MHLP_OK;
     }
+    /* residual of the initial guess, kept in the residual slot of the first
+       GMRES cycle (basis V_0..V_R, then w, r) so the cycle does not recompute it */
+    double *r0 = P->ws + (int64_t)(R + 2) * N;
+    double r0n = 0.0;
     if (opts->use_x0) {
-        double *w = P->ws, *r = P->ws + N;
+        double *w = P->ws + (int64_t)(R + 1) * N;
         TRY(launch_far(P, nullptr, mu, nullptr, w, 0.5, MHLP_FP64, st));
-        residual_kernel<<<nblocks(N, 256), 256, 0, st>>>(g, w, r, N);
-        double rn;
-        TRY(dnorm(P, r, N, st, &rn));
-        info->x0_residual = rn / bnorm;
+        residual_kernel<<<nblocks(N, 256), 256, 0, st>>>(g, w, r0, N);
+        TRY(dnorm(P, r0, N, st, &r0n));
+        info->x0_residual = r0n / bnorm;
         if (!(info->x0_residual < 1.0)) {
             fill_kernel<<<nblocks(N, 256), 256, 0, st>>>(mu, 0.0, N);
             info->used_x0 = 0;
@@ -1611,7 +1615,7 @@ extern "C" mhlp_status mhlp_gmres_solve(const mhlp_plan *Pc, const double *g, do
     double rel = 1.0;
     if (opts->precision == MHLP_FP64) {
         TRY(gmres_core(P, g, bnorm, mu, opts->tol, opts->restart, opts->max_iter, MHLP_FP64, st, &iters, &cycles, &rel,
-                       !info->used_x0));
+                       info->used_x0 ? r0 : g, info->used_x0 ? r0n : bnorm));
     } else {
         /* iterative refinement: FP64 residual r = g - A mu (FP64 operator), inner
            GMRES on the mixed-precision operator for A d = r to 1e-6 relative (the
@@ -1620,17 +1624,25 @@ extern "C" mhlp_status mhlp_gmres_solve(const mhlp_plan *Pc, const double *g, do
         double *w = P->ws + (int64_t)(R + 1) * N;
         const unsigned nbN = nblocks(N, 256);
         for (int outer = 0; outer < 20; ++outer) {
-            TRY(launch_far(P, nullptr, mu, nullptr, w, 0.5, MHLP_FP64, st));
-            residual_kernel<<<nbN, 256, 0, st>>>(g, w, r, N);
             double rn;
-            TRY(dnorm(P, r, N, st, &rn));
+            if (outer == 0 && !info->used_x0) {
+                rn = bnorm; /* zero initial guess: r = g */
+                HIPCHECK(hipMemcpyAsync(r, g, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+            } else if (outer == 0) {
+                rn = r0n;
+                HIPCHECK(hipMemcpyAsync(r, r0, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+            } else {
+                TRY(launch_far(P, nullptr, mu, nullptr, w, 0.5, MHLP_FP64, st));
+                residual_kernel<<<nbN, 256, 0, st>>>(g, w, r, N);
+                TRY(dnorm(P, r, N, st, &rn));
+            }
             rel = rn / bnorm;
             if (rel <= opts->tol || iters >= opts->max_iter) break;
             fill_kernel<<<nbN, 256, 0, st>>>(d, 0.0, N);
             int it_in = 0, cyc_in = 0;
             double rel_in = 1.0;
             TRY(gmres_core(P, r, rn, d, 1e-6, opts->restart, opts->max_iter - iters, MHLP_MIXED, st, &it_in, &cyc_in,
-                           &rel_in, true));
+                           &rel_in, r, rn));
             iters += it_in;
             cycles += 1;
             add_combo_kernel<<<nbN, 256, 0, st>>>(d, N, 1, P->hdev + 4000, mu, N);
