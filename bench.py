@@ -148,8 +148,9 @@ def main():
                 events.append((a, e0, e1))
                 stats.setdefault(a, []).append(dict(gmres_ms=(t2 - t1) * 1e3, iters=info["iters"],
                                                     residual=info["rel_residual"]))
-            # matvecs: one per Arnoldi step plus the residual checks (restart cycles + 1)
-            pairs += (info["iters"] + info["restarts"] + 1) * N * N + M * N
+            # operator applications of a zero-guess solve: one per Arnoldi step and
+            # one true-residual check per cycle (the first residual is g itself)
+            pairs += (info["iters"] + info["restarts"]) * N * N + M * N
         return pairs
 
     for _ in range(args.warmup):
