@@ -269,6 +269,7 @@ def bench_batched(mhlp, wl, t, torch):
     torch.cuda.synchronize()
     plan_ms = (time.perf_counter() - t0) * 1e3
     B = mhlp.Batch(plans, 4)
+    target, _ = B.autotune(reps=3)
     rhs = [t(it["rhs"][r]) for it in items for r in range(4)]
     gb = B.pack(rhs)
     B.gmres(gb, tol=1e-10)  # warm-up
@@ -288,7 +289,7 @@ def bench_batched(mhlp, wl, t, torch):
     torch.cuda.synchronize()
     seq_ms = (time.perf_counter() - t0) * 1e3
     n_nodes = sum(it["geom"].n_nodes for it in items)
-    return {"systems": len(infos), "total_nodes": n_nodes, "plan_build_ms": round(plan_ms, 1),
+    return {"systems": len(infos), "total_nodes": n_nodes, "plan_build_ms": round(plan_ms, 1), "block_target": target,
             "batched_ms": round(batched_ms, 2), "sequential_ms": round(seq_ms, 2),
             "speedup_vs_sequential": round(seq_ms / batched_ms, 2),
             "all_converged": all(i["converged"] for i in infos),

@@ -181,10 +181,17 @@ mhlp_status mhlp_batch_destroy(mhlp_batch *batch);
 mhlp_status mhlp_batch_info(const mhlp_batch *batch, int64_t *total_len, int32_t *n_systems, int64_t *offsets,
                             int64_t *lengths);
 /* out = (1/2 I + D) mu for every system in one grouped launch (kernel values
-   shared by the right-hand sides of a geometry); FP64. */
+   shared by the right-hand sides of a geometry); FP64.  The launch runs a
+   work list of (geometry, 256 targets, source split) items, longest first. */
 mhlp_status mhlp_batch_apply_bie(const mhlp_batch *batch, const double *mu, double *out, void *stream);
+/* Rebuild the work list for a total of 512, 1024, ..., 16384 blocks, time the
+   grouped operator for each (reps launches after a warm-up, HIP events on
+   `stream`) and keep the fewest blocks within 1% of the fastest; best_target
+   and best_ms (host) may be NULL.  Synchronises the stream. */
+mhlp_status mhlp_batch_autotune(mhlp_batch *batch, int32_t reps, void *stream, int64_t *best_target, double *best_ms);
 /* Lockstep restarted GMRES on every system (FP64, CGS2, restart <= 64),
-   converged systems frozen; each judged by its own true residual.  infos:
+   converged systems frozen (their geometries drop out of the operator
+   launches of the cycle); each judged by its own true residual.  infos:
    host array of n_geom*n_rhs.  Synchronises the stream.  Returns
    MHLP_NOT_CONVERGED if any system misses the tolerance within max_iter
    Arnoldi steps (counted per lockstep iteration). */

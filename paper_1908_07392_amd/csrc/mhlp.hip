@@ -1742,11 +1742,26 @@ struct BatchWork {
     int32_t g, tb, split, pad;
 };
 
+/* A geometry takes part in a batched operator application unless a gate is
+   given and all its right-hand sides are gated off (gate[g*R + r] == 0:
+   systems that have converged in the current GMRES cycle). */
+template <int R>
+__device__ __forceinline__ bool batch_gated_off(const double *__restrict__ gate, int g)
+{
+    if (!gate) return false;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (gate[(int64_t)g * R + r] != 0.0) return false;
+    return true;
+}
+
 template <int R>
 __global__ __launch_bounds__(FT_THREADS) void batch_far_dlp(const BatchGeo *__restrict__ G,
                                                             const BatchWork *__restrict__ W,
-                                                            const double *__restrict__ mu, double *__restrict__ part)
+                                                            const double *__restrict__ mu, double *__restrict__ part,
+                                                            const double *__restrict__ gate)
 {
+    if (batch_gated_off<R>(gate, W[blockIdx.x].g)) return;
     __shared__ double lx[FT_SRC], ly[FT_SRC];
     __shared__ double ldx[R][FT_SRC], ldy[R][FT_SRC];
     const BatchWork wk = W[blockIdx.x];
@@ -1816,8 +1831,9 @@ __global__ __launch_bounds__(FT_THREADS) void batch_far_dlp(const BatchGeo *__re
 template <int R>
 __global__ void batch_finalize(const BatchGeo *__restrict__ G, const BatchWork *__restrict__ W,
                                const double *__restrict__ part, const double *__restrict__ mu,
-                               double *__restrict__ out)
+                               double *__restrict__ out, const double *__restrict__ gate)
 {
+    if (batch_gated_off<R>(gate, W[blockIdx.x].g)) return;
     const BatchWork wk = W[blockIdx.x];
     const BatchGeo geo = G[wk.g];
     const int64_t i = (int64_t)wk.tb * FT_THREADS + threadIdx.x;
@@ -1907,7 +1923,11 @@ struct mhlp_batch {
     double *dsc = nullptr;               /* per-system scalars */
     int32_t *dk = nullptr;
     int ldh = 0;
+    std::vector<BatchGeo> hgeo; /* host copy of the per-geometry descriptors */
+    int64_t target = 0;         /* block target of the current work list    */
 };
+
+static mhlp_status batch_build_work(mhlp_batch *B, int64_t target, hipStream_t st);
 
 extern "C" mhlp_status mhlp_batch_destroy(mhlp_batch *B)
 {
@@ -1934,21 +1954,12 @@ extern "C" mhlp_status mhlp_batch_create(int32_t n_geom, const mhlp_plan *const 
     B->n_geom = n_geom;
     B->R = n_rhs;
     B->S = n_geom * n_rhs;
-    std::vector<BatchGeo> hg(n_geom);
-    std::vector<BatchWork> hw, hf;
-    int64_t voff = 0, poff = 0, tblocks_all = 0;
-    for (int g = 0; g < n_geom; ++g) tblocks_all += (plans[g]->M + FT_THREADS - 1) / FT_THREADS;
-    /* source splits: aim at ~2048 blocks in total, split the larger geometries */
-    const double target = 2048.0;
-    const double tot_work = [&] {
-        double t = 0;
-        for (int g = 0; g < n_geom; ++g) t += (double)plans[g]->g->N * plans[g]->M;
-        return t;
-    }();
+    B->hgeo.resize(n_geom);
+    int64_t voff = 0;
     for (int g = 0; g < n_geom; ++g) {
         const mhlp_plan *P = plans[g];
         const mhlp_geometry *G = P->g;
-        BatchGeo &b = hg[g];
+        BatchGeo &b = B->hgeo[g];
         b.x = G->soa;
         b.y = G->soa + G->N;
         b.w = G->w;
@@ -1961,20 +1972,6 @@ extern "C" mhlp_status mhlp_batch_create(int32_t n_geom, const mhlp_plan *const 
         b.Np = G->Np;
         b.alpha = P->alpha;
         b.voff = voff;
-        const int64_t tb = (G->N + FT_THREADS - 1) / FT_THREADS;
-        /* blocks for this geometry proportional to its share of pair work */
-        int64_t want = (int64_t)std::ceil(target * (double)G->N * G->N / tot_work);
-        int64_t ns = (want + tb - 1) / tb;
-        if (ns > G->Np / 4) ns = G->Np / 4;
-        if (ns < 1) ns = 1;
-        b.pps = (int32_t)((G->Np + ns - 1) / ns);
-        b.nsplit = (int32_t)((G->Np + b.pps - 1) / b.pps);
-        b.poff = poff;
-        poff += (int64_t)b.nsplit * n_rhs * G->N;
-        for (int64_t t = 0; t < tb; ++t) {
-            for (int sp = 0; sp < b.nsplit; ++sp) hw.push_back(BatchWork{g, (int32_t)t, sp, 0});
-            hf.push_back(BatchWork{g, (int32_t)t, 0, 0});
-        }
         for (int r = 0; r < n_rhs; ++r) {
             B->off.push_back(voff + (int64_t)r * G->N);
             B->n.push_back(G->N);
@@ -1982,27 +1979,75 @@ extern "C" mhlp_status mhlp_batch_create(int32_t n_geom, const mhlp_plan *const 
         B->max_n = std::max<int64_t>(B->max_n, G->N);
         voff += (int64_t)n_rhs * G->N;
     }
-    (void)tblocks_all;
     B->total = voff;
-    B->nwork = (int64_t)hw.size();
-    B->nfin = (int64_t)hf.size();
     mhlp_status s;
-    if ((s = dalloc(&B->dgeo, n_geom)) || (s = dalloc(&B->dwork, B->nwork)) || (s = dalloc(&B->dfin, B->nfin)) ||
-        (s = dalloc(&B->part, poff)) || (s = dalloc(&B->doff, B->S)) || (s = dalloc(&B->dn, B->S))) {
+    if ((s = dalloc(&B->dgeo, n_geom)) || (s = dalloc(&B->doff, B->S)) || (s = dalloc(&B->dn, B->S))) {
         mhlp_batch_destroy(B);
         return s;
     }
-    hipError_t e = hipMemcpyAsync(B->dgeo, hg.data(), sizeof(BatchGeo) * n_geom, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(B->dwork, hw.data(), sizeof(BatchWork) * B->nwork, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(B->dfin, hf.data(), sizeof(BatchWork) * B->nfin, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(B->doff, B->off.data(), sizeof(int64_t) * B->S, hipMemcpyHostToDevice, st);
+    hipError_t e = hipMemcpyAsync(B->doff, B->off.data(), sizeof(int64_t) * B->S, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(B->dn, B->n.data(), sizeof(int64_t) * B->S, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
         mhlp_batch_destroy(B);
         return fail(MHLP_HIP_ERROR, std::string("batch_create: ") + hipGetErrorString(e));
     }
+    if ((s = batch_build_work(B, 2048, st))) {
+        mhlp_batch_destroy(B);
+        return s;
+    }
     *out = B;
+    return MHLP_OK;
+}
+
+/* Work list of the grouped operator launch for about `target` blocks in total:
+   each geometry gets blocks in proportion to its share of the pair work
+   (N_g^2), as source splits of its target blocks (at least 4 panels per
+   split); items are ordered by decreasing cost so the longest start first. */
+static mhlp_status batch_build_work(mhlp_batch *B, int64_t target, hipStream_t st)
+{
+    const int n_geom = B->n_geom, n_rhs = B->R;
+    double tot_work = 0;
+    for (const BatchGeo &b : B->hgeo) tot_work += (double)b.N * b.N;
+    std::vector<BatchWork> hw, hf;
+    int64_t poff = 0;
+    for (int g = 0; g < n_geom; ++g) {
+        BatchGeo &b = B->hgeo[g];
+        const int64_t tb = (b.N + FT_THREADS - 1) / FT_THREADS;
+        const int64_t want = (int64_t)std::ceil((double)target * (double)b.N * b.N / tot_work);
+        int64_t ns = (want + tb - 1) / tb;
+        if (ns > b.Np / 4) ns = b.Np / 4;
+        if (ns < 1) ns = 1;
+        b.pps = (int32_t)((b.Np + ns - 1) / ns);
+        b.nsplit = (int32_t)((b.Np + b.pps - 1) / b.pps);
+        b.poff = poff;
+        poff += (int64_t)b.nsplit * n_rhs * b.N;
+        for (int64_t t = 0; t < tb; ++t) {
+            for (int sp = 0; sp < b.nsplit; ++sp) hw.push_back(BatchWork{g, (int32_t)t, sp, 0});
+            hf.push_back(BatchWork{g, (int32_t)t, 0, 0});
+        }
+    }
+    /* cost of an item ~ panels it sums over (all items have 256 targets) */
+    std::stable_sort(hw.begin(), hw.end(), [&](const BatchWork &a, const BatchWork &c) {
+        return B->hgeo[a.g].pps > B->hgeo[c.g].pps;
+    });
+    HIPCHECK(hipStreamSynchronize(st)); /* old buffers may be in use */
+    void *old[] = {B->dwork, B->dfin, B->part};
+    for (void *p : old)
+        if (p) (void)hipFree(p);
+    B->dwork = B->dfin = nullptr;
+    B->part = nullptr;
+    B->nwork = (int64_t)hw.size();
+    B->nfin = (int64_t)hf.size();
+    B->target = target;
+    TRY(dalloc(&B->dwork, B->nwork));
+    TRY(dalloc(&B->dfin, B->nfin));
+    TRY(dalloc(&B->part, poff));
+    hipError_t e = hipMemcpyAsync(B->dgeo, B->hgeo.data(), sizeof(BatchGeo) * n_geom, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(B->dwork, hw.data(), sizeof(BatchWork) * B->nwork, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(B->dfin, hf.data(), sizeof(BatchWork) * B->nfin, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(MHLP_HIP_ERROR, std::string("batch work list: ") + hipGetErrorString(e));
     return MHLP_OK;
 }
 
@@ -2019,25 +2064,23 @@ extern "C" mhlp_status mhlp_batch_info(const mhlp_batch *B, int64_t *total_len, 
     return MHLP_OK;
 }
 
-static mhlp_status batch_apply_impl(const mhlp_batch *B, const double *mu, double *out, hipStream_t st)
+template <int R>
+static void batch_apply_t(const mhlp_batch *B, const double *mu, double *out, const double *gate, hipStream_t st)
+{
+    batch_far_dlp<R><<<(unsigned)B->nwork, FT_THREADS, 0, st>>>(B->dgeo, B->dwork, mu, B->part, gate);
+    batch_finalize<R><<<(unsigned)B->nfin, FT_THREADS, 0, st>>>(B->dgeo, B->dfin, B->part, mu, out, gate);
+}
+
+/* out = (1/2 I + D) mu for every system; with a gate, geometries whose
+   systems are all gated off are skipped (their part of out is left as is) */
+static mhlp_status batch_apply_impl(const mhlp_batch *B, const double *mu, double *out, hipStream_t st,
+                                    const double *gate = nullptr)
 {
     switch (B->R) {
-    case 1:
-        batch_far_dlp<1><<<(unsigned)B->nwork, FT_THREADS, 0, st>>>(B->dgeo, B->dwork, mu, B->part);
-        batch_finalize<1><<<(unsigned)B->nfin, FT_THREADS, 0, st>>>(B->dgeo, B->dfin, B->part, mu, out);
-        break;
-    case 2:
-        batch_far_dlp<2><<<(unsigned)B->nwork, FT_THREADS, 0, st>>>(B->dgeo, B->dwork, mu, B->part);
-        batch_finalize<2><<<(unsigned)B->nfin, FT_THREADS, 0, st>>>(B->dgeo, B->dfin, B->part, mu, out);
-        break;
-    case 3:
-        batch_far_dlp<3><<<(unsigned)B->nwork, FT_THREADS, 0, st>>>(B->dgeo, B->dwork, mu, B->part);
-        batch_finalize<3><<<(unsigned)B->nfin, FT_THREADS, 0, st>>>(B->dgeo, B->dfin, B->part, mu, out);
-        break;
-    default:
-        batch_far_dlp<4><<<(unsigned)B->nwork, FT_THREADS, 0, st>>>(B->dgeo, B->dwork, mu, B->part);
-        batch_finalize<4><<<(unsigned)B->nfin, FT_THREADS, 0, st>>>(B->dgeo, B->dfin, B->part, mu, out);
-        break;
+    case 1: batch_apply_t<1>(B, mu, out, gate, st); break;
+    case 2: batch_apply_t<2>(B, mu, out, gate, st); break;
+    case 3: batch_apply_t<3>(B, mu, out, gate, st); break;
+    default: batch_apply_t<4>(B, mu, out, gate, st); break;
     }
     HIPCHECK(hipGetLastError());
     return MHLP_OK;
@@ -2048,6 +2091,51 @@ extern "C" mhlp_status mhlp_batch_apply_bie(const mhlp_batch *B, const double *m
     if (!B || !mu || !out) return fail(MHLP_INVALID_ARG, "NULL argument");
     if (mu == out) return fail(MHLP_INVALID_ARG, "mu and out must not alias");
     return batch_apply_impl(B, mu, out, (hipStream_t)stream);
+}
+
+extern "C" mhlp_status mhlp_batch_autotune(mhlp_batch *B, int32_t reps, void *stream, int64_t *best_target,
+                                           double *best_ms)
+{
+    if (!B) return fail(MHLP_INVALID_ARG, "batch is NULL");
+    if (reps < 1 || reps > 1000) return fail(MHLP_INVALID_ARG, "reps must be in [1, 1000]");
+    hipStream_t st = (hipStream_t)stream;
+    double *mu = nullptr, *out = nullptr;
+    TRY(dalloc(&mu, B->total));
+    mhlp_status s = dalloc(&out, B->total);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (s == MHLP_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+        s = fail(MHLP_HIP_ERROR, "hipEventCreate");
+    if (s == MHLP_OK) fill_kernel<<<nblocks(B->total, 256), 256, 0, st>>>(mu, 1.0, B->total);
+    std::vector<std::pair<int64_t, double>> tim;
+    for (int64_t tg : {512LL, 1024LL, 2048LL, 4096LL, 8192LL, 16384LL}) {
+        if (s) break;
+        if ((s = batch_build_work(B, tg, st))) break;
+        if ((s = batch_apply_impl(B, mu, out, st))) break;
+        float ms = 0.f;
+        hipError_t e = hipEventRecord(e0, st);
+        for (int r = 0; r < reps && e == hipSuccess && s == MHLP_OK; ++r) s = batch_apply_impl(B, mu, out, st);
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess && s == MHLP_OK) s = fail(MHLP_HIP_ERROR, std::string("batch autotune: ") + hipGetErrorString(e));
+        if (s == MHLP_OK) tim.emplace_back(tg, (double)ms / reps);
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(mu);
+    if (out) (void)hipFree(out);
+    if (s) return s;
+    double bms = 1e300;
+    for (const auto &t : tim) bms = std::min(bms, t.second);
+    int64_t best = 0;
+    double bt = 0.0;
+    for (const auto &t : tim) /* fewest blocks within 1% of the fastest */
+        if (t.second <= 1.01 * bms && (best == 0 || t.first < best)) best = t.first, bt = t.second;
+    TRY(batch_build_work(B, best, st));
+    if (best_target) *best_target = best;
+    if (best_ms) *best_ms = bt;
+    return MHLP_OK;
 }
 
 extern "C" mhlp_status mhlp_batch_gmres_solve(mhlp_batch *B, const double *g, double *mu, const mhlp_gmres_opts *opts,
@@ -2137,7 +2225,9 @@ extern "C" mhlp_status mhlp_batch_gmres_solve(mhlp_batch *B, const double *g, do
         for (; k < m && total_it < opts->max_iter; ++k) {
             ++total_it;
             double *Vk = B->V + (int64_t)k * T;
-            TRY(batch_apply_impl(B, Vk, B->w, st));
+            /* B->dsc holds 1/||.|| of the systems still active at this step, 0 for
+               the others: converged geometries skip the operator application */
+            TRY(batch_apply_impl(B, Vk, B->w, st, B->dsc));
             bdot_kernel<<<dim3((unsigned)S, (unsigned)(k + 1)), 256, 0, st>>>(B->V, T, B->w, B->doff, B->dn, ldh, h1);
             bcombo_kernel<<<gS, 256, 0, st>>>(B->V, T, k + 1, nullptr, h1, ldh, -1.0, B->w, B->doff, B->dn);
             bdot_kernel<<<dim3((unsigned)S, (unsigned)(k + 1)), 256, 0, st>>>(B->V, T, B->w, B->doff, B->dn, ldh, h2);

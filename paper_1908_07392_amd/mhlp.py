@@ -77,6 +77,7 @@ _SIGS = {
     "mhlp_batch_info": ([_V, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
                          ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int32),
     "mhlp_batch_apply_bie": ([_V, _V, _V, _V], ctypes.c_int32),
+    "mhlp_batch_autotune": ([_V, ctypes.c_int32, _V, ctypes.POINTER(ctypes.c_int64), _c_double_p], ctypes.c_int32),
     "mhlp_batch_gmres_solve": ([_V, _V, _V, ctypes.POINTER(GmresOpts), ctypes.POINTER(GmresInfo), _V],
                                ctypes.c_int32),
     "mhlp_volume_eval": ([_V, _V, _V, _V, ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_int32, _V,
@@ -317,6 +318,13 @@ class Batch:
         _check(load().mhlp_batch_apply_bie(self._h, _dev(mu, "mu", self.total), _dev(out, "out", self.total),
                                            _stream()), "batch_apply_bie")
         return out
+
+    def autotune(self, reps: int = 3):
+        """Pick the block target of the grouped launch; returns (target, ms)."""
+        tg, ms = ctypes.c_int64(), ctypes.c_double()
+        _check(load().mhlp_batch_autotune(self._h, int(reps), _stream(), ctypes.byref(tg), ctypes.byref(ms)),
+               "batch_autotune")
+        return tg.value, ms.value
 
     def gmres(self, g, x0=None, tol=1e-10, max_iter=500, restart=64):
         mu = torch.zeros(self.total, dtype=torch.float64, device=self.device) if x0 is None else x0.clone()

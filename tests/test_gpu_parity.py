@@ -275,11 +275,19 @@ def test_batch_apply_matches_single():
             vecs.append(_t(wl.fourier_density(g.theta, wl.random_fourier_coeffs(rng, 6))))
     out = B.unpack(B.apply(B.pack(vecs)))
     k = 0
+    refs = []
     for p in plans:
         for r in range(3):
             ref = mhlp.apply_bie(p, vecs[k])
-            assert _relerr(out[k].cpu().numpy(), ref.cpu().numpy()) < 1e-12
+            refs.append(ref.cpu().numpy())
+            assert _relerr(out[k].cpu().numpy(), refs[-1]) < 1e-12
             k += 1
+    # every work-list shape the autotuner may pick gives the same operator
+    target, ms = B.autotune(reps=2)
+    assert target in (512, 1024, 2048, 4096, 8192, 16384) and ms > 0
+    out2 = B.unpack(B.apply(B.pack(vecs)))
+    for k in range(len(vecs)):
+        assert _relerr(out2[k].cpu().numpy(), refs[k]) < 1e-12
 
 
 def test_batch_gmres_matches_single():
