@@ -93,7 +93,8 @@ struct mhlp_plan {
     double alpha = 0.0;
     int64_t M = 0;
     bool onsurf = false;
-    double *tx = nullptr, *ty = nullptr; /* owned unless onsurf */
+    double *tx = nullptr, *ty = nullptr; /* owned unless onsurf; off-surface: Morton order */
+    int32_t *perm = nullptr;             /* off-surface: caller index of internal target i */
     int32_t *near_ptr = nullptr;         /* [M+1] */
     int32_t *near_panel = nullptr;       /* [nnz] */
     int32_t *near_tgt = nullptr;         /* [nnz] */
@@ -355,6 +356,7 @@ struct FarArgs {
        basis (mu + j*jstride) and the launch does nothing once gs->done */
     const GState *gs;
     int64_t jstride;
+    const int32_t *perm; /* output index of internal target i (NULL: identity) */
 };
 
 
@@ -384,12 +386,13 @@ __device__ __forceinline__ void far_epilogue(const FarArgs &A, const double *__r
             if (DLP) cd = fma(A.wdl[16 * (int64_t)q + jj], mu[16 * p + jj], cd);
         }
     }
-    if (SLP) A.us[i] = fma(INV_2PI, accs, cs);
+    const int64_t o = A.perm ? (int64_t)A.perm[i] : i;
+    if (SLP) A.us[o] = fma(INV_2PI, accs, cs);
     if (DLP) {
         double v = fma(INV_2PI, accd, cd);
         /* identity term: only on-surface plans (targets are the nodes, M == N) */
         if (A.half_term != 0.0) v = fma(A.half_term, mu[i], v);
-        A.ud[i] = v;
+        A.ud[o] = v;
     }
 }
 
@@ -1006,7 +1009,7 @@ extern "C" mhlp_status mhlp_plan_destroy(mhlp_plan *P)
             if (gr.exec) (void)hipGraphExecDestroy(gr.exec);
     if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
     void *ptrs[] = {P->near_ptr, P->near_panel, P->near_tgt, P->near_ts, P->wslp, P->wdlp,
-                    P->ws,       P->hdev,       P->part,     P->gdev};
+                    P->ws,       P->hdev,       P->part,     P->gdev,    P->perm};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (P->hhost) (void)hipHostFree(P->hhost);
@@ -1047,12 +1050,61 @@ extern "C" mhlp_status mhlp_plan_create(const mhlp_geometry *g, double alpha, co
         P->ty = g->soa + g->N;
     } else {
         P->M = m;
-        if ((s = dalloc(&P->tx, m)) || (s = dalloc(&P->ty, m))) {
+        if ((s = dalloc(&P->tx, m)) || (s = dalloc(&P->ty, m)) || (s = dalloc(&P->perm, m))) {
             mhlp_plan_destroy(P);
             return s;
         }
-        hipError_t e = hipMemcpyAsync(P->tx, tx, sizeof(double) * m, hipMemcpyDeviceToDevice, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(P->ty, ty, sizeof(double) * m, hipMemcpyDeviceToDevice, st);
+        /* Targets are kept in Morton (Z-curve) order of their coordinates, so the
+           64 lanes of a wave hold nearby targets: they share near panels and
+           fall on the same side of the z = 2 switch of the kernel values more
+           often.  Results are written back through perm. */
+        std::vector<double> hx((size_t)m), hy((size_t)m);
+        hipError_t e = hipMemcpyAsync(hx.data(), tx, sizeof(double) * m, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(hy.data(), ty, sizeof(double) * m, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            mhlp_plan_destroy(P);
+            return fail(MHLP_HIP_ERROR, std::string("plan_create copy: ") + hipGetErrorString(e));
+        }
+        double x0 = hx[0], x1 = hx[0], y0 = hy[0], y1 = hy[0];
+        for (int64_t i = 0; i < m; ++i) {
+            if (!std::isfinite(hx[i]) || !std::isfinite(hy[i])) {
+                mhlp_plan_destroy(P);
+                return fail(MHLP_INVALID_ARG, "target coordinates must be finite");
+            }
+            x0 = std::min(x0, hx[i]), x1 = std::max(x1, hx[i]);
+            y0 = std::min(y0, hy[i]), y1 = std::max(y1, hy[i]);
+        }
+        const double span = std::max(std::max(x1 - x0, y1 - y0), 1e-300);
+        auto spread = [](uint32_t v) { /* 16 bits -> even bit positions */
+            uint64_t b = v & 0xFFFFu;
+            b = (b | (b << 8)) & 0x00FF00FFull;
+            b = (b | (b << 4)) & 0x0F0F0F0Full;
+            b = (b | (b << 2)) & 0x33333333ull;
+            b = (b | (b << 1)) & 0x55555555ull;
+            return b;
+        };
+        std::vector<std::pair<uint64_t, int32_t>> key((size_t)m);
+        for (int64_t i = 0; i < m; ++i) {
+            const uint32_t qx = (uint32_t)std::min(65535.0, std::floor((hx[i] - x0) / span * 65536.0));
+            const uint32_t qy = (uint32_t)std::min(65535.0, std::floor((hy[i] - y0) / span * 65536.0));
+            key[i] = {spread(qx) | (spread(qy) << 1), (int32_t)i};
+        }
+        std::stable_sort(key.begin(), key.end(),
+                         [](const std::pair<uint64_t, int32_t> &a, const std::pair<uint64_t, int32_t> &b) {
+                             return a.first < b.first;
+                         });
+        std::vector<double> px((size_t)m), py((size_t)m);
+        std::vector<int32_t> pm((size_t)m);
+        for (int64_t i = 0; i < m; ++i) {
+            pm[i] = key[i].second;
+            px[i] = hx[pm[i]];
+            py[i] = hy[pm[i]];
+        }
+        e = hipMemcpyAsync(P->tx, px.data(), sizeof(double) * m, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(P->ty, py.data(), sizeof(double) * m, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(P->perm, pm.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) {
             mhlp_plan_destroy(P);
             return fail(MHLP_HIP_ERROR, std::string("plan_create copy: ") + hipGetErrorString(e));
@@ -1209,6 +1261,7 @@ static mhlp_status launch_far(const mhlp_plan *P, const double *sigma, const dou
     A.part_d = P->part + (int64_t)P->nsplit * P->M;
     A.gs = gs;
     A.jstride = jstride;
+    A.perm = P->perm;
     if (sigma && mu)
         launch_far_t<true, true>(A, P->nsplit, precision, st);
     else if (sigma)
