@@ -1808,13 +1808,34 @@ __device__ __forceinline__ bool batch_gated_off(const double *__restrict__ gate,
     return true;
 }
 
+/* Device state of a lockstep batched GMRES cycle. */
+struct BState {
+    int32_t j;     /* current Arnoldi column (common to all systems)         */
+    int32_t kmax;  /* columns allowed in this cycle                          */
+    int32_t done;  /* all systems converged / broken down, or kmax reached   */
+    int32_t nact;  /* systems still active after the last step               */
+    int32_t steps; /* lockstep steps taken in this cycle                     */
+    int32_t pad[3];
+};
+
+/* density of a batched launch: fixed, or basis column bs->j; false = no-op */
+__device__ __forceinline__ bool batch_density(const BState *bs, int64_t jstride, const double *__restrict__ &mu)
+{
+    if (bs) {
+        if (bs->done) return false;
+        mu += (int64_t)bs->j * jstride;
+    }
+    return true;
+}
+
 template <int R>
 __global__ __launch_bounds__(FT_THREADS) void batch_far_dlp(const BatchGeo *__restrict__ G,
                                                             const BatchWork *__restrict__ W,
                                                             const double *__restrict__ mu, double *__restrict__ part,
-                                                            const double *__restrict__ gate)
+                                                            const double *__restrict__ gate, const BState *bs,
+                                                            int64_t jstride)
 {
-    if (batch_gated_off<R>(gate, W[blockIdx.x].g)) return;
+    if (batch_gated_off<R>(gate, W[blockIdx.x].g) || !batch_density(bs, jstride, mu)) return;
     __shared__ double lx[FT_SRC], ly[FT_SRC];
     __shared__ double ldx[R][FT_SRC], ldy[R][FT_SRC];
     const BatchWork wk = W[blockIdx.x];
@@ -1884,9 +1905,10 @@ __global__ __launch_bounds__(FT_THREADS) void batch_far_dlp(const BatchGeo *__re
 template <int R>
 __global__ void batch_finalize(const BatchGeo *__restrict__ G, const BatchWork *__restrict__ W,
                                const double *__restrict__ part, const double *__restrict__ mu,
-                               double *__restrict__ out, const double *__restrict__ gate)
+                               double *__restrict__ out, const double *__restrict__ gate, const BState *bs,
+                               int64_t jstride)
 {
-    if (batch_gated_off<R>(gate, W[blockIdx.x].g)) return;
+    if (batch_gated_off<R>(gate, W[blockIdx.x].g) || !batch_density(bs, jstride, mu)) return;
     const BatchWork wk = W[blockIdx.x];
     const BatchGeo geo = G[wk.g];
     const int64_t i = (int64_t)wk.tb * FT_THREADS + threadIdx.x;
@@ -1960,6 +1982,143 @@ __global__ void bscale_kernel(const double *__restrict__ in, const double *__res
     out[off[s] + i] = scale[s] * in[off[s] + i];
 }
 
+/* ---- device-driven lockstep GMRES over the batch (no-ops once done; a
+   system with gate[s] == 0 has converged in this cycle and is skipped) ---- */
+__global__ __launch_bounds__(256) void bdot_dev_kernel(const BState *__restrict__ bs, const double *__restrict__ V,
+                                                       int64_t ld, const double *__restrict__ w,
+                                                       const int64_t *__restrict__ off,
+                                                       const int64_t *__restrict__ n, int ldh,
+                                                       double *__restrict__ out, const double *__restrict__ gate)
+{
+    const int s = blockIdx.x, c = blockIdx.y;
+    if (bs->done || c > bs->j || gate[s] == 0.0) return;
+    __shared__ double red[256];
+    const double *v = V + c * ld + off[s];
+    const double *ww = w + off[s];
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < n[s]; i += 256) acc = fma(v[i], ww[i], acc);
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[(int64_t)s * ldh + c] = red[0];
+}
+
+/* w_s -= sum_{c<=j} h[s][c] V_c */
+__global__ void bsub_dev_kernel(const BState *__restrict__ bs, const double *__restrict__ V, int64_t ld,
+                                const double *__restrict__ h, int ldh, double *__restrict__ w,
+                                const int64_t *__restrict__ off, const int64_t *__restrict__ n,
+                                const double *__restrict__ gate)
+{
+    const int s = blockIdx.y;
+    if (bs->done || gate[s] == 0.0) return;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n[s]) return;
+    const int nc = bs->j + 1;
+    const int64_t e = off[s] + i;
+    double acc = w[e];
+    for (int c = 0; c < nc; ++c) acc = fma(-h[(int64_t)s * ldh + c], V[c * ld + e], acc);
+    w[e] = acc;
+}
+
+/* Hessenberg column j of every active system, its Givens rotations, the
+   rotated right-hand side and the per-system stopping test; gate[s] becomes
+   1/h_{j+1,j} (next basis vector scale) or 0 (converged).  One block. */
+__global__ __launch_bounds__(256) void bfinish_kernel(BState *__restrict__ bs, int S, int m, int ldh,
+                                                      double *__restrict__ H, double *__restrict__ cs,
+                                                      double *__restrict__ sn, double *__restrict__ gv,
+                                                      const double *__restrict__ h1, const double *__restrict__ h2,
+                                                      const double *__restrict__ hn, const double *__restrict__ thresh,
+                                                      double *__restrict__ resest, double *__restrict__ gate,
+                                                      int32_t *__restrict__ dk)
+{
+    __shared__ int cnt[256];
+    const bool skip = bs->done != 0;
+    const int k = bs->j;
+    int mine = 0;
+    if (!skip) {
+        for (int s = threadIdx.x; s < S; s += 256) {
+            if (gate[s] == 0.0) continue;
+            double *Hs = H + (int64_t)s * (m + 1) * m, *c_ = cs + (int64_t)s * m, *s_ = sn + (int64_t)s * m;
+            double *g_ = gv + (int64_t)s * (m + 1);
+            for (int j = 0; j <= k; ++j) Hs[(int64_t)j * m + k] = h1[(int64_t)s * ldh + j] + h2[(int64_t)s * ldh + j];
+            const double hk = sqrt(hn[(int64_t)s * ldh]);
+            Hs[(int64_t)(k + 1) * m + k] = hk;
+            for (int j = 0; j < k; ++j) {
+                const double a = Hs[(int64_t)j * m + k], c = Hs[(int64_t)(j + 1) * m + k];
+                Hs[(int64_t)j * m + k] = c_[j] * a + s_[j] * c;
+                Hs[(int64_t)(j + 1) * m + k] = -s_[j] * a + c_[j] * c;
+            }
+            const double a = Hs[(int64_t)k * m + k], c = Hs[(int64_t)(k + 1) * m + k];
+            const double den = hypot(a, c);
+            c_[k] = den > 0.0 ? a / den : 1.0;
+            s_[k] = den > 0.0 ? c / den : 0.0;
+            Hs[(int64_t)k * m + k] = den;
+            Hs[(int64_t)(k + 1) * m + k] = 0.0;
+            g_[k + 1] = -s_[k] * g_[k];
+            g_[k] = c_[k] * g_[k];
+            dk[s] = k + 1;
+            resest[s] = fabs(g_[k + 1]);
+            if (resest[s] <= thresh[s] || hk == 0.0) {
+                gate[s] = 0.0;
+            } else {
+                gate[s] = 1.0 / hk;
+                ++mine;
+            }
+        }
+    }
+    cnt[threadIdx.x] = mine;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) cnt[threadIdx.x] += cnt[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && !skip) {
+        bs->nact = cnt[0];
+        bs->steps = k + 1;
+        if (cnt[0] == 0 || k + 1 >= bs->kmax) bs->done = 1;
+    }
+}
+
+/* V_{j+1, s} = gate[s] * w_s */
+__global__ void bscale_dev_kernel(const BState *__restrict__ bs, const double *__restrict__ w,
+                                  const double *__restrict__ gate, double *__restrict__ V, int64_t ld,
+                                  const int64_t *__restrict__ off, const int64_t *__restrict__ n)
+{
+    const int s = blockIdx.y;
+    if (bs->done) return;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n[s]) return;
+    V[(int64_t)(bs->j + 1) * ld + off[s] + i] = gate[s] * w[off[s] + i];
+}
+
+__global__ void badvance_kernel(BState *__restrict__ bs)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0 && !bs->done) bs->j += 1;
+}
+
+/* y_s = R^{-1} g_s over the dk[s] leading columns; one wave per system */
+__global__ __launch_bounds__(64) void bsolve_kernel(int m, int ldh, const double *__restrict__ H,
+                                                    const double *__restrict__ gv, const int32_t *__restrict__ dk,
+                                                    double *__restrict__ y)
+{
+    const int s = blockIdx.x, k = dk[s];
+    const double *Hs = H + (int64_t)s * (m + 1) * m, *g_ = gv + (int64_t)s * (m + 1);
+    double *y_ = y + (int64_t)s * ldh;
+    for (int i = k - 1; i >= 0; --i) {
+        double acc = 0.0;
+        for (int c = i + 1 + (int)threadIdx.x; c < k; c += 64) acc = fma(Hs[(int64_t)i * m + c], y_[c], acc);
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+        if (threadIdx.x == 0) {
+            const double d = Hs[(int64_t)i * m + i];
+            y_[i] = d != 0.0 ? (g_[i] - acc) / d : 0.0;
+        }
+        __syncthreads();
+    }
+}
+
 struct mhlp_batch {
     int n_geom = 0, R = 0, S = 0;
     int64_t total = 0, max_n = 0;
@@ -1978,6 +2137,15 @@ struct mhlp_batch {
     int ldh = 0;
     std::vector<BatchGeo> hgeo; /* host copy of the per-geometry descriptors */
     int64_t target = 0;         /* block target of the current work list    */
+    /* device-driven GMRES: state, per-system Hessenberg data, step graphs */
+    char *gd = nullptr;         /* BState, H, cs, sn, gv, y, thresh, resest  */
+    char *hpin = nullptr;       /* pinned: BState + resest (down), gv + thresh (up) */
+    hipStream_t cap_stream = nullptr;
+    struct StepGraph {
+        hipGraphExec_t exec = nullptr;
+        const void *V = nullptr, *work = nullptr, *part = nullptr, *gd = nullptr;
+        int m = 0, S = 0;
+    } graphs[4];
 };
 
 static mhlp_status batch_build_work(mhlp_batch *B, int64_t target, hipStream_t st);
@@ -1985,10 +2153,15 @@ static mhlp_status batch_build_work(mhlp_batch *B, int64_t target, hipStream_t s
 extern "C" mhlp_status mhlp_batch_destroy(mhlp_batch *B)
 {
     if (!B) return MHLP_OK;
-    void *ptrs[] = {B->dgeo, B->dwork, B->dfin, B->part, B->doff, B->dn, B->V, B->w, B->r, B->dh, B->dsc, B->dk};
+    for (auto &gr : B->graphs)
+        if (gr.exec) (void)hipGraphExecDestroy(gr.exec);
+    if (B->cap_stream) (void)hipStreamDestroy(B->cap_stream);
+    void *ptrs[] = {B->dgeo, B->dwork, B->dfin, B->part, B->doff, B->dn, B->V,
+                    B->w,    B->r,     B->dh,   B->dsc,  B->dk,   B->gd};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (B->hh) (void)hipHostFree(B->hh);
+    if (B->hpin) (void)hipHostFree(B->hpin);
     delete B;
     return MHLP_OK;
 }
@@ -2118,22 +2291,25 @@ extern "C" mhlp_status mhlp_batch_info(const mhlp_batch *B, int64_t *total_len, 
 }
 
 template <int R>
-static void batch_apply_t(const mhlp_batch *B, const double *mu, double *out, const double *gate, hipStream_t st)
+static void batch_apply_t(const mhlp_batch *B, const double *mu, double *out, const double *gate,
+                          const BState *bs, int64_t jstride, hipStream_t st)
 {
-    batch_far_dlp<R><<<(unsigned)B->nwork, FT_THREADS, 0, st>>>(B->dgeo, B->dwork, mu, B->part, gate);
-    batch_finalize<R><<<(unsigned)B->nfin, FT_THREADS, 0, st>>>(B->dgeo, B->dfin, B->part, mu, out, gate);
+    batch_far_dlp<R><<<(unsigned)B->nwork, FT_THREADS, 0, st>>>(B->dgeo, B->dwork, mu, B->part, gate, bs, jstride);
+    batch_finalize<R><<<(unsigned)B->nfin, FT_THREADS, 0, st>>>(B->dgeo, B->dfin, B->part, mu, out, gate, bs,
+                                                                  jstride);
 }
 
 /* out = (1/2 I + D) mu for every system; with a gate, geometries whose
-   systems are all gated off are skipped (their part of out is left as is) */
+   systems are all gated off are skipped (their part of out is left as is);
+   with a GMRES state, mu is the basis and column bs->j is applied */
 static mhlp_status batch_apply_impl(const mhlp_batch *B, const double *mu, double *out, hipStream_t st,
-                                    const double *gate = nullptr)
+                                    const double *gate = nullptr, const BState *bs = nullptr, int64_t jstride = 0)
 {
     switch (B->R) {
-    case 1: batch_apply_t<1>(B, mu, out, gate, st); break;
-    case 2: batch_apply_t<2>(B, mu, out, gate, st); break;
-    case 3: batch_apply_t<3>(B, mu, out, gate, st); break;
-    default: batch_apply_t<4>(B, mu, out, gate, st); break;
+    case 1: batch_apply_t<1>(B, mu, out, gate, bs, jstride, st); break;
+    case 2: batch_apply_t<2>(B, mu, out, gate, bs, jstride, st); break;
+    case 3: batch_apply_t<3>(B, mu, out, gate, bs, jstride, st); break;
+    default: batch_apply_t<4>(B, mu, out, gate, bs, jstride, st); break;
     }
     HIPCHECK(hipGetLastError());
     return MHLP_OK;
@@ -2191,6 +2367,99 @@ extern "C" mhlp_status mhlp_batch_autotune(mhlp_batch *B, int32_t reps, void *st
     return MHLP_OK;
 }
 
+/* Device data of the batched GMRES for restart m (layout stride B->m). */
+struct BDev {
+    BState *bs;
+    double *H, *cs, *sn, *gv, *y, *thresh, *resest;
+};
+
+static BDev bdev_view(const mhlp_batch *B)
+{
+    const int64_t S = B->S, m = B->m, ldh = B->ldh;
+    BDev d;
+    d.bs = reinterpret_cast<BState *>(B->gd);
+    double *p = reinterpret_cast<double *>(B->gd + 64);
+    d.H = p;
+    p += S * (m + 1) * m;
+    d.cs = p;
+    p += S * m;
+    d.sn = p;
+    p += S * m;
+    d.gv = p;
+    p += S * (m + 1);
+    d.y = p;
+    p += S * ldh;
+    d.thresh = p;
+    p += S;
+    d.resest = p;
+    return d;
+}
+
+/* one lockstep Arnoldi step of every active system, enqueued on st */
+static mhlp_status enqueue_bstep(mhlp_batch *B, hipStream_t st)
+{
+    const int S = B->S, m = B->m, ldh = B->ldh;
+    const int64_t T = B->total;
+    const BDev d = bdev_view(B);
+    double *h1 = B->dh, *h2 = B->dh + (int64_t)S * ldh, *hn = B->dh + 2 * (int64_t)S * ldh;
+    const dim3 gS((unsigned)((B->max_n + 255) / 256), (unsigned)S);
+    TRY(batch_apply_impl(B, B->V, B->w, st, B->dsc, d.bs, T));
+    bdot_dev_kernel<<<dim3((unsigned)S, (unsigned)m), 256, 0, st>>>(d.bs, B->V, T, B->w, B->doff, B->dn, ldh, h1,
+                                                                     B->dsc);
+    bsub_dev_kernel<<<gS, 256, 0, st>>>(d.bs, B->V, T, h1, ldh, B->w, B->doff, B->dn, B->dsc);
+    bdot_dev_kernel<<<dim3((unsigned)S, (unsigned)m), 256, 0, st>>>(d.bs, B->V, T, B->w, B->doff, B->dn, ldh, h2,
+                                                                     B->dsc);
+    bsub_dev_kernel<<<gS, 256, 0, st>>>(d.bs, B->V, T, h2, ldh, B->w, B->doff, B->dn, B->dsc);
+    bdot_dev_kernel<<<dim3((unsigned)S, 1), 256, 0, st>>>(d.bs, B->w, 0, B->w, B->doff, B->dn, ldh, hn, B->dsc);
+    bfinish_kernel<<<1, 256, 0, st>>>(d.bs, S, m, ldh, d.H, d.cs, d.sn, d.gv, h1, h2, hn, d.thresh, d.resest, B->dsc,
+                                      B->dk);
+    bscale_dev_kernel<<<gS, 256, 0, st>>>(d.bs, B->w, B->dsc, B->V, T, B->doff, B->dn);
+    badvance_kernel<<<1, 64, 0, st>>>(d.bs);
+    HIPCHECK(hipGetLastError());
+    return MHLP_OK;
+}
+
+/* executable graph of 2^si lockstep steps, captured once per batch state */
+static mhlp_status bstep_graph(mhlp_batch *B, int si, hipGraphExec_t *out)
+{
+    const int S = 1 << si;
+    mhlp_batch::StepGraph &G = B->graphs[si];
+    if (G.exec && G.V == B->V && G.work == B->dwork && G.part == B->part && G.gd == B->gd && G.m == B->m &&
+        G.S == S) {
+        *out = G.exec;
+        return MHLP_OK;
+    }
+    if (G.exec) {
+        (void)hipGraphExecDestroy(G.exec);
+        G.exec = nullptr;
+    }
+    if (!B->cap_stream) HIPCHECK(hipStreamCreateWithFlags(&B->cap_stream, hipStreamNonBlocking));
+    HIPCHECK(hipStreamBeginCapture(B->cap_stream, hipStreamCaptureModeThreadLocal));
+    mhlp_status s = MHLP_OK;
+    for (int k = 0; k < S && s == MHLP_OK; ++k) s = enqueue_bstep(B, B->cap_stream);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(B->cap_stream, &graph);
+    if (s != MHLP_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return s;
+    }
+    if (e != hipSuccess) return fail(MHLP_HIP_ERROR, std::string("batch step capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        G.exec = nullptr;
+        return fail(MHLP_HIP_ERROR, std::string("batch step graph: ") + hipGetErrorString(e));
+    }
+    G.V = B->V;
+    G.work = B->dwork;
+    G.part = B->part;
+    G.gd = B->gd;
+    G.m = B->m;
+    G.S = S;
+    *out = G.exec;
+    return MHLP_OK;
+}
+
 extern "C" mhlp_status mhlp_batch_gmres_solve(mhlp_batch *B, const double *g, double *mu, const mhlp_gmres_opts *opts,
                                               mhlp_gmres_info *infos, void *stream)
 {
@@ -2199,39 +2468,52 @@ extern "C" mhlp_status mhlp_batch_gmres_solve(mhlp_batch *B, const double *g, do
     if (opts->precision != MHLP_FP64) return fail(MHLP_UNSUPPORTED, "batched GMRES runs in FP64");
     hipStream_t st = (hipStream_t)stream;
     const int S = B->S;
-    const int m = std::min(opts->restart, 64);
+    const int mreq = std::min(opts->restart, 64);
     const int64_t T = B->total;
-    if (B->m < m) {
-        void *ptrs[] = {B->V, B->w, B->r, B->dh, B->dsc, B->dk};
+    if (B->m < mreq) {
+        HIPCHECK(hipDeviceSynchronize());
+        void *ptrs[] = {B->V, B->w, B->r, B->dh, B->dsc, B->dk, B->gd};
         for (void *p : ptrs)
             if (p) (void)hipFree(p);
         if (B->hh) (void)hipHostFree(B->hh);
+        if (B->hpin) (void)hipHostFree(B->hpin);
         B->V = B->w = B->r = B->dh = B->dsc = nullptr;
         B->dk = nullptr;
+        B->gd = nullptr;
         B->hh = nullptr;
+        B->hpin = nullptr;
+        const int m = mreq;
         B->ldh = m + 2;
+        B->m = m;
+        const int64_t ngd = (int64_t)S * (m + 1) * m + 2 * (int64_t)S * m + (int64_t)S * (m + 1) +
+                            (int64_t)S * B->ldh + 2 * (int64_t)S;
         TRY(dalloc(&B->V, (int64_t)(m + 1) * T));
         TRY(dalloc(&B->w, T));
         TRY(dalloc(&B->r, T));
         TRY(dalloc(&B->dh, 3 * (int64_t)S * B->ldh));
         TRY(dalloc(&B->dsc, S));
         TRY(dalloc(&B->dk, S));
+        TRY(dalloc(&B->gd, 64 + 8 * ngd));
         HIPCHECK(hipHostMalloc((void **)&B->hh, sizeof(double) * 3 * (size_t)S * B->ldh, hipHostMallocDefault));
-        B->m = m;
+        HIPCHECK(hipHostMalloc((void **)&B->hpin, 64 + sizeof(double) * ((size_t)S * (m + 3) + S), hipHostMallocDefault));
     }
-    const int ldh = B->ldh;
+    const int m = B->m, ldh = B->ldh;
+    const int mcyc = std::min(opts->restart, m);
+    const BDev d = bdev_view(B);
     const dim3 gS((unsigned)((B->max_n + 255) / 256), (unsigned)S);
-    double *h1 = B->dh, *h2 = B->dh + (int64_t)S * ldh, *hn = B->dh + 2 * (int64_t)S * ldh;
-    std::vector<double> bn(S), rel(S, 1.0), x0res(S, 1.0), H((size_t)S * (m + 1) * m), cs((size_t)S * m),
-        sn((size_t)S * m), gv((size_t)S * (m + 1)), yv((size_t)S * ldh, 0.0), sc(S);
-    std::vector<int32_t> kdone(S), iters(S, 0), cyc(S, 0);
-    std::vector<char> conv(S, 0), active(S, 0);
+    double *hn = B->dh + 2 * (int64_t)S * ldh;
+    BState *bsh = reinterpret_cast<BState *>(B->hpin);
+    double *res_h = reinterpret_cast<double *>(B->hpin + 64);    /* [S] resest, device -> host */
+    double *up_h = res_h + S;                                     /* [S][m+1] gv then [S] thresh  */
+    std::vector<double> bn(S), rel(S, 1.0), x0res(S, 1.0), sc(S), last(S);
+    std::vector<int32_t> iters(S, 0), cyc(S, 0), kk(S);
+    std::vector<char> conv(S, 0);
     auto norms = [&](const double *v, std::vector<double> &outv) -> mhlp_status {
         bdot_kernel<<<dim3((unsigned)S, 1), 256, 0, st>>>(v, 0, v, B->doff, B->dn, ldh, hn);
         HIPCHECK(hipGetLastError());
         HIPCHECK(hipMemcpyAsync(B->hh, hn, sizeof(double) * (size_t)S * ldh, hipMemcpyDeviceToHost, st));
         HIPCHECK(hipStreamSynchronize(st));
-        for (int s = 0; s < S; ++s) outv[s] = std::sqrt(B->hh[(size_t)s * ldh]);
+        for (int s2 = 0; s2 < S; ++s2) outv[s2] = std::sqrt(B->hh[(size_t)s2 * ldh]);
         return MHLP_OK;
     };
     TRY(norms(g, bn));
@@ -2242,10 +2524,10 @@ extern "C" mhlp_status mhlp_batch_gmres_solve(mhlp_batch *B, const double *g, do
         residual_kernel<<<nblocks(T, 256), 256, 0, st>>>(g, B->w, B->r, T);
         TRY(norms(B->r, rn));
         bool any_bad = false;
-        for (int s = 0; s < S; ++s) {
-            x0res[s] = bn[s] > 0 ? rn[s] / bn[s] : 0.0;
-            sc[s] = (x0res[s] < 1.0) ? 1.0 : 0.0;
-            any_bad |= sc[s] == 0.0;
+        for (int s2 = 0; s2 < S; ++s2) {
+            x0res[s2] = bn[s2] > 0 ? rn[s2] / bn[s2] : 0.0;
+            sc[s2] = (x0res[s2] < 1.0) ? 1.0 : 0.0;
+            any_bad |= sc[s2] == 0.0;
         }
         if (any_bad) {
             HIPCHECK(hipMemcpyAsync(B->dsc, sc.data(), sizeof(double) * S, hipMemcpyHostToDevice, st));
@@ -2260,102 +2542,73 @@ extern "C" mhlp_status mhlp_batch_gmres_solve(mhlp_batch *B, const double *g, do
         residual_kernel<<<nblocks(T, 256), 256, 0, st>>>(g, B->w, B->r, T);
         TRY(norms(B->r, rn));
         int nact = 0;
-        for (int s = 0; s < S; ++s) {
-            rel[s] = bn[s] > 0 ? rn[s] / bn[s] : 0.0;
-            conv[s] = rel[s] <= opts->tol;
-            active[s] = !conv[s];
-            nact += active[s];
-            sc[s] = active[s] ? 1.0 / rn[s] : 0.0;
-            kdone[s] = 0;
-            std::fill(&gv[(size_t)s * (m + 1)], &gv[(size_t)s * (m + 1)] + m + 1, 0.0);
-            gv[(size_t)s * (m + 1)] = rn[s];
+        for (int s2 = 0; s2 < S; ++s2) {
+            rel[s2] = bn[s2] > 0 ? rn[s2] / bn[s2] : 0.0;
+            conv[s2] = rel[s2] <= opts->tol;
+            sc[s2] = conv[s2] ? 0.0 : 1.0 / rn[s2];
+            nact += !conv[s2];
+            cyc[s2] += !conv[s2];
+            last[s2] = rn[s2];
         }
         if (nact == 0 || total_it >= opts->max_iter) break;
+        /* cycle start: V_0 = r / ||r||, g = ||r|| e_1, thresholds, state */
+        for (int s2 = 0; s2 < S; ++s2) {
+            double *gs_ = up_h + (size_t)s2 * (m + 1);
+            std::fill(gs_, gs_ + m + 1, 0.0);
+            gs_[0] = rn[s2];
+            up_h[(size_t)S * (m + 1) + s2] = 0.5 * opts->tol * bn[s2];
+        }
+        *bsh = BState{0, std::min(mcyc, opts->max_iter - total_it), 0, nact, 0, {0, 0, 0}};
         HIPCHECK(hipMemcpyAsync(B->dsc, sc.data(), sizeof(double) * S, hipMemcpyHostToDevice, st));
         bscale_kernel<<<gS, 256, 0, st>>>(B->r, B->dsc, B->V, B->doff, B->dn);
-        for (int s = 0; s < S; ++s) cyc[s] += active[s];
-        int k = 0;
-        for (; k < m && total_it < opts->max_iter; ++k) {
-            ++total_it;
-            double *Vk = B->V + (int64_t)k * T;
-            /* B->dsc holds 1/||.|| of the systems still active at this step, 0 for
-               the others: converged geometries skip the operator application */
-            TRY(batch_apply_impl(B, Vk, B->w, st, B->dsc));
-            bdot_kernel<<<dim3((unsigned)S, (unsigned)(k + 1)), 256, 0, st>>>(B->V, T, B->w, B->doff, B->dn, ldh, h1);
-            bcombo_kernel<<<gS, 256, 0, st>>>(B->V, T, k + 1, nullptr, h1, ldh, -1.0, B->w, B->doff, B->dn);
-            bdot_kernel<<<dim3((unsigned)S, (unsigned)(k + 1)), 256, 0, st>>>(B->V, T, B->w, B->doff, B->dn, ldh, h2);
-            bcombo_kernel<<<gS, 256, 0, st>>>(B->V, T, k + 1, nullptr, h2, ldh, -1.0, B->w, B->doff, B->dn);
-            bdot_kernel<<<dim3((unsigned)S, 1), 256, 0, st>>>(B->w, 0, B->w, B->doff, B->dn, ldh, hn);
-            HIPCHECK(hipGetLastError());
-            HIPCHECK(hipMemcpyAsync(B->hh, B->dh, sizeof(double) * 3 * (size_t)S * ldh, hipMemcpyDeviceToHost, st));
-            HIPCHECK(hipStreamSynchronize(st));
-            int still = 0;
-            for (int s = 0; s < S; ++s) {
-                sc[s] = 0.0;
-                if (!active[s]) continue;
-                ++iters[s];
-                double *Hs = &H[(size_t)s * (m + 1) * m];
-                for (int j = 0; j <= k; ++j)
-                    Hs[(size_t)j * m + k] = B->hh[(size_t)s * ldh + j] + B->hh[(size_t)(S + s) * ldh + j];
-                const double hk = std::sqrt(B->hh[(size_t)(2 * S + s) * ldh]);
-                Hs[(size_t)(k + 1) * m + k] = hk;
-                double *c_ = &cs[(size_t)s * m], *s_ = &sn[(size_t)s * m], *g_ = &gv[(size_t)s * (m + 1)];
-                for (int j = 0; j < k; ++j) {
-                    const double a = Hs[(size_t)j * m + k], c = Hs[(size_t)(j + 1) * m + k];
-                    Hs[(size_t)j * m + k] = c_[j] * a + s_[j] * c;
-                    Hs[(size_t)(j + 1) * m + k] = -s_[j] * a + c_[j] * c;
-                }
-                const double a = Hs[(size_t)k * m + k], c = Hs[(size_t)(k + 1) * m + k];
-                const double den = std::hypot(a, c);
-                c_[k] = den > 0 ? a / den : 1.0;
-                s_[k] = den > 0 ? c / den : 0.0;
-                Hs[(size_t)k * m + k] = den;
-                Hs[(size_t)(k + 1) * m + k] = 0.0;
-                g_[k + 1] = -s_[k] * g_[k];
-                g_[k] = c_[k] * g_[k];
-                kdone[s] = k + 1;
-                if (std::fabs(g_[k + 1]) <= 0.5 * opts->tol * bn[s] || hk == 0.0) {
-                    active[s] = 0;
-                } else {
-                    sc[s] = 1.0 / hk;
-                    ++still;
-                }
-            }
-            HIPCHECK(hipMemcpyAsync(B->dsc, sc.data(), sizeof(double) * S, hipMemcpyHostToDevice, st));
-            bscale_kernel<<<gS, 256, 0, st>>>(B->w, B->dsc, B->V + (int64_t)(k + 1) * T, B->doff, B->dn);
-            if (still == 0) {
-                ++k;
-                break;
-            }
-        }
-        /* per-system back substitution and update x += V y */
-        for (int s = 0; s < S; ++s) {
-            const int ks = kdone[s];
-            const double *Hs = &H[(size_t)s * (m + 1) * m];
-            const double *g_ = &gv[(size_t)s * (m + 1)];
-            double *y_ = &yv[(size_t)s * ldh];
-            for (int i2 = ks - 1; i2 >= 0; --i2) {
-                double acc = g_[i2];
-                for (int j = i2 + 1; j < ks; ++j) acc -= Hs[(size_t)i2 * m + j] * y_[j];
-                y_[i2] = Hs[(size_t)i2 * m + i2] != 0.0 ? acc / Hs[(size_t)i2 * m + i2] : 0.0;
-            }
-        }
-        std::vector<int32_t> kk(kdone.begin(), kdone.end());
-        HIPCHECK(hipMemcpyAsync(h1, yv.data(), sizeof(double) * (size_t)S * ldh, hipMemcpyHostToDevice, st));
-        HIPCHECK(hipMemcpyAsync(B->dk, kk.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice, st));
-        bcombo_kernel<<<gS, 256, 0, st>>>(B->V, T, 0, B->dk, h1, ldh, 1.0, mu, B->doff, B->dn);
+        HIPCHECK(hipMemcpyAsync(d.gv, up_h, sizeof(double) * (size_t)S * (m + 1), hipMemcpyHostToDevice, st));
+        HIPCHECK(hipMemcpyAsync(d.thresh, up_h + (size_t)S * (m + 1), sizeof(double) * S, hipMemcpyHostToDevice, st));
+        HIPCHECK(hipMemcpyAsync(d.bs, bsh, sizeof(BState), hipMemcpyHostToDevice, st));
+        fill_i32_kernel<<<nblocks(S, 256), 256, 0, st>>>(B->dk, 0, S);
         HIPCHECK(hipGetLastError());
-        HIPCHECK(hipStreamSynchronize(st));
+        int chunk = 2, done_steps = 0;
+        for (;;) {
+            int si = 0;
+            while ((1 << si) < chunk && si < 3) ++si;
+            hipGraphExec_t ex;
+            TRY(bstep_graph(B, si, &ex));
+            HIPCHECK(hipGraphLaunch(ex, st));
+            HIPCHECK(hipMemcpyAsync(bsh, d.bs, sizeof(BState), hipMemcpyDeviceToHost, st));
+            HIPCHECK(hipMemcpyAsync(res_h, d.resest, sizeof(double) * S, hipMemcpyDeviceToHost, st));
+            HIPCHECK(hipStreamSynchronize(st));
+            if (bsh->done) break;
+            /* steps the slowest active system still needs at its observed rate */
+            const int ran = bsh->steps - done_steps;
+            done_steps = bsh->steps;
+            int need = 1;
+            for (int s2 = 0; s2 < S; ++s2) {
+                if (sc[s2] == 0.0) continue;
+                const double th = 0.5 * opts->tol * bn[s2], est = res_h[s2];
+                if (est <= th) continue;
+                int ns2 = 8;
+                if (ran > 0 && est > 0.0 && est < last[s2])
+                    ns2 = (int)std::ceil(std::log(th / est) / std::log(std::pow(est / last[s2], 1.0 / ran)));
+                need = std::max(need, ns2);
+                last[s2] = est;
+            }
+            chunk = std::max(1, std::min(need, 8));
+        }
+        total_it += bsh->steps;
+        HIPCHECK(hipMemcpy(kk.data(), B->dk, sizeof(int32_t) * S, hipMemcpyDeviceToHost));
+        for (int s2 = 0; s2 < S; ++s2) iters[s2] += kk[s2];
+        bsolve_kernel<<<(unsigned)S, 64, 0, st>>>(m, ldh, d.H, d.gv, B->dk, d.y);
+        bcombo_kernel<<<gS, 256, 0, st>>>(B->V, T, 0, B->dk, d.y, ldh, 1.0, mu, B->doff, B->dn);
+        HIPCHECK(hipGetLastError());
     }
     bool all = true;
-    for (int s = 0; s < S; ++s) {
-        infos[s].iters = iters[s];
-        infos[s].restarts = cyc[s];
-        infos[s].rel_residual = rel[s];
-        infos[s].x0_residual = opts->use_x0 ? x0res[s] : 1.0;
-        infos[s].converged = conv[s];
-        infos[s].used_x0 = opts->use_x0 ? (x0res[s] < 1.0) : 0;
-        all &= conv[s] != 0;
+    for (int s2 = 0; s2 < S; ++s2) {
+        infos[s2].iters = iters[s2];
+        infos[s2].restarts = cyc[s2];
+        infos[s2].rel_residual = rel[s2];
+        infos[s2].x0_residual = opts->use_x0 ? x0res[s2] : 1.0;
+        infos[s2].converged = conv[s2];
+        infos[s2].used_x0 = opts->use_x0 ? (x0res[s2] < 1.0) : 0;
+        all &= conv[s2] != 0;
     }
     return all ? MHLP_OK : MHLP_NOT_CONVERGED;
 }

@@ -309,3 +309,40 @@ def test_batch_gmres_matches_single():
             # both solutions have residual <= 1e-10; condition of (1/2 I + D) is O(1)
             assert _relerr(sols[k].cpu().numpy(), ref.cpu().numpy()) < 1e-9
             k += 1
+
+
+@pytest.mark.parametrize("restart", [2, 5])
+def test_batch_gmres_restarts_and_warm_start(restart):
+    """Several restart cycles of the lockstep solve, then a warm start in which
+    one system's guess is rejected (replaced by zero) and the others are kept."""
+    rng = np.random.default_rng(19)
+    geoms = _batch_geoms()
+    plans = [mhlp.Plan(_geom(g), a) for g, a in geoms]
+    B = mhlp.Batch(plans, 2)
+    rhs = []
+    for (g, a) in geoms:
+        for r in range(2):
+            rhs.append(_t(wl.fourier_density(g.theta, wl.random_fourier_coeffs(rng, 8))))
+    gb = B.pack(rhs)
+    mu, infos = B.gmres(gb, tol=1e-10, restart=restart, max_iter=400)
+    sols = B.unpack(mu)
+    refs = []
+    k = 0
+    for p in plans:
+        for r in range(2):
+            assert infos[k]["converged"] and infos[k]["rel_residual"] <= 1e-10, infos[k]
+            if restart == 2:
+                assert infos[k]["restarts"] >= 1
+            ref, _ = mhlp.gmres_solve(p, rhs[k], tol=1e-10)
+            refs.append(ref)
+            assert _relerr(sols[k].cpu().numpy(), ref.cpu().numpy()) < 1e-9
+            k += 1
+    guesses = [0.999 * x for x in refs]
+    guesses[3] = 1e6 * torch.ones_like(refs[3])
+    mu2, infos2 = B.gmres(gb, x0=B.pack(guesses), tol=1e-10, restart=restart, max_iter=400)
+    sols2 = B.unpack(mu2)
+    for k in range(len(rhs)):
+        assert infos2[k]["converged"] and infos2[k]["rel_residual"] <= 1e-10
+        assert infos2[k]["used_x0"] == (0 if k == 3 else 1)
+        assert _relerr(sols2[k].cpu().numpy(), refs[k].cpu().numpy()) < 1e-9
+    assert max(i["iters"] for i in infos2) <= max(i["iters"] for i in infos)
