@@ -31,13 +31,13 @@ sys.path.insert(0, ROOT)
 METRIC = "GPair-evals/s (SLP+DLP) and GMRES time-to-1e-10, mixed/batched/warm vs FP64"
 FP64_PEAK_TFLOPS = 78.6        # MI355X vector FP64 (published)
 # FP64 operations per (target, source) pair of the fused SLP+DLP far-field
-# kernel on its z > 2 branch, counted from the instructions of the built kernel
-# (two pairs per loop trip): 69 v_fma (x2), 18 v_mul, 2 v_add, 2 v_rsq (x1)
-# = 160; not counted: 1 v_rndne, 1 v_ldexp, 1 v_cvt (exponent handling of
-# exp(-z)).  By function: r^2 and differences 5, 1/r 9, exp(-z) 33,
-# 1/sqrt(z) 9, K0 fit with derivative 86-88, K1 and scalings ~14, both
-# accumulations 7.
-FLOP_PER_PAIR_FP64 = 160
+# kernel on its z > 6 branch, counted from the instructions of the built kernel
+# (two pairs per loop trip): 58 v_fma (x2), 20 v_mul, 2 v_add, 2 v_rsq (x1)
+# = 140 (the 2 < z <= 6 branch: 60 v_fma, 144); not counted: 1 v_rndne,
+# 1 v_ldexp, 1 v_cvt (exponent handling of exp(-z)).  By function: r^2 and
+# differences 5, 1/r 9, exp(-z) 33, 1/sqrt(z) 9, the K0 piece with derivative
+# 62 (degree 15), K1 and scalings ~15, both accumulations 7.
+FLOP_PER_PAIR_FP64 = 140
 # launch shapes (far-field source splits) chosen by the autotuner on MI355X for
 # the plans of this benchmark; the HBM byte counts below were taken with them
 TUNED_SPLITS = os.path.join(ROOT, "paper_1908_07392_amd", "tuning", "mi355x_far_splits.json")
@@ -45,7 +45,7 @@ TUNED_SPLITS = os.path.join(ROOT, "paper_1908_07392_amd", "tuning", "mi355x_far_
 # same counter's reading for a plain 256 MiB copy), averaged over the three
 # alphas, measured with these source splits
 # (profiles/far_eval_fp64_starfish4096_grid512_hbm_bytes.txt)
-PROFILED_TRAFFIC = {"splits": {"alpha=5": 20, "alpha=50": 16, "alpha=500": 16}, "bytes": 36912634}
+PROFILED_TRAFFIC = {"splits": {"alpha=5": 20, "alpha=50": 16, "alpha=500": 16}, "bytes": None}
 
 
 def parse():

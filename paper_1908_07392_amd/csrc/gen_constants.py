@@ -13,6 +13,10 @@ Device K0/K1 (modified Bessel functions of the second kind):
 * z > 2: e^z sqrt(z) K_nu(z) is smooth in u = 4/z - 1 in (-1, 1]; it is stored
   as a polynomial in u (Chebyshev interpolant of degree 22 for FP64 and 9 for
   FP32, converted to monomial form; coefficients stay O(1)).
+* z > 2, two pieces for the FP64 far-field tiles: z in [2, 6] (u in [-1/3, 1],
+  local v = 1.5 u - 0.5) and z >= 6 (u in (-1, -1/3], v = 3 u + 2); K0 to degree
+  16 / 15 so that K1 = -K0' taken from the derivative of the fit is also
+  accurate, K1 alone to degree 14 / 13.
 """
 import os
 
@@ -109,6 +113,26 @@ def check_large(coef, f, dtype):
     return float(np.max(np.abs(v - ref) / np.abs(ref)))
 
 
+def check_piece(coef, nu, lo, hi, with_derivative):
+    """max rel. error of K_nu (and of K1 from the derivative of a K0 fit) on a piece"""
+    dvdu = 2.0 / (hi - lo)
+    e0 = e1 = 0.0
+    for x in np.linspace(0.0, 1.0, 200):
+        u = mp.mpf(lo) + (mp.mpf(hi) - lo) * mp.mpf(x)
+        if u <= -1:
+            u = mp.mpf(-1) + mp.mpf("1e-6")
+        z = 4 / (u + 1)
+        v = (2 * u - lo - hi) / (mp.mpf(hi) - lo)
+        p = mp.fsum(c * v ** i for i, c in enumerate(coef))
+        E = mp.e ** (-z) / mp.sqrt(z)
+        e0 = max(e0, float(abs(E * p / mp.besselk(nu, z) - 1)))
+        if with_derivative:
+            dp = mp.fsum(i * c * v ** (i - 1) for i, c in enumerate(coef) if i) * dvdu
+            k1 = E * (p * (1 + 1 / (2 * z)) + (4 / z ** 2) * dp)
+            e1 = max(e1, float(abs(k1 / mp.besselk(1, z) - 1)))
+    return e0, e1
+
+
 def fmt(name, vals, ctype="double"):
     suffix = "" if ctype == "double" else "f"
     body = ",\n    ".join(f"{mp.nstr(v, 20, min_fixed=-1, max_fixed=-1)}{suffix}" if ctype == "double" else
@@ -189,10 +213,19 @@ def main():
         out.append(f"/* e^z sqrt(z) K{nu}(z) as a polynomial in u = 4/z - 1, z >= 2 */")
         out.append(fmt(f"KL{nu}", c64))
         out.append(fmt(f"KLF{nu}", c32, "float"))
+    us = mp.mpf(4) / 6 - 1
+    for name, nu, deg, lo, hi, der in (("KP0N", 0, 16, us, 1, True), ("KP0F", 0, 15, -1, us, True),
+                                       ("KP1N", 1, 14, us, 1, False), ("KP1F", 1, 13, -1, us, False)):
+        c = cheb_fit_mono(large_fn(nu), deg, lo, hi)
+        e0, e1 = check_piece(c, nu, lo, hi, der)
+        report.append((name, e0, e1))
+        out.append(f"/* e^z sqrt(z) K{nu}(z) on u in [{float(lo):.4f}, {float(hi):.4f}] (u = 4/z - 1), as a polynomial"
+                   f" in v = (2u - lo - hi)/(hi - lo) */")
+        out.append(fmt(name, c))
     with open(os.path.join(HERE, "constants.h"), "w") as fh:
         fh.write("\n".join(out) + "\n")
     for r in report:
-        print("%-4s fp64 rel err %.2e   fp32 rel err %.2e" % r)
+        print("%-4s rel err %.2e   %.2e  (fp64 / fp32, or K / K1 from the derivative)" % r)
 
 
 if __name__ == "__main__":

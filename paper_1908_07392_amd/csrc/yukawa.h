@@ -105,13 +105,16 @@ static constexpr double ATANH_T[11] = {1.0, 1.0 / 3.0, 1.0 / 5.0, 1.0 / 7.0, 1.0
    about 200 registers in the fused kernel: 4 instead of 2 waves per SIMD). */
 #define MHLP_CAS __attribute__((address_space(4)))
 struct FarTable {
-    double kl0[23], kl1[23], expt[14], atanh[11], ks_i0[12], ks_r0[13], ks_i1z[12], ks_r1[13];
+    double kp0n[17], kp0f[16], kp1n[15], kp1f[14], expt[14], atanh[11], ks_i0[12], ks_r0[13], ks_i1z[12], ks_r1[13];
 };
 
 constexpr FarTable make_far_table()
 {
     FarTable t{};
-    for (int i = 0; i < 23; ++i) t.kl0[i] = KL0[i], t.kl1[i] = KL1[i];
+    for (int i = 0; i < 17; ++i) t.kp0n[i] = KP0N[i];
+    for (int i = 0; i < 16; ++i) t.kp0f[i] = KP0F[i];
+    for (int i = 0; i < 15; ++i) t.kp1n[i] = KP1N[i];
+    for (int i = 0; i < 14; ++i) t.kp1f[i] = KP1F[i];
     for (int i = 0; i < 14; ++i) t.expt[i] = EXP_T[i];
     for (int i = 0; i < 11; ++i) t.atanh[i] = ATANH_T[i];
     for (int i = 0; i < 12; ++i) t.ks_i0[i] = KS_I0[i], t.ks_i1z[i] = KS_I1Z[i];
@@ -190,38 +193,59 @@ __device__ __forceinline__ double lean_log01(FarTab T, double q)
     return fma(de, LN2_HI, fma(de, LN2_LO, 2.0 * s * p));
 }
 
-/* K0(z) and alpha K1(z)/r for the far-field tiles.  When both layers are
-   wanted, K1 is taken from the derivative of the K0 fits (K1 = -K0'):
-     z > 2 : K0 = E P0(u), K1 = E [P0 (1 + 1/(2z)) + (4/z^2) P0'(u)],
-             E = e^{-z}/sqrt(z), u = 4/z - 1;
-     z <= 2: K1 = I0/z + (z/4) log(q) I0'(q) - (z/2) R0'(q), q = z^2/4,
-   which halves the coefficient tables (max rel. error 3e-15 vs 5e-16 for the
-   separate fits; measured against mpmath).  ia = 1/alpha.
-   k01_far_big evaluates the z > 2 form for any r2 > 0 (finite or inf/nan
-   garbage when z <= 2); k01_far_small is the z <= 2 form.  k01_far2 takes
-   two pairs: both big forms straight-line (independent instruction streams
-   the scheduler interleaves) on lanes where either pair needs it, then the
-   small form on lanes that need it, overwriting the big values. */
+/* K0(z) and alpha K1(z)/r for the far-field tiles.
+     z > 2 : K_nu = E P(v), E = e^{-z}/sqrt(z), u = 4/z - 1, on two pieces:
+             z <= 6 (v = 1.5 u - 0.5) and z > 6 (v = 3 u + 2), v in [-1, 1];
+             with both layers, K1 = -K0' = E [P0 (1 + 1/(2z)) + (4/z^2) dP0/du]
+             from the K0 pieces (degree 16 / 15; K1 alone: degree 14 / 13);
+     z <= 2: K1 = I0/z + (z/4) log(q) I0'(q) - (z/2) R0'(q), q = z^2/4.
+   Max rel. error of the z > 2 pieces 1.2e-16 for K0 and K1 (40-digit check).
+   k01_far_small is the z <= 2 form.  k01_far2 takes two sources: the z > 2
+   forms straight-line for both (independent instruction streams the
+   scheduler interleaves) on lanes where either needs it, with the common
+   piece when both fall on the same side of z = 6, then the z <= 2 form on
+   the lanes that need it, overwriting the other values. */
+struct FarConst {
+    double a, a2q, a4, ia; /* alpha, alpha^2/4, 4/alpha, 1/alpha */
+};
+
+__device__ __forceinline__ FarConst far_const(double alpha)
+{
+    return FarConst{alpha, 0.25 * alpha * alpha, 4.0 / alpha, 1.0 / alpha};
+}
+
+/* polynomial of the piece (value and d/du) at 1/r = ri */
+template <bool SLP, bool DLP, bool FAR>
+__device__ __forceinline__ double far_piece(FarTab T, const FarConst &c, double ri, double &dpdu)
+{
+    /* v = 3u + 2 = (12/alpha) ri - 1 (far);  v = 1.5u - 0.5 = (6/alpha) ri - 2 (near) */
+    const double v = FAR ? fma(3.0 * c.a4, ri, -1.0) : fma(1.5 * c.a4, ri, -2.0);
+    if (SLP && DLP) {
+        double d;
+        const double p = FAR ? hornercd<16>(T->kp0f, v, d) : hornercd<17>(T->kp0n, v, d);
+        dpdu = d * (FAR ? 3.0 : 1.5);
+        return p;
+    }
+    dpdu = 0.0;
+    if (SLP) return FAR ? hornerc<16>(T->kp0f, v) : hornerc<17>(T->kp0n, v);
+    return FAR ? hornerc<14>(T->kp1f, v) : hornerc<15>(T->kp1n, v);
+}
+
 template <bool SLP, bool DLP>
-__device__ __forceinline__ K01 k01_far_big(FarTab T, double r2, double a, double a4, double ia)
+__device__ __forceinline__ K01 far_finish(const FarConst &c, double ri, double z, double e, double p, double dpdu)
 {
     K01 o{0.0, 0.0};
-    const double ri = lean_rsq(r2);
-    const double z = a * (r2 * ri);
-    const double u = fma(a4, ri, -1.0);
-    const double e = lean_exp_neg(T, z) * lean_rsq(z);
     if (SLP && DLP) {
-        double dp;
-        const double p = hornercd<23>(T->kl0, u, dp);
         o.k0 = e * p;
-        const double iz = ia * ri; /* 1/z */
-        const double k1 = e * fma(4.0 * iz * iz, dp, p * fma(0.5, iz, 1.0));
-        o.ak1r = a * k1 * ri;
+        const double iz = c.ia * ri; /* 1/z */
+        const double k1 = e * fma(4.0 * iz * iz, dpdu, p * fma(0.5, iz, 1.0));
+        o.ak1r = c.a * k1 * ri;
     } else if (SLP) {
-        o.k0 = e * hornerc<23>(T->kl0, u);
+        o.k0 = e * p;
     } else {
-        o.ak1r = a * e * hornerc<23>(T->kl1, u) * ri;
+        o.ak1r = c.a * e * p * ri;
     }
+    (void)z;
     return o;
 }
 
@@ -247,22 +271,34 @@ __device__ __forceinline__ K01 k01_far_small(FarTab T, double r2, double a2q)
     return o;
 }
 
-struct FarConst {
-    double a, a2q, a4, ia; /* alpha, alpha^2/4, 4/alpha, 1/alpha */
-};
-
-__device__ __forceinline__ FarConst far_const(double alpha)
-{
-    return FarConst{alpha, 0.25 * alpha * alpha, 4.0 / alpha, 1.0 / alpha};
-}
-
 template <bool SLP, bool DLP>
 __device__ __forceinline__ void k01_far2(FarTab T, const FarConst &c, double r2a, double r2b, K01 &oa, K01 &ob)
 {
     const bool sa = c.a2q * r2a <= 1.0, sb = c.a2q * r2b <= 1.0;
     if (!(sa && sb)) {
-        oa = k01_far_big<SLP, DLP>(T, r2a, c.a, c.a4, c.ia);
-        ob = k01_far_big<SLP, DLP>(T, r2b, c.a, c.a4, c.ia);
+        const double ria = lean_rsq(r2a), rib = lean_rsq(r2b);
+        const double za = c.a * (r2a * ria), zb = c.a * (r2b * rib);
+        const double ea = lean_exp_neg(T, za) * lean_rsq(za), eb = lean_exp_neg(T, zb) * lean_rsq(zb);
+        const bool fa = za > 6.0, fb = zb > 6.0;
+        double pa, pb, da, db;
+        if (fa && fb) {
+            pa = far_piece<SLP, DLP, true>(T, c, ria, da);
+            pb = far_piece<SLP, DLP, true>(T, c, rib, db);
+        } else if (!fa && !fb) {
+            pa = far_piece<SLP, DLP, false>(T, c, ria, da);
+            pb = far_piece<SLP, DLP, false>(T, c, rib, db);
+        } else {
+            if (fa)
+                pa = far_piece<SLP, DLP, true>(T, c, ria, da);
+            else
+                pa = far_piece<SLP, DLP, false>(T, c, ria, da);
+            if (fb)
+                pb = far_piece<SLP, DLP, true>(T, c, rib, db);
+            else
+                pb = far_piece<SLP, DLP, false>(T, c, rib, db);
+        }
+        oa = far_finish<SLP, DLP>(c, ria, za, ea, pa, da);
+        ob = far_finish<SLP, DLP>(c, rib, zb, eb, pb, db);
     }
     if (sa || sb) {
         if (sa) oa = k01_far_small<SLP, DLP>(T, r2a, c.a2q);
