@@ -45,7 +45,7 @@ TUNED_SPLITS = os.path.join(ROOT, "paper_1908_07392_amd", "tuning", "mi355x_far_
 # same counter's reading for a plain 256 MiB copy), averaged over the three
 # alphas, measured with these source splits
 # (profiles/far_eval_fp64_starfish4096_grid512_hbm_bytes.txt)
-PROFILED_TRAFFIC = {"splits": {"alpha=5": 20, "alpha=50": 16, "alpha=500": 16}, "bytes": None}
+PROFILED_TRAFFIC = {"splits": {"alpha=5": 20, "alpha=50": 16, "alpha=500": 16}, "bytes": 36874791}
 
 
 def parse():
@@ -188,6 +188,15 @@ def main():
     on, off = plans[a_r]
     mu, _ = mhlp.gmres_solve(on, gdev[a_r], tol=1e-10)
     reps = 20
+    # context: the same evaluation launched back to back (steady clocks), alpha = 50
+    mhlp.eval_layer(off, sigma=mu, mu=mu)
+    eb0, eb1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    eb0.record()
+    for _ in range(reps):
+        mhlp.eval_layer(off, sigma=mu, mu=mu)
+    eb1.record()
+    torch.cuda.synchronize()
+    roofline["back_to_back_launch_ms_alpha50"] = round(eb0.elapsed_time(eb1) / reps, 4)
 
     gm = {f"alpha={a:g}": {"gmres_ms": round(float(np.median([s["gmres_ms"] for s in stats[a]])), 3),
                            "iters": stats[a][-1]["iters"], "residual": stats[a][-1]["residual"]}
