@@ -620,7 +620,7 @@ __global__ __launch_bounds__(FT_THREADS) void volume_kernel(VolArgs A)
                 r20 = self0 ? 1.0 : r20;
                 r21 = self1 ? 1.0 : r21;
                 K01 o0, o1;
-                k01_far2<true, false>(T, fc, r20, r21, o0, o1);
+                k01_far2<true, false, false>(T, fc, r20, r21, o0, o1);
                 acc = fma(self1 ? 0.0 : o1.k0, lq[l + 1], fma(self0 ? 0.0 : o0.k0, lq[l], acc));
             }
         }

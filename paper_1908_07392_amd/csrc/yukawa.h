@@ -105,12 +105,14 @@ static constexpr double ATANH_T[11] = {1.0, 1.0 / 3.0, 1.0 / 5.0, 1.0 / 7.0, 1.0
    about 200 registers in the fused kernel: 4 instead of 2 waves per SIMD). */
 #define MHLP_CAS __attribute__((address_space(4)))
 struct FarTable {
-    double kp0n[17], kp0f[16], kp1n[15], kp1f[14], expt[14], atanh[11], ks_i0[12], ks_r0[13], ks_i1z[12], ks_r1[13];
+    double kp0n[17], kp0f[16], kp1n[15], kp1f[14], kl0[23], expt[14], atanh[11], ks_i0[12], ks_r0[13], ks_i1z[12],
+        ks_r1[13];
 };
 
 constexpr FarTable make_far_table()
 {
     FarTable t{};
+    for (int i = 0; i < 23; ++i) t.kl0[i] = KL0[i];
     for (int i = 0; i < 17; ++i) t.kp0n[i] = KP0N[i];
     for (int i = 0; i < 16; ++i) t.kp0f[i] = KP0F[i];
     for (int i = 0; i < 15; ++i) t.kp1n[i] = KP1N[i];
@@ -271,17 +273,23 @@ __device__ __forceinline__ K01 k01_far_small(FarTab T, double r2, double a2q)
     return o;
 }
 
-template <bool SLP, bool DLP>
+/* PIECES = false (K0 only): one degree-22 fit over all z > 2 in u = 4/z - 1,
+   for launches whose lanes often straddle z = 6 (targets in no spatial order) */
+template <bool SLP, bool DLP, bool PIECES = true>
 __device__ __forceinline__ void k01_far2(FarTab T, const FarConst &c, double r2a, double r2b, K01 &oa, K01 &ob)
 {
+    static_assert(PIECES || (SLP && !DLP), "the single fit serves the single layer only");
     const bool sa = c.a2q * r2a <= 1.0, sb = c.a2q * r2b <= 1.0;
     if (!(sa && sb)) {
         const double ria = lean_rsq(r2a), rib = lean_rsq(r2b);
         const double za = c.a * (r2a * ria), zb = c.a * (r2b * rib);
         const double ea = lean_exp_neg(T, za) * lean_rsq(za), eb = lean_exp_neg(T, zb) * lean_rsq(zb);
         const bool fa = za > 6.0, fb = zb > 6.0;
-        double pa, pb, da, db;
-        if (fa && fb) {
+        double pa, pb, da = 0.0, db = 0.0;
+        if (!PIECES) {
+            pa = hornerc<23>(T->kl0, fma(c.a4, ria, -1.0));
+            pb = hornerc<23>(T->kl0, fma(c.a4, rib, -1.0));
+        } else if (fa && fb) {
             pa = far_piece<SLP, DLP, true>(T, c, ria, da);
             pb = far_piece<SLP, DLP, true>(T, c, rib, db);
         } else if (!fa && !fb) {
