@@ -346,3 +346,41 @@ def test_batch_gmres_restarts_and_warm_start(restart):
         assert infos2[k]["used_x0"] == (0 if k == 3 else 1)
         assert _relerr(sols2[k].cpu().numpy(), refs[k].cpu().numpy()) < 1e-9
     assert max(i["iters"] for i in infos2) <= max(i["iters"] for i in infos)
+
+
+def test_zero_rhs_and_exact_initial_guess():
+    g = wl.discretize(wl.starfish_curve(), 24)
+    P = mhlp.Plan(_geom(g), 12.0)
+    z = torch.zeros(g.n_nodes, dtype=torch.float64, device=DEV)
+    mu, info = mhlp.gmres_solve(P, z, tol=1e-10)
+    assert info["converged"] and info["iters"] == 0 and float(mu.abs().max()) == 0.0
+    b = _t(wl.fourier_density(g.theta, wl.random_fourier_coeffs(np.random.default_rng(4), 6)))
+    x, info = mhlp.gmres_solve(P, b, tol=1e-12)
+    # restarting from the converged solution needs no Arnoldi step
+    x2, info2 = mhlp.gmres_solve(P, b, x0=x, tol=1e-10)
+    assert info2["converged"] and info2["iters"] == 0 and info2["used_x0"] == 1
+    assert torch.equal(x, x2)
+
+
+@pytest.mark.parametrize("alpha", [0.05, 2000.0])
+def test_extreme_alpha_vs_oracle(alpha):
+    """alpha -> 0 (every pair in the z <= 2 series branch) and alpha h >> 4.5
+    (subdivided near panels, K0 underflow for most far pairs)."""
+    rng = np.random.default_rng(31)
+    curve = wl.starfish_curve()
+    g = wl.discretize(curve, 48)
+    tx, ty = _near_targets(curve, rng)
+    sigma = wl.fourier_density(g.theta, wl.random_fourier_coeffs(rng, 8))
+    P = mhlp.Plan(_geom(g), alpha, _t(tx), _t(ty))
+    us, ud = mhlp.eval_layer(P, sigma=_t(sigma), mu=_t(sigma))
+    os_, od = oracle.eval_potentials(g.x, g.y, alpha, tx, ty, sigma=sigma, mu=sigma)
+    assert _relerr(us.cpu().numpy(), os_) < 1e-11 and _relerr(ud.cpu().numpy(), od) < 1e-11
+
+
+def test_nonfinite_targets_rejected():
+    g = wl.discretize(wl.Curve("circle"), 4)
+    G = _geom(g)
+    with pytest.raises(mhlp.MhlpError):
+        mhlp.Plan(G, 3.0, _t([0.1, np.nan]), _t([0.0, 0.2]))
+    with pytest.raises(mhlp.MhlpError):
+        mhlp.Plan(G, 3.0, _t([0.1, np.inf]), _t([0.0, 0.2]))
