@@ -46,6 +46,10 @@ def lib():
                                         ctypes.c_double, ctypes.c_int, ctypes.c_int, _D]
         L.orc_eval.argtypes = [_D, _D, ctypes.c_int64, _D, _D, ctypes.c_double, _D, _D, ctypes.c_int64, _I64,
                                _D, _D, ctypes.c_int]
+        L.orc_panel_grad_weights.argtypes = [_D, _D, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                             ctypes.c_double, ctypes.c_int, _D]
+        L.orc_eval_grad.argtypes = [_D, _D, ctypes.c_int64, _D, _D, ctypes.c_double, _D, _D, ctypes.c_int64,
+                                    _D, _D, _D, _D, ctypes.c_int]
         L.orc_assemble_onsurface.argtypes = [_D, _D, ctypes.c_int64, ctypes.c_double, _D, _D, ctypes.c_int]
         L.orc_gmres.argtypes = [_D, ctypes.c_int64, _D, _D, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                 ctypes.POINTER(ctypes.c_int), _D, ctypes.c_int]
@@ -113,6 +117,33 @@ def eval_potentials(x, y, alpha, tx, ty, sigma=None, mu=None, tgt_node=None, nth
     if rc != 0:
         raise RuntimeError(f"orc_eval failed: {rc}")
     return us, ud
+
+
+def eval_gradients(x, y, alpha, tx, ty, sigma=None, mu=None, nthreads=0):
+    """Gradients of the SLP of sigma and the DLP of mu at off-surface targets
+    (exact near-panel integrals).  Returns (grad S as [2][m] or None, grad D as
+    [2][m] or None)."""
+    x, y, tx, ty = _c(x), _c(y), _c(tx), _c(ty)
+    sigma, mu = _c(sigma), _c(mu)
+    m = tx.size
+    gs = np.zeros((2, m)) if sigma is not None else None
+    gd = np.zeros((2, m)) if mu is not None else None
+    rc = lib().orc_eval_grad(_p(x), _p(y), x.size // 16, _p(sigma), _p(mu), float(alpha), _p(tx), _p(ty), m,
+                             None if gs is None else _p(gs[0]), None if gs is None else _p(gs[1]),
+                             None if gd is None else _p(gd[0]), None if gd is None else _p(gd[1]),
+                             int(nthreads))
+    if rc != 0:
+        raise RuntimeError(f"orc_eval_grad failed: {rc}")
+    return gs, gd
+
+
+def panel_grad_weights(x, y, panel, tx, ty, alpha, mode=0):
+    """64 gradient weights of one target against one panel (blocks d/dx1 SLP,
+    d/dx2 SLP, d/dx1 DLP, d/dx2 DLP)."""
+    x, y = _c(x), _c(y)
+    W = np.zeros(64)
+    lib().orc_panel_grad_weights(_p(x), _p(y), int(panel), float(tx), float(ty), float(alpha), int(mode), _p(W))
+    return W.reshape(4, 16)
 
 
 def onsurface_matrices(x, y, alpha, want_slp=False, want_dlp=True, nthreads=0):

@@ -10,6 +10,14 @@
  *   DLP  u(x) = int_Gamma dG/dn_y mu(y) dS_y
  *             = int_Gamma alpha K1(alpha r) (x-y).n_y / (2 pi r) mu(y) dS_y
  *
+ * and the target gradients of both (Sec. 4.6, the near-boundary gradient,
+ * restated for the scalar kernel; r = |x - y|, A = alpha K1(alpha r)/r):
+ *
+ *   grad_x G       = A (y - x) / (2 pi)
+ *   grad_x dG/dn_y = [A n_y - ((y-x).n_y)(y - x)(alpha^2 K0 + 2A)/r^2] / (2 pi)
+ *
+ * (from K0' = -K1 and (K1(z)/z)' = -(K0(z) + 2 K1(z)/z)/z).
+ *
  * K0(alpha r)/(2 pi) is the scalar Yukawa piece of the paper's modified
  * biharmonic Green's function (Sec. 2, eq. for G; App. B).  The boundary is the
  * composite 16-point Gauss-Legendre panel discretisation of Sec. 3.2, and the
@@ -223,7 +231,11 @@ typedef struct {
     double dref[16];         /* tref - t_j   */
     int self;                /* node index of the target on this panel, or -1 */
     double alpha;
+    int grad;                /* 0: potentials (32 values), 1: gradients (64) */
+    int nf;                  /* values per evaluation: 32 or 64              */
 } integrand_t;
+
+#define MAXF 64
 
 /* Lagrange basis l_j(t) of the 16 nodes at t = tref + s (barycentric form).
    Long double: the normal component (x-y).n of a target lying on or beside
@@ -246,8 +258,10 @@ static void lagrange(const integrand_t *c, double s, long double *l)
     for (int j = 0; j < 16; ++j) l[j] /= sum;
 }
 
-/* Integrand: for a target and panel parameter t = tref + s, the 32 values
-   F[j] = G(x, y(t)) l_j(t) |y'(t)|,  F[16+j] = dG/dn_y l_j(t) |y'(t)|.
+/* Integrand: for a target and panel parameter t = tref + s, the values
+   potentials: F[j] = G(x, y(t)) l_j(t) |y'(t)|,  F[16+j] = dG/dn_y l_j(t) |y'(t)|;
+   gradients:  F[j], F[16+j] = d/dx1, d/dx2 of G(x, y(t)), F[32+j], F[48+j] the
+               same of dG/dn_y, each times l_j(t) |y'(t)|.
    Differences y(t)-x are formed as sum_j l_j(t)(x_j - x) so that a target on
    the panel keeps full relative accuracy near its own node.              */
 static void integrand(const integrand_t *c, double s, double *F)
@@ -267,27 +281,44 @@ static void integrand(const integrand_t *c, double s, double *F)
     double k0, k1;
     orc_bessel_k01(c->alpha * r, &k0, &k1);
     double xmyn = (double)(rx * dy - ry * dx);
-    double gs = k0 / TWO_PI * speed;
-    double gd = c->alpha * k1 / (TWO_PI * r) * xmyn;
-    for (int j = 0; j < 16; ++j) {
-        F[j] = gs * (double)l[j];
-        F[16 + j] = gd * (double)l[j];
+    if (!c->grad) {
+        double gs = k0 / TWO_PI * speed;
+        double gd = c->alpha * k1 / (TWO_PI * r) * xmyn;
+        for (int j = 0; j < 16; ++j) {
+            F[j] = gs * (double)l[j];
+            F[16 + j] = gd * (double)l[j];
+        }
+        return;
     }
+    /* A = alpha K1/r, B = (alpha^2 K0 + 2A)/r^2; with d = y - x,
+       grad G = A d/(2 pi), grad dG/dn = (A n - (d.n) d B)/(2 pi), and
+       -(d.n)|y'| = xmyn, n |y'| = (-dy, dx). */
+    double A = c->alpha * k1 / r;
+    double B = (c->alpha * c->alpha * k0 + 2.0 * A) / (r * r);
+    double ddx = (double)rx, ddy = (double)ry;
+    double v[4];
+    v[0] = A * ddx * speed / TWO_PI;
+    v[1] = A * ddy * speed / TWO_PI;
+    v[2] = (-A * (double)dy + xmyn * ddx * B) / TWO_PI;
+    v[3] = (A * (double)dx + xmyn * ddy * B) / TWO_PI;
+    for (int k = 0; k < 4; ++k)
+        for (int j = 0; j < 16; ++j) F[16 * k + j] = v[k] * (double)l[j];
 }
 
 static void gl_rule(const integrand_t *c, int n, const double *T, const double *W, double a, double b,
                     double *I, double *Iabs)
 {
     double mid = 0.5 * (a + b), half = 0.5 * (b - a);
-    double F[32];
-    for (int k = 0; k < 32; ++k) {
+    double F[MAXF];
+    const int nf = c->nf;
+    for (int k = 0; k < nf; ++k) {
         I[k] = 0.0;
         if (Iabs) Iabs[k] = 0.0;
     }
     for (int i = 0; i < n; ++i) {
         integrand(c, mid + half * T[i], F);
         double w = W[i] * half;
-        for (int k = 0; k < 32; ++k) {
+        for (int k = 0; k < nf; ++k) {
             I[k] += w * F[k];
             if (Iabs) Iabs[k] += w * fabs(F[k]);
         }
@@ -296,36 +327,38 @@ static void gl_rule(const integrand_t *c, int n, const double *T, const double *
 
 /* Adaptive bisection: accept the 32-point value on [a,b] when the 16-point
    value agrees with it to `rtol` relative (per component, relative to the
-   integral of |F| over [a,b]) or to `fl` absolute (per kernel); the accepted
-   32-point value is then accurate to rounding.  The absolute floor bounds the
-   work where rounding in the node positions of a tiny interval next to a
-   near-singularity exceeds the relative test.  `absacc` (optional) collects
-   the integral of |F| over the accepted pieces.                            */
+   integral of |F| over [a,b]) or to `fl` absolute (per kernel, i.e. per block
+   of 16 components); the accepted 32-point value is then accurate to
+   rounding.  The absolute floor bounds the work where rounding in the node
+   positions of a tiny interval next to a near-singularity exceeds the
+   relative test.  `absacc` (optional) collects the integral of |F| over the
+   accepted pieces.                                                        */
 typedef struct { double a, b; int d; } seg_t;
 static void adaptive(const integrand_t *c, double a, double b, double rtol, const double *fl, double *acc,
                      double *absacc)
 {
     seg_t stack[128];
     int top = 0, visited = 0;
+    const int nf = c->nf;
     stack[top++] = (seg_t){a, b, 0};
     while (top > 0) {
         seg_t s = stack[--top];
         ++visited;
-        double I16[32], I32[32], A32[32];
+        double I16[MAXF], I32[MAXF], A32[MAXF];
         gl_rule(c, 16, GL16_T, GL16_W, s.a, s.b, I16, NULL);
         gl_rule(c, 32, GL32_T, GL32_W, s.a, s.b, I32, A32);
         int ok = 1;
-        for (int k = 0; k < 32; ++k) {
+        for (int k = 0; k < nf; ++k) {
             double e = fabs(I16[k] - I32[k]);
-            if (e > rtol * A32[k] && e > fl[k < 16 ? 0 : 1] && e > 1e-300) {
+            if (e > rtol * A32[k] && e > fl[k >> 4] && e > 1e-300) {
                 ok = 0;
                 break;
             }
         }
         if (ok || s.d >= 60 || (s.b - s.a) < 1e-17 || top > 124 || visited > 200000) {
-            for (int k = 0; k < 32; ++k) acc[k] += I32[k];
+            for (int k = 0; k < nf; ++k) acc[k] += I32[k];
             if (absacc)
-                for (int k = 0; k < 32; ++k) absacc[k] += A32[k];
+                for (int k = 0; k < nf; ++k) absacc[k] += A32[k];
         } else {
             double m = 0.5 * (s.a + s.b);
             stack[top++] = (seg_t){m, s.b, s.d + 1};
@@ -340,29 +373,30 @@ static void adaptive(const integrand_t *c, double a, double b, double rtol, cons
    pass itself uses a floor of 1e-12 of a 32-point estimate of that scale. */
 static void integrate_pieces(const integrand_t *c, const double *cuts, int ncut, double *W)
 {
-    double tmp[32], ab[32], fl0[2] = {0.0, 0.0}, fl[2];
-    for (int k = 0; k < 32; ++k) tmp[k] = ab[k] = W[k] = 0.0;
+    const int nf = c->nf, nk = c->nf / 16;
+    double tmp[MAXF], ab[MAXF], fl0[4] = {0.0, 0.0, 0.0, 0.0}, fl[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < nf; ++k) tmp[k] = ab[k] = W[k] = 0.0;
     for (int q = 0; q + 1 < ncut; ++q) {
-        double I[32], A[32];
+        double I[MAXF], A[MAXF];
         gl_rule(c, 32, GL32_T, GL32_W, cuts[q], cuts[q + 1], I, A);
-        for (int k = 0; k < 32; ++k) fl0[k < 16 ? 0 : 1] = fmax(fl0[k < 16 ? 0 : 1], A[k]);
+        for (int k = 0; k < nf; ++k) fl0[k >> 4] = fmax(fl0[k >> 4], A[k]);
     }
-    fl0[0] *= 1e-12;
-    fl0[1] *= 1e-12;
+    for (int b = 0; b < nk; ++b) fl0[b] *= 1e-12;
     for (int q = 0; q + 1 < ncut; ++q) adaptive(c, cuts[q], cuts[q + 1], 1e-8, fl0, tmp, ab);
-    fl[0] = fl[1] = 0.0;
-    for (int k = 0; k < 32; ++k) fl[k < 16 ? 0 : 1] = fmax(fl[k < 16 ? 0 : 1], ab[k]);
-    fl[0] *= 2e-16;
-    fl[1] *= 2e-16;
+    for (int k = 0; k < nf; ++k) fl[k >> 4] = fmax(fl[k >> 4], ab[k]);
+    for (int b = 0; b < nk; ++b) fl[b] *= 2e-16;
     for (int q = 0; q + 1 < ncut; ++q) adaptive(c, cuts[q], cuts[q + 1], ORC_RTOL, fl, W, NULL);
 }
 
 /* Exact panel weights W[0..15] (SLP) and W[16..31] (DLP) of target (tx,ty)
-   against panel p.  If self >= 0 the target is node `self` of this panel and
+   against panel p; with grad, W[0..63] = d/dx1, d/dx2 of the SLP, then of the
+   DLP.  If self >= 0 the target is node `self` of this panel and
    the integral is split there with geometric grading towards it.          */
-static void panel_exact(const panel_t *p, double tx, double ty, double alpha, int self, double *W)
+static void panel_exact_k(const panel_t *p, double tx, double ty, double alpha, int self, int grad, double *W)
 {
     integrand_t c;
+    c.grad = grad;
+    c.nf = grad ? 64 : 32;
     c.p = p;
     c.tx = tx;
     c.ty = ty;
@@ -395,6 +429,11 @@ static void panel_exact(const panel_t *p, double tx, double ty, double alpha, in
     integrate_pieces(&c, cuts, nc, W);
 }
 
+static void panel_exact(const panel_t *p, double tx, double ty, double alpha, int self, double *W)
+{
+    panel_exact_k(p, tx, ty, alpha, self, 0, W);
+}
+
 /* direct 16-point weights: K(x, y_j) |y'(t_j)| lambda_j */
 static void panel_direct(const panel_t *p, double tx, double ty, double alpha, double *W)
 {
@@ -407,6 +446,26 @@ static void panel_direct(const panel_t *p, double tx, double ty, double alpha, d
         double xmyn = rx * p->dy[j] - ry * p->dx[j];
         W[j] = k0 / TWO_PI * speed * GL16_W[j];
         W[16 + j] = alpha * k1 / (TWO_PI * r) * xmyn * GL16_W[j];
+    }
+}
+
+/* direct 16-point gradient weights (same layout as the exact ones) */
+static void panel_direct_grad(const panel_t *p, double tx, double ty, double alpha, double *W)
+{
+    for (int j = 0; j < 16; ++j) {
+        double rx = p->x[j] - tx, ry = p->y[j] - ty;
+        double r = hypot(rx, ry);
+        double k0, k1;
+        orc_bessel_k01(alpha * r, &k0, &k1);
+        double speed = hypot(p->dx[j], p->dy[j]);
+        double xmyn = rx * p->dy[j] - ry * p->dx[j];
+        double A = alpha * k1 / r;
+        double B = (alpha * alpha * k0 + 2.0 * A) / (r * r);
+        double w = GL16_W[j] / TWO_PI;
+        W[j] = A * rx * speed * w;
+        W[16 + j] = A * ry * speed * w;
+        W[32 + j] = (-A * p->dy[j] + xmyn * rx * B) * w;
+        W[48 + j] = (A * p->dx[j] + xmyn * ry * B) * w;
     }
 }
 
@@ -488,6 +547,66 @@ int orc_eval(const double *x, const double *y, int64_t n_panels, const double *s
         }
         if (u_slp) u_slp[i] = (double)us;
         if (u_dlp) u_dlp[i] = (double)ud;
+    }
+    free(P);
+    return 0;
+}
+
+/* Gradient weights of one off-surface target against one panel (W: 64
+   doubles, blocks d/dx1 SLP, d/dx2 SLP, d/dx1 DLP, d/dx2 DLP).  mode: 0 auto,
+   1 force exact, 2 force direct. */
+int orc_panel_grad_weights(const double *x, const double *y, int64_t panel, double tx, double ty, double alpha,
+                           int mode, double *W)
+{
+    init_rules();
+    panel_t p;
+    panel_setup(&p, x + 16 * panel, y + 16 * panel);
+    if (mode == 2)
+        panel_direct_grad(&p, tx, ty, alpha, W);
+    else if (mode == 1 || panel_is_near(&p, tx, ty))
+        panel_exact_k(&p, tx, ty, alpha, -1, 1, W);
+    else
+        panel_direct_grad(&p, tx, ty, alpha, W);
+    return 0;
+}
+
+/* Gradients of S[sigma] and D[mu] at m off-surface targets (targets must not
+   lie on the curve).  Outputs (any may be NULL with its density):
+   gsx, gsy = grad S[sigma];  gdx, gdy = grad D[mu]. */
+int orc_eval_grad(const double *x, const double *y, int64_t n_panels, const double *sigma, const double *mu,
+                  double alpha, const double *tx, const double *ty, int64_t m, double *gsx, double *gsy,
+                  double *gdx, double *gdy, int nthreads)
+{
+    init_rules();
+    if (alpha <= 0.0 || n_panels <= 0 || m < 0) return -1;
+    panel_t *P = (panel_t *)malloc(sizeof(panel_t) * (size_t)n_panels);
+    if (!P) return -2;
+    for (int64_t p = 0; p < n_panels; ++p) panel_setup(&P[p], x + 16 * p, y + 16 * p);
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t i = 0; i < m; ++i) {
+        long double a[4] = {0.0L, 0.0L, 0.0L, 0.0L};
+        for (int64_t p = 0; p < n_panels; ++p) {
+            double W[64];
+            if (panel_is_near(&P[p], tx[i], ty[i]))
+                panel_exact_k(&P[p], tx[i], ty[i], alpha, -1, 1, W);
+            else
+                panel_direct_grad(&P[p], tx[i], ty[i], alpha, W);
+            for (int j = 0; j < 16; ++j) {
+                if (sigma) {
+                    a[0] += (long double)W[j] * sigma[16 * p + j];
+                    a[1] += (long double)W[16 + j] * sigma[16 * p + j];
+                }
+                if (mu) {
+                    a[2] += (long double)W[32 + j] * mu[16 * p + j];
+                    a[3] += (long double)W[48 + j] * mu[16 * p + j];
+                }
+            }
+        }
+        if (gsx) gsx[i] = (double)a[0];
+        if (gsy) gsy[i] = (double)a[1];
+        if (gdx) gdx[i] = (double)a[2];
+        if (gdy) gdy[i] = (double)a[3];
     }
     free(P);
     return 0;
