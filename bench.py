@@ -38,6 +38,12 @@ FP64_PEAK_TFLOPS = 78.6        # MI355X vector FP64 (published)
 # differences 5, 1/r 9, exp(-z) 33, 1/sqrt(z) 9, the K0 piece with derivative
 # 62 (degree 15), K1 and scalings ~15, both accumulations 7.
 FLOP_PER_PAIR_FP64 = 140
+# the gradient kernel (grad S and grad D of the same densities) evaluates the
+# same K0 and alpha K1/r per pair, takes 1/r^2 = (1/r)^2 from the z > 2 form
+# (1 mul), and accumulates (x-y).n, (alpha^2 K0 + 2A)/r^2 and both gradients:
+# counted from the built kernel's loop, 42 + 2 FLOP per trip of two pairs
+# instead of the potentials' 14, so 140 + 15
+FLOP_PER_PAIR_GRAD = 155
 # launch shapes (far-field source splits) chosen by the autotuner on MI355X for
 # the plans of this benchmark; the HBM byte counts below were taken with them
 TUNED_SPLITS = os.path.join(ROOT, "paper_1908_07392_amd", "tuning", "mi355x_far_splits.json")
@@ -56,7 +62,9 @@ def parse():
     ap.add_argument("--grid", type=int, default=512)
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the batched, volume and warm-start legs")
+    ap.add_argument("--no-extra", action="store_true", help="skip the batched, volume, warm-start and gradient legs")
+    ap.add_argument("--legs", default="batched,volume,warm,gradient",
+                    help="comma list of the extra legs to run (batched, volume, warm, gradient)")
     ap.add_argument("--tune-cache", default=TUNED_SPLITS,
                     help="JSON cache of the autotuned launch shapes (read; plans missing from it are tuned afresh)")
     ap.add_argument("--tune-write", action="store_true", help="add freshly tuned plans to the cache file")
@@ -256,10 +264,15 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         out["copy_calibration"] = {"bytes_read": nbytes, "bytes_written": nbytes, "launches": 3}
-    if not args.no_extra:
+    legs = set() if args.no_extra else set(args.legs.split(","))
+    if "batched" in legs:
         out["batched"] = bench_batched(mhlp, wl, t, torch)
+    if "volume" in legs:
         out["volume"] = bench_volume(mhlp, wl, t, torch)
+    if "warm" in legs:
         out["warm_start"] = bench_warm(mhlp, wl, t, torch)
+    if "gradient" in legs:
+        out["gradient"] = bench_grad(mhlp, plans, gdev, cfg, args, torch)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, 50.0, args.cpu_seconds)
     print(json.dumps(out), flush=True)
@@ -304,6 +317,44 @@ def bench_batched(mhlp, wl, t, torch):
             "all_converged": all(i["converged"] for i in infos),
             "max_residual": max(i["rel_residual"] for i in infos),
             "max_iters": max(i["iters"] for i in infos), "sequential_total_iters": seq_iters}
+
+
+def bench_grad(mhlp, plans, gdev, cfg, args, torch):
+    """Target gradients grad S[mu] and grad D[mu] (both, one launch) of the solved
+    density at the 109,314 interior grid targets, FP64, per alpha: first call
+    (builds the 64 gradient weights per near pair) and the steady launch."""
+    print("# gradient leg", file=sys.stderr, flush=True)
+    from paper_1908_07392_amd import autotune
+    res = {"flop_per_pair": FLOP_PER_PAIR_GRAD}
+    launch = {}
+    for a in cfg["alphas"]:
+        on, off = plans[a]
+        mu, _ = mhlp.gmres_solve(on, gdev[a], tol=1e-10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mhlp.eval_grad(off, sigma=mu, mu=mu)
+        torch.cuda.synchronize()
+        build_ms = (time.perf_counter() - t0) * 1e3
+        r = autotune.tune(off, "grad", reps=5, use_cache=True, path=args.tune_cache, write=args.tune_write)
+        reps = 10
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        mhlp.eval_grad(off, sigma=mu, mu=mu)
+        e0.record()
+        for _ in range(reps):
+            mhlp.eval_grad(off, sigma=mu, mu=mu)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        launch[f"alpha={a:g}"] = {"launch_ms": round(ms, 4), "first_call_ms": round(build_ms, 2),
+                                  "nsplit": r["nsplit"], "near_pairs": off.n_near_pairs}
+    ms = float(np.mean([v["launch_ms"] for v in launch.values()]))
+    pairs = off.n_targets * off.n_sources
+    tf = pairs * FLOP_PER_PAIR_GRAD / (ms * 1e-3) / 1e12
+    res.update({"by_alpha": launch, "pairs_per_launch": pairs, "launch_ms": round(ms, 4),
+                "gpair_per_s": round(pairs / (ms * 1e-3) / 1e9, 3), "achieved_tflops": round(tf, 3),
+                "frac_of_fp64_peak": round(tf / FP64_PEAK_TFLOPS, 4),
+                "kernel": "far_grad_fp64<gradS,gradD> (+ grad_finalize when split)"})
+    return res
 
 
 def bench_volume(mhlp, wl, t, torch):

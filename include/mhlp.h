@@ -115,7 +115,7 @@ mhlp_status mhlp_plan_info(const mhlp_plan *plan, int64_t *n_targets, int64_t *n
    default gives about 1024 blocks.  set_split may reallocate the plan's
    partial-sum buffer (it synchronises the device then).
    mhlp_plan_autotune times the far evaluation (layers: 1 SLP, 2 DLP, 3 both,
-   4 the on-surface BIE operator) for nsplit = 1, 2, 4, ... (up to Np/4 and
+   4 the on-surface BIE operator, 5 the gradients of both, off-surface) for nsplit = 1, 2, 4, ... (up to Np/4 and
    256) plus the current value, reps timed launches each after one warm-up,
    with HIP events on `stream`, keeps the fewest splits within 1% of the
    fastest and reports it with its time (host outputs; cand/cand_ms receive up
@@ -141,6 +141,25 @@ mhlp_status mhlp_eval_dlp(const mhlp_plan *plan, const double *mu, double *u, in
    the interior limit).  Errors: MHLP_INVALID_ARG if the plan is not on-surface. */
 mhlp_status mhlp_apply_bie_operator(const mhlp_plan *onsurf, const double *mu, double *out, int32_t precision,
                                     void *stream);
+
+/* Target gradients of S[sigma] and D[mu] on an off-surface plan (the
+   near-boundary gradient of Sec. 4.4, for the scalar kernel):
+     grad S[sigma](x) = -(1/2pi) int alpha K1(alpha r)/r (x - y) sigma dS_y,
+     grad D[mu](x)    = (1/2pi) int [A n_y - ((x-y).n_y)(x - y)(alpha^2 K0 + 2A)/r^2] mu dS_y,
+   A = alpha K1(alpha r)/r.  The near panels of the plan are integrated with
+   the kernel split of the gradient: smooth, log, Cauchy (tau - z)^-1 and
+   (tau - z)^-2 parts with interpolatory weights on the upsampled panel, the
+   same Bernstein-radius tiers and subdivision as the potentials.
+   sigma, mu: device [N] (either may be NULL, not both); gs_x, gs_y (with
+   sigma) and gd_x, gd_y (with mu): device [M], overwritten, the x1 and x2
+   components in the caller's target order.  Targets must lie off the curve
+   (the gradient has no limit there).  FP64 throughout.  The first call on a
+   plan builds its gradient correction weights (64 doubles per near pair) and
+   synchronises the stream; later calls only enqueue.
+   Errors: MHLP_UNSUPPORTED on an on-surface plan; MHLP_INVALID_ARG for a
+   density without both of its outputs or outputs without their density. */
+mhlp_status mhlp_eval_grad(const mhlp_plan *plan, const double *sigma, const double *mu, double *gs_x, double *gs_y,
+                           double *gd_x, double *gd_y, void *stream);
 
 /* GMRES for (1/2 I + D) mu = g (Sec. 3.2), restarted, classical Gram-Schmidt
    with reorthogonalisation in FP64, judged by the true FP64 residual.  g, mu:

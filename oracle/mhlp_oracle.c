@@ -10,7 +10,7 @@
  *   DLP  u(x) = int_Gamma dG/dn_y mu(y) dS_y
  *             = int_Gamma alpha K1(alpha r) (x-y).n_y / (2 pi r) mu(y) dS_y
  *
- * and the target gradients of both (Sec. 4.6, the near-boundary gradient,
+ * and the target gradients of both (Sec. 4.4, the near-boundary gradient,
  * restated for the scalar kernel; r = |x - y|, A = alpha K1(alpha r)/r):
  *
  *   grad_x G       = A (y - x) / (2 pi)

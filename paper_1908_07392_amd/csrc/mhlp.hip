@@ -100,11 +100,12 @@ struct mhlp_plan {
     int32_t *near_tgt = nullptr;         /* [nnz] */
     double *near_ts = nullptr;           /* [nnz][2] */
     double *wslp = nullptr, *wdlp = nullptr; /* [nnz][16] */
+    double *wgrad = nullptr;  /* off-surface, built on first use: [4][nnz][16] gradient weights */
     int64_t nnz = 0;
     int32_t fill_mismatch = 0;
     int nsplit = 1;           /* source splits of the far field (small M)   */
     int32_t pps = 0;          /* panels per split                           */
-    double *part = nullptr;   /* [2][nsplit][M] partial sums                */
+    double *part = nullptr;   /* [2][nsplit][M] partial sums ([4][..] off-surface, for gradients) */
     NearParams np{};
     double near_factor = 1.2;
     int64_t part_cap = 0;     /* capacity of part (doubles)                 */
@@ -332,6 +333,28 @@ __global__ void near_weights_kernel(GeoView G, const double *__restrict__ tx, co
     near_weights_body(q, G, tx, ty, onsurf, panel, tgt, ts, alpha, P, wsl, wdl);
 }
 
+/* gradient correction weights of the off-surface pairs: wg[b][q][j] */
+__global__ void near_grad_weights_kernel(GeoView G, const double *__restrict__ tx, const double *__restrict__ ty,
+                                         const int32_t *__restrict__ panel, const int32_t *__restrict__ tgt,
+                                         const double *__restrict__ ts, int64_t nnz, double alpha, NearParams P,
+                                         double *__restrict__ wg)
+{
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= nnz) return;
+    const int64_t p = panel[q], i = tgt[q];
+    double W[4][16];
+    if (p < 0 || p >= G.Np) {
+        for (int b = 0; b < 4; ++b)
+            for (int j = 0; j < 16; ++j) W[b][j] = 0.0;
+    } else {
+        cplx a[16];
+        for (int m = 0; m < 16; ++m) a[m] = mk(G.pa[(16 * p + m) * 2], G.pa[(16 * p + m) * 2 + 1]);
+        pair_grad_weights(a, G.ph[p], mk(tx[i], ty[i]), mk(ts[2 * q], ts[2 * q + 1]), alpha, P, W);
+    }
+    for (int b = 0; b < 4; ++b)
+        for (int j = 0; j < 16; ++j) wg[(b * nnz + q) * 16 + j] = W[b][j];
+}
+
 /* ------------------------------------------------------------------------ */
 /* far field + corrections, FP64                                             */
 /* ------------------------------------------------------------------------ */
@@ -556,6 +579,147 @@ __global__ __launch_bounds__(FT_THREADS) void far_eval_mixed(FarArgs A)
 /*   u_i = sum_{j != i} K0(alpha r_ij)/(2 pi) w_j f_j + (w_i/h^2) Wcell f_i    */
 /* Sources are targets; the self pair (r == 0) is skipped in the sum.        */
 /* ------------------------------------------------------------------------ */
+/* ------------------------------------------------------------------------ */
+/* target gradients of the layer potentials, FP64 (off-surface plans)        */
+/*   grad S:  -(1/2pi) sum_j alpha K1(alpha r)/r (x - y_j) w_j sigma_j        */
+/*   grad D:  (1/2pi) sum_j [A n_j - ((x - y_j).n_j)(x - y_j)(alpha^2 K0 + 2A)/r^2] w_j mu_j, */
+/*            A = alpha K1(alpha r)/r                                          */
+/* with the listed near panels replaced by their gradient correction weights. */
+/* ------------------------------------------------------------------------ */
+struct GradArgs {
+    const double *sx, *sy, *sw, *snx, *sny;
+    const double *sigma, *mu;
+    const double *tx, *ty;
+    int64_t M, Np, nnz;
+    const int32_t *nptr, *npan, *perm;
+    const double *wg;  /* [4][nnz][16] */
+    double alpha;
+    int32_t pps;
+    double *part;      /* [4][nsplit][M] when split */
+    double *out[4];    /* d/dx1 S, d/dx2 S, d/dx1 D, d/dx2 D (caller order) */
+};
+
+template <bool GS, bool GD>
+__device__ __forceinline__ void grad_epilogue(const GradArgs &A, int64_t i, const double *acc)
+{
+    double c[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int32_t q = A.nptr[i]; q < A.nptr[i + 1]; ++q) {
+        const int64_t p = A.npan[q];
+        if (p < 0) continue;
+        for (int jj = 0; jj < 16; ++jj) {
+            const int64_t o = 16 * (int64_t)q + jj;
+            if (GS) {
+                const double sg = A.sigma[16 * p + jj];
+                c[0] = fma(A.wg[o], sg, c[0]);
+                c[1] = fma(A.wg[A.nnz * 16 + o], sg, c[1]);
+            }
+            if (GD) {
+                const double m = A.mu[16 * p + jj];
+                c[2] = fma(A.wg[2 * A.nnz * 16 + o], m, c[2]);
+                c[3] = fma(A.wg[3 * A.nnz * 16 + o], m, c[3]);
+            }
+        }
+    }
+    const int64_t o = A.perm ? (int64_t)A.perm[i] : i;
+    if (GS) {
+        A.out[0][o] = fma(-INV_2PI, acc[0], c[0]);
+        A.out[1][o] = fma(-INV_2PI, acc[1], c[1]);
+    }
+    if (GD) {
+        A.out[2][o] = fma(INV_2PI, acc[2], c[2]);
+        A.out[3][o] = fma(INV_2PI, acc[3], c[3]);
+    }
+}
+
+template <bool GS, bool GD>
+__global__ void grad_finalize(GradArgs A, int nsplit)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= A.M) return;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < nsplit; ++k)
+        for (int b = 0; b < 4; ++b)
+            if ((b < 2 && GS) || (b >= 2 && GD)) acc[b] += A.part[((int64_t)b * nsplit + k) * A.M + i];
+    grad_epilogue<GS, GD>(A, i, acc);
+}
+
+template <bool GS, bool GD, bool SPLIT>
+__global__ __launch_bounds__(FT_THREADS) void far_grad_fp64(GradArgs A)
+{
+    __shared__ double lx[FT_SRC], ly[FT_SRC], lq[FT_SRC], ldx[FT_SRC], ldy[FT_SRC];
+    const int64_t i = blockIdx.x * (int64_t)FT_THREADS + threadIdx.x;
+    const bool valid = i < A.M;
+    const double x = valid ? A.tx[i] : 0.0, y = valid ? A.ty[i] : 0.0;
+    const int64_t pb = SPLIT ? (int64_t)blockIdx.y * A.pps : 0;
+    const int64_t pe = SPLIT ? min(A.Np, pb + A.pps) : A.Np;
+    int32_t k = 0, kend = 0;
+    if (valid) {
+        k = A.nptr[i];
+        kend = A.nptr[i + 1];
+        while (k < kend && A.npan[k] >= 0 && A.npan[k] < pb) ++k;
+    }
+    int32_t nxt = (k < kend) ? A.npan[k] : INT_MAX;
+    const FarConst fc = far_const(A.alpha);
+    const double a2 = A.alpha * A.alpha;
+    double sx = 0.0, sy = 0.0, dx = 0.0, dy = 0.0;
+    for (int64_t base = 16 * pb; base < 16 * pe; base += FT_SRC) {
+        __syncthreads();
+        const int64_t j = base + threadIdx.x;
+        if (j < 16 * pe) {
+            const double wj = A.sw[j];
+            lx[threadIdx.x] = A.sx[j];
+            ly[threadIdx.x] = A.sy[j];
+            if (GS) lq[threadIdx.x] = wj * A.sigma[j];
+            if (GD) {
+                const double m = wj * A.mu[j];
+                ldx[threadIdx.x] = m * A.snx[j];
+                ldy[threadIdx.x] = m * A.sny[j];
+            }
+        }
+        __syncthreads();
+        const int32_t p0 = (int32_t)(base / 16);
+        const int npl = (pe - p0) < 16 ? (int)(pe - p0) : 16;
+        for (int pl = 0; pl < npl; ++pl) {
+            if (p0 + pl == nxt) {
+                ++k;
+                nxt = (k < kend) ? A.npan[k] : INT_MAX;
+                continue;
+            }
+#pragma unroll 1
+            for (int s = 0; s < 16; s += 2) {
+                const FarTab T = far_table();
+                const int l0 = pl * 16 + s, l1 = l0 + 1;
+                const double ex0 = x - lx[l0], ey0 = y - ly[l0];
+                const double ex1 = x - lx[l1], ey1 = y - ly[l1];
+                const double r20 = fma(ex0, ex0, ey0 * ey0), r21 = fma(ex1, ex1, ey1 * ey1);
+                K01 o0, o1;
+                k01_far2<GD, true>(T, fc, r20, r21, o0, o1);
+                if (GS) {
+                    const double c0 = o0.ak1r * lq[l0], c1 = o1.ak1r * lq[l1];
+                    sx = fma(c1, ex1, fma(c0, ex0, sx));
+                    sy = fma(c1, ey1, fma(c0, ey0, sy));
+                }
+                if (GD) {
+                    const double n0 = fma(ex0, ldx[l0], ey0 * ldy[l0]), n1 = fma(ex1, ldx[l1], ey1 * ldy[l1]);
+                    const double b0 = n0 * fma(a2, o0.k0, 2.0 * o0.ak1r) * o0.ri2;
+                    const double b1 = n1 * fma(a2, o1.k0, 2.0 * o1.ak1r) * o1.ri2;
+                    dx = fma(-b1, ex1, fma(o1.ak1r, ldx[l1], fma(-b0, ex0, fma(o0.ak1r, ldx[l0], dx))));
+                    dy = fma(-b1, ey1, fma(o1.ak1r, ldy[l1], fma(-b0, ey0, fma(o0.ak1r, ldy[l0], dy))));
+                }
+            }
+        }
+    }
+    if (!valid) return;
+    const double acc[4] = {sx, sy, dx, dy};
+    if (SPLIT) {
+        const int ns = gridDim.y;
+        for (int b = 0; b < 4; ++b)
+            if ((b < 2 && GS) || (b >= 2 && GD)) A.part[((int64_t)b * ns + blockIdx.y) * A.M + i] = acc[b];
+    } else {
+        grad_epilogue<GS, GD>(A, i, acc);
+    }
+}
+
 struct VolArgs {
     const double *x, *y, *w, *f;
     int64_t n;
@@ -981,7 +1145,7 @@ static mhlp_status plan_set_split(mhlp_plan *P, int ns)
     if (ns > Np) ns = (int)Np;
     const int32_t pps = (int32_t)((Np + ns - 1) / ns);
     const int nsplit = (int)((Np + pps - 1) / pps);
-    const int64_t need = nsplit > 1 ? 2 * (int64_t)nsplit * P->M : 0;
+    const int64_t need = nsplit > 1 ? (P->onsurf ? 2 : 4) * (int64_t)nsplit * P->M : 0;
     if (need > P->part_cap) {
         if (P->part) {
             HIPCHECK(hipDeviceSynchronize()); /* queued launches may still use it */
@@ -1009,7 +1173,7 @@ extern "C" mhlp_status mhlp_plan_destroy(mhlp_plan *P)
             if (gr.exec) (void)hipGraphExecDestroy(gr.exec);
     if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
     void *ptrs[] = {P->near_ptr, P->near_panel, P->near_tgt, P->near_ts, P->wslp, P->wdlp,
-                    P->ws,       P->hdev,       P->part,     P->gdev,    P->perm};
+                    P->ws,       P->hdev,       P->part,     P->gdev,    P->perm, P->wgrad};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (P->hhost) (void)hipHostFree(P->hhost);
@@ -1305,8 +1469,10 @@ extern "C" mhlp_status mhlp_plan_autotune(mhlp_plan *P, int32_t layers, int32_t 
                                           double *cand_ms, int32_t cap, int32_t *n_cand)
 {
     if (!P) return fail(MHLP_INVALID_ARG, "plan is NULL");
-    if (layers < 1 || layers > 4 || layers == 0) return fail(MHLP_INVALID_ARG, "layers must be 1, 2, 3 or 4");
+    if (layers < 1 || layers > 5) return fail(MHLP_INVALID_ARG, "layers must be 1, 2, 3, 4 or 5");
     if (layers == 4 && !P->onsurf) return fail(MHLP_INVALID_ARG, "layers 4 (BIE operator) needs an on-surface plan");
+    if (layers == 5 && P->onsurf) return fail(MHLP_INVALID_ARG, "layers 5 (gradients) needs an off-surface plan");
+    if (layers == 5 && precision != MHLP_FP64) return fail(MHLP_INVALID_ARG, "gradients are FP64 only");
     if (precision != MHLP_FP64 && precision != MHLP_MIXED) return fail(MHLP_INVALID_ARG, "unknown precision");
     if (reps < 1 || reps > 1000) return fail(MHLP_INVALID_ARG, "reps must be in [1, 1000]");
     if (cap < 0 || (cap > 0 && (!cand || !cand_ms))) return fail(MHLP_INVALID_ARG, "candidate arrays");
@@ -1317,7 +1483,7 @@ extern "C" mhlp_status mhlp_plan_autotune(mhlp_plan *P, int32_t layers, int32_t 
     if (std::find(cs.begin(), cs.end(), P->nsplit) == cs.end()) cs.push_back(P->nsplit);
     double *dens = nullptr, *out = nullptr;
     TRY(dalloc(&dens, N));
-    mhlp_status s = dalloc(&out, 2 * M);
+    mhlp_status s = dalloc(&out, 4 * M);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (s == MHLP_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
         s = fail(MHLP_HIP_ERROR, "hipEventCreate");
@@ -1329,6 +1495,7 @@ extern "C" mhlp_status mhlp_plan_autotune(mhlp_plan *P, int32_t layers, int32_t 
     for (size_t c = 0; c < cs.size() && s == MHLP_OK; ++c) {
         if ((s = plan_set_split(P, cs[c]))) break;
         auto run = [&]() -> mhlp_status {
+            if (layers == 5) return mhlp_eval_grad(P, dens, dens, out, out + M, out + 2 * M, out + 3 * M, st);
             const double *sg = (layers & 1) ? dens : nullptr, *mu = (layers & 2 || layers == 4) ? dens : nullptr;
             return launch_far(P, sg, mu, sg ? out : nullptr, mu ? out + M : nullptr, layers == 4 ? 0.5 : 0.0,
                               precision, st);
@@ -1400,6 +1567,85 @@ extern "C" mhlp_status mhlp_apply_bie_operator(const mhlp_plan *P, const double 
     if (!mu || !out) return fail(MHLP_INVALID_ARG, "mu or out is NULL");
     if (mu == out) return fail(MHLP_INVALID_ARG, "mu and out must not alias");
     return launch_far(P, nullptr, mu, nullptr, out, 0.5, precision, (hipStream_t)stream);
+}
+
+/* ------------------------------------------------------------------------ */
+/* target gradients                                                          */
+/* ------------------------------------------------------------------------ */
+static mhlp_status ensure_grad_weights(mhlp_plan *P, hipStream_t st)
+{
+    if (P->wgrad || P->nnz == 0) return MHLP_OK;
+    TRY(dalloc(&P->wgrad, 64 * P->nnz));
+    near_grad_weights_kernel<<<nblocks(P->nnz, 64), 64, 0, st>>>(view(P->g), P->tx, P->ty, P->near_panel,
+                                                                  P->near_tgt, P->near_ts, P->nnz, P->alpha, P->np,
+                                                                  P->wgrad);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        (void)hipFree(P->wgrad);
+        P->wgrad = nullptr;
+        return fail(MHLP_HIP_ERROR, std::string("gradient weights: ") + hipGetErrorString(e));
+    }
+    return MHLP_OK;
+}
+
+template <bool GS, bool GD>
+static void launch_grad_t(const GradArgs &A, int nsplit, hipStream_t st)
+{
+    const unsigned nb = nblocks(A.M, FT_THREADS);
+    if (nsplit <= 1) {
+        far_grad_fp64<GS, GD, false><<<nb, FT_THREADS, 0, st>>>(A);
+        return;
+    }
+    far_grad_fp64<GS, GD, true><<<dim3(nb, nsplit), FT_THREADS, 0, st>>>(A);
+    grad_finalize<GS, GD><<<nblocks(A.M, 256), 256, 0, st>>>(A, nsplit);
+}
+
+extern "C" mhlp_status mhlp_eval_grad(const mhlp_plan *Pc, const double *sigma, const double *mu, double *gs_x,
+                                      double *gs_y, double *gd_x, double *gd_y, void *stream)
+{
+    if (!Pc) return fail(MHLP_INVALID_ARG, "plan is NULL");
+    if (Pc->onsurf) return fail(MHLP_UNSUPPORTED, "eval_grad needs an off-surface plan (targets off the curve)");
+    const bool gs = sigma != nullptr, gd = mu != nullptr;
+    if (!gs && !gd) return fail(MHLP_INVALID_ARG, "no density given");
+    if (gs != (gs_x != nullptr) || gs != (gs_y != nullptr) || gd != (gd_x != nullptr) || gd != (gd_y != nullptr))
+        return fail(MHLP_INVALID_ARG, "each density needs both of its gradient outputs (and only then)");
+    mhlp_plan *P = const_cast<mhlp_plan *>(Pc); /* gradient weights are built on first use */
+    hipStream_t st = (hipStream_t)stream;
+    TRY(ensure_grad_weights(P, st));
+    const mhlp_geometry *g = P->g;
+    GradArgs A;
+    A.sx = g->soa;
+    A.sy = g->soa + g->N;
+    A.sw = g->w;
+    A.snx = g->nx;
+    A.sny = g->ny;
+    A.sigma = sigma;
+    A.mu = mu;
+    A.tx = P->tx;
+    A.ty = P->ty;
+    A.M = P->M;
+    A.Np = g->Np;
+    A.nnz = P->nnz;
+    A.nptr = P->near_ptr;
+    A.npan = P->near_panel;
+    A.perm = P->perm;
+    A.wg = P->wgrad;
+    A.alpha = P->alpha;
+    A.pps = P->pps;
+    A.part = P->part;
+    A.out[0] = gs_x;
+    A.out[1] = gs_y;
+    A.out[2] = gd_x;
+    A.out[3] = gd_y;
+    if (gs && gd)
+        launch_grad_t<true, true>(A, P->nsplit, st);
+    else if (gs)
+        launch_grad_t<true, false>(A, P->nsplit, st);
+    else
+        launch_grad_t<false, true>(A, P->nsplit, st);
+    HIPCHECK(hipGetLastError());
+    return MHLP_OK;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -412,9 +412,11 @@ __host__ __device__ inline void leaf_apply(const cplx *a, double ta, double tb, 
 
 /* Recursive bisection of [ta, tb] towards the target until every piece either
    satisfies alpha h <= ah_max or is far enough that its contribution is below
-   exp(-far_exp) of the kernel at the target's distance scale. */
-__host__ __device__ inline void subdivide(const cplx *a, double h, double ta, double tb, cplx z, cplx tstar,
-                                          double alpha, const NearParams &P, double *Ws, double *Wd)
+   exp(-far_exp) of the kernel at the target's distance scale; leaf(a, b) is
+   called for every final piece. */
+template <class Leaf>
+__host__ __device__ inline void subdivide_t(const cplx *a, double h, double ta, double tb, cplx z, cplx tstar,
+                                            double alpha, const NearParams &P, Leaf &&leaf)
 {
     double st_a[64], st_b[64];
     int top = 0;
@@ -425,25 +427,32 @@ __host__ __device__ inline void subdivide(const cplx *a, double h, double ta, do
         --top;
         const double a0 = st_a[top], b0 = st_b[top];
         const double hs = sub_len(h, a0, b0);
-        bool leaf = alpha * hs <= P.ah_max || top >= 60 || (b0 - a0) < 1e-12;
-        if (!leaf) {
+        bool is_leaf = alpha * hs <= P.ah_max || top >= 60 || (b0 - a0) < 1e-12;
+        if (!is_leaf) {
             const double mid = 0.5 * (a0 + b0), half = 0.5 * (b0 - a0);
             const cplx ss = (1.0 / half) * (tstar - mk(mid, 0.0));
             if (bernstein_rho(ss) >= P.rho_direct) {
                 cplx pm, dpm;
                 leg_eval(a, mk(mid, 0.0), pm, dpm);
                 const double dist = cabs(pm - z) - 0.5 * hs;
-                if (alpha * dist >= P.far_exp) leaf = true;
+                if (alpha * dist >= P.far_exp) is_leaf = true;
             }
         }
-        if (leaf) {
-            leaf_apply(a, a0, b0, z, tstar, alpha, P, Ws, Wd);
+        if (is_leaf) {
+            leaf(a0, b0);
         } else {
             const double m = 0.5 * (a0 + b0);
             st_a[top] = a0; st_b[top] = m; ++top;
             st_a[top] = m; st_b[top] = b0; ++top;
         }
     }
+}
+
+__host__ __device__ inline void subdivide(const cplx *a, double h, double ta, double tb, cplx z, cplx tstar,
+                                          double alpha, const NearParams &P, double *Ws, double *Wd)
+{
+    subdivide_t(a, h, ta, tb, z, tstar, alpha, P,
+                [&](double a0, double b0) { leaf_apply(a, a0, b0, z, tstar, alpha, P, Ws, Wd); });
 }
 
 /* Correction weights of target z against a panel with Legendre coefficients a
@@ -475,6 +484,164 @@ __host__ __device__ inline void pair_weights(const cplx *a, double h, cplx z, in
         leaf_apply(a, -1.0, 1.0, z, tstar, alpha, P, Ws, Wd);
     else
         subdivide(a, h, -1.0, 1.0, z, tstar, alpha, P, Ws, Wd);
+}
+
+/* ====================================================================== */
+/* Target gradients (Sec. 4.4 restated for the scalar kernel).             */
+/* ====================================================================== */
+/* With e = x - y, r = |e|, n = n_y and the split alpha K1(alpha r)/r =
+   S(r^2) + L(r^2) log r + 1/r^2 (the double-layer split of Sec. 4.1:
+   S = alpha^2 (K1^S/z + (I1/z) log alpha), L = alpha^2 I1/z, z = alpha r),
+     grad_x G       = -(1/2pi) e [S + L log r + 1/r^2],
+     grad_x dG/dn_y = (1/2pi) grad_x [(e.n) (S + L log r + 1/r^2)]
+                    = (1/2pi) { [n S + 2 (e.n) S' e]
+                              + [n L + 2 (e.n) L' e] log r
+                              + (e.n) L e / r^2
+                              + grad_x (e.n)/r^2 },          ' = d/d(r^2).
+   Each bracket is smooth, smooth times log r, smooth times the Cauchy-type
+   vector e/r^2, or the gradient of the Laplace double layer.  In complex
+   notation (vector (v1, v2) <-> v1 + i v2, tau - z = (s - s*) Q(s) on the
+   local parameter s, ds_arc = |tau'| ds):
+     int f e/r^2 ds_arc = -conj( int f |tau'| / Q  ds/(s - s*) )   (f real),
+     int mu (e.n)/r^2 ds_arc = Im F(z),  F(z) = int mu dtau/(tau - z),
+     grad Im F = (Im F', Re F'),  F'(z) = int mu tau'/Q^2 ds/(s - s*)^2.
+   The (s - s*)^-1 and (s - s*)^-2 integrals use the Cauchy moments and the
+   moments of (s - s*)^-2, the log integral the log moments, all through the
+   interpolatory weights of the upsampled rule (Sec. 4.3).  The paper lowers
+   a (tau - z)^-3 singularity of the stresslet by parts; for the scalar
+   kernel the highest order is (tau - z)^-2, integrated directly as the paper
+   does for its own (tau - z)^-2 terms.
+   Weight blocks: W[0], W[1] = d/dx1, d/dx2 of S; W[2], W[3] = of D.       */
+
+/* MH[m] = int P_m(t)/(t - s)^2 dt, m = 0..N-1, from the Cauchy moments MC
+   (m = 0..N-2): by parts, MH_m = B_m + int P_m'/(t - s) dt with
+   B_m = -1/(1 - s) - (-1)^m/(1 + s); with P_{m+1}' - P_{m-1}' = (2m+1) P_m
+   and B_{m+1} = B_{m-1} this gives MH_{m+1} = MH_{m-1} + (2m+1) MC_m,
+   MH_0 = B_0, MH_1 = B_1 + MC_0.                                          */
+template <int N>
+__host__ __device__ inline void hyper_moments(cplx s, const cplx *MC, cplx *MH)
+{
+    const cplx ia = mk(1.0, 0.0) / (mk(1.0, 0.0) - s), ib = mk(1.0, 0.0) / (mk(1.0, 0.0) + s);
+    MH[0] = -(ia + ib);
+    MH[1] = (ib - ia) + MC[0];
+    for (int m = 1; m + 1 < N; ++m) MH[m + 1] = MH[m - 1] + (2.0 * m + 1.0) * MC[m];
+}
+
+/* Direct (plain quadrature) gradient weights at one node. */
+__host__ __device__ inline void direct_node_grad(cplx z, const NodeGeo &g, double alpha, double *w4)
+{
+    const cplx e = z - g.tau;
+    const double r2 = cabs2(e);
+    const K01 o = k01_fp64<true, true>(r2, alpha, 0.25 * alpha * alpha, 4.0 / alpha);
+    const double sp_ = cabs(g.dtau);
+    const double nx = -g.dtau.im / sp_, ny = g.dtau.re / sp_;
+    const double en = e.re * nx + e.im * ny;
+    const double b = en * fma(alpha * alpha, o.k0, 2.0 * o.ak1r) / r2;
+    const double c = INV_2PI * g.w;
+    w4[0] = -c * o.ak1r * e.re;
+    w4[1] = -c * o.ak1r * e.im;
+    w4[2] = c * fma(o.ak1r, nx, -b * e.re);
+    w4[3] = c * fma(o.ak1r, ny, -b * e.im);
+}
+
+/* Fold NW blocks of node weights of a rule with NQ nodes on [ta, tb] of the
+   parent panel back to the parent's 16 nodes. */
+template <int NQ, int NW>
+__host__ __device__ inline void fold_add_n(const double *tq, double ta, double tb, const double (*WQ)[NQ],
+                                           double (*W)[16])
+{
+    const double mid = 0.5 * (ta + tb), half = 0.5 * (tb - ta);
+    for (int k = 0; k < NQ; ++k) {
+        double l[16];
+        lagrange16(mid + half * tq[k], l);
+        for (int b = 0; b < NW; ++b)
+            for (int j = 0; j < 16; ++j) W[b][j] = fma(l[j], WQ[b][k], W[b][j]);
+    }
+}
+
+template <int NQ>
+__host__ __device__ inline void leaf_direct_grad(const cplx *a, const double *tq, const double *wq, double ta,
+                                                 double tb, cplx z, double alpha, double (*W)[16])
+{
+    NodeGeo g[NQ];
+    double WQ[4][NQ];
+    rule_geo<NQ>(a, tq, wq, ta, tb, g);
+    for (int k = 0; k < NQ; ++k) {
+        double w4[4];
+        direct_node_grad(z, g[k], alpha, w4);
+        for (int b = 0; b < 4; ++b) WQ[b][k] = w4[b];
+    }
+    fold_add_n<NQ, 4>(tq, ta, tb, WQ, W);
+}
+
+/* Kernel split on the 32-point upsampled rule of [ta, tb] (target off the
+   curve, complex parent preimage tstar). */
+__host__ __device__ inline void leaf_split32_grad(const cplx *a, double ta, double tb, cplx z, cplx tstar,
+                                                  double alpha, double (*W)[16])
+{
+    constexpr int NQ = 32;
+    NodeGeo g[NQ];
+    double WQ[4][NQ];
+    rule_geo<NQ>(a, GL32_T, GL32_W, ta, tb, g);
+    const double mid = 0.5 * (ta + tb), half = 0.5 * (tb - ta);
+    const cplx ss = (1.0 / half) * (tstar - mk(mid, 0.0));
+    cplx MC[NQ + 1], ML[NQ], MH[NQ], pc[NQ], pl[NQ], ph[NQ];
+    legendre_moments<NQ>(ss, bernstein_rho(ss), MC, ML);
+    hyper_moments<NQ>(ss, MC, MH);
+    moments_to_weights<NQ>(LEGW32, MC, pc); /* (s - s*)^-1 */
+    moments_to_weights<NQ>(LEGW32, ML, pl); /* log(s - s*)  */
+    moments_to_weights<NQ>(LEGW32, MH, ph); /* (s - s*)^-2 */
+    const double la = log(alpha);
+    const double a2 = alpha * alpha, a4q = 0.25 * a2 * a2;
+    for (int k = 0; k < NQ; ++k) {
+        const cplx tk = mk(mid + half * GL32_T[k], 0.0);
+        const cplx Q = half * leg_divdiff(a, tk, tstar); /* (tau - z)/(s - s*) */
+        const double sp_ = cabs(g[k].dtau);
+        const double logw = fma(sp_, pl[k].re, g[k].w * log(cabs(Q)));
+        const cplx e = z - g[k].tau;
+        const SplitG sg = split_k01_grad(alpha * cabs(e));
+        const double S = a2 * fma(sg.s.i1z, la, sg.s.k1sz), L = a2 * sg.s.i1z;
+        const double Sq = a4q * fma(sg.i1z_q, la, sg.k1sz_q), Lq = a4q * sg.i1z_q;
+        const double nx = -g[k].dtau.im / sp_, ny = g[k].dtau.re / sp_;
+        const double en = e.re * nx + e.im * ny;
+        const double Aw = fma(S, g[k].w, L * logw);          /* smooth + log, order 0 */
+        const double Bw = 2.0 * en * fma(Sq, g[k].w, Lq * logw); /* from S', L'       */
+        const cplx cS = pc[k] * (mk(sp_, 0.0) / Q);            /* Cauchy, |tau'|/Q   */
+        const cplx cH = ph[k] * (g[k].dtau / (Q * Q));         /* (s - s*)^-2        */
+        WQ[0][k] = INV_2PI * fma(-e.re, Aw, cS.re);
+        WQ[1][k] = INV_2PI * fma(-e.im, Aw, -cS.im);
+        WQ[2][k] = INV_2PI * (fma(nx, Aw, Bw * e.re) - en * L * cS.re + cH.im);
+        WQ[3][k] = INV_2PI * (fma(ny, Aw, Bw * e.im) + en * L * cS.im + cH.re);
+    }
+    fold_add_n<NQ, 4>(GL32_T, ta, tb, WQ, W);
+}
+
+__host__ __device__ inline void leaf_apply_grad(const cplx *a, double ta, double tb, cplx z, cplx tstar,
+                                                double alpha, const NearParams &P, double (*W)[16])
+{
+    const double mid = 0.5 * (ta + tb), half = 0.5 * (tb - ta);
+    const cplx ss = (1.0 / half) * (tstar - mk(mid, 0.0));
+    const double rho = bernstein_rho(ss);
+    if (rho >= P.rho_direct)
+        leaf_direct_grad<16>(a, GL16_T, GL16_W, ta, tb, z, alpha, W);
+    else if (rho >= P.rho_split)
+        leaf_direct_grad<32>(a, GL32_T, GL32_W, ta, tb, z, alpha, W);
+    else
+        leaf_split32_grad(a, ta, tb, z, tstar, alpha, W);
+}
+
+/* Gradient correction weights of an off-curve target z against a panel
+   (same tiers and subdivision as the potentials). */
+__host__ __device__ inline void pair_grad_weights(const cplx *a, double h, cplx z, cplx tstar, double alpha,
+                                                  const NearParams &P, double (*W)[16])
+{
+    for (int b = 0; b < 4; ++b)
+        for (int j = 0; j < 16; ++j) W[b][j] = 0.0;
+    if (alpha * h <= P.ah_max)
+        leaf_apply_grad(a, -1.0, 1.0, z, tstar, alpha, P, W);
+    else
+        subdivide_t(a, h, -1.0, 1.0, z, tstar, alpha, P,
+                    [&](double a0, double b0) { leaf_apply_grad(a, a0, b0, z, tstar, alpha, P, W); });
 }
 
 } // namespace mhlp

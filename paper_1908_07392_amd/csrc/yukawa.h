@@ -46,13 +46,14 @@ __host__ __device__ __forceinline__ T horner(const T (&c)[N], T x)
 struct K01 {
     double k0;
     double ak1r;
+    double ri2; /* 1/r^2 (far-field evaluators only; dropped where unused) */
 };
 
 /* r2 = |x-y|^2 > 0; a = alpha, a2q = alpha^2/4, a4 = 4/alpha */
 template <bool SLP, bool DLP>
 __host__ __device__ __forceinline__ K01 k01_fp64(double r2, double a, double a2q, double a4)
 {
-    K01 o{0.0, 0.0};
+    K01 o{0.0, 0.0, 0.0};
     const double q = a2q * r2; /* z^2/4 */
     if (q <= 1.0) {
         const double lq = log(q); /* 2 log(z/2) */
@@ -236,7 +237,7 @@ __device__ __forceinline__ double far_piece(FarTab T, const FarConst &c, double 
 template <bool SLP, bool DLP>
 __device__ __forceinline__ K01 far_finish(const FarConst &c, double ri, double z, double e, double p, double dpdu)
 {
-    K01 o{0.0, 0.0};
+    K01 o{0.0, 0.0, ri * ri};
     if (SLP && DLP) {
         o.k0 = e * p;
         const double iz = c.ia * ri; /* 1/z */
@@ -254,7 +255,7 @@ __device__ __forceinline__ K01 far_finish(const FarConst &c, double ri, double z
 template <bool SLP, bool DLP>
 __device__ __forceinline__ K01 k01_far_small(FarTab T, double r2, double a2q)
 {
-    K01 o{0.0, 0.0};
+    K01 o{0.0, 0.0, lean_rcp(r2)};
     const double q = a2q * r2; /* z^2/4 */
     const double lq = lean_log01(T, q); /* 2 log(z/2) */
     if (SLP && DLP) {
@@ -263,12 +264,12 @@ __device__ __forceinline__ K01 k01_far_small(FarTab T, double r2, double a2q)
         const double r0 = hornercd<13>(T->ks_r0, q, dr0);
         o.k0 = fma(-0.5 * lq, i0, r0);
         /* alpha^2 K1/z = I0/r^2 + alpha^2 (lq I0'/4 - R0'/2) */
-        o.ak1r = fma(4.0 * a2q, fma(0.25 * lq, di0, -0.5 * dr0), i0 * lean_rcp(r2));
+        o.ak1r = fma(4.0 * a2q, fma(0.25 * lq, di0, -0.5 * dr0), i0 * o.ri2);
     } else if (SLP) {
         o.k0 = fma(-0.5 * lq, hornerc<12>(T->ks_i0, q), hornerc<13>(T->ks_r0, q));
     } else {
         const double t = fma(0.5 * lq, hornerc<12>(T->ks_i1z, q), -0.25 * hornerc<13>(T->ks_r1, q));
-        o.ak1r = fma(4.0 * a2q, t, lean_rcp(r2));
+        o.ak1r = fma(4.0 * a2q, t, o.ri2);
     }
     return o;
 }
@@ -358,32 +359,65 @@ struct Split {
     double i0, k0s, i1z, k1sz;
 };
 
-__host__ __device__ inline Split split_k01(double z)
+/* With the target gradient the double layer also needs d/dq of I1z and K1Sz
+   (q = z^2/4): i1z_q = (1/2) sum_{n>=1} n q^(n-1)/(n!(n+1)!), and the same
+   with the psi weights for K1Sz; the n-th derivative coefficient is the
+   (n-1)-th value coefficient divided by n+1. */
+struct SplitG {
+    Split s;
+    double i1z_q, k1sz_q;
+};
+
+template <bool GRAD>
+__host__ __device__ inline void split_series(double z, Split &s, double *i1z_q, double *k1sz_q)
 {
     const double q = 0.25 * z * z;
     double a = 1.0, b = 1.0; /* q^n/(n!)^2 and q^n/(n!(n+1)!) */
     double p1 = -EULER_G, p2 = 1.0 - EULER_G;
-    double si0 = 0.0, si1 = 0.0, sr0 = 0.0, sr1 = 0.0;
+    double si0 = 0.0, si1 = 0.0, sr0 = 0.0, sr1 = 0.0, sd1 = 0.0, sdr1 = 0.0;
     for (int n = 0; n < 80; ++n) {
         si0 += a;
         si1 += b;
         sr0 = fma(p1, a, sr0);
         sr1 = fma(p1 + p2, b, sr1);
-        if (a <= 1e-18 * si0 && b <= 1e-18 * si1) break;
         const double n1 = n + 1.0;
+        if (GRAD) {
+            /* term n+1 of the derivative series: q^n/(n!(n+2)!) = b/(n+2) with
+               the psi weights of index n+1 */
+            const double c = b / (n1 + 1.0);
+            sd1 += c;
+            sdr1 = fma(p1 + p2 + 1.0 / n1 + 1.0 / (n1 + 1.0), c, sdr1);
+        }
+        if (a <= 1e-18 * si0 && b <= 1e-18 * si1) break;
         a *= q / (n1 * n1);
         b *= q / (n1 * (n1 + 1.0));
         p1 += 1.0 / n1;
         p2 += 1.0 / (n1 + 1.0);
     }
-    Split s;
     s.i0 = si0;
     s.i1z = 0.5 * si1;
     /* K0 = -log(z/2) I0 + R0  =>  K0 + I0 log z = I0 log 2 + R0 */
     s.k0s = fma(LN2, si0, sr0);
     /* K1 = 1/z + log(z/2) I1 - (z/4) R1  =>  (K1 - I1 log z - 1/z)/z = -log2 I1/z - R1/4 */
     s.k1sz = fma(-LN2, s.i1z, -0.25 * sr1);
+    if (GRAD) {
+        *i1z_q = 0.5 * sd1;
+        *k1sz_q = fma(-LN2, *i1z_q, -0.25 * sdr1);
+    }
+}
+
+__host__ __device__ inline Split split_k01(double z)
+{
+    Split s;
+    split_series<false>(z, s, nullptr, nullptr);
     return s;
+}
+
+__host__ __device__ inline SplitG split_k01_grad(double z)
+{
+    SplitG g;
+    split_series<true>(z, g.s, &g.i1z_q, &g.k1sz_q);
+    return g;
 }
 
 /* ---------------------------------------------------------------------- */

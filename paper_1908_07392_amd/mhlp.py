@@ -70,6 +70,7 @@ _SIGS = {
     "mhlp_eval_slp": ([_V, _V, _V, ctypes.c_int32, _V], ctypes.c_int32),
     "mhlp_eval_dlp": ([_V, _V, _V, ctypes.c_int32, _V], ctypes.c_int32),
     "mhlp_apply_bie_operator": ([_V, _V, _V, ctypes.c_int32, _V], ctypes.c_int32),
+    "mhlp_eval_grad": ([_V, _V, _V, _V, _V, _V, _V, _V], ctypes.c_int32),
     "mhlp_gmres_solve": ([_V, _V, _V, ctypes.POINTER(GmresOpts), ctypes.POINTER(GmresInfo), _V], ctypes.c_int32),
     "mhlp_batch_create": ([ctypes.c_int32, ctypes.POINTER(_V), ctypes.c_int32, _V, ctypes.POINTER(_V)],
                           ctypes.c_int32),
@@ -248,6 +249,28 @@ def eval_layer(plan: Plan, sigma=None, mu=None, precision=FP64, out_slp=None, ou
         out_dlp = torch.empty(M, dtype=torch.float64, device=dev) if out_dlp is None else out_dlp
         ud = _dev(out_dlp, "u_dlp", M)
     _check(L.mhlp_eval_layer(plan.handle, ps, pm, us, ud, int(precision), _stream()), "eval_layer")
+    return (out_slp if sigma is not None else None), (out_dlp if mu is not None else None)
+
+
+def eval_grad(plan: Plan, sigma=None, mu=None, out_slp=None, out_dlp=None):
+    """Target gradients of the single layer of sigma and/or the double layer of
+    mu on an off-surface plan; each result is a [2][M] float64 tensor (x1 and
+    x2 components) or None."""
+    L = load()
+    N, M = plan.n_sources, plan.n_targets
+    dev = plan.geom.device
+    ps = pm = None
+    gs = [None, None]
+    gd = [None, None]
+    if sigma is not None:
+        ps = _dev(sigma, "sigma", N)
+        out_slp = torch.empty(2, M, dtype=torch.float64, device=dev) if out_slp is None else out_slp
+        gs = [_dev(out_slp[0], "grad_slp[0]", M), _dev(out_slp[1], "grad_slp[1]", M)]
+    if mu is not None:
+        pm = _dev(mu, "mu", N)
+        out_dlp = torch.empty(2, M, dtype=torch.float64, device=dev) if out_dlp is None else out_dlp
+        gd = [_dev(out_dlp[0], "grad_dlp[0]", M), _dev(out_dlp[1], "grad_dlp[1]", M)]
+    _check(L.mhlp_eval_grad(plan.handle, ps, pm, gs[0], gs[1], gd[0], gd[1], _stream()), "eval_grad")
     return (out_slp if sigma is not None else None), (out_dlp if mu is not None else None)
 
 
