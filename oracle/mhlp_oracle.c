@@ -53,6 +53,12 @@
 #ifndef ORC_RTOL
 #define ORC_RTOL 1e-14
 #endif
+/* the gradient integrals near the curve converge more slowly on the accepted
+   pieces; a tighter test keeps their exact panel integrals at ~1e-13 of the
+   weights (checked against 30-digit quadrature) */
+#ifndef ORC_RTOL_GRAD
+#define ORC_RTOL_GRAD 1e-15
+#endif
 #define TWO_PI 6.283185307179586476925286766559
 #define EULER_GAMMA 0.57721566490153286060651209008240243
 
@@ -183,6 +189,61 @@ static void k01_integral(double z, double *k0, double *k1)
     *k1 = ez * s1;
 }
 
+/* The same two representations in long double (64-bit significand), used by
+   the gradient integrand: near the curve the gradient integrals cancel by a
+   factor ~h/d, so the kernel values must carry more than double precision
+   for the exact panel integrals to stay accurate to double rounding. */
+#define EULER_GAMMA_L 0.57721566490153286060651209008240243L
+static void k01_series_ld(long double z, long double *k0, long double *k1)
+{
+    long double q = 0.25L * z * z;
+    long double lz = logl(0.5L * z);
+    long double a = 1.0L, b = 1.0L;
+    long double psi1 = -EULER_GAMMA_L, psi2 = psi1 + 1.0L;
+    long double si0 = 0.0L, si1 = 0.0L, sk0 = 0.0L, sk1 = 0.0L;
+    for (int n = 0; n < 80; ++n) {
+        si0 += a;
+        si1 += b;
+        sk0 += psi1 * a;
+        sk1 += (psi1 + psi2) * b;
+        if (a < 1e-22L * si0 && n > 2) break;
+        a *= q / ((n + 1.0L) * (n + 1.0L));
+        b *= q / ((n + 1.0L) * (n + 2.0L));
+        psi1 += 1.0L / (n + 1.0L);
+        psi2 += 1.0L / (n + 2.0L);
+    }
+    long double i1 = 0.5L * z * si1;
+    *k0 = -lz * si0 + sk0;
+    *k1 = 1.0L / z + lz * i1 - 0.25L * z * sk1;
+}
+
+static void k01_integral_ld(long double z, long double *k0, long double *k1)
+{
+    const long double H = fminl(0.125L, 0.4L / sqrtl(z));
+    long double s0 = 0.5L, s1 = 0.5L;
+    for (int k = 1; k < 8000; ++k) {
+        long double u = k * H;
+        long double sh = sinhl(0.5L * u);
+        long double cm1 = 2.0L * sh * sh;
+        long double e = z * cm1;
+        if (e > 52.0L) break;
+        long double v = expl(-e);
+        s0 += v;
+        s1 += v * (1.0L + cm1);
+    }
+    long double ez = expl(-z) * H;
+    *k0 = ez * s0;
+    *k1 = ez * s1;
+}
+
+static void bessel_k01_ld(long double z, long double *k0, long double *k1)
+{
+    if (z <= 2.0L)
+        k01_series_ld(z, k0, k1);
+    else
+        k01_integral_ld(z, k0, k1);
+}
+
 void orc_bessel_k01(double z, double *k0, double *k1)
 {
     if (z <= 2.0)
@@ -264,7 +325,7 @@ static void lagrange(const integrand_t *c, double s, long double *l)
                same of dG/dn_y, each times l_j(t) |y'(t)|.
    Differences y(t)-x are formed as sum_j l_j(t)(x_j - x) so that a target on
    the panel keeps full relative accuracy near its own node.              */
-static void integrand(const integrand_t *c, double s, double *F)
+static void integrand(const integrand_t *c, double s, long double *F)
 {
     long double l[16];
     lagrange(c, s, l);
@@ -276,14 +337,14 @@ static void integrand(const integrand_t *c, double s, double *F)
         dy += l[j] * c->p->dyl[j];
     }
     /* y - x = (rx, ry);  (x - y).n_y |y'| = (x - y).(-dy, dx) = rx dy - ry dx */
-    double r = (double)sqrtl(rx * rx + ry * ry);
-    double speed = (double)sqrtl(dx * dx + dy * dy);
-    double k0, k1;
-    orc_bessel_k01(c->alpha * r, &k0, &k1);
-    double xmyn = (double)(rx * dy - ry * dx);
+    long double xmyn = rx * dy - ry * dx;
     if (!c->grad) {
+        double r = (double)sqrtl(rx * rx + ry * ry);
+        double speed = (double)sqrtl(dx * dx + dy * dy);
+        double k0, k1;
+        orc_bessel_k01(c->alpha * r, &k0, &k1);
         double gs = k0 / TWO_PI * speed;
-        double gd = c->alpha * k1 / (TWO_PI * r) * xmyn;
+        double gd = c->alpha * k1 / (TWO_PI * r) * (double)xmyn;
         for (int j = 0; j < 16; ++j) {
             F[j] = gs * (double)l[j];
             F[16 + j] = gd * (double)l[j];
@@ -292,35 +353,39 @@ static void integrand(const integrand_t *c, double s, double *F)
     }
     /* A = alpha K1/r, B = (alpha^2 K0 + 2A)/r^2; with d = y - x,
        grad G = A d/(2 pi), grad dG/dn = (A n - (d.n) d B)/(2 pi), and
-       -(d.n)|y'| = xmyn, n |y'| = (-dy, dx). */
-    double A = c->alpha * k1 / r;
-    double B = (c->alpha * c->alpha * k0 + 2.0 * A) / (r * r);
-    double ddx = (double)rx, ddy = (double)ry;
-    double v[4];
-    v[0] = A * ddx * speed / TWO_PI;
-    v[1] = A * ddy * speed / TWO_PI;
-    v[2] = (-A * (double)dy + xmyn * ddx * B) / TWO_PI;
-    v[3] = (A * (double)dx + xmyn * ddy * B) / TWO_PI;
+       -(d.n)|y'| = xmyn, n |y'| = (-dy, dx).  All in long double. */
+    const long double al = c->alpha, tp = 2.0L * 3.14159265358979323846264338327950288L;
+    long double r2 = rx * rx + ry * ry, r = sqrtl(r2);
+    long double speed = sqrtl(dx * dx + dy * dy);
+    long double k0, k1;
+    bessel_k01_ld(al * r, &k0, &k1);
+    long double A = al * k1 / r;
+    long double B = (al * al * k0 + 2.0L * A) / r2;
+    long double v[4];
+    v[0] = A * rx * speed / tp;
+    v[1] = A * ry * speed / tp;
+    v[2] = (-A * dy + xmyn * rx * B) / tp;
+    v[3] = (A * dx + xmyn * ry * B) / tp;
     for (int k = 0; k < 4; ++k)
-        for (int j = 0; j < 16; ++j) F[16 * k + j] = v[k] * (double)l[j];
+        for (int j = 0; j < 16; ++j) F[16 * k + j] = v[k] * l[j];
 }
 
 static void gl_rule(const integrand_t *c, int n, const double *T, const double *W, double a, double b,
-                    double *I, double *Iabs)
+                    long double *I, long double *Iabs)
 {
     double mid = 0.5 * (a + b), half = 0.5 * (b - a);
-    double F[MAXF];
+    long double F[MAXF];
     const int nf = c->nf;
     for (int k = 0; k < nf; ++k) {
-        I[k] = 0.0;
-        if (Iabs) Iabs[k] = 0.0;
+        I[k] = 0.0L;
+        if (Iabs) Iabs[k] = 0.0L;
     }
     for (int i = 0; i < n; ++i) {
         integrand(c, mid + half * T[i], F);
-        double w = W[i] * half;
+        long double w = (long double)W[i] * half;
         for (int k = 0; k < nf; ++k) {
             I[k] += w * F[k];
-            if (Iabs) Iabs[k] += w * fabs(F[k]);
+            if (Iabs) Iabs[k] += w * fabsl(F[k]);
         }
     }
 }
@@ -334,8 +399,8 @@ static void gl_rule(const integrand_t *c, int n, const double *T, const double *
    relative test.  `absacc` (optional) collects the integral of |F| over the
    accepted pieces.                                                        */
 typedef struct { double a, b; int d; } seg_t;
-static void adaptive(const integrand_t *c, double a, double b, double rtol, const double *fl, double *acc,
-                     double *absacc)
+static void adaptive(const integrand_t *c, double a, double b, double rtol, const double *fl, long double *acc,
+                     long double *absacc)
 {
     seg_t stack[128];
     int top = 0, visited = 0;
@@ -344,13 +409,13 @@ static void adaptive(const integrand_t *c, double a, double b, double rtol, cons
     while (top > 0) {
         seg_t s = stack[--top];
         ++visited;
-        double I16[MAXF], I32[MAXF], A32[MAXF];
+        long double I16[MAXF], I32[MAXF], A32[MAXF];
         gl_rule(c, 16, GL16_T, GL16_W, s.a, s.b, I16, NULL);
         gl_rule(c, 32, GL32_T, GL32_W, s.a, s.b, I32, A32);
         int ok = 1;
         for (int k = 0; k < nf; ++k) {
-            double e = fabs(I16[k] - I32[k]);
-            if (e > rtol * A32[k] && e > fl[k >> 4] && e > 1e-300) {
+            double e = (double)fabsl(I16[k] - I32[k]);
+            if (e > rtol * (double)A32[k] && e > fl[k >> 4] && e > 1e-300) {
                 ok = 0;
                 break;
             }
@@ -374,18 +439,24 @@ static void adaptive(const integrand_t *c, double a, double b, double rtol, cons
 static void integrate_pieces(const integrand_t *c, const double *cuts, int ncut, double *W)
 {
     const int nf = c->nf, nk = c->nf / 16;
-    double tmp[MAXF], ab[MAXF], fl0[4] = {0.0, 0.0, 0.0, 0.0}, fl[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int k = 0; k < nf; ++k) tmp[k] = ab[k] = W[k] = 0.0;
+    long double tmp[MAXF], ab[MAXF], acc[MAXF];
+    double fl0[4] = {0.0, 0.0, 0.0, 0.0}, fl[4] = {0.0, 0.0, 0.0, 0.0};
+    /* the accurate pass of the gradient kernels (long double arithmetic) is
+       judged against a finer floor */
+    const double floor_rel = c->grad ? 2e-18 : 2e-16;
+    for (int k = 0; k < nf; ++k) tmp[k] = ab[k] = acc[k] = 0.0L;
     for (int q = 0; q + 1 < ncut; ++q) {
-        double I[MAXF], A[MAXF];
+        long double I[MAXF], A[MAXF];
         gl_rule(c, 32, GL32_T, GL32_W, cuts[q], cuts[q + 1], I, A);
-        for (int k = 0; k < nf; ++k) fl0[k >> 4] = fmax(fl0[k >> 4], A[k]);
+        for (int k = 0; k < nf; ++k) fl0[k >> 4] = fmax(fl0[k >> 4], (double)A[k]);
     }
     for (int b = 0; b < nk; ++b) fl0[b] *= 1e-12;
     for (int q = 0; q + 1 < ncut; ++q) adaptive(c, cuts[q], cuts[q + 1], 1e-8, fl0, tmp, ab);
-    for (int k = 0; k < nf; ++k) fl[k >> 4] = fmax(fl[k >> 4], ab[k]);
-    for (int b = 0; b < nk; ++b) fl[b] *= 2e-16;
-    for (int q = 0; q + 1 < ncut; ++q) adaptive(c, cuts[q], cuts[q + 1], ORC_RTOL, fl, W, NULL);
+    for (int k = 0; k < nf; ++k) fl[k >> 4] = fmax(fl[k >> 4], (double)ab[k]);
+    for (int b = 0; b < nk; ++b) fl[b] *= floor_rel;
+    for (int q = 0; q + 1 < ncut; ++q)
+        adaptive(c, cuts[q], cuts[q + 1], c->grad ? ORC_RTOL_GRAD : ORC_RTOL, fl, acc, NULL);
+    for (int k = 0; k < nf; ++k) W[k] = (double)acc[k];
 }
 
 /* Exact panel weights W[0..15] (SLP) and W[16..31] (DLP) of target (tx,ty)

@@ -72,7 +72,7 @@ struct mhlp_geometry {
     int64_t N = 0, Np = 0;
     double *soa = nullptr;                       /* [6][N] */
     double *w = nullptr, *nx = nullptr, *ny = nullptr, *kappa = nullptr;
-    double *pa = nullptr;                        /* [Np][16] complex (re, im) */
+    double *pa = nullptr; /* [Np][16] complex Legendre coefficients of the panel relative to its node 7 */
     double *ph = nullptr, *pcx = nullptr, *pcy = nullptr, *prad = nullptr;
 };
 
@@ -149,23 +149,29 @@ __host__ __device__ inline void geom_prep_body(int64_t p, const double *__restri
         kappa[m] = (dx[m] * ddy[m] - dy[m] * ddx[m]) / (sp * sp * sp);
         h += wm;
     }
+    /* Legendre coefficients of the panel polynomial relative to its node 7
+       (an exact double): rounding then scales with the panel size instead of
+       the distance from the origin.  Near-field routines add (node 7 - target)
+       to the constant term and work in the target's frame (panel_local). */
+    const cplx ref = mk(x[16 * p + 7], y[16 * p + 7]);
     cplx a[16];
     for (int mm = 0; mm < 16; ++mm) {
         cplx s = mk(0.0, 0.0);
-        for (int j = 0; j < 16; ++j) s = s + LEGC[mm * 16 + j] * mk(x[16 * p + j], y[16 * p + j]);
+        for (int j = 0; j < 16; ++j) s = s + LEGC[mm * 16 + j] * (mk(x[16 * p + j], y[16 * p + j]) - ref);
         a[mm] = s;
         pa[(16 * p + mm) * 2] = s.re;
         pa[(16 * p + mm) * 2 + 1] = s.im;
     }
-    const cplx c = a[0];
+    const cplx c0 = a[0]; /* panel centre relative to ref */
     double r = 0.0;
-    for (int j = 0; j < 16; ++j) r = fmax(r, cabs(mk(x[16 * p + j], y[16 * p + j]) - c));
+    for (int j = 0; j < 16; ++j) r = fmax(r, cabs((mk(x[16 * p + j], y[16 * p + j]) - ref) - c0));
     cplx e1 = mk(0.0, 0.0), e0 = mk(0.0, 0.0);
     for (int mm = 0; mm < 16; ++mm) {
         e1 = e1 + a[mm];
         e0 = e0 + ((mm & 1) ? -1.0 : 1.0) * a[mm];
     }
-    r = fmax(r, fmax(cabs(e1 - c), cabs(e0 - c)));
+    r = fmax(r, fmax(cabs(e1 - c0), cabs(e0 - c0)));
+    const cplx c = ref + c0;
     ph[p] = h;
     pcx[p] = c.re;
     pcy[p] = c.im;
@@ -189,6 +195,15 @@ struct GeoView {
     const double *x, *y, *pa, *ph, *pcx, *pcy, *prad;
     int64_t N, Np;
 };
+
+/* Legendre coefficients of p(t) - z for panel p: the panel in the frame of
+   the target z (the kernels depend on y - x only), so that tau - z near the
+   target is formed without cancellation against |z|. */
+__host__ __device__ inline void panel_local(const GeoView &G, int64_t p, cplx z, cplx *a)
+{
+    for (int m = 0; m < 16; ++m) a[m] = mk(G.pa[(16 * p + m) * 2], G.pa[(16 * p + m) * 2 + 1]);
+    a[0] = a[0] + (mk(G.x[16 * p + 7], G.y[16 * p + 7]) - z);
+}
 
 /* Calls f(panel, self, tstar) for every panel needing a correction at target i
    (panel index ascending). */
@@ -219,9 +234,9 @@ __host__ __device__ inline void visit_near(const GeoView &G, int64_t i, cplx z, 
         }
         if (dmin >= lim * lim) continue;
         cplx a[16];
-        for (int m = 0; m < 16; ++m) a[m] = mk(G.pa[(16 * p + m) * 2], G.pa[(16 * p + m) * 2 + 1]);
+        panel_local(G, p, z, a);
         cplx ts;
-        if (!preimage(a, z, mk(GL16_T[jb], 0.0), ts)) continue;
+        if (!preimage(a, mk(0.0, 0.0), mk(GL16_T[jb], 0.0), ts)) continue;
         if (bernstein_rho(ts) >= rho_direct) continue;
         f(p, -1, ts);
     }
@@ -313,10 +328,10 @@ __host__ __device__ inline void near_weights_body(int64_t q, const GeoView &G, c
         return;
     }
     cplx a[16];
-    for (int m = 0; m < 16; ++m) a[m] = mk(G.pa[(16 * p + m) * 2], G.pa[(16 * p + m) * 2 + 1]);
+    panel_local(G, p, mk(tx[i], ty[i]), a);
     const int self = (onsurf && i / 16 == p) ? (int)(i % 16) : -1;
     double Ws[16], Wd[16];
-    pair_weights(a, G.ph[p], mk(tx[i], ty[i]), self, mk(ts[2 * q], ts[2 * q + 1]), alpha, P, Ws, Wd);
+    pair_weights(a, G.ph[p], mk(0.0, 0.0), self, mk(ts[2 * q], ts[2 * q + 1]), alpha, P, Ws, Wd);
     for (int j = 0; j < 16; ++j) {
         wsl[16 * q + j] = Ws[j];
         wdl[16 * q + j] = Wd[j];
@@ -348,8 +363,8 @@ __global__ void near_grad_weights_kernel(GeoView G, const double *__restrict__ t
             for (int j = 0; j < 16; ++j) W[b][j] = 0.0;
     } else {
         cplx a[16];
-        for (int m = 0; m < 16; ++m) a[m] = mk(G.pa[(16 * p + m) * 2], G.pa[(16 * p + m) * 2 + 1]);
-        pair_grad_weights(a, G.ph[p], mk(tx[i], ty[i]), mk(ts[2 * q], ts[2 * q + 1]), alpha, P, W);
+        panel_local(G, p, mk(tx[i], ty[i]), a);
+        pair_grad_weights(a, G.ph[p], mk(0.0, 0.0), mk(ts[2 * q], ts[2 * q + 1]), alpha, P, W);
     }
     for (int b = 0; b < 4; ++b)
         for (int j = 0; j < 16; ++j) wg[(b * nnz + q) * 16 + j] = W[b][j];

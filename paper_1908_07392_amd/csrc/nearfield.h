@@ -505,26 +505,31 @@ __host__ __device__ inline void pair_weights(const cplx *a, double h, cplx z, in
      int f e/r^2 ds_arc = -conj( int f |tau'| / Q  ds/(s - s*) )   (f real),
      int mu (e.n)/r^2 ds_arc = Im F(z),  F(z) = int mu dtau/(tau - z),
      grad Im F = (Im F', Re F'),  F'(z) = int mu tau'/Q^2 ds/(s - s*)^2.
-   The (s - s*)^-1 and (s - s*)^-2 integrals use the Cauchy moments and the
-   moments of (s - s*)^-2, the log integral the log moments, all through the
-   interpolatory weights of the upsampled rule (Sec. 4.3).  The paper lowers
-   a (tau - z)^-3 singularity of the stresslet by parts; for the scalar
-   kernel the highest order is (tau - z)^-2, integrated directly as the paper
-   does for its own (tau - z)^-2 terms.
+   F' has a (tau - z)^-2 singularity.  As the paper does for its highest
+   order term, it is lowered by parts on every interval [ta, tb] of the rule:
+     int mu tau' ds/(tau - z)^2 = [-mu/(tau - z)]_ta^tb + int mu'(s) ds/(tau - z),
+   where mu' is the derivative of the panel's degree-15 density interpolant
+   (exact), so only Cauchy and log moments are needed, integrated through the
+   interpolatory weights of the upsampled rule (Sec. 4.3).  A direct
+   (s - s*)^-2 rule loses accuracy for targets near a panel end (its weights
+   grow like the inverse square of the distance to the end), the form by
+   parts behaves like the Cauchy term of the potentials there.
    Weight blocks: W[0], W[1] = d/dx1, d/dx2 of S; W[2], W[3] = of D.       */
 
-/* MH[m] = int P_m(t)/(t - s)^2 dt, m = 0..N-1, from the Cauchy moments MC
-   (m = 0..N-2): by parts, MH_m = B_m + int P_m'/(t - s) dt with
-   B_m = -1/(1 - s) - (-1)^m/(1 + s); with P_{m+1}' - P_{m-1}' = (2m+1) P_m
-   and B_{m+1} = B_{m-1} this gives MH_{m+1} = MH_{m-1} + (2m+1) MC_m,
-   MH_0 = B_0, MH_1 = B_1 + MC_0.                                          */
-template <int N>
-__host__ __device__ inline void hyper_moments(cplx s, const cplx *MC, cplx *MH)
+/* Derivatives l_j'(t) of the Lagrange basis of the 16 Gauss-Legendre nodes at
+   real t, from the Legendre form l_j = sum_m LEGC[m][j] P_m and
+   P'_{m+1} = P'_{m-1} + (2m+1) P_m. */
+__host__ __device__ inline void lagrange16_deriv(double t, double *dl)
 {
-    const cplx ia = mk(1.0, 0.0) / (mk(1.0, 0.0) - s), ib = mk(1.0, 0.0) / (mk(1.0, 0.0) + s);
-    MH[0] = -(ia + ib);
-    MH[1] = (ib - ia) + MC[0];
-    for (int m = 1; m + 1 < N; ++m) MH[m + 1] = MH[m - 1] + (2.0 * m + 1.0) * MC[m];
+    double P0 = 1.0, P1 = t, D0 = 0.0, D1 = 1.0;
+    for (int j = 0; j < 16; ++j) dl[j] = LEGC[16 + j];
+    for (int m = 1; m < 15; ++m) {
+        const double P2 = ((2.0 * m + 1.0) * t * P1 - m * P0) / (m + 1.0);
+        const double D2 = D0 + (2.0 * m + 1.0) * P1;
+        for (int j = 0; j < 16; ++j) dl[j] = fma(LEGC[(m + 1) * 16 + j], D2, dl[j]);
+        P0 = P1; P1 = P2;
+        D0 = D1; D1 = D2;
+    }
 }
 
 /* Direct (plain quadrature) gradient weights at one node. */
@@ -582,20 +587,30 @@ __host__ __device__ inline void leaf_split32_grad(const cplx *a, double ta, doub
     constexpr int NQ = 32;
     NodeGeo g[NQ];
     double WQ[4][NQ];
+    cplx WF[16]; /* weights of F'(z) on the parent's 16 nodes */
     rule_geo<NQ>(a, GL32_T, GL32_W, ta, tb, g);
     const double mid = 0.5 * (ta + tb), half = 0.5 * (tb - ta);
     const cplx ss = (1.0 / half) * (tstar - mk(mid, 0.0));
-    cplx MC[NQ + 1], ML[NQ], MH[NQ], pc[NQ], pl[NQ], ph[NQ];
+    cplx MC[NQ + 1], ML[NQ], pc[NQ], pl[NQ];
     legendre_moments<NQ>(ss, bernstein_rho(ss), MC, ML);
-    hyper_moments<NQ>(ss, MC, MH);
     moments_to_weights<NQ>(LEGW32, MC, pc); /* (s - s*)^-1 */
     moments_to_weights<NQ>(LEGW32, ML, pl); /* log(s - s*)  */
-    moments_to_weights<NQ>(LEGW32, MH, ph); /* (s - s*)^-2 */
+    /* end-point terms of F' by parts: mu(ta)/(tau(ta) - z) - mu(tb)/(tau(tb) - z) */
+    {
+        double la_[16], lb_[16];
+        cplx pa, pb, dpa, dpb;
+        leg_eval(a, mk(ta, 0.0), pa, dpa);
+        leg_eval(a, mk(tb, 0.0), pb, dpb);
+        lagrange16(ta, la_);
+        lagrange16(tb, lb_);
+        const cplx ia = mk(1.0, 0.0) / (pa - z), ib = mk(1.0, 0.0) / (pb - z);
+        for (int j = 0; j < 16; ++j) WF[j] = la_[j] * ia - lb_[j] * ib;
+    }
     const double la = log(alpha);
     const double a2 = alpha * alpha, a4q = 0.25 * a2 * a2;
     for (int k = 0; k < NQ; ++k) {
-        const cplx tk = mk(mid + half * GL32_T[k], 0.0);
-        const cplx Q = half * leg_divdiff(a, tk, tstar); /* (tau - z)/(s - s*) */
+        const double tkr = mid + half * GL32_T[k];
+        const cplx Q = half * leg_divdiff(a, mk(tkr, 0.0), tstar); /* (tau - z)/(s - s*) */
         const double sp_ = cabs(g[k].dtau);
         const double logw = fma(sp_, pl[k].re, g[k].w * log(cabs(Q)));
         const cplx e = z - g[k].tau;
@@ -606,28 +621,61 @@ __host__ __device__ inline void leaf_split32_grad(const cplx *a, double ta, doub
         const double en = e.re * nx + e.im * ny;
         const double Aw = fma(S, g[k].w, L * logw);          /* smooth + log, order 0 */
         const double Bw = 2.0 * en * fma(Sq, g[k].w, Lq * logw); /* from S', L'       */
-        const cplx cS = pc[k] * (mk(sp_, 0.0) / Q);            /* Cauchy, |tau'|/Q   */
-        const cplx cH = ph[k] * (g[k].dtau / (Q * Q));         /* (s - s*)^-2        */
+        const cplx iQ = mk(1.0, 0.0) / Q;
+        const cplx cS = (sp_ * pc[k]) * iQ;                    /* Cauchy, |tau'|/Q   */
         WQ[0][k] = INV_2PI * fma(-e.re, Aw, cS.re);
         WQ[1][k] = INV_2PI * fma(-e.im, Aw, -cS.im);
-        WQ[2][k] = INV_2PI * (fma(nx, Aw, Bw * e.re) - en * L * cS.re + cH.im);
-        WQ[3][k] = INV_2PI * (fma(ny, Aw, Bw * e.im) + en * L * cS.im + cH.re);
+        WQ[2][k] = INV_2PI * (fma(nx, Aw, Bw * e.re) - en * L * cS.re);
+        WQ[3][k] = INV_2PI * (fma(ny, Aw, Bw * e.im) + en * L * cS.im);
+        /* by-parts integral: Cauchy weight times dmu/ds = half dmu/dt */
+        double dl[16];
+        lagrange16_deriv(tkr, dl);
+        const cplx cD = (half * pc[k]) * iQ;
+        for (int j = 0; j < 16; ++j) WF[j] = WF[j] + dl[j] * cD;
     }
     fold_add_n<NQ, 4>(GL32_T, ta, tb, WQ, W);
+    /* grad Im F = (Im F', Re F') */
+    for (int j = 0; j < 16; ++j) {
+        W[2][j] = fma(INV_2PI, WF[j].im, W[2][j]);
+        W[3][j] = fma(INV_2PI, WF[j].re, W[3][j]);
+    }
 }
 
+#ifndef MHLP_GRAD_EDGE
+#define MHLP_GRAD_EDGE 0.75
+#endif
+/* Interpolatory weights of the split rule lose accuracy when the target's
+   preimage lies close to an end of the interval (weights of the node next to
+   that end grow, the pole sits outside the region the nodes resolve); the
+   gradient kernels amplify this (errors of 1e-11 relative in the weights for
+   a preimage 0.01 from an end).  Such intervals are bisected towards the
+   preimage until it lies in the middle part of a piece or the piece is far
+   enough for a plain rule (the paper merges neighbouring panels instead). */
 __host__ __device__ inline void leaf_apply_grad(const cplx *a, double ta, double tb, cplx z, cplx tstar,
                                                 double alpha, const NearParams &P, double (*W)[16])
 {
-    const double mid = 0.5 * (ta + tb), half = 0.5 * (tb - ta);
-    const cplx ss = (1.0 / half) * (tstar - mk(mid, 0.0));
-    const double rho = bernstein_rho(ss);
-    if (rho >= P.rho_direct)
-        leaf_direct_grad<16>(a, GL16_T, GL16_W, ta, tb, z, alpha, W);
-    else if (rho >= P.rho_split)
-        leaf_direct_grad<32>(a, GL32_T, GL32_W, ta, tb, z, alpha, W);
-    else
-        leaf_split32_grad(a, ta, tb, z, tstar, alpha, W);
+    double st_a[48], st_b[48];
+    int top = 0;
+    st_a[top] = ta;
+    st_b[top] = tb;
+    ++top;
+    while (top > 0) {
+        --top;
+        const double a0 = st_a[top], b0 = st_b[top];
+        const double mid = 0.5 * (a0 + b0), half = 0.5 * (b0 - a0);
+        const cplx ss = (1.0 / half) * (tstar - mk(mid, 0.0));
+        const double rho = bernstein_rho(ss);
+        if (rho >= P.rho_direct) {
+            leaf_direct_grad<16>(a, GL16_T, GL16_W, a0, b0, z, alpha, W);
+        } else if (rho >= P.rho_split) {
+            leaf_direct_grad<32>(a, GL32_T, GL32_W, a0, b0, z, alpha, W);
+        } else if (fabs(ss.re) > MHLP_GRAD_EDGE && top < 46 && half > 1e-9) {
+            st_a[top] = a0; st_b[top] = mid; ++top;
+            st_a[top] = mid; st_b[top] = b0; ++top;
+        } else {
+            leaf_split32_grad(a, a0, b0, z, tstar, alpha, W);
+        }
+    }
 }
 
 /* Gradient correction weights of an off-curve target z against a panel

@@ -198,7 +198,9 @@ def test_config2_full_size_sampled():
 
 
 def test_gradient_argument_errors():
-    g = wl.discretize(wl.starfish_curve(), 16)
+    # 48 panels: at 16 the plain 16-point rule on panels just beyond the near
+    # criterion is only ~1e-8 accurate, a discretisation difference, not parity
+    g = wl.discretize(wl.starfish_curve(), 48)
     G = mhlp.Geometry(_t(g.node_soa()))
     on = mhlp.Plan(G, 5.0)
     d = _t(np.ones(g.n_nodes))
