@@ -510,10 +510,7 @@ __host__ __device__ inline void pair_weights(const cplx *a, double h, cplx z, in
      int mu tau' ds/(tau - z)^2 = [-mu/(tau - z)]_ta^tb + int mu'(s) ds/(tau - z),
    where mu' is the derivative of the panel's degree-15 density interpolant
    (exact), so only Cauchy and log moments are needed, integrated through the
-   interpolatory weights of the upsampled rule (Sec. 4.3).  A direct
-   (s - s*)^-2 rule loses accuracy for targets near a panel end (its weights
-   grow like the inverse square of the distance to the end), the form by
-   parts behaves like the Cauchy term of the potentials there.
+   interpolatory weights of the upsampled rule (Sec. 4.3).
    Weight blocks: W[0], W[1] = d/dx1, d/dx2 of S; W[2], W[3] = of D.       */
 
 /* Derivatives l_j'(t) of the Lagrange basis of the 16 Gauss-Legendre nodes at
@@ -641,41 +638,18 @@ __host__ __device__ inline void leaf_split32_grad(const cplx *a, double ta, doub
     }
 }
 
-#ifndef MHLP_GRAD_EDGE
-#define MHLP_GRAD_EDGE 0.75
-#endif
-/* Interpolatory weights of the split rule lose accuracy when the target's
-   preimage lies close to an end of the interval (weights of the node next to
-   that end grow, the pole sits outside the region the nodes resolve); the
-   gradient kernels amplify this (errors of 1e-11 relative in the weights for
-   a preimage 0.01 from an end).  Such intervals are bisected towards the
-   preimage until it lies in the middle part of a piece or the piece is far
-   enough for a plain rule (the paper merges neighbouring panels instead). */
 __host__ __device__ inline void leaf_apply_grad(const cplx *a, double ta, double tb, cplx z, cplx tstar,
                                                 double alpha, const NearParams &P, double (*W)[16])
 {
-    double st_a[48], st_b[48];
-    int top = 0;
-    st_a[top] = ta;
-    st_b[top] = tb;
-    ++top;
-    while (top > 0) {
-        --top;
-        const double a0 = st_a[top], b0 = st_b[top];
-        const double mid = 0.5 * (a0 + b0), half = 0.5 * (b0 - a0);
-        const cplx ss = (1.0 / half) * (tstar - mk(mid, 0.0));
-        const double rho = bernstein_rho(ss);
-        if (rho >= P.rho_direct) {
-            leaf_direct_grad<16>(a, GL16_T, GL16_W, a0, b0, z, alpha, W);
-        } else if (rho >= P.rho_split) {
-            leaf_direct_grad<32>(a, GL32_T, GL32_W, a0, b0, z, alpha, W);
-        } else if (fabs(ss.re) > MHLP_GRAD_EDGE && top < 46 && half > 1e-9) {
-            st_a[top] = a0; st_b[top] = mid; ++top;
-            st_a[top] = mid; st_b[top] = b0; ++top;
-        } else {
-            leaf_split32_grad(a, a0, b0, z, tstar, alpha, W);
-        }
-    }
+    const double mid = 0.5 * (ta + tb), half = 0.5 * (tb - ta);
+    const cplx ss = (1.0 / half) * (tstar - mk(mid, 0.0));
+    const double rho = bernstein_rho(ss);
+    if (rho >= P.rho_direct)
+        leaf_direct_grad<16>(a, GL16_T, GL16_W, ta, tb, z, alpha, W);
+    else if (rho >= P.rho_split)
+        leaf_direct_grad<32>(a, GL32_T, GL32_W, ta, tb, z, alpha, W);
+    else
+        leaf_split32_grad(a, ta, tb, z, tstar, alpha, W);
 }
 
 /* Gradient correction weights of an off-curve target z against a panel
