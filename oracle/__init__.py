@@ -50,6 +50,12 @@ def lib():
                                              ctypes.c_double, ctypes.c_int, _D]
         L.orc_eval_grad.argtypes = [_D, _D, ctypes.c_int64, _D, _D, ctypes.c_double, _D, _D, ctypes.c_int64,
                                     _D, _D, _D, _D, ctypes.c_int]
+        L.orc_stresslet_T.argtypes = [ctypes.c_double, _D]
+        L.orc_stokes_panel_weights.argtypes = [_D, _D, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                               ctypes.c_double, ctypes.c_int, ctypes.c_int, _D]
+        L.orc_stokes_eval.argtypes = [_D, _D, ctypes.c_int64, _D, _D, ctypes.c_double, _D, _D, ctypes.c_int64,
+                                      _I64, _D, _D, ctypes.c_int]
+        L.orc_stokes_matrix.argtypes = [_D, _D, ctypes.c_int64, ctypes.c_double, _D, ctypes.c_int]
         L.orc_assemble_onsurface.argtypes = [_D, _D, ctypes.c_int64, ctypes.c_double, _D, _D, ctypes.c_int]
         L.orc_gmres.argtypes = [_D, ctypes.c_int64, _D, _D, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                 ctypes.POINTER(ctypes.c_int), _D, ctypes.c_int]
@@ -144,6 +150,60 @@ def panel_grad_weights(x, y, panel, tx, ty, alpha, mode=0):
     W = np.zeros(64)
     lib().orc_panel_grad_weights(_p(x), _p(y), int(panel), float(tx), float(ty), float(alpha), int(mode), _p(W))
     return W.reshape(4, 16)
+
+
+# --------------------------------------------------------------------------------------
+# modified-Stokes double layer (stresslet)
+# --------------------------------------------------------------------------------------
+def stresslet_T(z):
+    """(T1, T2, T3) of the stresslet at z > 0."""
+    out = np.zeros(3)
+    lib().orc_stresslet_T(float(z), _p(out))
+    return tuple(out)
+
+
+def stokes_panel_weights(x, y, panel, tx, ty, alpha, self_node=-1, mode=0):
+    """[2][2][16] weights: u_i += sum_j,l W[i][j][l] mu_j(node l of the panel)."""
+    x, y = _c(x), _c(y)
+    W = np.zeros(64)
+    lib().orc_stokes_panel_weights(_p(x), _p(y), int(panel), float(tx), float(ty), float(alpha), int(self_node),
+                                   int(mode), _p(W))
+    return W.reshape(2, 2, 16)
+
+
+def stokes_eval(x, y, alpha, tx, ty, mu, tgt_node=None, nthreads=0):
+    """Modified-Stokes double layer of mu ([2][N]) at the targets; returns [2][m]
+    (on-surface targets marked by tgt_node: principal value, no 1/2 mu)."""
+    x, y, tx, ty = _c(x), _c(y), _c(tx), _c(ty)
+    mu = _c(mu).reshape(2, -1)
+    m = tx.size
+    u = np.zeros((2, m))
+    tn = None if tgt_node is None else _c(tgt_node, np.int64)
+    m1, m2 = np.ascontiguousarray(mu[0]), np.ascontiguousarray(mu[1])
+    rc = lib().orc_stokes_eval(_p(x), _p(y), x.size // 16, _p(m1), _p(m2), float(alpha), _p(tx), _p(ty), m,
+                               None if tn is None else tn.ctypes.data_as(_I64), _p(u[0]), _p(u[1]), int(nthreads))
+    if rc != 0:
+        raise RuntimeError(f"orc_stokes_eval failed: {rc}")
+    return u
+
+
+def stokes_matrix(x, y, alpha, nthreads=0):
+    """Dense on-surface principal-value stresslet matrix, 2N x 2N (rows a N + i)."""
+    x, y = _c(x), _c(y)
+    n = x.size
+    Dm = np.empty((2 * n, 2 * n))
+    rc = lib().orc_stokes_matrix(_p(x), _p(y), n // 16, float(alpha), _p(Dm), int(nthreads))
+    if rc != 0:
+        raise RuntimeError(f"orc_stokes_matrix failed: {rc}")
+    return Dm
+
+
+def stokes_bie_matrix(Dm, w, nx, ny):
+    """1/2 I + D_pv + W with W mu = n (sum_j w_j mu_j . n_j) / sum_j w_j (Sec. 3.2)."""
+    n = w.size
+    nn = np.concatenate([nx, ny])
+    wn = np.concatenate([w * nx, w * ny]) / np.sum(w)
+    return 0.5 * np.eye(2 * n) + Dm + np.outer(nn, wn)
 
 
 def onsurface_matrices(x, y, alpha, want_slp=False, want_dlp=True, nthreads=0):

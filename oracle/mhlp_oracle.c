@@ -18,6 +18,15 @@
  *
  * (from K0' = -K1 and (K1(z)/z)' = -(K0(z) + 2 K1(z)/z)/z).
  *
+ * The modified-Stokes double layer of Sec. 3.2 (the paper's own BIE):
+ *
+ *   D[mu]_i(x) = int_Gamma D_ij(x,y) mu_j(y) dS_y,  D_ij = -T_jik(x,y) n_k(y),
+ *   T_ijk = a^2 T1 (d_jk r_i + d_ik r_j + d_ij r_k) + a^4 T2 r_i r_j r_k + a^2 T3 d_ik r_j,
+ *
+ * r = x - y, with T1..T3 of App. B (closed forms in K0, K1 for z > 1.5, the
+ * power series of App. C below), and the on-surface operator
+ * (1/2) mu + D_pv mu + W mu, W mu = n (int mu.n dS) / |Gamma| (Sec. 3.2).
+ *
  * K0(alpha r)/(2 pi) is the scalar Yukawa piece of the paper's modified
  * biharmonic Green's function (Sec. 2, eq. for G; App. B).  The boundary is the
  * composite 16-point Gauss-Legendre panel discretisation of Sec. 3.2, and the
@@ -292,7 +301,7 @@ typedef struct {
     double dref[16];         /* tref - t_j   */
     int self;                /* node index of the target on this panel, or -1 */
     double alpha;
-    int grad;                /* 0: potentials (32 values), 1: gradients (64) */
+    int grad;                /* 0: potentials (32 values), 1: gradients (64), 2: stresslet (64) */
     int nf;                  /* values per evaluation: 32 or 64              */
 } integrand_t;
 
@@ -319,10 +328,82 @@ static void lagrange(const integrand_t *c, double s, long double *l)
     for (int j = 0; j < 16; ++j) l[j] /= sum;
 }
 
+/* Stresslet functions of App. B, long double:
+     T1 = -(2 z^2 K0 + (z^2 + 4) z K1 - 4)/(2 pi z^4),
+     T2 = (4 z^2 K0 + (z^2 + 8) z K1 - 8)/(pi z^6),
+     T3 = (z K1 - 1)/(2 pi z^2)
+   for z > 1.5; below, the power series of App. C with
+     k0(n) = (psi(n+1) - log(z/2)) / (4^n n!^2),
+     k1(n) = (2 log(z/2) - psi(n+1) - psi(n+2)) / (4^(n+1) n! (n+1)!),
+     T1 = -(1/2pi) sum_{n>=1} (2 k0(n) + 4 k1(n) + k1(n-1)) z^(2n-2),
+     T2 = -1/(pi z^4) + 1/(8 pi z^2) + (1/pi) sum_{n>=2} (4 k0(n) + 8 k1(n) + k1(n-1)) z^(2n-4),
+     T3 = (1/2pi) sum_{n>=0} k1(n) z^(2n).                                   */
+static void stresslet_T(long double z, long double *T1, long double *T2, long double *T3)
+{
+    const long double PI_L = 3.14159265358979323846264338327950288L;
+    if (z > 1.5L) {
+        long double k0, k1;
+        bessel_k01_ld(z, &k0, &k1);
+        long double z2 = z * z;
+        *T1 = -(2.0L * z2 * k0 + (z2 + 4.0L) * z * k1 - 4.0L) / (2.0L * PI_L * z2 * z2);
+        *T2 = (4.0L * z2 * k0 + (z2 + 8.0L) * z * k1 - 8.0L) / (PI_L * z2 * z2 * z2);
+        *T3 = (z * k1 - 1.0L) / (2.0L * PI_L * z2);
+        return;
+    }
+    const long double L = logl(0.5L * z), z2 = z * z;
+    long double k0[40], k1[40];
+    long double psi = -EULER_GAMMA_L; /* psi(n+1) */
+    long double f0 = 1.0L, f1 = 0.25L; /* 1/(4^n n!^2), 1/(4^(n+1) n! (n+1)!) */
+    for (int n = 0; n < 40; ++n) {
+        const long double psi2 = psi + 1.0L / (n + 1.0L);
+        k0[n] = (psi - L) * f0;
+        k1[n] = (2.0L * L - psi - psi2) * f1;
+        psi = psi2;
+        f0 /= 4.0L * (n + 1.0L) * (n + 1.0L);
+        f1 /= 4.0L * (n + 1.0L) * (n + 2.0L);
+    }
+    long double s1 = 0.0L, s2 = 0.0L, s3 = 0.0L, zp;
+    zp = 1.0L; /* z^(2n-2) from n = 1 */
+    for (int n = 1; n < 40; ++n, zp *= z2) s1 += (2.0L * k0[n] + 4.0L * k1[n] + k1[n - 1]) * zp;
+    zp = 1.0L; /* z^(2n-4) from n = 2 */
+    for (int n = 2; n < 40; ++n, zp *= z2) s2 += (4.0L * k0[n] + 8.0L * k1[n] + k1[n - 1]) * zp;
+    zp = 1.0L;
+    for (int n = 0; n < 40; ++n, zp *= z2) s3 += k1[n] * zp;
+    *T1 = -s1 / (2.0L * PI_L);
+    *T2 = -1.0L / (PI_L * z2 * z2) + 1.0L / (8.0L * PI_L * z2) + s2 / PI_L;
+    *T3 = s3 / (2.0L * PI_L);
+}
+
+void orc_stresslet_T(double z, double *T)
+{
+    long double a, b, c;
+    stresslet_T(z, &a, &b, &c);
+    T[0] = (double)a;
+    T[1] = (double)b;
+    T[2] = (double)c;
+}
+
+/* D_ij(x, y) of the modified-Stokes double layer for r = x - y, n = n_y. */
+static void stresslet_D(long double rx, long double ry, long double nx, long double ny, long double alpha,
+                        long double D[2][2])
+{
+    const long double r2 = rx * rx + ry * ry;
+    long double T1, T2, T3;
+    stresslet_T(alpha * sqrtl(r2), &T1, &T2, &T3);
+    const long double a2 = alpha * alpha, a4 = a2 * a2;
+    const long double r[2] = {rx, ry}, n[2] = {nx, ny};
+    const long double rn = rx * nx + ry * ny;
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            D[i][j] = -a2 * T1 * (n[i] * r[j] + r[i] * n[j] + (i == j ? rn : 0.0L)) - a4 * T2 * r[i] * r[j] * rn -
+                      a2 * T3 * r[i] * n[j];
+}
+
 /* Integrand: for a target and panel parameter t = tref + s, the values
    potentials: F[j] = G(x, y(t)) l_j(t) |y'(t)|,  F[16+j] = dG/dn_y l_j(t) |y'(t)|;
    gradients:  F[j], F[16+j] = d/dx1, d/dx2 of G(x, y(t)), F[32+j], F[48+j] the
-               same of dG/dn_y, each times l_j(t) |y'(t)|.
+               same of dG/dn_y, each times l_j(t) |y'(t)|;
+   stresslet:  F[(2i+j)16 + l] = D_ij(x, y(t)) l_l(t) |y'(t)|.
    Differences y(t)-x are formed as sum_j l_j(t)(x_j - x) so that a target on
    the panel keeps full relative accuracy near its own node.              */
 static void integrand(const integrand_t *c, double s, long double *F)
@@ -338,6 +419,16 @@ static void integrand(const integrand_t *c, double s, long double *F)
     }
     /* y - x = (rx, ry);  (x - y).n_y |y'| = (x - y).(-dy, dx) = rx dy - ry dx */
     long double xmyn = rx * dy - ry * dx;
+    if (c->grad == 2) {
+        /* stresslet: F[(2i+j)16 + l] = D_ij l_l |y'|, r = x - y = -(rx, ry) */
+        long double speed = sqrtl(dx * dx + dy * dy);
+        long double D[2][2];
+        stresslet_D(-rx, -ry, -dy / speed, dx / speed, c->alpha, D);
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j)
+                for (int k = 0; k < 16; ++k) F[(2 * i + j) * 16 + k] = D[i][j] * speed * l[k];
+        return;
+    }
     if (!c->grad) {
         double r = (double)sqrtl(rx * rx + ry * ry);
         double speed = (double)sqrtl(dx * dx + dy * dy);
@@ -467,7 +558,7 @@ static void panel_exact_k(const panel_t *p, double tx, double ty, double alpha, 
 {
     integrand_t c;
     c.grad = grad;
-    c.nf = grad ? 64 : 32;
+    c.nf = grad ? 64 : 32; /* gradients and stresslet: 4 blocks of 16 */
     c.p = p;
     c.tx = tx;
     c.ty = ty;
@@ -537,6 +628,19 @@ static void panel_direct_grad(const panel_t *p, double tx, double ty, double alp
         W[16 + j] = A * ry * speed * w;
         W[32 + j] = (-A * p->dy[j] + xmyn * rx * B) * w;
         W[48 + j] = (A * p->dx[j] + xmyn * ry * B) * w;
+    }
+}
+
+/* direct 16-point stresslet weights (same layout as the exact ones) */
+static void panel_direct_stokes(const panel_t *p, double tx, double ty, double alpha, double *W)
+{
+    for (int j = 0; j < 16; ++j) {
+        long double speed = sqrtl(p->dxl[j] * p->dxl[j] + p->dyl[j] * p->dyl[j]);
+        long double D[2][2];
+        stresslet_D((long double)tx - p->x[j], (long double)ty - p->y[j], -p->dyl[j] / speed, p->dxl[j] / speed,
+                     alpha, D);
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) W[(2 * a + b) * 16 + j] = (double)(D[a][b] * speed * GL16_W[j]);
     }
 }
 
@@ -678,6 +782,91 @@ int orc_eval_grad(const double *x, const double *y, int64_t n_panels, const doub
         if (gsy) gsy[i] = (double)a[1];
         if (gdx) gdx[i] = (double)a[2];
         if (gdy) gdy[i] = (double)a[3];
+    }
+    free(P);
+    return 0;
+}
+
+/* Stresslet weights of one target against one panel (W: 64 doubles, block
+   2i+j = D_ij).  self: node of the target on this panel or -1.  mode: 0 auto,
+   1 exact, 2 direct. */
+int orc_stokes_panel_weights(const double *x, const double *y, int64_t panel, double tx, double ty, double alpha,
+                             int self, int mode, double *W)
+{
+    init_rules();
+    panel_t p;
+    panel_setup(&p, x + 16 * panel, y + 16 * panel);
+    if (mode == 2 && self < 0)
+        panel_direct_stokes(&p, tx, ty, alpha, W);
+    else if (mode == 1 || self >= 0 || panel_is_near(&p, tx, ty))
+        panel_exact_k(&p, tx, ty, alpha, self, 2, W);
+    else
+        panel_direct_stokes(&p, tx, ty, alpha, W);
+    return 0;
+}
+
+/* Modified-Stokes double layer D[mu] at m targets (mu1, mu2: the density's
+   components at the N nodes; u1, u2: outputs).  tgt_node[i] >= 0 marks target
+   i as that boundary node (principal value, no 1/2 mu term); NULL for
+   off-surface targets. */
+int orc_stokes_eval(const double *x, const double *y, int64_t n_panels, const double *mu1, const double *mu2,
+                    double alpha, const double *tx, const double *ty, int64_t m, const int64_t *tgt_node,
+                    double *u1, double *u2, int nthreads)
+{
+    init_rules();
+    if (alpha <= 0.0 || n_panels <= 0 || m < 0) return -1;
+    panel_t *P = (panel_t *)malloc(sizeof(panel_t) * (size_t)n_panels);
+    if (!P) return -2;
+    for (int64_t p = 0; p < n_panels; ++p) panel_setup(&P[p], x + 16 * p, y + 16 * p);
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t i = 0; i < m; ++i) {
+        long double a1 = 0.0L, a2 = 0.0L;
+        int64_t node = tgt_node ? tgt_node[i] : -1;
+        for (int64_t p = 0; p < n_panels; ++p) {
+            double W[64];
+            int self = (node >= 0 && node / 16 == p) ? (int)(node % 16) : -1;
+            if (self >= 0 || panel_is_near(&P[p], tx[i], ty[i]))
+                panel_exact_k(&P[p], tx[i], ty[i], alpha, self, 2, W);
+            else
+                panel_direct_stokes(&P[p], tx[i], ty[i], alpha, W);
+            for (int j = 0; j < 16; ++j) {
+                const long double m1 = mu1[16 * p + j], m2 = mu2[16 * p + j];
+                a1 += (long double)W[j] * m1 + (long double)W[16 + j] * m2;
+                a2 += (long double)W[32 + j] * m1 + (long double)W[48 + j] * m2;
+            }
+        }
+        u1[i] = (double)a1;
+        u2[i] = (double)a2;
+    }
+    free(P);
+    return 0;
+}
+
+/* Dense on-surface principal-value stresslet matrix (2N x 2N, row-major):
+   row a N + i (component a at node i), column b N + j. */
+int orc_stokes_matrix(const double *x, const double *y, int64_t n_panels, double alpha, double *Dm, int nthreads)
+{
+    init_rules();
+    if (alpha <= 0.0 || n_panels <= 0) return -1;
+    int64_t N = 16 * n_panels;
+    panel_t *P = (panel_t *)malloc(sizeof(panel_t) * (size_t)n_panels);
+    if (!P) return -2;
+    for (int64_t p = 0; p < n_panels; ++p) panel_setup(&P[p], x + 16 * p, y + 16 * p);
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t i = 0; i < N; ++i) {
+        for (int64_t p = 0; p < n_panels; ++p) {
+            double W[64];
+            int self = (i / 16 == p) ? (int)(i % 16) : -1;
+            if (self >= 0 || panel_is_near(&P[p], x[i], y[i]))
+                panel_exact_k(&P[p], x[i], y[i], alpha, self, 2, W);
+            else
+                panel_direct_stokes(&P[p], x[i], y[i], alpha, W);
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b)
+                    for (int j = 0; j < 16; ++j) Dm[(a * N + i) * 2 * N + b * N + 16 * p + j] = W[(2 * a + b) * 16 + j];
+        }
     }
     free(P);
     return 0;
