@@ -115,7 +115,8 @@ mhlp_status mhlp_plan_info(const mhlp_plan *plan, int64_t *n_targets, int64_t *n
    default gives about 1024 blocks.  set_split may reallocate the plan's
    partial-sum buffer (it synchronises the device then).
    mhlp_plan_autotune times the far evaluation (layers: 1 SLP, 2 DLP, 3 both,
-   4 the on-surface BIE operator, 5 the gradients of both, off-surface) for nsplit = 1, 2, 4, ... (up to Np/4 and
+   4 the on-surface BIE operator, 5 the gradients of both, off-surface, 6 the
+   stresslet operator of a stokes plan) for nsplit = 1, 2, 4, ... (up to Np/4 and
    256) plus the current value, reps timed launches each after one warm-up,
    with HIP events on `stream`, keeps the fewest splits within 1% of the
    fastest and reports it with its time (host outputs; cand/cand_ms receive up
@@ -141,6 +142,31 @@ mhlp_status mhlp_eval_dlp(const mhlp_plan *plan, const double *mu, double *u, in
    the interior limit).  Errors: MHLP_INVALID_ARG if the plan is not on-surface. */
 mhlp_status mhlp_apply_bie_operator(const mhlp_plan *onsurf, const double *mu, double *out, int32_t precision,
                                     void *stream);
+
+/* Modified-Stokes double layer, the paper's own BIE kernel (Sec. 3.2, the
+   stresslet of App. B with its split of Sec. 4.1 and the complex forms of
+   Sec. 4.3):
+     D[mu]_i(x) = int_Gamma D_ij(x,y) mu_j(y) dS_y,  D_ij = -T_jik(x,y) n_k(y),
+     T_ijk = alpha^2 T1 (d_jk r_i + d_ik r_j + d_ij r_k) + alpha^4 T2 r_i r_j r_k
+             + alpha^2 T3 d_ik r_j,   r = x - y, n into the domain.
+   A stokes plan has the near lists of mhlp_plan_create and 64 stresslet
+   correction weights per near pair (2x2 blocks on the panel's 16 nodes); it
+   serves only the mhlp_stokes_* calls (the scalar calls reject it and vice
+   versa).  Densities and outputs are component-major: mu [2][N] (mu_1 at
+   mu[0..N), mu_2 at mu[N..2N)), u [2][M].  FP64 throughout.
+   mhlp_stokes_eval: D[mu] at the plan's targets (on-surface: principal value,
+   no 1/2 mu or W term).
+   mhlp_stokes_apply_bie (on-surface plan): out = 1/2 mu + D mu + W mu with the
+   nullspace correction W mu = n(x) int mu.n dS / |Gamma| (Sec. 3.2), out [2][N].
+   mhlp_stokes_gmres_solve: GMRES for (1/2 I + D + W) mu = g, g and mu [2][N],
+   same options and behaviour as mhlp_gmres_solve (precision must be FP64).
+   Errors: MHLP_INVALID_ARG (NULL or aliased arrays, wrong plan kind). */
+mhlp_status mhlp_stokes_plan_create(const mhlp_geometry *geom, double alpha, const double *tx, const double *ty,
+                                    int64_t m, const mhlp_params *params, void *stream, mhlp_plan **out);
+mhlp_status mhlp_stokes_eval(const mhlp_plan *plan, const double *mu, double *u, void *stream);
+mhlp_status mhlp_stokes_apply_bie(const mhlp_plan *onsurf, const double *mu, double *out, void *stream);
+mhlp_status mhlp_stokes_gmres_solve(const mhlp_plan *onsurf, const double *g, double *mu, const mhlp_gmres_opts *opts,
+                                    mhlp_gmres_info *info, void *stream);
 
 /* Target gradients of S[sigma] and D[mu] on an off-surface plan (the
    near-boundary gradient of Sec. 4.4, for the scalar kernel):

@@ -101,6 +101,10 @@ struct mhlp_plan {
     double *near_ts = nullptr;           /* [nnz][2] */
     double *wslp = nullptr, *wdlp = nullptr; /* [nnz][16] */
     double *wgrad = nullptr;  /* off-surface, built on first use: [4][nnz][16] gradient weights */
+    bool stokes = false;      /* modified-Stokes (stresslet) plan: operator on [2][N] densities */
+    double *wstk = nullptr;   /* stokes: [4][nnz][16] stresslet weights (D11, D12, D21, D22)   */
+    double *stk_flux = nullptr; /* stokes: device scalar sum_j w_j mu_j.n_j / |Gamma|           */
+    double inv_len = 0.0;     /* 1 / |Gamma| */
     int64_t nnz = 0;
     int32_t fill_mismatch = 0;
     int nsplit = 1;           /* source splits of the far field (small M)   */
@@ -368,6 +372,29 @@ __global__ void near_grad_weights_kernel(GeoView G, const double *__restrict__ t
     }
     for (int b = 0; b < 4; ++b)
         for (int j = 0; j < 16; ++j) wg[(b * nnz + q) * 16 + j] = W[b][j];
+}
+
+/* stresslet correction weights of all pairs: ws[b][q][j] */
+__global__ void near_stokes_weights_kernel(GeoView G, const double *__restrict__ tx, const double *__restrict__ ty,
+                                           int onsurf, const int32_t *__restrict__ panel,
+                                           const int32_t *__restrict__ tgt, const double *__restrict__ ts,
+                                           int64_t nnz, double alpha, NearParams P, double *__restrict__ wst)
+{
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= nnz) return;
+    const int64_t p = panel[q], i = tgt[q];
+    double W[4][16];
+    if (p < 0 || p >= G.Np) {
+        for (int b = 0; b < 4; ++b)
+            for (int j = 0; j < 16; ++j) W[b][j] = 0.0;
+    } else {
+        cplx a[16];
+        panel_local(G, p, mk(tx[i], ty[i]), a);
+        const int self = (onsurf && i / 16 == p) ? (int)(i % 16) : -1;
+        pair_stokes_weights(a, G.ph[p], mk(0.0, 0.0), self, mk(ts[2 * q], ts[2 * q + 1]), alpha, P, W);
+    }
+    for (int b = 0; b < 4; ++b)
+        for (int j = 0; j < 16; ++j) wst[(b * nnz + q) * 16 + j] = W[b][j];
 }
 
 /* ------------------------------------------------------------------------ */
@@ -732,6 +759,175 @@ __global__ __launch_bounds__(FT_THREADS) void far_grad_fp64(GradArgs A)
             if ((b < 2 && GS) || (b >= 2 && GD)) A.part[((int64_t)b * ns + blockIdx.y) * A.M + i] = acc[b];
     } else {
         grad_epilogue<GS, GD>(A, i, acc);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* modified-Stokes double layer, FP64 (stokes plans)                         */
+/*   u_i(x) = sum_j D_ij(x, y_j) w_j mu_j,                                     */
+/*   D_ij = -[A1 (n_i r_j + r_i n_j + d_ij r.n) + A2 r_i r_j r.n + A3 r_i n_j], */
+/*   r = x - y, A1 = alpha^2 T1, A2 = alpha^4 T2, A3 = alpha^2 T3            */
+/* with the listed near panels replaced by their stresslet weights, and on    */
+/* on-surface plans (BIE) the 1/2 mu and W mu = n sum_j w_j mu_j.n_j / |Gamma| */
+/* terms.  Densities and outputs are [2][N] / [2][M] (component-major).       */
+/* ------------------------------------------------------------------------ */
+struct StkArgs {
+    const double *sx, *sy, *sw, *snx, *sny;
+    const double *mu; /* [2][N] (or the GMRES basis, column j at mu + j*jstride) */
+    int64_t N;
+    const double *tx, *ty;
+    int64_t M, Np, nnz;
+    const int32_t *nptr, *npan, *perm;
+    const double *wst; /* [4][nnz][16] */
+    double alpha;
+    int32_t pps;
+    double *part;      /* [2][nsplit][M] */
+    double *u;         /* u1 = u[o], u2 = u[ustride + o] */
+    int64_t ustride;
+    int32_t bie;
+    const double *flux; /* sum_j w_j mu_j.n_j / |Gamma| (bie) */
+    const GState *gs;
+    int64_t jstride;
+};
+
+__device__ __forceinline__ bool stk_density(const StkArgs &A, const double *&mu)
+{
+    mu = A.mu;
+    if (A.gs) {
+        if (A.gs->done) return false;
+        mu += (int64_t)A.gs->j * A.jstride;
+    }
+    return true;
+}
+
+__device__ __forceinline__ void stk_epilogue(const StkArgs &A, const double *__restrict__ mu, int64_t i, double a1,
+                                             double a2)
+{
+    for (int32_t q = A.nptr[i]; q < A.nptr[i + 1]; ++q) {
+        const int64_t p = A.npan[q];
+        if (p < 0) continue;
+        for (int jj = 0; jj < 16; ++jj) {
+            const int64_t o = 16 * (int64_t)q + jj;
+            const double m1 = mu[16 * p + jj], m2 = mu[A.N + 16 * p + jj];
+            a1 = fma(A.wst[o], m1, fma(A.wst[A.nnz * 16 + o], m2, a1));
+            a2 = fma(A.wst[2 * A.nnz * 16 + o], m1, fma(A.wst[3 * A.nnz * 16 + o], m2, a2));
+        }
+    }
+    if (A.bie) {
+        const double f = A.flux[0];
+        a1 = fma(0.5, mu[i], fma(A.snx[i], f, a1));
+        a2 = fma(0.5, mu[A.N + i], fma(A.sny[i], f, a2));
+    }
+    const int64_t o = A.perm ? (int64_t)A.perm[i] : i;
+    A.u[o] = a1;
+    A.u[A.ustride + o] = a2;
+}
+
+__global__ void stk_finalize(StkArgs A, int nsplit)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const double *mu;
+    if (i >= A.M || !stk_density(A, mu)) return;
+    double a1 = 0.0, a2 = 0.0;
+    for (int k = 0; k < nsplit; ++k) {
+        a1 += A.part[(int64_t)k * A.M + i];
+        a2 += A.part[((int64_t)nsplit + k) * A.M + i];
+    }
+    stk_epilogue(A, mu, i, a1, a2);
+}
+
+/* flux sum_j w_j mu_j.n_j / |Gamma| of the density into flux[0]; one block,
+   fixed summation order */
+__global__ __launch_bounds__(256) void stk_flux_kernel(StkArgs A, double inv_len, double *__restrict__ flux)
+{
+    __shared__ double red[256];
+    const double *mu;
+    if (!stk_density(A, mu)) return;
+    double s = 0.0;
+    for (int64_t j = threadIdx.x; j < A.N; j += 256) s = fma(A.sw[j], fma(mu[j], A.snx[j], mu[A.N + j] * A.sny[j]), s);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) flux[0] = red[0] * inv_len;
+}
+
+template <bool SPLIT>
+__global__ __launch_bounds__(FT_THREADS) void far_stokes_fp64(StkArgs A)
+{
+    __shared__ double lx[FT_SRC], ly[FT_SRC], lm1[FT_SRC], lm2[FT_SRC], lnx[FT_SRC], lny[FT_SRC];
+    const double *mu;
+    if (!stk_density(A, mu)) return;
+    const int64_t i = blockIdx.x * (int64_t)FT_THREADS + threadIdx.x;
+    const bool valid = i < A.M;
+    const double x = valid ? A.tx[i] : 0.0, y = valid ? A.ty[i] : 0.0;
+    const int64_t pb = SPLIT ? (int64_t)blockIdx.y * A.pps : 0;
+    const int64_t pe = SPLIT ? min(A.Np, pb + A.pps) : A.Np;
+    int32_t k = 0, kend = 0;
+    if (valid) {
+        k = A.nptr[i];
+        kend = A.nptr[i + 1];
+        while (k < kend && A.npan[k] >= 0 && A.npan[k] < pb) ++k;
+    }
+    int32_t nxt = (k < kend) ? A.npan[k] : INT_MAX;
+    const FarConst fc = far_const(A.alpha);
+    double a1 = 0.0, a2 = 0.0;
+    for (int64_t base = 16 * pb; base < 16 * pe; base += FT_SRC) {
+        __syncthreads();
+        const int64_t j = base + threadIdx.x;
+        if (j < 16 * pe) {
+            const double wj = A.sw[j];
+            lx[threadIdx.x] = A.sx[j];
+            ly[threadIdx.x] = A.sy[j];
+            lm1[threadIdx.x] = wj * mu[j];
+            lm2[threadIdx.x] = wj * mu[A.N + j];
+            lnx[threadIdx.x] = A.snx[j];
+            lny[threadIdx.x] = A.sny[j];
+        }
+        __syncthreads();
+        const int32_t p0 = (int32_t)(base / 16);
+        const int npl = (pe - p0) < 16 ? (int)(pe - p0) : 16;
+        for (int pl = 0; pl < npl; ++pl) {
+            if (p0 + pl == nxt) {
+                ++k;
+                nxt = (k < kend) ? A.npan[k] : INT_MAX;
+                continue;
+            }
+#pragma unroll 1
+            for (int s = 0; s < 16; s += 2) {
+                const FarTab T = far_table();
+                const int l0 = pl * 16 + s;
+                const double ex0 = x - lx[l0], ey0 = y - ly[l0];
+                const double ex1 = x - lx[l0 + 1], ey1 = y - ly[l0 + 1];
+                const double r20 = fma(ex0, ex0, ey0 * ey0), r21 = fma(ex1, ex1, ey1 * ey1);
+                K01 o[2];
+                k01_far2<true, true>(T, fc, r20, r21, o[0], o[1]);
+                const double ex[2] = {ex0, ex1}, ey[2] = {ey0, ey1}, r2[2] = {r20, r21};
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int l = l0 + u;
+                    double Ak[3];
+                    stresslet_scaled(A.alpha, r2[u], o[u].ri2, o[u].k0, o[u].ak1r, Ak);
+                    const double nx = lnx[l], ny = lny[l], m1 = lm1[l], m2 = lm2[l];
+                    const double rn = fma(ex[u], nx, ey[u] * ny);
+                    const double rm = fma(ex[u], m1, ey[u] * m2);
+                    const double nm = fma(nx, m1, ny * m2);
+                    const double c = fma(Ak[1] * rm, rn, Ak[2] * nm);
+                    a1 -= fma(Ak[0], fma(nx, rm, fma(ex[u], nm, m1 * rn)), c * ex[u]);
+                    a2 -= fma(Ak[0], fma(ny, rm, fma(ey[u], nm, m2 * rn)), c * ey[u]);
+                }
+            }
+        }
+    }
+    if (!valid) return;
+    if (SPLIT) {
+        const int ns = gridDim.y;
+        A.part[(int64_t)blockIdx.y * A.M + i] = a1;
+        A.part[((int64_t)ns + blockIdx.y) * A.M + i] = a2;
+    } else {
+        stk_epilogue(A, mu, i, a1, a2);
     }
 }
 
@@ -1187,8 +1383,8 @@ extern "C" mhlp_status mhlp_plan_destroy(mhlp_plan *P)
         for (auto &gr : gp)
             if (gr.exec) (void)hipGraphExecDestroy(gr.exec);
     if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
-    void *ptrs[] = {P->near_ptr, P->near_panel, P->near_tgt, P->near_ts, P->wslp, P->wdlp,
-                    P->ws,       P->hdev,       P->part,     P->gdev,    P->perm, P->wgrad};
+    void *ptrs[] = {P->near_ptr, P->near_panel, P->near_tgt, P->near_ts, P->wslp,  P->wdlp,    P->ws,
+                    P->hdev,     P->part,       P->gdev,     P->perm,    P->wgrad, P->wstk,    P->stk_flux};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (P->hhost) (void)hipHostFree(P->hhost);
@@ -1197,8 +1393,8 @@ extern "C" mhlp_status mhlp_plan_destroy(mhlp_plan *P)
     return MHLP_OK;
 }
 
-extern "C" mhlp_status mhlp_plan_create(const mhlp_geometry *g, double alpha, const double *tx, const double *ty,
-                                        int64_t m, const mhlp_params *prm, void *stream, mhlp_plan **out)
+static mhlp_status plan_create_impl(const mhlp_geometry *g, double alpha, const double *tx, const double *ty,
+                                    int64_t m, const mhlp_params *prm, void *stream, mhlp_plan **out, bool stokes)
 {
     if (!out) return fail(MHLP_INVALID_ARG, "out is NULL");
     *out = nullptr;
@@ -1210,6 +1406,7 @@ extern "C" mhlp_status mhlp_plan_create(const mhlp_geometry *g, double alpha, co
     mhlp_plan *P = new mhlp_plan();
     P->g = g;
     P->alpha = alpha;
+    P->stokes = stokes;
     P->np.rho_direct = 3.5;
     P->np.rho_split = std::sqrt(3.5);
     P->np.ah_max = 4.5;
@@ -1327,7 +1524,8 @@ extern "C" mhlp_status mhlp_plan_create(const mhlp_geometry *g, double alpha, co
     P->nnz = nnz;
     if (nnz > 0) {
         if ((s = dalloc(&P->near_panel, nnz)) || (s = dalloc(&P->near_tgt, nnz)) || (s = dalloc(&P->near_ts, 2 * (int64_t)nnz)) ||
-            (s = dalloc(&P->wslp, 16 * (int64_t)nnz)) || (s = dalloc(&P->wdlp, 16 * (int64_t)nnz))) {
+            (!stokes && ((s = dalloc(&P->wslp, 16 * (int64_t)nnz)) || (s = dalloc(&P->wdlp, 16 * (int64_t)nnz)))) ||
+            (stokes && (s = dalloc(&P->wstk, 64 * (int64_t)nnz)))) {
             mhlp_plan_destroy(P);
             return s;
         }
@@ -1354,9 +1552,14 @@ extern "C" mhlp_status mhlp_plan_create(const mhlp_geometry *g, double alpha, co
                     return fail(MHLP_HIP_ERROR, "plan_create: near list holds an invalid panel index");
                 }
         }
-        near_weights_kernel<<<nblocks(nnz, 64), 64, 0, st>>>(G, P->tx, P->ty, P->onsurf ? 1 : 0, P->near_panel,
-                                                              P->near_tgt, P->near_ts, nnz, alpha, P->np, P->wslp,
-                                                              P->wdlp);
+        if (stokes)
+            near_stokes_weights_kernel<<<nblocks(nnz, 64), 64, 0, st>>>(G, P->tx, P->ty, P->onsurf ? 1 : 0,
+                                                                         P->near_panel, P->near_tgt, P->near_ts, nnz,
+                                                                         alpha, P->np, P->wstk);
+        else
+            near_weights_kernel<<<nblocks(nnz, 64), 64, 0, st>>>(G, P->tx, P->ty, P->onsurf ? 1 : 0, P->near_panel,
+                                                                  P->near_tgt, P->near_ts, nnz, alpha, P->np, P->wslp,
+                                                                  P->wdlp);
         e = hipGetLastError();
         int32_t mism = 0;
         if (e == hipSuccess) e = hipMemcpyAsync(&mism, cnt + M, sizeof(int32_t), hipMemcpyDeviceToHost, st);
@@ -1369,8 +1572,38 @@ extern "C" mhlp_status mhlp_plan_create(const mhlp_geometry *g, double alpha, co
         P->fill_mismatch = mism;
     }
     (void)hipFree(cnt);
+    if (stokes) {
+        /* W term: device scalar for the flux, host 1/|Gamma| */
+        if ((s = dalloc(&P->stk_flux, 8))) {
+            mhlp_plan_destroy(P);
+            return s;
+        }
+        std::vector<double> hw((size_t)g->N);
+        hipError_t e2 = hipMemcpyAsync(hw.data(), g->w, sizeof(double) * g->N, hipMemcpyDeviceToHost, st);
+        if (e2 == hipSuccess) e2 = hipStreamSynchronize(st);
+        if (e2 != hipSuccess) {
+            mhlp_plan_destroy(P);
+            return fail(MHLP_HIP_ERROR, std::string("stokes plan: ") + hipGetErrorString(e2));
+        }
+        double len = 0.0;
+        for (double v : hw) len += v;
+        P->inv_len = 1.0 / len;
+    }
     *out = P;
     return MHLP_OK;
+}
+
+extern "C" mhlp_status mhlp_plan_create(const mhlp_geometry *g, double alpha, const double *tx, const double *ty,
+                                        int64_t m, const mhlp_params *prm, void *stream, mhlp_plan **out)
+{
+    return plan_create_impl(g, alpha, tx, ty, m, prm, stream, out, false);
+}
+
+extern "C" mhlp_status mhlp_stokes_plan_create(const mhlp_geometry *g, double alpha, const double *tx,
+                                               const double *ty, int64_t m, const mhlp_params *prm, void *stream,
+                                               mhlp_plan **out)
+{
+    return plan_create_impl(g, alpha, tx, ty, m, prm, stream, out, true);
 }
 
 extern "C" mhlp_status mhlp_plan_info(const mhlp_plan *P, int64_t *n_targets, int64_t *n_sources,
@@ -1411,6 +1644,7 @@ static mhlp_status launch_far(const mhlp_plan *P, const double *sigma, const dou
                               int64_t jstride = 0)
 {
     if (precision != MHLP_FP64 && precision != MHLP_MIXED) return fail(MHLP_INVALID_ARG, "unknown precision");
+    if (P->stokes) return fail(MHLP_INVALID_ARG, "a stokes plan evaluates with the mhlp_stokes_* calls");
     const mhlp_geometry *g = P->g;
     if (half_term != 0.0 && (!P->onsurf || P->M != g->N))
         return fail(MHLP_INVALID_ARG, "identity term needs an on-surface plan");
@@ -1479,12 +1713,17 @@ extern "C" mhlp_status mhlp_plan_get_split(const mhlp_plan *P, int32_t *nsplit)
     return MHLP_OK;
 }
 
+static mhlp_status launch_stokes(const mhlp_plan *P, const double *mu, double *u, int64_t ustride, bool bie,
+                                 hipStream_t st, const GState *gs = nullptr, int64_t jstride = 0);
+
 extern "C" mhlp_status mhlp_plan_autotune(mhlp_plan *P, int32_t layers, int32_t precision, int32_t reps,
                                           void *stream, int32_t *best_nsplit, double *best_ms, int32_t *cand,
                                           double *cand_ms, int32_t cap, int32_t *n_cand)
 {
     if (!P) return fail(MHLP_INVALID_ARG, "plan is NULL");
-    if (layers < 1 || layers > 5) return fail(MHLP_INVALID_ARG, "layers must be 1, 2, 3, 4 or 5");
+    if (layers < 1 || layers > 6) return fail(MHLP_INVALID_ARG, "layers must be 1 to 6");
+    if ((layers == 6) != P->stokes) return fail(MHLP_INVALID_ARG, "layers 6 (and only 6) tunes a stokes plan");
+    if (layers == 6 && precision != MHLP_FP64) return fail(MHLP_INVALID_ARG, "the stresslet is FP64 only");
     if (layers == 4 && !P->onsurf) return fail(MHLP_INVALID_ARG, "layers 4 (BIE operator) needs an on-surface plan");
     if (layers == 5 && P->onsurf) return fail(MHLP_INVALID_ARG, "layers 5 (gradients) needs an off-surface plan");
     if (layers == 5 && precision != MHLP_FP64) return fail(MHLP_INVALID_ARG, "gradients are FP64 only");
@@ -1497,7 +1736,7 @@ extern "C" mhlp_status mhlp_plan_autotune(mhlp_plan *P, int32_t layers, int32_t 
     for (int64_t ns = 1; ns <= std::max<int64_t>(1, Np / 4) && ns <= 256; ns *= 2) cs.push_back((int)ns);
     if (std::find(cs.begin(), cs.end(), P->nsplit) == cs.end()) cs.push_back(P->nsplit);
     double *dens = nullptr, *out = nullptr;
-    TRY(dalloc(&dens, N));
+    TRY(dalloc(&dens, 2 * N));
     mhlp_status s = dalloc(&out, 4 * M);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (s == MHLP_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
@@ -1506,11 +1745,12 @@ extern "C" mhlp_status mhlp_plan_autotune(mhlp_plan *P, int32_t layers, int32_t 
     double bms = 1e300;
     int nc = 0;
     std::vector<std::pair<int, double>> tim;
-    if (s == MHLP_OK) fill_kernel<<<nblocks(N, 256), 256, 0, st>>>(dens, 1.0, N);
+    if (s == MHLP_OK) fill_kernel<<<nblocks(2 * N, 256), 256, 0, st>>>(dens, 1.0, 2 * N);
     for (size_t c = 0; c < cs.size() && s == MHLP_OK; ++c) {
         if ((s = plan_set_split(P, cs[c]))) break;
         auto run = [&]() -> mhlp_status {
             if (layers == 5) return mhlp_eval_grad(P, dens, dens, out, out + M, out + 2 * M, out + 3 * M, st);
+            if (layers == 6) return launch_stokes(P, dens, out, M, P->onsurf, st);
             const double *sg = (layers & 1) ? dens : nullptr, *mu = (layers & 2 || layers == 4) ? dens : nullptr;
             return launch_far(P, sg, mu, sg ? out : nullptr, mu ? out + M : nullptr, layers == 4 ? 0.5 : 0.0,
                               precision, st);
@@ -1621,6 +1861,7 @@ extern "C" mhlp_status mhlp_eval_grad(const mhlp_plan *Pc, const double *sigma, 
 {
     if (!Pc) return fail(MHLP_INVALID_ARG, "plan is NULL");
     if (Pc->onsurf) return fail(MHLP_UNSUPPORTED, "eval_grad needs an off-surface plan (targets off the curve)");
+    if (Pc->stokes) return fail(MHLP_INVALID_ARG, "eval_grad needs a scalar plan");
     const bool gs = sigma != nullptr, gd = mu != nullptr;
     if (!gs && !gd) return fail(MHLP_INVALID_ARG, "no density given");
     if (gs != (gs_x != nullptr) || gs != (gs_y != nullptr) || gd != (gd_x != nullptr) || gd != (gd_y != nullptr))
@@ -1664,14 +1905,90 @@ extern "C" mhlp_status mhlp_eval_grad(const mhlp_plan *Pc, const double *sigma, 
 }
 
 /* ------------------------------------------------------------------------ */
+/* modified-Stokes double layer: entry points                                */
+/* ------------------------------------------------------------------------ */
+static mhlp_status launch_stokes(const mhlp_plan *P, const double *mu, double *u, int64_t ustride, bool bie,
+                                 hipStream_t st, const GState *gs, int64_t jstride)
+{
+    const mhlp_geometry *g = P->g;
+    StkArgs A;
+    A.sx = g->soa;
+    A.sy = g->soa + g->N;
+    A.sw = g->w;
+    A.snx = g->nx;
+    A.sny = g->ny;
+    A.mu = mu;
+    A.N = g->N;
+    A.tx = P->tx;
+    A.ty = P->ty;
+    A.M = P->M;
+    A.Np = g->Np;
+    A.nnz = P->nnz;
+    A.nptr = P->near_ptr;
+    A.npan = P->near_panel;
+    A.perm = P->perm;
+    A.wst = P->wstk;
+    A.alpha = P->alpha;
+    A.pps = P->pps;
+    A.part = P->part;
+    A.u = u;
+    A.ustride = ustride;
+    A.bie = bie ? 1 : 0;
+    A.flux = P->stk_flux;
+    A.gs = gs;
+    A.jstride = jstride;
+    if (bie) stk_flux_kernel<<<1, 256, 0, st>>>(A, P->inv_len, P->stk_flux);
+    const unsigned nb = nblocks(A.M, FT_THREADS);
+    if (P->nsplit <= 1) {
+        far_stokes_fp64<false><<<nb, FT_THREADS, 0, st>>>(A);
+    } else {
+        far_stokes_fp64<true><<<dim3(nb, P->nsplit), FT_THREADS, 0, st>>>(A);
+        stk_finalize<<<nblocks(A.M, 256), 256, 0, st>>>(A, P->nsplit);
+    }
+    HIPCHECK(hipGetLastError());
+    return MHLP_OK;
+}
+
+extern "C" mhlp_status mhlp_stokes_eval(const mhlp_plan *P, const double *mu, double *u, void *stream)
+{
+    if (!P) return fail(MHLP_INVALID_ARG, "plan is NULL");
+    if (!P->stokes) return fail(MHLP_INVALID_ARG, "stokes_eval needs a plan from mhlp_stokes_plan_create");
+    if (!mu || !u) return fail(MHLP_INVALID_ARG, "mu or u is NULL");
+    if (mu == u) return fail(MHLP_INVALID_ARG, "mu and u must not alias");
+    return launch_stokes(P, mu, u, P->M, false, (hipStream_t)stream);
+}
+
+extern "C" mhlp_status mhlp_stokes_apply_bie(const mhlp_plan *P, const double *mu, double *out, void *stream)
+{
+    if (!P) return fail(MHLP_INVALID_ARG, "plan is NULL");
+    if (!P->stokes || !P->onsurf)
+        return fail(MHLP_INVALID_ARG, "stokes_apply_bie needs an on-surface plan from mhlp_stokes_plan_create");
+    if (!mu || !out) return fail(MHLP_INVALID_ARG, "mu or out is NULL");
+    if (mu == out) return fail(MHLP_INVALID_ARG, "mu and out must not alias");
+    return launch_stokes(P, mu, out, P->M, true, (hipStream_t)stream);
+}
+
+/* ------------------------------------------------------------------------ */
 /* GMRES                                                                     */
 /* ------------------------------------------------------------------------ */
+/* length of the unknown vector and the on-surface operator of the plan:
+   (1/2 I + D) mu for the scalar kernel (N), (1/2 I + D + W) mu for the
+   stresslet (2N, component-major) */
+static int64_t vlen(const mhlp_plan *P) { return P->stokes ? 2 * P->g->N : P->g->N; }
+
+static mhlp_status apply_op(mhlp_plan *P, const double *x, double *out, int32_t prec, hipStream_t st,
+                            const GState *gs = nullptr, int64_t jstride = 0)
+{
+    if (P->stokes) return launch_stokes(P, x, out, P->g->N, true, st, gs, jstride);
+    return launch_far(P, nullptr, x, nullptr, out, 0.5, prec, st, gs, jstride);
+}
+
 static mhlp_status ensure_ws(mhlp_plan *P, int64_t cols)
 {
     if (P->ws && P->ws_cols >= cols) return MHLP_OK;
     if (P->ws) (void)hipFree(P->ws);
     P->ws = nullptr;
-    TRY(dalloc(&P->ws, (cols + 4) * P->g->N));
+    TRY(dalloc(&P->ws, (cols + 4) * vlen(P)));
     P->ws_cols = cols;
     if (!P->hdev) {
         TRY(dalloc(&P->hdev, 4 * 1024));
@@ -1743,12 +2060,12 @@ static mhlp_status ensure_gdev(mhlp_plan *P, int R)
 /* One Arnoldi step of the device-driven GMRES, enqueued on st. */
 static mhlp_status enqueue_step(mhlp_plan *P, int32_t prec, hipStream_t st)
 {
-    const int64_t N = P->g->N;
+    const int64_t N = vlen(P);
     const int R = P->gdev_R;
     double *V = P->ws, *w = P->ws + (int64_t)(R + 1) * N;
     const GmresDev d = gdev_view(P);
     const unsigned nbN = nblocks(N, 256);
-    TRY(launch_far(P, nullptr, V, nullptr, w, 0.5, prec, st, d.gs, N));
+    TRY(apply_op(P, V, w, prec, st, d.gs, N));
     /* classical Gram-Schmidt, twice */
     gs_dot_kernel<<<R, 256, 0, st>>>(d.gs, V, N, w, N, d.h1);
     gs_sub_kernel<<<nbN, 256, 0, st>>>(d.gs, V, N, d.h1, w, N);
@@ -1815,7 +2132,7 @@ static mhlp_status gmres_core(mhlp_plan *P, const double *b, double bnorm, doubl
                               int max_iter, int32_t prec, hipStream_t st, int *iters, int *cycles, double *relres,
                               const double *r_first, double beta_first)
 {
-    const int64_t N = P->g->N;
+    const int64_t N = vlen(P);
     TRY(ensure_gdev(P, restart));
     const int R = P->gdev_R;
     double *V = P->ws;
@@ -1833,7 +2150,7 @@ static mhlp_status gmres_core(mhlp_plan *P, const double *b, double bnorm, doubl
         if (r_first && *cycles == 0) {
             beta = beta_first;
         } else {
-            TRY(launch_far(P, nullptr, x, nullptr, w, 0.5, prec, st));
+            TRY(apply_op(P, x, w, prec, st));
             residual_kernel<<<nbN, 256, 0, st>>>(b, w, r, N);
             TRY(dnorm(P, r, N, st, &beta));
             rr = r;
@@ -1878,8 +2195,8 @@ static mhlp_status gmres_core(mhlp_plan *P, const double *b, double bnorm, doubl
     return MHLP_OK;
 }
 
-extern "C" mhlp_status mhlp_gmres_solve(const mhlp_plan *Pc, const double *g, double *mu, const mhlp_gmres_opts *opts,
-                                        mhlp_gmres_info *info, void *stream)
+static mhlp_status gmres_solve_impl(const mhlp_plan *Pc, const double *g, double *mu, const mhlp_gmres_opts *opts,
+                                    mhlp_gmres_info *info, void *stream)
 {
     if (!Pc) return fail(MHLP_INVALID_ARG, "plan is NULL");
     if (!Pc->onsurf) return fail(MHLP_INVALID_ARG, "gmres_solve needs an on-surface plan (m == 0)");
@@ -1889,9 +2206,11 @@ extern "C" mhlp_status mhlp_gmres_solve(const mhlp_plan *Pc, const double *g, do
         return fail(MHLP_INVALID_ARG, "bad GMRES options");
     if (opts->precision != MHLP_FP64 && opts->precision != MHLP_MIXED)
         return fail(MHLP_INVALID_ARG, "unknown precision");
+    if (Pc->stokes && opts->precision != MHLP_FP64)
+        return fail(MHLP_INVALID_ARG, "the stresslet operator is FP64 only");
     mhlp_plan *P = const_cast<mhlp_plan *>(Pc);
     hipStream_t st = (hipStream_t)stream;
-    const int64_t N = P->g->N;
+    const int64_t N = vlen(P);
     std::memset(info, 0, sizeof(*info));
     /* workspace columns: basis V_0..V_R, w, r (cycle residual), and the two
        refinement vectors; R >= restart is the largest restart seen */
@@ -1913,7 +2232,7 @@ extern "C" mhlp_status mhlp_gmres_solve(const mhlp_plan *Pc, const double *g, do
     double r0n = 0.0;
     if (opts->use_x0) {
         double *w = P->ws + (int64_t)(R + 1) * N;
-        TRY(launch_far(P, nullptr, mu, nullptr, w, 0.5, MHLP_FP64, st));
+        TRY(apply_op(P, mu, w, MHLP_FP64, st));
         residual_kernel<<<nblocks(N, 256), 256, 0, st>>>(g, w, r0, N);
         TRY(dnorm(P, r0, N, st, &r0n));
         info->x0_residual = r0n / bnorm;
@@ -1946,7 +2265,7 @@ extern "C" mhlp_status mhlp_gmres_solve(const mhlp_plan *Pc, const double *g, do
                 rn = r0n;
                 HIPCHECK(hipMemcpyAsync(r, r0, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
             } else {
-                TRY(launch_far(P, nullptr, mu, nullptr, w, 0.5, MHLP_FP64, st));
+                TRY(apply_op(P, mu, w, MHLP_FP64, st));
                 residual_kernel<<<nbN, 256, 0, st>>>(g, w, r, N);
                 TRY(dnorm(P, r, N, st, &rn));
             }
@@ -1967,6 +2286,20 @@ extern "C" mhlp_status mhlp_gmres_solve(const mhlp_plan *Pc, const double *g, do
     info->rel_residual = rel;
     info->converged = rel <= opts->tol ? 1 : 0;
     return info->converged ? MHLP_OK : MHLP_NOT_CONVERGED;
+}
+
+extern "C" mhlp_status mhlp_gmres_solve(const mhlp_plan *P, const double *g, double *mu, const mhlp_gmres_opts *opts,
+                                        mhlp_gmres_info *info, void *stream)
+{
+    if (P && P->stokes) return fail(MHLP_INVALID_ARG, "stokes plans solve with mhlp_stokes_gmres_solve");
+    return gmres_solve_impl(P, g, mu, opts, info, stream);
+}
+
+extern "C" mhlp_status mhlp_stokes_gmres_solve(const mhlp_plan *P, const double *g, double *mu,
+                                               const mhlp_gmres_opts *opts, mhlp_gmres_info *info, void *stream)
+{
+    if (P && !P->stokes) return fail(MHLP_INVALID_ARG, "stokes_gmres_solve needs a plan from mhlp_stokes_plan_create");
+    return gmres_solve_impl(P, g, mu, opts, info, stream);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -2435,7 +2768,8 @@ extern "C" mhlp_status mhlp_batch_create(int32_t n_geom, const mhlp_plan *const 
     if (n_geom < 1 || !plans) return fail(MHLP_INVALID_ARG, "need at least one plan");
     if (n_rhs < 1 || n_rhs > BATCH_R_MAX) return fail(MHLP_INVALID_ARG, "n_rhs must be 1..4");
     for (int g = 0; g < n_geom; ++g)
-        if (!plans[g] || !plans[g]->onsurf) return fail(MHLP_INVALID_ARG, "batch needs on-surface plans");
+        if (!plans[g] || !plans[g]->onsurf || plans[g]->stokes)
+            return fail(MHLP_INVALID_ARG, "batch needs on-surface scalar plans");
     hipStream_t st = (hipStream_t)stream;
     mhlp_batch *B = new mhlp_batch();
     B->n_geom = n_geom;

@@ -666,4 +666,242 @@ __host__ __device__ inline void pair_grad_weights(const cplx *a, double h, cplx 
                     [&](double a0, double b0) { leaf_apply_grad(a, a0, b0, z, tstar, alpha, P, W); });
 }
 
+/* ====================================================================== */
+/* Modified-Stokes double layer (the paper's BIE kernel, Sec. 4.1-4.3).    */
+/* ====================================================================== */
+/* D_ij(x, y) = -T_jik(x, y) n_k(y) with r = x - y:
+     D_ij = -[A1 (n_i r_j + r_i n_j + d_ij (r.n)) + A2 r_i r_j (r.n) + A3 r_i n_j],
+   A1 = alpha^2 T1, A2 = alpha^4 T2, A3 = alpha^2 T3 (z = alpha |r|).  With the
+   split of T1..T3 (Sec. 4.1) the kernel is
+     D = D[A^S] + D[A^L] log|r| - (alpha^2/8pi) r_i r_j (r.n)/|r|^2
+         + (1/pi) r_i r_j (r.n)/|r|^4,
+   A^S = (alpha^2 (T1S + T1L log alpha), alpha^4 (T2S + T2L log alpha), ...),
+   A^L = (alpha^2 T1L, alpha^4 T2L, alpha^2 T3L).  The first two terms are
+   smooth and smooth times log; the third is a smooth factor times the
+   Laplace double-layer kernel (r.n)/|r|^2, integrated as Im of a Cauchy
+   integral (Sec. 4.3); the fourth is the Stokes stresslet, whose complex
+   form (Sec. 4.3; e = tau - z, omega = mu_1 + i mu_2, nu = n_1 + i n_2) is
+     int (mu.e) e (e.n)/|e|^4 dS = -(1/2) int omega Im(dtau/e)
+        + (1/4i) conj(int omega conj(nu)^2 dtau/e)
+        + (1/4i) conj(int omega conj(e) dtau/e^2),
+   and r = -e flips its sign.  The (tau - z)^-2 integral is lowered by parts
+   as for the gradients: int f dtau/e^2 = [-f/e] + int f'(s) ds/e with
+   f = omega conj(e), f' = omega' conj(e) + omega conj(tau'), the density's
+   derivative taken from its degree-15 interpolant.
+   Weight blocks: W[0..3] = D11, D12, D21, D22 on the panel's 16 nodes.       */
+
+__host__ __device__ inline void stk_tensor(double rx, double ry, double nx, double ny, const double *A, double *D)
+{
+    const double rn = rx * nx + ry * ny;
+    D[0] = -(A[0] * (2.0 * nx * rx + rn) + A[1] * rx * rx * rn + A[2] * rx * nx);
+    D[1] = -(A[0] * (nx * ry + rx * ny) + A[1] * rx * ry * rn + A[2] * rx * ny);
+    D[2] = -(A[0] * (ny * rx + ry * nx) + A[1] * ry * rx * rn + A[2] * ry * nx);
+    D[3] = -(A[0] * (2.0 * ny * ry + rn) + A[1] * ry * ry * rn + A[2] * ry * ny);
+}
+
+/* conj(B omega) as a real 2x2 block acting on (mu_1, mu_2), added to W[.][j] */
+__host__ __device__ inline void add_conj_block(cplx B, double (*W)[16], int j)
+{
+    W[0][j] += B.re;
+    W[1][j] -= B.im;
+    W[2][j] -= B.im;
+    W[3][j] -= B.re;
+}
+
+/* split coefficients A^S, A^L at distance r */
+__host__ __device__ inline void stk_split_coeffs(double alpha, double r, double *AS, double *AL)
+{
+    const StkSplit t = stresslet_split(alpha * r);
+    const double la = log(alpha), a2 = alpha * alpha, sc[3] = {a2, a2 * a2, a2};
+    for (int i = 0; i < 3; ++i) {
+        AS[i] = sc[i] * fma(t.l[i], la, t.s[i]);
+        AL[i] = sc[i] * t.l[i];
+    }
+}
+
+__host__ __device__ inline void direct_node_stokes(cplx z, const NodeGeo &g, double alpha, double *w4)
+{
+    const cplx e = z - g.tau; /* r = x - y */
+    const double r2 = cabs2(e);
+    const K01 o = k01_fp64<true, true>(r2, alpha, 0.25 * alpha * alpha, 4.0 / alpha);
+    double A[3];
+    stresslet_scaled(alpha, r2, 1.0 / r2, o.k0, o.ak1r, A);
+    const double sp_ = cabs(g.dtau);
+    double D[4];
+    stk_tensor(e.re, e.im, -g.dtau.im / sp_, g.dtau.re / sp_, A, D);
+    for (int b = 0; b < 4; ++b) w4[b] = D[b] * g.w;
+}
+
+template <int NQ>
+__host__ __device__ inline void leaf_direct_stokes(const cplx *a, const double *tq, const double *wq, double ta,
+                                                   double tb, cplx z, double alpha, double (*W)[16])
+{
+    NodeGeo g[NQ];
+    double WQ[4][NQ];
+    rule_geo<NQ>(a, tq, wq, ta, tb, g);
+    for (int k = 0; k < NQ; ++k) {
+        double w4[4];
+        direct_node_stokes(z, g[k], alpha, w4);
+        for (int b = 0; b < 4; ++b) WQ[b][k] = w4[b];
+    }
+    fold_add_n<NQ, 4>(tq, ta, tb, WQ, W);
+}
+
+/* Kernel split on the 32-point upsampled rule of [ta, tb] for a target off the
+   interval (complex parent preimage tstar, or real outside [ta, tb]). */
+__host__ __device__ inline void leaf_split32_stokes(const cplx *a, double ta, double tb, cplx z, cplx tstar,
+                                                    double alpha, double (*W)[16])
+{
+    constexpr int NQ = 32;
+    NodeGeo g[NQ];
+    double WQ[4][NQ];
+    cplx WB[16]; /* conj(WB omega): the by-parts stresslet term on the parent nodes */
+    rule_geo<NQ>(a, GL32_T, GL32_W, ta, tb, g);
+    const double mid = 0.5 * (ta + tb), half = 0.5 * (tb - ta);
+    const cplx ss = (1.0 / half) * (tstar - mk(mid, 0.0));
+    cplx MC[NQ + 1], ML[NQ], pc[NQ], pl[NQ];
+    legendre_moments<NQ>(ss, bernstein_rho(ss), MC, ML);
+    moments_to_weights<NQ>(LEGW32, MC, pc);
+    moments_to_weights<NQ>(LEGW32, ML, pl);
+    const cplx cf = mk(0.0, -0.25 / PI); /* -i/(4 pi) */
+    /* end-point terms of the by-parts integral: [-omega conj(e)/e]_ta^tb */
+    {
+        double la_[16], lb_[16];
+        cplx pa, pb, dpa, dpb;
+        leg_eval(a, mk(ta, 0.0), pa, dpa);
+        leg_eval(a, mk(tb, 0.0), pb, dpb);
+        lagrange16(ta, la_);
+        lagrange16(tb, lb_);
+        const cplx ea = pa - z, eb = pb - z;
+        const cplx qa = conj(ea) / ea, qb = conj(eb) / eb;
+        for (int j = 0; j < 16; ++j) WB[j] = cf * (la_[j] * qa - lb_[j] * qb);
+    }
+    const double a2 = alpha * alpha;
+    for (int k = 0; k < NQ; ++k) {
+        const double tkr = mid + half * GL32_T[k];
+        const cplx Q = half * leg_divdiff(a, mk(tkr, 0.0), tstar); /* (tau - z)/(s - s*) */
+        const double sp_ = cabs(g[k].dtau);
+        const double logw = fma(sp_, pl[k].re, g[k].w * log(cabs(Q)));
+        const cplx r = z - g[k].tau; /* x - y */
+        const cplx nu = mk(-g[k].dtau.im / sp_, g[k].dtau.re / sp_);
+        double AS[3], AL[3], Ds[4], Dl[4];
+        stk_split_coeffs(alpha, cabs(r), AS, AL);
+        stk_tensor(r.re, r.im, nu.re, nu.im, AS, Ds);
+        stk_tensor(r.re, r.im, nu.re, nu.im, AL, Dl);
+        const cplx iQ = mk(1.0, 0.0) / Q;
+        const cplx cdt = pc[k] * (g[k].dtau * iQ); /* weight of int f dtau/(tau - z) */
+        const double cw = cdt.im;                 /* Laplace double layer */
+        /* -(alpha^2/8pi) r_i r_j (r.n)/|r|^2  and  (1/2pi) omega Im(dtau/e) */
+        const double c8 = -a2 / (8.0 * PI) * cw, c2 = 0.5 / PI * cw;
+        WQ[0][k] = fma(Ds[0], g[k].w, Dl[0] * logw) + c8 * r.re * r.re + c2;
+        WQ[1][k] = fma(Ds[1], g[k].w, Dl[1] * logw) + c8 * r.re * r.im;
+        WQ[2][k] = fma(Ds[2], g[k].w, Dl[2] * logw) + c8 * r.im * r.re;
+        WQ[3][k] = fma(Ds[3], g[k].w, Dl[3] * logw) + c8 * r.im * r.im + c2;
+        /* conj((-i/4pi) int omega conj(nu)^2 dtau/e) at this node, and the
+           omega conj(tau') part of the by-parts integrand */
+        const cplx nb2 = conj(nu * nu);
+        const cplx B1 = cf * (nb2 * cdt);
+        const cplx B2 = cf * (pc[k] * conj(g[k].dtau) * iQ);
+        WQ[0][k] += B1.re + B2.re;
+        WQ[1][k] -= B1.im + B2.im;
+        WQ[2][k] -= B1.im + B2.im;
+        WQ[3][k] -= B1.re + B2.re;
+        /* omega' conj(e) part: the density derivative on the parent nodes */
+        double dl[16];
+        lagrange16_deriv(tkr, dl);
+        const cplx cD = cf * ((half * pc[k]) * (conj(mk(0.0, 0.0) - r) * iQ)); /* conj(e) = -conj(r) */
+        for (int j = 0; j < 16; ++j) WB[j] = WB[j] + dl[j] * cD;
+    }
+    fold_add_n<NQ, 4>(GL32_T, ta, tb, WQ, W);
+    for (int j = 0; j < 16; ++j) add_conj_block(WB[j], W, j);
+}
+
+/* Target on the curve at real local parameter sstar inside the rule's interval
+   (not at one of its nodes): the log part by kernel split with real moments;
+   the Cauchy-type and stresslet terms are smooth on the curve and taken by the
+   plain rule, with (x - y) and (x - y).n/|x - y|^2 from divided differences. */
+__host__ __device__ inline void leaf_oncurve_stokes(const cplx *a, double ta, double tb, double tstar, double alpha,
+                                                    double (*W)[16])
+{
+    constexpr int NQ = 32;
+    NodeGeo g[NQ];
+    double WQ[4][NQ];
+    rule_geo<NQ>(a, GL32_T, GL32_W, ta, tb, g);
+    const double mid = 0.5 * (ta + tb), half = 0.5 * (tb - ta);
+    const double ss = (tstar - mid) / half;
+    double MC[NQ + 1], ML[NQ], pl[NQ];
+    legendre_moments_real<NQ>(ss, MC, ML);
+    moments_to_weights<NQ>(LEGW32, ML, pl);
+    const double a2 = alpha * alpha;
+    for (int k = 0; k < NQ; ++k) {
+        const double sp_ = cabs(g[k].dtau);
+        const double tk = mid + half * GL32_T[k];
+        const double dl = tk - tstar;
+        cplx Qp, Rp;
+        leg_divdiff2(a, tk, tstar, Qp, Rp);
+        const double qq = cabs2(Qp);
+        const double r2 = dl * dl * qq;
+        const double spp = cabs(Qp + dl * Rp);
+        const double xr = (Qp.re * Rp.im - Qp.im * Rp.re) / (qq * spp); /* (x-y).n / r^2 */
+        const cplx r = (-dl) * Qp;                                       /* x - y */
+        const double ux = Qp.re * Qp.re / qq, uxy = Qp.re * Qp.im / qq, uy = Qp.im * Qp.im / qq; /* r^ r^ */
+        const double logw = fma(sp_, pl[k], g[k].w * log(half * sqrt(qq)));
+        const double nx = -g[k].dtau.im / sp_, ny = g[k].dtau.re / sp_;
+        double AS[3], AL[3], Ds[4], Dl[4];
+        stk_split_coeffs(alpha, sqrt(r2), AS, AL);
+        stk_tensor(r.re, r.im, nx, ny, AS, Ds);
+        stk_tensor(r.re, r.im, nx, ny, AL, Dl);
+        /* -(alpha^2/8pi) r_i r_j xr + (1/pi) r^_i r^_j xr */
+        const double cq = xr * (1.0 / PI - a2 / (8.0 * PI) * r2);
+        WQ[0][k] = fma(Ds[0], g[k].w, Dl[0] * logw) + cq * ux * g[k].w;
+        WQ[1][k] = fma(Ds[1], g[k].w, Dl[1] * logw) + cq * uxy * g[k].w;
+        WQ[2][k] = fma(Ds[2], g[k].w, Dl[2] * logw) + cq * uxy * g[k].w;
+        WQ[3][k] = fma(Ds[3], g[k].w, Dl[3] * logw) + cq * uy * g[k].w;
+    }
+    fold_add_n<NQ, 4>(GL32_T, ta, tb, WQ, W);
+}
+
+__host__ __device__ inline void leaf_apply_stokes(const cplx *a, double ta, double tb, cplx z, cplx tstar,
+                                                  double alpha, const NearParams &P, double (*W)[16])
+{
+    const double mid = 0.5 * (ta + tb), half = 0.5 * (tb - ta);
+    const cplx ss = (1.0 / half) * (tstar - mk(mid, 0.0));
+    const double rho = bernstein_rho(ss);
+    if (rho >= P.rho_direct)
+        leaf_direct_stokes<16>(a, GL16_T, GL16_W, ta, tb, z, alpha, W);
+    else if (rho >= P.rho_split)
+        leaf_direct_stokes<32>(a, GL32_T, GL32_W, ta, tb, z, alpha, W);
+    else
+        leaf_split32_stokes(a, ta, tb, z, tstar, alpha, W);
+}
+
+/* Stresslet correction weights of target z against a panel; self: node of
+   this panel that the target is (on-surface), or -1 (same tiers, subdivision
+   and on-curve treatment as the scalar double layer). */
+__host__ __device__ inline void pair_stokes_weights(const cplx *a, double h, cplx z, int self, cplx tstar,
+                                                    double alpha, const NearParams &P, double (*W)[16])
+{
+    for (int b = 0; b < 4; ++b)
+        for (int j = 0; j < 16; ++j) W[b][j] = 0.0;
+    auto leaf = [&](double a0, double b0) { leaf_apply_stokes(a, a0, b0, z, tstar, alpha, P, W); };
+    if (self >= 0) {
+        const double ts = GL16_T[self];
+        if (alpha * h <= P.ah_max) {
+            leaf_oncurve_stokes(a, -1.0, 1.0, ts, alpha, W);
+            return;
+        }
+        const double d = P.ah_max / (alpha * h);
+        const double c0 = ts - d > -1.0 ? ts - d : -1.0;
+        const double c1 = ts + d < 1.0 ? ts + d : 1.0;
+        leaf_oncurve_stokes(a, c0, c1, ts, alpha, W);
+        if (c0 > -1.0) subdivide_t(a, h, -1.0, c0, z, tstar, alpha, P, leaf);
+        if (c1 < 1.0) subdivide_t(a, h, c1, 1.0, z, tstar, alpha, P, leaf);
+        return;
+    }
+    if (alpha * h <= P.ah_max)
+        leaf(-1.0, 1.0);
+    else
+        subdivide_t(a, h, -1.0, 1.0, z, tstar, alpha, P, leaf);
+}
+
 } // namespace mhlp

@@ -421,6 +421,98 @@ __host__ __device__ inline SplitG split_k01_grad(double z)
 }
 
 /* ---------------------------------------------------------------------- */
+/* Stresslet functions of the modified-Stokes double layer (App. B, C).     */
+/*   T1 = -(2 z^2 K0 + (z^2 + 4) z K1 - 4)/(2 pi z^4)                         */
+/*   T2 = (4 z^2 K0 + (z^2 + 8) z K1 - 8)/(pi z^6)                            */
+/*   T3 = (z K1 - 1)/(2 pi z^2)                                              */
+/* and their kernel split (Sec. 4.1)                                          */
+/*   T1 = T1S + T1L log z,  T3 = T3S + T3L log z,                             */
+/*   T2 = T2S + T2L log z + 1/(8 pi z^2) - 1/(pi z^4),                         */
+/* the smooth parts from the power series of App. C with the log z factor     */
+/* taken out of its coefficients:                                             */
+/*   k0(n) = (psi(n+1) + log 2 - log z) a_n,  a_n = 1/(4^n n!^2),              */
+/*   k1(n) = (2 log z - 2 log 2 - psi(n+1) - psi(n+2)) b_n,                    */
+/*   b_n = 1/(4^(n+1) n! (n+1)!),                                             */
+/*   T1 = -(1/2pi) sum_{n>=1} (2 k0(n) + 4 k1(n) + k1(n-1)) z^(2n-2),           */
+/*   T2 - (explicit) = (1/pi) sum_{n>=2} (4 k0(n) + 8 k1(n) + k1(n-1)) z^(2n-4), */
+/*   T3 = (1/2pi) sum_{n>=0} k1(n) z^(2n).                                    */
+/* ---------------------------------------------------------------------- */
+struct StkSplit {
+    double s[3], l[3]; /* T1S, T2S, T3S and T1L, T2L, T3L */
+};
+
+__host__ __device__ inline StkSplit stresslet_split(double z)
+{
+    const double w = z * z;
+    double a = 1.0, b = 0.25;                       /* a_n, b_n */
+    double psi = -EULER_G, psi1 = 1.0 - EULER_G;    /* psi(n+1), psi(n+2) */
+    double pw = 1.0, pw1 = 0.0, pw2 = 0.0;          /* w^n, w^(n-1), w^(n-2) */
+    double k1s_prev = 0.0, k1l_prev = 0.0;
+    double t1s = 0.0, t1l = 0.0, t2s = 0.0, t2l = 0.0, t3s = 0.0, t3l = 0.0;
+    for (int n = 0; n < 64; ++n) {
+        const double k0s = (psi + LN2) * a, k0l = -a;
+        const double k1s = -(2.0 * LN2 + psi + psi1) * b, k1l = 2.0 * b;
+        const double d3s = k1s * pw, d3l = k1l * pw;
+        t3s += d3s;
+        t3l += d3l;
+        double d1 = 0.0, d2 = 0.0;
+        if (n >= 1) {
+            d1 = (2.0 * k0s + 4.0 * k1s + k1s_prev) * pw1;
+            t1s += d1;
+            t1l += (2.0 * k0l + 4.0 * k1l + k1l_prev) * pw1;
+        }
+        if (n >= 2) {
+            d2 = (4.0 * k0s + 8.0 * k1s + k1s_prev) * pw2;
+            t2s += d2;
+            t2l += (4.0 * k0l + 8.0 * k1l + k1l_prev) * pw2;
+        }
+        if (n >= 4 && fabs(d1) <= 1e-18 * fabs(t1s) && fabs(d2) <= 1e-18 * fabs(t2s) &&
+            fabs(d3s) <= 1e-18 * fabs(t3s))
+            break;
+        k1s_prev = k1s;
+        k1l_prev = k1l;
+        const double n1 = n + 1.0;
+        a *= 1.0 / (4.0 * n1 * n1);
+        b *= 1.0 / (4.0 * n1 * (n1 + 1.0));
+        psi += 1.0 / n1;
+        psi1 += 1.0 / (n1 + 1.0);
+        pw2 = pw1;
+        pw1 = pw;
+        pw *= w;
+    }
+    StkSplit o;
+    o.s[0] = -INV_2PI * t1s;
+    o.l[0] = -INV_2PI * t1l;
+    o.s[1] = t2s / PI;
+    o.l[1] = t2l / PI;
+    o.s[2] = INV_2PI * t3s;
+    o.l[2] = INV_2PI * t3l;
+    return o;
+}
+
+/* alpha^2 T1, alpha^4 T2, alpha^2 T3 at a source-target pair with r^2 = r2
+   (1/r^2 = ri2) from K0 and alpha K1(alpha r)/r (far-field values): closed
+   forms for z > 2, the split series for z <= 2 (the closed forms cancel). */
+__host__ __device__ inline void stresslet_scaled(double alpha, double r2, double ri2, double k0, double ak1r,
+                                                 double *A)
+{
+    const double a2 = alpha * alpha, w = a2 * r2; /* z^2 */
+    if (w > 4.0) {
+        const double zk1 = ak1r * r2;      /* z K1 */
+        const double ia2 = 1.0 / a2;
+        A[0] = -INV_2PI * ia2 * ri2 * ri2 * fma(2.0 * w, k0, fma(w + 4.0, zk1, -4.0));
+        A[1] = (ia2 / PI) * ri2 * ri2 * ri2 * fma(4.0 * w, k0, fma(w + 8.0, zk1, -8.0));
+        A[2] = INV_2PI * ri2 * (zk1 - 1.0);
+        return;
+    }
+    const StkSplit t = stresslet_split(sqrt(w));
+    const double lz = 0.5 * log(w);
+    A[0] = a2 * fma(t.l[0], lz, t.s[0]);
+    A[1] = a2 * a2 * fma(t.l[1], lz, t.s[1]) + a2 * ri2 / (8.0 * PI) - ri2 * ri2 / PI;
+    A[2] = a2 * fma(t.l[2], lz, t.s[2]);
+}
+
+/* ---------------------------------------------------------------------- */
 /* Minimal complex arithmetic                                               */
 /* ---------------------------------------------------------------------- */
 struct cplx {

@@ -71,6 +71,12 @@ _SIGS = {
     "mhlp_eval_dlp": ([_V, _V, _V, ctypes.c_int32, _V], ctypes.c_int32),
     "mhlp_apply_bie_operator": ([_V, _V, _V, ctypes.c_int32, _V], ctypes.c_int32),
     "mhlp_eval_grad": ([_V, _V, _V, _V, _V, _V, _V, _V], ctypes.c_int32),
+    "mhlp_stokes_plan_create": ([_V, ctypes.c_double, _V, _V, ctypes.c_int64, _V, _V, ctypes.POINTER(_V)],
+                                ctypes.c_int32),
+    "mhlp_stokes_eval": ([_V, _V, _V, _V], ctypes.c_int32),
+    "mhlp_stokes_apply_bie": ([_V, _V, _V, _V], ctypes.c_int32),
+    "mhlp_stokes_gmres_solve": ([_V, _V, _V, ctypes.POINTER(GmresOpts), ctypes.POINTER(GmresInfo), _V],
+                                ctypes.c_int32),
     "mhlp_gmres_solve": ([_V, _V, _V, ctypes.POINTER(GmresOpts), ctypes.POINTER(GmresInfo), _V], ctypes.c_int32),
     "mhlp_batch_create": ([ctypes.c_int32, ctypes.POINTER(_V), ctypes.c_int32, _V, ctypes.POINTER(_V)],
                           ctypes.c_int32),
@@ -175,13 +181,16 @@ class Geometry:
 
 
 class Plan:
-    """Targets + near-field corrections (``tx``/``ty`` None: on-surface plan)."""
+    """Targets + near-field corrections (``tx``/``ty`` None: on-surface plan).
+    ``stokes=True`` builds the modified-Stokes (stresslet) plan of the
+    ``stokes_*`` calls."""
 
     def __init__(self, geom: Geometry, alpha: float, tx: torch.Tensor | None = None, ty: torch.Tensor | None = None,
-                 params: dict | None = None):
+                 params: dict | None = None, stokes: bool = False):
         L = load()
         self.geom = geom
         self.alpha = float(alpha)
+        self.stokes = bool(stokes)
         prm = None
         if params:
             prm = Params(**{k: float(v) for k, v in params.items()})
@@ -191,8 +200,9 @@ class Plan:
         else:
             m = int(tx.numel())
             ptx, pty = _dev(tx, "tx"), _dev(ty, "ty", m)
-        _check(L.mhlp_plan_create(geom.handle, self.alpha, ptx, pty, m, ctypes.byref(prm) if prm else None, _stream(),
-                                  ctypes.byref(h)), "plan_create")
+        create = L.mhlp_stokes_plan_create if self.stokes else L.mhlp_plan_create
+        _check(create(geom.handle, self.alpha, ptx, pty, m, ctypes.byref(prm) if prm else None, _stream(),
+                      ctypes.byref(h)), "plan_create")
         self._h = h
         nt, ns, nn = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         _check(L.mhlp_plan_info(h, ctypes.byref(nt), ctypes.byref(ns), ctypes.byref(nn), None), "plan_info")
@@ -272,6 +282,38 @@ def eval_grad(plan: Plan, sigma=None, mu=None, out_slp=None, out_dlp=None):
         gd = [_dev(out_dlp[0], "grad_dlp[0]", M), _dev(out_dlp[1], "grad_dlp[1]", M)]
     _check(L.mhlp_eval_grad(plan.handle, ps, pm, gs[0], gs[1], gd[0], gd[1], _stream()), "eval_grad")
     return (out_slp if sigma is not None else None), (out_dlp if mu is not None else None)
+
+
+def stokes_eval(plan: Plan, mu, out=None):
+    """Modified-Stokes double layer of mu ([2][N] float64) at the plan's targets; returns [2][M]."""
+    L = load()
+    N, M = plan.n_sources, plan.n_targets
+    out = torch.empty(2, M, dtype=torch.float64, device=plan.geom.device) if out is None else out
+    _check(L.mhlp_stokes_eval(plan.handle, _dev(mu, "mu", 2 * N), _dev(out, "u", 2 * M), _stream()), "stokes_eval")
+    return out
+
+
+def stokes_apply_bie(plan: Plan, mu, out=None):
+    """(1/2 I + D + W) mu on an on-surface stokes plan; mu and the result [2][N]."""
+    L = load()
+    N = plan.n_sources
+    out = torch.empty(2, N, dtype=torch.float64, device=plan.geom.device) if out is None else out
+    _check(L.mhlp_stokes_apply_bie(plan.handle, _dev(mu, "mu", 2 * N), _dev(out, "out", 2 * N), _stream()),
+           "stokes_apply_bie")
+    return out
+
+
+def stokes_gmres_solve(plan: Plan, g, x0=None, tol=1e-10, max_iter=500, restart=100):
+    """Solve (1/2 I + D + W) mu = g ([2][N]); returns (mu, info dict)."""
+    L = load()
+    N = plan.n_sources
+    mu = torch.zeros(2, N, dtype=torch.float64, device=plan.geom.device) if x0 is None else x0.clone()
+    opts = GmresOpts(float(tol), int(max_iter), int(restart), FP64, 0 if x0 is None else 1)
+    info = GmresInfo()
+    rc = L.mhlp_stokes_gmres_solve(plan.handle, _dev(g, "g", 2 * N), _dev(mu, "mu", 2 * N), ctypes.byref(opts),
+                                   ctypes.byref(info), _stream())
+    _check(rc, "stokes_gmres_solve")
+    return mu, info.as_dict()
 
 
 def apply_bie(plan: Plan, mu, precision=FP64, out=None):

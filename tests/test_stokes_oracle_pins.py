@@ -191,3 +191,38 @@ def test_panel_stresslet_weights_bruteforce(dist):
     W = oracle.stokes_panel_weights(g.x, g.y, p, pt.real, pt.imag, alpha, mode=1)
     B = _bruteforce_panel_stokes(g.x[sl], g.y[sl], pt.real, pt.imag, alpha)
     assert np.max(np.abs(W - B)) < 1e-11 * np.max(np.abs(B))
+
+
+# ---------------------------------------------------------------------------
+# End to end: Dirichlet data of a modified-Stokes flow (the stokeslet of App. B,
+# S_ij = S1 d_ij + alpha^2 S2 r_i r_j, of point forces outside the domain),
+# solved with 1/2 I + D + W and represented by D[mu] inside, is the flow itself.
+# ---------------------------------------------------------------------------
+def stokeslet_field(alpha, x, y, sources):
+    u = np.zeros((2, np.size(x)))
+    for x0, F in sources:
+        rx, ry = x - x0.real, y - x0.imag
+        z = alpha * np.hypot(rx, ry)
+        K0, K1 = sp.k0(z), sp.k1(z)
+        S1 = (z * z * K0 + z * K1 - 1) / (2 * np.pi * z * z)
+        S2 = -(z * z * K0 + 2 * z * K1 - 2) / (2 * np.pi * z ** 4)
+        rF = rx * F[0] + ry * F[1]
+        u += np.array([S1 * F[0] + alpha ** 2 * S2 * rx * rF, S1 * F[1] + alpha ** 2 * S2 * ry * rF])
+    return u
+
+
+def test_stokeslet_flow_reproduced():
+    alpha = 3.0
+    curve = wl.starfish_curve()
+    g = wl.discretize(curve, 48)
+    sources = [(2.2 + 0.4j, (1.0, 0.3)), (-0.5 - 2.1j, (-0.4, 0.8))]
+    gb = stokeslet_field(alpha, g.x, g.y, sources)
+    nx, ny = g.normals
+    B = oracle.stokes_bie_matrix(oracle.stokes_matrix(g.x, g.y, alpha), g.weights, nx, ny)
+    mu = np.linalg.solve(B, gb.ravel()).reshape(2, -1)
+    th = np.array([0.3, 1.7, 4.0])
+    z, dz, _ = curve.eval(th)
+    nrm = 1j * dz / np.abs(dz)
+    pts = np.concatenate([[0.1 + 0.2j, -0.3 + 0.5j], z + 0.1 * nrm, z + 1e-3 * nrm])
+    u = oracle.stokes_eval(g.x, g.y, alpha, pts.real, pts.imag, mu)
+    assert np.abs(u - stokeslet_field(alpha, pts.real, pts.imag, sources)).max() < 1e-12 * np.abs(gb).max()
