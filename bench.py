@@ -44,6 +44,13 @@ FLOP_PER_PAIR_FP64 = 140
 # counted from the built kernel's loop, 42 + 2 FLOP per trip of two pairs
 # instead of the potentials' 14, so 140 + 15
 FLOP_PER_PAIR_GRAD = 155
+# modified-Stokes double layer (2x2 stresslet per pair): the same K0 and
+# alpha K1/r (140 less the potentials' 7 of accumulation), then 1/r^2 (1),
+# alpha^2 T1, alpha^4 T2, alpha^2 T3 from the closed forms of App. B (22) and
+# the contraction D_ij w mu_j into two accumulators (31): 187, counted from
+# the source of the z > 2 path (the counters read 191.6 at alpha = 500, 193.0
+# at 50 and 208.6 at 5, where more pairs take the z <= 2 fits)
+FLOP_PER_PAIR_STOKES = 187
 # launch shapes (far-field source splits) chosen by the autotuner on MI355X for
 # the plans of this benchmark; the HBM byte counts below were taken with them
 TUNED_SPLITS = os.path.join(ROOT, "paper_1908_07392_amd", "tuning", "mi355x_far_splits.json")
@@ -63,8 +70,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched, volume, warm-start and gradient legs")
-    ap.add_argument("--legs", default="batched,volume,warm,gradient",
-                    help="comma list of the extra legs to run (batched, volume, warm, gradient)")
+    ap.add_argument("--legs", default="batched,volume,warm,gradient,stokes",
+                    help="comma list of the extra legs to run (batched, volume, warm, gradient, stokes)")
     ap.add_argument("--tune-cache", default=TUNED_SPLITS,
                     help="JSON cache of the autotuned launch shapes (read; plans missing from it are tuned afresh)")
     ap.add_argument("--tune-write", action="store_true", help="add freshly tuned plans to the cache file")
@@ -273,6 +280,8 @@ def main():
         out["warm_start"] = bench_warm(mhlp, wl, t, torch)
     if "gradient" in legs:
         out["gradient"] = bench_grad(mhlp, plans, gdev, cfg, args, torch)
+    if "stokes" in legs:
+        out["stokes"] = bench_stokes(mhlp, wl, cfg, G, tx, ty, t, args, torch)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, 50.0, args.cpu_seconds)
     print(json.dumps(out), flush=True)
@@ -354,6 +363,65 @@ def bench_grad(mhlp, plans, gdev, cfg, args, torch):
                 "gpair_per_s": round(pairs / (ms * 1e-3) / 1e9, 3), "achieved_tflops": round(tf, 3),
                 "frac_of_fp64_peak": round(tf / FP64_PEAK_TFLOPS, 4),
                 "kernel": "far_grad_fp64<gradS,gradD> (+ grad_finalize when split)"})
+    return res
+
+
+def bench_stokes(mhlp, wl, cfg, G, tx, ty, t, args, torch):
+    """Modified-Stokes double layer (the paper's BIE kernel) on the same starfish and
+    targets: Dirichlet data of two exterior point forces (modified stokeslets),
+    GMRES for (1/2 I + D + W) mu = g to 1e-10 on the 2N = 8192 unknowns, then
+    D[mu] at the 109,314 targets; per alpha."""
+    print("# stokes leg", file=sys.stderr, flush=True)
+    import scipy.special as sp
+    from paper_1908_07392_amd import autotune
+    g = cfg["geom"]
+    sources = [(2.2 + 0.4j, (1.0, 0.3)), (-0.5 - 2.1j, (-0.4, 0.8))]
+    res = {"flop_per_pair": FLOP_PER_PAIR_STOKES}
+    by = {}
+    for a in cfg["alphas"]:
+        gb = np.zeros((2, g.n_nodes))
+        for x0, F in sources:
+            rx, ry = g.x - x0.real, g.y - x0.imag
+            z = a * np.hypot(rx, ry)
+            K0, K1 = sp.k0(z), sp.k1(z)  # underflow to 0 at large alpha: the 1/z^2 parts remain
+            S1 = (z * z * K0 + z * K1 - 1) / (2 * np.pi * z * z)
+            S2 = -(z * z * K0 + 2 * z * K1 - 2) / (2 * np.pi * z ** 4)
+            rF = rx * F[0] + ry * F[1]
+            gb += np.array([S1 * F[0] + a * a * S2 * rx * rF, S1 * F[1] + a * a * S2 * ry * rF])
+        gb /= np.abs(gb).max()
+        gd = t(gb)
+        t0 = time.perf_counter()
+        on = mhlp.Plan(G, a, stokes=True)
+        off = mhlp.Plan(G, a, tx, ty, stokes=True)
+        torch.cuda.synchronize()
+        build_ms = (time.perf_counter() - t0) * 1e3
+        kw = dict(use_cache=True, path=args.tune_cache, write=args.tune_write)
+        r_on = autotune.tune(on, "stokes", reps=3, **kw)
+        r_off = autotune.tune(off, "stokes", reps=3, **kw)
+        mhlp.stokes_gmres_solve(on, gd, tol=1e-10, restart=200)  # warm-up (graph capture)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mu, info = mhlp.stokes_gmres_solve(on, gd, tol=1e-10, restart=200)
+        torch.cuda.synchronize()
+        gm_ms = (time.perf_counter() - t0) * 1e3
+        mhlp.stokes_eval(off, mu)
+        reps = 10
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            mhlp.stokes_eval(off, mu)
+        e1.record()
+        torch.cuda.synchronize()
+        by[f"alpha={a:g}"] = {"gmres_ms": round(gm_ms, 3), "iters": info["iters"], "residual": info["rel_residual"],
+                              "eval_launch_ms": round(e0.elapsed_time(e1) / reps, 4), "plans_ms": round(build_ms, 1),
+                              "nsplit_bie": r_on["nsplit"], "nsplit_eval": r_off["nsplit"]}
+    ms = float(np.mean([v["eval_launch_ms"] for v in by.values()]))
+    pairs = off.n_targets * off.n_sources
+    tf = pairs * FLOP_PER_PAIR_STOKES / (ms * 1e-3) / 1e12
+    res.update({"by_alpha": by, "pairs_per_launch": pairs, "eval_launch_ms": round(ms, 4),
+                "eval_gpair_per_s": round(pairs / (ms * 1e-3) / 1e9, 3), "achieved_tflops": round(tf, 3),
+                "frac_of_fp64_peak": round(tf / FP64_PEAK_TFLOPS, 4),
+                "kernel": "far_stokes_fp64 (+ stk_finalize when split)"})
     return res
 
 

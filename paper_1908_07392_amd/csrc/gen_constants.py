@@ -80,6 +80,55 @@ def small_fns():
     return dict(I0=I0, I1Z=I1z, R0=R0, R1=R1)
 
 
+def stokes_small_fns():
+    """Smooth parts of the stresslet functions (paper Sec. 4.1, App. B) as
+    functions of q = z^2/4:  T1 = T1S + T1L log z,  T3 = T3S + T3L log z,
+    T2 = T2S + T2L log z + 1/(8 pi z^2) - 1/(pi z^4); evaluated from the closed
+    forms in 40-digit arithmetic (Chebyshev nodes are interior, q > 0)."""
+    def zq(q):
+        return 2 * mp.sqrt(q)
+
+    def T(z):
+        K0, K1 = mp.besselk(0, z), mp.besselk(1, z)
+        return (-(2 * z ** 2 * K0 + (z ** 2 + 4) * z * K1 - 4) / (2 * mp.pi * z ** 4),
+                (4 * z ** 2 * K0 + (z ** 2 + 8) * z * K1 - 8) / (mp.pi * z ** 6),
+                (z * K1 - 1) / (2 * mp.pi * z ** 2))
+
+    def TL(z):
+        I0, I1 = mp.besseli(0, z), mp.besseli(1, z)
+        return ((2 * z * I0 - (z ** 2 + 4) * I1) / (2 * mp.pi * z ** 3),
+                ((z ** 2 + 8) * I1 - 4 * z * I0) / (mp.pi * z ** 5),
+                I1 / (2 * mp.pi * z))
+
+    def S(i):
+        def f(q):
+            with mp.workdps(80):
+                z = zq(mp.mpf(q))
+                t, tl = T(z), TL(z)
+                v = t[i] - tl[i] * mp.log(z)
+                if i == 1:
+                    v -= 1 / (8 * mp.pi * z ** 2) - 1 / (mp.pi * z ** 4)
+                return +v
+        return f
+
+    def L(i):
+        def f(q):
+            with mp.workdps(80):
+                return +TL(zq(mp.mpf(q)))[i]
+        return f
+    return {f"STK_S{i + 1}": S(i) for i in range(3)} | {f"STK_L{i + 1}": L(i) for i in range(3)}
+
+
+def check_abs(coef, f):
+    qs = np.linspace(1e-6, 1, 400)
+    cc = np.array([float(c) for c in coef])
+    v = np.zeros_like(qs)
+    for a in cc[::-1]:
+        v = v * qs + a
+    ref = np.array([float(f(mp.mpf(q))) for q in qs])
+    return float(np.max(np.abs(v - ref)) / np.max(np.abs(ref)))
+
+
 def mono_in_q(f, deg):
     """Fit on q in [0, 1] with v = 2q - 1, then expand to powers of q."""
     m = cheb_fit_mono(f, deg, 0, 1)
@@ -222,6 +271,11 @@ def main():
         out.append(f"/* e^z sqrt(z) K{nu}(z) on u in [{float(lo):.4f}, {float(hi):.4f}] (u = 4/z - 1), as a polynomial"
                    f" in v = (2u - lo - hi)/(hi - lo) */")
         out.append(fmt(name, c))
+    for nm, f in stokes_small_fns().items():
+        c = mono_in_q(f, 13)
+        report.append((nm, check_abs(c, f), 0.0))
+        out.append(f"/* {nm}(q), q = z^2/4 in [0, 1]: smooth part of the stresslet function (max-abs fit) */")
+        out.append(fmt(nm, c))
     with open(os.path.join(HERE, "constants.h"), "w") as fh:
         fh.write("\n".join(out) + "\n")
     for r in report:

@@ -873,6 +873,7 @@ __global__ __launch_bounds__(FT_THREADS) void far_stokes_fp64(StkArgs A)
     }
     int32_t nxt = (k < kend) ? A.npan[k] : INT_MAX;
     const FarConst fc = far_const(A.alpha);
+    const double al2 = A.alpha * A.alpha, ial2 = fc.ia * fc.ia;
     double a1 = 0.0, a2 = 0.0;
     for (int64_t base = 16 * pb; base < 16 * pe; base += FT_SRC) {
         __syncthreads();
@@ -902,14 +903,13 @@ __global__ __launch_bounds__(FT_THREADS) void far_stokes_fp64(StkArgs A)
                 const double ex0 = x - lx[l0], ey0 = y - ly[l0];
                 const double ex1 = x - lx[l0 + 1], ey1 = y - ly[l0 + 1];
                 const double r20 = fma(ex0, ex0, ey0 * ey0), r21 = fma(ex1, ex1, ey1 * ey1);
-                K01 o[2];
-                k01_far2<true, true>(T, fc, r20, r21, o[0], o[1]);
-                const double ex[2] = {ex0, ex1}, ey[2] = {ey0, ey1}, r2[2] = {r20, r21};
+                double Ak2[2][3];
+                stk_far2(T, fc, al2, ial2, r20, r21, Ak2[0], Ak2[1]);
+                const double ex[2] = {ex0, ex1}, ey[2] = {ey0, ey1};
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
                     const int l = l0 + u;
-                    double Ak[3];
-                    stresslet_scaled(A.alpha, r2[u], o[u].ri2, o[u].k0, o[u].ak1r, Ak);
+                    const double *Ak = Ak2[u];
                     const double nx = lnx[l], ny = lny[l], m1 = lm1[l], m2 = lm2[l];
                     const double rn = fma(ex[u], nx, ey[u] * ny);
                     const double rm = fma(ex[u], m1, ey[u] * m2);

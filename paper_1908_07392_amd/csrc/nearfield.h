@@ -725,7 +725,7 @@ __host__ __device__ inline void direct_node_stokes(cplx z, const NodeGeo &g, dou
     const double r2 = cabs2(e);
     const K01 o = k01_fp64<true, true>(r2, alpha, 0.25 * alpha * alpha, 4.0 / alpha);
     double A[3];
-    stresslet_scaled(alpha, r2, 1.0 / r2, o.k0, o.ak1r, A);
+    stresslet_scaled(alpha * alpha, 1.0 / (alpha * alpha), r2, 1.0 / r2, o.k0, o.ak1r, A);
     const double sp_ = cabs(g.dtau);
     double D[4];
     stk_tensor(e.re, e.im, -g.dtau.im / sp_, g.dtau.re / sp_, A, D);

@@ -108,6 +108,7 @@ static constexpr double ATANH_T[11] = {1.0, 1.0 / 3.0, 1.0 / 5.0, 1.0 / 7.0, 1.0
 struct FarTable {
     double kp0n[17], kp0f[16], kp1n[15], kp1f[14], kl0[23], expt[14], atanh[11], ks_i0[12], ks_r0[13], ks_i1z[12],
         ks_r1[13];
+    double stk[6][14]; /* stresslet smooth parts T1S, T2S, T3S, T1L, T2L, T3L in q = z^2/4 <= 1 */
 };
 
 constexpr FarTable make_far_table()
@@ -122,6 +123,10 @@ constexpr FarTable make_far_table()
     for (int i = 0; i < 11; ++i) t.atanh[i] = ATANH_T[i];
     for (int i = 0; i < 12; ++i) t.ks_i0[i] = KS_I0[i], t.ks_i1z[i] = KS_I1Z[i];
     for (int i = 0; i < 13; ++i) t.ks_r0[i] = KS_R0[i], t.ks_r1[i] = KS_R1[i];
+    for (int i = 0; i < 14; ++i) {
+        t.stk[0][i] = STK_S1[i], t.stk[1][i] = STK_S2[i], t.stk[2][i] = STK_S3[i];
+        t.stk[3][i] = STK_L1[i], t.stk[4][i] = STK_L2[i], t.stk[5][i] = STK_L3[i];
+    }
     return t;
 }
 
@@ -276,42 +281,94 @@ __device__ __forceinline__ K01 k01_far_small(FarTab T, double r2, double a2q)
 
 /* PIECES = false (K0 only): one degree-22 fit over all z > 2 in u = 4/z - 1,
    for launches whose lanes often straddle z = 6 (targets in no spatial order) */
+/* the z > 2 forms for two sources, straight-line (see k01_far2) */
+template <bool SLP, bool DLP, bool PIECES = true>
+__device__ __forceinline__ void k01_far2_big(FarTab T, const FarConst &c, double r2a, double r2b, K01 &oa, K01 &ob)
+{
+    static_assert(PIECES || (SLP && !DLP), "the single fit serves the single layer only");
+    const double ria = lean_rsq(r2a), rib = lean_rsq(r2b);
+    const double za = c.a * (r2a * ria), zb = c.a * (r2b * rib);
+    const double ea = lean_exp_neg(T, za) * lean_rsq(za), eb = lean_exp_neg(T, zb) * lean_rsq(zb);
+    const bool fa = za > 6.0, fb = zb > 6.0;
+    double pa, pb, da = 0.0, db = 0.0;
+    if (!PIECES) {
+        pa = hornerc<23>(T->kl0, fma(c.a4, ria, -1.0));
+        pb = hornerc<23>(T->kl0, fma(c.a4, rib, -1.0));
+    } else if (fa && fb) {
+        pa = far_piece<SLP, DLP, true>(T, c, ria, da);
+        pb = far_piece<SLP, DLP, true>(T, c, rib, db);
+    } else if (!fa && !fb) {
+        pa = far_piece<SLP, DLP, false>(T, c, ria, da);
+        pb = far_piece<SLP, DLP, false>(T, c, rib, db);
+    } else {
+        if (fa)
+            pa = far_piece<SLP, DLP, true>(T, c, ria, da);
+        else
+            pa = far_piece<SLP, DLP, false>(T, c, ria, da);
+        if (fb)
+            pb = far_piece<SLP, DLP, true>(T, c, rib, db);
+        else
+            pb = far_piece<SLP, DLP, false>(T, c, rib, db);
+    }
+    oa = far_finish<SLP, DLP>(c, ria, za, ea, pa, da);
+    ob = far_finish<SLP, DLP>(c, rib, zb, eb, pb, db);
+}
+
+/* PIECES = false (K0 only): one degree-22 fit over all z > 2 in u = 4/z - 1,
+   for launches whose lanes often straddle z = 6 (targets in no spatial order) */
 template <bool SLP, bool DLP, bool PIECES = true>
 __device__ __forceinline__ void k01_far2(FarTab T, const FarConst &c, double r2a, double r2b, K01 &oa, K01 &ob)
 {
-    static_assert(PIECES || (SLP && !DLP), "the single fit serves the single layer only");
     const bool sa = c.a2q * r2a <= 1.0, sb = c.a2q * r2b <= 1.0;
-    if (!(sa && sb)) {
-        const double ria = lean_rsq(r2a), rib = lean_rsq(r2b);
-        const double za = c.a * (r2a * ria), zb = c.a * (r2b * rib);
-        const double ea = lean_exp_neg(T, za) * lean_rsq(za), eb = lean_exp_neg(T, zb) * lean_rsq(zb);
-        const bool fa = za > 6.0, fb = zb > 6.0;
-        double pa, pb, da = 0.0, db = 0.0;
-        if (!PIECES) {
-            pa = hornerc<23>(T->kl0, fma(c.a4, ria, -1.0));
-            pb = hornerc<23>(T->kl0, fma(c.a4, rib, -1.0));
-        } else if (fa && fb) {
-            pa = far_piece<SLP, DLP, true>(T, c, ria, da);
-            pb = far_piece<SLP, DLP, true>(T, c, rib, db);
-        } else if (!fa && !fb) {
-            pa = far_piece<SLP, DLP, false>(T, c, ria, da);
-            pb = far_piece<SLP, DLP, false>(T, c, rib, db);
-        } else {
-            if (fa)
-                pa = far_piece<SLP, DLP, true>(T, c, ria, da);
-            else
-                pa = far_piece<SLP, DLP, false>(T, c, ria, da);
-            if (fb)
-                pb = far_piece<SLP, DLP, true>(T, c, rib, db);
-            else
-                pb = far_piece<SLP, DLP, false>(T, c, rib, db);
-        }
-        oa = far_finish<SLP, DLP>(c, ria, za, ea, pa, da);
-        ob = far_finish<SLP, DLP>(c, rib, zb, eb, pb, db);
-    }
+    if (!(sa && sb)) k01_far2_big<SLP, DLP, PIECES>(T, c, r2a, r2b, oa, ob);
     if (sa || sb) {
         if (sa) oa = k01_far_small<SLP, DLP>(T, r2a, c.a2q);
         if (sb) ob = k01_far_small<SLP, DLP>(T, r2b, c.a2q);
+    }
+}
+
+/* alpha^2 T1, alpha^4 T2, alpha^2 T3 of the stresslet for two sources (far
+   tiles): closed forms from the z > 2 values of K0 and alpha K1/r, and for
+   z <= 2 the split T = TS + TL log z (+ the explicit terms of T2) with TS, TL
+   fitted in q = z^2/4 (the closed forms cancel there).  al2 = alpha^2,
+   ial2 = 1/alpha^2. */
+__device__ __forceinline__ void stk_closed(double al2, double ial2, double r2, double ri2, double k0, double ak1r,
+                                           double *A)
+{
+    const double w = al2 * r2;    /* z^2 */
+    const double zk1 = ak1r * r2; /* z K1 */
+    const double ri4 = ri2 * ri2;
+    A[0] = (-INV_2PI * ial2) * ri4 * fma(2.0 * w, k0, fma(w + 4.0, zk1, -4.0));
+    A[1] = (ial2 * (1.0 / PI)) * ri4 * ri2 * fma(4.0 * w, k0, fma(w + 8.0, zk1, -8.0));
+    A[2] = INV_2PI * ri2 * (zk1 - 1.0);
+}
+
+__device__ __forceinline__ void stk_small(FarTab T, const FarConst &c, double al2, double r2, double *A)
+{
+    const double q = c.a2q * r2;
+    const double lz = fma(0.5, lean_log01(T, q), LN2); /* log z = log(q)/2 + log 2 */
+    const double ri2 = lean_rcp(r2);
+    const double t1 = fma(hornerc<14>(T->stk[3], q), lz, hornerc<14>(T->stk[0], q));
+    const double t2 = fma(hornerc<14>(T->stk[4], q), lz, hornerc<14>(T->stk[1], q));
+    const double t3 = fma(hornerc<14>(T->stk[5], q), lz, hornerc<14>(T->stk[2], q));
+    A[0] = al2 * t1;
+    A[1] = fma(al2 * al2, t2, ri2 * fma(al2, 1.0 / (8.0 * PI), -ri2 * (1.0 / PI)));
+    A[2] = al2 * t3;
+}
+
+__device__ __forceinline__ void stk_far2(FarTab T, const FarConst &c, double al2, double ial2, double r2a,
+                                         double r2b, double *Aa, double *Ab)
+{
+    const bool sa = c.a2q * r2a <= 1.0, sb = c.a2q * r2b <= 1.0;
+    if (!(sa && sb)) {
+        K01 oa, ob;
+        k01_far2_big<true, true>(T, c, r2a, r2b, oa, ob);
+        stk_closed(al2, ial2, r2a, oa.ri2, oa.k0, oa.ak1r, Aa);
+        stk_closed(al2, ial2, r2b, ob.ri2, ob.k0, ob.ak1r, Ab);
+    }
+    if (sa || sb) {
+        if (sa) stk_small(T, c, al2, r2a, Aa);
+        if (sb) stk_small(T, c, al2, r2b, Ab);
     }
 }
 
@@ -492,16 +549,17 @@ __host__ __device__ inline StkSplit stresslet_split(double z)
 
 /* alpha^2 T1, alpha^4 T2, alpha^2 T3 at a source-target pair with r^2 = r2
    (1/r^2 = ri2) from K0 and alpha K1(alpha r)/r (far-field values): closed
-   forms for z > 2, the split series for z <= 2 (the closed forms cancel). */
-__host__ __device__ inline void stresslet_scaled(double alpha, double r2, double ri2, double k0, double ak1r,
+   forms for z > 2, the split series for z <= 2 (the closed forms cancel).
+   a2 = alpha^2, ia2 = 1/alpha^2. */
+__host__ __device__ inline void stresslet_scaled(double a2, double ia2, double r2, double ri2, double k0, double ak1r,
                                                  double *A)
 {
-    const double a2 = alpha * alpha, w = a2 * r2; /* z^2 */
+    const double w = a2 * r2; /* z^2 */
     if (w > 4.0) {
-        const double zk1 = ak1r * r2;      /* z K1 */
-        const double ia2 = 1.0 / a2;
-        A[0] = -INV_2PI * ia2 * ri2 * ri2 * fma(2.0 * w, k0, fma(w + 4.0, zk1, -4.0));
-        A[1] = (ia2 / PI) * ri2 * ri2 * ri2 * fma(4.0 * w, k0, fma(w + 8.0, zk1, -8.0));
+        const double zk1 = ak1r * r2; /* z K1 */
+        const double ri4 = ri2 * ri2;
+        A[0] = (-INV_2PI * ia2) * ri4 * fma(2.0 * w, k0, fma(w + 4.0, zk1, -4.0));
+        A[1] = (ia2 / PI) * ri4 * ri2 * fma(4.0 * w, k0, fma(w + 8.0, zk1, -8.0));
         A[2] = INV_2PI * ri2 * (zk1 - 1.0);
         return;
     }

@@ -224,7 +224,8 @@ class Plan:
 
     def autotune(self, layers: int = 3, precision=FP64, reps: int = 5):
         """Time the far evaluation over source-split counts and keep the fastest.
-        layers: 1 SLP, 2 DLP, 3 both, 4 BIE operator.  Returns (best, best_ms, {nsplit: ms})."""
+        layers: 1 SLP, 2 DLP, 3 both, 4 BIE operator, 5 gradients, 6 stresslet operator of a stokes
+        plan.  Returns (best, best_ms, {nsplit: ms})."""
         cap = 32
         cand, cms = (ctypes.c_int32 * cap)(), (ctypes.c_double * cap)()
         best, bms, nc = ctypes.c_int32(), ctypes.c_double(), ctypes.c_int32()
