@@ -55,6 +55,11 @@ def lib():
                                                ctypes.c_double, ctypes.c_int, ctypes.c_int, _D]
         L.orc_stokes_eval.argtypes = [_D, _D, ctypes.c_int64, _D, _D, ctypes.c_double, _D, _D, ctypes.c_int64,
                                       _I64, _D, _D, ctypes.c_int]
+        L.orc_stresslet_dT.argtypes = [ctypes.c_double, _D]
+        L.orc_stokes_grad_panel_weights.argtypes = [_D, _D, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                                    ctypes.c_double, ctypes.c_int, _D]
+        L.orc_stokes_grad_eval.argtypes = [_D, _D, ctypes.c_int64, _D, _D, ctypes.c_double, _D, _D, ctypes.c_int64,
+                                           _D, ctypes.c_int]
         L.orc_stokes_matrix.argtypes = [_D, _D, ctypes.c_int64, ctypes.c_double, _D, ctypes.c_int]
         L.orc_assemble_onsurface.argtypes = [_D, _D, ctypes.c_int64, ctypes.c_double, _D, _D, ctypes.c_int]
         L.orc_gmres.argtypes = [_D, ctypes.c_int64, _D, _D, ctypes.c_double, ctypes.c_int, ctypes.c_int,
@@ -185,6 +190,37 @@ def stokes_eval(x, y, alpha, tx, ty, mu, tgt_node=None, nthreads=0):
     if rc != 0:
         raise RuntimeError(f"orc_stokes_eval failed: {rc}")
     return u
+
+
+def stresslet_dT(z):
+    """(T1', T2', T3') at z > 0."""
+    out = np.zeros(3)
+    lib().orc_stresslet_dT(float(z), _p(out))
+    return tuple(out)
+
+
+def stokes_grad_panel_weights(x, y, panel, tx, ty, alpha, mode=0):
+    """[2][2][2][16] weights W[a][l][j]: d u_a/d x_l += sum_k W[a][l][j][k] mu_j(node k)."""
+    x, y = _c(x), _c(y)
+    W = np.zeros(128)
+    lib().orc_stokes_grad_panel_weights(_p(x), _p(y), int(panel), float(tx), float(ty), float(alpha), int(mode),
+                                        _p(W))
+    return W.reshape(2, 2, 2, 16)
+
+
+def stokes_grad_eval(x, y, alpha, tx, ty, mu, nthreads=0):
+    """Target gradient of the stresslet double layer of mu ([2][N]) at off-surface
+    targets; returns [2][2][m] = d u_a / d x_l."""
+    x, y, tx, ty = _c(x), _c(y), _c(tx), _c(ty)
+    mu = _c(mu).reshape(2, -1)
+    m = tx.size
+    g = np.zeros((4, m))
+    m1, m2 = np.ascontiguousarray(mu[0]), np.ascontiguousarray(mu[1])
+    rc = lib().orc_stokes_grad_eval(_p(x), _p(y), x.size // 16, _p(m1), _p(m2), float(alpha), _p(tx), _p(ty), m,
+                                    _p(g), int(nthreads))
+    if rc != 0:
+        raise RuntimeError(f"orc_stokes_grad_eval failed: {rc}")
+    return g.reshape(2, 2, m)
 
 
 def stokes_matrix(x, y, alpha, nthreads=0):

@@ -301,11 +301,12 @@ typedef struct {
     double dref[16];         /* tref - t_j   */
     int self;                /* node index of the target on this panel, or -1 */
     double alpha;
-    int grad;                /* 0: potentials (32 values), 1: gradients (64), 2: stresslet (64) */
+    int grad;                /* 0: potentials (32 values), 1: gradients (64), 2: stresslet (64),
+                                3: stresslet target gradient (128) */
     int nf;                  /* values per evaluation: 32 or 64              */
 } integrand_t;
 
-#define MAXF 64
+#define MAXF 128
 
 /* Lagrange basis l_j(t) of the 16 nodes at t = tref + s (barycentric form).
    Long double: the normal component (x-y).n of a target lying on or beside
@@ -374,6 +375,99 @@ static void stresslet_T(long double z, long double *T1, long double *T2, long do
     *T3 = s3 / (2.0L * PI_L);
 }
 
+/* Derivatives T1'..T3' (d/dz): for z > 1.5 from K0' = -K1, (z K1)' = -z K0:
+     T1' = K0/(2 pi z) - 4 T1/z,  T2' = -(z K0 + 2 K1)/(pi z^4) - 6 T2/z,
+     T3' = -K0/(2 pi z) - 2 T3/z;
+   below, the App. C series differentiated term by term (d log(z/2)/dz = 1/z). */
+static void stresslet_dT(long double z, long double *dT1, long double *dT2, long double *dT3)
+{
+    const long double PI_L = 3.14159265358979323846264338327950288L;
+    long double T1, T2, T3;
+    stresslet_T(z, &T1, &T2, &T3);
+    if (z > 1.5L) {
+        long double k0, k1;
+        bessel_k01_ld(z, &k0, &k1);
+        *dT1 = k0 / (2.0L * PI_L * z) - 4.0L * T1 / z;
+        *dT2 = -(z * k0 + 2.0L * k1) / (PI_L * z * z * z * z) - 6.0L * T2 / z;
+        *dT3 = -k0 / (2.0L * PI_L * z) - 2.0L * T3 / z;
+        return;
+    }
+    const long double L = logl(0.5L * z), z2 = z * z;
+    long double a[40], b[40], k0[40], k1[40];
+    long double psi = -EULER_GAMMA_L, f0 = 1.0L, f1 = 0.25L;
+    for (int n = 0; n < 40; ++n) {
+        const long double psi2 = psi + 1.0L / (n + 1.0L);
+        a[n] = f0;
+        b[n] = f1;
+        k0[n] = (psi - L) * f0;
+        k1[n] = (2.0L * L - psi - psi2) * f1;
+        psi = psi2;
+        f0 /= 4.0L * (n + 1.0L) * (n + 1.0L);
+        f1 /= 4.0L * (n + 1.0L) * (n + 2.0L);
+    }
+    /* d/dz [c_n z^p] = (dc_n/dL) z^(p-1) + p c_n z^(p-1), dk0/dL = -a_n, dk1/dL = 2 b_n */
+    long double s1 = 0.0L, s2 = 0.0L, s3 = 0.0L, zp;
+    zp = 1.0L / z; /* z^(2n-3) from n = 1 */
+    for (int n = 1; n < 40; ++n, zp *= z2) {
+        const long double c = 2.0L * k0[n] + 4.0L * k1[n] + k1[n - 1];
+        const long double dc = -2.0L * a[n] + 8.0L * b[n] + 2.0L * b[n - 1];
+        s1 += (dc + (2.0L * n - 2.0L) * c) * zp;
+    }
+    zp = 1.0L / z; /* z^(2n-5) from n = 2 */
+    for (int n = 2; n < 40; ++n, zp *= z2) {
+        const long double c = 4.0L * k0[n] + 8.0L * k1[n] + k1[n - 1];
+        const long double dc = -4.0L * a[n] + 16.0L * b[n] + 2.0L * b[n - 1];
+        s2 += (dc + (2.0L * n - 4.0L) * c) * zp;
+    }
+    zp = 1.0L / z; /* z^(2n-1) from n = 0 */
+    for (int n = 0; n < 40; ++n, zp *= z2) s3 += (2.0L * b[n] + 2.0L * n * k1[n]) * zp;
+    *dT1 = -s1 / (2.0L * PI_L);
+    *dT2 = 4.0L / (PI_L * z2 * z2 * z) - 1.0L / (4.0L * PI_L * z2 * z) + s2 / PI_L;
+    *dT3 = s3 / (2.0L * PI_L);
+}
+
+void orc_stresslet_dT(double z, double *T)
+{
+    long double a, b, c;
+    stresslet_dT(z, &a, &b, &c);
+    T[0] = (double)a;
+    T[1] = (double)b;
+    T[2] = (double)c;
+}
+
+/* Target gradient of the stresslet double layer kernel:
+   dD[(2 i + l) 2 + j] = d/dx_l D_ij(x, y), r = x - y, n = n_y, with
+   A_k = a_k T_k(z), B_k = A_k'(|r|)/|r| = a_k alpha T_k'(z)/|r|, a = (alpha^2, alpha^4, alpha^2):
+   d_l D_ij = -[ r_l (B1 P1_ij + B2 P2_ij + B3 P3_ij)
+                 + A1 (n_i d_jl + d_il n_j + d_ij n_l)
+                 + A2 (d_il r_j (r.n) + r_i d_jl (r.n) + r_i r_j n_l) + A3 d_il n_j ],
+   P1 = n_i r_j + r_i n_j + d_ij (r.n), P2 = r_i r_j (r.n), P3 = r_i n_j. */
+static void stresslet_dD(long double rx, long double ry, long double nx, long double ny, long double alpha,
+                         long double *dD)
+{
+    const long double r2 = rx * rx + ry * ry, r = sqrtl(r2), z = alpha * r;
+    long double T1, T2, T3, d1, d2, d3;
+    stresslet_T(z, &T1, &T2, &T3);
+    stresslet_dT(z, &d1, &d2, &d3);
+    const long double a2 = alpha * alpha, a4 = a2 * a2;
+    const long double A[3] = {a2 * T1, a4 * T2, a2 * T3};
+    const long double B[3] = {a2 * alpha * d1 / r, a4 * alpha * d2 / r, a2 * alpha * d3 / r};
+    const long double rv[2] = {rx, ry}, nv[2] = {nx, ny};
+    const long double rn = rx * nx + ry * ny;
+    for (int i = 0; i < 2; ++i)
+        for (int l = 0; l < 2; ++l)
+            for (int j = 0; j < 2; ++j) {
+                const long double dij = i == j, dil = i == l, djl = j == l;
+                const long double P1 = nv[i] * rv[j] + rv[i] * nv[j] + dij * rn;
+                const long double P2 = rv[i] * rv[j] * rn, P3 = rv[i] * nv[j];
+                const long double v = rv[l] * (B[0] * P1 + B[1] * P2 + B[2] * P3) +
+                                      A[0] * (nv[i] * djl + dil * nv[j] + dij * nv[l]) +
+                                      A[1] * (dil * rv[j] * rn + rv[i] * djl * rn + rv[i] * rv[j] * nv[l]) +
+                                      A[2] * dil * nv[j];
+                dD[(2 * i + l) * 2 + j] = -v;
+            }
+}
+
 void orc_stresslet_T(double z, double *T)
 {
     long double a, b, c;
@@ -419,6 +513,15 @@ static void integrand(const integrand_t *c, double s, long double *F)
     }
     /* y - x = (rx, ry);  (x - y).n_y |y'| = (x - y).(-dy, dx) = rx dy - ry dx */
     long double xmyn = rx * dy - ry * dx;
+    if (c->grad == 3) {
+        /* stresslet gradient: F[b 16 + k] = dD[b] l_k |y'|, b = (2i + l) 2 + j */
+        long double speed = sqrtl(dx * dx + dy * dy);
+        long double dD[8];
+        stresslet_dD(-rx, -ry, -dy / speed, dx / speed, c->alpha, dD);
+        for (int b = 0; b < 8; ++b)
+            for (int k = 0; k < 16; ++k) F[b * 16 + k] = dD[b] * speed * l[k];
+        return;
+    }
     if (c->grad == 2) {
         /* stresslet: F[(2i+j)16 + l] = D_ij l_l |y'|, r = x - y = -(rx, ry) */
         long double speed = sqrtl(dx * dx + dy * dy);
@@ -531,10 +634,10 @@ static void integrate_pieces(const integrand_t *c, const double *cuts, int ncut,
 {
     const int nf = c->nf, nk = c->nf / 16;
     long double tmp[MAXF], ab[MAXF], acc[MAXF];
-    double fl0[4] = {0.0, 0.0, 0.0, 0.0}, fl[4] = {0.0, 0.0, 0.0, 0.0};
+    double fl0[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, fl[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     /* the accurate pass of the gradient kernels (long double arithmetic) is
        judged against a finer floor */
-    const double floor_rel = c->grad ? 2e-18 : 2e-16;
+    const double floor_rel = (c->grad == 1 || c->grad == 3) ? 2e-18 : 2e-16;
     for (int k = 0; k < nf; ++k) tmp[k] = ab[k] = acc[k] = 0.0L;
     for (int q = 0; q + 1 < ncut; ++q) {
         long double I[MAXF], A[MAXF];
@@ -546,7 +649,7 @@ static void integrate_pieces(const integrand_t *c, const double *cuts, int ncut,
     for (int k = 0; k < nf; ++k) fl[k >> 4] = fmax(fl[k >> 4], (double)ab[k]);
     for (int b = 0; b < nk; ++b) fl[b] *= floor_rel;
     for (int q = 0; q + 1 < ncut; ++q)
-        adaptive(c, cuts[q], cuts[q + 1], c->grad ? ORC_RTOL_GRAD : ORC_RTOL, fl, acc, NULL);
+        adaptive(c, cuts[q], cuts[q + 1], (c->grad == 1 || c->grad == 3) ? ORC_RTOL_GRAD : ORC_RTOL, fl, acc, NULL);
     for (int k = 0; k < nf; ++k) W[k] = (double)acc[k];
 }
 
@@ -558,7 +661,7 @@ static void panel_exact_k(const panel_t *p, double tx, double ty, double alpha, 
 {
     integrand_t c;
     c.grad = grad;
-    c.nf = grad ? 64 : 32; /* gradients and stresslet: 4 blocks of 16 */
+    c.nf = grad == 3 ? 128 : grad ? 64 : 32; /* 2, 4 or 8 blocks of 16 */
     c.p = p;
     c.tx = tx;
     c.ty = ty;
@@ -641,6 +744,18 @@ static void panel_direct_stokes(const panel_t *p, double tx, double ty, double a
                      alpha, D);
         for (int a = 0; a < 2; ++a)
             for (int b = 0; b < 2; ++b) W[(2 * a + b) * 16 + j] = (double)(D[a][b] * speed * GL16_W[j]);
+    }
+}
+
+/* direct 16-point weights of the stresslet gradient (128 values) */
+static void panel_direct_stokes_grad(const panel_t *p, double tx, double ty, double alpha, double *W)
+{
+    for (int j = 0; j < 16; ++j) {
+        long double speed = sqrtl(p->dxl[j] * p->dxl[j] + p->dyl[j] * p->dyl[j]);
+        long double dD[8];
+        stresslet_dD((long double)tx - p->x[j], (long double)ty - p->y[j], -p->dyl[j] / speed, p->dxl[j] / speed,
+                     alpha, dD);
+        for (int b = 0; b < 8; ++b) W[b * 16 + j] = (double)(dD[b] * speed * GL16_W[j]);
     }
 }
 
@@ -838,6 +953,56 @@ int orc_stokes_eval(const double *x, const double *y, int64_t n_panels, const do
         }
         u1[i] = (double)a1;
         u2[i] = (double)a2;
+    }
+    free(P);
+    return 0;
+}
+
+/* Stresslet-gradient weights of one off-surface target against one panel
+   (W: 128 doubles, block (2i + l) 2 + j = d/dx_l D_ij).  mode: 0 auto,
+   1 exact, 2 direct. */
+int orc_stokes_grad_panel_weights(const double *x, const double *y, int64_t panel, double tx, double ty,
+                                  double alpha, int mode, double *W)
+{
+    init_rules();
+    panel_t p;
+    panel_setup(&p, x + 16 * panel, y + 16 * panel);
+    if (mode == 2)
+        panel_direct_stokes_grad(&p, tx, ty, alpha, W);
+    else if (mode == 1 || panel_is_near(&p, tx, ty))
+        panel_exact_k(&p, tx, ty, alpha, -1, 3, W);
+    else
+        panel_direct_stokes_grad(&p, tx, ty, alpha, W);
+    return 0;
+}
+
+/* Target gradient of the stresslet double layer at m off-surface targets:
+   g[c * m + i] = d/dx_l u_a(x_i) for c = 2a + l (du1/dx1, du1/dx2, du2/dx1,
+   du2/dx2). */
+int orc_stokes_grad_eval(const double *x, const double *y, int64_t n_panels, const double *mu1, const double *mu2,
+                         double alpha, const double *tx, const double *ty, int64_t m, double *g, int nthreads)
+{
+    init_rules();
+    if (alpha <= 0.0 || n_panels <= 0 || m < 0) return -1;
+    panel_t *P = (panel_t *)malloc(sizeof(panel_t) * (size_t)n_panels);
+    if (!P) return -2;
+    for (int64_t p = 0; p < n_panels; ++p) panel_setup(&P[p], x + 16 * p, y + 16 * p);
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 2)
+    for (int64_t i = 0; i < m; ++i) {
+        long double acc[4] = {0.0L, 0.0L, 0.0L, 0.0L};
+        for (int64_t p = 0; p < n_panels; ++p) {
+            double W[128];
+            if (panel_is_near(&P[p], tx[i], ty[i]))
+                panel_exact_k(&P[p], tx[i], ty[i], alpha, -1, 3, W);
+            else
+                panel_direct_stokes_grad(&P[p], tx[i], ty[i], alpha, W);
+            for (int c = 0; c < 4; ++c)
+                for (int k = 0; k < 16; ++k)
+                    acc[c] += (long double)W[(2 * c) * 16 + k] * mu1[16 * p + k] +
+                              (long double)W[(2 * c + 1) * 16 + k] * mu2[16 * p + k];
+        }
+        for (int c = 0; c < 4; ++c) g[c * m + i] = (double)acc[c];
     }
     free(P);
     return 0;

@@ -226,3 +226,124 @@ def test_stokeslet_flow_reproduced():
     pts = np.concatenate([[0.1 + 0.2j, -0.3 + 0.5j], z + 0.1 * nrm, z + 1e-3 * nrm])
     u = oracle.stokes_eval(g.x, g.y, alpha, pts.real, pts.imag, mu)
     assert np.abs(u - stokeslet_field(alpha, pts.real, pts.imag, sources)).max() < 1e-12 * np.abs(gb).max()
+
+
+# ---------------------------------------------------------------------------
+# Target gradient of the stresslet double layer (the paper's Sec. 4.4)
+# ---------------------------------------------------------------------------
+def test_stresslet_function_derivatives():
+    mp.mp.dps = 40
+
+    def T(z):
+        K0, K1 = mp.besselk(0, z), mp.besselk(1, z)
+        return [-(2 * z ** 2 * K0 + (z ** 2 + 4) * z * K1 - 4) / (2 * mp.pi * z ** 4),
+                (4 * z ** 2 * K0 + (z ** 2 + 8) * z * K1 - 8) / (mp.pi * z ** 6),
+                (z * K1 - 1) / (2 * mp.pi * z ** 2)]
+    for z in (1e-3, 0.1, 0.9, 1.4999, 1.5001, 3.0, 20.0):
+        d = oracle.stresslet_dT(z)
+        for i in range(3):
+            ref = mp.diff(lambda t: T(t)[i], mp.mpf(z))
+            assert abs(d[i] / float(ref) - 1.0) < 1e-15, (z, i)
+
+
+def test_stokes_gradient_finite_differences_and_divergence(starfish):
+    g, mu = starfish
+    alpha = 8.0
+    curve = wl.starfish_curve()
+    zc, dzc, _ = curve.eval(np.array([0.4, 2.0, 4.4]))
+    nrm = 1j * dzc / np.abs(dzc)
+    pts = np.concatenate([[0.1 + 0.2j, -0.4 + 0.3j], zc + 0.05 * nrm])
+    G = oracle.stokes_grad_eval(g.x, g.y, alpha, pts.real, pts.imag, mu)  # [a][l][m]
+    h = 2.5e-4  # truncation ~ (h/0.05)^4 next to the curve
+    for l in range(2):
+        vals = []
+        for k in (-2, -1, 1, 2):
+            d = k * h * (1 if l == 0 else 1j)
+            vals.append(oracle.stokes_eval(g.x, g.y, alpha, (pts + d).real, (pts + d).imag, mu))
+        fd = (vals[0] - 8 * vals[1] + 8 * vals[2] - vals[3]) / (12 * h)
+        assert np.abs(fd - G[:, l, :]).max() < 1e-8 * np.abs(G).max(), l
+    # the flow is divergence-free, also next to the curve
+    near = np.concatenate([zc + d * nrm for d in (1e-2, 1e-3, 1e-4)])
+    Gn = oracle.stokes_grad_eval(g.x, g.y, alpha, near.real, near.imag, mu)
+    assert np.abs(Gn[0, 0] + Gn[1, 1]).max() < 1e-10 * np.abs(Gn).max()
+
+
+def stokeslet_gradient(alpha, x, y, sources, h=1e-6):
+    """Gradient [a][l][m] of the stokeslet field by fourth-order differences of its closed form."""
+    G = np.zeros((2, 2, np.size(x)))
+    for l, d in enumerate((h, 1j * h)):
+        v = [stokeslet_field(alpha, x + (k * d).real, y + (k * d).imag, sources) for k in (-2, -1, 1, 2)]
+        G[:, l, :] = (v[0] - 8 * v[1] + 8 * v[2] - v[3]) / (12 * h)
+    return G
+
+
+def test_stokeslet_flow_gradient_reproduced():
+    alpha = 3.0
+    curve = wl.starfish_curve()
+    g = wl.discretize(curve, 48)
+    sources = [(2.2 + 0.4j, (1.0, 0.3)), (-0.5 - 2.1j, (-0.4, 0.8))]
+    gb = stokeslet_field(alpha, g.x, g.y, sources)
+    nx, ny = g.normals
+    B = oracle.stokes_bie_matrix(oracle.stokes_matrix(g.x, g.y, alpha), g.weights, nx, ny)
+    mu = np.linalg.solve(B, gb.ravel()).reshape(2, -1)
+    z, dz, _ = curve.eval(np.array([0.3, 1.7, 4.0]))
+    nrm = 1j * dz / np.abs(dz)
+    pts = np.concatenate([[0.1 + 0.2j, -0.3 + 0.5j], z + 0.1 * nrm, z + 1e-2 * nrm])
+    G = oracle.stokes_grad_eval(g.x, g.y, alpha, pts.real, pts.imag, mu)
+    ref = stokeslet_gradient(alpha, pts.real, pts.imag, sources)
+    assert np.abs(G - ref).max() < 1e-8 * np.abs(ref).max()
+
+
+def _bruteforce_panel_stokes_grad(x, y, tx, ty, alpha):
+    leg = np.polynomial.legendre
+    t16, _ = leg.leggauss(16)
+    Vinv = np.linalg.inv(leg.legvander(t16, 15))
+    cx, cy = Vinv @ x, Vinv @ y
+    dcx, dcy = leg.legder(cx), leg.legder(cy)
+    tg, wg = leg.leggauss(20)
+    g = np.linspace(-1, 1, 65)
+    W = np.zeros((2, 2, 2, 16))
+    for a, b in zip(g[:-1], g[1:]):
+        t = 0.5 * (a + b) + 0.5 * (b - a) * tg
+        wq = 0.5 * (b - a) * wg
+        L = leg.legvander(t, 15) @ Vinv
+        px, py = leg.legval(t, cx), leg.legval(t, cy)
+        dx, dy = leg.legval(t, dcx), leg.legval(t, dcy)
+        speed = np.hypot(dx, dy)
+        n = np.array([-dy / speed, dx / speed])
+        r = np.array([tx - px, ty - py])
+        rr = np.hypot(r[0], r[1])
+        z = alpha * rr
+        K0, K1 = sp.k0(z), sp.k1(z)
+        T = [-(2 * z ** 2 * K0 + (z ** 2 + 4) * z * K1 - 4) / (2 * np.pi * z ** 4),
+             (4 * z ** 2 * K0 + (z ** 2 + 8) * z * K1 - 8) / (np.pi * z ** 6), (z * K1 - 1) / (2 * np.pi * z ** 2)]
+        dT = [K0 / (2 * np.pi * z) - 4 * T[0] / z, -(z * K0 + 2 * K1) / (np.pi * z ** 4) - 6 * T[1] / z,
+              -K0 / (2 * np.pi * z) - 2 * T[2] / z]
+        sc = [alpha ** 2, alpha ** 4, alpha ** 2]
+        A = [sc[k] * T[k] for k in range(3)]
+        Bk = [sc[k] * alpha * dT[k] / rr for k in range(3)]
+        rn = r[0] * n[0] + r[1] * n[1]
+        for i in range(2):
+            for l in range(2):
+                for j in range(2):
+                    P1 = n[i] * r[j] + r[i] * n[j] + (i == j) * rn
+                    v = (r[l] * (Bk[0] * P1 + Bk[1] * r[i] * r[j] * rn + Bk[2] * r[i] * n[j])
+                         + A[0] * (n[i] * (j == l) + (i == l) * n[j] + (i == j) * n[l])
+                         + A[1] * ((i == l) * r[j] * rn + r[i] * (j == l) * rn + r[i] * r[j] * n[l])
+                         + A[2] * (i == l) * n[j])
+                    W[i, l, j] += (L * (-v * speed * wq)[:, None]).sum(0)
+    return W
+
+
+def test_panel_stokes_gradient_weights_bruteforce():
+    # target 0.3 from the panel with alpha 30: z >= 9 everywhere, plain composite rule
+    curve = wl.Curve("ellipse", a=1.3, b=0.7)
+    g = wl.discretize(curve, 12)
+    p = 4
+    sl = slice(16 * p, 16 * p + 16)
+    th = 0.5 * (g.theta[sl][6] + g.theta[sl][7])
+    z, dz, _ = curve.eval(th)
+    pt = z + 0.3 * 1j * dz / abs(dz)
+    W = oracle.stokes_grad_panel_weights(g.x, g.y, p, pt.real, pt.imag, 30.0, mode=1)
+    B = _bruteforce_panel_stokes_grad(g.x[sl], g.y[sl], pt.real, pt.imag, 30.0)
+    assert np.max(np.abs(W - B)) < 1e-12 * np.max(np.abs(B))
