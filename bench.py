@@ -51,6 +51,11 @@ FLOP_PER_PAIR_GRAD = 155
 # the source of the z > 2 path (the counters read 191.6 at alpha = 500, 193.0
 # at 50 and 208.6 at 5, where more pairs take the z <= 2 fits)
 FLOP_PER_PAIR_STOKES = 187
+# target gradient of the stresslet double layer (velocity gradient, 4 outputs):
+# the same K0, alpha K1/r, 1/r^2 and A_k (156), B_k = A_k'(r)/r from K0 and A_k
+# (12), and the contraction d_l D_ij w mu_j into four accumulators (71), counted
+# from the source of the z > 2 path
+FLOP_PER_PAIR_STOKES_GRAD = 239
 # launch shapes (far-field source splits) chosen by the autotuner on MI355X for
 # the plans of this benchmark; the HBM byte counts below were taken with them
 TUNED_SPLITS = os.path.join(ROOT, "paper_1908_07392_amd", "tuning", "mi355x_far_splits.json")
@@ -370,7 +375,8 @@ def bench_stokes(mhlp, wl, cfg, G, tx, ty, t, args, torch):
     """Modified-Stokes double layer (the paper's BIE kernel) on the same starfish and
     targets: Dirichlet data of two exterior point forces (modified stokeslets),
     GMRES for (1/2 I + D + W) mu = g to 1e-10 on the 2N = 8192 unknowns, then
-    D[mu] at the 109,314 targets; per alpha."""
+    D[mu] and its target gradient (the velocity gradient) at the 109,314 targets;
+    per alpha."""
     print("# stokes leg", file=sys.stderr, flush=True)
     import scipy.special as sp
     from paper_1908_07392_amd import autotune
@@ -412,16 +418,39 @@ def bench_stokes(mhlp, wl, cfg, G, tx, ty, t, args, torch):
             mhlp.stokes_eval(off, mu)
         e1.record()
         torch.cuda.synchronize()
+        eval_ms = e0.elapsed_time(e1) / reps
+        # velocity gradient of the same flow at the same targets: first call
+        # (builds the 128 gradient weights per near pair), then steady launches
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mhlp.stokes_eval_grad(off, mu)
+        torch.cuda.synchronize()
+        gbuild_ms = (time.perf_counter() - t0) * 1e3
+        r_g = autotune.tune(off, "stokes_grad", reps=3, **kw)
+        mhlp.stokes_eval_grad(off, mu)
+        e0.record()
+        for _ in range(reps):
+            mhlp.stokes_eval_grad(off, mu)
+        e1.record()
+        torch.cuda.synchronize()
         by[f"alpha={a:g}"] = {"gmres_ms": round(gm_ms, 3), "iters": info["iters"], "residual": info["rel_residual"],
-                              "eval_launch_ms": round(e0.elapsed_time(e1) / reps, 4), "plans_ms": round(build_ms, 1),
-                              "nsplit_bie": r_on["nsplit"], "nsplit_eval": r_off["nsplit"]}
+                              "eval_launch_ms": round(eval_ms, 4), "plans_ms": round(build_ms, 1),
+                              "nsplit_bie": r_on["nsplit"], "nsplit_eval": r_off["nsplit"],
+                              "grad_launch_ms": round(e0.elapsed_time(e1) / reps, 4),
+                              "grad_first_call_ms": round(gbuild_ms, 2), "nsplit_grad": r_g["nsplit"]}
     ms = float(np.mean([v["eval_launch_ms"] for v in by.values()]))
+    gms = float(np.mean([v["grad_launch_ms"] for v in by.values()]))
     pairs = off.n_targets * off.n_sources
     tf = pairs * FLOP_PER_PAIR_STOKES / (ms * 1e-3) / 1e12
+    gtf = pairs * FLOP_PER_PAIR_STOKES_GRAD / (gms * 1e-3) / 1e12
     res.update({"by_alpha": by, "pairs_per_launch": pairs, "eval_launch_ms": round(ms, 4),
                 "eval_gpair_per_s": round(pairs / (ms * 1e-3) / 1e9, 3), "achieved_tflops": round(tf, 3),
                 "frac_of_fp64_peak": round(tf / FP64_PEAK_TFLOPS, 4),
-                "kernel": "far_stokes_fp64 (+ stk_finalize when split)"})
+                "kernel": "far_stokes_fp64 (+ stk_finalize when split)",
+                "grad": {"flop_per_pair": FLOP_PER_PAIR_STOKES_GRAD, "launch_ms": round(gms, 4),
+                         "gpair_per_s": round(pairs / (gms * 1e-3) / 1e9, 3), "achieved_tflops": round(gtf, 3),
+                         "frac_of_fp64_peak": round(gtf / FP64_PEAK_TFLOPS, 4),
+                         "kernel": "far_stokes_grad_fp64 (+ stkg_finalize when split)"}})
     return res
 
 

@@ -116,7 +116,8 @@ mhlp_status mhlp_plan_info(const mhlp_plan *plan, int64_t *n_targets, int64_t *n
    partial-sum buffer (it synchronises the device then).
    mhlp_plan_autotune times the far evaluation (layers: 1 SLP, 2 DLP, 3 both,
    4 the on-surface BIE operator, 5 the gradients of both, off-surface, 6 the
-   stresslet operator of a stokes plan) for nsplit = 1, 2, 4, ... (up to Np/4 and
+   stresslet operator of a stokes plan, 7 the stresslet target gradient of an
+   off-surface stokes plan) for nsplit = 1, 2, 4, ... (up to Np/4 and
    256) plus the current value, reps timed launches each after one warm-up,
    with HIP events on `stream`, keeps the fewest splits within 1% of the
    fastest and reports it with its time (host outputs; cand/cand_ms receive up
@@ -167,6 +168,29 @@ mhlp_status mhlp_stokes_eval(const mhlp_plan *plan, const double *mu, double *u,
 mhlp_status mhlp_stokes_apply_bie(const mhlp_plan *onsurf, const double *mu, double *out, void *stream);
 mhlp_status mhlp_stokes_gmres_solve(const mhlp_plan *onsurf, const double *g, double *mu, const mhlp_gmres_opts *opts,
                                     mhlp_gmres_info *info, void *stream);
+
+/* Target gradient of the modified-Stokes double layer on an off-surface
+   stokes plan (the near-boundary gradient of Sec. 4.4 for the paper's BIE
+   kernel), the velocity gradient of the represented flow:
+     d u_i/d x_l = int_Gamma d/dx_l D_ij(x, y) mu_j(y) dS_y,
+     d_l D_ij = -[ r_l (B1 P1 + B2 P2 + B3 P3)_ij + A1 dP1 + A2 dP2 + A3 dP3 ],
+   with D_ij = -(A1 P1 + A2 P2 + A3 P3)_ij as for mhlp_stokes_eval
+   (P1 = n_i r_j + r_i n_j + d_ij r.n, P2 = r_i r_j r.n, P3 = r_i n_j),
+   dPk = d Pk/d x_l and B_k = A_k'(r)/r (from T1' = K0/(2 pi z) - 4 T1/z,
+   T2' = -(z K0 + 2 K1)/(pi z^4) - 6 T2/z, T3' = -K0/(2 pi z) - 2 T3/z).  The
+   near panels are integrated with the split of the stresslet carried to the
+   gradient: smooth and log parts, the Cauchy vector (tau - z)^-1 part, the
+   Laplace double-layer gradient under the alpha^2 r_i r_j r.n/(8 pi r^2) term
+   and, for the Stokes stresslet part, the complex derivatives d/dz and d/dzbar
+   of its complex form with the (tau - z)^-2 and (tau - z)^-3 integrals (the
+   latter lowered by parts).  mu: device [2][N]; g: device [4][M], overwritten,
+   row c = 2 i + l (i the velocity component, l the derivative direction) in
+   the caller's target order.  Targets must lie off the curve.  FP64.  The
+   first call on a plan builds its gradient weights (128 doubles per near
+   pair) and synchronises the stream; later calls only enqueue.
+   Errors: MHLP_INVALID_ARG (NULL or aliased arrays, a scalar plan),
+   MHLP_UNSUPPORTED on an on-surface plan. */
+mhlp_status mhlp_stokes_eval_grad(const mhlp_plan *plan, const double *mu, double *g, void *stream);
 
 /* Target gradients of S[sigma] and D[mu] on an off-surface plan (the
    near-boundary gradient of Sec. 4.4, for the scalar kernel):

@@ -15,7 +15,7 @@ import torch
 
 from . import mhlp
 
-LAYERS = {"slp": 1, "dlp": 2, "both": 3, "bie": 4, "grad": 5, "stokes": 6}
+LAYERS = {"slp": 1, "dlp": 2, "both": 3, "bie": 4, "grad": 5, "stokes": 6, "stokes_grad": 7}
 
 
 def cache_path() -> str:

@@ -103,6 +103,8 @@ struct mhlp_plan {
     double *wgrad = nullptr;  /* off-surface, built on first use: [4][nnz][16] gradient weights */
     bool stokes = false;      /* modified-Stokes (stresslet) plan: operator on [2][N] densities */
     double *wstk = nullptr;   /* stokes: [4][nnz][16] stresslet weights (D11, D12, D21, D22)   */
+    double *wstkg = nullptr;  /* stokes, off-surface, built on first use: [8][nnz][16] stresslet
+                                 gradient weights, block (2a + l) 2 + j = d u_a/d x_l per mu_j */
     double *stk_flux = nullptr; /* stokes: device scalar sum_j w_j mu_j.n_j / |Gamma|           */
     double inv_len = 0.0;     /* 1 / |Gamma| */
     int64_t nnz = 0;
@@ -395,6 +397,28 @@ __global__ void near_stokes_weights_kernel(GeoView G, const double *__restrict__
     }
     for (int b = 0; b < 4; ++b)
         for (int j = 0; j < 16; ++j) wst[(b * nnz + q) * 16 + j] = W[b][j];
+}
+
+/* stresslet gradient correction weights of the off-surface pairs: wg[b][q][j] */
+__global__ void near_stokes_grad_weights_kernel(GeoView G, const double *__restrict__ tx,
+                                                const double *__restrict__ ty, const int32_t *__restrict__ panel,
+                                                const int32_t *__restrict__ tgt, const double *__restrict__ ts,
+                                                int64_t nnz, double alpha, NearParams P, double *__restrict__ wg)
+{
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= nnz) return;
+    const int64_t p = panel[q], i = tgt[q];
+    double W[8][16];
+    if (p < 0 || p >= G.Np) {
+        for (int b = 0; b < 8; ++b)
+            for (int j = 0; j < 16; ++j) W[b][j] = 0.0;
+    } else {
+        cplx a[16];
+        panel_local(G, p, mk(tx[i], ty[i]), a);
+        pair_stokes_grad_weights(a, G.ph[p], mk(0.0, 0.0), mk(ts[2 * q], ts[2 * q + 1]), alpha, P, W);
+    }
+    for (int b = 0; b < 8; ++b)
+        for (int j = 0; j < 16; ++j) wg[(b * nnz + q) * 16 + j] = W[b][j];
 }
 
 /* ------------------------------------------------------------------------ */
@@ -931,6 +955,141 @@ __global__ __launch_bounds__(FT_THREADS) void far_stokes_fp64(StkArgs A)
     }
 }
 
+/* ------------------------------------------------------------------------ */
+/* target gradient of the modified-Stokes double layer, FP64 (off-surface    */
+/* stokes plans):  d u_i/d x_l = sum_j d_l D_ij(x, y_j) w_j mu_j with        */
+/*   d_l D_ij m_j = -[ r_l Pm_i + n_l (A1 m_i + A2 (r.m) r_i)                  */
+/*                     + m_l (A1 n_i + A2 (r.n) r_i)                           */
+/*                     + d_il ((A1 + A3)(n.m) + A2 (r.n)(r.m)) ],              */
+/*   Pm_i = B1 (n_i (r.m) + m_i (r.n)) + r_i (B2 (r.n)(r.m) + (B1 + B3)(n.m)), */
+/* B_k = A_k'(r)/r, and the listed near panels replaced by their weights.    */
+/* Outputs g[c][M], c = 2i + l.                                               */
+/* ------------------------------------------------------------------------ */
+struct StkGArgs {
+    const double *sx, *sy, *sw, *snx, *sny;
+    const double *mu; /* [2][N] */
+    int64_t N;
+    const double *tx, *ty;
+    int64_t M, Np, nnz;
+    const int32_t *nptr, *npan, *perm;
+    const double *wg; /* [8][nnz][16] */
+    double alpha;
+    int32_t pps;
+    double *part;     /* [4][nsplit][M] */
+    double *g;        /* [4][M] */
+};
+
+__device__ __forceinline__ void stkg_epilogue(const StkGArgs &A, int64_t i, const double *acc)
+{
+    double c[4] = {acc[0], acc[1], acc[2], acc[3]};
+    const int64_t bs = A.nnz * 16;
+    for (int32_t q = A.nptr[i]; q < A.nptr[i + 1]; ++q) {
+        const int64_t p = A.npan[q];
+        if (p < 0) continue;
+        for (int jj = 0; jj < 16; ++jj) {
+            const int64_t o = 16 * (int64_t)q + jj;
+            const double m1 = A.mu[16 * p + jj], m2 = A.mu[A.N + 16 * p + jj];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) c[b] = fma(A.wg[(2 * b) * bs + o], m1, fma(A.wg[(2 * b + 1) * bs + o], m2, c[b]));
+        }
+    }
+    const int64_t o = A.perm ? (int64_t)A.perm[i] : i;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) A.g[b * A.M + o] = c[b];
+}
+
+__global__ void stkg_finalize(StkGArgs A, int nsplit)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= A.M) return;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < nsplit; ++k)
+        for (int b = 0; b < 4; ++b) acc[b] += A.part[((int64_t)b * nsplit + k) * A.M + i];
+    stkg_epilogue(A, i, acc);
+}
+
+template <bool SPLIT>
+__global__ __launch_bounds__(FT_THREADS) void far_stokes_grad_fp64(StkGArgs A)
+{
+    __shared__ double lx[FT_SRC], ly[FT_SRC], lm1[FT_SRC], lm2[FT_SRC], lnx[FT_SRC], lny[FT_SRC];
+    const int64_t i = blockIdx.x * (int64_t)FT_THREADS + threadIdx.x;
+    const bool valid = i < A.M;
+    const double x = valid ? A.tx[i] : 0.0, y = valid ? A.ty[i] : 0.0;
+    const int64_t pb = SPLIT ? (int64_t)blockIdx.y * A.pps : 0;
+    const int64_t pe = SPLIT ? min(A.Np, pb + A.pps) : A.Np;
+    int32_t k = 0, kend = 0;
+    if (valid) {
+        k = A.nptr[i];
+        kend = A.nptr[i + 1];
+        while (k < kend && A.npan[k] >= 0 && A.npan[k] < pb) ++k;
+    }
+    int32_t nxt = (k < kend) ? A.npan[k] : INT_MAX;
+    const FarConst fc = far_const(A.alpha);
+    const double al2 = A.alpha * A.alpha, ial2 = fc.ia * fc.ia;
+    double g11 = 0.0, g12 = 0.0, g21 = 0.0, g22 = 0.0;
+    for (int64_t base = 16 * pb; base < 16 * pe; base += FT_SRC) {
+        __syncthreads();
+        const int64_t j = base + threadIdx.x;
+        if (j < 16 * pe) {
+            const double wj = A.sw[j];
+            lx[threadIdx.x] = A.sx[j];
+            ly[threadIdx.x] = A.sy[j];
+            lm1[threadIdx.x] = wj * A.mu[j];
+            lm2[threadIdx.x] = wj * A.mu[A.N + j];
+            lnx[threadIdx.x] = A.snx[j];
+            lny[threadIdx.x] = A.sny[j];
+        }
+        __syncthreads();
+        const int32_t p0 = (int32_t)(base / 16);
+        const int npl = (pe - p0) < 16 ? (int)(pe - p0) : 16;
+        for (int pl = 0; pl < npl; ++pl) {
+            if (p0 + pl == nxt) {
+                ++k;
+                nxt = (k < kend) ? A.npan[k] : INT_MAX;
+                continue;
+            }
+#pragma unroll 1
+            for (int s = 0; s < 16; s += 2) {
+                const FarTab T = far_table();
+                const int l0 = pl * 16 + s;
+                const double ex0 = x - lx[l0], ey0 = y - ly[l0];
+                const double ex1 = x - lx[l0 + 1], ey1 = y - ly[l0 + 1];
+                const double r20 = fma(ex0, ex0, ey0 * ey0), r21 = fma(ex1, ex1, ey1 * ey1);
+                double Ak[2][3], Bk[2][3];
+                stk_far2_ab(T, fc, al2, ial2, r20, r21, Ak[0], Bk[0], Ak[1], Bk[1]);
+                const double ex[2] = {ex0, ex1}, ey[2] = {ey0, ey1};
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int l = l0 + u;
+                    const double *a = Ak[u], *b = Bk[u];
+                    const double nx = lnx[l], ny = lny[l], m1 = lm1[l], m2 = lm2[l];
+                    const double rn = fma(ex[u], nx, ey[u] * ny);
+                    const double rm = fma(ex[u], m1, ey[u] * m2);
+                    const double nm = fma(nx, m1, ny * m2);
+                    const double sr = fma(b[1] * rn, rm, (b[0] + b[2]) * nm);
+                    const double p1 = fma(b[0], fma(nx, rm, m1 * rn), ex[u] * sr);
+                    const double p2 = fma(b[0], fma(ny, rm, m2 * rn), ey[u] * sr);
+                    const double a1 = fma(a[0], m1, a[1] * rm * ex[u]), a2 = fma(a[0], m2, a[1] * rm * ey[u]);
+                    const double c1 = fma(a[0], nx, a[1] * rn * ex[u]), c2 = fma(a[0], ny, a[1] * rn * ey[u]);
+                    const double d = fma(a[0] + a[2], nm, a[1] * rn * rm);
+                    g11 -= fma(ex[u], p1, fma(nx, a1, fma(m1, c1, d)));
+                    g12 -= fma(ey[u], p1, fma(ny, a1, m2 * c1));
+                    g21 -= fma(ex[u], p2, fma(nx, a2, m1 * c2));
+                    g22 -= fma(ey[u], p2, fma(ny, a2, fma(m2, c2, d)));
+                }
+            }
+        }
+    }
+    if (!valid) return;
+    const double acc[4] = {g11, g12, g21, g22};
+    if (SPLIT) {
+        const int ns = gridDim.y;
+        for (int b = 0; b < 4; ++b) A.part[((int64_t)b * ns + blockIdx.y) * A.M + i] = acc[b];
+    } else {
+        stkg_epilogue(A, i, acc);
+    }
+}
+
 struct VolArgs {
     const double *x, *y, *w, *f;
     int64_t n;
@@ -1384,7 +1543,8 @@ extern "C" mhlp_status mhlp_plan_destroy(mhlp_plan *P)
             if (gr.exec) (void)hipGraphExecDestroy(gr.exec);
     if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
     void *ptrs[] = {P->near_ptr, P->near_panel, P->near_tgt, P->near_ts, P->wslp,  P->wdlp,    P->ws,
-                    P->hdev,     P->part,       P->gdev,     P->perm,    P->wgrad, P->wstk,    P->stk_flux};
+                    P->hdev,     P->part,       P->gdev,     P->perm,    P->wgrad, P->wstk,    P->stk_flux,
+                    P->wstkg};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (P->hhost) (void)hipHostFree(P->hhost);
@@ -1721,9 +1881,10 @@ extern "C" mhlp_status mhlp_plan_autotune(mhlp_plan *P, int32_t layers, int32_t 
                                           double *cand_ms, int32_t cap, int32_t *n_cand)
 {
     if (!P) return fail(MHLP_INVALID_ARG, "plan is NULL");
-    if (layers < 1 || layers > 6) return fail(MHLP_INVALID_ARG, "layers must be 1 to 6");
-    if ((layers == 6) != P->stokes) return fail(MHLP_INVALID_ARG, "layers 6 (and only 6) tunes a stokes plan");
-    if (layers == 6 && precision != MHLP_FP64) return fail(MHLP_INVALID_ARG, "the stresslet is FP64 only");
+    if (layers < 1 || layers > 7) return fail(MHLP_INVALID_ARG, "layers must be 1 to 7");
+    if ((layers >= 6) != P->stokes) return fail(MHLP_INVALID_ARG, "layers 6 and 7 (and only they) tune a stokes plan");
+    if (layers >= 6 && precision != MHLP_FP64) return fail(MHLP_INVALID_ARG, "the stresslet is FP64 only");
+    if (layers == 7 && P->onsurf) return fail(MHLP_INVALID_ARG, "layers 7 (stresslet gradient) needs an off-surface plan");
     if (layers == 4 && !P->onsurf) return fail(MHLP_INVALID_ARG, "layers 4 (BIE operator) needs an on-surface plan");
     if (layers == 5 && P->onsurf) return fail(MHLP_INVALID_ARG, "layers 5 (gradients) needs an off-surface plan");
     if (layers == 5 && precision != MHLP_FP64) return fail(MHLP_INVALID_ARG, "gradients are FP64 only");
@@ -1751,6 +1912,7 @@ extern "C" mhlp_status mhlp_plan_autotune(mhlp_plan *P, int32_t layers, int32_t 
         auto run = [&]() -> mhlp_status {
             if (layers == 5) return mhlp_eval_grad(P, dens, dens, out, out + M, out + 2 * M, out + 3 * M, st);
             if (layers == 6) return launch_stokes(P, dens, out, M, P->onsurf, st);
+            if (layers == 7) return mhlp_stokes_eval_grad(P, dens, out, st);
             const double *sg = (layers & 1) ? dens : nullptr, *mu = (layers & 2 || layers == 4) ? dens : nullptr;
             return launch_far(P, sg, mu, sg ? out : nullptr, mu ? out + M : nullptr, layers == 4 ? 0.5 : 0.0,
                               precision, st);
@@ -1966,6 +2128,66 @@ extern "C" mhlp_status mhlp_stokes_apply_bie(const mhlp_plan *P, const double *m
     if (!mu || !out) return fail(MHLP_INVALID_ARG, "mu or out is NULL");
     if (mu == out) return fail(MHLP_INVALID_ARG, "mu and out must not alias");
     return launch_stokes(P, mu, out, P->M, true, (hipStream_t)stream);
+}
+
+static mhlp_status ensure_stokes_grad_weights(mhlp_plan *P, hipStream_t st)
+{
+    if (P->wstkg || P->nnz == 0) return MHLP_OK;
+    TRY(dalloc(&P->wstkg, 128 * P->nnz));
+    near_stokes_grad_weights_kernel<<<nblocks(P->nnz, 64), 64, 0, st>>>(view(P->g), P->tx, P->ty, P->near_panel,
+                                                                         P->near_tgt, P->near_ts, P->nnz, P->alpha,
+                                                                         P->np, P->wstkg);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        (void)hipFree(P->wstkg);
+        P->wstkg = nullptr;
+        return fail(MHLP_HIP_ERROR, std::string("stresslet gradient weights: ") + hipGetErrorString(e));
+    }
+    return MHLP_OK;
+}
+
+extern "C" mhlp_status mhlp_stokes_eval_grad(const mhlp_plan *Pc, const double *mu, double *g, void *stream)
+{
+    if (!Pc) return fail(MHLP_INVALID_ARG, "plan is NULL");
+    if (!Pc->stokes) return fail(MHLP_INVALID_ARG, "stokes_eval_grad needs a plan from mhlp_stokes_plan_create");
+    if (Pc->onsurf) return fail(MHLP_UNSUPPORTED, "stokes_eval_grad needs an off-surface plan (targets off the curve)");
+    if (!mu || !g) return fail(MHLP_INVALID_ARG, "mu or g is NULL");
+    if (mu == g) return fail(MHLP_INVALID_ARG, "mu and g must not alias");
+    mhlp_plan *P = const_cast<mhlp_plan *>(Pc); /* gradient weights are built on first use */
+    hipStream_t st = (hipStream_t)stream;
+    TRY(ensure_stokes_grad_weights(P, st));
+    const mhlp_geometry *geo = P->g;
+    StkGArgs A;
+    A.sx = geo->soa;
+    A.sy = geo->soa + geo->N;
+    A.sw = geo->w;
+    A.snx = geo->nx;
+    A.sny = geo->ny;
+    A.mu = mu;
+    A.N = geo->N;
+    A.tx = P->tx;
+    A.ty = P->ty;
+    A.M = P->M;
+    A.Np = geo->Np;
+    A.nnz = P->nnz;
+    A.nptr = P->near_ptr;
+    A.npan = P->near_panel;
+    A.perm = P->perm;
+    A.wg = P->wstkg;
+    A.alpha = P->alpha;
+    A.pps = P->pps;
+    A.part = P->part;
+    A.g = g;
+    const unsigned nb = nblocks(A.M, FT_THREADS);
+    if (P->nsplit <= 1) {
+        far_stokes_grad_fp64<false><<<nb, FT_THREADS, 0, st>>>(A);
+    } else {
+        far_stokes_grad_fp64<true><<<dim3(nb, P->nsplit), FT_THREADS, 0, st>>>(A);
+        stkg_finalize<<<nblocks(A.M, 256), 256, 0, st>>>(A, P->nsplit);
+    }
+    HIPCHECK(hipGetLastError());
+    return MHLP_OK;
 }
 
 /* ------------------------------------------------------------------------ */

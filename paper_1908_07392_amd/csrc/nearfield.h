@@ -904,4 +904,227 @@ __host__ __device__ inline void pair_stokes_weights(const cplx *a, double h, cpl
         subdivide_t(a, h, -1.0, 1.0, z, tstar, alpha, P, leaf);
 }
 
+/* ---------------------------------------------------------------------- */
+/* Target gradient of the stresslet double layer (Sec. 4.4).               */
+/* ---------------------------------------------------------------------- */
+/* With A_k(r) as above and B_k = A_k'(|r|)/|r|,
+     d/dx_l D_ij = -[ r_l (B1 P1 + B2 P2 + B3 P3)_ij + A1 dP1_ijl + A2 dP2_ijl + A3 dP3_ijl ],
+   P1 = n_i r_j + r_i n_j + d_ij (r.n), P2 = r_i r_j (r.n), P3 = r_i n_j,
+   dP1 = n_i d_jl + d_il n_j + d_ij n_l, dP2 = d_il r_j (r.n) + r_i d_jl (r.n) + r_i r_j n_l, dP3 = d_il n_j.
+   Split (Sec. 4.1, 4.4): with A_k = A_k^S + A_k^L log|r| + (explicit terms of A2),
+     smooth    -[r_l sum B^S P + sum A^S dP]
+     log       -[r_l sum B^L P + sum A^L dP] log|r|        (B^S, B^L = 2 d/d(r^2))
+     Cauchy    -(sum A^L P)_ij r_l/|r|^2                  (vector Cauchy kernel, as for grad S)
+     d_l of -(alpha^2/8pi) r_i r_j (r.n)/|r|^2:
+         -(alpha^2/8pi) [(d_il r_j + r_i d_jl) (r.n)/|r|^2 + r_i r_j d_l((r.n)/|r|^2)],
+       the second a frozen smooth factor times the Laplace double-layer gradient
+       (Im F', Re F'), F' = int f dtau/(tau - z)^2 by (s - s*)^-2 moments;
+     d_l of (1/pi) r_i r_j (r.n)/|r|^4 (Stokes stresslet): with u = -(1/pi) I(z) and
+       I the complex form of the double layer (see above),
+         dI/dz  = (i/2) Re H1(omega),
+         dI/dzb = (1/4i) conj(H1(conj omega)) + (1/4i) conj(H1(omega conj(nu)^2))
+                  + (1/2i) conj(H2(omega conj(e))),
+       H1(f) = int f dtau/e^2, H2(f) = int f dtau/e^3, lowered once by parts:
+       H2(f) = [-f/(2 e^2)] + (1/2) int f'(s) ds/e^2, and d/dx = d/dz + d/dzb,
+       d/dy = i (d/dz - d/dzb).
+   Weight blocks: W[(2i + l) 2 + j] = d/dx_l of u_i per mu_j, on the panel's 16 nodes. */
+
+/* MH[m] = int P_m(t)/(t - s)^2 dt, m = 0..N-1, from the Cauchy moments MC
+   (m = 0..N-2): by parts, MH_m = B_m + int P_m'/(t - s) dt with
+   B_m = -1/(1 - s) - (-1)^m/(1 + s); P_{m+1}' - P_{m-1}' = (2m+1) P_m and
+   B_{m+1} = B_{m-1} give MH_{m+1} = MH_{m-1} + (2m+1) MC_m,
+   MH_0 = B_0, MH_1 = B_1 + MC_0. */
+template <int N>
+__host__ __device__ inline void hyper_moments(cplx s, const cplx *MC, cplx *MH)
+{
+    const cplx ia = mk(1.0, 0.0) / (mk(1.0, 0.0) - s), ib = mk(1.0, 0.0) / (mk(1.0, 0.0) + s);
+    MH[0] = -(ia + ib);
+    MH[1] = (ib - ia) + MC[0];
+    for (int m = 1; m + 1 < N; ++m) MH[m + 1] = MH[m - 1] + (2.0 * m + 1.0) * MC[m];
+}
+
+/* G[(2i+l)2+j] = r_l (sum_k B_k P_k)_ij + sum_k A_k dP_k,ijl (no sign) */
+__host__ __device__ inline void stk_dtensor(double rx, double ry, double nx, double ny, const double *A,
+                                            const double *B, double *G)
+{
+    const double r[2] = {rx, ry}, n[2] = {nx, ny};
+    const double rn = rx * nx + ry * ny;
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+            const double dij = i == j ? 1.0 : 0.0;
+            const double P = B[0] * (n[i] * r[j] + r[i] * n[j] + dij * rn) + B[1] * r[i] * r[j] * rn + B[2] * r[i] * n[j];
+            for (int l = 0; l < 2; ++l) {
+                const double dil = i == l ? 1.0 : 0.0, djl = j == l ? 1.0 : 0.0;
+                G[(2 * i + l) * 2 + j] = r[l] * P + A[0] * (n[i] * djl + dil * n[j] + dij * n[l]) +
+                                         A[1] * (dil * r[j] * rn + r[i] * djl * rn + r[i] * r[j] * n[l]) +
+                                         A[2] * dil * n[j];
+            }
+        }
+}
+
+/* adds  u_l += a omega + conj(b omega)  (u = u1 + i u2, omega = mu1 + i mu2) for
+   derivative direction l to the eight real weights w8 of one node */
+__host__ __device__ inline void add_ab(cplx a, cplx b, int l, double *w8, int stride)
+{
+    w8[((0 + l) * 2 + 0) * stride] += a.re + b.re;
+    w8[((0 + l) * 2 + 1) * stride] += -a.im - b.im;
+    w8[((2 + l) * 2 + 0) * stride] += a.im - b.im;
+    w8[((2 + l) * 2 + 1) * stride] += a.re - b.re;
+}
+
+/* the Stokes-stresslet part of the gradient for a coefficient pair of dI/dz
+   (az, bz) and dI/dzb (azb, bzb): d/dx u = -(1/pi)(dI/dz + dI/dzb),
+   d/dy u = -(i/pi)(dI/dz - dI/dzb) */
+__host__ __device__ inline void add_stresslet_grad(cplx az, cplx bz, cplx azb, cplx bzb, double *w8, int stride)
+{
+    const double ip = 1.0 / PI;
+    add_ab(-ip * (az + azb), -ip * (bz + bzb), 0, w8, stride);
+    add_ab(mk(0.0, -ip) * (az - azb), mk(0.0, ip) * (bz - bzb), 1, w8, stride);
+}
+
+__host__ __device__ inline void direct_node_stokes_grad(cplx z, const NodeGeo &g, double alpha, double *w8)
+{
+    const cplx r = z - g.tau;
+    const double r2 = cabs2(r);
+    const K01 o = k01_fp64<true, true>(r2, alpha, 0.25 * alpha * alpha, 4.0 / alpha);
+    double A[3], B[3], G[8];
+    stk_AB(alpha, r2, o.k0, o.ak1r, A, B);
+    const double sp_ = cabs(g.dtau);
+    stk_dtensor(r.re, r.im, -g.dtau.im / sp_, g.dtau.re / sp_, A, B, G);
+    for (int b = 0; b < 8; ++b) w8[b] = -G[b] * g.w;
+}
+
+template <int NQ>
+__host__ __device__ inline void leaf_direct_stokes_grad(const cplx *a, const double *tq, const double *wq, double ta,
+                                                        double tb, cplx z, double alpha, double (*W)[16])
+{
+    NodeGeo g[NQ];
+    double WQ[8][NQ];
+    rule_geo<NQ>(a, tq, wq, ta, tb, g);
+    for (int k = 0; k < NQ; ++k) {
+        double w8[8];
+        direct_node_stokes_grad(z, g[k], alpha, w8);
+        for (int b = 0; b < 8; ++b) WQ[b][k] = w8[b];
+    }
+    fold_add_n<NQ, 8>(tq, ta, tb, WQ, W);
+}
+
+__host__ __device__ inline void leaf_split32_stokes_grad(const cplx *a, double ta, double tb, cplx z, cplx tstar,
+                                                         double alpha, double (*W)[16])
+{
+    constexpr int NQ = 32;
+    NodeGeo g[NQ];
+    double WQ[8][NQ];
+    cplx PB[16]; /* dI/dzb, conj part, on the parent nodes (H2 by parts) */
+    rule_geo<NQ>(a, GL32_T, GL32_W, ta, tb, g);
+    const double mid = 0.5 * (ta + tb), half = 0.5 * (tb - ta);
+    const cplx ss = (1.0 / half) * (tstar - mk(mid, 0.0));
+    cplx MC[NQ + 1], ML[NQ], MH[NQ], pc[NQ], pl[NQ], ph[NQ];
+    legendre_moments<NQ>(ss, bernstein_rho(ss), MC, ML);
+    hyper_moments<NQ>(ss, MC, MH);
+    moments_to_weights<NQ>(LEGW32, MC, pc);
+    moments_to_weights<NQ>(LEGW32, ML, pl);
+    moments_to_weights<NQ>(LEGW32, MH, ph);
+    const cplx i2 = mk(0.0, 0.5), i4 = mk(0.0, 0.25);
+    /* end points of H2 by parts: [-omega conj(e)/(2 e^2)]_ta^tb, times (i/2) in dI/dzb */
+    {
+        double la_[16], lb_[16];
+        cplx pa, pb, dpa, dpb;
+        leg_eval(a, mk(ta, 0.0), pa, dpa);
+        leg_eval(a, mk(tb, 0.0), pb, dpb);
+        lagrange16(ta, la_);
+        lagrange16(tb, lb_);
+        const cplx ea = pa - z, eb = pb - z;
+        const cplx qa = conj(ea) / (2.0 * (ea * ea)), qb = conj(eb) / (2.0 * (eb * eb));
+        for (int j = 0; j < 16; ++j) PB[j] = i2 * (la_[j] * qa - lb_[j] * qb);
+    }
+    const double la = log(alpha), a2 = alpha * alpha, c8 = -a2 / (8.0 * PI);
+    const double sc[3] = {a2, a2 * a2, a2};
+    for (int k = 0; k < NQ; ++k) {
+        const double tkr = mid + half * GL32_T[k];
+        const cplx Q = half * leg_divdiff(a, mk(tkr, 0.0), tstar);
+        const double sp_ = cabs(g[k].dtau);
+        const double logw = fma(sp_, pl[k].re, g[k].w * log(cabs(Q)));
+        const cplx r = z - g[k].tau; /* x - y */
+        const cplx e = -r;           /* tau - z */
+        const double nx = -g[k].dtau.im / sp_, ny = g[k].dtau.re / sp_;
+        const cplx nu = mk(nx, ny);
+        const StkSplit t = stresslet_split_t<true>(alpha * cabs(r));
+        double AS[3], AL[3], BS[3], BL[3];
+        for (int q = 0; q < 3; ++q) {
+            AS[q] = sc[q] * fma(t.l[q], la, t.s[q]);
+            AL[q] = sc[q] * t.l[q];
+            BS[q] = 2.0 * sc[q] * a2 * fma(t.dl[q], la, t.ds[q]);
+            BL[q] = 2.0 * sc[q] * a2 * t.dl[q];
+        }
+        double Gs[8], Gl[8];
+        stk_dtensor(r.re, r.im, nx, ny, AS, BS, Gs);
+        stk_dtensor(r.re, r.im, nx, ny, AL, BL, Gl);
+        double w8[8];
+        for (int b = 0; b < 8; ++b) w8[b] = -fma(Gs[b], g[k].w, Gl[b] * logw);
+        const cplx iQ = mk(1.0, 0.0) / Q;
+        const cplx cS = (sp_ * pc[k]) * iQ;        /* int f ds/(tau - z) */
+        const double cw = (pc[k] * (g[k].dtau * iQ)).im; /* Laplace double layer */
+        const cplx h = ph[k] * (g[k].dtau * (iQ * iQ));    /* int f dtau/(tau - z)^2 */
+        const double rv[2] = {r.re, r.im}, n[2] = {nx, ny};
+        const double rn = r.re * nx + r.im * ny;
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j) {
+                const double dij = i == j ? 1.0 : 0.0;
+                /* Cauchy part of the log term: -(sum A^L P)_ij r_l/|r|^2 */
+                const double M = AL[0] * (n[i] * rv[j] + rv[i] * n[j] + dij * rn) + AL[1] * rv[i] * rv[j] * rn +
+                                 AL[2] * rv[i] * n[j];
+                w8[(2 * i + 0) * 2 + j] += cS.re * M;
+                w8[(2 * i + 1) * 2 + j] -= cS.im * M;
+                /* -(alpha^2/8pi) [(d_il r_j + r_i d_jl) (r.n)/|r|^2 + r_i r_j d_l((r.n)/|r|^2)] */
+                for (int l = 0; l < 2; ++l) {
+                    const double dil = i == l ? 1.0 : 0.0, djl = j == l ? 1.0 : 0.0;
+                    w8[(2 * i + l) * 2 + j] += c8 * (dil * rv[j] + rv[i] * djl) * cw;
+                }
+                w8[(2 * i + 0) * 2 + j] += c8 * rv[i] * rv[j] * h.im;
+                w8[(2 * i + 1) * 2 + j] += c8 * rv[i] * rv[j] * h.re;
+            }
+        /* Stokes stresslet: node terms of dI/dz and dI/dzb */
+        const cplx az = i4 * h, bz = -(i4 * h);
+        const cplx azb = -(i4 * conj(h));
+        const cplx bzb = i4 * (h * conj(nu * nu)) + i2 * (0.5 * (ph[k] * (conj(g[k].dtau) * (iQ * iQ))));
+        add_stresslet_grad(az, bz, azb, bzb, w8, 1);
+        for (int b = 0; b < 8; ++b) WQ[b][k] = w8[b];
+        /* omega' conj(e) part of H2 by parts (parent nodes) */
+        double dl[16];
+        lagrange16_deriv(tkr, dl);
+        const cplx cD = i2 * (0.5 * half * (ph[k] * (conj(e) * (iQ * iQ))));
+        for (int j = 0; j < 16; ++j) PB[j] = PB[j] + dl[j] * cD;
+    }
+    fold_add_n<NQ, 8>(GL32_T, ta, tb, WQ, W);
+    for (int j = 0; j < 16; ++j) add_stresslet_grad(mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0), PB[j], &W[0][j], 16);
+}
+
+__host__ __device__ inline void leaf_apply_stokes_grad(const cplx *a, double ta, double tb, cplx z, cplx tstar,
+                                                       double alpha, const NearParams &P, double (*W)[16])
+{
+    const double mid = 0.5 * (ta + tb), half = 0.5 * (tb - ta);
+    const cplx ss = (1.0 / half) * (tstar - mk(mid, 0.0));
+    const double rho = bernstein_rho(ss);
+    if (rho >= P.rho_direct)
+        leaf_direct_stokes_grad<16>(a, GL16_T, GL16_W, ta, tb, z, alpha, W);
+    else if (rho >= P.rho_split)
+        leaf_direct_stokes_grad<32>(a, GL32_T, GL32_W, ta, tb, z, alpha, W);
+    else
+        leaf_split32_stokes_grad(a, ta, tb, z, tstar, alpha, W);
+}
+
+/* Stresslet-gradient correction weights of an off-curve target (8 blocks). */
+__host__ __device__ inline void pair_stokes_grad_weights(const cplx *a, double h, cplx z, cplx tstar, double alpha,
+                                                         const NearParams &P, double (*W)[16])
+{
+    for (int b = 0; b < 8; ++b)
+        for (int j = 0; j < 16; ++j) W[b][j] = 0.0;
+    auto leaf = [&](double a0, double b0) { leaf_apply_stokes_grad(a, a0, b0, z, tstar, alpha, P, W); };
+    if (alpha * h <= P.ah_max)
+        leaf(-1.0, 1.0);
+    else
+        subdivide_t(a, h, -1.0, 1.0, z, tstar, alpha, P, leaf);
+}
+
 } // namespace mhlp

@@ -372,6 +372,57 @@ __device__ __forceinline__ void stk_far2(FarTab T, const FarConst &c, double al2
     }
 }
 
+/* A_k and B_k = A_k'(r)/r of the stresslet (target gradient) for two
+   sources of a far tile.  z > 2: B from K0, alpha K1/r and A,
+     B1 = (alpha^2 K0/(2 pi) - 4 A1)/r^2, B2 = -(alpha^2 K0 + 2 alpha K1/r)/(pi r^4) - 6 A2/r^2,
+     B3 = -(alpha^2 K0/(2 pi) + 2 A3)/r^2;
+   z <= 2: B = 2 d A/d(r^2) from the fitted smooth parts (d/dw = d/(4 dq),
+   w = z^2) and the explicit terms of A2. */
+__device__ __forceinline__ void stk_closed_ab(double al2, double ial2, double r2, double ri2, double k0, double ak1r,
+                                              double *A, double *B)
+{
+    stk_closed(al2, ial2, r2, ri2, k0, ak1r, A);
+    const double ak0 = al2 * k0;
+    B[0] = ri2 * fma(INV_2PI, ak0, -4.0 * A[0]);
+    B[1] = -ri2 * fma(ri2 * (1.0 / PI), fma(2.0, ak1r, ak0), 6.0 * A[1]);
+    B[2] = -ri2 * fma(INV_2PI, ak0, 2.0 * A[2]);
+}
+
+__device__ __forceinline__ void stk_small_ab(FarTab T, const FarConst &c, double al2, double r2, double *A, double *B)
+{
+    const double q = c.a2q * r2;
+    const double lz = fma(0.5, lean_log01(T, q), LN2);
+    const double ri2 = lean_rcp(r2);
+    const double sc[3] = {al2, al2 * al2, al2};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double dS, dL;
+        const double tS = hornercd<14>(T->stk[k], q, dS);
+        const double tL = hornercd<14>(T->stk[3 + k], q, dL);
+        A[k] = sc[k] * fma(tL, lz, tS);
+        B[k] = sc[k] * fma(0.5 * al2, fma(dL, lz, dS), tL * ri2);
+    }
+    const double ri4 = ri2 * ri2;
+    A[1] += ri2 * fma(al2, 1.0 / (8.0 * PI), -ri2 * (1.0 / PI));
+    B[1] += ri4 * fma(al2, -1.0 / (4.0 * PI), 4.0 * ri2 * (1.0 / PI));
+}
+
+__device__ __forceinline__ void stk_far2_ab(FarTab T, const FarConst &c, double al2, double ial2, double r2a,
+                                            double r2b, double *Aa, double *Ba, double *Ab, double *Bb)
+{
+    const bool sa = c.a2q * r2a <= 1.0, sb = c.a2q * r2b <= 1.0;
+    if (!(sa && sb)) {
+        K01 oa, ob;
+        k01_far2_big<true, true>(T, c, r2a, r2b, oa, ob);
+        stk_closed_ab(al2, ial2, r2a, oa.ri2, oa.k0, oa.ak1r, Aa, Ba);
+        stk_closed_ab(al2, ial2, r2b, ob.ri2, ob.k0, ob.ak1r, Ab, Bb);
+    }
+    if (sa || sb) {
+        if (sa) stk_small_ab(T, c, al2, r2a, Aa, Ba);
+        if (sb) stk_small_ab(T, c, al2, r2b, Ab, Bb);
+    }
+}
+
 /* ---------------------------------------------------------------------- */
 /* Far-field kernel values, FP32 (mixed-precision far field).               */
 /* Same two regimes with the FP32 fits; exp/log/rsqrt/rcp are the hardware  */
@@ -495,36 +546,53 @@ __host__ __device__ inline SplitG split_k01_grad(double z)
 /*   T3 = (1/2pi) sum_{n>=0} k1(n) z^(2n).                                    */
 /* ---------------------------------------------------------------------- */
 struct StkSplit {
-    double s[3], l[3]; /* T1S, T2S, T3S and T1L, T2L, T3L */
+    double s[3], l[3];   /* T1S, T2S, T3S and T1L, T2L, T3L                    */
+    double ds[3], dl[3]; /* their derivatives with respect to w = z^2 (GRAD) */
 };
 
-__host__ __device__ inline StkSplit stresslet_split(double z)
+template <bool GRAD>
+__host__ __device__ inline StkSplit stresslet_split_t(double z)
 {
     const double w = z * z;
     double a = 1.0, b = 0.25;                       /* a_n, b_n */
     double psi = -EULER_G, psi1 = 1.0 - EULER_G;    /* psi(n+1), psi(n+2) */
-    double pw = 1.0, pw1 = 0.0, pw2 = 0.0;          /* w^n, w^(n-1), w^(n-2) */
+    double pw = 1.0, pw1 = 0.0, pw2 = 0.0, pw3 = 0.0; /* w^n, w^(n-1), w^(n-2), w^(n-3) */
     double k1s_prev = 0.0, k1l_prev = 0.0;
     double t1s = 0.0, t1l = 0.0, t2s = 0.0, t2l = 0.0, t3s = 0.0, t3l = 0.0;
+    double d1s = 0.0, d1l = 0.0, d2s = 0.0, d2l = 0.0, d3s = 0.0, d3l = 0.0;
     for (int n = 0; n < 64; ++n) {
         const double k0s = (psi + LN2) * a, k0l = -a;
         const double k1s = -(2.0 * LN2 + psi + psi1) * b, k1l = 2.0 * b;
-        const double d3s = k1s * pw, d3l = k1l * pw;
-        t3s += d3s;
-        t3l += d3l;
-        double d1 = 0.0, d2 = 0.0;
+        const double e3s = k1s * pw, e3l = k1l * pw;
+        t3s += e3s;
+        t3l += e3l;
+        if (GRAD && n >= 1) {
+            d3s += n * k1s * pw1;
+            d3l += n * k1l * pw1;
+        }
+        double e1 = 0.0, e2 = 0.0;
         if (n >= 1) {
-            d1 = (2.0 * k0s + 4.0 * k1s + k1s_prev) * pw1;
-            t1s += d1;
-            t1l += (2.0 * k0l + 4.0 * k1l + k1l_prev) * pw1;
+            const double c1s = 2.0 * k0s + 4.0 * k1s + k1s_prev, c1l = 2.0 * k0l + 4.0 * k1l + k1l_prev;
+            e1 = c1s * pw1;
+            t1s += e1;
+            t1l += c1l * pw1;
+            if (GRAD && n >= 2) {
+                d1s += (n - 1.0) * c1s * pw2;
+                d1l += (n - 1.0) * c1l * pw2;
+            }
         }
         if (n >= 2) {
-            d2 = (4.0 * k0s + 8.0 * k1s + k1s_prev) * pw2;
-            t2s += d2;
-            t2l += (4.0 * k0l + 8.0 * k1l + k1l_prev) * pw2;
+            const double c2s = 4.0 * k0s + 8.0 * k1s + k1s_prev, c2l = 4.0 * k0l + 8.0 * k1l + k1l_prev;
+            e2 = c2s * pw2;
+            t2s += e2;
+            t2l += c2l * pw2;
+            if (GRAD && n >= 3) {
+                d2s += (n - 2.0) * c2s * pw3;
+                d2l += (n - 2.0) * c2l * pw3;
+            }
         }
-        if (n >= 4 && fabs(d1) <= 1e-18 * fabs(t1s) && fabs(d2) <= 1e-18 * fabs(t2s) &&
-            fabs(d3s) <= 1e-18 * fabs(t3s))
+        if (n >= 4 && fabs(e1) <= 1e-18 * fabs(t1s) && fabs(e2) <= 1e-18 * fabs(t2s) &&
+            fabs(e3s) <= 1e-18 * fabs(t3s))
             break;
         k1s_prev = k1s;
         k1l_prev = k1l;
@@ -533,6 +601,7 @@ __host__ __device__ inline StkSplit stresslet_split(double z)
         b *= 1.0 / (4.0 * n1 * (n1 + 1.0));
         psi += 1.0 / n1;
         psi1 += 1.0 / (n1 + 1.0);
+        pw3 = pw2;
         pw2 = pw1;
         pw1 = pw;
         pw *= w;
@@ -544,8 +613,16 @@ __host__ __device__ inline StkSplit stresslet_split(double z)
     o.l[1] = t2l / PI;
     o.s[2] = INV_2PI * t3s;
     o.l[2] = INV_2PI * t3l;
+    o.ds[0] = -INV_2PI * d1s;
+    o.dl[0] = -INV_2PI * d1l;
+    o.ds[1] = d2s / PI;
+    o.dl[1] = d2l / PI;
+    o.ds[2] = INV_2PI * d3s;
+    o.dl[2] = INV_2PI * d3l;
     return o;
 }
+
+__host__ __device__ inline StkSplit stresslet_split(double z) { return stresslet_split_t<false>(z); }
 
 /* alpha^2 T1, alpha^4 T2, alpha^2 T3 at a source-target pair with r^2 = r2
    (1/r^2 = ri2) from K0 and alpha K1(alpha r)/r (far-field values): closed
@@ -568,6 +645,37 @@ __host__ __device__ inline void stresslet_scaled(double a2, double ia2, double r
     A[0] = a2 * fma(t.l[0], lz, t.s[0]);
     A[1] = a2 * a2 * fma(t.l[1], lz, t.s[1]) + a2 * ri2 / (8.0 * PI) - ri2 * ri2 / PI;
     A[2] = a2 * fma(t.l[2], lz, t.s[2]);
+}
+
+/* Near-field values of A_k = a_k T_k(alpha r) and B_k = A_k'(r)/r (the radial
+   derivative over r), a = (alpha^2, alpha^4, alpha^2), for the target gradient:
+   z > 2 from K0, alpha K1/r:
+     B1 = (alpha^2 K0/(2 pi) - 4 A1)/r^2,
+     B2 = -(alpha^2 K0 + 2 alpha K1/r)/(pi r^4) - 6 A2/r^2,
+     B3 = -(alpha^2 K0/(2 pi) + 2 A3)/r^2
+   (from T1' = K0/(2 pi z) - 4 T1/z, T2' = -(z K0 + 2 K1)/(pi z^4) - 6 T2/z,
+   T3' = -K0/(2 pi z) - 2 T3/z); z <= 2 from the split series and its
+   derivative in w = z^2 (B = 2 dA/d(r^2)). */
+__host__ __device__ inline void stk_AB(double alpha, double r2, double k0, double ak1r, double *A, double *B)
+{
+    const double a2 = alpha * alpha, w = a2 * r2, ri2 = 1.0 / r2;
+    if (w > 4.0) {
+        stresslet_scaled(a2, 1.0 / a2, r2, ri2, k0, ak1r, A);
+        B[0] = ri2 * fma(a2 * INV_2PI, k0, -4.0 * A[0]);
+        B[1] = -ri2 * ri2 / PI * fma(a2, k0, 2.0 * ak1r) - 6.0 * A[1] * ri2;
+        B[2] = -ri2 * fma(a2 * INV_2PI, k0, 2.0 * A[2]);
+        return;
+    }
+    const StkSplit t = stresslet_split_t<true>(sqrt(w));
+    const double lz = 0.5 * log(w);
+    const double sc[3] = {a2, a2 * a2, a2};
+    for (int k = 0; k < 3; ++k) {
+        A[k] = sc[k] * fma(t.l[k], lz, t.s[k]);
+        /* d/d(r^2) = a2 d/dw;  d(TL log z)/dw = dTL log z + TL/(2w) */
+        B[k] = 2.0 * sc[k] * a2 * (fma(t.dl[k], lz, t.ds[k]) + 0.5 * t.l[k] / w);
+    }
+    A[1] += a2 * ri2 / (8.0 * PI) - ri2 * ri2 / PI;
+    B[1] += -a2 * ri2 * ri2 / (4.0 * PI) + 4.0 * ri2 * ri2 * ri2 / PI;
 }
 
 /* ---------------------------------------------------------------------- */

@@ -75,6 +75,7 @@ _SIGS = {
                                 ctypes.c_int32),
     "mhlp_stokes_eval": ([_V, _V, _V, _V], ctypes.c_int32),
     "mhlp_stokes_apply_bie": ([_V, _V, _V, _V], ctypes.c_int32),
+    "mhlp_stokes_eval_grad": ([_V, _V, _V, _V], ctypes.c_int32),
     "mhlp_stokes_gmres_solve": ([_V, _V, _V, ctypes.POINTER(GmresOpts), ctypes.POINTER(GmresInfo), _V],
                                 ctypes.c_int32),
     "mhlp_gmres_solve": ([_V, _V, _V, ctypes.POINTER(GmresOpts), ctypes.POINTER(GmresInfo), _V], ctypes.c_int32),
@@ -225,7 +226,7 @@ class Plan:
     def autotune(self, layers: int = 3, precision=FP64, reps: int = 5):
         """Time the far evaluation over source-split counts and keep the fastest.
         layers: 1 SLP, 2 DLP, 3 both, 4 BIE operator, 5 gradients, 6 stresslet operator of a stokes
-        plan.  Returns (best, best_ms, {nsplit: ms})."""
+        plan, 7 stresslet gradient (off-surface stokes plan).  Returns (best, best_ms, {nsplit: ms})."""
         cap = 32
         cand, cms = (ctypes.c_int32 * cap)(), (ctypes.c_double * cap)()
         best, bms, nc = ctypes.c_int32(), ctypes.c_double(), ctypes.c_int32()
@@ -291,6 +292,17 @@ def stokes_eval(plan: Plan, mu, out=None):
     N, M = plan.n_sources, plan.n_targets
     out = torch.empty(2, M, dtype=torch.float64, device=plan.geom.device) if out is None else out
     _check(L.mhlp_stokes_eval(plan.handle, _dev(mu, "mu", 2 * N), _dev(out, "u", 2 * M), _stream()), "stokes_eval")
+    return out
+
+
+def stokes_eval_grad(plan: Plan, mu, out=None):
+    """Target gradient of the modified-Stokes double layer of mu ([2][N]) on an
+    off-surface stokes plan; returns [2][2][M] float64, out[i][l] = d u_i / d x_l."""
+    L = load()
+    N, M = plan.n_sources, plan.n_targets
+    out = torch.empty(2, 2, M, dtype=torch.float64, device=plan.geom.device) if out is None else out
+    _check(L.mhlp_stokes_eval_grad(plan.handle, _dev(mu, "mu", 2 * N), _dev(out, "g", 4 * M), _stream()),
+           "stokes_eval_grad")
     return out
 
 

@@ -1,5 +1,5 @@
 """Pins of the oracle's target gradients of the layer potentials (the
-near-boundary gradient of Sec. 4.6, restated for the scalar Yukawa kernel).
+near-boundary gradient of Sec. 4.4, restated for the scalar Yukawa kernel).
 
 Every expected value comes from outside the oracle's gradient code: circle
 closed forms (Graf's addition theorem differentiated in polar coordinates),
