@@ -75,8 +75,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched, volume, warm-start and gradient legs")
-    ap.add_argument("--legs", default="batched,volume,warm,gradient,stokes",
-                    help="comma list of the extra legs to run (batched, volume, warm, gradient, stokes)")
+    ap.add_argument("--legs", default="batched,volume,warm,gradient,stokes,fmm",
+                    help="comma list of the extra legs to run (batched, volume, warm, gradient, stokes, fmm)")
     ap.add_argument("--tune-cache", default=TUNED_SPLITS,
                     help="JSON cache of the autotuned launch shapes (read; plans missing from it are tuned afresh)")
     ap.add_argument("--tune-write", action="store_true", help="add freshly tuned plans to the cache file")
@@ -287,9 +287,63 @@ def main():
         out["gradient"] = bench_grad(mhlp, plans, gdev, cfg, args, torch)
     if "stokes" in legs:
         out["stokes"] = bench_stokes(mhlp, wl, cfg, G, tx, ty, t, args, torch)
+    if "fmm" in legs:
+        out["fmm"] = bench_fmm(mhlp, wl, plans, gdev, cfg, G, tx, ty, t, torch)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, 50.0, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def _event_ms(torch, fn, reps):
+    fn()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def bench_fmm(mhlp, wl, plans, gdev, cfg, G, tx, ty, t, torch):
+    """FMM far field (order 40, the paper's) against the direct tile sums on the
+    same inputs: the fused SLP+DLP evaluation of the solved densities at the
+    109,314 config-2 targets per alpha (own FMM plans, automatic leaf level), and
+    the config-3 volume sum (65,536 points, 4.3e9 pairs).  Times per evaluation
+    with HIP events; the tree build is reported separately."""
+    print("# fmm leg", file=sys.stderr, flush=True)
+    res = {"order": 40, "eval": {}}
+    for a in cfg["alphas"]:
+        on, off = plans[a]
+        mu, _ = mhlp.gmres_solve(on, gdev[a], tol=1e-10)
+        P = mhlp.Plan(G, a, tx, ty)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P.set_fmm(40)
+        build_ms = (time.perf_counter() - t0) * 1e3
+        ds, dd = mhlp.eval_layer(off, sigma=mu, mu=mu)
+        fs, fd = mhlp.eval_layer(P, sigma=mu, mu=mu)
+        diff = max(float((fs - ds).abs().max() / ds.abs().max()), float((fd - dd).abs().max() / dd.abs().max()))
+        fms = _event_ms(torch, lambda: mhlp.eval_layer(P, sigma=mu, mu=mu, out_slp=fs, out_dlp=fd), 10)
+        dms = _event_ms(torch, lambda: mhlp.eval_layer(off, sigma=mu, mu=mu, out_slp=ds, out_dlp=dd), 10)
+        res["eval"][f"alpha={a:g}"] = {"fmm_ms": round(fms, 4), "direct_ms": round(dms, 4),
+                                       "speedup": round(dms / fms, 2), "leaf_level": P.fmm[1],
+                                       "tree_build_ms": round(build_ms, 1), "max_rel_diff": diff}
+    c = wl.config3()
+    x, y, w, f = (t(c[k]) for k in ("x", "y", "w", "f"))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    V = mhlp.VolumeFMM(x, y, w, c["alpha"], c["h"], order=40)
+    build_ms = (time.perf_counter() - t0) * 1e3
+    u = V.eval(f)
+    ud, _ = mhlp.volume_eval(x, y, w, f, c["alpha"], c["h"])
+    fms = _event_ms(torch, lambda: V.eval(f, out=u), 10)
+    dms = _event_ms(torch, lambda: mhlp.volume_eval(x, y, w, f, c["alpha"], c["h"], out=ud), 3)
+    res["volume"] = {"fmm_ms": round(fms, 4), "direct_ms": round(dms, 4), "speedup": round(dms / fms, 2),
+                     "leaf_level": V.leaf_level, "tree_build_ms": round(build_ms, 1),
+                     "max_rel_diff": float((u - ud).abs().max() / ud.abs().max()),
+                     "gpair_equiv_per_s": round(c["x"].size ** 2 / (fms * 1e-3) / 1e9, 1)}
+    return res
 
 
 def bench_batched(mhlp, wl, t, torch):

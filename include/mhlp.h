@@ -224,6 +224,48 @@ mhlp_status mhlp_eval_grad(const mhlp_plan *plan, const double *sigma, const dou
 mhlp_status mhlp_gmres_solve(const mhlp_plan *onsurf, const double *g, double *mu, const mhlp_gmres_opts *opts,
                              mhlp_gmres_info *info, void *stream);
 
+/* Fast multipole far field (Sec. 3.2.1, "Fast summation"), for the scalar
+   kernel.  The far sums sum_j [q_j K0(alpha r) + d_j . grad_y K0(alpha r)] (q = w sigma
+   for S, d = w mu n for D) are evaluated on a uniform quadtree: each leaf box
+   takes the sources of its 3x3 neighbourhood directly and every other source
+   through multipole (K_n) and local (I_n) expansions of order `order`
+   (|n| <= order), translated by Graf's addition theorem (the paper's
+   expansions restricted to modified-Helmholtz fields).  The truncation error
+   falls geometrically with the order (order 40, the paper's choice, gives about
+   1e-15 relative to the field; 20 about 1e-9).  Levels whose well-separated
+   pairs are all below K0(40) (alpha 0.586 side > 40) are left out.
+   Root square: centre at the midpoint of the bounding box of all sources and
+   targets, side = largest extent x (1 + 2^-20); leaf level L has 4^L boxes.
+   mhlp_plan_set_fmm (off-surface scalar plan): order 0 turns the FMM off; order
+   in [4, 60] builds the tree for the plan's nodes and targets, after which
+   mhlp_eval_layer / _slp / _dlp with MHLP_FP64 evaluate the far field by the
+   FMM (near-panel corrections unchanged; the direct part skips each target's
+   near panels); MHLP_MIXED keeps the direct FP32 tiles.  leaf_level -1 picks the
+   finest level <= 8 (about 32 points per leaf or more) at which every node of
+   each target's near panels lies in the target's 3x3 leaf neighbourhood; an
+   explicit level must satisfy that (MHLP_INVALID_ARG otherwise).  Builds on the
+   host and the device, synchronises the stream.  Errors: MHLP_UNSUPPORTED on an
+   on-surface plan, MHLP_INVALID_ARG for a stokes plan or parameters out of range.
+   mhlp_plan_get_fmm (host outputs): order (0 when off) and leaf level (-1). */
+mhlp_status mhlp_plan_set_fmm(mhlp_plan *plan, int32_t order, int32_t leaf_level, void *stream);
+mhlp_status mhlp_plan_get_fmm(const mhlp_plan *plan, int32_t *order, int32_t *leaf_level);
+
+/* The volume sum of mhlp_volume_eval by the FMM: the object holds the tree of
+   the n points (x, y, w: device [n], copied in leaf order at create; the
+   caller's arrays may be freed afterwards) and the self-cell weight.
+   mhlp_volume_fmm_eval: u (device [n], overwritten) for the density f (device
+   [n]); coincident points are skipped in the direct part as in
+   mhlp_volume_eval.  leaf_level -1: about 64 points per leaf (<= 8).
+   mhlp_volume_fmm_info: order, leaf level and Wcell (host outputs, may be NULL).
+   Errors: MHLP_INVALID_ARG (NULL or aliased arrays, n < 1, alpha or h not > 0,
+   order not in [4, 60], level not -1 or in [0, 10]). */
+typedef struct mhlp_volume_fmm mhlp_volume_fmm;
+mhlp_status mhlp_volume_fmm_create(const double *x, const double *y, const double *w, int64_t n, double alpha,
+                                   double h, int32_t order, int32_t leaf_level, void *stream, mhlp_volume_fmm **out);
+mhlp_status mhlp_volume_fmm_eval(const mhlp_volume_fmm *vf, const double *f, double *u, void *stream);
+mhlp_status mhlp_volume_fmm_info(const mhlp_volume_fmm *vf, int32_t *order, int32_t *leaf_level, double *self_cell);
+mhlp_status mhlp_volume_fmm_destroy(mhlp_volume_fmm *vf);
+
 /* Volume-style all-pairs Yukawa sum on a tensor grid (the dense stress case;
    the paper instead treats volume potentials by FFT, Sec. 3.1):
      u_i = sum_{j != i} K0(alpha |x_i - x_j|)/(2 pi) w_j f_j + (w_i / h^2) Wcell f_i,

@@ -88,6 +88,10 @@ struct GState {
     double pad;
 };
 
+namespace mhlp {
+struct FmmTree;
+}
+
 struct mhlp_plan {
     const mhlp_geometry *g = nullptr;
     double alpha = 0.0;
@@ -103,6 +107,7 @@ struct mhlp_plan {
     double *wgrad = nullptr;  /* off-surface, built on first use: [4][nnz][16] gradient weights */
     bool stokes = false;      /* modified-Stokes (stresslet) plan: operator on [2][N] densities */
     double *wstk = nullptr;   /* stokes: [4][nnz][16] stresslet weights (D11, D12, D21, D22)   */
+    mhlp::FmmTree *fmm = nullptr; /* off-surface scalar plans: FMM far field (mhlp_plan_set_fmm) */
     double *wstkg = nullptr;  /* stokes, off-surface, built on first use: [8][nnz][16] stresslet
                                  gradient weights, block (2a + l) 2 + j = d u_a/d x_l per mu_j */
     double *stk_flux = nullptr; /* stokes: device scalar sum_j w_j mu_j.n_j / |Gamma|           */
@@ -1408,6 +1413,8 @@ __global__ void fill_kernel(double *__restrict__ x, double v, int64_t N)
     if (i < N) x[i] = v;
 }
 
+#include "fmm.h"
+
 /* ------------------------------------------------------------------------ */
 /* host helpers                                                              */
 /* ------------------------------------------------------------------------ */
@@ -1428,6 +1435,291 @@ static mhlp_status dalloc(T **p, int64_t n)
         mhlp_status s_ = (x);           \
         if (s_ != MHLP_OK) return s_;   \
     } while (0)
+
+/* ------------------------------------------------------------------------ */
+/* FMM tree (host side): root square, stable counting sort of sources and    */
+/* targets into leaf boxes, per-level occupancy, leaf work items, and the    */
+/* translation tables (computed on the device)                               */
+/* ------------------------------------------------------------------------ */
+namespace mhlp {
+struct FmmTree {
+    FmmDev d{};
+    std::vector<void *> bufs;
+    int32_t order = 0, level = 0;
+    ~FmmTree()
+    {
+        for (void *b : bufs)
+            if (b) (void)hipFree(b);
+    }
+    template <class T>
+    mhlp_status alloc(T **p, int64_t n)
+    {
+        mhlp_status s = dalloc(p, n < 1 ? 1 : n);
+        if (s == MHLP_OK) bufs.push_back((void *)*p);
+        return s;
+    }
+};
+} // namespace mhlp
+using mhlp::FmmTree;
+
+static int fmm_coord(double v, double v0, double side, int nb)
+{
+    const double f = std::floor((v - v0) / side);
+    return f < 0.0 ? 0 : (f >= (double)nb ? nb - 1 : (int)f);
+}
+
+struct FmmGeom {
+    double x0, y0, S;
+};
+
+/* root square of the sources and targets (same definition as the oracle's) */
+static FmmGeom fmm_root(const std::vector<double> &sx, const std::vector<double> &sy, const std::vector<double> &tx,
+                        const std::vector<double> &ty)
+{
+    double xmin = INFINITY, xmax = -INFINITY, ymin = INFINITY, ymax = -INFINITY;
+    auto upd = [&](const std::vector<double> &a, const std::vector<double> &b) {
+        for (size_t k = 0; k < a.size(); ++k) {
+            xmin = std::min(xmin, a[k]);
+            xmax = std::max(xmax, a[k]);
+            ymin = std::min(ymin, b[k]);
+            ymax = std::max(ymax, b[k]);
+        }
+    };
+    upd(sx, sy);
+    upd(tx, ty);
+    const double cx = 0.5 * (xmin + xmax), cy = 0.5 * (ymin + ymax);
+    const double ext = std::max(xmax - xmin, ymax - ymin);
+    const double S = ext > 0.0 ? ext * (1.0 + 0x1p-20) : 1.0;
+    const double hS = 0.5 * S;
+    return FmmGeom{cx - hS, cy - hS, S};
+}
+
+/* every node of every near panel of a target lies in the target's 3x3 leaf
+   neighbourhood (then skipping near panels in the direct part skips them everywhere) */
+static bool fmm_contains_near(const FmmGeom &G, int L, const std::vector<double> &sx, const std::vector<double> &sy,
+                              const std::vector<double> &tx, const std::vector<double> &ty,
+                              const std::vector<int32_t> &nptr, const std::vector<int32_t> &npan)
+{
+    const int nb = 1 << L;
+    const double side = G.S / (double)nb;
+    const int64_t M = (int64_t)tx.size(), Np = (int64_t)sx.size() / 16;
+    for (int64_t i = 0; i < M; ++i) {
+        const int ix = fmm_coord(tx[i], G.x0, side, nb), iy = fmm_coord(ty[i], G.y0, side, nb);
+        for (int32_t q = nptr[i]; q < nptr[i + 1]; ++q) {
+            const int64_t pn = npan[q];
+            if (pn < 0 || pn >= Np) continue;
+            for (int j = 0; j < 16; ++j) {
+                const int jx = fmm_coord(sx[16 * pn + j], G.x0, side, nb);
+                const int jy = fmm_coord(sy[16 * pn + j], G.y0, side, nb);
+                if (std::abs(jx - ix) > 1 || std::abs(jy - iy) > 1) return false;
+            }
+        }
+    }
+    return true;
+}
+
+/* Build the tree.  Sources: host copies sx, sy and device arrays dsx.. (gathered
+   into leaf order; dnx/dny NULL for the volume); targets tx, ty (host), or the
+   sources themselves when same_points. */
+static mhlp_status fmm_build(FmmTree *F, const FmmGeom &G, int L, int p, double alpha,
+                             const std::vector<double> &sx, const std::vector<double> &sy,
+                             const std::vector<double> &tx, const std::vector<double> &ty, bool same_points,
+                             const double *dsx, const double *dsy, const double *dsw, const double *dnx,
+                             const double *dny, hipStream_t st)
+{
+    FmmDev &T = F->d;
+    const int nb = 1 << L;
+    const int64_t nleaf = (int64_t)nb * nb, N = (int64_t)sx.size(), M = same_points ? N : (int64_t)tx.size();
+    T.L = L;
+    T.p = p;
+    T.alpha = alpha;
+    T.x0 = G.x0;
+    T.y0 = G.y0;
+    T.S = G.S;
+    for (int l = 0; l <= L; ++l) {
+        T.side[l] = G.S / (double)(1 << l);
+        T.sig[l] = std::min(1.0, alpha * T.side[l]);
+    }
+    T.lstart = L + 1;
+    for (int l = 2; l <= L; ++l)
+        if (alpha * 0.586 * T.side[l] <= 40.0) {
+            T.lstart = l;
+            break;
+        }
+    /* stable counting sorts into the leaves */
+    auto sort_pts = [&](const std::vector<double> &ax, const std::vector<double> &ay, int64_t n,
+                        std::vector<int32_t> &start, std::vector<int32_t> &idx) {
+        std::vector<int32_t> leaf(n);
+        start.assign(nleaf + 1, 0);
+        for (int64_t k = 0; k < n; ++k) {
+            const int ix = fmm_coord(ax[k], G.x0, T.side[L], nb), iy = fmm_coord(ay[k], G.y0, T.side[L], nb);
+            leaf[k] = iy * nb + ix;
+            ++start[leaf[k] + 1];
+        }
+        for (int64_t b = 0; b < nleaf; ++b) start[b + 1] += start[b];
+        std::vector<int32_t> pos(start.begin(), start.end() - 1);
+        idx.resize(n);
+        for (int64_t k = 0; k < n; ++k) idx[pos[leaf[k]]++] = (int32_t)k;
+    };
+    std::vector<int32_t> sstart, sidx, tstart, tidx;
+    sort_pts(sx, sy, N, sstart, sidx);
+    if (same_points) {
+        tstart = sstart;
+        tidx = sidx;
+    } else {
+        sort_pts(tx, ty, M, tstart, tidx);
+    }
+    /* occupancy per level */
+    const int64_t nall = mhlp::lev4(L + 1);
+    std::vector<int32_t> socc(nall, 0), tocc(nall, 0);
+    for (int64_t b = 0; b < nleaf; ++b) {
+        socc[mhlp::lev4(L) + b] = sstart[b + 1] - sstart[b];
+        tocc[mhlp::lev4(L) + b] = tstart[b + 1] - tstart[b];
+    }
+    for (int l = L - 1; l >= 0; --l) {
+        const int n1 = 1 << l;
+        for (int iy = 0; iy < 2 * n1; ++iy)
+            for (int ix = 0; ix < 2 * n1; ++ix) {
+                const int64_t c = mhlp::lev4(l + 1) + iy * 2 * n1 + ix, pb = mhlp::lev4(l) + (iy >> 1) * n1 + (ix >> 1);
+                socc[pb] += socc[c];
+                tocc[pb] += tocc[c];
+            }
+    }
+    /* leaf work items */
+    std::vector<int32_t> wbox, wt0;
+    for (int64_t b = 0; b < nleaf; ++b)
+        for (int32_t t0 = tstart[b]; t0 < tstart[b + 1]; t0 += mhlp::FMM_TILE) {
+            wbox.push_back((int32_t)b);
+            wt0.push_back(t0);
+        }
+    T.nwork = (int)wbox.size();
+    /* expansions and tables */
+    int64_t eo = 0, to = 0;
+    const int64_t rl = 3 * p + 1;
+    std::vector<mhlp::FmmRow> rows;
+    for (int l = 0; l <= L; ++l) {
+        T.eoff[l] = T.t2l[l] = T.tmm[l] = T.tll[l] = 0;
+        if (l < T.lstart) continue;
+        T.eoff[l] = eo;
+        eo += 2 * ((int64_t)1 << (2 * l)) * (p + 1);
+        T.t2l[l] = to;
+        for (int ox = -3; ox <= 3; ++ox)
+            for (int oy = -3; oy <= 3; ++oy) {
+                if (std::abs(ox) <= 1 && std::abs(oy) <= 1) continue;
+                rows.push_back(mhlp::FmmRow{-ox * T.side[l], -oy * T.side[l], T.sig[l],
+                                            to + ((ox + 3) * 7 + (oy + 3)) * rl, 0});
+            }
+        to += 49 * rl;
+        if (l < L) {
+            const double hc = 0.5 * T.side[l + 1];
+            T.tmm[l] = to;
+            for (int ch = 0; ch < 4; ++ch)
+                rows.push_back(mhlp::FmmRow{(ch & 1) ? hc : -hc, (ch >> 1) ? hc : -hc, T.sig[l], to + ch * rl, 1});
+            to += 4 * rl;
+            T.tll[l] = to;
+            for (int ch = 0; ch < 4; ++ch)
+                rows.push_back(mhlp::FmmRow{(ch & 1) ? hc : -hc, (ch >> 1) ? hc : -hc, T.sig[l + 1], to + ch * rl, 1});
+            to += 4 * rl;
+        }
+    }
+    int32_t *d_sstart, *d_tstart, *d_sidx, *d_tidx, *d_socc, *d_tocc, *d_wbox, *d_wt0, *d_lpan = nullptr;
+    double *d_lx, *d_ly, *d_lw, *d_lnx = nullptr, *d_lny = nullptr;
+    cplx *d_mexp, *d_lexp, *d_tab;
+    TRY(F->alloc(&d_sstart, nleaf + 1));
+    TRY(F->alloc(&d_tstart, nleaf + 1));
+    TRY(F->alloc(&d_sidx, N));
+    TRY(F->alloc(&d_tidx, M));
+    TRY(F->alloc(&d_socc, nall));
+    TRY(F->alloc(&d_tocc, nall));
+    TRY(F->alloc(&d_wbox, T.nwork));
+    TRY(F->alloc(&d_wt0, T.nwork));
+    TRY(F->alloc(&d_lx, N));
+    TRY(F->alloc(&d_ly, N));
+    TRY(F->alloc(&d_lw, N));
+    if (dnx) {
+        TRY(F->alloc(&d_lnx, N));
+        TRY(F->alloc(&d_lny, N));
+        TRY(F->alloc(&d_lpan, N));
+    }
+    TRY(F->alloc(&d_mexp, eo));
+    TRY(F->alloc(&d_lexp, eo));
+    TRY(F->alloc(&d_tab, to));
+    mhlp::FmmRow *d_rows = nullptr;
+    double *d_scr = nullptr;
+    const int nrows = (int)rows.size();
+    if (nrows > 0) {
+        TRY(dalloc(&d_rows, nrows));
+        mhlp_status s2 = dalloc(&d_scr, (int64_t)nrows * (2 * p + 1));
+        if (s2 != MHLP_OK) {
+            (void)hipFree(d_rows);
+            return s2;
+        }
+    }
+    auto up = [&](void *d, const void *h, size_t bytes) -> hipError_t {
+        return bytes ? hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, st) : hipSuccess;
+    };
+    hipError_t e = up(d_sstart, sstart.data(), sstart.size() * 4);
+    if (e == hipSuccess) e = up(d_tstart, tstart.data(), tstart.size() * 4);
+    if (e == hipSuccess) e = up(d_sidx, sidx.data(), sidx.size() * 4);
+    if (e == hipSuccess) e = up(d_tidx, tidx.data(), tidx.size() * 4);
+    if (e == hipSuccess) e = up(d_socc, socc.data(), socc.size() * 4);
+    if (e == hipSuccess) e = up(d_tocc, tocc.data(), tocc.size() * 4);
+    if (e == hipSuccess) e = up(d_wbox, wbox.data(), wbox.size() * 4);
+    if (e == hipSuccess) e = up(d_wt0, wt0.data(), wt0.size() * 4);
+    if (e == hipSuccess && nrows > 0) e = up(d_rows, rows.data(), rows.size() * sizeof(mhlp::FmmRow));
+    if (e == hipSuccess) {
+        mhlp::fmm_gather_kernel<<<nblocks(N, 256), 256, 0, st>>>(d_sidx, N, dsx, dsy, dsw, dnx, dny, d_lx, d_ly, d_lw,
+                                                                 d_lnx, d_lny, d_lpan);
+        if (nrows > 0)
+            mhlp::fmm_tables_kernel<<<nblocks(nrows, 64), 64, 0, st>>>(d_rows, nrows, p, alpha, d_tab, d_scr);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (d_rows) (void)hipFree(d_rows);
+    if (d_scr) (void)hipFree(d_scr);
+    if (e != hipSuccess) return fail(MHLP_HIP_ERROR, std::string("fmm build: ") + hipGetErrorString(e));
+    T.sstart = d_sstart;
+    T.tstart = d_tstart;
+    T.sidx = d_sidx;
+    T.tidx = d_tidx;
+    T.socc = d_socc;
+    T.tocc = d_tocc;
+    T.wbox = d_wbox;
+    T.wt0 = d_wt0;
+    T.lx = d_lx;
+    T.ly = d_ly;
+    T.lw = d_lw;
+    T.lnx = d_lnx;
+    T.lny = d_lny;
+    T.lpan = d_lpan;
+    T.mexp = d_mexp;
+    T.lexp = d_lexp;
+    T.tab = d_tab;
+    F->order = p;
+    F->level = L;
+    return MHLP_OK;
+}
+
+/* upward and downward passes; the leaf kernel is launched by the caller */
+template <bool SLP, bool DLP>
+static void fmm_passes(const FmmTree *F, const double *sigma, const double *mu, hipStream_t st)
+{
+    const FmmDev &T = F->d;
+    if (T.lstart > T.L) return;
+    mhlp::fmm_p2m_kernel<SLP, DLP><<<(unsigned)(1u << (2 * T.L)), 64, 0, st>>>(T, sigma, mu);
+    for (int l = T.L - 1; l >= T.lstart; --l)
+        mhlp::fmm_m2m_kernel<SLP, DLP><<<(unsigned)(1u << (2 * l)), 256, 0, st>>>(T, l);
+    for (int l = T.lstart; l <= T.L; ++l)
+        mhlp::fmm_down_kernel<SLP, DLP><<<(unsigned)(1u << (2 * l)), 64 * mhlp::FMM_DW, 0, st>>>(T, l);
+}
+
+template <bool SLP, bool DLP>
+static void fmm_far_t(const FmmTree *F, const FarArgs &A, hipStream_t st)
+{
+    fmm_passes<SLP, DLP>(F, A.sigma, A.mu, st);
+    if (F->d.nwork > 0)
+        mhlp::fmm_leaf_kernel<SLP, DLP, 0><<<(unsigned)F->d.nwork, 64 * mhlp::FMM_LW, 0, st>>>(F->d, A, mhlp::FmmVol{});
+}
 
 static GeoView view(const mhlp_geometry *g)
 {
@@ -1547,6 +1839,7 @@ extern "C" mhlp_status mhlp_plan_destroy(mhlp_plan *P)
                     P->wstkg};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    delete P->fmm;
     if (P->hhost) (void)hipHostFree(P->hhost);
     if (P->gstate_host) (void)hipHostFree(P->gstate_host);
     delete P;
@@ -1835,6 +2128,16 @@ static mhlp_status launch_far(const mhlp_plan *P, const double *sigma, const dou
     A.gs = gs;
     A.jstride = jstride;
     A.perm = P->perm;
+    if (P->fmm && precision == MHLP_FP64 && !gs) {
+        if (sigma && mu)
+            fmm_far_t<true, true>(P->fmm, A, st);
+        else if (sigma)
+            fmm_far_t<true, false>(P->fmm, A, st);
+        else
+            fmm_far_t<false, true>(P->fmm, A, st);
+        HIPCHECK(hipGetLastError());
+        return MHLP_OK;
+    }
     if (sigma && mu)
         launch_far_t<true, true>(A, P->nsplit, precision, st);
     else if (sigma)
@@ -2527,6 +2830,163 @@ extern "C" mhlp_status mhlp_stokes_gmres_solve(const mhlp_plan *P, const double 
 /* ------------------------------------------------------------------------ */
 /* volume API                                                                */
 /* ------------------------------------------------------------------------ */
+/* ------------------------------------------------------------------------ */
+/* FMM far field: plans and the volume sum                                   */
+/* ------------------------------------------------------------------------ */
+template <class T>
+static mhlp_status to_host(std::vector<T> &h, const T *d, int64_t n, hipStream_t st)
+{
+    h.resize(n);
+    if (n == 0) return MHLP_OK;
+    hipError_t e = hipMemcpyAsync(h.data(), d, sizeof(T) * (size_t)n, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(MHLP_HIP_ERROR, std::string("copy to host: ") + hipGetErrorString(e));
+    return MHLP_OK;
+}
+
+static int fmm_auto_level(int64_t npts, int64_t per_leaf)
+{
+    int L = 0;
+    while (L < 8 && ((int64_t)1 << (2 * L)) * per_leaf < npts) ++L;
+    return L;
+}
+
+extern "C" mhlp_status mhlp_plan_set_fmm(mhlp_plan *P, int32_t order, int32_t leaf_level, void *stream)
+{
+    if (!P) return fail(MHLP_INVALID_ARG, "plan is NULL");
+    if (order == 0) {
+        delete P->fmm;
+        P->fmm = nullptr;
+        return MHLP_OK;
+    }
+    if (P->stokes) return fail(MHLP_INVALID_ARG, "the FMM serves scalar plans");
+    if (P->onsurf) return fail(MHLP_UNSUPPORTED, "the FMM serves off-surface plans");
+    if (order < 4 || order > mhlp::FMM_PMAX) return fail(MHLP_INVALID_ARG, "order must be 0 or in [4, 60]");
+    if (leaf_level < -1 || leaf_level > mhlp::FMM_LMAX) return fail(MHLP_INVALID_ARG, "leaf_level must be -1 or in [0, 10]");
+    hipStream_t st = (hipStream_t)stream;
+    const mhlp_geometry *g = P->g;
+    std::vector<double> sx, sy, tx, ty;
+    std::vector<int32_t> nptr, npan;
+    TRY(to_host(sx, g->soa, g->N, st));
+    TRY(to_host(sy, g->soa + g->N, g->N, st));
+    TRY(to_host(tx, P->tx, P->M, st));
+    TRY(to_host(ty, P->ty, P->M, st));
+    TRY(to_host(nptr, P->near_ptr, P->M + 1, st));
+    TRY(to_host(npan, P->near_panel, P->nnz, st));
+    const FmmGeom G = fmm_root(sx, sy, tx, ty);
+    int L = leaf_level;
+    if (L < 0) {
+        L = fmm_auto_level(P->M + g->N, 32);
+        while (L > 0 && !fmm_contains_near(G, L, sx, sy, tx, ty, nptr, npan)) --L;
+    } else if (!fmm_contains_near(G, L, sx, sy, tx, ty, nptr, npan)) {
+        return fail(MHLP_INVALID_ARG, "leaf_level too fine: a near panel reaches beyond a target's 3x3 leaf neighbourhood");
+    }
+    FmmTree *F = new FmmTree();
+    mhlp_status s = fmm_build(F, G, L, order, P->alpha, sx, sy, tx, ty, false, g->soa, g->soa + g->N, g->w, g->nx,
+                              g->ny, st);
+    if (s != MHLP_OK) {
+        delete F;
+        return s;
+    }
+    delete P->fmm;
+    P->fmm = F;
+    return MHLP_OK;
+}
+
+extern "C" mhlp_status mhlp_plan_get_fmm(const mhlp_plan *P, int32_t *order, int32_t *leaf_level)
+{
+    if (!P) return fail(MHLP_INVALID_ARG, "plan is NULL");
+    if (order) *order = P->fmm ? P->fmm->order : 0;
+    if (leaf_level) *leaf_level = P->fmm ? P->fmm->level : -1;
+    return MHLP_OK;
+}
+
+struct mhlp_volume_fmm {
+    FmmTree tree;
+    int64_t n = 0;
+    double alpha = 0.0, h = 0.0, selfc = 0.0, wcell = 0.0;
+};
+
+static mhlp_status self_cell_value(double alpha, double h, hipStream_t st, double *wc)
+{
+    double *dev = nullptr;
+    TRY(dalloc(&dev, 1));
+    self_cell_kernel<<<1, 64, 0, st>>>(alpha, h, dev);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(wc, dev, sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(dev);
+    if (e != hipSuccess) return fail(MHLP_HIP_ERROR, std::string("volume self cell: ") + hipGetErrorString(e));
+    return MHLP_OK;
+}
+
+extern "C" mhlp_status mhlp_volume_fmm_create(const double *x, const double *y, const double *w, int64_t n,
+                                              double alpha, double h, int32_t order, int32_t leaf_level, void *stream,
+                                              mhlp_volume_fmm **out)
+{
+    if (!out) return fail(MHLP_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!x || !y || !w) return fail(MHLP_INVALID_ARG, "NULL argument");
+    if (n < 1 || n > INT_MAX - 1) return fail(MHLP_INVALID_ARG, "n out of range");
+    if (!(alpha > 0.0) || !std::isfinite(alpha) || !(h > 0.0)) return fail(MHLP_INVALID_ARG, "alpha and h must be > 0");
+    if (order < 4 || order > mhlp::FMM_PMAX) return fail(MHLP_INVALID_ARG, "order must be in [4, 60]");
+    if (leaf_level < -1 || leaf_level > mhlp::FMM_LMAX) return fail(MHLP_INVALID_ARG, "leaf_level must be -1 or in [0, 10]");
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<double> hx, hy;
+    TRY(to_host(hx, x, n, st));
+    TRY(to_host(hy, y, n, st));
+    for (int64_t k = 0; k < n; ++k)
+        if (!std::isfinite(hx[k]) || !std::isfinite(hy[k])) return fail(MHLP_INVALID_ARG, "coordinates must be finite");
+    const std::vector<double> none;
+    const FmmGeom G = fmm_root(hx, hy, none, none);
+    const int L = leaf_level < 0 ? fmm_auto_level(n, 64) : leaf_level;
+    mhlp_volume_fmm *V = new mhlp_volume_fmm();
+    V->n = n;
+    V->alpha = alpha;
+    V->h = h;
+    mhlp_status s = self_cell_value(alpha, h, st, &V->wcell);
+    if (s == MHLP_OK) s = fmm_build(&V->tree, G, L, order, alpha, hx, hy, none, none, true, x, y, w, nullptr, nullptr, st);
+    if (s != MHLP_OK) {
+        delete V;
+        return s;
+    }
+    V->selfc = V->wcell / (h * h);
+    *out = V;
+    return MHLP_OK;
+}
+
+extern "C" mhlp_status mhlp_volume_fmm_eval(const mhlp_volume_fmm *V, const double *f, double *u, void *stream)
+{
+    if (!V) return fail(MHLP_INVALID_ARG, "volume FMM is NULL");
+    if (!f || !u) return fail(MHLP_INVALID_ARG, "f or u is NULL");
+    if (f == u) return fail(MHLP_INVALID_ARG, "f and u must not alias");
+    hipStream_t st = (hipStream_t)stream;
+    const FmmTree *F = &V->tree;
+    fmm_passes<true, false>(F, f, nullptr, st);
+    FarArgs A{};
+    mhlp::FmmVol vol{f, V->selfc, u};
+    if (F->d.nwork > 0)
+        mhlp::fmm_leaf_kernel<true, false, 1><<<(unsigned)F->d.nwork, 64 * mhlp::FMM_LW, 0, st>>>(F->d, A, vol);
+    HIPCHECK(hipGetLastError());
+    return MHLP_OK;
+}
+
+extern "C" mhlp_status mhlp_volume_fmm_info(const mhlp_volume_fmm *V, int32_t *order, int32_t *leaf_level,
+                                            double *self_cell)
+{
+    if (!V) return fail(MHLP_INVALID_ARG, "volume FMM is NULL");
+    if (order) *order = V->tree.order;
+    if (leaf_level) *leaf_level = V->tree.level;
+    if (self_cell) *self_cell = V->wcell;
+    return MHLP_OK;
+}
+
+extern "C" mhlp_status mhlp_volume_fmm_destroy(mhlp_volume_fmm *V)
+{
+    delete V;
+    return MHLP_OK;
+}
+
 extern "C" mhlp_status mhlp_volume_eval(const double *x, const double *y, const double *w, const double *f, int64_t n,
                                         double alpha, double h, int32_t precision, double *u, double *self_cell,
                                         void *stream)

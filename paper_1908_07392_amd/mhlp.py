@@ -76,6 +76,14 @@ _SIGS = {
     "mhlp_stokes_eval": ([_V, _V, _V, _V], ctypes.c_int32),
     "mhlp_stokes_apply_bie": ([_V, _V, _V, _V], ctypes.c_int32),
     "mhlp_stokes_eval_grad": ([_V, _V, _V, _V], ctypes.c_int32),
+    "mhlp_plan_set_fmm": ([_V, ctypes.c_int32, ctypes.c_int32, _V], ctypes.c_int32),
+    "mhlp_plan_get_fmm": ([_V, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int32),
+    "mhlp_volume_fmm_create": ([_V, _V, _V, ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                ctypes.c_int32, _V, ctypes.POINTER(_V)], ctypes.c_int32),
+    "mhlp_volume_fmm_eval": ([_V, _V, _V, _V], ctypes.c_int32),
+    "mhlp_volume_fmm_info": ([_V, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), _c_double_p],
+                             ctypes.c_int32),
+    "mhlp_volume_fmm_destroy": ([_V], ctypes.c_int32),
     "mhlp_stokes_gmres_solve": ([_V, _V, _V, ctypes.POINTER(GmresOpts), ctypes.POINTER(GmresInfo), _V],
                                 ctypes.c_int32),
     "mhlp_gmres_solve": ([_V, _V, _V, ctypes.POINTER(GmresOpts), ctypes.POINTER(GmresInfo), _V], ctypes.c_int32),
@@ -234,6 +242,17 @@ class Plan:
                                          ctypes.byref(bms), cand, cms, cap, ctypes.byref(nc)), "plan_autotune")
         return best.value, bms.value, {cand[i]: cms[i] for i in range(nc.value)}
 
+    def set_fmm(self, order: int = 40, leaf_level: int = -1):
+        """FMM far field for FP64 evaluations of an off-surface plan (order 0: off)."""
+        _check(load().mhlp_plan_set_fmm(self._h, int(order), int(leaf_level), _stream()), "plan_set_fmm")
+
+    @property
+    def fmm(self):
+        """(order, leaf level) of the plan's FMM; (0, -1) when the far field is direct."""
+        o, lv = ctypes.c_int32(), ctypes.c_int32()
+        _check(load().mhlp_plan_get_fmm(self._h, ctypes.byref(o), ctypes.byref(lv)), "plan_get_fmm")
+        return o.value, lv.value
+
     def close(self):
         if getattr(self, "_h", None):
             load().mhlp_plan_destroy(self._h)
@@ -362,6 +381,41 @@ def volume_eval(x, y, w, f, alpha, h, precision=FP64, out=None):
                               float(h), int(precision), _dev(out, "u", n), ctypes.byref(wc), _stream()),
            "volume_eval")
     return out, wc.value
+
+
+class VolumeFMM:
+    """The volume sum of ``volume_eval`` by the FMM; the tree of the points is
+    built once, ``eval(f)`` returns u."""
+
+    def __init__(self, x, y, w, alpha, h, order: int = 40, leaf_level: int = -1):
+        L = load()
+        self.n = int(x.numel())
+        self.device = x.device
+        hnd = ctypes.c_void_p()
+        _check(L.mhlp_volume_fmm_create(_dev(x, "x", self.n), _dev(y, "y", self.n), _dev(w, "w", self.n), self.n,
+                                        float(alpha), float(h), int(order), int(leaf_level), _stream(),
+                                        ctypes.byref(hnd)), "volume_fmm_create")
+        self._h = hnd
+        o, lv, wc = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        _check(L.mhlp_volume_fmm_info(hnd, ctypes.byref(o), ctypes.byref(lv), ctypes.byref(wc)), "volume_fmm_info")
+        self.order, self.leaf_level, self.self_cell = o.value, lv.value, wc.value
+
+    def eval(self, f, out=None):
+        out = torch.empty(self.n, dtype=torch.float64, device=self.device) if out is None else out
+        _check(load().mhlp_volume_fmm_eval(self._h, _dev(f, "f", self.n), _dev(out, "u", self.n), _stream()),
+               "volume_fmm_eval")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().mhlp_volume_fmm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Batch:
