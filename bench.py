@@ -75,8 +75,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched, volume, warm-start and gradient legs")
-    ap.add_argument("--legs", default="batched,volume,warm,gradient,stokes,fmm",
-                    help="comma list of the extra legs to run (batched, volume, warm, gradient, stokes, fmm)")
+    ap.add_argument("--legs", default="batched,volume,warm,gradient,stokes,fmm,step",
+                    help="comma list of the extra legs to run (batched, volume, warm, gradient, stokes, fmm, step)")
     ap.add_argument("--tune-cache", default=TUNED_SPLITS,
                     help="JSON cache of the autotuned launch shapes (read; plans missing from it are tuned afresh)")
     ap.add_argument("--tune-write", action="store_true", help="add freshly tuned plans to the cache file")
@@ -289,6 +289,8 @@ def main():
         out["stokes"] = bench_stokes(mhlp, wl, cfg, G, tx, ty, t, args, torch)
     if "fmm" in legs:
         out["fmm"] = bench_fmm(mhlp, wl, plans, gdev, cfg, G, tx, ty, t, torch)
+    if "step" in legs:
+        out["implicit_step"] = bench_step(mhlp, wl, cfg, G, t, torch)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, 50.0, args.cpu_seconds)
     print(json.dumps(out), flush=True)
@@ -343,6 +345,61 @@ def bench_fmm(mhlp, wl, plans, gdev, cfg, G, tx, ty, t, torch):
                      "leaf_level": V.leaf_level, "tree_build_ms": round(build_ms, 1),
                      "max_rel_diff": float((u - ud).abs().max() / ud.abs().max()),
                      "gpair_equiv_per_s": round(c["x"].size ** 2 / (fms * 1e-3) / 1e9, 1)}
+    return res
+
+
+def bench_step(mhlp, wl, cfg, G, t, torch):
+    """One implicit modified-Stokes step on the starfish (N = 4096): the particular
+    solution of a smooth forcing on the periodic box [-1.6, 1.6)^2 with a 512^2
+    grid (u, its gradient and the values at the 4096 boundary nodes), GMRES for
+    (1/2 I + D + W) mu = g - u^P on the 8192 unknowns to 1e-10, and the double
+    layer at the interior grid points; per alpha, after one untimed warm-up step."""
+    print("# implicit step leg", file=sys.stderr, flush=True)
+    g = cfg["geom"]
+    M, x0, Lb = 512, -1.6, 3.2
+    gx = x0 + np.arange(M) * Lb / M
+    X, Y = np.meshgrid(gx, gx, indexing="xy")
+    th = np.arctan2(Y, X)
+    inside = np.hypot(X, Y) < 1.0 + 0.3 * np.cos(5 * th)
+    ix = np.flatnonzero(inside.ravel())
+    rng = np.random.default_rng(77)
+    F = np.zeros((2, M, M))
+    for _ in range(6):
+        c = rng.uniform(-0.5, 0.5, 2)
+        bump = np.exp(-((X - c[0]) ** 2 + (Y - c[1]) ** 2) / (2 * 0.15 ** 2))
+        F[0] += rng.standard_normal() * bump
+        F[1] += rng.standard_normal() * bump
+    Fd = t(F)
+    nx_, ny_ = t(g.x), t(g.y)
+    gb = t(np.stack([np.cos(g.theta), np.sin(2 * g.theta)]))
+    tx, ty = t(X.ravel()[ix]), t(Y.ravel()[ix])
+    res = {"grid": M, "interior_points": int(ix.size), "by_alpha": {}}
+    for a in cfg["alphas"]:
+        box = mhlp.Box(M, x0, x0, Lb, a)
+        on = mhlp.Plan(G, a, stokes=True)
+        off = mhlp.Plan(G, a, tx, ty, stokes=True)
+
+        def step():
+            u, gr, ub = box.particular(Fd, want_u=True, want_grad=True, px=nx_, py=ny_)
+            mu, info = mhlp.stokes_gmres_solve(on, gb - ub, tol=1e-10, restart=200)
+            return u, gr, mhlp.stokes_eval(off, mu), info
+
+        step()
+        torch.cuda.synchronize()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        t0 = time.perf_counter()
+        e[0].record()
+        u, gr, ub = box.particular(Fd, want_u=True, want_grad=True, px=nx_, py=ny_)
+        e[1].record()
+        mu, info = mhlp.stokes_gmres_solve(on, gb - ub, tol=1e-10, restart=200)
+        e[2].record()
+        uh = mhlp.stokes_eval(off, mu)
+        e[3].record()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3
+        res["by_alpha"][f"alpha={a:g}"] = {"particular_ms": round(e[0].elapsed_time(e[1]), 3),
+                                           "gmres_ms": round(e[1].elapsed_time(e[2]), 3), "iters": info["iters"],
+                                           "eval_ms": round(e[2].elapsed_time(e[3]), 3), "step_ms": round(wall, 3)}
     return res
 
 

@@ -266,6 +266,30 @@ mhlp_status mhlp_volume_fmm_eval(const mhlp_volume_fmm *vf, const double *f, dou
 mhlp_status mhlp_volume_fmm_info(const mhlp_volume_fmm *vf, int32_t *order, int32_t *leaf_level, double *self_cell);
 mhlp_status mhlp_volume_fmm_destroy(mhlp_volume_fmm *vf);
 
+/* Particular solution of the modified Stokes equations on a periodic box
+   (Sec. 3.1: (alpha^2 - Delta) u + grad p = F, div u = 0 by the periodic stokeslet
+   multiplier; Sec. 4.1.2: grid FFTs, the gradient by Fourier differentiation
+   and values at boundary points by type-2 sums):
+     u^_j(k) = S^_jl(k) F^_l(k), S^_jl = (delta_jl - k_j k_l/|k|^2)/(alpha^2 + |k|^2), S^(0) = I/alpha^2,
+   on the box [x0, x0 + Lb) x [y0, y0 + Lb) with the M x M grid x_a = x0 + a Lb/M,
+   y_b = y0 + b Lb/M, fields stored [b][a] (row = y); F^ = (1/M^2) DFT of the grid
+   values, wavenumbers k = (2 pi/Lb)(k1, k2), k1, k2 in [-M/2, M/2), Nyquist modes
+   set to zero.  F must be the grid values of a smooth periodic (compactly
+   supported in the box) forcing; the result is spectrally accurate then.
+   mhlp_box_create: M a power of two in [16, 2048], Lb > 0, alpha > 0; the box
+   holds the twiddles and spectra (FP64).  mhlp_box_particular: F device
+   [2][M][M] (F_1 then F_2); outputs (device, each may be NULL, not all): u
+   [2][M][M], grad [4][M][M] (du1/dx, du1/dy, du2/dx, du2/dy), and at n points
+   (px, py device [n]) up [2][n] = sum_k u^_j(k) e^{i k.(x - x0)} evaluated directly
+   (the sum a type-2 non-uniform FFT approximates).  Enqueues only (the first
+   point evaluation with more points than before synchronises to grow a buffer).
+   Calls on one box must not overlap.  Errors: MHLP_INVALID_ARG. */
+typedef struct mhlp_box mhlp_box;
+mhlp_status mhlp_box_create(int32_t M, double x0, double y0, double Lb, double alpha, void *stream, mhlp_box **out);
+mhlp_status mhlp_box_particular(mhlp_box *box, const double *F, double *u, double *grad, int64_t n, const double *px,
+                                const double *py, double *up, void *stream);
+mhlp_status mhlp_box_destroy(mhlp_box *box);
+
 /* Volume-style all-pairs Yukawa sum on a tensor grid (the dense stress case;
    the paper instead treats volume potentials by FFT, Sec. 3.1):
      u_i = sum_{j != i} K0(alpha |x_i - x_j|)/(2 pi) w_j f_j + (w_i / h^2) Wcell f_i,

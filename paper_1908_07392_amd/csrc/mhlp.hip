@@ -1414,6 +1414,7 @@ __global__ void fill_kernel(double *__restrict__ x, double v, int64_t N)
 }
 
 #include "fmm.h"
+#include "fourier.h"
 
 /* ------------------------------------------------------------------------ */
 /* host helpers                                                              */
@@ -2984,6 +2985,117 @@ extern "C" mhlp_status mhlp_volume_fmm_info(const mhlp_volume_fmm *V, int32_t *o
 extern "C" mhlp_status mhlp_volume_fmm_destroy(mhlp_volume_fmm *V)
 {
     delete V;
+    return MHLP_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* particular solution on a periodic box                                     */
+/* ------------------------------------------------------------------------ */
+struct mhlp_box {
+    int M = 0;
+    double x0 = 0.0, y0 = 0.0, Lb = 0.0, alpha = 0.0;
+    cplx *tw = nullptr;   /* M/2 twiddles */
+    cplx *spec = nullptr; /* [2][M^2] forcing spectra */
+    cplx *uh = nullptr;   /* [6][M^2] u^_1, u^_2 and the four gradient spectra */
+    double *part = nullptr;
+    int64_t part_cap = 0;
+    ~mhlp_box()
+    {
+        for (void *q : {(void *)tw, (void *)spec, (void *)uh, (void *)part})
+            if (q) (void)hipFree(q);
+    }
+};
+
+extern "C" mhlp_status mhlp_box_create(int32_t M, double x0, double y0, double Lb, double alpha, void *stream,
+                                       mhlp_box **out)
+{
+    if (!out) return fail(MHLP_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (M < 16 || M > 2048 || (M & (M - 1))) return fail(MHLP_INVALID_ARG, "M must be a power of two in [16, 2048]");
+    if (!std::isfinite(x0) || !std::isfinite(y0) || !(Lb > 0.0) || !std::isfinite(Lb))
+        return fail(MHLP_INVALID_ARG, "box corner must be finite and Lb > 0");
+    if (!(alpha > 0.0) || !std::isfinite(alpha)) return fail(MHLP_INVALID_ARG, "alpha must be finite and > 0");
+    mhlp_box *B = new mhlp_box();
+    B->M = M;
+    B->x0 = x0;
+    B->y0 = y0;
+    B->Lb = Lb;
+    B->alpha = alpha;
+    const int64_t MM = (int64_t)M * M;
+    mhlp_status s;
+    if ((s = dalloc(&B->tw, M / 2)) || (s = dalloc(&B->spec, 2 * MM)) || (s = dalloc(&B->uh, 6 * MM))) {
+        delete B;
+        return s;
+    }
+    std::vector<cplx> tw(M / 2);
+    for (int j = 0; j < M / 2; ++j) {
+        const double a = 2.0 * PI * (double)j / (double)M;
+        tw[j] = mk(std::cos(a), -std::sin(a));
+    }
+    hipError_t e = hipMemcpyAsync(B->tw, tw.data(), sizeof(cplx) * tw.size(), hipMemcpyHostToDevice, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) {
+        delete B;
+        return fail(MHLP_HIP_ERROR, std::string("box_create: ") + hipGetErrorString(e));
+    }
+    *out = B;
+    return MHLP_OK;
+}
+
+static void fft2_fields(const mhlp_box *B, cplx *data, int nf, double sign, hipStream_t st)
+{
+    const int M = B->M;
+    const int64_t MM = (int64_t)M * M;
+    const size_t sh = sizeof(cplx) * 2 * (size_t)M;
+    mhlp::fft_lines_kernel<<<dim3(M, nf), M / 2, sh, st>>>(data, M, 1, M, MM, B->tw, sign); /* rows (x) */
+    mhlp::fft_lines_kernel<<<dim3(M, nf), M / 2, sh, st>>>(data, M, M, 1, MM, B->tw, sign); /* columns (y) */
+}
+
+extern "C" mhlp_status mhlp_box_particular(mhlp_box *B, const double *F, double *u, double *grad, int64_t n,
+                                           const double *px, const double *py, double *up, void *stream)
+{
+    if (!B) return fail(MHLP_INVALID_ARG, "box is NULL");
+    if (!F) return fail(MHLP_INVALID_ARG, "F is NULL");
+    if (n < 0 || n > INT_MAX) return fail(MHLP_INVALID_ARG, "n out of range");
+    if (n > 0 && (!px || !py || !up)) return fail(MHLP_INVALID_ARG, "points need px, py and up");
+    if (!u && !grad && n == 0) return fail(MHLP_INVALID_ARG, "no output requested");
+    hipStream_t st = (hipStream_t)stream;
+    const int M = B->M;
+    const int64_t MM = (int64_t)M * M;
+    mhlp::fft_load_real_kernel<<<nblocks(2 * MM, 256), 256, 0, st>>>(F, 2 * MM, B->spec);
+    fft2_fields(B, B->spec, 2, -1.0, st);
+    mhlp::stokes_multiplier_kernel<<<nblocks(MM, 256), 256, 0, st>>>(B->spec, M, B->Lb, B->alpha, grad != nullptr,
+                                                                     B->uh);
+    if (n > 0) {
+        const int nchunk = M / mhlp::FT2_R;
+        const int64_t need = 2 * (int64_t)nchunk * n;
+        if (need > B->part_cap) {
+            HIPCHECK(hipStreamSynchronize(st));
+            if (B->part) (void)hipFree(B->part);
+            B->part = nullptr;
+            B->part_cap = 0;
+            TRY(dalloc(&B->part, need));
+            B->part_cap = need;
+        }
+        mhlp::type2_points_kernel<<<dim3(nblocks(n, mhlp::FT2_T), nchunk), mhlp::FT2_T, 0, st>>>(
+            B->uh, M, B->Lb, B->x0, B->y0, px, py, n, B->part);
+        mhlp::type2_reduce_kernel<<<nblocks(n, 256), 256, 0, st>>>(B->part, nchunk, n, up);
+    }
+    if (u) {
+        fft2_fields(B, B->uh, 2, 1.0, st);
+        mhlp::fft_store_real_kernel<<<nblocks(2 * MM, 256), 256, 0, st>>>(B->uh, 2 * MM, u);
+    }
+    if (grad) {
+        fft2_fields(B, B->uh + 2 * MM, 4, 1.0, st);
+        mhlp::fft_store_real_kernel<<<nblocks(4 * MM, 256), 256, 0, st>>>(B->uh + 2 * MM, 4 * MM, grad);
+    }
+    HIPCHECK(hipGetLastError());
+    return MHLP_OK;
+}
+
+extern "C" mhlp_status mhlp_box_destroy(mhlp_box *B)
+{
+    delete B;
     return MHLP_OK;
 }
 

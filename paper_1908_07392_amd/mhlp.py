@@ -84,6 +84,10 @@ _SIGS = {
     "mhlp_volume_fmm_info": ([_V, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), _c_double_p],
                              ctypes.c_int32),
     "mhlp_volume_fmm_destroy": ([_V], ctypes.c_int32),
+    "mhlp_box_create": ([ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, _V,
+                         ctypes.POINTER(_V)], ctypes.c_int32),
+    "mhlp_box_particular": ([_V, _V, _V, _V, ctypes.c_int64, _V, _V, _V, _V], ctypes.c_int32),
+    "mhlp_box_destroy": ([_V], ctypes.c_int32),
     "mhlp_stokes_gmres_solve": ([_V, _V, _V, ctypes.POINTER(GmresOpts), ctypes.POINTER(GmresInfo), _V],
                                 ctypes.c_int32),
     "mhlp_gmres_solve": ([_V, _V, _V, ctypes.POINTER(GmresOpts), ctypes.POINTER(GmresInfo), _V], ctypes.c_int32),
@@ -409,6 +413,45 @@ class VolumeFMM:
     def close(self):
         if getattr(self, "_h", None):
             load().mhlp_volume_fmm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Box:
+    """Periodic box [x0, x0+Lb) x [y0, y0+Lb) with an M x M grid for the particular
+    solution of the modified Stokes equations (``particular``)."""
+
+    def __init__(self, M: int, x0: float, y0: float, Lb: float, alpha: float, device="cuda:0"):
+        hnd = ctypes.c_void_p()
+        _check(load().mhlp_box_create(int(M), float(x0), float(y0), float(Lb), float(alpha), _stream(),
+                                      ctypes.byref(hnd)), "box_create")
+        self._h = hnd
+        self.M, self.x0, self.y0, self.Lb, self.alpha = int(M), float(x0), float(y0), float(Lb), float(alpha)
+        self.device = device
+
+    def particular(self, F, want_u=True, want_grad=False, px=None, py=None):
+        """F: [2][M][M] float64 on the device.  Returns (u [2][M][M] or None,
+        grad [4][M][M] or None, up [2][n] at the points or None)."""
+        M = self.M
+        MM = M * M
+        u = torch.empty(2, M, M, dtype=torch.float64, device=self.device) if want_u else None
+        g = torch.empty(4, M, M, dtype=torch.float64, device=self.device) if want_grad else None
+        n = 0 if px is None else int(px.numel())
+        up = torch.empty(2, n, dtype=torch.float64, device=self.device) if n else None
+        _check(load().mhlp_box_particular(self._h, _dev(F, "F", 2 * MM), None if u is None else _dev(u, "u", 2 * MM),
+                                          None if g is None else _dev(g, "grad", 4 * MM), n,
+                                          _dev(px, "px", n) if n else None, _dev(py, "py", n) if n else None,
+                                          _dev(up, "up", 2 * n) if n else None, _stream()), "box_particular")
+        return u, g, up
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().mhlp_box_destroy(self._h)
             self._h = None
 
     def __del__(self):
