@@ -1315,11 +1315,10 @@ __global__ __launch_bounds__(256) void gs_norm_kernel(const GState *__restrict__
    ||w||), the earlier Givens rotations applied to it, a new rotation that
    zeroes the subdiagonal, the rotated right-hand side g and the stopping
    decision.  H is (R+1) x R row-major.  One thread. */
-__global__ void gs_finish_kernel(GState *__restrict__ gs, double *__restrict__ H, int R, double *__restrict__ cs,
-                                 double *__restrict__ sn, double *__restrict__ gv, const double *__restrict__ h1,
-                                 const double *__restrict__ h2, const double *__restrict__ hn)
+__device__ void gs_finish_body(GState *__restrict__ gs, double *__restrict__ H, int R, double *__restrict__ cs,
+                               double *__restrict__ sn, double *__restrict__ gv, const double *__restrict__ h1,
+                               const double *__restrict__ h2, const double *__restrict__ hn)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0 || gs->done) return;
     const int k = gs->j;
     for (int j = 0; j <= k; ++j) H[(int64_t)j * R + k] = h1[j] + h2[j];
     const double hn1 = sqrt(hn[0]);
@@ -1341,6 +1340,91 @@ __global__ void gs_finish_kernel(GState *__restrict__ gs, double *__restrict__ H
     gs->resest = fabs(gv[k + 1]);
     gs->inv = hn1 > 0.0 ? 1.0 / hn1 : 0.0;
     if (gs->resest <= gs->thresh || hn1 == 0.0 || k + 1 >= gs->kmax) gs->done = 1;
+}
+
+__global__ void gs_finish_kernel(GState *__restrict__ gs, double *__restrict__ H, int R, double *__restrict__ cs,
+                                 double *__restrict__ sn, double *__restrict__ gv, const double *__restrict__ h1,
+                                 const double *__restrict__ h2, const double *__restrict__ hn)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0 || gs->done) return;
+    gs_finish_body(gs, H, R, cs, sn, gv, h1, h2, hn);
+}
+
+/* The whole Gram-Schmidt part of an Arnoldi step in one block (small N):
+   both CGS passes, the norm, the Hessenberg column with its rotations and the
+   stopping test, the next basis vector and the advance.  Dot products: each
+   thread sums its strided elements, waves reduce by a fixed butterfly, the
+   wave sums are added in wave order. */
+constexpr int GSF_T = 1024, GSF_W = GSF_T / 64, GSF_RMAX = 256;
+
+__device__ __forceinline__ double gsf_wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+/* hs[c] = V_c . w for c < ncol (LDS) */
+__device__ void gsf_dots(const double *__restrict__ V, int64_t ld, const double *__restrict__ w, int64_t N, int ncol,
+                         double (*red)[GSF_RMAX], double *hs)
+{
+    const int t = threadIdx.x, wv = t >> 6, ln = t & 63;
+    for (int c = 0; c < ncol; ++c) {
+        const double *v = V + (int64_t)c * ld;
+        double sacc = 0.0;
+        for (int64_t i = t; i < N; i += GSF_T) sacc = fma(v[i], w[i], sacc);
+        sacc = gsf_wave_sum(sacc);
+        if (ln == 0) red[wv][c] = sacc;
+    }
+    __syncthreads();
+    for (int c = t; c < ncol; c += GSF_T) {
+        double sacc = red[0][c];
+        for (int q = 1; q < GSF_W; ++q) sacc += red[q][c];
+        hs[c] = sacc;
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(GSF_T) void gs_fused_kernel(GState *__restrict__ gs, double *__restrict__ V, int64_t ld,
+                                                         double *__restrict__ w, int64_t N, double *__restrict__ H,
+                                                         int R, double *__restrict__ cs, double *__restrict__ sn,
+                                                         double *__restrict__ gv, double *__restrict__ h1,
+                                                         double *__restrict__ h2, double *__restrict__ hn)
+{
+    __shared__ double red[GSF_W][GSF_RMAX];
+    __shared__ double hs[2][GSF_RMAX];
+    __shared__ double nrm[GSF_W], hnl[1];
+    __shared__ int done_after;
+    __shared__ double inv;
+    if (gs->done) return; /* the whole block */
+    const int t = threadIdx.x;
+    const int j = gs->j, ncol = j + 1;
+    /* each thread owns the elements t, t + GSF_T, ... of w and of the new column */
+    for (int pass = 0; pass < 2; ++pass) {
+        double *hp = hs[pass];
+        gsf_dots(V, ld, w, N, ncol, red, hp);
+        for (int64_t i = t; i < N; i += GSF_T) {
+            double v = w[i];
+            for (int c = 0; c < ncol; ++c) v = fma(-hp[c], V[(int64_t)c * ld + i], v);
+            w[i] = v;
+        }
+    }
+    double sacc = 0.0;
+    for (int64_t i = t; i < N; i += GSF_T) sacc = fma(w[i], w[i], sacc);
+    sacc = gsf_wave_sum(sacc);
+    if ((t & 63) == 0) nrm[t >> 6] = sacc;
+    __syncthreads();
+    if (t == 0) {
+        double s2 = nrm[0];
+        for (int q = 1; q < GSF_W; ++q) s2 += nrm[q];
+        hnl[0] = s2;
+        gs_finish_body(gs, H, R, cs, sn, gv, hs[0], hs[1], hnl);
+        done_after = gs->done;
+        inv = gs->inv;
+    }
+    __syncthreads();
+    if (done_after) return;
+    for (int64_t i = t; i < N; i += GSF_T) V[(int64_t)(j + 1) * ld + i] = inv * w[i];
+    if (t == 0) gs->j = j + 1;
 }
 
 /* V_{j+1} = w / h_{j+1,j} */
@@ -2592,6 +2676,13 @@ static mhlp_status enqueue_step(mhlp_plan *P, int32_t prec, hipStream_t st)
     const GmresDev d = gdev_view(P);
     const unsigned nbN = nblocks(N, 256);
     TRY(apply_op(P, V, w, prec, st, d.gs, N));
+    /* one block reads every basis column: worth it while that stays within one
+       compute unit's bandwidth, i.e. for short vectors */
+    if (N <= 4096 && R <= GSF_RMAX) {
+        gs_fused_kernel<<<1, GSF_T, 0, st>>>(d.gs, V, N, w, N, d.H, R, d.cs, d.sn, d.gv, d.h1, d.h2, d.hn);
+        HIPCHECK(hipGetLastError());
+        return MHLP_OK;
+    }
     /* classical Gram-Schmidt, twice */
     gs_dot_kernel<<<R, 256, 0, st>>>(d.gs, V, N, w, N, d.h1);
     gs_sub_kernel<<<nbN, 256, 0, st>>>(d.gs, V, N, d.h1, w, N);
