@@ -400,6 +400,21 @@ def bench_step(mhlp, wl, cfg, G, t, torch):
         res["by_alpha"][f"alpha={a:g}"] = {"particular_ms": round(e[0].elapsed_time(e[1]), 3),
                                            "gmres_ms": round(e[1].elapsed_time(e[2]), 3), "iters": info["iters"],
                                            "eval_ms": round(e[2].elapsed_time(e[3]), 3), "step_ms": round(wall, 3)}
+    # SISDC time steps of periodic Navier-Stokes on the same 512^2 grid (Re = 100,
+    # dt = 0.01, orders K = 2 and 3: 2 and 6 implicit solves per step)
+    Re, dtn = 100.0, 0.01
+    gp = np.arange(M) * 2 * np.pi / M
+    Xp, Yp = np.meshgrid(gp, gp, indexing="xy")
+    u0 = np.stack([np.sin(Xp) * np.cos(2 * Yp), -0.5 * np.cos(Xp) * np.sin(2 * Yp)])
+    g0 = np.stack([np.cos(Xp) * np.cos(2 * Yp), -2 * np.sin(Xp) * np.sin(2 * Yp), 0.5 * np.sin(Xp) * np.sin(2 * Yp),
+                   -np.cos(Xp) * np.cos(2 * Yp)])
+    res["sisdc_periodic"] = {"grid": M, "Re": Re, "dt": dtn}
+    for K in (2, 3):
+        box = mhlp.Box(M, 0.0, 0.0, 2 * np.pi, np.sqrt(Re * (K - 1) / dtn))
+        u, gr, L = t(u0), t(g0), t(-5.0 * u0)
+        box.sisdc_step(Re, dtn, K, u, gr, L)
+        ms = _event_ms(torch, lambda: box.sisdc_step(Re, dtn, K, u, gr, L), 5)
+        res["sisdc_periodic"][f"K={K}"] = {"ms_per_step": round(ms, 3), "implicit_solves": (K - 1) * K}
     return res
 
 

@@ -290,6 +290,24 @@ mhlp_status mhlp_box_particular(mhlp_box *box, const double *F, double *u, doubl
                                 const double *py, double *up, void *stream);
 mhlp_status mhlp_box_destroy(mhlp_box *box);
 
+/* One SISDC time step (Sec. 4.3) of the Navier-Stokes equations
+   u_t = -(u.grad)u + (1/Re) Delta u - grad p, div u = 0, on the periodic box
+   (every term on the grid: no embedded boundary and no function extension).
+   K in [2, 5]: p = K - 1 equal substeps dts = dt/p, a first implicit-explicit
+   Euler sweep and K - 1 correction sweeps (global order K); each implicit
+   substep is the box's particular solution with alpha^2 = Re/dts, which the box
+   must have been created with (MHLP_INVALID_ARG otherwise).  Correction sweep:
+     F_{m+1} = alpha^2 u'_m - Re (N'_m - N_m) - L_{m+1} + sum_j q_j^m (L_j - Re N_j),
+   N = (u.grad)u, L = Delta u - Re grad p recovered as alpha^2 u - F from each solve,
+   q_j^m the integrals over [t_m, t_{m+1}] of the Lagrange basis of the substep
+   times (in units of dts).  In/out (device, overwritten with the end-of-step
+   values): u [2][M][M], grad [4][M][M] (du1/dx, du1/dy, du2/dx, du2/dy of u), lap
+   [2][M][M] = L at the start (Delta u of the initial field suffices: gradient
+   terms do not change u).  The first step with a larger K synchronises to grow
+   the box's workspace ((5 K + 1) 2 M^2 doubles).  Errors: MHLP_INVALID_ARG. */
+mhlp_status mhlp_sisdc_step(mhlp_box *box, double Re, double dt, int32_t K, double *u, double *grad, double *lap,
+                            void *stream);
+
 /* Volume-style all-pairs Yukawa sum on a tensor grid (the dense stress case;
    the paper instead treats volume potentials by FFT, Sec. 3.1):
      u_i = sum_{j != i} K0(alpha |x_i - x_j|)/(2 pi) w_j f_j + (w_i / h^2) Wcell f_i,

@@ -179,4 +179,32 @@ __global__ void type2_reduce_kernel(const double *__restrict__ partial, int nchu
     up[n + i] = s2;
 }
 
+/* (u.grad) u from u [2][n] and its gradient g [4][n] (du1/dx, du1/dy, du2/dx, du2/dy) */
+__global__ void advect_kernel(const double *__restrict__ u, const double *__restrict__ g, int64_t n,
+                              double *__restrict__ out)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double u1 = u[i], u2 = u[n + i];
+    out[i] = fma(u1, g[i], u2 * g[n + i]);
+    out[n + i] = fma(u1, g[2 * n + i], u2 * g[3 * n + i]);
+}
+
+/* out = sum_{k < nterm} c_k x_k over n elements (terms added in order) */
+constexpr int LC_MAX = 16;
+struct LinComb {
+    const double *x[LC_MAX];
+    double c[LC_MAX];
+    int nterm;
+};
+
+__global__ void lincomb_kernel(LinComb T, int64_t n, double *__restrict__ out)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = T.c[0] * T.x[0][i];
+    for (int k = 1; k < T.nterm; ++k) s = fma(T.c[k], T.x[k][i], s);
+    out[i] = s;
+}
+
 } // namespace mhlp

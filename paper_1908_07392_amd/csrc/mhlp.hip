@@ -3090,9 +3090,11 @@ struct mhlp_box {
     cplx *uh = nullptr;   /* [6][M^2] u^_1, u^_2 and the four gradient spectra */
     double *part = nullptr;
     int64_t part_cap = 0;
+    double *sdc = nullptr; /* SISDC workspace */
+    int64_t sdc_cap = 0;
     ~mhlp_box()
     {
-        for (void *q : {(void *)tw, (void *)spec, (void *)uh, (void *)part})
+        for (void *q : {(void *)tw, (void *)spec, (void *)uh, (void *)part, (void *)sdc})
             if (q) (void)hipFree(q);
     }
 };
@@ -3187,6 +3189,124 @@ extern "C" mhlp_status mhlp_box_particular(mhlp_box *B, const double *F, double 
 extern "C" mhlp_status mhlp_box_destroy(mhlp_box *B)
 {
     delete B;
+    return MHLP_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* SISDC time step of the Navier-Stokes equations on the periodic box         */
+/* ------------------------------------------------------------------------ */
+/* q[m][j] = (1/dts) int_{t_m}^{t_{m+1}} l_j(t) dt, t_i = i dts: the Lagrange basis
+   polynomial of node j expanded in monomials and integrated exactly */
+static void sisdc_weights(int p, std::vector<double> &q)
+{
+    q.assign((size_t)p * (p + 1), 0.0);
+    for (int j = 0; j <= p; ++j) {
+        std::vector<double> c(1, 1.0); /* coefficients of prod_{i != j} (t - i)/(j - i), ascending */
+        for (int i = 0; i <= p; ++i) {
+            if (i == j) continue;
+            std::vector<double> nc(c.size() + 1, 0.0);
+            for (size_t d = 0; d < c.size(); ++d) {
+                nc[d + 1] += c[d] / (double)(j - i);
+                nc[d] -= c[d] * (double)i / (double)(j - i);
+            }
+            c.swap(nc);
+        }
+        for (int m = 0; m < p; ++m) {
+            double s = 0.0;
+            for (size_t d = 0; d < c.size(); ++d)
+                s += c[d] * (std::pow((double)(m + 1), (double)(d + 1)) - std::pow((double)m, (double)(d + 1))) /
+                     (double)(d + 1);
+            q[(size_t)m * (p + 1) + j] = s;
+        }
+    }
+}
+
+static void lincomb(const std::vector<std::pair<double, const double *>> &terms, int64_t n, double *out,
+                    hipStream_t st)
+{
+    mhlp::LinComb T{};
+    T.nterm = (int)terms.size();
+    for (int k = 0; k < T.nterm; ++k) {
+        T.c[k] = terms[k].first;
+        T.x[k] = terms[k].second;
+    }
+    mhlp::lincomb_kernel<<<nblocks(n, 256), 256, 0, st>>>(T, n, out);
+}
+
+extern "C" mhlp_status mhlp_sisdc_step(mhlp_box *B, double Re, double dt, int32_t K, double *u, double *grad,
+                                       double *lap, void *stream)
+{
+    if (!B) return fail(MHLP_INVALID_ARG, "box is NULL");
+    if (!u || !grad || !lap) return fail(MHLP_INVALID_ARG, "u, grad and lap are required");
+    if (K < 2 || K > 5) return fail(MHLP_INVALID_ARG, "K must be in [2, 5]");
+    if (!(Re > 0.0) || !(dt > 0.0) || !std::isfinite(Re) || !std::isfinite(dt))
+        return fail(MHLP_INVALID_ARG, "Re and dt must be finite and > 0");
+    const int p = K - 1;
+    const double dts = dt / p, a2 = Re / dts;
+    if (std::fabs(B->alpha * B->alpha - a2) > 1e-12 * a2)
+        return fail(MHLP_INVALID_ARG, "the box's alpha must satisfy alpha^2 = Re K'/dt, K' = K - 1 substeps");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n2 = 2 * (int64_t)B->M * B->M, n4 = 2 * n2;
+    /* workspace: N, L of the previous sweep, U, N, L of the new one (p + 1 each), F */
+    const int64_t need = (5 * (int64_t)(p + 1) + 1) * n2;
+    if (need > B->sdc_cap) {
+        HIPCHECK(hipStreamSynchronize(st));
+        if (B->sdc) (void)hipFree(B->sdc);
+        B->sdc = nullptr;
+        B->sdc_cap = 0;
+        TRY(dalloc(&B->sdc, need));
+        B->sdc_cap = need;
+    }
+    double *w = B->sdc;
+    auto slot = [&](int k) { return w + (int64_t)k * n2; };
+    std::vector<double *> No(p + 1), Lo(p + 1), Un(p + 1), Nn(p + 1), Ln(p + 1);
+    for (int m = 0; m <= p; ++m) {
+        No[m] = slot(m);
+        Lo[m] = slot(p + 1 + m);
+        Un[m] = slot(2 * (p + 1) + m);
+        Nn[m] = slot(3 * (p + 1) + m);
+        Ln[m] = slot(4 * (p + 1) + m);
+    }
+    double *F = slot(5 * (p + 1));
+    std::vector<double> q;
+    sisdc_weights(p, q);
+    const unsigned nb = nblocks(n2 / 2, 256);
+    /* start of the step: u0, N0 = (u0.grad) u0, L0 = lap */
+    HIPCHECK(hipMemcpyAsync(Un[0], u, sizeof(double) * n2, hipMemcpyDeviceToDevice, st));
+    mhlp::advect_kernel<<<nb, 256, 0, st>>>(u, grad, n2 / 2, Nn[0]);
+    HIPCHECK(hipMemcpyAsync(Ln[0], lap, sizeof(double) * n2, hipMemcpyDeviceToDevice, st));
+    auto solve_into = [&](int m) -> mhlp_status {
+        /* (alpha^2 - Delta) U_{m+1} + Re grad p = F; N_{m+1}, L_{m+1} = alpha^2 U_{m+1} - F */
+        TRY(mhlp_box_particular(B, F, Un[m + 1], grad, 0, nullptr, nullptr, nullptr, stream));
+        mhlp::advect_kernel<<<nb, 256, 0, st>>>(Un[m + 1], grad, n2 / 2, Nn[m + 1]);
+        lincomb({{a2, Un[m + 1]}, {-1.0, F}}, n2, Ln[m + 1], st);
+        return MHLP_OK;
+    };
+    for (int m = 0; m < p; ++m) { /* first sweep: implicit-explicit Euler */
+        lincomb({{a2, Un[m]}, {-Re, Nn[m]}}, n2, F, st);
+        TRY(solve_into(m));
+    }
+    for (int k = 1; k < K; ++k) { /* corrections */
+        std::swap(No, Nn);
+        std::swap(Lo, Ln);
+        /* the new sweep starts from the same initial values */
+        HIPCHECK(hipMemcpyAsync(Nn[0], No[0], sizeof(double) * n2, hipMemcpyDeviceToDevice, st));
+        HIPCHECK(hipMemcpyAsync(Ln[0], Lo[0], sizeof(double) * n2, hipMemcpyDeviceToDevice, st));
+        for (int m = 0; m < p; ++m) {
+            std::vector<std::pair<double, const double *>> t = {
+                {a2, Un[m]}, {-Re, Nn[m]}, {Re, No[m]}, {-1.0, Lo[m + 1]}};
+            for (int j = 0; j <= p; ++j) {
+                t.push_back({q[(size_t)m * (p + 1) + j], Lo[j]});
+                t.push_back({-Re * q[(size_t)m * (p + 1) + j], No[j]});
+            }
+            lincomb(t, n2, F, st);
+            TRY(solve_into(m));
+        }
+    }
+    HIPCHECK(hipMemcpyAsync(u, Un[p], sizeof(double) * n2, hipMemcpyDeviceToDevice, st));
+    HIPCHECK(hipMemcpyAsync(lap, Ln[p], sizeof(double) * n2, hipMemcpyDeviceToDevice, st));
+    (void)n4;
+    HIPCHECK(hipGetLastError());
     return MHLP_OK;
 }
 

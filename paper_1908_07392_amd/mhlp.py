@@ -88,6 +88,7 @@ _SIGS = {
                          ctypes.POINTER(_V)], ctypes.c_int32),
     "mhlp_box_particular": ([_V, _V, _V, _V, ctypes.c_int64, _V, _V, _V, _V], ctypes.c_int32),
     "mhlp_box_destroy": ([_V], ctypes.c_int32),
+    "mhlp_sisdc_step": ([_V, ctypes.c_double, ctypes.c_double, ctypes.c_int32, _V, _V, _V, _V], ctypes.c_int32),
     "mhlp_stokes_gmres_solve": ([_V, _V, _V, ctypes.POINTER(GmresOpts), ctypes.POINTER(GmresInfo), _V],
                                 ctypes.c_int32),
     "mhlp_gmres_solve": ([_V, _V, _V, ctypes.POINTER(GmresOpts), ctypes.POINTER(GmresInfo), _V], ctypes.c_int32),
@@ -448,6 +449,12 @@ class Box:
                                           _dev(px, "px", n) if n else None, _dev(py, "py", n) if n else None,
                                           _dev(up, "up", 2 * n) if n else None, _stream()), "box_particular")
         return u, g, up
+
+    def sisdc_step(self, Re, dt, K, u, grad, lap):
+        """One SISDC step of periodic Navier-Stokes in place on u [2][M][M], grad [4][M][M], lap [2][M][M]."""
+        MM = self.M * self.M
+        _check(load().mhlp_sisdc_step(self._h, float(Re), float(dt), int(K), _dev(u, "u", 2 * MM),
+                                      _dev(grad, "grad", 4 * MM), _dev(lap, "lap", 2 * MM), _stream()), "sisdc_step")
 
     def close(self):
         if getattr(self, "_h", None):
