@@ -285,6 +285,14 @@ mhlp_status mhlp_volume_fmm_destroy(mhlp_volume_fmm *vf);
    point evaluation with more points than before synchronises to grow a buffer).
    Calls on one box must not overlap.  Errors: MHLP_INVALID_ARG. */
 typedef struct mhlp_box mhlp_box;
+/* mhlp_box_set_point_method: how the point values are formed.  0: the type-2
+   sums written out directly (exact, n M^2 work); 1 (the default for M <= 1024):
+   a non-uniform FFT as in Sec. 4.1.2 (coefficients divided by the transform of
+   an exponential-of-semicircle kernel of width 14, inverse FFT on a 2M x 2M
+   grid, a 14 x 14 kernel sum per point; ~1e-14 of sum |u^| from the exact sums;
+   the first call allocates 2 (2M)^2 complex and synchronises).  Errors:
+   MHLP_INVALID_ARG (method not 0 or 1, method 1 with M > 1024). */
+mhlp_status mhlp_box_set_point_method(mhlp_box *box, int32_t method);
 mhlp_status mhlp_box_create(int32_t M, double x0, double y0, double Lb, double alpha, void *stream, mhlp_box **out);
 mhlp_status mhlp_box_particular(mhlp_box *box, const double *F, double *u, double *grad, int64_t n, const double *px,
                                 const double *py, double *up, void *stream);

@@ -179,6 +179,76 @@ __global__ void type2_reduce_kernel(const double *__restrict__ partial, int nchu
     up[n + i] = s2;
 }
 
+/* ---- type-2 sums at points by a non-uniform FFT (spreading kernel) ----
+   The exponential-of-semicircle kernel phi(z) = exp(beta (sqrt(1 - z^2) - 1)),
+   |z| < 1, spans NU_W points of a fine grid of Mf = 2M points (spacing hf):
+     b(y_l) = sum_k c(k) e^{i k (y_l - x0)},  c(k) = u^(k) hf^2 / (psi^(k1) psi^(k2)),
+     u(x) ~ sum_{l near x} b(y_l) phi_h(x1 - y_l1) phi_h(x2 - y_l2),
+   psi^ the Fourier transform of phi_h(x) = phi(2x/(NU_W hf)) (Poisson summation;
+   the 2x oversampling and the kernel's decay keep the aliased terms ~1e-14 of
+   sum |u^|).  b comes from an inverse FFT of size Mf of the zero-padded c. */
+constexpr int NU_W = 14;
+constexpr double NU_BETA = 2.30 * NU_W;
+
+/* c = u^ corr(k1) corr(k2) placed in the fine spectrum (zero outside |k| < M/2);
+   corr[j] = hf / psi^(k_j) in coarse FFT order */
+__global__ void nufft_fine_spectrum_kernel(const cplx *__restrict__ Uh, int M, int Mf, const double *__restrict__ corr,
+                                           cplx *__restrict__ fine)
+{
+    const int64_t MMf = (int64_t)Mf * Mf;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= 2 * MMf) return;
+    const int comp = (int)(i / MMf);
+    const int64_t e = i % MMf;
+    const int r = (int)(e / Mf), c = (int)(e % Mf);
+    const int h = M / 2;
+    const int jr = r < h ? r : (r >= Mf - h ? r - Mf + M : -1);
+    const int jc = c < h ? c : (c >= Mf - h ? c - Mf + M : -1);
+    cplx v = mk(0.0, 0.0);
+    if (jr >= 0 && jc >= 0) v = (corr[jr] * corr[jc]) * Uh[(int64_t)comp * M * M + (int64_t)jr * M + jc];
+    fine[i] = v;
+}
+
+__device__ __forceinline__ double nu_phi(double z)
+{
+    const double q = 1.0 - z * z;
+    return q > 0.0 ? exp(NU_BETA * (sqrt(q) - 1.0)) : 0.0;
+}
+
+/* u at the points from the fine-grid values b (real parts), NU_W x NU_W stencil */
+__global__ void nufft_interp_kernel(const cplx *__restrict__ fine, int Mf, double hf, double x0, double y0,
+                                    const double *__restrict__ px, const double *__restrict__ py, int64_t n,
+                                    double *__restrict__ up)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double xf = (px[i] - x0) / hf, yf = (py[i] - y0) / hf;
+    const int ix0 = (int)floor(xf) - NU_W / 2 + 1, iy0 = (int)floor(yf) - NU_W / 2 + 1;
+    double wx[NU_W], wy[NU_W];
+#pragma unroll
+    for (int a = 0; a < NU_W; ++a) {
+        wx[a] = nu_phi((xf - (ix0 + a)) * (2.0 / NU_W));
+        wy[a] = nu_phi((yf - (iy0 + a)) * (2.0 / NU_W));
+    }
+    const int64_t MMf = (int64_t)Mf * Mf;
+    double s1 = 0.0, s2 = 0.0;
+    for (int b = 0; b < NU_W; ++b) {
+        const int ry = ((iy0 + b) % Mf + Mf) % Mf;
+        double t1 = 0.0, t2 = 0.0;
+#pragma unroll
+        for (int a = 0; a < NU_W; ++a) {
+            const int cx = ((ix0 + a) % Mf + Mf) % Mf;
+            const int64_t o = (int64_t)ry * Mf + cx;
+            t1 = fma(wx[a], fine[o].re, t1);
+            t2 = fma(wx[a], fine[MMf + o].re, t2);
+        }
+        s1 = fma(wy[b], t1, s1);
+        s2 = fma(wy[b], t2, s2);
+    }
+    up[i] = s1;
+    up[n + i] = s2;
+}
+
 /* (u.grad) u from u [2][n] and its gradient g [4][n] (du1/dx, du1/dy, du2/dx, du2/dy) */
 __global__ void advect_kernel(const double *__restrict__ u, const double *__restrict__ g, int64_t n,
                               double *__restrict__ out)

@@ -3092,12 +3092,64 @@ struct mhlp_box {
     int64_t part_cap = 0;
     double *sdc = nullptr; /* SISDC workspace */
     int64_t sdc_cap = 0;
+    int point_method = 1;  /* 0: direct type-2 sums, 1: non-uniform FFT */
+    cplx *twf = nullptr;   /* NUFFT: twiddles of the fine size 2M */
+    double *corr = nullptr; /* NUFFT: hf / psi^(k_j), coarse FFT order */
+    cplx *fine = nullptr;  /* NUFFT: [2][(2M)^2] */
     ~mhlp_box()
     {
-        for (void *q : {(void *)tw, (void *)spec, (void *)uh, (void *)part, (void *)sdc})
+        for (void *q : {(void *)tw, (void *)spec, (void *)uh, (void *)part, (void *)sdc, (void *)twf, (void *)corr,
+                        (void *)fine})
             if (q) (void)hipFree(q);
     }
 };
+
+/* NUFFT tables of the box: fine twiddles and the deconvolution factors
+   hf/psi^(k) with psi^(k) = (W hf/2) int_{-1}^{1} phi(z) cos(k W hf z/2) dz by
+   composite 32-point Gauss-Legendre quadrature on 16 panels */
+static mhlp_status box_nufft_setup(mhlp_box *B, hipStream_t st)
+{
+    if (B->fine) return MHLP_OK;
+    const int M = B->M, Mf = 2 * M;
+    const double hf = B->Lb / Mf, half = 0.5 * mhlp::NU_W * hf;
+    std::vector<cplx> twf(Mf / 2);
+    for (int j = 0; j < Mf / 2; ++j) {
+        const double a = 2.0 * PI * (double)j / (double)Mf;
+        twf[j] = mk(std::cos(a), -std::sin(a));
+    }
+    std::vector<double> corr(M);
+    for (int j = 0; j < M; ++j) {
+        const double k = 2.0 * PI / B->Lb * (j < M / 2 ? j : j - M);
+        double s = 0.0;
+        for (int pnl = 0; pnl < 16; ++pnl) {
+            const double a = -1.0 + pnl * 0.125, b = a + 0.125;
+            for (int q = 0; q < 32; ++q) {
+                const double z = 0.5 * (a + b) + 0.5 * (b - a) * GL32_T[q];
+                const double qz = 1.0 - z * z;
+                const double ph = qz > 0.0 ? std::exp(mhlp::NU_BETA * (std::sqrt(qz) - 1.0)) : 0.0;
+                s += 0.5 * (b - a) * GL32_W[q] * ph * std::cos(k * half * z);
+            }
+        }
+        corr[j] = hf / (half * s);
+    }
+    TRY(dalloc(&B->twf, Mf / 2));
+    TRY(dalloc(&B->corr, M));
+    TRY(dalloc(&B->fine, 2 * (int64_t)Mf * Mf));
+    hipError_t e = hipMemcpyAsync(B->twf, twf.data(), sizeof(cplx) * twf.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(B->corr, corr.data(), sizeof(double) * M, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(MHLP_HIP_ERROR, std::string("box NUFFT tables: ") + hipGetErrorString(e));
+    return MHLP_OK;
+}
+
+extern "C" mhlp_status mhlp_box_set_point_method(mhlp_box *B, int32_t method)
+{
+    if (!B) return fail(MHLP_INVALID_ARG, "box is NULL");
+    if (method != 0 && method != 1) return fail(MHLP_INVALID_ARG, "method must be 0 (direct) or 1 (NUFFT)");
+    if (method == 1 && B->M > 1024) return fail(MHLP_INVALID_ARG, "the NUFFT serves boxes with M <= 1024");
+    B->point_method = method;
+    return MHLP_OK;
+}
 
 extern "C" mhlp_status mhlp_box_create(int32_t M, double x0, double y0, double Lb, double alpha, void *stream,
                                        mhlp_box **out)
@@ -3114,6 +3166,7 @@ extern "C" mhlp_status mhlp_box_create(int32_t M, double x0, double y0, double L
     B->y0 = y0;
     B->Lb = Lb;
     B->alpha = alpha;
+    B->point_method = M <= 1024 ? 1 : 0;
     const int64_t MM = (int64_t)M * M;
     mhlp_status s;
     if ((s = dalloc(&B->tw, M / 2)) || (s = dalloc(&B->spec, 2 * MM)) || (s = dalloc(&B->uh, 6 * MM))) {
@@ -3159,7 +3212,17 @@ extern "C" mhlp_status mhlp_box_particular(mhlp_box *B, const double *F, double 
     fft2_fields(B, B->spec, 2, -1.0, st);
     mhlp::stokes_multiplier_kernel<<<nblocks(MM, 256), 256, 0, st>>>(B->spec, M, B->Lb, B->alpha, grad != nullptr,
                                                                      B->uh);
-    if (n > 0) {
+    if (n > 0 && B->point_method == 1) {
+        TRY(box_nufft_setup(B, st));
+        const int Mf = 2 * M;
+        const int64_t MMf = (int64_t)Mf * Mf;
+        mhlp::nufft_fine_spectrum_kernel<<<nblocks(2 * MMf, 256), 256, 0, st>>>(B->uh, M, Mf, B->corr, B->fine);
+        const size_t sh = sizeof(cplx) * 2 * (size_t)Mf;
+        mhlp::fft_lines_kernel<<<dim3(Mf, 2), Mf / 2, sh, st>>>(B->fine, Mf, 1, Mf, MMf, B->twf, 1.0);
+        mhlp::fft_lines_kernel<<<dim3(Mf, 2), Mf / 2, sh, st>>>(B->fine, Mf, Mf, 1, MMf, B->twf, 1.0);
+        mhlp::nufft_interp_kernel<<<nblocks(n, 128), 128, 0, st>>>(B->fine, Mf, B->Lb / Mf, B->x0, B->y0, px, py, n,
+                                                                  up);
+    } else if (n > 0) {
         const int nchunk = M / mhlp::FT2_R;
         const int64_t need = 2 * (int64_t)nchunk * n;
         if (need > B->part_cap) {

@@ -88,6 +88,7 @@ _SIGS = {
                          ctypes.POINTER(_V)], ctypes.c_int32),
     "mhlp_box_particular": ([_V, _V, _V, _V, ctypes.c_int64, _V, _V, _V, _V], ctypes.c_int32),
     "mhlp_box_destroy": ([_V], ctypes.c_int32),
+    "mhlp_box_set_point_method": ([_V, ctypes.c_int32], ctypes.c_int32),
     "mhlp_sisdc_step": ([_V, ctypes.c_double, ctypes.c_double, ctypes.c_int32, _V, _V, _V, _V], ctypes.c_int32),
     "mhlp_stokes_gmres_solve": ([_V, _V, _V, ctypes.POINTER(GmresOpts), ctypes.POINTER(GmresInfo), _V],
                                 ctypes.c_int32),
@@ -449,6 +450,10 @@ class Box:
                                           _dev(px, "px", n) if n else None, _dev(py, "py", n) if n else None,
                                           _dev(up, "up", 2 * n) if n else None, _stream()), "box_particular")
         return u, g, up
+
+    def set_point_method(self, method: int):
+        """0: direct type-2 sums; 1: non-uniform FFT (default for M <= 1024)."""
+        _check(load().mhlp_box_set_point_method(self._h, int(method)), "box_set_point_method")
 
     def sisdc_step(self, Re, dt, K, u, grad, lap):
         """One SISDC step of periodic Navier-Stokes in place on u [2][M][M], grad [4][M][M], lap [2][M][M]."""

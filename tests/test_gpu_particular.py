@@ -5,7 +5,8 @@ boundary values at the nodes + second-kind BIE + GMRES + double layer at the
 interior grid points) against a manufactured solution.
 
 Bars: grid values, gradient and point values 1e-12 relative to the largest
-oracle value; the implicit step 1e-9 relative to the solution's size (GMRES to
+oracle value (the non-uniform FFT's point values are ~1e-14 of sum |u^| from
+the exact sums, well inside it); the implicit step 1e-9 relative to the solution's size (GMRES to
 1e-12, the boundary discretisation resolved to ~1e-11).
 """
 import numpy as np
@@ -45,11 +46,14 @@ def _forcing(x0, y0, Lb, M, seed, nb=5, width=(0.08, 0.2)):
     return F, X, Y
 
 
+@pytest.mark.parametrize("method", [0, 1])
 @pytest.mark.parametrize("M,alpha", [(64, 3.0), (256, 20.0), (512, 300.0)])
-def test_particular_solution_vs_oracle(M, alpha):
+def test_particular_solution_vs_oracle(M, alpha, method):
+    # method 0: direct type-2 sums at the points; 1: the non-uniform FFT
     x0, y0, Lb = -1.6, -1.5, 3.1
     F, X, Y = _forcing(x0, y0, Lb, M, seed=M)
     box = mhlp.Box(M, x0, y0, Lb, alpha)
+    box.set_point_method(method)
     rng = np.random.default_rng(5)
     px, py = x0 + Lb * rng.uniform(0, 1, 333), y0 + Lb * rng.uniform(0, 1, 333)  # ragged against the blocks
     u, g, up = box.particular(_t(F), want_u=True, want_grad=True, px=_t(px), py=_t(py))
@@ -58,7 +62,7 @@ def test_particular_solution_vs_oracle(M, alpha):
     ref_g = np.stack([*PO.grid_gradient(u1h, Lb), *PO.grid_gradient(u2h, Lb)])
     ref_p = np.stack([PO.point_values(u1h, Lb, x0, y0, px, py), PO.point_values(u2h, Lb, x0, y0, px, py)])
     eu, eg, ep = _rel(u.cpu().numpy(), ref_u), _rel(g.cpu().numpy(), ref_g), _rel(up.cpu().numpy(), ref_p)
-    print(f"M={M} alpha={alpha}: u {eu:.2e} grad {eg:.2e} points {ep:.2e}")
+    print(f"M={M} alpha={alpha} method={method}: u {eu:.2e} grad {eg:.2e} points {ep:.2e}")
     assert eu < 1e-12 and eg < 1e-12 and ep < 1e-12
     # partial requests: points only, gradient only
     _, _, up2 = box.particular(_t(F), want_u=False, px=_t(px), py=_t(py))
@@ -131,6 +135,10 @@ def test_box_argument_errors():
         box.particular(_t(np.zeros((2, 32, 32))), want_u=False)  # nothing requested
     with pytest.raises(mhlp.MhlpError):
         box.particular(_t(np.zeros((2, 16, 16))))  # wrong size
+    with pytest.raises(mhlp.MhlpError):
+        box.set_point_method(2)
+    with pytest.raises(mhlp.MhlpError):
+        mhlp.Box(2048, 0.0, 0.0, 1.0, 1.0).set_point_method(1)  # the NUFFT serves M <= 1024
     # a constant forcing gives F/alpha^2 everywhere, also at points
     u, _, up = box.particular(_t(np.ones((2, 32, 32))), px=_t([0.3]), py=_t([0.9]))
     assert np.allclose(u.cpu().numpy(), 0.25, atol=1e-15) and np.allclose(up.cpu().numpy(), 0.25, atol=1e-15)
