@@ -121,7 +121,8 @@ mhlp_status mhlp_plan_info(const mhlp_plan *plan, int64_t *n_targets, int64_t *n
    256) plus the current value, reps timed launches each after one warm-up,
    with HIP events on `stream`, keeps the fewest splits within 1% of the
    fastest and reports it with its time (host outputs; cand/cand_ms receive up
-   to cap candidates and their ms per launch).
+   to cap candidates and their ms per launch).  A plan whose FP64 far field is
+   the FMM (mhlp_plan_set_fmm) has no splits to tune for layers 1-3 in FP64.
    Synchronises the stream.  Errors: MHLP_INVALID_ARG. */
 mhlp_status mhlp_plan_set_split(mhlp_plan *plan, int32_t nsplit);
 mhlp_status mhlp_plan_get_split(const mhlp_plan *plan, int32_t *nsplit);

@@ -2270,6 +2270,8 @@ extern "C" mhlp_status mhlp_plan_autotune(mhlp_plan *P, int32_t layers, int32_t 
 {
     if (!P) return fail(MHLP_INVALID_ARG, "plan is NULL");
     if (layers < 1 || layers > 7) return fail(MHLP_INVALID_ARG, "layers must be 1 to 7");
+    if (P->fmm && layers <= 3 && precision == MHLP_FP64)
+        return fail(MHLP_INVALID_ARG, "the plan's FP64 far field is the FMM (no source splits); turn it off to tune");
     if ((layers >= 6) != P->stokes) return fail(MHLP_INVALID_ARG, "layers 6 and 7 (and only they) tune a stokes plan");
     if (layers >= 6 && precision != MHLP_FP64) return fail(MHLP_INVALID_ARG, "the stresslet is FP64 only");
     if (layers == 7 && P->onsurf) return fail(MHLP_INVALID_ARG, "layers 7 (stresslet gradient) needs an off-surface plan");
@@ -3132,13 +3134,26 @@ static mhlp_status box_nufft_setup(mhlp_box *B, hipStream_t st)
         }
         corr[j] = hf / (half * s);
     }
-    TRY(dalloc(&B->twf, Mf / 2));
-    TRY(dalloc(&B->corr, M));
-    TRY(dalloc(&B->fine, 2 * (int64_t)Mf * Mf));
-    hipError_t e = hipMemcpyAsync(B->twf, twf.data(), sizeof(cplx) * twf.size(), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(B->corr, corr.data(), sizeof(double) * M, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return fail(MHLP_HIP_ERROR, std::string("box NUFFT tables: ") + hipGetErrorString(e));
+    cplx *d_twf = nullptr, *d_fine = nullptr;
+    double *d_corr = nullptr;
+    mhlp_status s = dalloc(&d_twf, Mf / 2);
+    if (s == MHLP_OK) s = dalloc(&d_corr, M);
+    if (s == MHLP_OK) s = dalloc(&d_fine, 2 * (int64_t)Mf * Mf);
+    hipError_t e = hipSuccess;
+    if (s == MHLP_OK) {
+        e = hipMemcpyAsync(d_twf, twf.data(), sizeof(cplx) * twf.size(), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(d_corr, corr.data(), sizeof(double) * M, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) s = fail(MHLP_HIP_ERROR, std::string("box NUFFT tables: ") + hipGetErrorString(e));
+    }
+    if (s != MHLP_OK) { /* nothing half-built stays behind */
+        for (void *q : {(void *)d_twf, (void *)d_corr, (void *)d_fine})
+            if (q) (void)hipFree(q);
+        return s;
+    }
+    B->twf = d_twf;
+    B->corr = d_corr;
+    B->fine = d_fine;
     return MHLP_OK;
 }
 
@@ -3309,7 +3324,7 @@ extern "C" mhlp_status mhlp_sisdc_step(mhlp_box *B, double Re, double dt, int32_
     if (std::fabs(B->alpha * B->alpha - a2) > 1e-12 * a2)
         return fail(MHLP_INVALID_ARG, "the box's alpha must satisfy alpha^2 = Re K'/dt, K' = K - 1 substeps");
     hipStream_t st = (hipStream_t)stream;
-    const int64_t n2 = 2 * (int64_t)B->M * B->M, n4 = 2 * n2;
+    const int64_t n2 = 2 * (int64_t)B->M * B->M;
     /* workspace: N, L of the previous sweep, U, N, L of the new one (p + 1 each), F */
     const int64_t need = (5 * (int64_t)(p + 1) + 1) * n2;
     if (need > B->sdc_cap) {
@@ -3368,7 +3383,6 @@ extern "C" mhlp_status mhlp_sisdc_step(mhlp_box *B, double Re, double dt, int32_
     }
     HIPCHECK(hipMemcpyAsync(u, Un[p], sizeof(double) * n2, hipMemcpyDeviceToDevice, st));
     HIPCHECK(hipMemcpyAsync(lap, Ln[p], sizeof(double) * n2, hipMemcpyDeviceToDevice, st));
-    (void)n4;
     HIPCHECK(hipGetLastError());
     return MHLP_OK;
 }

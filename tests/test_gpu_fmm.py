@@ -121,6 +121,10 @@ def test_plan_fmm_layer_potentials_vs_oracle(alpha):
     assert none is None and _rel(s_only.cpu().numpy(), fs.cpu().numpy()) < 1e-14
     P.set_fmm(0)
     assert P.fmm == (0, -1)
+    P.set_fmm(20)
+    with pytest.raises(mhlp.MhlpError):
+        P.autotune(layers=3)  # the FMM has no source splits to tune
+    P.set_fmm(0)
     ds2, _ = mhlp.eval_layer(P, sigma=_t(sigma))
     assert _rel(ds2.cpu().numpy(), ds.cpu().numpy()) == 0.0
 
