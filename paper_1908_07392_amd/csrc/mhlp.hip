@@ -535,7 +535,8 @@ __global__ __launch_bounds__(FT_THREADS) void far_eval_fp64(FarArgs A)
             ly[threadIdx.x] = A.sy[j];
             if (SLP) lq[threadIdx.x] = wj * A.sigma[j];
             if (DLP) {
-                const double m = wj * mu[j];
+                /* alpha goes with the dipole: the pair evaluates K1(z)/r */
+                const double m = (A.alpha * wj) * mu[j];
                 ldx[threadIdx.x] = m * A.snx[j];
                 ldy[threadIdx.x] = m * A.sny[j];
             }
@@ -556,7 +557,7 @@ __global__ __launch_bounds__(FT_THREADS) void far_eval_fp64(FarArgs A)
                 const double ex0 = x - lx[l0], ey0 = y - ly[l0];
                 const double ex1 = x - lx[l1], ey1 = y - ly[l1];
                 K01 o0, o1;
-                k01_far2<SLP, DLP>(T, fc, fma(ex0, ex0, ey0 * ey0), fma(ex1, ex1, ey1 * ey1), o0, o1);
+                k01_far2<SLP, DLP, true, true>(T, fc, fma(ex0, ex0, ey0 * ey0), fma(ex1, ex1, ey1 * ey1), o0, o1);
                 if (SLP) accs = fma(o1.k0, lq[l1], fma(o0.k0, lq[l0], accs));
                 if (DLP)
                     accd = fma(o1.ak1r, fma(ex1, ldx[l1], ey1 * ldy[l1]),
@@ -3543,7 +3544,7 @@ __global__ __launch_bounds__(FT_THREADS) void batch_far_dlp(const BatchGeo *__re
             const double nxj = geo.nx[j], nyj = geo.ny[j];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const double m = wj * mug[r * geo.N + j];
+                const double m = (geo.alpha * wj) * mug[r * geo.N + j]; /* the pair gives K1(z)/r */
                 ldx[r][threadIdx.x] = m * nxj;
                 ldy[r][threadIdx.x] = m * nyj;
             }
@@ -3564,7 +3565,7 @@ __global__ __launch_bounds__(FT_THREADS) void batch_far_dlp(const BatchGeo *__re
                 const double ex0 = x - lx[l0], ey0 = y - ly[l0];
                 const double ex1 = x - lx[l1], ey1 = y - ly[l1];
                 K01 o0, o1;
-                k01_far2<false, true>(T, fc, fma(ex0, ex0, ey0 * ey0), fma(ex1, ex1, ey1 * ey1), o0, o1);
+                k01_far2<false, true, true, true>(T, fc, fma(ex0, ex0, ey0 * ey0), fma(ex1, ex1, ey1 * ey1), o0, o1);
 #pragma unroll
                 for (int r = 0; r < R; ++r)
                     acc[r] = fma(o1.ak1r, fma(ex1, ldx[r][l1], ey1 * ldy[r][l1]),

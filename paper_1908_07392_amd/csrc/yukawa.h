@@ -215,23 +215,30 @@ __device__ __forceinline__ double lean_log01(FarTab T, double q)
    the lanes that need it, overwriting the other values. */
 struct FarConst {
     double a, a2q, a4, ia; /* alpha, alpha^2/4, 4/alpha, 1/alpha */
+    double vf, vn;         /* 12/alpha, 6/alpha: piece variables from 1/r */
+    double kf, kn;         /* 12/alpha^2, 6/alpha^2: (4/alpha^2) dv/du     */
+    double ha;             /* 1/(2 alpha) */
 };
 
 __device__ __forceinline__ FarConst far_const(double alpha)
 {
-    return FarConst{alpha, 0.25 * alpha * alpha, 4.0 / alpha, 1.0 / alpha};
+    const double ia = 1.0 / alpha;
+    return FarConst{alpha, 0.25 * alpha * alpha, 4.0 / alpha, ia,
+                    12.0 * ia, 6.0 * ia, 12.0 * ia * ia, 6.0 * ia * ia, 0.5 * ia};
 }
 
-/* polynomial of the piece (value and d/du) at 1/r = ri */
-template <bool SLP, bool DLP, bool FAR>
+/* polynomial of the piece (value and d/du) at 1/r = ri.  K1R: the derivative
+   comes back as (4/alpha^2) dP/du, the form far_finish<.., K1R> takes. */
+template <bool SLP, bool DLP, bool FAR, bool K1R = false>
 __device__ __forceinline__ double far_piece(FarTab T, const FarConst &c, double ri, double &dpdu)
 {
     /* v = 3u + 2 = (12/alpha) ri - 1 (far);  v = 1.5u - 0.5 = (6/alpha) ri - 2 (near) */
-    const double v = FAR ? fma(3.0 * c.a4, ri, -1.0) : fma(1.5 * c.a4, ri, -2.0);
+    const double v = K1R ? (FAR ? fma(c.vf, ri, -1.0) : fma(c.vn, ri, -2.0))
+                         : (FAR ? fma(3.0 * c.a4, ri, -1.0) : fma(1.5 * c.a4, ri, -2.0));
     if (SLP && DLP) {
         double d;
         const double p = FAR ? hornercd<16>(T->kp0f, v, d) : hornercd<17>(T->kp0n, v, d);
-        dpdu = d * (FAR ? 3.0 : 1.5);
+        dpdu = K1R ? d * (FAR ? c.kf : c.kn) : d * (FAR ? 3.0 : 1.5);
         return p;
     }
     dpdu = 0.0;
@@ -239,42 +246,53 @@ __device__ __forceinline__ double far_piece(FarTab T, const FarConst &c, double 
     return FAR ? hornerc<14>(T->kp1f, v) : hornerc<15>(T->kp1n, v);
 }
 
-template <bool SLP, bool DLP>
+/* K1R = false: out.ak1r = alpha K1(z)/r.  K1R = true: out.ak1r = K1(z)/r (the
+   caller scales its dipoles by alpha), with K1/E = P + (1/z)(P/2 + (4/z) dP/du)
+   written as P + ri (P/(2 alpha) + ri (4/alpha^2) dP/du). */
+template <bool SLP, bool DLP, bool K1R = false>
 __device__ __forceinline__ K01 far_finish(const FarConst &c, double ri, double z, double e, double p, double dpdu)
 {
     K01 o{0.0, 0.0, ri * ri};
     if (SLP && DLP) {
         o.k0 = e * p;
-        const double iz = c.ia * ri; /* 1/z */
-        const double k1 = e * fma(4.0 * iz * iz, dpdu, p * fma(0.5, iz, 1.0));
-        o.ak1r = c.a * k1 * ri;
+        if (K1R) {
+            const double g = fma(p, c.ha, ri * dpdu);
+            o.ak1r = (e * ri) * fma(ri, g, p);
+        } else {
+            const double iz = c.ia * ri; /* 1/z */
+            const double k1 = e * fma(4.0 * iz * iz, dpdu, p * fma(0.5, iz, 1.0));
+            o.ak1r = c.a * k1 * ri;
+        }
     } else if (SLP) {
         o.k0 = e * p;
     } else {
-        o.ak1r = c.a * e * p * ri;
+        o.ak1r = K1R ? e * p * ri : c.a * e * p * ri;
     }
     (void)z;
     return o;
 }
 
-template <bool SLP, bool DLP>
-__device__ __forceinline__ K01 k01_far_small(FarTab T, double r2, double a2q)
+/* z <= 2.  K1R: out.ak1r = K1(z)/r, from 1/(alpha r^2) in place of 1/r^2
+   (out.ri2 then holds 1/(alpha r^2): K1R callers use k0 and ak1r only). */
+template <bool SLP, bool DLP, bool K1R = false>
+__device__ __forceinline__ K01 k01_far_small(FarTab T, double r2, const FarConst &c)
 {
-    K01 o{0.0, 0.0, lean_rcp(r2)};
-    const double q = a2q * r2; /* z^2/4 */
+    K01 o{0.0, 0.0, lean_rcp(K1R ? c.a * r2 : r2)};
+    const double q = c.a2q * r2; /* z^2/4 */
     const double lq = lean_log01(T, q); /* 2 log(z/2) */
+    const double s = K1R ? c.a : 4.0 * c.a2q; /* alpha^2, over alpha with K1R */
     if (SLP && DLP) {
         double di0, dr0;
         const double i0 = hornercd<12>(T->ks_i0, q, di0);
         const double r0 = hornercd<13>(T->ks_r0, q, dr0);
         o.k0 = fma(-0.5 * lq, i0, r0);
         /* alpha^2 K1/z = I0/r^2 + alpha^2 (lq I0'/4 - R0'/2) */
-        o.ak1r = fma(4.0 * a2q, fma(0.25 * lq, di0, -0.5 * dr0), i0 * o.ri2);
+        o.ak1r = fma(s, fma(0.25 * lq, di0, -0.5 * dr0), i0 * o.ri2);
     } else if (SLP) {
         o.k0 = fma(-0.5 * lq, hornerc<12>(T->ks_i0, q), hornerc<13>(T->ks_r0, q));
     } else {
         const double t = fma(0.5 * lq, hornerc<12>(T->ks_i1z, q), -0.25 * hornerc<13>(T->ks_r1, q));
-        o.ak1r = fma(4.0 * a2q, t, o.ri2);
+        o.ak1r = fma(s, t, o.ri2);
     }
     return o;
 }
@@ -282,7 +300,7 @@ __device__ __forceinline__ K01 k01_far_small(FarTab T, double r2, double a2q)
 /* PIECES = false (K0 only): one degree-22 fit over all z > 2 in u = 4/z - 1,
    for launches whose lanes often straddle z = 6 (targets in no spatial order) */
 /* the z > 2 forms for two sources, straight-line (see k01_far2) */
-template <bool SLP, bool DLP, bool PIECES = true>
+template <bool SLP, bool DLP, bool PIECES = true, bool K1R = false>
 __device__ __forceinline__ void k01_far2_big(FarTab T, const FarConst &c, double r2a, double r2b, K01 &oa, K01 &ob)
 {
     static_assert(PIECES || (SLP && !DLP), "the single fit serves the single layer only");
@@ -295,35 +313,35 @@ __device__ __forceinline__ void k01_far2_big(FarTab T, const FarConst &c, double
         pa = hornerc<23>(T->kl0, fma(c.a4, ria, -1.0));
         pb = hornerc<23>(T->kl0, fma(c.a4, rib, -1.0));
     } else if (fa && fb) {
-        pa = far_piece<SLP, DLP, true>(T, c, ria, da);
-        pb = far_piece<SLP, DLP, true>(T, c, rib, db);
+        pa = far_piece<SLP, DLP, true, K1R>(T, c, ria, da);
+        pb = far_piece<SLP, DLP, true, K1R>(T, c, rib, db);
     } else if (!fa && !fb) {
-        pa = far_piece<SLP, DLP, false>(T, c, ria, da);
-        pb = far_piece<SLP, DLP, false>(T, c, rib, db);
+        pa = far_piece<SLP, DLP, false, K1R>(T, c, ria, da);
+        pb = far_piece<SLP, DLP, false, K1R>(T, c, rib, db);
     } else {
         if (fa)
-            pa = far_piece<SLP, DLP, true>(T, c, ria, da);
+            pa = far_piece<SLP, DLP, true, K1R>(T, c, ria, da);
         else
-            pa = far_piece<SLP, DLP, false>(T, c, ria, da);
+            pa = far_piece<SLP, DLP, false, K1R>(T, c, ria, da);
         if (fb)
-            pb = far_piece<SLP, DLP, true>(T, c, rib, db);
+            pb = far_piece<SLP, DLP, true, K1R>(T, c, rib, db);
         else
-            pb = far_piece<SLP, DLP, false>(T, c, rib, db);
+            pb = far_piece<SLP, DLP, false, K1R>(T, c, rib, db);
     }
-    oa = far_finish<SLP, DLP>(c, ria, za, ea, pa, da);
-    ob = far_finish<SLP, DLP>(c, rib, zb, eb, pb, db);
+    oa = far_finish<SLP, DLP, K1R>(c, ria, za, ea, pa, da);
+    ob = far_finish<SLP, DLP, K1R>(c, rib, zb, eb, pb, db);
 }
 
 /* PIECES = false (K0 only): one degree-22 fit over all z > 2 in u = 4/z - 1,
    for launches whose lanes often straddle z = 6 (targets in no spatial order) */
-template <bool SLP, bool DLP, bool PIECES = true>
+template <bool SLP, bool DLP, bool PIECES = true, bool K1R = false>
 __device__ __forceinline__ void k01_far2(FarTab T, const FarConst &c, double r2a, double r2b, K01 &oa, K01 &ob)
 {
     const bool sa = c.a2q * r2a <= 1.0, sb = c.a2q * r2b <= 1.0;
-    if (!(sa && sb)) k01_far2_big<SLP, DLP, PIECES>(T, c, r2a, r2b, oa, ob);
+    if (!(sa && sb)) k01_far2_big<SLP, DLP, PIECES, K1R>(T, c, r2a, r2b, oa, ob);
     if (sa || sb) {
-        if (sa) oa = k01_far_small<SLP, DLP>(T, r2a, c.a2q);
-        if (sb) ob = k01_far_small<SLP, DLP>(T, r2b, c.a2q);
+        if (sa) oa = k01_far_small<SLP, DLP, K1R>(T, r2a, c);
+        if (sb) ob = k01_far_small<SLP, DLP, K1R>(T, r2b, c);
     }
 }
 
