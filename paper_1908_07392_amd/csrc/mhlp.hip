@@ -134,7 +134,7 @@ struct mhlp_plan {
         hipGraphExec_t exec = nullptr;
         const void *ws = nullptr, *part = nullptr, *gdev = nullptr;
         int R = 0, nsplit = 0, S = 0;
-    } graphs[2][4]; /* [precision][chunk length 1, 2, 4, 8] */
+    } graphs[2][2][4]; /* [precision][Gram-Schmidt in one block, over slices][chunk length 1, 2, 4, 8] */
 };
 
 /* ------------------------------------------------------------------------ */
@@ -490,19 +490,53 @@ __device__ __forceinline__ void far_epilogue(const FarArgs &A, const double *__r
     }
 }
 
-/* Sum of the source-split partials in fixed order, then the epilogue. */
+/* Sum of the source-split partials, near corrections, 1/(2 pi) scaling and
+   identity term.  A block takes FZ_TG consecutive targets with FZ_L lanes
+   each (lane l is wave l, so every partial load is a coalesced row segment):
+   lane l adds the partials l, l + FZ_L, ... and the correction terms of node l
+   of each near panel; the lane sums are then added in lane order. */
+constexpr int FZ_TG = 64, FZ_L = 16;
+
 template <bool SLP, bool DLP>
-__global__ void far_finalize(FarArgs A, int nsplit)
+__global__ __launch_bounds__(FZ_TG *FZ_L) void far_finalize(FarArgs A, int nsplit)
 {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    __shared__ double red[4][FZ_L][FZ_TG]; /* far S, near S, far D, near D */
     const double *mu;
-    if (i >= A.M || !far_density(A, mu)) return;
-    double s_ = 0.0, d_ = 0.0;
-    for (int k = 0; k < nsplit; ++k) {
-        if (SLP) s_ += A.part_s[k * A.M + i];
-        if (DLP) d_ += A.part_d[k * A.M + i];
+    if (!far_density(A, mu)) return; /* the same for every thread of the launch */
+    const int g = threadIdx.x % FZ_TG, l = threadIdx.x / FZ_TG;
+    const int64_t i = blockIdx.x * (int64_t)FZ_TG + g;
+    double fs = 0.0, ns = 0.0, fd = 0.0, nd = 0.0;
+    if (i < A.M) {
+        for (int k = l; k < nsplit; k += FZ_L) {
+            if (SLP) fs += A.part_s[k * A.M + i];
+            if (DLP) fd += A.part_d[k * A.M + i];
+        }
+        for (int32_t q = A.nptr[i]; q < A.nptr[i + 1]; ++q) {
+            const int64_t p = A.npan[q];
+            if (p < 0) continue;
+            if (SLP) ns = fma(A.wsl[16 * (int64_t)q + l], A.sigma[16 * p + l], ns);
+            if (DLP) nd = fma(A.wdl[16 * (int64_t)q + l], mu[16 * p + l], nd);
+        }
     }
-    far_epilogue<SLP, DLP>(A, mu, i, s_, d_);
+    red[0][l][g] = fs;
+    red[1][l][g] = ns;
+    red[2][l][g] = fd;
+    red[3][l][g] = nd;
+    __syncthreads();
+    if (l != 0 || i >= A.M) return;
+    for (int q = 1; q < FZ_L; ++q) {
+        fs += red[0][q][g];
+        ns += red[1][q][g];
+        fd += red[2][q][g];
+        nd += red[3][q][g];
+    }
+    const int64_t o = A.perm ? (int64_t)A.perm[i] : i;
+    if (SLP) A.us[o] = fma(INV_2PI, fs, ns);
+    if (DLP) {
+        double v = fma(INV_2PI, fd, nd);
+        if (A.half_term != 0.0) v = fma(A.half_term, mu[i], v);
+        A.ud[o] = v;
+    }
 }
 
 template <bool SLP, bool DLP, bool SPLIT>
@@ -1263,92 +1297,50 @@ __global__ void residual_kernel(const double *__restrict__ g, const double *__re
 }
 
 /* ---- device-driven GMRES steps (every kernel does nothing once done) ---- */
-/* h[c] = V_c . w for c <= j; one block per column, blocks beyond j exit */
-__global__ __launch_bounds__(256) void gs_dot_kernel(const GState *__restrict__ gs, const double *__restrict__ V,
-                                                     int64_t ld, const double *__restrict__ w, int64_t N,
-                                                     double *__restrict__ h)
-{
-    if (gs->done || (int)blockIdx.x > gs->j) return;
-    __shared__ double red[256];
-    const double *v = V + (int64_t)blockIdx.x * ld;
-    double s = 0.0;
-    for (int64_t i = threadIdx.x; i < N; i += 256) s = fma(v[i], w[i], s);
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) h[blockIdx.x] = red[0];
-}
-
-/* w -= sum_{c<=j} h[c] V_c */
-__global__ void gs_sub_kernel(const GState *__restrict__ gs, const double *__restrict__ V, int64_t ld,
-                              const double *__restrict__ h, double *__restrict__ w, int64_t N)
-{
-    if (gs->done) return;
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const int ncol = gs->j + 1;
-    double v = w[i];
-    for (int c = 0; c < ncol; ++c) v = fma(-h[c], V[c * ld + i], v);
-    w[i] = v;
-}
-
-/* hn = w . w (one block) */
-__global__ __launch_bounds__(256) void gs_norm_kernel(const GState *__restrict__ gs, const double *__restrict__ w,
-                                                      int64_t N, double *__restrict__ hn)
-{
-    if (gs->done) return;
-    __shared__ double red[256];
-    double s = 0.0;
-    for (int64_t i = threadIdx.x; i < N; i += 256) s = fma(w[i], w[i], s);
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) hn[0] = red[0];
-}
-
-/* Column j of the Hessenberg matrix (CGS2 coefficients h1 + h2, subdiagonal
-   ||w||), the earlier Givens rotations applied to it, a new rotation that
-   zeroes the subdiagonal, the rotated right-hand side g and the stopping
-   decision.  H is (R+1) x R row-major.  One thread. */
-__device__ void gs_finish_body(GState *__restrict__ gs, double *__restrict__ H, int R, double *__restrict__ cs,
-                               double *__restrict__ sn, double *__restrict__ gv, const double *__restrict__ h1,
-                               const double *__restrict__ h2, const double *__restrict__ hn)
+/* Column k = j of the Hessenberg matrix (CGS2 coefficients h1 + h2,
+   subdiagonal ||w|| = sqrt(hnsq)), the earlier Givens rotations applied to it,
+   a new rotation that zeroes the subdiagonal, the rotated right-hand side g
+   and the stopping decision.  H is (R+1) x R row-major.  Called by every
+   thread of one block: the column and the rotations are staged in LDS (col:
+   R + 2 values, rot: 2R) by all threads, the rotations run on thread 0, and
+   the column is written back by all threads. */
+__device__ void gs_finish_block(GState *__restrict__ gs, double *__restrict__ H, int R, double *__restrict__ cs,
+                                double *__restrict__ sn, double *__restrict__ gv, const double *__restrict__ h1,
+                                const double *__restrict__ h2, double hnsq, double *col, double *rot)
 {
     const int k = gs->j;
-    for (int j = 0; j <= k; ++j) H[(int64_t)j * R + k] = h1[j] + h2[j];
-    const double hn1 = sqrt(hn[0]);
-    H[(int64_t)(k + 1) * R + k] = hn1;
-    for (int j = 0; j < k; ++j) {
-        const double a = H[(int64_t)j * R + k], c = H[(int64_t)(j + 1) * R + k];
-        H[(int64_t)j * R + k] = cs[j] * a + sn[j] * c;
-        H[(int64_t)(j + 1) * R + k] = -sn[j] * a + cs[j] * c;
+    for (int c = threadIdx.x; c <= k; c += blockDim.x) {
+        col[c] = h1[c] + h2[c];
+        if (c < k) {
+            rot[2 * c] = cs[c];
+            rot[2 * c + 1] = sn[c];
+        }
     }
-    const double a = H[(int64_t)k * R + k], c = H[(int64_t)(k + 1) * R + k];
-    const double den = hypot(a, c);
-    cs[k] = a / den;
-    sn[k] = c / den;
-    H[(int64_t)k * R + k] = den;
-    H[(int64_t)(k + 1) * R + k] = 0.0;
-    gv[k + 1] = -sn[k] * gv[k];
-    gv[k] = cs[k] * gv[k];
-    gs->steps = k + 1;
-    gs->resest = fabs(gv[k + 1]);
-    gs->inv = hn1 > 0.0 ? 1.0 / hn1 : 0.0;
-    if (gs->resest <= gs->thresh || hn1 == 0.0 || k + 1 >= gs->kmax) gs->done = 1;
-}
-
-__global__ void gs_finish_kernel(GState *__restrict__ gs, double *__restrict__ H, int R, double *__restrict__ cs,
-                                 double *__restrict__ sn, double *__restrict__ gv, const double *__restrict__ h1,
-                                 const double *__restrict__ h2, const double *__restrict__ hn)
-{
-    if (threadIdx.x != 0 || blockIdx.x != 0 || gs->done) return;
-    gs_finish_body(gs, H, R, cs, sn, gv, h1, h2, hn);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double hn1 = sqrt(hnsq);
+        col[k + 1] = hn1;
+        for (int j = 0; j < k; ++j) {
+            const double a = col[j], c = col[j + 1];
+            col[j] = rot[2 * j] * a + rot[2 * j + 1] * c;
+            col[j + 1] = -rot[2 * j + 1] * a + rot[2 * j] * c;
+        }
+        const double a = col[k], c = col[k + 1];
+        const double den = hypot(a, c);
+        const double ck = a / den, sk = c / den;
+        cs[k] = ck;
+        sn[k] = sk;
+        col[k] = den;
+        col[k + 1] = 0.0;
+        gv[k + 1] = -sk * gv[k];
+        gv[k] = ck * gv[k];
+        gs->steps = k + 1;
+        gs->resest = fabs(gv[k + 1]);
+        gs->inv = hn1 > 0.0 ? 1.0 / hn1 : 0.0;
+        if (gs->resest <= gs->thresh || hn1 == 0.0 || k + 1 >= gs->kmax) gs->done = 1;
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c <= k + 1; c += blockDim.x) H[(int64_t)c * R + k] = col[c];
 }
 
 /* The whole Gram-Schmidt part of an Arnoldi step in one block (small N):
@@ -1357,6 +1349,11 @@ __global__ void gs_finish_kernel(GState *__restrict__ gs, double *__restrict__ H
    thread sums its strided elements, waves reduce by a fixed butterfly, the
    wave sums are added in wave order. */
 constexpr int GSF_T = 1024, GSF_W = GSF_T / 64, GSF_RMAX = 256;
+/* the one-block form serves vectors up to GSF_NMAX long for the first
+   GSF_STEPS Arnoldi steps of a cycle: its cost grows with the number of basis
+   columns, while the slice form below costs a few short launches per step */
+constexpr int64_t GSF_NMAX = 4096;
+constexpr int GSF_STEPS = 3;
 
 __device__ __forceinline__ double gsf_wave_sum(double v)
 {
@@ -1394,8 +1391,7 @@ __global__ __launch_bounds__(GSF_T) void gs_fused_kernel(GState *__restrict__ gs
     __shared__ double red[GSF_W][GSF_RMAX];
     __shared__ double hs[2][GSF_RMAX];
     __shared__ double nrm[GSF_W], hnl[1];
-    __shared__ int done_after;
-    __shared__ double inv;
+    __shared__ double col[GSF_RMAX + 2], rot[2 * GSF_RMAX];
     if (gs->done) return; /* the whole block */
     const int t = threadIdx.x;
     const int j = gs->j, ncol = j + 1;
@@ -1418,28 +1414,127 @@ __global__ __launch_bounds__(GSF_T) void gs_fused_kernel(GState *__restrict__ gs
         double s2 = nrm[0];
         for (int q = 1; q < GSF_W; ++q) s2 += nrm[q];
         hnl[0] = s2;
-        gs_finish_body(gs, H, R, cs, sn, gv, hs[0], hs[1], hnl);
-        done_after = gs->done;
-        inv = gs->inv;
     }
     __syncthreads();
-    if (done_after) return;
+    gs_finish_block(gs, H, R, cs, sn, gv, hs[0], hs[1], hnl[0], col, rot);
+    if (gs->done) return; /* written by thread 0 before the block's last barrier */
+    const double inv = gs->inv;
     for (int64_t i = t; i < N; i += GSF_T) V[(int64_t)(j + 1) * ld + i] = inv * w[i];
+    __syncthreads(); /* every thread has read gs->j and gs->done */
     if (t == 0) gs->j = j + 1;
 }
 
-/* V_{j+1} = w / h_{j+1,j} */
-__global__ void gs_scale_kernel(const GState *__restrict__ gs, const double *__restrict__ w, double *__restrict__ V,
-                                int64_t ld, int64_t N)
+/* The Gram-Schmidt part of an Arnoldi step over many blocks (CGS2), for
+   vectors too long for one block.  Block b owns the element slice
+   [b L, (b+1) L); a pass leaves one partial dot product per (block, column)
+   in P[b][c] (row stride pld), and the next kernel adds the partials in
+   block order, so no result depends on timing.  Column c of a slice's dot
+   products is summed by wave c % GSM_W. */
+constexpr int GSM_T = 256, GSM_W = GSM_T / 64, GSM_NBMAX = 128, GSM_HMAX = 520;
+
+
+/* slice length: a multiple of GSM_T giving at most GSM_NBMAX blocks */
+static int64_t gsm_slice(int64_t N)
 {
-    if (gs->done) return;
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < N) V[(int64_t)(gs->j + 1) * ld + i] = gs->inv * w[i];
+    const int64_t per = (N + (int64_t)GSM_T * GSM_NBMAX - 1) / ((int64_t)GSM_T * GSM_NBMAX);
+    return GSM_T * std::max<int64_t>(1, per);
 }
 
-__global__ void gs_advance_kernel(GState *__restrict__ gs)
+__device__ void gsm_partial_dots(const double *__restrict__ V, int64_t ld, const double *__restrict__ w, int64_t i0,
+                                 int64_t n, int ncol, double *__restrict__ Prow)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0 && !gs->done) gs->j += 1;
+    const int t = threadIdx.x, wv = t >> 6, ln = t & 63;
+    for (int c = wv; c < ncol; c += GSM_W) {
+        const double *v = V + (int64_t)c * ld + i0;
+        double sacc = 0.0;
+        for (int64_t e = ln; e < n; e += 64) sacc = fma(v[e], w[i0 + e], sacc);
+        sacc = gsf_wave_sum(sacc);
+        if (ln == 0) Prow[c] = sacc;
+    }
+}
+
+/* first pass: P[b][c] = V_c . w over slice b, c <= j */
+__global__ __launch_bounds__(GSM_T) void gsm_dot_kernel(const GState *__restrict__ gs, const double *__restrict__ V,
+                                                        int64_t ld, const double *__restrict__ w, int64_t N,
+                                                        int64_t L, double *__restrict__ P, int pld)
+{
+    if (gs->done) return;
+    const int64_t i0 = blockIdx.x * L;
+    gsm_partial_dots(V, ld, w, i0, min(L, N - i0), gs->j + 1, P + (int64_t)blockIdx.x * pld);
+}
+
+/* h = sum_b Pin[b] (block 0 also stores it in hout); w -= sum_c h_c V_c on
+   the slice; then either the partial dots of the new w (NORM = false, into
+   Pout[b][c]) or its partial squared norm (NORM = true, into Pout[b]). */
+template <bool NORM>
+__global__ __launch_bounds__(GSM_T) void gsm_sub_kernel(const GState *__restrict__ gs, const double *__restrict__ V,
+                                                        int64_t ld, double *__restrict__ w, int64_t N, int64_t L,
+                                                        const double *__restrict__ Pin, int nb, int pld,
+                                                        double *__restrict__ hout, double *__restrict__ Pout)
+{
+    __shared__ double hl[GSM_HMAX];
+    __shared__ double red[GSM_W];
+    if (gs->done) return;
+    const int t = threadIdx.x;
+    const int ncol = gs->j + 1;
+    for (int c = t; c < ncol; c += GSM_T) {
+        double h = Pin[c];
+        for (int b = 1; b < nb; ++b) h += Pin[(int64_t)b * pld + c];
+        hl[c] = h;
+        if (blockIdx.x == 0) hout[c] = h;
+    }
+    __syncthreads();
+    const int64_t i0 = blockIdx.x * L, n = min(L, N - i0);
+    double sq = 0.0;
+    for (int64_t e = t; e < n; e += GSM_T) {
+        const int64_t i = i0 + e;
+        double v = w[i];
+        for (int c = 0; c < ncol; ++c) v = fma(-hl[c], V[(int64_t)c * ld + i], v);
+        w[i] = v;
+        sq = fma(v, v, sq);
+    }
+    if (NORM) {
+        sq = gsf_wave_sum(sq);
+        if ((t & 63) == 0) red[t >> 6] = sq;
+        __syncthreads();
+        if (t == 0) {
+            double s2 = red[0];
+            for (int q = 1; q < GSM_W; ++q) s2 += red[q];
+            Pout[blockIdx.x] = s2;
+        }
+    } else {
+        __syncthreads(); /* the slice of w, written above, is read across waves */
+        gsm_partial_dots(V, ld, w, i0, n, ncol, Pout + (int64_t)blockIdx.x * pld);
+    }
+}
+
+/* ||w||^2 from the slice partials (block order), the Hessenberg column, then
+   V_{j+1} = w / ||w|| and the advance; one block */
+__global__ __launch_bounds__(GSF_T) void gsm_finish_kernel(GState *__restrict__ gs, double *__restrict__ V,
+                                                           int64_t ld, const double *__restrict__ w, int64_t N,
+                                                           const double *__restrict__ Pn, int nb,
+                                                           double *__restrict__ H, int R, double *__restrict__ cs,
+                                                           double *__restrict__ sn, double *__restrict__ gv,
+                                                           const double *__restrict__ h1,
+                                                           const double *__restrict__ h2)
+{
+    __shared__ double col[GSM_HMAX + 2], rot[2 * GSM_HMAX];
+    __shared__ double hn;
+    if (gs->done) return;
+    const int t = threadIdx.x;
+    const int j = gs->j;
+    if (t == 0) {
+        double s2 = Pn[0];
+        for (int b = 1; b < nb; ++b) s2 += Pn[b];
+        hn = s2;
+    }
+    __syncthreads();
+    gs_finish_block(gs, H, R, cs, sn, gv, h1, h2, hn, col, rot);
+    if (gs->done) return; /* written by thread 0 before the block's last barrier */
+    const double inv = gs->inv;
+    for (int64_t i = t; i < N; i += GSF_T) V[(int64_t)(j + 1) * ld + i] = inv * w[i];
+    __syncthreads(); /* every thread has read gs->j and gs->done */
+    if (t == 0) gs->j = j + 1;
 }
 
 /* start of a cycle: state, g = beta e_1 */
@@ -1917,8 +2012,9 @@ extern "C" mhlp_status mhlp_plan_destroy(mhlp_plan *P)
         if (P->ty) (void)hipFree(P->ty);
     }
     for (auto &gp : P->graphs)
-        for (auto &gr : gp)
-            if (gr.exec) (void)hipGraphExecDestroy(gr.exec);
+        for (auto &gv : gp)
+            for (auto &gr : gv)
+                if (gr.exec) (void)hipGraphExecDestroy(gr.exec);
     if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
     void *ptrs[] = {P->near_ptr, P->near_panel, P->near_tgt, P->near_ts, P->wslp,  P->wdlp,    P->ws,
                     P->hdev,     P->part,       P->gdev,     P->perm,    P->wgrad, P->wstk,    P->stk_flux,
@@ -2175,7 +2271,7 @@ static void launch_far_t(const FarArgs &A, int nsplit, int32_t precision, hipStr
         far_eval_mixed<SLP, DLP, true><<<grid, FT_THREADS, 0, st>>>(A);
     else
         far_eval_fp64<SLP, DLP, true><<<grid, FT_THREADS, 0, st>>>(A);
-    far_finalize<SLP, DLP><<<nblocks(A.M, 256), 256, 0, st>>>(A, nsplit);
+    far_finalize<SLP, DLP><<<nblocks(A.M, FZ_TG), FZ_TG * FZ_L, 0, st>>>(A, nsplit);
 }
 
 static mhlp_status launch_far(const mhlp_plan *P, const double *sigma, const double *mu, double *us, double *ud,
@@ -2627,6 +2723,7 @@ static mhlp_status dnorm(mhlp_plan *P, const double *v, int64_t N, hipStream_t s
 struct GmresDev {
     GState *gs;
     double *H, *cs, *sn, *gv, *y, *h1, *h2, *hn;
+    double *p1, *p2, *pn; /* multi-block Gram-Schmidt partials: [nb][R+1], [nb][R+1], [nb] */
 };
 
 static GmresDev gdev_view(const mhlp_plan *P)
@@ -2650,6 +2747,13 @@ static GmresDev gdev_view(const mhlp_plan *P)
     v.h2 = d;
     d += R + 1;
     v.hn = d;
+    d += 1;
+    const int64_t nb = (vlen(P) + gsm_slice(vlen(P)) - 1) / gsm_slice(vlen(P));
+    v.p1 = d;
+    d += nb * (R + 1);
+    v.p2 = d;
+    d += nb * (R + 1);
+    v.pn = d;
     return v;
 }
 
@@ -2661,7 +2765,8 @@ static mhlp_status ensure_gdev(mhlp_plan *P, int R)
         (void)hipFree(P->gdev);
         P->gdev = nullptr;
     }
-    const int64_t nd = (int64_t)(R + 1) * R + 3 * R + 3 * (R + 1) + 1;
+    const int64_t nb = (vlen(P) + gsm_slice(vlen(P)) - 1) / gsm_slice(vlen(P));
+    const int64_t nd = (int64_t)(R + 1) * R + 3 * R + 3 * (R + 1) + 1 + nb * (2 * (R + 1) + 1);
     char *g = nullptr;
     TRY(dalloc(&g, 64 + 8 * nd));
     P->gdev = g;
@@ -2671,40 +2776,35 @@ static mhlp_status ensure_gdev(mhlp_plan *P, int R)
 }
 
 /* One Arnoldi step of the device-driven GMRES, enqueued on st. */
-static mhlp_status enqueue_step(mhlp_plan *P, int32_t prec, hipStream_t st)
+static mhlp_status enqueue_step(mhlp_plan *P, int32_t prec, bool one_block, hipStream_t st)
 {
     const int64_t N = vlen(P);
     const int R = P->gdev_R;
     double *V = P->ws, *w = P->ws + (int64_t)(R + 1) * N;
     const GmresDev d = gdev_view(P);
-    const unsigned nbN = nblocks(N, 256);
     TRY(apply_op(P, V, w, prec, st, d.gs, N));
-    /* one block reads every basis column: worth it while that stays within one
-       compute unit's bandwidth, i.e. for short vectors */
-    if (N <= 4096 && R <= GSF_RMAX) {
+    if (one_block) {
         gs_fused_kernel<<<1, GSF_T, 0, st>>>(d.gs, V, N, w, N, d.H, R, d.cs, d.sn, d.gv, d.h1, d.h2, d.hn);
         HIPCHECK(hipGetLastError());
         return MHLP_OK;
     }
-    /* classical Gram-Schmidt, twice */
-    gs_dot_kernel<<<R, 256, 0, st>>>(d.gs, V, N, w, N, d.h1);
-    gs_sub_kernel<<<nbN, 256, 0, st>>>(d.gs, V, N, d.h1, w, N);
-    gs_dot_kernel<<<R, 256, 0, st>>>(d.gs, V, N, w, N, d.h2);
-    gs_sub_kernel<<<nbN, 256, 0, st>>>(d.gs, V, N, d.h2, w, N);
-    gs_norm_kernel<<<1, 256, 0, st>>>(d.gs, w, N, d.hn);
-    gs_finish_kernel<<<1, 64, 0, st>>>(d.gs, d.H, R, d.cs, d.sn, d.gv, d.h1, d.h2, d.hn);
-    gs_scale_kernel<<<nbN, 256, 0, st>>>(d.gs, w, V, N, N);
-    gs_advance_kernel<<<1, 64, 0, st>>>(d.gs);
+    /* classical Gram-Schmidt, twice, over element slices */
+    const int64_t L = gsm_slice(N);
+    const int nb = (int)((N + L - 1) / L);
+    gsm_dot_kernel<<<nb, GSM_T, 0, st>>>(d.gs, V, N, w, N, L, d.p1, R + 1);
+    gsm_sub_kernel<false><<<nb, GSM_T, 0, st>>>(d.gs, V, N, w, N, L, d.p1, nb, R + 1, d.h1, d.p2);
+    gsm_sub_kernel<true><<<nb, GSM_T, 0, st>>>(d.gs, V, N, w, N, L, d.p2, nb, R + 1, d.h2, d.pn);
+    gsm_finish_kernel<<<1, GSF_T, 0, st>>>(d.gs, V, N, w, N, d.pn, nb, d.H, R, d.cs, d.sn, d.gv, d.h1, d.h2);
     HIPCHECK(hipGetLastError());
     return MHLP_OK;
 }
 
 /* Executable graph of S consecutive Arnoldi steps (S = 1, 2, 4, 8), captured
    once per plan state (workspace, split and restart) on a private stream. */
-static mhlp_status step_graph(mhlp_plan *P, int32_t prec, int si, hipGraphExec_t *out)
+static mhlp_status step_graph(mhlp_plan *P, int32_t prec, bool one_block, int si, hipGraphExec_t *out)
 {
     const int S = 1 << si;
-    mhlp_plan::StepGraph &G = P->graphs[prec == MHLP_MIXED ? 1 : 0][si];
+    mhlp_plan::StepGraph &G = P->graphs[prec == MHLP_MIXED ? 1 : 0][one_block ? 0 : 1][si];
     if (G.exec && G.ws == P->ws && G.part == P->part && G.gdev == P->gdev && G.R == P->gdev_R &&
         G.nsplit == P->nsplit && G.S == S) {
         *out = G.exec;
@@ -2717,7 +2817,7 @@ static mhlp_status step_graph(mhlp_plan *P, int32_t prec, int si, hipGraphExec_t
     if (!P->cap_stream) HIPCHECK(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
     HIPCHECK(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
     mhlp_status s = MHLP_OK;
-    for (int k = 0; k < S && s == MHLP_OK; ++k) s = enqueue_step(P, prec, P->cap_stream);
+    for (int k = 0; k < S && s == MHLP_OK; ++k) s = enqueue_step(P, prec, one_block, P->cap_stream);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(P->cap_stream, &graph);
     if (s != MHLP_OK) {
@@ -2788,8 +2888,10 @@ static mhlp_status gmres_core(mhlp_plan *P, const double *b, double bnorm, doubl
         for (;;) {
             int si = 0;
             while ((1 << si) < chunk && si < 3) ++si;
+            /* Gram-Schmidt in one block while the chunk stays within its first steps */
+            const bool one_block = N <= GSF_NMAX && R <= GSF_RMAX && done_steps + (1 << si) <= GSF_STEPS;
             hipGraphExec_t ex;
-            TRY(step_graph(P, prec, si, &ex));
+            TRY(step_graph(P, prec, one_block, si, &ex));
             HIPCHECK(hipGraphLaunch(ex, st));
             HIPCHECK(hipMemcpyAsync(P->gstate_host, d.gs, sizeof(GState), hipMemcpyDeviceToHost, st));
             HIPCHECK(hipStreamSynchronize(st));
