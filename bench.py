@@ -32,20 +32,21 @@ METRIC = "GPair-evals/s (SLP+DLP) and GMRES time-to-1e-10, mixed/batched/warm vs
 FP64_PEAK_TFLOPS = 78.6        # MI355X vector FP64 (published)
 # FP64 operations per (target, source) pair of the fused SLP+DLP far-field
 # kernel on its z > 6 branch, counted from the instructions of the built kernel
-# (two pairs per loop trip): 58 v_fma (x2), 20 v_mul, 2 v_add, 2 v_rsq (x1)
-# = 140 (the 2 < z <= 6 branch: 60 v_fma, 144); not counted: 1 v_rndne,
-# 1 v_ldexp, 1 v_cvt (exponent handling of exp(-z)).  By function: r^2 and
-# differences 5, 1/r 9, exp(-z) 33, 1/sqrt(z) 9, the K0 piece with derivative
-# 62 (degree 15), K1 and scalings ~15, both accumulations 7.
-FLOP_PER_PAIR_FP64 = 140
-# the gradient kernel (grad S and grad D of the same densities) evaluates the
-# same K0 and alpha K1/r per pair, takes 1/r^2 = (1/r)^2 from the z > 2 form
+# (two pairs per loop trip): 58 v_fma (x2), 15 v_mul, 3 v_add, 2 v_rsq (x1)
+# = 136 (the 2 < z <= 6 branch: 60 v_fma, 140); not counted: v_ldexp and the
+# integer exponent of exp(-z).  By function: differences and r^2 5, 1/r 9,
+# z and exp(-z) 35, 1/sqrt(z) 9, the K0 piece with its derivative 61 (degree
+# 15), K1(z)/r and the scalings 10, both accumulations 7.
+FLOP_PER_PAIR_FP64 = 136
+# the gradient kernel (grad S and grad D of the same densities) evaluates K0
+# and alpha K1/r per pair (the potentials' evaluation with alpha kept inside
+# K1/r: 140 by the same count), takes 1/r^2 = (1/r)^2 from the z > 2 form
 # (1 mul), and accumulates (x-y).n, (alpha^2 K0 + 2A)/r^2 and both gradients:
 # counted from the built kernel's loop, 42 + 2 FLOP per trip of two pairs
 # instead of the potentials' 14, so 140 + 15
 FLOP_PER_PAIR_GRAD = 155
-# modified-Stokes double layer (2x2 stresslet per pair): the same K0 and
-# alpha K1/r (140 less the potentials' 7 of accumulation), then 1/r^2 (1),
+# modified-Stokes double layer (2x2 stresslet per pair): K0 and alpha K1/r as
+# in the gradient kernel (140 less 7 of accumulation), then 1/r^2 (1),
 # alpha^2 T1, alpha^4 T2, alpha^2 T3 from the closed forms of App. B (22) and
 # the contraction D_ij w mu_j into two accumulators (31): 187, counted from
 # the source of the z > 2 path (the counters read 191.6 at alpha = 500, 193.0
@@ -63,7 +64,7 @@ TUNED_SPLITS = os.path.join(ROOT, "paper_1908_07392_amd", "tuning", "mi355x_far_
 # same counter's reading for a plain 256 MiB copy), averaged over the three
 # alphas, measured with these source splits
 # (profiles/far_eval_fp64_starfish4096_grid512_hbm_bytes.txt)
-PROFILED_TRAFFIC = {"splits": {"alpha=5": 20, "alpha=50": 16, "alpha=500": 16}, "bytes": 36874791}
+PROFILED_TRAFFIC = {"splits": {"alpha=5": 20, "alpha=50": 16, "alpha=500": 16}, "bytes": 36885048}
 
 
 def parse():

@@ -491,45 +491,53 @@ __device__ __forceinline__ void far_epilogue(const FarArgs &A, const double *__r
 }
 
 /* Sum of the source-split partials, near corrections, 1/(2 pi) scaling and
-   identity term.  A block takes FZ_TG consecutive targets with FZ_L lanes
-   each (lane l is wave l, so every partial load is a coalesced row segment):
-   lane l adds the partials l, l + FZ_L, ... and the correction terms of node l
-   of each near panel; the lane sums are then added in lane order. */
-constexpr int FZ_TG = 64, FZ_L = 16;
+   identity term.  A block takes FZ_TG consecutive targets with L lanes each
+   (lane l is wave l, so every partial load is a coalesced row segment): lane
+   l adds the partials l, l + L, ... and the correction terms of node l, l + L,
+   ... of each near panel; the lane sums are then added in lane order.  L = 16
+   for short target lists (many splits, few targets: the on-surface operator),
+   L = 1 (one thread per target, 256 targets a block) otherwise. */
+constexpr int FZ_TG = 64, FZ_L = 16, FZ_SHORT = 16384;
 
-template <bool SLP, bool DLP>
-__global__ __launch_bounds__(FZ_TG *FZ_L) void far_finalize(FarArgs A, int nsplit)
+template <bool SLP, bool DLP, int L>
+__global__ __launch_bounds__(L == 1 ? 256 : FZ_TG * L) void far_finalize(FarArgs A, int nsplit)
 {
-    __shared__ double red[4][FZ_L][FZ_TG]; /* far S, near S, far D, near D */
+    constexpr int TG = L == 1 ? 256 : FZ_TG;
+    __shared__ double red[4][L == 1 ? 1 : L][L == 1 ? 1 : TG]; /* far S, near S, far D, near D */
     const double *mu;
     if (!far_density(A, mu)) return; /* the same for every thread of the launch */
-    const int g = threadIdx.x % FZ_TG, l = threadIdx.x / FZ_TG;
-    const int64_t i = blockIdx.x * (int64_t)FZ_TG + g;
+    const int g = threadIdx.x % TG, l = L == 1 ? 0 : threadIdx.x / TG; /* L = 1: loops unroll */
+    const int64_t i = blockIdx.x * (int64_t)TG + g;
     double fs = 0.0, ns = 0.0, fd = 0.0, nd = 0.0;
     if (i < A.M) {
-        for (int k = l; k < nsplit; k += FZ_L) {
+        for (int k = l; k < nsplit; k += L) {
             if (SLP) fs += A.part_s[k * A.M + i];
             if (DLP) fd += A.part_d[k * A.M + i];
         }
         for (int32_t q = A.nptr[i]; q < A.nptr[i + 1]; ++q) {
             const int64_t p = A.npan[q];
             if (p < 0) continue;
-            if (SLP) ns = fma(A.wsl[16 * (int64_t)q + l], A.sigma[16 * p + l], ns);
-            if (DLP) nd = fma(A.wdl[16 * (int64_t)q + l], mu[16 * p + l], nd);
+            for (int jj = l; jj < 16; jj += L) {
+                if (SLP) ns = fma(A.wsl[16 * (int64_t)q + jj], A.sigma[16 * p + jj], ns);
+                if (DLP) nd = fma(A.wdl[16 * (int64_t)q + jj], mu[16 * p + jj], nd);
+            }
         }
     }
-    red[0][l][g] = fs;
-    red[1][l][g] = ns;
-    red[2][l][g] = fd;
-    red[3][l][g] = nd;
-    __syncthreads();
-    if (l != 0 || i >= A.M) return;
-    for (int q = 1; q < FZ_L; ++q) {
-        fs += red[0][q][g];
-        ns += red[1][q][g];
-        fd += red[2][q][g];
-        nd += red[3][q][g];
+    if (L > 1) {
+        red[0][l][g] = fs;
+        red[1][l][g] = ns;
+        red[2][l][g] = fd;
+        red[3][l][g] = nd;
+        __syncthreads();
+        if (l != 0) return;
+        for (int q = 1; q < L; ++q) {
+            fs += red[0][q][g];
+            ns += red[1][q][g];
+            fd += red[2][q][g];
+            nd += red[3][q][g];
+        }
     }
+    if (i >= A.M) return;
     const int64_t o = A.perm ? (int64_t)A.perm[i] : i;
     if (SLP) A.us[o] = fma(INV_2PI, fs, ns);
     if (DLP) {
@@ -2271,7 +2279,10 @@ static void launch_far_t(const FarArgs &A, int nsplit, int32_t precision, hipStr
         far_eval_mixed<SLP, DLP, true><<<grid, FT_THREADS, 0, st>>>(A);
     else
         far_eval_fp64<SLP, DLP, true><<<grid, FT_THREADS, 0, st>>>(A);
-    far_finalize<SLP, DLP><<<nblocks(A.M, FZ_TG), FZ_TG * FZ_L, 0, st>>>(A, nsplit);
+    if (A.M <= FZ_SHORT)
+        far_finalize<SLP, DLP, FZ_L><<<nblocks(A.M, FZ_TG), FZ_TG * FZ_L, 0, st>>>(A, nsplit);
+    else
+        far_finalize<SLP, DLP, 1><<<nblocks(A.M, 256), 256, 0, st>>>(A, nsplit);
 }
 
 static mhlp_status launch_far(const mhlp_plan *P, const double *sigma, const double *mu, double *us, double *ud,

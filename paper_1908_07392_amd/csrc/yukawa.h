@@ -154,10 +154,12 @@ __device__ __forceinline__ double hornerc(const MHLP_CAS double *c, double x)
 template <int N>
 __device__ __forceinline__ double hornercd(const MHLP_CAS double *c, double x, double &d)
 {
-    double v = c[N - 1];
-    d = 0.0;
+    /* first step written out (d would start as fma(0, x, c[N-1]), which the
+       compiler may not fold) */
+    d = c[N - 1];
+    double v = fma(c[N - 1], x, c[N - 2]);
 #pragma unroll
-    for (int i = N - 2; i >= 0; --i) {
+    for (int i = N - 3; i >= 0; --i) {
         d = fma(d, x, v);
         v = fma(v, x, c[i]);
     }
@@ -180,12 +182,16 @@ __device__ __forceinline__ double lean_rcp(double x)
     return fma(y, e, y);
 }
 
+/* e^{-z} = 2^m e^r, m = round(-z log2 e), |r| <= ln2/2 (+ rounding): m comes
+   from adding 1.5 * 2^52, whose low word then holds m as an integer */
 __device__ __forceinline__ double lean_exp_neg(FarTab T, double z)
 {
-    const double n = rint(z * LOG2E);
-    double r = fma(n, LN2_HI, -z);
-    r = fma(n, LN2_LO, r);
-    return ldexp(hornerc<14>(T->expt, r), -(int)n);
+    constexpr double SHIFT = 6755399441055744.0; /* 1.5 * 2^52 */
+    const double t = fma(z, -LOG2E, SHIFT);
+    const double m = t - SHIFT;
+    double r = fma(m, -LN2_HI, -z);
+    r = fma(m, -LN2_LO, r);
+    return ldexp(hornerc<14>(T->expt, r), __double2loint(t));
 }
 
 __device__ __forceinline__ double lean_log01(FarTab T, double q)
