@@ -112,13 +112,14 @@ mhlp_status mhlp_plan_info(const mhlp_plan *plan, int64_t *n_targets, int64_t *n
 /* Far-field launch shape.  The direct sum over sources can be split into
    nsplit ranges of panels evaluated by separate blocks (partial sums added
    in fixed order, so results do not depend on nsplit beyond rounding); the
-   default gives about 1024 blocks.  set_split may reallocate the plan's
+   default aims at about 8192 blocks of 256 targets with at least 2 panels
+   per split.  set_split may reallocate the plan's
    partial-sum buffer (it synchronises the device then).
    mhlp_plan_autotune times the far evaluation (layers: 1 SLP, 2 DLP, 3 both,
    4 the on-surface BIE operator, 5 the gradients of both, off-surface, 6 the
    stresslet operator of a stokes plan, 7 the stresslet target gradient of an
-   off-surface stokes plan) for nsplit = 1, 2, 4, ... (up to Np/4 and
-   256) plus the current value, reps timed launches each after one warm-up,
+   off-surface stokes plan) for nsplit = 1, 2, 4, ... (up to Np and 256)
+   plus the current value, reps timed launches each after one warm-up,
    with HIP events on `stream`, keeps the fewest splits within 1% of the
    fastest and reports it with its time (host outputs; cand/cand_ms receive up
    to cap candidates and their ms per launch).  A plan whose FP64 far field is

@@ -2133,10 +2133,10 @@ static mhlp_status plan_create_impl(const mhlp_geometry *g, double alpha, const 
     {
         /* source splits so that about 8192 blocks of 256 targets run (the
            chip holds about 1024 at a time; several rounds keep the tail
-           short); at least 4 panels per split.  mhlp_plan_autotune refines. */
+           short); at least 2 panels per split.  mhlp_plan_autotune refines. */
         const int64_t tblocks = (M + FT_THREADS - 1) / FT_THREADS;
         int64_t ns = (8192 + tblocks - 1) / tblocks;
-        if (ns > g->Np / 4) ns = g->Np / 4;
+        if (ns > g->Np / 2) ns = g->Np / 2;
         if (ns < 1) ns = 1;
         if ((s = plan_set_split(P, (int)ns))) {
             mhlp_plan_destroy(P);
@@ -2392,7 +2392,7 @@ extern "C" mhlp_status mhlp_plan_autotune(mhlp_plan *P, int32_t layers, int32_t 
     hipStream_t st = (hipStream_t)stream;
     const int64_t N = P->g->N, M = P->M, Np = P->g->Np;
     std::vector<int> cs;
-    for (int64_t ns = 1; ns <= std::max<int64_t>(1, Np / 4) && ns <= 256; ns *= 2) cs.push_back((int)ns);
+    for (int64_t ns = 1; ns <= Np && ns <= 256; ns *= 2) cs.push_back((int)ns);
     if (std::find(cs.begin(), cs.end(), P->nsplit) == cs.end()) cs.push_back(P->nsplit);
     double *dens = nullptr, *out = nullptr;
     TRY(dalloc(&dens, 2 * N));
