@@ -895,17 +895,66 @@ __device__ __forceinline__ void stk_epilogue(const StkArgs &A, const double *__r
     A.u[A.ustride + o] = a2;
 }
 
-__global__ void stk_finalize(StkArgs A, int nsplit)
+/* Split partials + the epilogue, laid out as far_finalize: L = FZ_L lanes per
+   target (lane l: partials l, l + L, ..., node l of each near panel, lane sums
+   added in lane order) for short target lists, one thread per target
+   otherwise. */
+template <int L>
+__global__ __launch_bounds__(L == 1 ? 256 : FZ_TG * L) void stk_finalize(StkArgs A, int nsplit)
 {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const double *mu;
-    if (i >= A.M || !stk_density(A, mu)) return;
-    double a1 = 0.0, a2 = 0.0;
-    for (int k = 0; k < nsplit; ++k) {
-        a1 += A.part[(int64_t)k * A.M + i];
-        a2 += A.part[((int64_t)nsplit + k) * A.M + i];
+    if (L == 1) {
+        const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+        const double *mu;
+        if (i >= A.M || !stk_density(A, mu)) return;
+        double a1 = 0.0, a2 = 0.0;
+        for (int k = 0; k < nsplit; ++k) {
+            a1 += A.part[(int64_t)k * A.M + i];
+            a2 += A.part[((int64_t)nsplit + k) * A.M + i];
+        }
+        stk_epilogue(A, mu, i, a1, a2);
+        return;
     }
-    stk_epilogue(A, mu, i, a1, a2);
+    __shared__ double red[4][L][FZ_TG]; /* far 1, near 1, far 2, near 2 */
+    const double *mu;
+    if (!stk_density(A, mu)) return; /* the same for every thread of the launch */
+    const int g = threadIdx.x % FZ_TG, l = threadIdx.x / FZ_TG;
+    const int64_t i = blockIdx.x * (int64_t)FZ_TG + g;
+    double f1 = 0.0, n1 = 0.0, f2 = 0.0, n2 = 0.0;
+    if (i < A.M) {
+        for (int k = l; k < nsplit; k += L) {
+            f1 += A.part[(int64_t)k * A.M + i];
+            f2 += A.part[((int64_t)nsplit + k) * A.M + i];
+        }
+        for (int32_t q = A.nptr[i]; q < A.nptr[i + 1]; ++q) {
+            const int64_t p = A.npan[q];
+            if (p < 0) continue;
+            const int64_t o = 16 * (int64_t)q + l;
+            const double m1 = mu[16 * p + l], m2 = mu[A.N + 16 * p + l];
+            n1 = fma(A.wst[o], m1, fma(A.wst[A.nnz * 16 + o], m2, n1));
+            n2 = fma(A.wst[2 * A.nnz * 16 + o], m1, fma(A.wst[3 * A.nnz * 16 + o], m2, n2));
+        }
+    }
+    red[0][l][g] = f1;
+    red[1][l][g] = n1;
+    red[2][l][g] = f2;
+    red[3][l][g] = n2;
+    __syncthreads();
+    if (l != 0 || i >= A.M) return;
+    for (int q = 1; q < L; ++q) {
+        f1 += red[0][q][g];
+        n1 += red[1][q][g];
+        f2 += red[2][q][g];
+        n2 += red[3][q][g];
+    }
+    double a1 = f1 + n1, a2 = f2 + n2;
+    if (A.bie) {
+        const double f = A.flux[0];
+        a1 = fma(0.5, mu[i], fma(A.snx[i], f, a1));
+        a2 = fma(0.5, mu[A.N + i], fma(A.sny[i], f, a2));
+    }
+    const int64_t o = A.perm ? (int64_t)A.perm[i] : i;
+    A.u[o] = a1;
+    A.u[A.ustride + o] = a2;
 }
 
 /* flux sum_j w_j mu_j.n_j / |Gamma| of the density into flux[0]; one block,
@@ -2603,7 +2652,10 @@ static mhlp_status launch_stokes(const mhlp_plan *P, const double *mu, double *u
         far_stokes_fp64<false><<<nb, FT_THREADS, 0, st>>>(A);
     } else {
         far_stokes_fp64<true><<<dim3(nb, P->nsplit), FT_THREADS, 0, st>>>(A);
-        stk_finalize<<<nblocks(A.M, 256), 256, 0, st>>>(A, P->nsplit);
+        if (A.M <= FZ_SHORT)
+            stk_finalize<FZ_L><<<nblocks(A.M, FZ_TG), FZ_TG * FZ_L, 0, st>>>(A, P->nsplit);
+        else
+            stk_finalize<1><<<nblocks(A.M, 256), 256, 0, st>>>(A, P->nsplit);
     }
     HIPCHECK(hipGetLastError());
     return MHLP_OK;
