@@ -31,13 +31,19 @@ sys.path.insert(0, ROOT)
 METRIC = "GPair-evals/s (SLP+DLP) and GMRES time-to-1e-10, mixed/batched/warm vs FP64"
 FP64_PEAK_TFLOPS = 78.6        # MI355X vector FP64 (published)
 # FP64 operations per (target, source) pair of the fused SLP+DLP far-field
-# kernel on its z > 6 branch, counted from the instructions of the built kernel
-# (two pairs per loop trip): 58 v_fma (x2), 15 v_mul, 3 v_add, 2 v_rsq (x1)
-# = 136 (the 2 < z <= 6 branch: 60 v_fma, 140); not counted: v_ldexp and the
-# integer exponent of exp(-z).  By function: differences and r^2 5, 1/r 9,
-# z and exp(-z) 35, 1/sqrt(z) 9, the K0 piece with its derivative 61 (degree
-# 15), K1(z)/r and the scalings 10, both accumulations 7.
-FLOP_PER_PAIR_FP64 = 136
+# kernel on its z > 20 branch (the branch most pairs of the alpha = 50 and 500
+# evaluations take), counted from the instructions of the built kernel (two
+# pairs per loop trip): 46 v_fma (x2), 15 v_mul, 3 v_add, 2 v_rsq (x1) = 112;
+# the 6 < z <= 20 branch takes 52 v_fma (124), the 2 < z <= 6 branch 60 (140).
+# Not counted: v_ldexp and the integer exponent of exp(-z).  By function:
+# differences and r^2 5, 1/r 9, z and exp(-z) 35, 1/sqrt(z) 9, the K0 piece with
+# its derivative 37 (degree 9), K1(z)/r and the scalings 10, accumulations 7.
+FLOP_PER_PAIR_FP64 = 112
+# VALU instructions per pair on that branch (all types), and the issue rate
+# they are bound by: 256 CUs x 2.4 GHz, one 64-lane VALU instruction per CU
+# per clock
+VALU_PER_PAIR_FP64 = 72
+VALU_ISSUE_PER_S = 256 * 2.4e9 * 64
 # the gradient kernel (grad S and grad D of the same densities) evaluates K0
 # and alpha K1/r per pair (the potentials' evaluation with alpha kept inside
 # K1/r: 140 by the same count), takes 1/r^2 = (1/r)^2 from the z > 2 form
@@ -64,7 +70,7 @@ TUNED_SPLITS = os.path.join(ROOT, "paper_1908_07392_amd", "tuning", "mi355x_far_
 # same counter's reading for a plain 256 MiB copy), averaged over the three
 # alphas, measured with these source splits
 # (profiles/far_eval_fp64_starfish4096_grid512_hbm_bytes.txt)
-PROFILED_TRAFFIC = {"splits": {"alpha=5": 20, "alpha=50": 16, "alpha=500": 16}, "bytes": 36885048}
+PROFILED_TRAFFIC = {"splits": {"alpha=5": 20, "alpha=50": 16, "alpha=500": 16}, "bytes": 36893199}
 
 
 def parse():
@@ -204,7 +210,9 @@ def main():
                 "launch_ms": round(launch_ms, 4),
                 "launch_ms_by_alpha": {f"alpha={a:g}": round(float(np.mean(v)), 4) for a, v in per_a.items()},
                 "pairs_per_launch": eval_pairs, "flop_per_pair": FLOP_PER_PAIR_FP64,
-                "eval_gpair_per_s": round(eval_pairs / (launch_ms * 1e-3) / 1e9, 3)}
+                "eval_gpair_per_s": round(eval_pairs / (launch_ms * 1e-3) / 1e9, 3),
+                "valu_per_pair": VALU_PER_PAIR_FP64,
+                "valu_issue_frac": round(eval_pairs * VALU_PER_PAIR_FP64 / (launch_ms * 1e-3) / VALU_ISSUE_PER_S, 4)}
     a_r = 50.0
     on, off = plans[a_r]
     mu, _ = mhlp.gmres_solve(on, gdev[a_r], tol=1e-10)

@@ -263,8 +263,13 @@ def main():
         out.append(fmt(f"KL{nu}", c64))
         out.append(fmt(f"KLF{nu}", c32, "float"))
     us = mp.mpf(4) / 6 - 1
+    ux = mp.mpf(4) / 20 - 1
+    # two pieces split at z = 6 (N: 2 < z <= 6, F: z > 6), and the far piece
+    # split again at z = 20 (M: 6 < z <= 20, X: z > 20) for shorter polynomials
     for name, nu, deg, lo, hi, der in (("KP0N", 0, 16, us, 1, True), ("KP0F", 0, 15, -1, us, True),
-                                       ("KP1N", 1, 14, us, 1, False), ("KP1F", 1, 13, -1, us, False)):
+                                       ("KP1N", 1, 14, us, 1, False), ("KP1F", 1, 13, -1, us, False),
+                                       ("KP0M", 0, 12, ux, us, True), ("KP0X", 0, 9, -1, ux, True),
+                                       ("KP1M", 1, 10, ux, us, False), ("KP1X", 1, 8, -1, ux, False)):
         c = cheb_fit_mono(large_fn(nu), deg, lo, hi)
         e0, e1 = check_piece(c, nu, lo, hi, der)
         report.append((name, e0, e1))

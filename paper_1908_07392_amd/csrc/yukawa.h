@@ -108,6 +108,7 @@ static constexpr double ATANH_T[11] = {1.0, 1.0 / 3.0, 1.0 / 5.0, 1.0 / 7.0, 1.0
 struct FarTable {
     double kp0n[17], kp0f[16], kp1n[15], kp1f[14], kl0[23], expt[14], atanh[11], ks_i0[12], ks_r0[13], ks_i1z[12],
         ks_r1[13];
+    double kp0m[13], kp0x[10], kp1m[11], kp1x[9]; /* the z > 6 piece split at z = 20 */
     double stk[6][14]; /* stresslet smooth parts T1S, T2S, T3S, T1L, T2L, T3L in q = z^2/4 <= 1 */
 };
 
@@ -119,6 +120,10 @@ constexpr FarTable make_far_table()
     for (int i = 0; i < 16; ++i) t.kp0f[i] = KP0F[i];
     for (int i = 0; i < 15; ++i) t.kp1n[i] = KP1N[i];
     for (int i = 0; i < 14; ++i) t.kp1f[i] = KP1F[i];
+    for (int i = 0; i < 13; ++i) t.kp0m[i] = KP0M[i];
+    for (int i = 0; i < 10; ++i) t.kp0x[i] = KP0X[i];
+    for (int i = 0; i < 11; ++i) t.kp1m[i] = KP1M[i];
+    for (int i = 0; i < 9; ++i) t.kp1x[i] = KP1X[i];
     for (int i = 0; i < 14; ++i) t.expt[i] = EXP_T[i];
     for (int i = 0; i < 11; ++i) t.atanh[i] = ATANH_T[i];
     for (int i = 0; i < 12; ++i) t.ks_i0[i] = KS_I0[i], t.ks_i1z[i] = KS_I1Z[i];
@@ -214,6 +219,9 @@ __device__ __forceinline__ double lean_log01(FarTab T, double q)
              from the K0 pieces (degree 16 / 15; K1 alone: degree 14 / 13);
      z <= 2: K1 = I0/z + (z/4) log(q) I0'(q) - (z/2) R0'(q), q = z^2/4.
    Max rel. error of the z > 2 pieces 1.2e-16 for K0 and K1 (40-digit check).
+   The K1R form (the potentials' tiles) splits the z > 6 piece again at
+   z = 20: degree 12 / 9 for K0 with its derivative, 10 / 8 for K1 alone
+   (1.7e-16), which shortens the polynomials of the far pairs.
    k01_far_small is the z <= 2 form.  k01_far2 takes two sources: the z > 2
    forms straight-line for both (independent instruction streams the
    scheduler interleaves) on lanes where either needs it, with the common
@@ -224,13 +232,17 @@ struct FarConst {
     double vf, vn;         /* 12/alpha, 6/alpha: piece variables from 1/r */
     double kf, kn;         /* 12/alpha^2, 6/alpha^2: (4/alpha^2) dv/du     */
     double ha;             /* 1/(2 alpha) */
+    /* pieces 6 < z <= 20 (v = vm/r + om) and z > 20 (v = vx/r - 1): with
+       u = 4/z - 1 on [-0.8, -1/3] and [-1, -0.8], v = (30u + 17)/7 and 10u + 9 */
+    double vm, om, km, vx, kx;
 };
 
 __device__ __forceinline__ FarConst far_const(double alpha)
 {
     const double ia = 1.0 / alpha;
-    return FarConst{alpha, 0.25 * alpha * alpha, 4.0 / alpha, ia,
-                    12.0 * ia, 6.0 * ia, 12.0 * ia * ia, 6.0 * ia * ia, 0.5 * ia};
+    return FarConst{alpha,          0.25 * alpha * alpha, 4.0 / alpha,         ia,      12.0 * ia,
+                    6.0 * ia,       12.0 * ia * ia,       6.0 * ia * ia,       0.5 * ia, 120.0 / 7.0 * ia,
+                    -13.0 / 7.0,    120.0 / 7.0 * ia * ia, 40.0 * ia,          40.0 * ia * ia};
 }
 
 /* polynomial of the piece (value and d/du) at 1/r = ri.  K1R: the derivative
@@ -250,6 +262,25 @@ __device__ __forceinline__ double far_piece(FarTab T, const FarConst &c, double 
     dpdu = 0.0;
     if (SLP) return FAR ? hornerc<16>(T->kp0f, v) : hornerc<17>(T->kp0n, v);
     return FAR ? hornerc<14>(T->kp1f, v) : hornerc<15>(T->kp1n, v);
+}
+
+/* the K1R pieces: P = 0 for 2 < z <= 6, 1 for 6 < z <= 20, 2 for z > 20;
+   value (and (4/alpha^2) dP/du with both layers) at 1/r = ri */
+template <bool SLP, bool DLP, int P>
+__device__ __forceinline__ double far_piece3(FarTab T, const FarConst &c, double ri, double &dpdu)
+{
+    const double v = P == 0 ? fma(c.vn, ri, -2.0) : P == 1 ? fma(c.vm, ri, c.om) : fma(c.vx, ri, -1.0);
+    if (SLP && DLP) {
+        double d;
+        const double p = P == 0   ? hornercd<17>(T->kp0n, v, d)
+                         : P == 1 ? hornercd<13>(T->kp0m, v, d)
+                                  : hornercd<10>(T->kp0x, v, d);
+        dpdu = d * (P == 0 ? c.kn : P == 1 ? c.km : c.kx);
+        return p;
+    }
+    dpdu = 0.0;
+    if (SLP) return P == 0 ? hornerc<17>(T->kp0n, v) : P == 1 ? hornerc<13>(T->kp0m, v) : hornerc<10>(T->kp0x, v);
+    return P == 0 ? hornerc<15>(T->kp1n, v) : P == 1 ? hornerc<11>(T->kp1m, v) : hornerc<9>(T->kp1x, v);
 }
 
 /* K1R = false: out.ak1r = alpha K1(z)/r.  K1R = true: out.ak1r = K1(z)/r (the
@@ -318,6 +349,32 @@ __device__ __forceinline__ void k01_far2_big(FarTab T, const FarConst &c, double
     if (!PIECES) {
         pa = hornerc<23>(T->kl0, fma(c.a4, ria, -1.0));
         pb = hornerc<23>(T->kl0, fma(c.a4, rib, -1.0));
+    } else if (K1R) {
+        /* three pieces; both sources in one piece run straight-line */
+        const bool xa = za > 20.0, xb = zb > 20.0;
+        if (xa && xb) {
+            pa = far_piece3<SLP, DLP, 2>(T, c, ria, da);
+            pb = far_piece3<SLP, DLP, 2>(T, c, rib, db);
+        } else if (fa && fb && !xa && !xb) {
+            pa = far_piece3<SLP, DLP, 1>(T, c, ria, da);
+            pb = far_piece3<SLP, DLP, 1>(T, c, rib, db);
+        } else if (!fa && !fb) {
+            pa = far_piece3<SLP, DLP, 0>(T, c, ria, da);
+            pb = far_piece3<SLP, DLP, 0>(T, c, rib, db);
+        } else {
+            if (xa)
+                pa = far_piece3<SLP, DLP, 2>(T, c, ria, da);
+            else if (fa)
+                pa = far_piece3<SLP, DLP, 1>(T, c, ria, da);
+            else
+                pa = far_piece3<SLP, DLP, 0>(T, c, ria, da);
+            if (xb)
+                pb = far_piece3<SLP, DLP, 2>(T, c, rib, db);
+            else if (fb)
+                pb = far_piece3<SLP, DLP, 1>(T, c, rib, db);
+            else
+                pb = far_piece3<SLP, DLP, 0>(T, c, rib, db);
+        }
     } else if (fa && fb) {
         pa = far_piece<SLP, DLP, true, K1R>(T, c, ria, da);
         pb = far_piece<SLP, DLP, true, K1R>(T, c, rib, db);
