@@ -1,0 +1,70 @@
+"""The fitted far-field tables in the generated constants header against SciPy's
+exponentially scaled Bessel functions (no GPU): each piece of e^z sqrt(z) K_nu(z)
+for z > 2 as a polynomial in the local variable of u = 4/z - 1 (this library's
+evaluation of the kernels K0 and K1 of Sec. 2; the paper's series of App. C cover
+small z), and K1 taken from the derivative of the K0 piece, as the tile kernels
+use them."""
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.special as sp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "paper_1908_07392_amd", "csrc", "constants.h")
+
+
+def table(name):
+    text = open(HEADER).read()
+    m = re.search(r"static constexpr double " + name + r"\[(\d+)\] = \{(.*?)\};", text, re.S)
+    vals = [float(x) for x in m.group(2).replace("\n", " ").split(",")]
+    assert len(vals) == int(m.group(1))
+    return np.array(vals)
+
+
+def horner(c, v):
+    p = np.zeros_like(v)
+    for a in c[::-1]:
+        p = p * v + a
+    return p
+
+
+def dhorner(c, v):
+    return horner(np.arange(1, len(c)) * c[1:], v)
+
+
+U6, U20 = 4.0 / 6 - 1, 4.0 / 20 - 1
+PIECES = [  # name, nu, u range, with derivative
+    ("KP0N", 0, (U6, 1.0), True), ("KP0F", 0, (-1.0, U6), True),
+    ("KP0M", 0, (U20, U6), True), ("KP0X", 0, (-1.0, U20), True),
+    ("KP1N", 1, (U6, 1.0), False), ("KP1F", 1, (-1.0, U6), False),
+    ("KP1M", 1, (U20, U6), False), ("KP1X", 1, (-1.0, U20), False),
+]
+
+
+@pytest.mark.parametrize("name,nu,urange,der", PIECES)
+def test_piece_matches_scaled_bessel(name, nu, urange, der):
+    c = table(name)
+    lo, hi = urange
+    u = np.linspace(lo, hi, 2001)[1:] if lo == -1.0 else np.linspace(lo, hi, 2001)
+    z = 4.0 / (u + 1.0)
+    v = (2 * u - lo - hi) / (hi - lo)
+    p = horner(c, v)
+    ref = np.sqrt(z) * sp.kve(nu, z)
+    assert np.max(np.abs(p / ref - 1)) < 4e-15, name
+    if der:
+        dp = dhorner(c, v) * 2 / (hi - lo)  # d/du
+        k1 = p * (1 + 1 / (2 * z)) + 4 / z ** 2 * dp
+        ref1 = np.sqrt(z) * sp.kve(1, z)
+        assert np.max(np.abs(k1 / ref1 - 1)) < 4e-15, name
+
+
+def test_pieces_join_at_the_breakpoints():
+    """both sides of z = 6 and z = 20 give the same K0 (to rounding)"""
+    def piece(name, lo, hi, z):
+        u = 4.0 / z - 1
+        return horner(table(name), np.array([(2 * u - lo - hi) / (hi - lo)]))[0]
+    assert abs(piece("KP0N", U6, 1.0, 6.0) / piece("KP0M", U20, U6, 6.0) - 1) < 1e-15
+    assert abs(piece("KP0M", U20, U6, 20.0) / piece("KP0X", -1.0, U20, 20.0) - 1) < 1e-15
+    assert abs(piece("KP0F", -1.0, U6, 20.0) / piece("KP0X", -1.0, U20, 20.0) - 1) < 1e-15
