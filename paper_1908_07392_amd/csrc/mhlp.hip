@@ -85,7 +85,7 @@ struct GState {
     double thresh; /* stop when the residual estimate |g_{j+1}| <= thresh  */
     double inv;    /* 1 / h_{j+1,j}: scaling of the next basis vector      */
     double resest; /* |g_{j+1}| after the last step                        */
-    double pad;
+    double bnorm;  /* ||b|| when the solve left it on the device (first cycle) */
 };
 
 namespace mhlp {
@@ -1442,8 +1442,7 @@ __device__ void gsf_dots(const double *__restrict__ V, int64_t ld, const double 
 __global__ __launch_bounds__(GSF_T) void gs_fused_kernel(GState *__restrict__ gs, double *__restrict__ V, int64_t ld,
                                                          double *__restrict__ w, int64_t N, double *__restrict__ H,
                                                          int R, double *__restrict__ cs, double *__restrict__ sn,
-                                                         double *__restrict__ gv, double *__restrict__ h1,
-                                                         double *__restrict__ h2, double *__restrict__ hn)
+                                                         double *__restrict__ gv)
 {
     __shared__ double red[GSF_W][GSF_RMAX];
     __shared__ double hs[2][GSF_RMAX];
@@ -1607,7 +1606,32 @@ __global__ void gs_init_kernel(GState *__restrict__ gs, double *__restrict__ gv,
         gs->thresh = thresh;
         gs->inv = 0.0;
         gs->resest = beta;
-        gs->pad = 0.0;
+    }
+}
+
+/* start of the first cycle of a zero-guess solve whose ||b|| stays on the
+   device: beta = ||b|| from its square bn2[0], V_0 = b / beta (zero when b
+   is), g = beta e_1, the stopping threshold half_tol * beta, and ||b|| kept in
+   the state for the host's first read (a zero b ends the cycle at once) */
+__global__ void gs_init_dev_kernel(GState *__restrict__ gs, double *__restrict__ gv, int R, int kmax,
+                                   double half_tol, const double *__restrict__ bn2, const double *__restrict__ b,
+                                   double *__restrict__ V0, int64_t N)
+{
+    const double beta = sqrt(bn2[0]);
+    const double sc = beta > 0.0 ? 1.0 / beta : 0.0;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < N) V0[i] = sc * b[i];
+    if (blockIdx.x != 0) return;
+    for (int k = threadIdx.x; k <= R; k += blockDim.x) gv[k] = k == 0 ? beta : 0.0;
+    if (threadIdx.x == 0) {
+        gs->j = 0;
+        gs->kmax = kmax;
+        gs->done = beta > 0.0 ? 0 : 1;
+        gs->steps = 0;
+        gs->thresh = half_tol * beta;
+        gs->inv = 0.0;
+        gs->resest = beta;
+        gs->bnorm = beta;
     }
 }
 
@@ -2847,7 +2871,7 @@ static mhlp_status enqueue_step(mhlp_plan *P, int32_t prec, bool one_block, hipS
     const GmresDev d = gdev_view(P);
     TRY(apply_op(P, V, w, prec, st, d.gs, N));
     if (one_block) {
-        gs_fused_kernel<<<1, GSF_T, 0, st>>>(d.gs, V, N, w, N, d.H, R, d.cs, d.sn, d.gv, d.h1, d.h2, d.hn);
+        gs_fused_kernel<<<1, GSF_T, 0, st>>>(d.gs, V, N, w, N, d.H, R, d.cs, d.sn, d.gv);
         HIPCHECK(hipGetLastError());
         return MHLP_OK;
     }
@@ -2913,8 +2937,11 @@ static mhlp_status step_graph(mhlp_plan *P, int32_t prec, bool one_block, int si
    steps after the stopping point do nothing. */
 static mhlp_status gmres_core(mhlp_plan *P, const double *b, double bnorm, double *x, double tol, int restart,
                               int max_iter, int32_t prec, hipStream_t st, int *iters, int *cycles, double *relres,
-                              const double *r_first, double beta_first)
+                              const double *r_first, double beta_first, bool bnorm_dev = false)
 {
+    /* bnorm_dev: a zero-guess solve (tol < 1) whose ||b||^2 the caller left in
+       P->hdev[0]; the first cycle starts from it on the device and ||b|| comes
+       back with the first read of the state */
     const int64_t N = vlen(P);
     TRY(ensure_gdev(P, restart));
     const int R = P->gdev_R;
@@ -2930,7 +2957,10 @@ static mhlp_status gmres_core(mhlp_plan *P, const double *b, double bnorm, doubl
            its norm (b itself for a zero initial guess) */
         double beta;
         const double *rr = r_first;
-        if (r_first && *cycles == 0) {
+        const bool first_dev = bnorm_dev && *cycles == 0;
+        if (first_dev) {
+            beta = 0.0; /* known after the first read of the state */
+        } else if (r_first && *cycles == 0) {
             beta = beta_first;
         } else {
             TRY(apply_op(P, x, w, prec, st));
@@ -2938,16 +2968,21 @@ static mhlp_status gmres_core(mhlp_plan *P, const double *b, double bnorm, doubl
             TRY(dnorm(P, r, N, st, &beta));
             rr = r;
         }
-        *relres = beta / bnorm;
-        if (*relres <= tol || it >= max_iter) break;
+        if (!first_dev) {
+            *relres = beta / bnorm;
+            if (*relres <= tol || it >= max_iter) break;
+        }
         ++*cycles;
-        scale_kernel<<<nbN, 256, 0, st>>>(rr, 1.0 / beta, V, N);
         const int kmax = std::min(restart, max_iter - it);
-        const double thresh = 0.5 * tol * bnorm;
-        gs_init_kernel<<<1, 256, 0, st>>>(d.gs, d.gv, R, kmax, beta, thresh);
+        if (first_dev) {
+            gs_init_dev_kernel<<<nbN, 256, 0, st>>>(d.gs, d.gv, R, kmax, 0.5 * tol, P->hdev, b, V, N);
+        } else {
+            scale_kernel<<<nbN, 256, 0, st>>>(rr, 1.0 / beta, V, N);
+            gs_init_kernel<<<1, 256, 0, st>>>(d.gs, d.gv, R, kmax, beta, 0.5 * tol * bnorm);
+        }
         HIPCHECK(hipGetLastError());
         int done_steps = 0, chunk = 2;
-        double last_est = beta;
+        double last_est = beta, thresh = 0.5 * tol * bnorm;
         for (;;) {
             int si = 0;
             while ((1 << si) < chunk && si < 3) ++si;
@@ -2959,6 +2994,17 @@ static mhlp_status gmres_core(mhlp_plan *P, const double *b, double bnorm, doubl
             HIPCHECK(hipMemcpyAsync(P->gstate_host, d.gs, sizeof(GState), hipMemcpyDeviceToHost, st));
             HIPCHECK(hipStreamSynchronize(st));
             const GState gsh = *P->gstate_host;
+            if (first_dev && done_steps == 0) {
+                bnorm = gsh.bnorm;
+                if (bnorm == 0.0) { /* b = 0: x = 0 (the caller's zero guess) */
+                    *relres = 0.0;
+                    *iters = 0;
+                    *cycles = 0;
+                    return MHLP_OK;
+                }
+                last_est = bnorm;
+                thresh = 0.5 * tol * bnorm;
+            }
             if (gsh.done) break;
             /* steps still needed at the rate observed over this chunk */
             const int ran = gsh.steps - done_steps;
@@ -3002,10 +3048,18 @@ static mhlp_status gmres_solve_impl(const mhlp_plan *Pc, const double *g, double
     TRY(ensure_gdev(P, opts->restart));
     const int R = P->gdev_R;
     TRY(ensure_ws(P, R + 1));
-    double bnorm;
-    TRY(dnorm(P, g, N, st, &bnorm));
+    /* an FP64 solve from zero keeps ||g|| on the device until the first read
+       of the GMRES state (one host round trip fewer); the others need it now */
+    const bool bnorm_dev = opts->precision == MHLP_FP64 && !opts->use_x0 && opts->tol < 1.0;
+    double bnorm = 0.0;
+    if (bnorm_dev) {
+        multi_dot_kernel<<<1, 256, 0, st>>>(g, N, g, N, P->hdev); /* ||g||^2 */
+        HIPCHECK(hipGetLastError());
+    } else {
+        TRY(dnorm(P, g, N, st, &bnorm));
+    }
     info->used_x0 = opts->use_x0 ? 1 : 0;
-    if (bnorm == 0.0) {
+    if (!bnorm_dev && bnorm == 0.0) {
         fill_kernel<<<nblocks(N, 256), 256, 0, st>>>(mu, 0.0, N);
         HIPCHECK(hipStreamSynchronize(st));
         info->converged = 1;
@@ -3033,7 +3087,7 @@ static mhlp_status gmres_solve_impl(const mhlp_plan *Pc, const double *g, double
     double rel = 1.0;
     if (opts->precision == MHLP_FP64) {
         TRY(gmres_core(P, g, bnorm, mu, opts->tol, opts->restart, opts->max_iter, MHLP_FP64, st, &iters, &cycles, &rel,
-                       info->used_x0 ? r0 : g, info->used_x0 ? r0n : bnorm));
+                       info->used_x0 ? r0 : g, info->used_x0 ? r0n : bnorm, bnorm_dev));
     } else {
         /* iterative refinement: FP64 residual r = g - A mu (FP64 operator), inner
            GMRES on the mixed-precision operator for A d = r to 1e-6 relative (the

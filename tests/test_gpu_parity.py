@@ -384,3 +384,27 @@ def test_nonfinite_targets_rejected():
         mhlp.Plan(G, 3.0, _t([0.1, np.nan]), _t([0.0, 0.2]))
     with pytest.raises(mhlp.MhlpError):
         mhlp.Plan(G, 3.0, _t([0.1, np.inf]), _t([0.0, 0.2]))
+
+
+def test_zero_rhs_and_loose_tolerance_paths():
+    """||g|| stays on the device for FP64 solves from zero: a zero right-hand side
+    (scalar and stresslet) ends at the first read of the state with x = 0; a
+    tolerance of at least 1 is met by the zero guess before any step; a zero
+    right-hand side after a nonzero one reuses the same plan cleanly."""
+    g = wl.discretize(wl.starfish_curve(), 24)
+    G = _geom(g)
+    P = mhlp.Plan(G, 12.0)
+    b = _t(wl.fourier_density(g.theta, wl.random_fourier_coeffs(np.random.default_rng(5), 6)))
+    x, info = mhlp.gmres_solve(P, b, tol=1e-10)
+    assert info["converged"] and info["iters"] > 0
+    z = torch.zeros(g.n_nodes, dtype=torch.float64, device=DEV)
+    mu, info = mhlp.gmres_solve(P, z, tol=1e-10)
+    assert info["converged"] and info["iters"] == 0 and info["restarts"] == 0 and float(mu.abs().max()) == 0.0
+    mu, info = mhlp.gmres_solve(P, b, tol=1.5)
+    assert info["converged"] and info["iters"] == 0 and float(mu.abs().max()) == 0.0
+    x2, info = mhlp.gmres_solve(P, b, tol=1e-10)
+    assert torch.equal(x, x2)
+    S = mhlp.Plan(G, 12.0, stokes=True)
+    z2 = torch.zeros(2 * g.n_nodes, dtype=torch.float64, device=DEV)
+    mu, info = mhlp.stokes_gmres_solve(S, z2, tol=1e-10)
+    assert info["converged"] and info["iters"] == 0 and float(mu.abs().max()) == 0.0
