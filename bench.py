@@ -45,14 +45,15 @@ FLOP_PER_PAIR_FP64 = 112
 VALU_PER_PAIR_FP64 = 72
 VALU_ISSUE_PER_S = 256 * 2.4e9 * 64
 # the gradient kernel (grad S and grad D of the same densities) evaluates K0
-# and alpha K1/r per pair (the potentials' evaluation with alpha kept inside
-# K1/r: 140 by the same count), takes 1/r^2 = (1/r)^2 from the z > 2 form
-# (1 mul), and accumulates (x-y).n, (alpha^2 K0 + 2A)/r^2 and both gradients:
-# counted from the built kernel's loop, 42 + 2 FLOP per trip of two pairs
-# instead of the potentials' 14, so 140 + 15
-FLOP_PER_PAIR_GRAD = 155
-# modified-Stokes double layer (2x2 stresslet per pair): K0 and alpha K1/r as
-# in the gradient kernel (140 less 7 of accumulation), then 1/r^2 (1),
+# and K1(z)/r per pair as the potentials' tiles do (alpha carried by the staged
+# densities; 105 of their 112 on the z > 20 piece, without their accumulation),
+# then 1/r^2, (x-y).d, (alpha K0 + 2 K1/r)/r^2 and the four accumulations:
+# counted from the built kernel's loop, 51 v_fma (x2), 19 v_mul, 4 v_add,
+# 2 v_rsq = 127 per pair on the z > 20 piece
+FLOP_PER_PAIR_GRAD = 127
+# modified-Stokes double layer (2x2 stresslet per pair): K0 and alpha K1/r from
+# the two-piece fits split at z = 6 (140 by the potentials' count of that form,
+# less 7 of accumulation), then 1/r^2 (1),
 # alpha^2 T1, alpha^4 T2, alpha^2 T3 from the closed forms of App. B (22) and
 # the contraction D_ij w mu_j into two accumulators (31): 187, counted from
 # the source of the z > 2 path (the counters read 191.6 at alpha = 500, 193.0

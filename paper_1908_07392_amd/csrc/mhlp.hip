@@ -774,13 +774,13 @@ __global__ __launch_bounds__(FT_THREADS) void far_grad_fp64(GradArgs A)
     }
     int32_t nxt = (k < kend) ? A.npan[k] : INT_MAX;
     const FarConst fc = far_const(A.alpha);
-    const double a2 = A.alpha * A.alpha;
     double sx = 0.0, sy = 0.0, dx = 0.0, dy = 0.0;
     for (int64_t base = 16 * pb; base < 16 * pe; base += FT_SRC) {
         __syncthreads();
         const int64_t j = base + threadIdx.x;
         if (j < 16 * pe) {
-            const double wj = A.sw[j];
+            /* alpha goes with the charges and dipoles: the pair evaluates K1(z)/r */
+            const double wj = A.alpha * A.sw[j];
             lx[threadIdx.x] = A.sx[j];
             ly[threadIdx.x] = A.sy[j];
             if (GS) lq[threadIdx.x] = wj * A.sigma[j];
@@ -806,17 +806,18 @@ __global__ __launch_bounds__(FT_THREADS) void far_grad_fp64(GradArgs A)
                 const double ex0 = x - lx[l0], ey0 = y - ly[l0];
                 const double ex1 = x - lx[l1], ey1 = y - ly[l1];
                 const double r20 = fma(ex0, ex0, ey0 * ey0), r21 = fma(ex1, ex1, ey1 * ey1);
-                K01 o0, o1;
-                k01_far2<GD, true>(T, fc, r20, r21, o0, o1);
+                K01 o0, o1; /* ak1r holds K1(z)/r; the staged densities carry alpha */
+                k01_far2<GD, true, true, true>(T, fc, r20, r21, o0, o1);
                 if (GS) {
                     const double c0 = o0.ak1r * lq[l0], c1 = o1.ak1r * lq[l1];
                     sx = fma(c1, ex1, fma(c0, ex0, sx));
                     sy = fma(c1, ey1, fma(c0, ey0, sy));
                 }
                 if (GD) {
+                    /* (alpha^2 K0 + 2 alpha K1/r) (x-y).d / r^2, alpha from the dipole */
                     const double n0 = fma(ex0, ldx[l0], ey0 * ldy[l0]), n1 = fma(ex1, ldx[l1], ey1 * ldy[l1]);
-                    const double b0 = n0 * fma(a2, o0.k0, 2.0 * o0.ak1r) * o0.ri2;
-                    const double b1 = n1 * fma(a2, o1.k0, 2.0 * o1.ak1r) * o1.ri2;
+                    const double b0 = n0 * fma(A.alpha, o0.k0, 2.0 * o0.ak1r) * o0.ri2;
+                    const double b1 = n1 * fma(A.alpha, o1.k0, 2.0 * o1.ak1r) * o1.ri2;
                     dx = fma(-b1, ex1, fma(o1.ak1r, ldx[l1], fma(-b0, ex0, fma(o0.ak1r, ldx[l0], dx))));
                     dy = fma(-b1, ey1, fma(o1.ak1r, ldy[l1], fma(-b0, ey0, fma(o0.ak1r, ldy[l0], dy))));
                 }

@@ -309,27 +309,27 @@ __device__ __forceinline__ K01 far_finish(const FarConst &c, double ri, double z
     return o;
 }
 
-/* z <= 2.  K1R: out.ak1r = K1(z)/r, from 1/(alpha r^2) in place of 1/r^2
-   (out.ri2 then holds 1/(alpha r^2): K1R callers use k0 and ak1r only). */
+/* z <= 2.  K1R: out.ak1r = K1(z)/r (the alpha^2 K1/z form over alpha). */
 template <bool SLP, bool DLP, bool K1R = false>
 __device__ __forceinline__ K01 k01_far_small(FarTab T, double r2, const FarConst &c)
 {
-    K01 o{0.0, 0.0, lean_rcp(K1R ? c.a * r2 : r2)};
+    K01 o{0.0, 0.0, lean_rcp(r2)};
     const double q = c.a2q * r2; /* z^2/4 */
     const double lq = lean_log01(T, q); /* 2 log(z/2) */
-    const double s = K1R ? c.a : 4.0 * c.a2q; /* alpha^2, over alpha with K1R */
+    const double s = K1R ? c.a : 4.0 * c.a2q;      /* alpha^2, over alpha with K1R */
+    const double ri2 = K1R ? o.ri2 * c.ia : o.ri2; /* 1/r^2, over alpha with K1R */
     if (SLP && DLP) {
         double di0, dr0;
         const double i0 = hornercd<12>(T->ks_i0, q, di0);
         const double r0 = hornercd<13>(T->ks_r0, q, dr0);
         o.k0 = fma(-0.5 * lq, i0, r0);
         /* alpha^2 K1/z = I0/r^2 + alpha^2 (lq I0'/4 - R0'/2) */
-        o.ak1r = fma(s, fma(0.25 * lq, di0, -0.5 * dr0), i0 * o.ri2);
+        o.ak1r = fma(s, fma(0.25 * lq, di0, -0.5 * dr0), i0 * ri2);
     } else if (SLP) {
         o.k0 = fma(-0.5 * lq, hornerc<12>(T->ks_i0, q), hornerc<13>(T->ks_r0, q));
     } else {
         const double t = fma(0.5 * lq, hornerc<12>(T->ks_i1z, q), -0.25 * hornerc<13>(T->ks_r1, q));
-        o.ak1r = fma(s, t, o.ri2);
+        o.ak1r = fma(s, t, ri2);
     }
     return o;
 }
