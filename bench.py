@@ -51,19 +51,18 @@ VALU_ISSUE_PER_S = 256 * 2.4e9 * 64
 # counted from the built kernel's loop, 51 v_fma (x2), 19 v_mul, 4 v_add,
 # 2 v_rsq = 127 per pair on the z > 20 piece
 FLOP_PER_PAIR_GRAD = 127
-# modified-Stokes double layer (2x2 stresslet per pair): K0 and alpha K1/r from
-# the two-piece fits split at z = 6 (140 by the potentials' count of that form,
-# less 7 of accumulation), then 1/r^2 (1),
-# alpha^2 T1, alpha^4 T2, alpha^2 T3 from the closed forms of App. B (22) and
-# the contraction D_ij w mu_j into two accumulators (31): 187, counted from
-# the source of the z > 2 path (the counters read 191.6 at alpha = 500, 193.0
-# at 50 and 208.6 at 5, where more pairs take the z <= 2 fits)
-FLOP_PER_PAIR_STOKES = 187
+# modified-Stokes double layer (2x2 stresslet per pair): K0 and K1(z)/r from
+# the three-piece fits, alpha K1/r, 1/r^2, the closed forms of alpha^2 T1,
+# alpha^4 T2, alpha^2 T3 (App. B) and the contraction D_ij w mu_j into two
+# accumulators: counted from the built kernel's loop on the z > 20 piece, 60
+# v_fma (x2), 36 v_mul, 6 v_add, 2 v_rsq = 164 (counters 164.7 at alpha = 500)
+FLOP_PER_PAIR_STOKES = 164
 # target gradient of the stresslet double layer (velocity gradient, 4 outputs):
-# the same K0, alpha K1/r, 1/r^2 and A_k (156), B_k = A_k'(r)/r from K0 and A_k
-# (12), and the contraction d_l D_ij w mu_j into four accumulators (71), counted
-# from the source of the z > 2 path
-FLOP_PER_PAIR_STOKES_GRAD = 239
+# the same K0, K1(z)/r, 1/r^2 and A_k, B_k = A_k'(r)/r from K0 and A_k, and the
+# contraction d_l D_ij w mu_j into four accumulators: counted from the built
+# kernel's loop on the z > 20 piece, 77 v_fma (x2), 52 v_mul, 11 v_add,
+# 2 v_rsq = 219 (counters 219.8 at alpha = 500)
+FLOP_PER_PAIR_STOKES_GRAD = 219
 # launch shapes (far-field source splits) chosen by the autotuner on MI355X for
 # the plans of this benchmark; the HBM byte counts below were taken with them
 TUNED_SPLITS = os.path.join(ROOT, "paper_1908_07392_amd", "tuning", "mi355x_far_splits.json")

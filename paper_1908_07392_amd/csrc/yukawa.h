@@ -442,10 +442,10 @@ __device__ __forceinline__ void stk_far2(FarTab T, const FarConst &c, double al2
 {
     const bool sa = c.a2q * r2a <= 1.0, sb = c.a2q * r2b <= 1.0;
     if (!(sa && sb)) {
-        K01 oa, ob;
-        k01_far2_big<true, true>(T, c, r2a, r2b, oa, ob);
-        stk_closed(al2, ial2, r2a, oa.ri2, oa.k0, oa.ak1r, Aa);
-        stk_closed(al2, ial2, r2b, ob.ri2, ob.k0, ob.ak1r, Ab);
+        K01 oa, ob; /* three pieces, K1(z)/r; alpha K1/r for the closed forms */
+        k01_far2_big<true, true, true, true>(T, c, r2a, r2b, oa, ob);
+        stk_closed(al2, ial2, r2a, oa.ri2, oa.k0, c.a * oa.ak1r, Aa);
+        stk_closed(al2, ial2, r2b, ob.ri2, ob.k0, c.a * ob.ak1r, Ab);
     }
     if (sa || sb) {
         if (sa) stk_small(T, c, al2, r2a, Aa);
@@ -493,10 +493,10 @@ __device__ __forceinline__ void stk_far2_ab(FarTab T, const FarConst &c, double 
 {
     const bool sa = c.a2q * r2a <= 1.0, sb = c.a2q * r2b <= 1.0;
     if (!(sa && sb)) {
-        K01 oa, ob;
-        k01_far2_big<true, true>(T, c, r2a, r2b, oa, ob);
-        stk_closed_ab(al2, ial2, r2a, oa.ri2, oa.k0, oa.ak1r, Aa, Ba);
-        stk_closed_ab(al2, ial2, r2b, ob.ri2, ob.k0, ob.ak1r, Ab, Bb);
+        K01 oa, ob; /* three pieces, K1(z)/r; alpha K1/r for the closed forms */
+        k01_far2_big<true, true, true, true>(T, c, r2a, r2b, oa, ob);
+        stk_closed_ab(al2, ial2, r2a, oa.ri2, oa.k0, c.a * oa.ak1r, Aa, Ba);
+        stk_closed_ab(al2, ial2, r2b, ob.ri2, ob.k0, c.a * ob.ak1r, Ab, Bb);
     }
     if (sa || sb) {
         if (sa) stk_small_ab(T, c, al2, r2a, Aa, Ba);
