@@ -408,3 +408,26 @@ def test_zero_rhs_and_loose_tolerance_paths():
     z2 = torch.zeros(2 * g.n_nodes, dtype=torch.float64, device=DEV)
     mu, info = mhlp.stokes_gmres_solve(S, z2, tol=1e-10)
     assert info["converged"] and info["iters"] == 0 and float(mu.abs().max()) == 0.0
+
+
+def test_gmres_long_vectors_circle_modal():
+    """N = 36,864 nodes: Gram-Schmidt over element slices of 512 (several
+    elements per thread, 72 slices) from the first step; a right-hand side with
+    sixteen Fourier modes on the circle, whose exact solution divides each mode
+    by its eigenvalue of 1/2 I + D."""
+    R, alpha = 1.0, 10.0
+    g = wl.discretize(wl.Curve("circle", R=R), 2304)
+    x = alpha * R
+
+    def lam(n):
+        return x * sp.ive(n, x) * 0.5 * (sp.kve(n - 1, x) + sp.kve(n + 1, x))
+
+    rng = np.random.default_rng(11)
+    a, c = rng.standard_normal(16), rng.standard_normal(16)
+    b = sum(a[n] * np.cos(n * g.theta) + c[n] * np.sin(n * g.theta) for n in range(16))
+    exact = sum((a[n] * np.cos(n * g.theta) + c[n] * np.sin(n * g.theta)) / lam(n) for n in range(16))
+    P = mhlp.Plan(_geom(g), alpha)
+    mu, info = mhlp.gmres_solve(P, _t(b), tol=1e-12)
+    print(info)
+    assert g.n_nodes == 36864 and info["converged"] and info["iters"] >= 5
+    assert np.max(np.abs(mu.cpu().numpy() - exact)) < 1e-9 * np.max(np.abs(exact))
