@@ -59,7 +59,9 @@ struct FmmDev {
     const int32_t *wbox, *wt0;               /* leaf work items: box, first sorted target (<= FMM_TILE each) */
     const double *lx, *ly, *lw, *lnx, *lny;  /* sources in leaf order */
     const int32_t *lpan;                     /* panel of each sorted source (plans) */
-    cplx *mexp, *lexp;                       /* expansions [level][field][box][p+1] */
+    cplx *mexp, *lexp;                       /* expansions [level][field][box][p+1]; lexp holds nch[l] */
+    int64_t lch;                             /* partial local expansions, lch apart (their sum is L) */
+    int nch[FMM_LMAX + 1];                   /* partials (blocks per box) of level l's downward pass */
     const cplx *tab;                         /* translation tables */
 };
 
@@ -233,6 +235,13 @@ __global__ __launch_bounds__(256) void fmm_m2m_kernel(FmmDev T, int l)
    multipole and table row staged in LDS); per-wave sums are added in wave
    order, so the result does not depend on timing. */
 constexpr int FMM_DW = 8;
+/* blocks per box in the downward pass of the coarse levels (fewer than
+   FMM_CH_BOXES boxes, too few blocks to fill the chip): block c of nch takes
+   interactions c, c + nch, ... of the box's list (one round of FMM_DW waves for
+   up to 27 entries) and writes partial local expansion c; chunk 0 also carries
+   the L2L term.  The consumers (the children's L2L, the leaf's L2P) add the
+   level's partials in order.  Finer levels run one block per box. */
+constexpr int FMM_CH = 4, FMM_CH_BOXES = 256;
 
 template <bool SLP, bool DLP>
 __global__ __launch_bounds__(64 * FMM_DW) void fmm_down_kernel(FmmDev T, int l)
@@ -242,7 +251,7 @@ __global__ __launch_bounds__(64 * FMM_DW) void fmm_down_kernel(FmmDev T, int l)
     __shared__ double pw[FMM_PMAX + 1], pr[FMM_PMAX + 1];
     __shared__ int il_box[27], il_off[27], il_flag[36], n_il;
     const int p = T.p, nb = 1 << l, rl = 3 * p + 1;
-    const int box = blockIdx.x, tid = threadIdx.x, w = tid >> 6, m = tid & 63;
+    const int box = blockIdx.x, chunk = blockIdx.y, tid = threadIdx.x, w = tid >> 6, m = tid & 63;
     if (T.tocc[lev4(l) + box] == 0) return; /* whole block */
     const int ix = box % nb, iy = box / nb, px = ix >> 1, py = iy >> 1;
     const double s = T.sig[l];
@@ -272,13 +281,19 @@ __global__ __launch_bounds__(64 * FMM_DW) void fmm_down_kernel(FmmDev T, int l)
         n_il = n;
     }
     const int64_t nbx = (int64_t)nb * nb;
-    const bool l2l = l > T.lstart;
+    const bool l2l = l > T.lstart && chunk == 0;
     if (l2l) {
         const int pnb = nb >> 1, pb = py * pnb + px, ch = (ix & 1) + 2 * (iy & 1);
         const int64_t pbx = (int64_t)pnb * pnb;
         if (tid <= p) {
-            lm[0][0][tid] = SLP ? T.lexp[T.eoff[l - 1] + (0 * pbx + pb) * (p + 1) + tid] : mk(0.0, 0.0);
-            lm[0][1][tid] = DLP ? T.lexp[T.eoff[l - 1] + (1 * pbx + pb) * (p + 1) + tid] : mk(0.0, 0.0);
+            cplx a = mk(0.0, 0.0), b = mk(0.0, 0.0);
+            for (int c = 0; c < T.nch[l - 1]; ++c) {
+                const cplx *lp = T.lexp + c * T.lch + T.eoff[l - 1];
+                if (SLP) a = a + lp[(0 * pbx + pb) * (p + 1) + tid];
+                if (DLP) b = b + lp[(1 * pbx + pb) * (p + 1) + tid];
+            }
+            lm[0][0][tid] = a;
+            lm[0][1][tid] = b;
         }
         for (int j = tid; j < rl; j += 64 * FMM_DW) lt[0][j] = T.tab[T.tll[l - 1] + (int64_t)ch * rl + j];
     }
@@ -295,10 +310,13 @@ __global__ __launch_bounds__(64 * FMM_DW) void fmm_down_kernel(FmmDev T, int l)
     }
     __syncthreads(); /* lm[0], lt[0] are reused below */
     cplx acce[2] = {mk(0.0, 0.0), mk(0.0, 0.0)};
-    const int nil = n_il, nr = (nil + FMM_DW - 1) / FMM_DW;
+    /* this block's share of the list: entries chunk, chunk + FMM_CH, ... */
+    const int nchk = (int)gridDim.y;
+    const int nil = n_il, nk = nil > chunk ? (nil - chunk + nchk - 1) / nchk : 0;
+    const int nr = (nk + FMM_DW - 1) / FMM_DW;
     for (int r = 0; r < nr; ++r) {
-        const int k = r * FMM_DW + w;
-        const bool act = k < nil;
+        const int kc = r * FMM_DW + w, k = chunk + nchk * kc;
+        const bool act = kc < nk;
         if (act) {
             const int sb = il_box[k];
             if (m <= p) {
@@ -358,8 +376,9 @@ __global__ __launch_bounds__(64 * FMM_DW) void fmm_down_kernel(FmmDev T, int l)
             s0 = s0 + part[ww][0][m];
             s1 = s1 + part[ww][1][m];
         }
-        if (SLP) T.lexp[T.eoff[l] + (0 * nbx + box) * (p + 1) + m] = s0;
-        if (DLP) T.lexp[T.eoff[l] + (1 * nbx + box) * (p + 1) + m] = s1;
+        cplx *lo = T.lexp + chunk * T.lch + T.eoff[l];
+        if (SLP) lo[(0 * nbx + box) * (p + 1) + m] = s0;
+        if (DLP) lo[(1 * nbx + box) * (p + 1) + m] = s1;
     }
 }
 
@@ -403,8 +422,14 @@ __global__ __launch_bounds__(64 * FMM_LW) void fmm_leaf_kernel(FmmDev T, FarArgs
     const bool local = T.lstart <= L;
     if (local && tid <= p) {
         const int64_t nbx = (int64_t)nb * nb;
-        if (SLP) lcs[tid] = T.lexp[T.eoff[L] + (0 * nbx + box) * (p + 1) + tid];
-        if (DLP) lcd[tid] = T.lexp[T.eoff[L] + (1 * nbx + box) * (p + 1) + tid];
+        cplx a = mk(0.0, 0.0), b = mk(0.0, 0.0);
+        for (int c = 0; c < T.nch[L]; ++c) { /* the partial local expansions, in order */
+            const cplx *lp = T.lexp + c * T.lch + T.eoff[L];
+            if (SLP) a = a + lp[(0 * nbx + box) * (p + 1) + tid];
+            if (DLP) b = b + lp[(1 * nbx + box) * (p + 1) + tid];
+        }
+        if (SLP) lcs[tid] = a;
+        if (DLP) lcd[tid] = b;
     }
     /* the neighbourhood's source ranges (one thread per box) and their tile
        counts, in a fixed order */

@@ -1905,7 +1905,7 @@ static mhlp_status fmm_build(FmmTree *F, const FmmGeom &G, int L, int p, double 
         TRY(F->alloc(&d_lpan, N));
     }
     TRY(F->alloc(&d_mexp, eo));
-    TRY(F->alloc(&d_lexp, eo));
+    TRY(F->alloc(&d_lexp, mhlp::FMM_CH * eo));
     TRY(F->alloc(&d_tab, to));
     mhlp::FmmRow *d_rows = nullptr;
     double *d_scr = nullptr;
@@ -1957,6 +1957,8 @@ static mhlp_status fmm_build(FmmTree *F, const FmmGeom &G, int L, int p, double 
     T.lpan = d_lpan;
     T.mexp = d_mexp;
     T.lexp = d_lexp;
+    T.lch = eo;
+    for (int l = 0; l <= mhlp::FMM_LMAX; ++l) T.nch[l] = ((int64_t)1 << (2 * l)) < mhlp::FMM_CH_BOXES ? mhlp::FMM_CH : 1;
     T.tab = d_tab;
     F->order = p;
     F->level = L;
@@ -1973,7 +1975,7 @@ static void fmm_passes(const FmmTree *F, const double *sigma, const double *mu, 
     for (int l = T.L - 1; l >= T.lstart; --l)
         mhlp::fmm_m2m_kernel<SLP, DLP><<<(unsigned)(1u << (2 * l)), 256, 0, st>>>(T, l);
     for (int l = T.lstart; l <= T.L; ++l)
-        mhlp::fmm_down_kernel<SLP, DLP><<<(unsigned)(1u << (2 * l)), 64 * mhlp::FMM_DW, 0, st>>>(T, l);
+        mhlp::fmm_down_kernel<SLP, DLP><<<dim3(1u << (2 * l), (unsigned)T.nch[l]), 64 * mhlp::FMM_DW, 0, st>>>(T, l);
 }
 
 template <bool SLP, bool DLP>
