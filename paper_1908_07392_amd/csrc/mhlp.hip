@@ -1317,17 +1317,6 @@ __global__ __launch_bounds__(256) void multi_dot_kernel(const double *__restrict
     if (threadIdx.x == 0) out[c] = red[0];
 }
 
-/* w[i] -= sum_{c<ncol} h[c] V[c*ld + i] */
-__global__ void sub_combo_kernel(const double *__restrict__ V, int64_t ld, int ncol, const double *__restrict__ h,
-                                 double *__restrict__ w, int64_t N)
-{
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    double s = w[i];
-    for (int c = 0; c < ncol; ++c) s = fma(-h[c], V[c * ld + i], s);
-    w[i] = s;
-}
-
 /* x[i] += sum_{c<ncol} y[c] V[c*ld + i] */
 __global__ void add_combo_kernel(const double *__restrict__ V, int64_t ld, int ncol, const double *__restrict__ yv,
                                  double *__restrict__ x, int64_t N)
