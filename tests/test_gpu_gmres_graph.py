@@ -89,7 +89,7 @@ def test_split_change_invalidates_step_graphs(starfish):
     b, ref = d["rhs"][2], d["refs"][2]
     base = P.nsplit
     try:
-        for ns in (1, 3, 10):
+        for ns in (1, 3, 10, d["g"].n_panels):  # the last: one panel per split
             P.set_split(ns)
             mu, info = mhlp.gmres_solve(P, _t(b), tol=1e-10, restart=50)
             assert info["converged"] and _relerr(mu.cpu().numpy(), ref) < 1e-8
