@@ -108,6 +108,12 @@ struct mhlp_plan {
     bool stokes = false;      /* modified-Stokes (stresslet) plan: operator on [2][N] densities */
     double *wstk = nullptr;   /* stokes: [4][nnz][16] stresslet weights (D11, D12, D21, D22)   */
     mhlp::FmmTree *fmm = nullptr; /* off-surface scalar plans: FMM far field (mhlp_plan_set_fmm) */
+    /* on-surface scalar plans up to SYM_NMAX nodes: the double layer's far sum
+       with each unordered pair evaluated once (sym_far_kernel) */
+    int2 *sym_tiles = nullptr;   /* (row block, column chunk) of each tile */
+    int32_t sym_ntiles = 0;
+    double *sym_p1 = nullptr;    /* [column chunks][N] row sums */
+    double *sym_p2 = nullptr;    /* [row blocks][N] column sums */
     double *wstkg = nullptr;  /* stokes, off-surface, built on first use: [8][nnz][16] stresslet
                                  gradient weights, block (2a + l) 2 + j = d u_a/d x_l per mu_j */
     double *stk_flux = nullptr; /* stokes: device scalar sum_j w_j mu_j.n_j / |Gamma|           */
@@ -545,6 +551,166 @@ __global__ __launch_bounds__(L == 1 ? 256 : FZ_TG * L) void far_finalize(FarArgs
         if (A.half_term != 0.0) v = fma(A.half_term, mu[i], v);
         A.ud[o] = v;
     }
+}
+
+/* ---- on-surface double layer, each unordered far pair once ----
+   K1(z)/r depends on the pair only through r, so one evaluation serves the
+   term of source j at node i and of source i at node j.  Tiles pair a block of
+   SYM_R = 256 row nodes (16 panels) with a chunk of SYM_C = 16 column nodes
+   (one panel; small tiles keep enough blocks in flight); tile (I, J) exists
+   when the chunk does not start before the block (column panels >= 16 I), and on the block's own chunks only row < column
+   counts.  The row node takes the column terms (unless the column panel is
+   listed near it) into p1[J][i]; each column node takes the row terms (unless
+   the row's panel is listed near the column node), summed over lanes by a
+   butterfly and over waves in order, into p2[I][j].  Every pair of distinct
+   nodes is evaluated in exactly one tile. */
+constexpr int SYM_R = 256, SYM_C = 16, SYM_RP = SYM_R / 16, SYM_CP = SYM_C / 16, SYM_NMAX = 8192;
+
+/* sum over the 64 lanes of a wave by a fixed butterfly (every lane gets it) */
+__device__ __forceinline__ double gsf_wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+
+struct SymArgs {
+    FarArgs A;
+    const int2 *tiles;
+    double *p1, *p2;
+};
+
+__global__ __launch_bounds__(SYM_R) void sym_far_kernel(SymArgs S)
+{
+    const FarArgs &A = S.A;
+    __shared__ double cx[SYM_C], cy[SYM_C], cdx[SYM_C], cdy[SYM_C];
+    __shared__ uint32_t cmask[SYM_C];
+    __shared__ double red[SYM_R / 64][SYM_C];
+    const double *mu;
+    if (!far_density(A, mu)) return; /* the same for the whole launch */
+    const int2 tl = S.tiles[blockIdx.x];
+    const int I = tl.x, J = tl.y, t = threadIdx.x, wv = t >> 6, ln = t & 63;
+    const int64_t N = A.N, i = (int64_t)I * SYM_R + t, j0 = (int64_t)J * SYM_C;
+    const int pb = SYM_RP * I; /* first panel of the row block */
+    if (t < SYM_C) {
+        const int64_t j = j0 + t;
+        double xj = 0.0, yj = 0.0, dx = 0.0, dy = 0.0;
+        uint32_t msk = 0;
+        if (j < N) {
+            xj = A.sx[j];
+            yj = A.sy[j];
+            const double m = (A.alpha * A.sw[j]) * mu[j];
+            dx = m * A.snx[j];
+            dy = m * A.sny[j];
+            for (int32_t q = A.nptr[j]; q < A.nptr[j + 1]; ++q) {
+                const int32_t pp = A.npan[q] - pb;
+                if (pp >= 0 && pp < SYM_RP) msk |= 1u << pp;
+            }
+        }
+        cx[t] = xj;
+        cy[t] = yj;
+        cdx[t] = dx;
+        cdy[t] = dy;
+        cmask[t] = msk;
+    }
+    for (int c = t; c < (SYM_R / 64) * SYM_C; c += SYM_R) red[c / SYM_C][c % SYM_C] = 0.0;
+    const bool valid = i < N;
+    double x = 0.0, y = 0.0, dix = 0.0, diy = 0.0;
+    uint32_t rnear = 0; /* bit k: column panel SYM_CP J + k listed near row i */
+    int kp = 0;         /* row panel within the block */
+    if (valid) {
+        x = A.sx[i];
+        y = A.sy[i];
+        const double m = (A.alpha * A.sw[i]) * mu[i];
+        dix = m * A.snx[i];
+        diy = m * A.sny[i];
+        kp = (int)(i / 16) - pb;
+        for (int32_t q = A.nptr[i]; q < A.nptr[i + 1]; ++q) {
+            const int32_t pp = A.npan[q] - SYM_CP * J;
+            if (pp >= 0 && pp < SYM_CP) rnear |= 1u << pp;
+        }
+    }
+    const bool diag = SYM_CP * J < pb + SYM_RP; /* the chunk lies in the row block */
+    __syncthreads();
+    const FarConst fc = far_const(A.alpha);
+    double acc = 0.0;
+    const int ncol = (int)min((int64_t)SYM_C, N - j0);
+    /* columns in groups of 8: the row terms accumulate as they come, the 8
+       column terms of a group are reduced over the lanes together (8
+       independent butterflies) */
+#pragma unroll 1
+    for (int s0 = 0; s0 < ncol; s0 += 8) {
+        double v[8];
+#pragma unroll
+        for (int h = 0; h < 8; h += 2) {
+            const FarTab T = far_table();
+            const int s = s0 + h;
+            const int64_t ja = j0 + s, jb = ja + 1;
+            const double ex0 = x - cx[s], ey0 = y - cy[s], ex1 = x - cx[s + 1], ey1 = y - cy[s + 1];
+            /* row and column terms wanted for the two columns (s, s + 1 share a panel) */
+            const bool rfar = valid && !((rnear >> (s >> 4)) & 1u);
+            const bool r0 = rfar && (!diag || i < ja), r1 = rfar && (!diag || i < jb);
+            const bool c0 = valid && !((cmask[s] >> kp) & 1u) && (!diag || i < ja);
+            const bool c1 = valid && !((cmask[s + 1] >> kp) & 1u) && (!diag || i < jb);
+            double r20 = fma(ex0, ex0, ey0 * ey0), r21 = fma(ex1, ex1, ey1 * ey1);
+            r20 = (r0 || c0) ? r20 : 1.0; /* unused pairs (the node itself among them) */
+            r21 = (r1 || c1) ? r21 : 1.0;
+            K01 o0, o1;
+            k01_far2<false, true, true, true>(T, fc, r20, r21, o0, o1);
+            if (r0) acc = fma(o0.ak1r, fma(ex0, cdx[s], ey0 * cdy[s]), acc);
+            if (r1) acc = fma(o1.ak1r, fma(ex1, cdx[s + 1], ey1 * cdy[s + 1]), acc);
+            v[h] = c0 ? -o0.ak1r * fma(ex0, dix, ey0 * diy) : 0.0;
+            v[h + 1] = c1 ? -o1.ak1r * fma(ex1, dix, ey1 * diy) : 0.0;
+        }
+#pragma unroll
+        for (int h = 0; h < 8; ++h) v[h] = gsf_wave_sum(v[h]);
+        if (ln == 0) {
+#pragma unroll
+            for (int h = 0; h < 8; ++h) red[wv][s0 + h] = v[h];
+        }
+    }
+    __syncthreads();
+    if (t < ncol) {
+        double sc = red[0][t];
+        for (int q = 1; q < SYM_R / 64; ++q) sc += red[q][t];
+        S.p2[(int64_t)I * N + j0 + t] = sc;
+    }
+    if (valid) S.p1[(int64_t)J * N + i] = acc;
+}
+
+/* node n: row sums of the chunks from its block on, column sums of the blocks
+   up to its own, then the near corrections, 1/(2 pi) and the identity term;
+   FZ_L lanes per node as in far_finalize */
+__global__ __launch_bounds__(FZ_TG *FZ_L) void sym_finalize(SymArgs S, int nchunk)
+{
+    const FarArgs &A = S.A;
+    __shared__ double red[2][FZ_L][FZ_TG];
+    const double *mu;
+    if (!far_density(A, mu)) return;
+    const int g = threadIdx.x % FZ_TG, l = threadIdx.x / FZ_TG;
+    const int64_t n = blockIdx.x * (int64_t)FZ_TG + g;
+    double fd = 0.0, nd = 0.0;
+    if (n < A.N) {
+        const int B = (int)(n / SYM_R);
+        for (int c = SYM_RP * B / SYM_CP + l; c < nchunk; c += FZ_L) fd += S.p1[(int64_t)c * A.N + n];
+        for (int b = l; b <= B; b += FZ_L) fd += S.p2[(int64_t)b * A.N + n];
+        for (int32_t q = A.nptr[n]; q < A.nptr[n + 1]; ++q) {
+            const int64_t p = A.npan[q];
+            if (p < 0) continue;
+            nd = fma(A.wdl[16 * (int64_t)q + l], mu[16 * p + l], nd);
+        }
+    }
+    red[0][l][g] = fd;
+    red[1][l][g] = nd;
+    __syncthreads();
+    if (l != 0 || n >= A.N) return;
+    for (int q = 1; q < FZ_L; ++q) {
+        fd += red[0][q][g];
+        nd += red[1][q][g];
+    }
+    double v = fma(INV_2PI, fd, nd);
+    if (A.half_term != 0.0) v = fma(A.half_term, mu[n], v);
+    A.ud[n] = v;
 }
 
 template <bool SLP, bool DLP, bool SPLIT>
@@ -1402,11 +1568,6 @@ constexpr int GSF_T = 1024, GSF_W = GSF_T / 64, GSF_RMAX = 256;
 constexpr int64_t GSF_NMAX = 4096;
 constexpr int GSF_STEPS = 3;
 
-__device__ __forceinline__ double gsf_wave_sum(double v)
-{
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
-}
 
 /* hs[c] = V_c . w for c < ncol (LDS) */
 __device__ void gsf_dots(const double *__restrict__ V, int64_t ld, const double *__restrict__ w, int64_t N, int ncol,
@@ -2091,7 +2252,7 @@ extern "C" mhlp_status mhlp_plan_destroy(mhlp_plan *P)
     if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
     void *ptrs[] = {P->near_ptr, P->near_panel, P->near_tgt, P->near_ts, P->wslp,  P->wdlp,    P->ws,
                     P->hdev,     P->part,       P->gdev,     P->perm,    P->wgrad, P->wstk,    P->stk_flux,
-                    P->wstkg};
+                    P->wstkg,    P->sym_tiles,  P->sym_p1,   P->sym_p2};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete P->fmm;
@@ -2207,6 +2368,21 @@ static mhlp_status plan_create_impl(const mhlp_geometry *g, double alpha, const 
             mhlp_plan_destroy(P);
             return s;
         }
+    }
+    if (P->onsurf && !P->stokes && g->N <= SYM_NMAX && g->N % 16 == 0) {
+        /* tiles of the symmetric on-surface double layer (row block I, column
+           chunk J from the block's first panel on) */
+        const int64_t nrb = (g->N + SYM_R - 1) / SYM_R, ncc = (g->N + SYM_C - 1) / SYM_C;
+        std::vector<int2> tiles;
+        for (int64_t I = 0; I < nrb; ++I)
+            for (int64_t J = SYM_RP * I / SYM_CP; J < ncc; ++J) tiles.push_back(make_int2((int)I, (int)J));
+        P->sym_ntiles = (int32_t)tiles.size();
+        if ((s = dalloc(&P->sym_tiles, (int64_t)tiles.size())) || (s = dalloc(&P->sym_p1, ncc * g->N)) ||
+            (s = dalloc(&P->sym_p2, nrb * g->N))) {
+            mhlp_plan_destroy(P);
+            return s;
+        }
+        HIPCHECK(hipMemcpy(P->sym_tiles, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice));
     }
     int32_t *cnt = nullptr;
     if ((s = dalloc(&cnt, M + 1)) || (s = dalloc(&P->near_ptr, M + 1))) {
@@ -2386,6 +2562,13 @@ static mhlp_status launch_far(const mhlp_plan *P, const double *sigma, const dou
     A.gs = gs;
     A.jstride = jstride;
     A.perm = P->perm;
+    if (P->sym_tiles && !sigma && mu && precision == MHLP_FP64) {
+        SymArgs S{A, P->sym_tiles, P->sym_p1, P->sym_p2};
+        sym_far_kernel<<<(unsigned)P->sym_ntiles, SYM_R, 0, st>>>(S);
+        sym_finalize<<<nblocks(A.M, FZ_TG), FZ_TG * FZ_L, 0, st>>>(S, (int)((g->N + SYM_C - 1) / SYM_C));
+        HIPCHECK(hipGetLastError());
+        return MHLP_OK;
+    }
     if (P->fmm && precision == MHLP_FP64 && !gs) {
         if (sigma && mu)
             fmm_far_t<true, true>(P->fmm, A, st);
