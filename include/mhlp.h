@@ -113,7 +113,10 @@ mhlp_status mhlp_plan_info(const mhlp_plan *plan, int64_t *n_targets, int64_t *n
    nsplit ranges of panels evaluated by separate blocks (partial sums added
    in fixed order, so results do not depend on nsplit beyond rounding); the
    default aims at about 8192 blocks of 256 targets with at least 2 panels
-   per split.  set_split may reallocate the plan's
+   per split.  The FP64 double layer of an on-surface scalar plan of up to
+   8192 nodes (the BIE operator, GMRES) evaluates each unordered pair once
+   on tiles of its own and does not use the split (its autotuning, layers 4
+   in FP64, then finds all counts equal).  set_split may reallocate the plan's
    partial-sum buffer (it synchronises the device then).
    mhlp_plan_autotune times the far evaluation (layers: 1 SLP, 2 DLP, 3 both,
    4 the on-surface BIE operator, 5 the gradients of both, off-surface, 6 the
