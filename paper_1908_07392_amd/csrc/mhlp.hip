@@ -114,6 +114,8 @@ struct mhlp_plan {
     int32_t sym_ntiles = 0;
     double *sym_p1 = nullptr;    /* [column chunks][N] row sums */
     double *sym_p2 = nullptr;    /* [row blocks][N] column sums */
+    uint32_t *sym_bits = nullptr; /* [N][sym_nw] near panels of each node as bits */
+    int32_t sym_nw = 0;
     double *wstkg = nullptr;  /* stokes, off-surface, built on first use: [8][nnz][16] stresslet
                                  gradient weights, block (2a + l) 2 + j = d u_a/d x_l per mu_j */
     double *stk_flux = nullptr; /* stokes: device scalar sum_j w_j mu_j.n_j / |Gamma|           */
@@ -578,7 +580,24 @@ struct SymArgs {
     FarArgs A;
     const int2 *tiles;
     double *p1, *p2;
+    const uint32_t *bits; /* [N][nw] near panels of each node */
+    int nw;
 };
+static_assert(SYM_RP == 16 && SYM_CP == 1, "the near masks below read 16 row panels and one column panel");
+
+/* per node, its near panels as a bit set of nw words */
+__global__ void near_bits_kernel(const int32_t *__restrict__ nptr, const int32_t *__restrict__ npan, int64_t M,
+                                 int nw, uint32_t *__restrict__ bits)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    uint32_t *b = bits + i * nw;
+    for (int k = 0; k < nw; ++k) b[k] = 0u;
+    for (int32_t q = nptr[i]; q < nptr[i + 1]; ++q) {
+        const int32_t p = npan[q];
+        if (p >= 0) b[p >> 5] |= 1u << (p & 31);
+    }
+}
 
 __global__ __launch_bounds__(SYM_R) void sym_far_kernel(SymArgs S)
 {
@@ -602,10 +621,7 @@ __global__ __launch_bounds__(SYM_R) void sym_far_kernel(SymArgs S)
             const double m = (A.alpha * A.sw[j]) * mu[j];
             dx = m * A.snx[j];
             dy = m * A.sny[j];
-            for (int32_t q = A.nptr[j]; q < A.nptr[j + 1]; ++q) {
-                const int32_t pp = A.npan[q] - pb;
-                if (pp >= 0 && pp < SYM_RP) msk |= 1u << pp;
-            }
+            msk = (S.bits[j * S.nw + (pb >> 5)] >> (pb & 31)) & 0xFFFFu; /* the block's 16 panels */
         }
         cx[t] = xj;
         cy[t] = yj;
@@ -625,10 +641,7 @@ __global__ __launch_bounds__(SYM_R) void sym_far_kernel(SymArgs S)
         dix = m * A.snx[i];
         diy = m * A.sny[i];
         kp = (int)(i / 16) - pb;
-        for (int32_t q = A.nptr[i]; q < A.nptr[i + 1]; ++q) {
-            const int32_t pp = A.npan[q] - SYM_CP * J;
-            if (pp >= 0 && pp < SYM_CP) rnear |= 1u << pp;
-        }
+        rnear = (S.bits[i * S.nw + (J >> 5)] >> (J & 31)) & 1u; /* column panel J */
     }
     const bool diag = SYM_CP * J < pb + SYM_RP; /* the chunk lies in the row block */
     __syncthreads();
@@ -2252,7 +2265,7 @@ extern "C" mhlp_status mhlp_plan_destroy(mhlp_plan *P)
     if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
     void *ptrs[] = {P->near_ptr, P->near_panel, P->near_tgt, P->near_ts, P->wslp,  P->wdlp,    P->ws,
                     P->hdev,     P->part,       P->gdev,     P->perm,    P->wgrad, P->wstk,    P->stk_flux,
-                    P->wstkg,    P->sym_tiles,  P->sym_p1,   P->sym_p2};
+                    P->wstkg,    P->sym_tiles,  P->sym_p1,   P->sym_p2,  P->sym_bits};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete P->fmm;
@@ -2377,8 +2390,9 @@ static mhlp_status plan_create_impl(const mhlp_geometry *g, double alpha, const 
         for (int64_t I = 0; I < nrb; ++I)
             for (int64_t J = SYM_RP * I / SYM_CP; J < ncc; ++J) tiles.push_back(make_int2((int)I, (int)J));
         P->sym_ntiles = (int32_t)tiles.size();
+        P->sym_nw = (int32_t)((g->Np + 31) / 32);
         if ((s = dalloc(&P->sym_tiles, (int64_t)tiles.size())) || (s = dalloc(&P->sym_p1, ncc * g->N)) ||
-            (s = dalloc(&P->sym_p2, nrb * g->N))) {
+            (s = dalloc(&P->sym_p2, nrb * g->N)) || (s = dalloc(&P->sym_bits, (int64_t)P->sym_nw * g->N))) {
             mhlp_plan_destroy(P);
             return s;
         }
@@ -2456,6 +2470,15 @@ static mhlp_status plan_create_impl(const mhlp_geometry *g, double alpha, const 
         P->fill_mismatch = mism;
     }
     (void)hipFree(cnt);
+    if (P->sym_bits) {
+        near_bits_kernel<<<nblocks(M, 256), 256, 0, st>>>(P->near_ptr, P->near_panel, M, P->sym_nw, P->sym_bits);
+        hipError_t eb = hipGetLastError();
+        if (eb == hipSuccess) eb = hipStreamSynchronize(st); /* later calls may come on other streams */
+        if (eb != hipSuccess) {
+            mhlp_plan_destroy(P);
+            return fail(MHLP_HIP_ERROR, std::string("plan_create near bits: ") + hipGetErrorString(eb));
+        }
+    }
     if (stokes) {
         /* W term: device scalar for the flux, host 1/|Gamma| */
         if ((s = dalloc(&P->stk_flux, 8))) {
@@ -2563,7 +2586,7 @@ static mhlp_status launch_far(const mhlp_plan *P, const double *sigma, const dou
     A.jstride = jstride;
     A.perm = P->perm;
     if (P->sym_tiles && !sigma && mu && precision == MHLP_FP64) {
-        SymArgs S{A, P->sym_tiles, P->sym_p1, P->sym_p2};
+        SymArgs S{A, P->sym_tiles, P->sym_p1, P->sym_p2, P->sym_bits, P->sym_nw};
         sym_far_kernel<<<(unsigned)P->sym_ntiles, SYM_R, 0, st>>>(S);
         sym_finalize<<<nblocks(A.M, FZ_TG), FZ_TG * FZ_L, 0, st>>>(S, (int)((g->N + SYM_C - 1) / SYM_C));
         HIPCHECK(hipGetLastError());
