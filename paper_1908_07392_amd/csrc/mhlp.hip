@@ -599,6 +599,53 @@ __global__ void near_bits_kernel(const int32_t *__restrict__ nptr, const int32_t
     }
 }
 
+/* the column loop of sym_far_kernel; DIAG: the tile's chunk lies in its row
+   block, where only row < column counts */
+template <bool DIAG>
+__device__ __forceinline__ double sym_columns(const FarArgs &A, const FarConst &fc, int ncol, int64_t i, int64_t j0,
+                                              bool valid, double x, double y, double dix, double diy, uint32_t rnear,
+                                              int kp, const double *cx, const double *cy, const double *cdx,
+                                              const double *cdy, const uint32_t *cmask, double (*red)[SYM_C], int wv,
+                                              int ln)
+{
+    double acc = 0.0;
+    /* columns in groups of 8: the row terms accumulate as they come, the 8
+       column terms of a group are reduced over the lanes together (8
+       independent butterflies) */
+#pragma unroll 1
+    for (int s0 = 0; s0 < ncol; s0 += 8) {
+        double v[8];
+#pragma unroll
+        for (int h = 0; h < 8; h += 2) {
+            const FarTab T = far_table();
+            const int s = s0 + h;
+            const int64_t ja = j0 + s, jb = ja + 1;
+            const double ex0 = x - cx[s], ey0 = y - cy[s], ex1 = x - cx[s + 1], ey1 = y - cy[s + 1];
+            /* row and column terms wanted for the two columns (s, s + 1 share a panel) */
+            const bool rfar = valid && !((rnear >> (s >> 4)) & 1u);
+            const bool r0 = rfar && (!DIAG || i < ja), r1 = rfar && (!DIAG || i < jb);
+            const bool c0 = valid && !((cmask[s] >> kp) & 1u) && (!DIAG || i < ja);
+            const bool c1 = valid && !((cmask[s + 1] >> kp) & 1u) && (!DIAG || i < jb);
+            double r20 = fma(ex0, ex0, ey0 * ey0), r21 = fma(ex1, ex1, ey1 * ey1);
+            r20 = (r0 || c0) ? r20 : 1.0; /* unused pairs (the node itself among them) */
+            r21 = (r1 || c1) ? r21 : 1.0;
+            K01 o0, o1;
+            k01_far2<false, true, true, true>(T, fc, r20, r21, o0, o1);
+            if (r0) acc = fma(o0.ak1r, fma(ex0, cdx[s], ey0 * cdy[s]), acc);
+            if (r1) acc = fma(o1.ak1r, fma(ex1, cdx[s + 1], ey1 * cdy[s + 1]), acc);
+            v[h] = c0 ? -o0.ak1r * fma(ex0, dix, ey0 * diy) : 0.0;
+            v[h + 1] = c1 ? -o1.ak1r * fma(ex1, dix, ey1 * diy) : 0.0;
+        }
+#pragma unroll
+        for (int h = 0; h < 8; ++h) v[h] = gsf_wave_sum(v[h]);
+        if (ln == 0) {
+#pragma unroll
+            for (int h = 0; h < 8; ++h) red[wv][s0 + h] = v[h];
+        }
+    }
+    return acc;
+}
+
 __global__ __launch_bounds__(SYM_R) void sym_far_kernel(SymArgs S)
 {
     const FarArgs &A = S.A;
@@ -646,42 +693,11 @@ __global__ __launch_bounds__(SYM_R) void sym_far_kernel(SymArgs S)
     const bool diag = SYM_CP * J < pb + SYM_RP; /* the chunk lies in the row block */
     __syncthreads();
     const FarConst fc = far_const(A.alpha);
-    double acc = 0.0;
     const int ncol = (int)min((int64_t)SYM_C, N - j0);
-    /* columns in groups of 8: the row terms accumulate as they come, the 8
-       column terms of a group are reduced over the lanes together (8
-       independent butterflies) */
-#pragma unroll 1
-    for (int s0 = 0; s0 < ncol; s0 += 8) {
-        double v[8];
-#pragma unroll
-        for (int h = 0; h < 8; h += 2) {
-            const FarTab T = far_table();
-            const int s = s0 + h;
-            const int64_t ja = j0 + s, jb = ja + 1;
-            const double ex0 = x - cx[s], ey0 = y - cy[s], ex1 = x - cx[s + 1], ey1 = y - cy[s + 1];
-            /* row and column terms wanted for the two columns (s, s + 1 share a panel) */
-            const bool rfar = valid && !((rnear >> (s >> 4)) & 1u);
-            const bool r0 = rfar && (!diag || i < ja), r1 = rfar && (!diag || i < jb);
-            const bool c0 = valid && !((cmask[s] >> kp) & 1u) && (!diag || i < ja);
-            const bool c1 = valid && !((cmask[s + 1] >> kp) & 1u) && (!diag || i < jb);
-            double r20 = fma(ex0, ex0, ey0 * ey0), r21 = fma(ex1, ex1, ey1 * ey1);
-            r20 = (r0 || c0) ? r20 : 1.0; /* unused pairs (the node itself among them) */
-            r21 = (r1 || c1) ? r21 : 1.0;
-            K01 o0, o1;
-            k01_far2<false, true, true, true>(T, fc, r20, r21, o0, o1);
-            if (r0) acc = fma(o0.ak1r, fma(ex0, cdx[s], ey0 * cdy[s]), acc);
-            if (r1) acc = fma(o1.ak1r, fma(ex1, cdx[s + 1], ey1 * cdy[s + 1]), acc);
-            v[h] = c0 ? -o0.ak1r * fma(ex0, dix, ey0 * diy) : 0.0;
-            v[h + 1] = c1 ? -o1.ak1r * fma(ex1, dix, ey1 * diy) : 0.0;
-        }
-#pragma unroll
-        for (int h = 0; h < 8; ++h) v[h] = gsf_wave_sum(v[h]);
-        if (ln == 0) {
-#pragma unroll
-            for (int h = 0; h < 8; ++h) red[wv][s0 + h] = v[h];
-        }
-    }
+    const double acc = diag ? sym_columns<true>(A, fc, ncol, i, j0, valid, x, y, dix, diy, rnear, kp, cx, cy, cdx, cdy,
+                                                cmask, red, wv, ln)
+                            : sym_columns<false>(A, fc, ncol, i, j0, valid, x, y, dix, diy, rnear, kp, cx, cy, cdx,
+                                                 cdy, cmask, red, wv, ln);
     __syncthreads();
     if (t < ncol) {
         double sc = red[0][t];
