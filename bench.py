@@ -70,7 +70,7 @@ TUNED_SPLITS = os.path.join(ROOT, "paper_1908_07392_amd", "tuning", "mi355x_far_
 # same counter's reading for a plain 256 MiB copy), averaged over the three
 # alphas, measured with these source splits
 # (profiles/far_eval_fp64_starfish4096_grid512_hbm_bytes.txt)
-PROFILED_TRAFFIC = {"splits": {"alpha=5": 20, "alpha=50": 16, "alpha=500": 16}, "bytes": 36895882}
+PROFILED_TRAFFIC = {"splits": {"alpha=5": 20, "alpha=50": 16, "alpha=500": 16}, "bytes": 36894316}
 
 
 def parse():
