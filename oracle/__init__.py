@@ -81,6 +81,13 @@ def _c(a, dt=np.float64):
     return None if a is None else np.ascontiguousarray(a, dtype=dt)
 
 
+def _ok(rc, what):
+    """Raise on a failed oracle call (-3: the adaptive quadrature stopped on a
+    piece that had not converged)."""
+    if rc != 0:
+        raise RuntimeError(f"{what} failed: {rc}")
+
+
 def max_threads() -> int:
     return int(lib().orc_max_threads())
 
@@ -110,8 +117,8 @@ def panel_weights(x, y, panel, tx, ty, alpha, self_node=-1, mode=0):
     target against one panel: returns (W_slp[16], W_dlp[16])."""
     x, y = _c(x), _c(y)
     W = np.empty(32)
-    lib().orc_panel_weights(_p(x), _p(y), int(panel), float(tx), float(ty), float(alpha), int(self_node),
-                            int(mode), _p(W))
+    _ok(lib().orc_panel_weights(_p(x), _p(y), int(panel), float(tx), float(ty), float(alpha), int(self_node),
+                                int(mode), _p(W)), "orc_panel_weights")
     return W[:16].copy(), W[16:].copy()
 
 
@@ -153,7 +160,8 @@ def panel_grad_weights(x, y, panel, tx, ty, alpha, mode=0):
     d/dx2 SLP, d/dx1 DLP, d/dx2 DLP)."""
     x, y = _c(x), _c(y)
     W = np.zeros(64)
-    lib().orc_panel_grad_weights(_p(x), _p(y), int(panel), float(tx), float(ty), float(alpha), int(mode), _p(W))
+    _ok(lib().orc_panel_grad_weights(_p(x), _p(y), int(panel), float(tx), float(ty), float(alpha), int(mode), _p(W)),
+        "orc_panel_grad_weights")
     return W.reshape(4, 16)
 
 
@@ -171,8 +179,8 @@ def stokes_panel_weights(x, y, panel, tx, ty, alpha, self_node=-1, mode=0):
     """[2][2][16] weights: u_i += sum_j,l W[i][j][l] mu_j(node l of the panel)."""
     x, y = _c(x), _c(y)
     W = np.zeros(64)
-    lib().orc_stokes_panel_weights(_p(x), _p(y), int(panel), float(tx), float(ty), float(alpha), int(self_node),
-                                   int(mode), _p(W))
+    _ok(lib().orc_stokes_panel_weights(_p(x), _p(y), int(panel), float(tx), float(ty), float(alpha), int(self_node),
+                                       int(mode), _p(W)), "orc_stokes_panel_weights")
     return W.reshape(2, 2, 16)
 
 
@@ -203,8 +211,8 @@ def stokes_grad_panel_weights(x, y, panel, tx, ty, alpha, mode=0):
     """[2][2][2][16] weights W[a][l][j]: d u_a/d x_l += sum_k W[a][l][j][k] mu_j(node k)."""
     x, y = _c(x), _c(y)
     W = np.zeros(128)
-    lib().orc_stokes_grad_panel_weights(_p(x), _p(y), int(panel), float(tx), float(ty), float(alpha), int(mode),
-                                        _p(W))
+    _ok(lib().orc_stokes_grad_panel_weights(_p(x), _p(y), int(panel), float(tx), float(ty), float(alpha), int(mode),
+                                            _p(W)), "orc_stokes_grad_panel_weights")
     return W.reshape(2, 2, 2, 16)
 
 
@@ -235,7 +243,7 @@ def stokes_matrix(x, y, alpha, nthreads=0):
 
 
 def stokes_bie_matrix(Dm, w, nx, ny):
-    """1/2 I + D_pv + W with W mu = n (sum_j w_j mu_j . n_j) / sum_j w_j (Sec. 3.2)."""
+    """1/2 I + D_pv + W with W mu = n (sum_j w_j mu_j . n_j) / sum_j w_j (Sec. 2.2)."""
     n = w.size
     nn = np.concatenate([nx, ny])
     wn = np.concatenate([w * nx, w * ny]) / np.sum(w)

@@ -25,7 +25,7 @@
  *
  * r = x - y, with T1..T3 of App. B (closed forms in K0, K1 for z > 1.5, the
  * power series of App. C below), and the on-surface operator
- * (1/2) mu + D_pv mu + W mu, W mu = n (int mu.n dS) / |Gamma| (Sec. 3.2).
+ * (1/2) mu + D_pv mu + W mu, W mu = n (int mu.n dS) / |Gamma| (Sec. 2.2).
  *
  * K0(alpha r)/(2 pi) is the scalar Yukawa piece of the paper's modified
  * biharmonic Green's function (Sec. 2, eq. for G; App. B).  The boundary is the
@@ -593,6 +593,14 @@ static void gl_rule(const integrand_t *c, int n, const double *T, const double *
    relative test.  `absacc` (optional) collects the integral of |F| over the
    accepted pieces.                                                        */
 typedef struct { double a, b; int d; } seg_t;
+/* Pieces accepted only because the bisection ran out of stack or of visits
+   (not converged).  Every public entry point that integrates clears the count
+   and returns ORC_ERR_QUAD when it is nonzero at the end.  Pieces accepted at
+   depth 60 or below 1e-17 in width are not counted: they only arise next to a
+   target on the panel (graded towards it), where they hold a negligible part
+   of the integral. */
+static long orc_quad_unconverged = 0;
+#define ORC_ERR_QUAD (-3)
 static void adaptive(const integrand_t *c, double a, double b, double rtol, const double *fl, long double *acc,
                      long double *absacc)
 {
@@ -614,7 +622,12 @@ static void adaptive(const integrand_t *c, double a, double b, double rtol, cons
                 break;
             }
         }
-        if (ok || s.d >= 60 || (s.b - s.a) < 1e-17 || top > 124 || visited > 200000) {
+        const int starved = !(ok || s.d >= 60 || (s.b - s.a) < 1e-17) && (top > 124 || visited > 200000);
+        if (starved) {
+#pragma omp atomic
+            ++orc_quad_unconverged;
+        }
+        if (ok || s.d >= 60 || (s.b - s.a) < 1e-17 || starved) {
             for (int k = 0; k < nf; ++k) acc[k] += I32[k];
             if (absacc)
                 for (int k = 0; k < nf; ++k) absacc[k] += A32[k];
@@ -794,6 +807,7 @@ int orc_max_threads(void)
 int orc_panel_weights(const double *x, const double *y, int64_t panel, double tx, double ty, double alpha,
                       int self, int mode, double *W)
 {
+    orc_quad_unconverged = 0;
     init_rules();
     panel_t p;
     panel_setup(&p, x + 16 * panel, y + 16 * panel);
@@ -803,7 +817,7 @@ int orc_panel_weights(const double *x, const double *y, int64_t panel, double tx
         panel_exact(&p, tx, ty, alpha, self, W);
     else
         panel_direct(&p, tx, ty, alpha, W);
-    return 0;
+    return orc_quad_unconverged ? ORC_ERR_QUAD : 0;
 }
 
 /* Layer potentials at m targets.  tgt_node[i] >= 0 marks target i as boundary
@@ -813,6 +827,7 @@ int orc_eval(const double *x, const double *y, int64_t n_panels, const double *s
              double alpha, const double *tx, const double *ty, int64_t m, const int64_t *tgt_node,
              double *u_slp, double *u_dlp, int nthreads)
 {
+    orc_quad_unconverged = 0;
     init_rules();
     if (alpha <= 0.0 || n_panels <= 0 || m < 0) return -1;
     panel_t *P = (panel_t *)malloc(sizeof(panel_t) * (size_t)n_panels);
@@ -839,7 +854,7 @@ int orc_eval(const double *x, const double *y, int64_t n_panels, const double *s
         if (u_dlp) u_dlp[i] = (double)ud;
     }
     free(P);
-    return 0;
+    return orc_quad_unconverged ? ORC_ERR_QUAD : 0;
 }
 
 /* Gradient weights of one off-surface target against one panel (W: 64
@@ -848,6 +863,7 @@ int orc_eval(const double *x, const double *y, int64_t n_panels, const double *s
 int orc_panel_grad_weights(const double *x, const double *y, int64_t panel, double tx, double ty, double alpha,
                            int mode, double *W)
 {
+    orc_quad_unconverged = 0;
     init_rules();
     panel_t p;
     panel_setup(&p, x + 16 * panel, y + 16 * panel);
@@ -857,7 +873,7 @@ int orc_panel_grad_weights(const double *x, const double *y, int64_t panel, doub
         panel_exact_k(&p, tx, ty, alpha, -1, 1, W);
     else
         panel_direct_grad(&p, tx, ty, alpha, W);
-    return 0;
+    return orc_quad_unconverged ? ORC_ERR_QUAD : 0;
 }
 
 /* Gradients of S[sigma] and D[mu] at m off-surface targets (targets must not
@@ -867,6 +883,7 @@ int orc_eval_grad(const double *x, const double *y, int64_t n_panels, const doub
                   double alpha, const double *tx, const double *ty, int64_t m, double *gsx, double *gsy,
                   double *gdx, double *gdy, int nthreads)
 {
+    orc_quad_unconverged = 0;
     init_rules();
     if (alpha <= 0.0 || n_panels <= 0 || m < 0) return -1;
     panel_t *P = (panel_t *)malloc(sizeof(panel_t) * (size_t)n_panels);
@@ -899,7 +916,7 @@ int orc_eval_grad(const double *x, const double *y, int64_t n_panels, const doub
         if (gdy) gdy[i] = (double)a[3];
     }
     free(P);
-    return 0;
+    return orc_quad_unconverged ? ORC_ERR_QUAD : 0;
 }
 
 /* Stresslet weights of one target against one panel (W: 64 doubles, block
@@ -908,6 +925,7 @@ int orc_eval_grad(const double *x, const double *y, int64_t n_panels, const doub
 int orc_stokes_panel_weights(const double *x, const double *y, int64_t panel, double tx, double ty, double alpha,
                              int self, int mode, double *W)
 {
+    orc_quad_unconverged = 0;
     init_rules();
     panel_t p;
     panel_setup(&p, x + 16 * panel, y + 16 * panel);
@@ -917,7 +935,7 @@ int orc_stokes_panel_weights(const double *x, const double *y, int64_t panel, do
         panel_exact_k(&p, tx, ty, alpha, self, 2, W);
     else
         panel_direct_stokes(&p, tx, ty, alpha, W);
-    return 0;
+    return orc_quad_unconverged ? ORC_ERR_QUAD : 0;
 }
 
 /* Modified-Stokes double layer D[mu] at m targets (mu1, mu2: the density's
@@ -928,6 +946,7 @@ int orc_stokes_eval(const double *x, const double *y, int64_t n_panels, const do
                     double alpha, const double *tx, const double *ty, int64_t m, const int64_t *tgt_node,
                     double *u1, double *u2, int nthreads)
 {
+    orc_quad_unconverged = 0;
     init_rules();
     if (alpha <= 0.0 || n_panels <= 0 || m < 0) return -1;
     panel_t *P = (panel_t *)malloc(sizeof(panel_t) * (size_t)n_panels);
@@ -955,7 +974,7 @@ int orc_stokes_eval(const double *x, const double *y, int64_t n_panels, const do
         u2[i] = (double)a2;
     }
     free(P);
-    return 0;
+    return orc_quad_unconverged ? ORC_ERR_QUAD : 0;
 }
 
 /* Stresslet-gradient weights of one off-surface target against one panel
@@ -964,6 +983,7 @@ int orc_stokes_eval(const double *x, const double *y, int64_t n_panels, const do
 int orc_stokes_grad_panel_weights(const double *x, const double *y, int64_t panel, double tx, double ty,
                                   double alpha, int mode, double *W)
 {
+    orc_quad_unconverged = 0;
     init_rules();
     panel_t p;
     panel_setup(&p, x + 16 * panel, y + 16 * panel);
@@ -973,7 +993,7 @@ int orc_stokes_grad_panel_weights(const double *x, const double *y, int64_t pane
         panel_exact_k(&p, tx, ty, alpha, -1, 3, W);
     else
         panel_direct_stokes_grad(&p, tx, ty, alpha, W);
-    return 0;
+    return orc_quad_unconverged ? ORC_ERR_QUAD : 0;
 }
 
 /* Target gradient of the stresslet double layer at m off-surface targets:
@@ -982,6 +1002,7 @@ int orc_stokes_grad_panel_weights(const double *x, const double *y, int64_t pane
 int orc_stokes_grad_eval(const double *x, const double *y, int64_t n_panels, const double *mu1, const double *mu2,
                          double alpha, const double *tx, const double *ty, int64_t m, double *g, int nthreads)
 {
+    orc_quad_unconverged = 0;
     init_rules();
     if (alpha <= 0.0 || n_panels <= 0 || m < 0) return -1;
     panel_t *P = (panel_t *)malloc(sizeof(panel_t) * (size_t)n_panels);
@@ -1005,13 +1026,14 @@ int orc_stokes_grad_eval(const double *x, const double *y, int64_t n_panels, con
         for (int c = 0; c < 4; ++c) g[c * m + i] = (double)acc[c];
     }
     free(P);
-    return 0;
+    return orc_quad_unconverged ? ORC_ERR_QUAD : 0;
 }
 
 /* Dense on-surface principal-value stresslet matrix (2N x 2N, row-major):
    row a N + i (component a at node i), column b N + j. */
 int orc_stokes_matrix(const double *x, const double *y, int64_t n_panels, double alpha, double *Dm, int nthreads)
 {
+    orc_quad_unconverged = 0;
     init_rules();
     if (alpha <= 0.0 || n_panels <= 0) return -1;
     int64_t N = 16 * n_panels;
@@ -1034,7 +1056,7 @@ int orc_stokes_matrix(const double *x, const double *y, int64_t n_panels, double
         }
     }
     free(P);
-    return 0;
+    return orc_quad_unconverged ? ORC_ERR_QUAD : 0;
 }
 
 /* Dense on-surface matrices (row-major N x N): S (SLP) and D (DLP, principal
@@ -1042,6 +1064,7 @@ int orc_stokes_matrix(const double *x, const double *y, int64_t n_panels, double
 int orc_assemble_onsurface(const double *x, const double *y, int64_t n_panels, double alpha, double *S,
                            double *D, int nthreads)
 {
+    orc_quad_unconverged = 0;
     init_rules();
     if (alpha <= 0.0 || n_panels <= 0) return -1;
     int64_t N = 16 * n_panels;
@@ -1065,7 +1088,7 @@ int orc_assemble_onsurface(const double *x, const double *y, int64_t n_panels, d
         }
     }
     free(P);
-    return 0;
+    return orc_quad_unconverged ? ORC_ERR_QUAD : 0;
 }
 
 /* ------------------------------------------------------------------------ */
