@@ -289,6 +289,24 @@ def eval_layer(plan: Plan, sigma=None, mu=None, precision=FP64, out_slp=None, ou
     return (out_slp if sigma is not None else None), (out_dlp if mu is not None else None)
 
 
+def eval_slp(plan: Plan, sigma, precision=FP64, out=None):
+    """S[sigma] at the plan's targets (mhlp_eval_slp)."""
+    L = load()
+    out = torch.empty(plan.n_targets, dtype=torch.float64, device=plan.geom.device) if out is None else out
+    _check(L.mhlp_eval_slp(plan.handle, _dev(sigma, "sigma", plan.n_sources), _dev(out, "u", plan.n_targets),
+                           int(precision), _stream()), "eval_slp")
+    return out
+
+
+def eval_dlp(plan: Plan, mu, precision=FP64, out=None):
+    """D[mu] at the plan's targets (mhlp_eval_dlp; principal value on an on-surface plan)."""
+    L = load()
+    out = torch.empty(plan.n_targets, dtype=torch.float64, device=plan.geom.device) if out is None else out
+    _check(L.mhlp_eval_dlp(plan.handle, _dev(mu, "mu", plan.n_sources), _dev(out, "u", plan.n_targets),
+                           int(precision), _stream()), "eval_dlp")
+    return out
+
+
 def eval_grad(plan: Plan, sigma=None, mu=None, out_slp=None, out_dlp=None):
     """Target gradients of the single layer of sigma and/or the double layer of
     mu on an off-surface plan; each result is a [2][M] float64 tensor (x1 and
