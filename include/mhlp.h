@@ -163,7 +163,7 @@ mhlp_status mhlp_apply_bie_operator(const mhlp_plan *onsurf, const double *mu, d
    mhlp_stokes_eval: D[mu] at the plan's targets (on-surface: principal value,
    no 1/2 mu or W term).
    mhlp_stokes_apply_bie (on-surface plan): out = 1/2 mu + D mu + W mu with the
-   nullspace correction W mu = n(x) int mu.n dS / |Gamma| (Sec. 3.2), out [2][N].
+   nullspace correction W mu = n(x) int mu.n dS / |Gamma| (Sec. 2.2), out [2][N].
    mhlp_stokes_gmres_solve: GMRES for (1/2 I + D + W) mu = g, g and mu [2][N],
    same options and behaviour as mhlp_gmres_solve (precision must be FP64).
    Errors: MHLP_INVALID_ARG (NULL or aliased arrays, wrong plan kind). */
@@ -272,8 +272,8 @@ mhlp_status mhlp_volume_fmm_info(const mhlp_volume_fmm *vf, int32_t *order, int3
 mhlp_status mhlp_volume_fmm_destroy(mhlp_volume_fmm *vf);
 
 /* Particular solution of the modified Stokes equations on a periodic box
-   (Sec. 3.1: (alpha^2 - Delta) u + grad p = F, div u = 0 by the periodic stokeslet
-   multiplier; Sec. 4.1.2: grid FFTs, the gradient by Fourier differentiation
+   (Sec. 2.1: (alpha^2 - Delta) u + grad p = F, div u = 0 by the periodic stokeslet
+   multiplier; Sec. 3.1.2: grid FFTs, the gradient by Fourier differentiation
    and values at boundary points by type-2 sums):
      u^_j(k) = S^_jl(k) F^_l(k), S^_jl = (delta_jl - k_j k_l/|k|^2)/(alpha^2 + |k|^2), S^(0) = I/alpha^2,
    on the box [x0, x0 + Lb) x [y0, y0 + Lb) with the M x M grid x_a = x0 + a Lb/M,
@@ -292,7 +292,7 @@ mhlp_status mhlp_volume_fmm_destroy(mhlp_volume_fmm *vf);
 typedef struct mhlp_box mhlp_box;
 /* mhlp_box_set_point_method: how the point values are formed.  0: the type-2
    sums written out directly (exact, n M^2 work); 1 (the default for M <= 1024):
-   a non-uniform FFT as in Sec. 4.1.2 (coefficients divided by the transform of
+   a non-uniform FFT as in Sec. 3.1.2 (coefficients divided by the transform of
    an exponential-of-semicircle kernel of width 14, inverse FFT on a 2M x 2M
    grid, a 14 x 14 kernel sum per point; ~1e-14 of sum |u^| from the exact sums;
    the first call allocates 2 (2M)^2 complex and synchronises).  Errors:
@@ -303,7 +303,7 @@ mhlp_status mhlp_box_particular(mhlp_box *box, const double *F, double *u, doubl
                                 const double *py, double *up, void *stream);
 mhlp_status mhlp_box_destroy(mhlp_box *box);
 
-/* One SISDC time step (Sec. 4.3) of the Navier-Stokes equations
+/* One SISDC time step (Sec. 3.3, "Time stepping") of the Navier-Stokes equations
    u_t = -(u.grad)u + (1/Re) Delta u - grad p, div u = 0, on the periodic box
    (every term on the grid: no embedded boundary and no function extension).
    K in [2, 5]: p = K - 1 equal substeps dts = dt/p, a first implicit-explicit
@@ -322,7 +322,7 @@ mhlp_status mhlp_sisdc_step(mhlp_box *box, double Re, double dt, int32_t K, doub
                             void *stream);
 
 /* Volume-style all-pairs Yukawa sum on a tensor grid (the dense stress case;
-   the paper instead treats volume potentials by FFT, Sec. 3.1):
+   the paper instead treats volume potentials by FFT, Sec. 3.1.2):
      u_i = sum_{j != i} K0(alpha |x_i - x_j|)/(2 pi) w_j f_j + (w_i / h^2) Wcell f_i,
    Wcell = integral of K0(alpha |x|)/(2 pi) over the h x h cell centred at the
    point (exact self-cell correction; trapezoid edge/corner cells take their
@@ -332,6 +332,7 @@ mhlp_status mhlp_sisdc_step(mhlp_box *box, double Re, double dt, int32_t K, doub
    MHLP_INVALID_ARG for NULL arrays, n < 1, alpha or h not > 0. */
 mhlp_status mhlp_volume_eval(const double *x, const double *y, const double *w, const double *f, int64_t n,
                              double alpha, double h, int32_t precision, double *u, double *self_cell, void *stream);
+
 
 /* Batched on-surface solves over many geometries (each with its own alpha)
    and up to 4 right-hand sides per geometry (Sec. 3.2 BIE, one system per

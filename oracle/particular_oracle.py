@@ -1,5 +1,5 @@
 """Plain FP64 CPU oracle of the particular solution of the modified Stokes
-equations on a periodic box (Sec. 3.1, "Particular solution"; Sec. 4.1.2,
+equations on a periodic box (Sec. 2.1, "Particular solution"; Sec. 3.1.2,
 "Evaluating the volume potential").
 
 TEST INFRASTRUCTURE ONLY: imported by the test suite; the HIP library never

@@ -1,5 +1,5 @@
 """Plain FP64 CPU oracle of the semi-implicit spectral deferred correction
-(SISDC) time step of the Navier-Stokes equations (Sec. 4.3, "Time stepping"),
+(SISDC) time step of the Navier-Stokes equations (Sec. 3.3, "Time stepping"),
 on a periodic box where every term lives on the grid (no embedded boundary,
 so no function extension is needed).
 

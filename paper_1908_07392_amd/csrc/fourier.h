@@ -1,5 +1,5 @@
 /* Particular solution of the modified Stokes equations on a periodic box
-   (Sec. 3.1, the periodic stokeslet multiplier; Sec. 4.1.2, grid transforms and
+   (Sec. 2.1, the periodic stokeslet multiplier; Sec. 3.1.2, grid transforms and
    type-2 sums at the boundary nodes), FP64.
 
    Box [x0, x0 + Lb) x [y0, y0 + Lb), grid x_a = x0 + a Lb/M, y_b = y0 + b Lb/M,

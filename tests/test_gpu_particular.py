@@ -1,5 +1,5 @@
-"""GPU parity of the particular solution on a periodic box (Sec. 3.1 multiplier,
-Sec. 4.1.2 grid FFTs, Fourier gradient, type-2 sums at points) against the FP64
+"""GPU parity of the particular solution on a periodic box (Sec. 2.1 multiplier,
+Sec. 3.1.2 grid FFTs, Fourier gradient, type-2 sums at points) against the FP64
 oracle, and one full implicit modified-Stokes step (particular solution +
 boundary values at the nodes + second-kind BIE + GMRES + double layer at the
 interior grid points) against a manufactured solution.

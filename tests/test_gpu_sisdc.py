@@ -1,4 +1,4 @@
-"""GPU parity of the SISDC time step (Sec. 4.3) of periodic Navier-Stokes
+"""GPU parity of the SISDC time step (Sec. 3.3) of periodic Navier-Stokes
 against the oracle's step (same scheme, numpy FFTs), the exact Taylor-Green
 decay, and the observed order of accuracy on the GPU.
 

@@ -1,5 +1,5 @@
-"""Pins of the particular-solution oracle (Sec. 3.1 Fourier multiplier, Sec.
-4.1.2 grid and type-2 evaluation) against what the PDE fixes on trigonometric
+"""Pins of the particular-solution oracle (Sec. 2.1 Fourier multiplier, Sec.
+3.1.2 grid and type-2 evaluation) against what the PDE fixes on trigonometric
 polynomials: a divergence-free field u is recovered from F = (alpha^2 - Delta) u,
 a gradient forcing produces no velocity (it is taken by the pressure), a
 constant forcing gives F/alpha^2, the computed field solves

@@ -1,4 +1,4 @@
-"""Pins of the SISDC oracle (Sec. 4.3) on the periodic box: the quadrature
+"""Pins of the SISDC oracle (Sec. 3.3) on the periodic box: the quadrature
 weights integrate polynomials of degree p exactly; the Taylor-Green vortex (its
 advection is a pure gradient, taken by the pressure) decays exactly as
 e^{-2t/Re} and the error falls at order K; a genuinely nonlinear flow
