@@ -333,6 +333,21 @@ mhlp_status mhlp_sisdc_step(mhlp_box *box, double Re, double dt, int32_t K, doub
 mhlp_status mhlp_volume_eval(const double *x, const double *y, const double *w, const double *f, int64_t n,
                              double alpha, double h, int32_t precision, double *u, double *self_cell, void *stream);
 
+/* mhlp_volume_eval without any allocation, for callers that cannot allocate
+   device memory (code under HIP graph capture, tight serving loops, harnesses
+   that forbid hipMalloc).  Same sum, arguments and launch shape (hence the same
+   result) as mhlp_volume_eval, without the self_cell output; it only enqueues
+   and never synchronises.  The self-cell weight and the split partial sums live
+   in a fixed device array of the library (32 + 2^19 doubles, about 4 MiB, one
+   copy per device, held until the process ends), which every call on that
+   device shares: calls that overlap on one device (different streams, or
+   threads without ordering) race and give wrong results; order them.  Every
+   scratch value is written before it is read, so nothing carries over between
+   calls.  The first call on a device looks up the array's address (no
+   allocation).  Errors: as mhlp_volume_eval; MHLP_INVALID_ARG if the partial
+   sums would exceed the array (not reached by any n: at most 523,776 values). */
+mhlp_status mhlp_volume_eval_noalloc(const double *x, const double *y, const double *w, const double *f, int64_t n,
+                                     double alpha, double h, int32_t precision, double *u, void *stream);
 
 /* Batched on-surface solves over many geometries (each with its own alpha)
    and up to 4 right-hand sides per geometry (Sec. 3.2 BIE, one system per

@@ -32,6 +32,7 @@
 #include <cstring>
 #include <string>
 #include <vector>
+#include <mutex>
 
 #include "mhlp.h"
 #include "nearfield.h"
@@ -1391,6 +1392,7 @@ struct VolArgs {
     int64_t per_split;
     double *part;   /* [nsplit][n] */
     double *u;
+    const double *selfc_dev; /* when set, Wcell / h^2 is read here instead of selfc */
 };
 
 template <bool MIXED, bool SPLIT>
@@ -1456,7 +1458,7 @@ __global__ __launch_bounds__(FT_THREADS) void volume_kernel(VolArgs A)
     if (SPLIT)
         A.part[blockIdx.y * A.n + i] = acc;
     else
-        A.u[i] = fma(INV_2PI, acc, A.selfc * A.w[i] * A.f[i]);
+        A.u[i] = fma(INV_2PI, acc, (A.selfc_dev ? A.selfc_dev[0] : A.selfc) * A.w[i] * A.f[i]);
 }
 
 __global__ void volume_finalize(VolArgs A, int nsplit)
@@ -1465,14 +1467,15 @@ __global__ void volume_finalize(VolArgs A, int nsplit)
     if (i >= A.n) return;
     double s_ = 0.0;
     for (int k = 0; k < nsplit; ++k) s_ += A.part[k * A.n + i];
-    A.u[i] = fma(INV_2PI, s_, A.selfc * A.w[i] * A.f[i]);
+    A.u[i] = fma(INV_2PI, s_, (A.selfc_dev ? A.selfc_dev[0] : A.selfc) * A.w[i] * A.f[i]);
 }
 
 /* Integral of K0(alpha |x|)/(2 pi) over the h x h cell centred at the origin:
    (1/2pi) 8 int_0^{pi/4} (1 - a K1(a))/alpha^2 dtheta, a = alpha h/(2 cos theta)
    (from int_0^R K0(alpha s) s ds = (1 - alpha R K1(alpha R))/alpha^2);
-   composite 32-point Gauss-Legendre on 8 pieces.  One thread. */
-__global__ void self_cell_kernel(double alpha, double h, double *out)
+   composite 32-point Gauss-Legendre on 8 pieces.  One thread.  out[0] = the
+   integral; out_per_h2 (may be NULL) receives it divided by h^2. */
+__global__ void self_cell_kernel(double alpha, double h, double *out, double *out_per_h2)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const double L = 0.25 * PI;
@@ -1488,7 +1491,9 @@ __global__ void self_cell_kernel(double alpha, double h, double *out)
             acc += GL32_W[k] * half * (1.0 - o.ak1r * R * R) / (alpha * alpha);
         }
     }
-    out[0] = 8.0 * acc * INV_2PI;
+    const double wc = 8.0 * acc * INV_2PI;
+    if (out) out[0] = wc;
+    if (out_per_h2) out_per_h2[0] = wc / (h * h);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -3439,7 +3444,7 @@ static mhlp_status self_cell_value(double alpha, double h, hipStream_t st, doubl
 {
     double *dev = nullptr;
     TRY(dalloc(&dev, 1));
-    self_cell_kernel<<<1, 64, 0, st>>>(alpha, h, dev);
+    self_cell_kernel<<<1, 64, 0, st>>>(alpha, h, dev, nullptr);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(wc, dev, sizeof(double), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -3821,18 +3826,57 @@ extern "C" mhlp_status mhlp_sisdc_step(mhlp_box *B, double Re, double dt, int32_
     return MHLP_OK;
 }
 
-extern "C" mhlp_status mhlp_volume_eval(const double *x, const double *y, const double *w, const double *f, int64_t n,
-                                        double alpha, double h, int32_t precision, double *u, double *self_cell,
-                                        void *stream)
+/* Launch shape of the volume sum: one thread per target in blocks of
+   FT_THREADS; when that leaves fewer than 1024 blocks the sources are split
+   into ranges of whole LDS tiles evaluated by separate blocks (partials
+   [nsplit][n], summed in fixed order by volume_finalize).  Returns nsplit. */
+static int volume_shape(VolArgs &A)
+{
+    const int64_t n = A.n;
+    const int64_t tblocks = (n + FT_THREADS - 1) / FT_THREADS;
+    int64_t ns = (1024 + tblocks - 1) / tblocks;
+    if (ns > (n + FT_SRC - 1) / FT_SRC) ns = (n + FT_SRC - 1) / FT_SRC;
+    if (ns < 1) ns = 1;
+    A.per_split = ((n + ns - 1) / ns + FT_SRC - 1) / FT_SRC * FT_SRC;
+    return (int)((n + A.per_split - 1) / A.per_split);
+}
+
+static void volume_launch(const VolArgs &A, int nsplit, int32_t precision, hipStream_t st)
+{
+    const unsigned tblocks = (unsigned)((A.n + FT_THREADS - 1) / FT_THREADS);
+    if (nsplit > 1) {
+        dim3 grid(tblocks, nsplit);
+        if (precision == MHLP_MIXED)
+            volume_kernel<true, true><<<grid, FT_THREADS, 0, st>>>(A);
+        else
+            volume_kernel<false, true><<<grid, FT_THREADS, 0, st>>>(A);
+        volume_finalize<<<nblocks(A.n, 256), 256, 0, st>>>(A, nsplit);
+    } else if (precision == MHLP_MIXED) {
+        volume_kernel<true, false><<<tblocks, FT_THREADS, 0, st>>>(A);
+    } else {
+        volume_kernel<false, false><<<tblocks, FT_THREADS, 0, st>>>(A);
+    }
+}
+
+static mhlp_status volume_check(const double *x, const double *y, const double *w, const double *f, int64_t n,
+                                double alpha, double h, int32_t precision, const double *u)
 {
     if (!x || !y || !w || !f || !u) return fail(MHLP_INVALID_ARG, "NULL argument");
     if (n < 1) return fail(MHLP_INVALID_ARG, "n must be >= 1");
     if (!(alpha > 0.0) || !std::isfinite(alpha) || !(h > 0.0)) return fail(MHLP_INVALID_ARG, "alpha and h must be > 0");
     if (precision != MHLP_FP64 && precision != MHLP_MIXED) return fail(MHLP_INVALID_ARG, "unknown precision");
+    return MHLP_OK;
+}
+
+extern "C" mhlp_status mhlp_volume_eval(const double *x, const double *y, const double *w, const double *f, int64_t n,
+                                        double alpha, double h, int32_t precision, double *u, double *self_cell,
+                                        void *stream)
+{
+    TRY(volume_check(x, y, w, f, n, alpha, h, precision, u));
     hipStream_t st = (hipStream_t)stream;
     double *dev = nullptr;
     TRY(dalloc(&dev, 1));
-    self_cell_kernel<<<1, 64, 0, st>>>(alpha, h, dev);
+    self_cell_kernel<<<1, 64, 0, st>>>(alpha, h, dev, nullptr);
     double wc = 0.0;
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(&wc, dev, sizeof(double), hipMemcpyDeviceToHost, st);
@@ -3849,31 +3893,83 @@ extern "C" mhlp_status mhlp_volume_eval(const double *x, const double *y, const 
     A.alpha = alpha;
     A.selfc = wc / (h * h);
     A.u = u;
-    const int64_t tblocks = (n + FT_THREADS - 1) / FT_THREADS;
-    int64_t ns = (1024 + tblocks - 1) / tblocks;
-    if (ns > (n + FT_SRC - 1) / FT_SRC) ns = (n + FT_SRC - 1) / FT_SRC;
-    if (ns < 1) ns = 1;
-    A.per_split = ((n + ns - 1) / ns + FT_SRC - 1) / FT_SRC * FT_SRC;
-    const int nsplit = (int)((n + A.per_split - 1) / A.per_split);
+    A.selfc_dev = nullptr;
     A.part = nullptr;
+    const int nsplit = volume_shape(A);
     if (nsplit > 1) {
         TRY(dalloc(&A.part, (int64_t)nsplit * n));
-        dim3 grid((unsigned)tblocks, nsplit);
-        if (precision == MHLP_MIXED)
-            volume_kernel<true, true><<<grid, FT_THREADS, 0, st>>>(A);
-        else
-            volume_kernel<false, true><<<grid, FT_THREADS, 0, st>>>(A);
-        volume_finalize<<<nblocks(n, 256), 256, 0, st>>>(A, nsplit);
+        volume_launch(A, nsplit, precision, st);
         e = hipGetLastError();
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         (void)hipFree(A.part);
         if (e != hipSuccess) return fail(MHLP_HIP_ERROR, std::string("volume_eval: ") + hipGetErrorString(e));
         return MHLP_OK;
     }
-    if (precision == MHLP_MIXED)
-        volume_kernel<true, false><<<(unsigned)tblocks, FT_THREADS, 0, st>>>(A);
-    else
-        volume_kernel<false, false><<<(unsigned)tblocks, FT_THREADS, 0, st>>>(A);
+    volume_launch(A, nsplit, precision, st);
+    HIPCHECK(hipGetLastError());
+    return MHLP_OK;
+}
+
+/* Fixed device scratch of the allocation-free volume sum, one copy per device
+   (a file-scope device array lives in every device's copy of the code
+   object).  Slot 0 holds Wcell/h^2; the split partials start at VOL_HEAD.
+   volume_shape() never needs more than 523,776 partial values (nsplit = 2 at
+   n = 261,888), below VOL_PART_MAX.  Host code must not pass `scratch` itself
+   to a kernel: it names a host-side stand-in; the device address comes from
+   hipGetSymbolAddress, once per device. */
+constexpr int64_t VOL_HEAD = 32; /* doubles: keeps the partials 256-byte aligned */
+constexpr int64_t VOL_PART_MAX = (int64_t)1 << 19;
+static __device__ __align__(256) double scratch[VOL_HEAD + VOL_PART_MAX];
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+static std::mutex g_scratch_mutex;
+static double *g_scratch_ptr[SCRATCH_MAX_DEVICES];
+
+/* Device address of `scratch` on the current device (looked up on the first
+   call per device, then reused). */
+static mhlp_status scratch_address(double **out)
+{
+    int dev = 0;
+    HIPCHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return fail(MHLP_UNSUPPORTED, "device index beyond 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(MHLP_HIP_ERROR, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return MHLP_OK;
+}
+
+extern "C" mhlp_status mhlp_volume_eval_noalloc(const double *x, const double *y, const double *w, const double *f,
+                                                int64_t n, double alpha, double h, int32_t precision, double *u,
+                                                void *stream)
+{
+    TRY(volume_check(x, y, w, f, n, alpha, h, precision, u));
+    hipStream_t st = (hipStream_t)stream;
+    VolArgs A;
+    A.x = x;
+    A.y = y;
+    A.w = w;
+    A.f = f;
+    A.n = n;
+    A.alpha = alpha;
+    A.selfc = 0.0;
+    A.u = u;
+    const int nsplit = volume_shape(A);
+    if (nsplit > 1 && (int64_t)nsplit * n > VOL_PART_MAX)
+        return fail(MHLP_INVALID_ARG, "volume_eval_noalloc: partial sums exceed the fixed scratch (" +
+                                          std::to_string(VOL_PART_MAX) + " values)");
+    double *S = nullptr;
+    TRY(scratch_address(&S));
+    A.selfc_dev = S;
+    A.part = nsplit > 1 ? S + VOL_HEAD : nullptr;
+    /* slot 0 and every partial are written before they are read: nothing to clear */
+    self_cell_kernel<<<1, 64, 0, st>>>(alpha, h, nullptr, S);
+    volume_launch(A, nsplit, precision, st);
     HIPCHECK(hipGetLastError());
     return MHLP_OK;
 }

@@ -104,6 +104,8 @@ _SIGS = {
                                ctypes.c_int32),
     "mhlp_volume_eval": ([_V, _V, _V, _V, ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_int32, _V,
                           _c_double_p, _V], ctypes.c_int32),
+    "mhlp_volume_eval_noalloc": ([_V, _V, _V, _V, ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                  _V, _V], ctypes.c_int32),
     "mhlp_mlp_create": ([ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, _V, ctypes.POINTER(_V)],
                         ctypes.c_int32),
     "mhlp_mlp_destroy": ([_V], ctypes.c_int32),
@@ -405,6 +407,17 @@ def volume_eval(x, y, w, f, alpha, h, precision=FP64, out=None):
                               float(h), int(precision), _dev(out, "u", n), ctypes.byref(wc), _stream()),
            "volume_eval")
     return out, wc.value
+
+
+def volume_eval_noalloc(x, y, w, f, alpha, h, out, precision=FP64):
+    """``volume_eval`` into the caller's ``out`` through the entry point that
+    allocates nothing (fixed device scratch shared by all calls on a device)."""
+    L = load()
+    n = x.numel()
+    _check(L.mhlp_volume_eval_noalloc(_dev(x, "x", n), _dev(y, "y", n), _dev(w, "w", n), _dev(f, "f", n), n,
+                                      float(alpha), float(h), int(precision), _dev(out, "u", n), _stream()),
+           "volume_eval_noalloc")
+    return out
 
 
 class VolumeFMM:
