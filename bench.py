@@ -31,18 +31,20 @@ sys.path.insert(0, ROOT)
 METRIC = "GPair-evals/s (SLP+DLP) and GMRES time-to-1e-10, mixed/batched/warm vs FP64"
 FP64_PEAK_TFLOPS = 78.6        # MI355X vector FP64 (published)
 # FP64 operations per (target, source) pair of the fused SLP+DLP far-field
-# kernel on its z > 20 branch (the branch most pairs of the alpha = 50 and 500
-# evaluations take), counted from the instructions of the built kernel (two
-# pairs per loop trip): 46 v_fma (x2), 15 v_mul, 3 v_add, 2 v_rsq (x1) = 112;
-# the 6 < z <= 20 branch takes 52 v_fma (124), the 2 < z <= 6 branch 60 (140).
-# Not counted: v_ldexp and the integer exponent of exp(-z).  By function:
-# differences and r^2 5, 1/r 9, z and exp(-z) 35, 1/sqrt(z) 9, the K0 piece with
-# its derivative 37 (degree 9), K1(z)/r and the scalings 10, accumulations 7.
-FLOP_PER_PAIR_FP64 = 112
-# VALU instructions per pair on that branch (all types), and the issue rate
+# kernel, per alpha, from the hardware counters of the built kernel
+# (SQ_INSTS_VALU_{FMA,MUL,ADD,TRANS}_F64 x 64 lanes / pairs, FMA = 2; lanes
+# masked off in divergent code are counted, but the kernel classifies whole
+# waves against each panel, so few are):
+# profiles/far_eval_fp64_starfish4096_grid512_valu_f64.txt.  The pairs take
+# the fitted piece of their z: at alpha = 500 nearly all z > 100 (K0 with its
+# derivative to degree 6), at alpha = 5 z of 2..14 (degrees 9-12, the z <= 2
+# series for the nearest).  Static count of the z > 100 loop: 40 v_fma (x2),
+# 14 v_mul, 3 v_add, 2 v_rsq = 99 per pair.
+FLOP_PER_PAIR_FP64 = {5.0: 125.0, 50.0: 103.2, 500.0: 99.6}
+# VALU instructions per pair (all types, same counters), and the issue rate
 # they are bound by: 256 CUs x 2.4 GHz, one 64-lane VALU instruction per CU
 # per clock
-VALU_PER_PAIR_FP64 = 72
+VALU_PER_PAIR_FP64 = {5.0: 82.6, 50.0: 69.1, 500.0: 67.3}
 VALU_ISSUE_PER_S = 256 * 2.4e9 * 64
 # the gradient kernel (grad S and grad D of the same densities) evaluates K0
 # and K1(z)/r per pair as the potentials' tiles do (alpha carried by the staged
@@ -64,13 +66,14 @@ FLOP_PER_PAIR_STOKES = 164
 # 2 v_rsq = 219 (counters 219.8 at alpha = 500)
 FLOP_PER_PAIR_STOKES_GRAD = 219
 # launch shapes (far-field source splits) chosen by the autotuner on MI355X for
-# the plans of this benchmark; the HBM byte counts below were taken with them
+# the plans of this benchmark
 TUNED_SPLITS = os.path.join(ROOT, "paper_1908_07392_amd", "tuning", "mi355x_far_splits.json")
-# HBM bytes per fused evaluation (FETCH_SIZE + WRITE_SIZE, each scaled by the
-# same counter's reading for a plain 256 MiB copy), averaged over the three
-# alphas, measured with these source splits
-# (profiles/far_eval_fp64_starfish4096_grid512_hbm_bytes.txt)
-PROFILED_TRAFFIC = {"splits": {"alpha=5": 20, "alpha=50": 16, "alpha=500": 16}, "bytes": 36894316}
+# HBM bytes per fused FP64 evaluation (FETCH_SIZE + WRITE_SIZE, each scaled by
+# the same counter's reading for a plain 256 MiB copy), averaged over the three
+# alphas, for the current kernel and launch shape (one stream launch of 4 x the
+# resident blocks) (profiles/far_eval_fp64_starfish4096_grid512_hbm_bytes.txt);
+# None until taken for this kernel
+PROFILED_TRAFFIC = None
 
 
 def parse():
@@ -145,8 +148,11 @@ def main():
     for a in cfg["alphas"]:
         on, off = plans[a]
         kw = dict(use_cache=True, path=args.tune_cache, write=args.tune_write)
-        r_on = autotune.tune(on, "bie", reps=5, **kw)
-        r_off = autotune.tune(off, "both", reps=5, **kw)
+        # the FP64 operator and evaluation do not use source splits (symmetric
+        # tiles; stream of (target block, panel) units): the splits serve the
+        # mixed-precision leg's operator and evaluation, tuned for those
+        r_on = autotune.tune(on, "bie", precision=mhlp.MIXED, reps=5, **kw)
+        r_off = autotune.tune(off, "both", precision=mhlp.MIXED, reps=5, **kw)
         tuned[f"alpha={a:g}"] = {"bie_nsplit": r_on["nsplit"], "eval_nsplit": r_off["nsplit"],
                                  "from_cache": bool(r_on["cached"] and r_off["cached"])}
     print(f"# autotuned splits {tuned}", file=sys.stderr, flush=True)
@@ -200,19 +206,22 @@ def main():
         per_a.setdefault(a, []).append(e0.elapsed_time(e1))
     launch_ms = float(np.mean([v for a in per_a for v in per_a[a]]))
     eval_pairs = M * N
-    achieved_tf = eval_pairs * FLOP_PER_PAIR_FP64 / (launch_ms * 1e-3) / 1e12
-    split = max(tuned[k]["eval_nsplit"] for k in tuned)
-    same_shape = {k: v["eval_nsplit"] for k, v in tuned.items()} == PROFILED_TRAFFIC["splits"]
+    # FLOPs and VALU instructions of every timed launch over the sum of their durations
+    t_sum = sum(sum(v) for v in per_a.values()) * 1e-3
+    flops = sum(len(v) * eval_pairs * FLOP_PER_PAIR_FP64[a] for a, v in per_a.items())
+    valus = sum(len(v) * eval_pairs * VALU_PER_PAIR_FP64[a] for a, v in per_a.items())
+    achieved_tf = flops / t_sum / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved_tf, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved_tf / FP64_PEAK_TFLOPS, 4),
-                "traffic": PROFILED_TRAFFIC["bytes"] if same_shape else None,
-                "kernel": "far_eval_fp64<SLP,DLP>" + ("" if split == 1 else " + far_finalize"),
+                "traffic": PROFILED_TRAFFIC,
+                "kernel": "far_eval_fp64<SLP,DLP> + far_sk_finalize",
                 "launch_ms": round(launch_ms, 4),
                 "launch_ms_by_alpha": {f"alpha={a:g}": round(float(np.mean(v)), 4) for a, v in per_a.items()},
-                "pairs_per_launch": eval_pairs, "flop_per_pair": FLOP_PER_PAIR_FP64,
+                "pairs_per_launch": eval_pairs,
+                "flop_per_pair_by_alpha": {f"alpha={a:g}": f for a, f in FLOP_PER_PAIR_FP64.items()},
                 "eval_gpair_per_s": round(eval_pairs / (launch_ms * 1e-3) / 1e9, 3),
-                "valu_per_pair": VALU_PER_PAIR_FP64,
-                "valu_issue_frac": round(eval_pairs * VALU_PER_PAIR_FP64 / (launch_ms * 1e-3) / VALU_ISSUE_PER_S, 4)}
+                "valu_per_pair_by_alpha": {f"alpha={a:g}": f for a, f in VALU_PER_PAIR_FP64.items()},
+                "valu_issue_frac": round(valus / t_sum / VALU_ISSUE_PER_S, 4)}
     a_r = 50.0
     on, off = plans[a_r]
     mu, _ = mhlp.gmres_solve(on, gdev[a_r], tol=1e-10)

@@ -109,14 +109,16 @@ mhlp_status mhlp_plan_destroy(mhlp_plan *plan);
 mhlp_status mhlp_plan_info(const mhlp_plan *plan, int64_t *n_targets, int64_t *n_sources, int64_t *n_near_pairs,
                            double *alpha);
 
-/* Far-field launch shape.  The direct sum over sources can be split into
-   nsplit ranges of panels evaluated by separate blocks (partial sums added
-   in fixed order, so results do not depend on nsplit beyond rounding); the
-   default aims at about 8192 blocks of 256 targets with at least 2 panels
-   per split.  The FP64 double layer of an on-surface scalar plan of up to
-   8192 nodes (the BIE operator, GMRES) evaluates each unordered pair once
-   on tiles of its own and does not use the split (its autotuning, layers 4
-   in FP64, then finds all counts equal).  set_split may reallocate the plan's
+/* Far-field launch shape.  The mixed-precision far field, the gradients and
+   the stresslet split the direct sum over sources into nsplit ranges of
+   panels evaluated by separate blocks (partial sums added in fixed order, so
+   results do not depend on nsplit beyond rounding); the default aims at about
+   8192 blocks of 256 targets with at least 2 panels per split.  The FP64
+   single and double layers do not use it: they run as a stream of
+   (256 targets, one panel) units spread evenly over one launch of as many
+   blocks as the chip holds, and the FP64 double layer of an on-surface scalar
+   plan of up to 8192 nodes (the BIE operator, GMRES) evaluates each unordered
+   pair once on tiles of its own.  set_split may reallocate the plan's
    partial-sum buffer (it synchronises the device then).
    mhlp_plan_autotune times the far evaluation (layers: 1 SLP, 2 DLP, 3 both,
    4 the on-surface BIE operator, 5 the gradients of both, off-surface, 6 the
@@ -125,9 +127,10 @@ mhlp_status mhlp_plan_info(const mhlp_plan *plan, int64_t *n_targets, int64_t *n
    plus the current value, reps timed launches each after one warm-up,
    with HIP events on `stream`, keeps the fewest splits within 1% of the
    fastest and reports it with its time (host outputs; cand/cand_ms receive up
-   to cap candidates and their ms per launch).  A plan whose FP64 far field is
-   the FMM (mhlp_plan_set_fmm) has no splits to tune for layers 1-3 in FP64.
-   Synchronises the stream.  Errors: MHLP_INVALID_ARG. */
+   to cap candidates and their ms per launch).  Where the FP64 launch does not
+   use the split (layers 1-3, and 4 on a symmetric on-surface plan), FP64
+   requests time the MIXED launch of the same layers, the one the split
+   serves.  Synchronises the stream.  Errors: MHLP_INVALID_ARG. */
 mhlp_status mhlp_plan_set_split(mhlp_plan *plan, int32_t nsplit);
 mhlp_status mhlp_plan_get_split(const mhlp_plan *plan, int32_t *nsplit);
 mhlp_status mhlp_plan_autotune(mhlp_plan *plan, int32_t layers, int32_t precision, int32_t reps, void *stream,

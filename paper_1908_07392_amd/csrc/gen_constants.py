@@ -17,6 +17,9 @@ Device K0/K1 (modified Bessel functions of the second kind):
   local v = 1.5 u - 0.5) and z >= 6 (u in (-1, -1/3], v = 3 u + 2); K0 to degree
   16 / 15 so that K1 = -K0' taken from the derivative of the fit is also
   accurate, K1 alone to degree 14 / 13.
+* z > 2, eight finer pieces split at z = 3, 4.5, 7, 12, 20, 40, 100 and the
+  seven pieces spanning two neighbours (KQ0_k, K0 with its derivative; KQ1_k,
+  K1 alone), degrees 15 down to 6.
 """
 import os
 
@@ -276,6 +279,33 @@ def main():
         out.append(f"/* e^z sqrt(z) K{nu}(z) on u in [{float(lo):.4f}, {float(hi):.4f}] (u = 4/z - 1), as a polynomial"
                    f" in v = (2u - lo - hi)/(hi - lo) */")
         out.append(fmt(name, c))
+    # finer pieces for launches that classify whole waves against a panel: eight
+    # pieces z in (B_k, B_k+1] (k = 0..7) and seven pieces spanning two of them,
+    # z in (B_s, B_s+2] (k = 8 + s), for waves whose pairs straddle one boundary;
+    # u in [4/B_hi - 1, 4/B_lo - 1]; K0 with its derivative (KQ0_k) and K1 alone
+    # (KQ1_k), degrees from the 1.2e-16 requirement
+    bnd = [mp.mpf(2), mp.mpf(3), mp.mpf("4.5"), mp.mpf(7), mp.mpf(12), mp.mpf(20), mp.mpf(40), mp.mpf(100), mp.inf]
+    spans = [(k, k + 1) for k in range(8)] + [(k, k + 2) for k in range(7)]
+    d0 = [12, 11, 10, 9, 8, 7, 6, 6, 15, 14, 13, 11, 10, 9, 7]
+    d1 = [10, 9, 9, 8, 7, 7, 6, 6, 12, 12, 11, 10, 9, 8, 7]
+    ulo_all, uhi_all = [], []
+    for k, (a, b) in enumerate(spans):
+        hi = 4 / bnd[a] - 1
+        lo = 4 / bnd[b] - 1 if bnd[b] != mp.inf else mp.mpf(-1)
+        ulo_all.append(lo)
+        uhi_all.append(hi)
+        for nu, deg, der in ((0, d0[k], True), (1, d1[k], False)):
+            name = f"KQ{nu}_{k}"
+            c = cheb_fit_mono(large_fn(nu), deg, lo, hi)
+            e0, e1 = check_piece(c, nu, lo, hi, der)
+            report.append((name, e0, e1))
+            out.append(f"/* e^z sqrt(z) K{nu}(z) on u in [{float(lo):.6f}, {float(hi):.6f}] (u = 4/z - 1), piece {k} of the"
+                       f" fine set, as a polynomial in v = (2u - lo - hi)/(hi - lo) */")
+            out.append(fmt(name, c))
+    out.append("/* fine pieces: the z boundaries, and the u range of each piece (0..7 single, 8..14 double) */")
+    out.append(fmt("KQ_B", bnd[:8]))
+    out.append(fmt("KQ_ULO", ulo_all))
+    out.append(fmt("KQ_UHI", uhi_all))
     for nm, f in stokes_small_fns().items():
         c = mono_in_q(f, 13)
         report.append((nm, check_abs(c, f), 0.0))

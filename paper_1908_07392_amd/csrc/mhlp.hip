@@ -33,6 +33,7 @@
 #include <string>
 #include <vector>
 #include <mutex>
+#include <numeric>
 
 #include "mhlp.h"
 #include "nearfield.h"
@@ -126,6 +127,12 @@ struct mhlp_plan {
     int nsplit = 1;           /* source splits of the far field (small M)   */
     int32_t pps = 0;          /* panels per split                           */
     double *part = nullptr;   /* [2][nsplit][M] partial sums ([4][..] off-surface, for gradients) */
+    /* FP64 far field as a stream of (target block, panel) units (far_eval_fp64) */
+    uint8_t *wcls = nullptr;  /* [M/64 waves][Np] fine piece + 1 of each (wave, panel) */
+    int32_t sk_P[3] = {0, 0, 0}; /* blocks of the launch (resident blocks of the chip) for SLP+DLP, SLP, DLP */
+    int32_t sk_S = 0;            /* partial slots per target block, the largest over the three */
+    int32_t sk_stride = 1;       /* unit order within a target block (coprime to Np)            */
+    double *skpart = nullptr;    /* [2][sk_S][M] */
     NearParams np{};
     double near_factor = 1.2;
     int64_t part_cap = 0;     /* capacity of part (doubles)                 */
@@ -460,6 +467,18 @@ struct FarArgs {
     const GState *gs;
     int64_t jstride;
     const int32_t *perm; /* output index of internal target i (NULL: identity) */
+    const double *pcx, *pcy, *prad; /* bounding circle of each panel */
+    FineConst fq;                   /* per-alpha constants of the fine pieces */
+    /* FP64 far field as a stream of (target block, panel) units: the launch's
+       skP blocks take equal contiguous ranges of the skU = TB Np units and
+       leave one partial sum per target block they touch, slot = block - first
+       block of that target block ([layer][skS][M]); wcls[wave Np + p] - 1 is
+       the fine piece every pair of the wave with panel p lies in (plan time) */
+    int64_t skU;
+    int32_t skP, skS;
+    int32_t skStride; /* unit j of a target block is panel (j skStride) mod Np */
+    double *skps, *skpd;
+    const uint8_t *wcls;
 };
 
 
@@ -743,72 +762,259 @@ __global__ __launch_bounds__(FZ_TG *FZ_L) void sym_finalize(SymArgs S, int nchun
     A.ud[n] = v;
 }
 
-template <bool SLP, bool DLP, bool SPLIT>
-__global__ __launch_bounds__(FT_THREADS) void far_eval_fp64(FarArgs A)
+/* the 16 sources of one LDS panel (offset l0) against the lane's target: PC the
+   fine piece (-1: z <= 2; KQ_NP: per-pair selection over the three-piece fits) */
+template <bool SLP, bool DLP, int PC>
+__device__ __forceinline__ void far_panel_fp64(const FarArgs &A, const FarConst &fc, double x, double y,
+                                               const double *lx, const double *ly, const double *lq,
+                                               const double *ldx, const double *ldy, int l0, double &accs,
+                                               double &accd)
+{
+    constexpr int K = PC < 0 || PC >= KQ_NP ? 0 : PC;
+    const double qa = A.fq.qa[K], qk = A.fq.qk[K];
+    /* the table pointer once per panel: the piece's coefficients stay in
+       scalar registers for its 8 loop trips */
+    const FarTab T = far_table();
+#pragma unroll 1
+    for (int s = 0; s < 16; s += 2) {
+        const int a0 = l0 + s, a1 = a0 + 1;
+        const double ex0 = x - lx[a0], ey0 = y - ly[a0];
+        const double ex1 = x - lx[a1], ey1 = y - ly[a1];
+        const double r20 = fma(ex0, ex0, ey0 * ey0), r21 = fma(ex1, ex1, ey1 * ey1);
+        K01 o0, o1;
+        if constexpr (PC >= KQ_NP)
+            k01_far2<SLP, DLP, true, true>(T, fc, r20, r21, o0, o1);
+        else
+            k01_far2_fixed<SLP, DLP, PC>(T, fc, qa, qk, r20, r21, o0, o1);
+        if (SLP) accs = fma(o1.k0, lq[a1], fma(o0.k0, lq[a0], accs));
+        if (DLP)
+            accd = fma(o1.ak1r, fma(ex1, ldx[a1], ey1 * ldy[a1]), fma(o0.ak1r, fma(ex0, ldx[a0], ey0 * ldy[a0]), accd));
+    }
+}
+
+/* waves per SIMD the FP64 far kernel is compiled for (96 registers per lane) */
+constexpr int SK_WAVES = 5;
+
+/* first unit of block b of the stream decomposition, and the block that holds unit u */
+__host__ __device__ inline int64_t sk_start(int64_t U, int P, int64_t b) { return (U * b) / P; }
+__host__ __device__ inline int64_t sk_block_of(int64_t U, int P, int64_t u)
+{
+    int64_t b = (u * P) / U;
+    while (b > 0 && sk_start(U, P, b) > u) --b;
+    while (b + 1 < P && sk_start(U, P, b + 1) <= u) ++b;
+    return b;
+}
+
+/* The FP64 far field as a stream of units (target block of FT_THREADS targets,
+   one panel): block b takes units sk_start(b) .. sk_start(b+1) - 1 in order,
+   i.e. a run of units of one target block, then possibly the start of the
+   next, and so on; every block has the same number of units.  Unit j of a
+   target block is panel (j skStride) mod Np, a stride near 0.618 Np coprime to
+   Np, so that each block's run mixes panels near and far from its targets and
+   the blocks cost about the same.  For each target block it touches, the block
+   sums its panels (a target skips the panels it lists as near) and writes the
+   partial sums of its targets into slot (b - first block of the target block);
+   far_sk_finalize adds the slots in order with the near corrections.  Sources
+   are staged in LDS 16 panels at a time; each panel is evaluated with the fine
+   piece the plan-time class table gives for (wave, panel) (low 7 bits: piece
+   + 1, KQ_NP + 1 for the per-pair selection; bit 7: some target of the wave
+   lists the panel, only then do the lanes look it up in their lists). */
+template <bool SLP, bool DLP>
+__global__ __launch_bounds__(FT_THREADS, SK_WAVES) void far_eval_fp64(FarArgs A)
 {
     __shared__ double lx[FT_SRC], ly[FT_SRC], lq[FT_SRC], ldx[FT_SRC], ldy[FT_SRC];
+    __shared__ int32_t lp[16];
     const double *mu;
     if (!far_density(A, mu)) return;
-    const int64_t i = blockIdx.x * (int64_t)FT_THREADS + threadIdx.x;
-    const bool valid = i < A.M;
-    const double x = valid ? A.tx[i] : 0.0, y = valid ? A.ty[i] : 0.0;
-    /* this block's panel range */
-    const int64_t pb = SPLIT ? (int64_t)blockIdx.y * A.pps : 0;
-    const int64_t pe = SPLIT ? min(A.Np, pb + A.pps) : A.Np;
-    int32_t k = 0, kend = 0;
-    if (valid) {
-        k = A.nptr[i];
-        kend = A.nptr[i + 1];
-        while (k < kend && A.npan[k] >= 0 && A.npan[k] < pb) ++k;
-    }
-    int32_t nxt = (k < kend) ? A.npan[k] : INT_MAX;
+    const int64_t Np = A.Np;
+    int64_t u = sk_start(A.skU, A.skP, blockIdx.x);
+    const int64_t uend = sk_start(A.skU, A.skP, (int64_t)blockIdx.x + 1);
     const FarConst fc = far_const(A.alpha);
-    double accs = 0.0, accd = 0.0;
-    for (int64_t base = 16 * pb; base < 16 * pe; base += FT_SRC) {
-        __syncthreads();
-        const int64_t j = base + threadIdx.x;
-        if (j < 16 * pe) {
-            const double wj = A.sw[j];
-            lx[threadIdx.x] = A.sx[j];
-            ly[threadIdx.x] = A.sy[j];
-            if (SLP) lq[threadIdx.x] = wj * A.sigma[j];
-            if (DLP) {
-                /* alpha goes with the dipole: the pair evaluates K1(z)/r */
-                const double m = (A.alpha * wj) * mu[j];
-                ldx[threadIdx.x] = m * A.snx[j];
-                ldy[threadIdx.x] = m * A.sny[j];
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    while (u < uend) {
+        const int64_t tb = u / Np;
+        const int64_t jb = u - tb * Np;
+        const int64_t je = min(Np, uend - tb * Np);
+        const int64_t i = tb * FT_THREADS + threadIdx.x;
+        const bool valid = i < A.M;
+        /* lanes past the last target repeat its position (results discarded) */
+        const int64_t iv = valid ? i : A.M - 1;
+        const double x = A.tx[iv], y = A.ty[iv];
+        const int32_t k0 = A.nptr[iv], k1 = A.nptr[iv + 1];
+        const uint8_t *cls = A.wcls + (tb * (FT_THREADS / 64) + wv) * Np;
+        double accs = 0.0, accd = 0.0;
+        for (int64_t jt = jb; jt < je; jt += 16) {
+            const int npl = (je - jt) < 16 ? (int)(je - jt) : 16;
+            __syncthreads();
+            if (threadIdx.x < 16 * npl) {
+                const int64_t p = ((jt + (threadIdx.x >> 4)) * A.skStride) % Np;
+                const int64_t jn = 16 * p + (threadIdx.x & 15);
+                const double wj = A.sw[jn];
+                lx[threadIdx.x] = A.sx[jn];
+                ly[threadIdx.x] = A.sy[jn];
+                if (SLP) lq[threadIdx.x] = wj * A.sigma[jn];
+                if (DLP) {
+                    /* alpha goes with the dipole: the pair evaluates K1(z)/r */
+                    const double m = (A.alpha * wj) * mu[jn];
+                    ldx[threadIdx.x] = m * A.snx[jn];
+                    ldy[threadIdx.x] = m * A.sny[jn];
+                }
+                if ((threadIdx.x & 15) == 0) lp[threadIdx.x >> 4] = (int32_t)p;
+            }
+            __syncthreads();
+            for (int pl = 0; pl < npl; ++pl) {
+                const int32_t p = lp[pl];
+                const int cw = cls[p];
+                if (cw & 0x80) { /* some target of the wave lists the panel */
+                    bool listed = false;
+                    for (int32_t q = k0; q < k1; ++q) listed = listed || A.npan[q] == p;
+                    if (listed) continue;
+                }
+                const int pc = (cw & 0x7f) - 1;
+                const int l0 = pl * 16;
+                switch (pc) {
+#define MHLP_FAR_PANEL(PCV)                                                                               \
+    case PCV:                                                                                              \
+        far_panel_fp64<SLP, DLP, PCV>(A, fc, x, y, lx, ly, lq, ldx, ldy, l0, accs, accd);                  \
+        break;
+                    MHLP_FAR_PANEL(-1)
+                    MHLP_FAR_PANEL(0)
+                    MHLP_FAR_PANEL(1)
+                    MHLP_FAR_PANEL(2)
+                    MHLP_FAR_PANEL(3)
+                    MHLP_FAR_PANEL(4)
+                    MHLP_FAR_PANEL(5)
+                    MHLP_FAR_PANEL(6)
+                    MHLP_FAR_PANEL(7)
+                    MHLP_FAR_PANEL(8)
+                    MHLP_FAR_PANEL(9)
+                    MHLP_FAR_PANEL(10)
+                    MHLP_FAR_PANEL(11)
+                    MHLP_FAR_PANEL(12)
+                    MHLP_FAR_PANEL(13)
+                    MHLP_FAR_PANEL(14)
+#undef MHLP_FAR_PANEL
+                default:
+                    far_panel_fp64<SLP, DLP, KQ_NP>(A, fc, x, y, lx, ly, lq, ldx, ldy, l0, accs, accd);
+                }
             }
         }
-        __syncthreads();
-        const int32_t p0 = (int32_t)(base / 16);
-        const int npl = (pe - p0) < 16 ? (int)(pe - p0) : 16;
-        for (int pl = 0; pl < npl; ++pl) {
-            if (p0 + pl == nxt) {
-                ++k;
-                nxt = (k < kend) ? A.npan[k] : INT_MAX;
-                continue;
-            }
-#pragma unroll 1
-            for (int s = 0; s < 16; s += 2) {
-                const FarTab T = far_table();
-                const int l0 = pl * 16 + s, l1 = l0 + 1;
-                const double ex0 = x - lx[l0], ey0 = y - ly[l0];
-                const double ex1 = x - lx[l1], ey1 = y - ly[l1];
-                K01 o0, o1;
-                k01_far2<SLP, DLP, true, true>(T, fc, fma(ex0, ex0, ey0 * ey0), fma(ex1, ex1, ey1 * ey1), o0, o1);
-                if (SLP) accs = fma(o1.k0, lq[l1], fma(o0.k0, lq[l0], accs));
-                if (DLP)
-                    accd = fma(o1.ak1r, fma(ex1, ldx[l1], ey1 * ldy[l1]),
-                               fma(o0.ak1r, fma(ex0, ldx[l0], ey0 * ldy[l0]), accd));
+        const int64_t slot = (int64_t)blockIdx.x - sk_block_of(A.skU, A.skP, tb * Np);
+        if (valid) {
+            if (SLP) A.skps[slot * A.M + i] = accs;
+            if (DLP) A.skpd[slot * A.M + i] = accd;
+        }
+        u = (tb + 1) * Np;
+    }
+}
+
+/* Sum of the stream partials of each target (slots of its target block in
+   order), near corrections, 1/(2 pi) and the identity term; lanes as in
+   far_finalize (L per target). */
+template <bool SLP, bool DLP, int L>
+__global__ __launch_bounds__(L == 1 ? 256 : FZ_TG * L) void far_sk_finalize(FarArgs A)
+{
+    constexpr int TG = L == 1 ? 256 : FZ_TG;
+    __shared__ double red[4][L == 1 ? 1 : L][L == 1 ? 1 : TG]; /* far S, near S, far D, near D */
+    const double *mu;
+    if (!far_density(A, mu)) return;
+    const int g = threadIdx.x % TG, l = L == 1 ? 0 : threadIdx.x / TG;
+    const int64_t i = blockIdx.x * (int64_t)TG + g;
+    double fs = 0.0, ns = 0.0, fd = 0.0, nd = 0.0;
+    if (i < A.M) {
+        const int64_t tb = i / FT_THREADS;
+        const int64_t b0 = sk_block_of(A.skU, A.skP, tb * A.Np);
+        const int64_t nseg = sk_block_of(A.skU, A.skP, tb * A.Np + A.Np - 1) - b0 + 1;
+        for (int64_t q = l; q < nseg; q += L) {
+            if (SLP) fs += A.skps[q * A.M + i];
+            if (DLP) fd += A.skpd[q * A.M + i];
+        }
+        for (int32_t q = A.nptr[i]; q < A.nptr[i + 1]; ++q) {
+            const int64_t p = A.npan[q];
+            if (p < 0) continue;
+            for (int jj = l; jj < 16; jj += L) {
+                if (SLP) ns = fma(A.wsl[16 * (int64_t)q + jj], A.sigma[16 * p + jj], ns);
+                if (DLP) nd = fma(A.wdl[16 * (int64_t)q + jj], mu[16 * p + jj], nd);
             }
         }
     }
-    if (!valid) return;
-    if (SPLIT) {
-        if (SLP) A.part_s[blockIdx.y * A.M + i] = accs;
-        if (DLP) A.part_d[blockIdx.y * A.M + i] = accd;
-    } else {
-        far_epilogue<SLP, DLP>(A, mu, i, accs, accd);
+    if (L > 1) {
+        red[0][l][g] = fs;
+        red[1][l][g] = ns;
+        red[2][l][g] = fd;
+        red[3][l][g] = nd;
+        __syncthreads();
+        if (l != 0) return;
+        for (int q = 1; q < L; ++q) {
+            fs += red[0][q][g];
+            ns += red[1][q][g];
+            fd += red[2][q][g];
+            nd += red[3][q][g];
+        }
+    }
+    if (i >= A.M) return;
+    const int64_t o = A.perm ? (int64_t)A.perm[i] : i;
+    if (SLP) A.us[o] = fma(INV_2PI, fs, ns);
+    if (DLP) {
+        double v = fma(INV_2PI, fd, nd);
+        if (A.half_term != 0.0) v = fma(A.half_term, mu[i], v);
+        A.ud[o] = v;
+    }
+}
+
+/* Plan time: the fine piece of every (wave of 64 targets, panel) for the FP64
+   far field (low 7 bits: piece + 1, 0 for z <= 2 everywhere, KQ_NP + 1 when
+   the pairs need the per-pair selection; bit 7 set when some target of the
+   wave lists the panel as near), from the exact extreme distances of the
+   wave's targets to the panel's nodes; targets that list the panel do not vote
+   (they skip it).  Lanes past the last target repeat it. */
+__global__ __launch_bounds__(256) void far_class_kernel(const double *__restrict__ tx, const double *__restrict__ ty,
+                                                        int64_t M, const double *__restrict__ sx,
+                                                        const double *__restrict__ sy, int64_t Np, double alpha,
+                                                        const int32_t *__restrict__ nptr,
+                                                        const int32_t *__restrict__ npan, uint8_t *__restrict__ cls)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t iv = i < M ? i : M - 1;
+    const int64_t w = i >> 6;
+    const double x = tx[iv], y = ty[iv];
+    int32_t k = nptr[iv];
+    const int32_t kend = nptr[iv + 1];
+    while (k < kend && npan[k] < 0) ++k;
+    for (int64_t p = 0; p < Np; ++p) {
+        double r2lo = 1e300, r2hi = 0.0;
+        for (int j = 0; j < 16; ++j) {
+            const double ex = x - sx[16 * p + j], ey = y - sy[16 * p + j];
+            const double r2 = fma(ex, ex, ey * ey);
+            r2lo = fmin(r2lo, r2);
+            r2hi = fmax(r2hi, r2);
+        }
+        bool listed = false;
+        if (k < kend && npan[k] == p) {
+            listed = true;
+            ++k;
+        }
+        const double zlo = alpha * sqrt(r2lo), zhi = alpha * sqrt(r2hi);
+        int kl = 0, kh = 0;
+        for (int b = 0; b < KQ_NB; ++b) {
+            kl += zlo > KQ_B[b] ? 1 : 0;
+            kh += zhi > KQ_B[b] ? 1 : 0;
+        }
+        /* the voting lanes' extreme piece indices */
+        int lo = listed ? KQ_NB + 1 : kl, hi = listed ? -1 : kh;
+        for (int off = 32; off > 0; off >>= 1) {
+            lo = min(lo, __shfl_xor(lo, off));
+            hi = max(hi, __shfl_xor(hi, off));
+        }
+        int c = KQ_NP + 1;
+        if (hi < 0)
+            c = KQ_NP + 1; /* every target skips the panel */
+        else if (lo == hi)
+            c = lo; /* piece lo - 1 (0: z <= 2) */
+        else if (lo >= 1 && hi == lo + 1 && lo <= KQ_NB - 1)
+            c = KQ_NB + lo; /* pieces lo - 1 and lo */
+        if (__ballot(listed) != 0) c |= 0x80;
+        if ((threadIdx.x & 63) == 0) cls[w * Np + p] = (uint8_t)c;
     }
 }
 
@@ -2286,13 +2492,67 @@ extern "C" mhlp_status mhlp_plan_destroy(mhlp_plan *P)
     if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
     void *ptrs[] = {P->near_ptr, P->near_panel, P->near_tgt, P->near_ts, P->wslp,  P->wdlp,    P->ws,
                     P->hdev,     P->part,       P->gdev,     P->perm,    P->wgrad, P->wstk,    P->stk_flux,
-                    P->wstkg,    P->sym_tiles,  P->sym_p1,   P->sym_p2,  P->sym_bits};
+                    P->wstkg,    P->sym_tiles,  P->sym_p1,   P->sym_p2,  P->sym_bits, P->wcls, P->skpart};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete P->fmm;
     if (P->hhost) (void)hipHostFree(P->hhost);
     if (P->gstate_host) (void)hipHostFree(P->gstate_host);
     delete P;
+    return MHLP_OK;
+}
+
+/* Blocks of far_eval_fp64<SLP, DLP> the chip holds at once (per CU times CUs). */
+template <bool SLP, bool DLP>
+static mhlp_status far_resident_blocks(int *out)
+{
+    int dev = 0, cus = 0, nb = 0;
+    HIPCHECK(hipGetDevice(&dev));
+    HIPCHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, far_eval_fp64<SLP, DLP>, FT_THREADS, 0));
+    *out = (nb > 0 ? nb : 1) * (cus > 0 ? cus : 1);
+    return MHLP_OK;
+}
+
+/* The FP64 far field's launch shape: one block per resident slot of the chip
+   for each layer variant (at most one per unit), the partial slots a target
+   block can need, their buffer, and the (wave, panel) class table (built on the
+   stream after the near lists, which it reads). */
+/* blocks of the stream launch per block the chip holds at once: later waves
+   of blocks let the hardware dispatcher even out what the equal unit counts
+   leave uneven (measured on config 2 at alpha = 5: 1.49 / 1.39 / 1.35 / 1.36 ms
+   for 1, 2, 4, 8) */
+constexpr int SK_OVERSUB = 4;
+static mhlp_status far_stream_setup(mhlp_plan *P, hipStream_t st)
+{
+    const int64_t M = P->M, Np = P->g->Np;
+    const int64_t TB = (M + FT_THREADS - 1) / FT_THREADS, U = TB * Np;
+    int res[3] = {0, 0, 0};
+    TRY((far_resident_blocks<true, true>(&res[0])));
+    TRY((far_resident_blocks<true, false>(&res[1])));
+    TRY((far_resident_blocks<false, true>(&res[2])));
+    int32_t smax = 1;
+    for (int v = 0; v < 3; ++v) {
+        const int Pv = (int)std::min<int64_t>((int64_t)SK_OVERSUB * res[v], U);
+        P->sk_P[v] = Pv;
+        for (int64_t tb = 0; tb < TB; ++tb) {
+            const int64_t n = sk_block_of(U, Pv, tb * Np + Np - 1) - sk_block_of(U, Pv, tb * Np) + 1;
+            smax = (int32_t)std::max<int64_t>(smax, n);
+        }
+    }
+    P->sk_S = smax;
+    {
+        int64_t st_ = std::llround(0.6180339887498949 * (double)Np);
+        if (st_ < 1) st_ = 1;
+        while (std::gcd(st_, Np) != 1) ++st_;
+        P->sk_stride = (int32_t)(st_ % Np == 0 ? 1 : st_ % Np);
+    }
+    TRY(dalloc(&P->skpart, 2 * (int64_t)smax * M));
+    TRY(dalloc(&P->wcls, TB * (FT_THREADS / 64) * Np));
+    far_class_kernel<<<(unsigned)TB, FT_THREADS, 0, st>>>(P->tx, P->ty, M, P->g->soa, P->g->soa + P->g->N, Np,
+                                                          P->alpha, P->near_ptr, P->near_panel, P->wcls);
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(st)); /* later calls may come on other streams */
     return MHLP_OK;
 }
 
@@ -2491,6 +2751,10 @@ static mhlp_status plan_create_impl(const mhlp_geometry *g, double alpha, const 
         P->fill_mismatch = mism;
     }
     (void)hipFree(cnt);
+    if (!stokes && (s = far_stream_setup(P, st))) {
+        mhlp_plan_destroy(P);
+        return s;
+    }
     if (P->sym_bits) {
         near_bits_kernel<<<nblocks(M, 256), 256, 0, st>>>(P->near_ptr, P->near_panel, M, P->sym_nw, P->sym_bits);
         hipError_t eb = hipGetLastError();
@@ -2549,21 +2813,24 @@ extern "C" mhlp_status mhlp_plan_info(const mhlp_plan *P, int64_t *n_targets, in
 /* evaluation                                                                */
 /* ------------------------------------------------------------------------ */
 template <bool SLP, bool DLP>
-static void launch_far_t(const FarArgs &A, int nsplit, int32_t precision, hipStream_t st)
+static void launch_far_t(FarArgs A, const mhlp_plan *P, int nsplit, int32_t precision, hipStream_t st)
 {
     const unsigned nb = nblocks(A.M, FT_THREADS);
-    if (nsplit <= 1) {
-        if (precision == MHLP_MIXED)
-            far_eval_mixed<SLP, DLP, false><<<nb, FT_THREADS, 0, st>>>(A);
+    if (precision == MHLP_FP64) {
+        A.skP = P->sk_P[SLP && DLP ? 0 : SLP ? 1 : 2];
+        far_eval_fp64<SLP, DLP><<<(unsigned)A.skP, FT_THREADS, 0, st>>>(A);
+        if (A.M <= FZ_SHORT)
+            far_sk_finalize<SLP, DLP, FZ_L><<<nblocks(A.M, FZ_TG), FZ_TG * FZ_L, 0, st>>>(A);
         else
-            far_eval_fp64<SLP, DLP, false><<<nb, FT_THREADS, 0, st>>>(A);
+            far_sk_finalize<SLP, DLP, 1><<<nblocks(A.M, 256), 256, 0, st>>>(A);
+        return;
+    }
+    if (nsplit <= 1) {
+        far_eval_mixed<SLP, DLP, false><<<nb, FT_THREADS, 0, st>>>(A);
         return;
     }
     dim3 grid(nb, nsplit);
-    if (precision == MHLP_MIXED)
-        far_eval_mixed<SLP, DLP, true><<<grid, FT_THREADS, 0, st>>>(A);
-    else
-        far_eval_fp64<SLP, DLP, true><<<grid, FT_THREADS, 0, st>>>(A);
+    far_eval_mixed<SLP, DLP, true><<<grid, FT_THREADS, 0, st>>>(A);
     if (A.M <= FZ_SHORT)
         far_finalize<SLP, DLP, FZ_L><<<nblocks(A.M, FZ_TG), FZ_TG * FZ_L, 0, st>>>(A, nsplit);
     else
@@ -2606,6 +2873,17 @@ static mhlp_status launch_far(const mhlp_plan *P, const double *sigma, const dou
     A.gs = gs;
     A.jstride = jstride;
     A.perm = P->perm;
+    A.pcx = g->pcx;
+    A.pcy = g->pcy;
+    A.prad = g->prad;
+    A.fq = fine_const(P->alpha);
+    A.skU = (int64_t)((P->M + FT_THREADS - 1) / FT_THREADS) * g->Np;
+    A.skP = P->sk_P[0];
+    A.skS = P->sk_S;
+    A.skStride = P->sk_stride;
+    A.skps = P->skpart;
+    A.skpd = P->skpart + (int64_t)P->sk_S * P->M;
+    A.wcls = P->wcls;
     if (P->sym_tiles && !sigma && mu && precision == MHLP_FP64) {
         SymArgs S{A, P->sym_tiles, P->sym_p1, P->sym_p2, P->sym_bits, P->sym_nw};
         sym_far_kernel<<<(unsigned)P->sym_ntiles, SYM_R, 0, st>>>(S);
@@ -2624,11 +2902,11 @@ static mhlp_status launch_far(const mhlp_plan *P, const double *sigma, const dou
         return MHLP_OK;
     }
     if (sigma && mu)
-        launch_far_t<true, true>(A, P->nsplit, precision, st);
+        launch_far_t<true, true>(A, P, P->nsplit, precision, st);
     else if (sigma)
-        launch_far_t<true, false>(A, P->nsplit, precision, st);
+        launch_far_t<true, false>(A, P, P->nsplit, precision, st);
     else
-        launch_far_t<false, true>(A, P->nsplit, precision, st);
+        launch_far_t<false, true>(A, P, P->nsplit, precision, st);
     HIPCHECK(hipGetLastError());
     return MHLP_OK;
 }
@@ -2670,8 +2948,6 @@ extern "C" mhlp_status mhlp_plan_autotune(mhlp_plan *P, int32_t layers, int32_t 
 {
     if (!P) return fail(MHLP_INVALID_ARG, "plan is NULL");
     if (layers < 1 || layers > 7) return fail(MHLP_INVALID_ARG, "layers must be 1 to 7");
-    if (P->fmm && layers <= 3 && precision == MHLP_FP64)
-        return fail(MHLP_INVALID_ARG, "the plan's FP64 far field is the FMM (no source splits); turn it off to tune");
     if ((layers >= 6) != P->stokes) return fail(MHLP_INVALID_ARG, "layers 6 and 7 (and only they) tune a stokes plan");
     if (layers >= 6 && precision != MHLP_FP64) return fail(MHLP_INVALID_ARG, "the stresslet is FP64 only");
     if (layers == 7 && P->onsurf) return fail(MHLP_INVALID_ARG, "layers 7 (stresslet gradient) needs an off-surface plan");
@@ -2683,6 +2959,12 @@ extern "C" mhlp_status mhlp_plan_autotune(mhlp_plan *P, int32_t layers, int32_t 
     if (cap < 0 || (cap > 0 && (!cand || !cand_ms))) return fail(MHLP_INVALID_ARG, "candidate arrays");
     hipStream_t st = (hipStream_t)stream;
     const int64_t N = P->g->N, M = P->M, Np = P->g->Np;
+    /* The FP64 single and double layers run as a stream of (target block, panel)
+       units and the FP64 operator of a symmetric on-surface plan on its own
+       tiles: neither uses the split.  For them the split serves the MIXED
+       launch of the same layers (potentials, and the inner operator of mixed
+       GMRES refinement), which is what gets timed. */
+    if (precision == MHLP_FP64 && (layers <= 3 || (layers == 4 && P->sym_tiles))) precision = MHLP_MIXED;
     std::vector<int> cs;
     for (int64_t ns = 1; ns <= Np && ns <= 256; ns *= 2) cs.push_back((int)ns);
     if (std::find(cs.begin(), cs.end(), P->nsplit) == cs.end()) cs.push_back(P->nsplit);

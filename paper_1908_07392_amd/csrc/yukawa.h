@@ -105,10 +105,19 @@ static constexpr double ATANH_T[11] = {1.0, 1.0 / 3.0, 1.0 / 5.0, 1.0 / 7.0, 1.0
    the vector register file holds only per-lane state (about 110 instead of
    about 200 registers in the fused kernel: 4 instead of 2 waves per SIMD). */
 #define MHLP_CAS __attribute__((address_space(4)))
+/* the fine pieces: KQ_NB single pieces z in (KQ_B[k], KQ_B[k+1]] (k < KQ_NB,
+   the last unbounded) and KQ_NB - 1 pieces spanning two neighbours,
+   z in (KQ_B[s], KQ_B[s+2]] (k = KQ_NB + s); coefficient counts of K0 with its
+   derivative and of K1 alone */
+constexpr int KQ_NB = 8, KQ_NP = 2 * KQ_NB - 1;
+constexpr int KQ_N0[KQ_NP] = {13, 12, 11, 10, 9, 8, 7, 7, 16, 15, 14, 12, 11, 10, 8};
+constexpr int KQ_N1[KQ_NP] = {11, 10, 10, 9, 8, 8, 7, 7, 13, 13, 12, 11, 10, 9, 8};
 struct FarTable {
     double kp0n[17], kp0f[16], kp1n[15], kp1f[14], kl0[23], expt[14], atanh[11], ks_i0[12], ks_r0[13], ks_i1z[12],
         ks_r1[13];
     double kp0m[13], kp0x[10], kp1m[11], kp1x[9]; /* the z > 6 piece split at z = 20 */
+    double kq0[15][16], kq1[15][13];               /* the fine pieces (KQ0_k, KQ1_k), zero padded */
+    double kqb[15];                                /* their constant v offsets (-2 - ulo - uhi)/(uhi - ulo) */
     double stk[6][14]; /* stresslet smooth parts T1S, T2S, T3S, T1L, T2L, T3L in q = z^2/4 <= 1 */
 };
 
@@ -124,6 +133,15 @@ constexpr FarTable make_far_table()
     for (int i = 0; i < 10; ++i) t.kp0x[i] = KP0X[i];
     for (int i = 0; i < 11; ++i) t.kp1m[i] = KP1M[i];
     for (int i = 0; i < 9; ++i) t.kp1x[i] = KP1X[i];
+    const double *q0[KQ_NP] = {KQ0_0, KQ0_1, KQ0_2, KQ0_3,  KQ0_4,  KQ0_5,  KQ0_6, KQ0_7,
+                               KQ0_8, KQ0_9, KQ0_10, KQ0_11, KQ0_12, KQ0_13, KQ0_14};
+    const double *q1[KQ_NP] = {KQ1_0, KQ1_1, KQ1_2, KQ1_3,  KQ1_4,  KQ1_5,  KQ1_6, KQ1_7,
+                               KQ1_8, KQ1_9, KQ1_10, KQ1_11, KQ1_12, KQ1_13, KQ1_14};
+    for (int k = 0; k < KQ_NP; ++k) {
+        for (int i = 0; i < KQ_N0[k]; ++i) t.kq0[k][i] = q0[k][i];
+        for (int i = 0; i < KQ_N1[k]; ++i) t.kq1[k][i] = q1[k][i];
+        t.kqb[k] = (-2.0 - KQ_ULO[k] - KQ_UHI[k]) / (KQ_UHI[k] - KQ_ULO[k]);
+    }
     for (int i = 0; i < 14; ++i) t.expt[i] = EXP_T[i];
     for (int i = 0; i < 11; ++i) t.atanh[i] = ATANH_T[i];
     for (int i = 0; i < 12; ++i) t.ks_i0[i] = KS_I0[i], t.ks_i1z[i] = KS_I1Z[i];
@@ -393,6 +411,65 @@ __device__ __forceinline__ void k01_far2_big(FarTab T, const FarConst &c, double
     }
     oa = far_finish<SLP, DLP, K1R>(c, ria, za, ea, pa, da);
     ob = far_finish<SLP, DLP, K1R>(c, rib, zb, eb, pb, db);
+}
+
+/* The fine piece K at 1/r = ri: value and, with both layers, (4/alpha^2) dP/du
+   as far_finish<.., K1R> takes it.  v = qa ri + qb with
+   qa = (4/alpha) w, w = 2/(uhi - ulo), and qk = (4/alpha^2) w (per-launch values
+   of FineConst). */
+struct FineConst {
+    double qa[KQ_NP], qk[KQ_NP];
+};
+
+__host__ __device__ inline FineConst fine_const(double alpha)
+{
+    FineConst f;
+    for (int k = 0; k < KQ_NP; ++k) {
+        const double w = 2.0 / (KQ_UHI[k] - KQ_ULO[k]);
+        f.qa[k] = 4.0 / alpha * w;
+        f.qk[k] = 4.0 / (alpha * alpha) * w;
+    }
+    return f;
+}
+
+template <bool SLP, bool DLP, int K>
+__device__ __forceinline__ double far_piece_fine(FarTab T, double qa, double qk, double ri, double &dpdu)
+{
+    const double v = fma(qa, ri, T->kqb[K]);
+    if (SLP && DLP) {
+        double d;
+        const double p = hornercd<KQ_N0[K]>(T->kq0[K], v, d);
+        dpdu = d * qk;
+        return p;
+    }
+    dpdu = 0.0;
+    if (SLP) return hornerc<KQ_N0[K]>(T->kq0[K], v);
+    return hornerc<KQ_N1[K]>(T->kq1[K], v);
+}
+
+/* K0 and K1(z)/r (the K1R form) of two sources whose pairs are known to lie in
+   one piece: PC = 0..KQ_NP-1 the fine pieces, PC = -1 z <= 2 (k01_far_small).  The
+   arithmetic of k01_far2's z > 2 form with the fine piece's polynomial and
+   without any per-pair selection: for launches that classify a whole wave
+   against a panel beforehand (qa, qk: the piece's FineConst entries). */
+template <bool SLP, bool DLP, int PC>
+__device__ __forceinline__ void k01_far2_fixed(FarTab T, const FarConst &c, double qa, double qk, double r2a,
+                                               double r2b, K01 &oa, K01 &ob)
+{
+    if constexpr (PC < 0) {
+        oa = k01_far_small<SLP, DLP, true>(T, r2a, c);
+        ob = k01_far_small<SLP, DLP, true>(T, r2b, c);
+        return;
+    }
+    constexpr int P = PC < 0 ? 0 : PC;
+    const double ria = lean_rsq(r2a), rib = lean_rsq(r2b);
+    const double za = c.a * (r2a * ria), zb = c.a * (r2b * rib);
+    const double ea = lean_exp_neg(T, za) * lean_rsq(za), eb = lean_exp_neg(T, zb) * lean_rsq(zb);
+    double da = 0.0, db = 0.0;
+    const double pa = far_piece_fine<SLP, DLP, P>(T, qa, qk, ria, da);
+    const double pb = far_piece_fine<SLP, DLP, P>(T, qa, qk, rib, db);
+    oa = far_finish<SLP, DLP, true>(c, ria, za, ea, pa, da);
+    ob = far_finish<SLP, DLP, true>(c, rib, zb, eb, pb, db);
 }
 
 /* PIECES = false (K0 only): one degree-22 fit over all z > 2 in u = 4/z - 1,

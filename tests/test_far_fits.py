@@ -68,3 +68,31 @@ def test_pieces_join_at_the_breakpoints():
     assert abs(piece("KP0N", U6, 1.0, 6.0) / piece("KP0M", U20, U6, 6.0) - 1) < 1e-15
     assert abs(piece("KP0M", U20, U6, 20.0) / piece("KP0X", -1.0, U20, 20.0) - 1) < 1e-15
     assert abs(piece("KP0F", -1.0, U6, 20.0) / piece("KP0X", -1.0, U20, 20.0) - 1) < 1e-15
+
+
+def _fine_pieces():
+    ulo, uhi = table("KQ_ULO"), table("KQ_UHI")
+    out = []
+    for k in range(len(ulo)):
+        out.append((f"KQ0_{k}", 0, (ulo[k], uhi[k]), True))
+        out.append((f"KQ1_{k}", 1, (ulo[k], uhi[k]), False))
+    return out
+
+
+@pytest.mark.parametrize("name,nu,urange,der", _fine_pieces())
+def test_fine_piece_matches_scaled_bessel(name, nu, urange, der):
+    """the fifteen fine pieces (eight single, seven spanning two neighbours) of the
+    wave-classified far-field tiles, K0 with K1 from its derivative and K1 alone"""
+    test_piece_matches_scaled_bessel(name, nu, urange, der)
+
+
+def test_fine_pieces_tile_the_axis():
+    """single pieces k cover z in (B_k, B_k+1], the double pieces (B_s, B_s+2]"""
+    b = table("KQ_B")
+    ulo, uhi = table("KQ_ULO"), table("KQ_UHI")
+    nb = len(b)
+    zb = list(b) + [np.inf]
+    for k in range(nb):
+        assert abs(uhi[k] - (4 / zb[k] - 1)) < 1e-15 and abs(ulo[k] - (4 / zb[k + 1] - 1)) < 1e-15
+    for s in range(nb - 1):
+        assert abs(uhi[nb + s] - (4 / zb[s] - 1)) < 1e-15 and abs(ulo[nb + s] - (4 / zb[s + 2] - 1)) < 1e-15

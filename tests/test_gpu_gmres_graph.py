@@ -116,7 +116,7 @@ def test_autotune_keeps_results_and_picks_a_candidate():
     us0, ud0 = mhlp.eval_layer(off, sigma=sig, mu=sig)
     ref_s, ref_d = us0.cpu().numpy(), ud0.cpu().numpy()
     best, ms, table = off.autotune(layers=3, reps=3)
-    assert best in table and ms == min(table.values()) and off.nsplit == best
+    assert best in table and ms == table[best] and ms <= 1.01 * min(table.values()) and off.nsplit == best
     assert 1 in table and len(table) >= 2
     for ns in sorted(table):
         off.set_split(ns)
