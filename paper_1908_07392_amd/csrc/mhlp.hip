@@ -118,6 +118,7 @@ struct mhlp_plan {
     double *sym_p2 = nullptr;    /* [row blocks][N] column sums */
     uint32_t *sym_bits = nullptr; /* [N][sym_nw] near panels of each node as bits */
     int32_t sym_nw = 0;
+    uint8_t *sym_cls = nullptr;   /* [4 row blocks][Np] piece class of each (row wave, column panel) */
     double *wstkg = nullptr;  /* stokes, off-surface, built on first use: [8][nnz][16] stresslet
                                  gradient weights, block (2a + l) 2 + j = d u_a/d x_l per mu_j */
     double *stk_flux = nullptr; /* stokes: device scalar sum_j w_j mu_j.n_j / |Gamma|           */
@@ -602,6 +603,8 @@ struct SymArgs {
     double *p1, *p2;
     const uint32_t *bits; /* [N][nw] near panels of each node */
     int nw;
+    const uint8_t *cls;   /* [N/64 row waves][Np] fine piece + 1 of every pair of (wave, column panel); bit 7:
+                             some pair of them is near on either side */
 };
 static_assert(SYM_RP == 16 && SYM_CP == 1, "the near masks below read 16 row panels and one column panel");
 
@@ -619,63 +622,113 @@ __global__ void near_bits_kernel(const int32_t *__restrict__ nptr, const int32_t
     }
 }
 
-/* the column loop of sym_far_kernel; DIAG: the tile's chunk lies in its row
-   block, where only row < column counts */
-template <bool DIAG>
+/* the column loop of sym_far_kernel for 16 columns, two at a time, with the
+   fine piece PC (-1: z <= 2; KQ_NP: per-pair selection) of the wave and column
+   panel.  MASK: the wave has near pairs (on either side) or is on the diagonal
+   block, where only row < column counts.  The row terms accumulate in the
+   returned sum; the column terms go to colv[s][t] for the block's reduction. */
+template <int PC, bool MASK>
 __device__ __forceinline__ double sym_columns(const FarArgs &A, const FarConst &fc, int ncol, int64_t i, int64_t j0,
-                                              bool valid, double x, double y, double dix, double diy, uint32_t rnear,
-                                              int kp, const double *cx, const double *cy, const double *cdx,
-                                              const double *cdy, const uint32_t *cmask, double (*red)[SYM_C], int wv,
-                                              int ln)
+                                              bool valid, bool diag, double x, double y, double dix, double diy,
+                                              uint32_t rnear, int kp, const double *cx, const double *cy,
+                                              const double *cdx, const double *cdy, const uint32_t *cmask,
+                                              double (*colv)[SYM_R])
 {
+    constexpr int K = PC < 0 || PC >= KQ_NP ? 0 : PC;
+    const double qa = A.fq.qa[K], qk = A.fq.qk[K];
+    const FarTab T = far_table();
+    const int t = threadIdx.x;
     double acc = 0.0;
-    /* columns in groups of 8: the row terms accumulate as they come, the 8
-       column terms of a group are reduced over the lanes together (8
-       independent butterflies) */
 #pragma unroll 1
-    for (int s0 = 0; s0 < ncol; s0 += 8) {
-        double v[8];
-#pragma unroll
-        for (int h = 0; h < 8; h += 2) {
-            const FarTab T = far_table();
-            const int s = s0 + h;
-            const int64_t ja = j0 + s, jb = ja + 1;
-            const double ex0 = x - cx[s], ey0 = y - cy[s], ex1 = x - cx[s + 1], ey1 = y - cy[s + 1];
+    for (int s = 0; s < ncol; s += 2) {
+        const int64_t ja = j0 + s, jb = ja + 1;
+        const double ex0 = x - cx[s], ey0 = y - cy[s], ex1 = x - cx[s + 1], ey1 = y - cy[s + 1];
+        double r20 = fma(ex0, ex0, ey0 * ey0), r21 = fma(ex1, ex1, ey1 * ey1);
+        bool r0 = valid, r1 = valid, c0 = valid, c1 = valid;
+        if (MASK) {
             /* row and column terms wanted for the two columns (s, s + 1 share a panel) */
-            const bool rfar = valid && !((rnear >> (s >> 4)) & 1u);
-            const bool r0 = rfar && (!DIAG || i < ja), r1 = rfar && (!DIAG || i < jb);
-            const bool c0 = valid && !((cmask[s] >> kp) & 1u) && (!DIAG || i < ja);
-            const bool c1 = valid && !((cmask[s + 1] >> kp) & 1u) && (!DIAG || i < jb);
-            double r20 = fma(ex0, ex0, ey0 * ey0), r21 = fma(ex1, ex1, ey1 * ey1);
+            const bool rfar = valid && !(rnear & 1u);
+            r0 = rfar && (!diag || i < ja);
+            r1 = rfar && (!diag || i < jb);
+            c0 = valid && !((cmask[s] >> kp) & 1u) && (!diag || i < ja);
+            c1 = valid && !((cmask[s + 1] >> kp) & 1u) && (!diag || i < jb);
             r20 = (r0 || c0) ? r20 : 1.0; /* unused pairs (the node itself among them) */
             r21 = (r1 || c1) ? r21 : 1.0;
-            K01 o0, o1;
-            k01_far2<false, true, true, true>(T, fc, r20, r21, o0, o1);
-            if (r0) acc = fma(o0.ak1r, fma(ex0, cdx[s], ey0 * cdy[s]), acc);
-            if (r1) acc = fma(o1.ak1r, fma(ex1, cdx[s + 1], ey1 * cdy[s + 1]), acc);
-            v[h] = c0 ? -o0.ak1r * fma(ex0, dix, ey0 * diy) : 0.0;
-            v[h + 1] = c1 ? -o1.ak1r * fma(ex1, dix, ey1 * diy) : 0.0;
         }
-#pragma unroll
-        for (int h = 0; h < 8; ++h) v[h] = gsf_wave_sum(v[h]);
-        if (ln == 0) {
-#pragma unroll
-            for (int h = 0; h < 8; ++h) red[wv][s0 + h] = v[h];
+        K01 o0, o1;
+        if constexpr (PC >= KQ_NP)
+            k01_far2<false, true, true, true>(T, fc, r20, r21, o0, o1);
+        else
+            k01_far2_fixed<false, true, PC>(T, fc, qa, qk, r20, r21, o0, o1);
+        const double f0 = fma(ex0, cdx[s], ey0 * cdy[s]), f1 = fma(ex1, cdx[s + 1], ey1 * cdy[s + 1]);
+        const double g0 = -fma(ex0, dix, ey0 * diy), g1 = -fma(ex1, dix, ey1 * diy);
+        if (MASK) {
+            if (r0) acc = fma(o0.ak1r, f0, acc);
+            if (r1) acc = fma(o1.ak1r, f1, acc);
+            colv[s][t] = c0 ? o0.ak1r * g0 : 0.0;
+            colv[s + 1][t] = c1 ? o1.ak1r * g1 : 0.0;
+        } else {
+            acc = fma(o1.ak1r, f1, fma(o0.ak1r, f0, acc));
+            colv[s][t] = o0.ak1r * g0;
+            colv[s + 1][t] = o1.ak1r * g1;
         }
     }
     return acc;
 }
 
+template <bool MASK>
+__device__ __forceinline__ double sym_columns_pc(int pc, const FarArgs &A, const FarConst &fc, int ncol, int64_t i,
+                                                 int64_t j0, bool valid, bool diag, double x, double y, double dix,
+                                                 double diy, uint32_t rnear, int kp, const double *cx,
+                                                 const double *cy, const double *cdx, const double *cdy,
+                                                 const uint32_t *cmask, double (*colv)[SYM_R])
+{
+    switch (pc) {
+#define MHLP_SYM_PC(PCV)                                                                                   \
+    case PCV:                                                                                              \
+        return sym_columns<PCV, MASK>(A, fc, ncol, i, j0, valid, diag, x, y, dix, diy, rnear, kp, cx, cy, cdx, \
+                                      cdy, cmask, colv);
+        MHLP_SYM_PC(-1)
+        MHLP_SYM_PC(0)
+        MHLP_SYM_PC(1)
+        MHLP_SYM_PC(2)
+        MHLP_SYM_PC(3)
+        MHLP_SYM_PC(4)
+        MHLP_SYM_PC(5)
+        MHLP_SYM_PC(6)
+        MHLP_SYM_PC(7)
+        MHLP_SYM_PC(8)
+        MHLP_SYM_PC(9)
+        MHLP_SYM_PC(10)
+        MHLP_SYM_PC(11)
+        MHLP_SYM_PC(12)
+        MHLP_SYM_PC(13)
+        MHLP_SYM_PC(14)
+#undef MHLP_SYM_PC
+    default:
+        return sym_columns<KQ_NP, MASK>(A, fc, ncol, i, j0, valid, diag, x, y, dix, diy, rnear, kp, cx, cy, cdx,
+                                        cdy, cmask, colv);
+    }
+}
+
+/* One tile: 256 row nodes (block I) against the 16 nodes of column panel J.
+   The row sums go to p1[J][i]; the column terms of the tile's 256 rows are
+   reduced through LDS (each thread adds 16 rows of one column, 16 lanes then
+   combine by a fixed butterfly) into p2[I][j].  Each wave takes the fine piece
+   of its (row wave, column panel) from the plan's class table and checks near
+   masks only when that pair of wave and panel has near pairs on either side or
+   lies on the diagonal block. */
 __global__ __launch_bounds__(SYM_R) void sym_far_kernel(SymArgs S)
 {
     const FarArgs &A = S.A;
     __shared__ double cx[SYM_C], cy[SYM_C], cdx[SYM_C], cdy[SYM_C];
     __shared__ uint32_t cmask[SYM_C];
-    __shared__ double red[SYM_R / 64][SYM_C];
+    __shared__ double colv[SYM_C][SYM_R];
     const double *mu;
     if (!far_density(A, mu)) return; /* the same for the whole launch */
     const int2 tl = S.tiles[blockIdx.x];
-    const int I = tl.x, J = tl.y, t = threadIdx.x, wv = t >> 6, ln = t & 63;
+    const int I = tl.x, J = tl.y, t = threadIdx.x;
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
     const int64_t N = A.N, i = (int64_t)I * SYM_R + t, j0 = (int64_t)J * SYM_C;
     const int pb = SYM_RP * I; /* first panel of the row block */
     if (t < SYM_C) {
@@ -696,10 +749,9 @@ __global__ __launch_bounds__(SYM_R) void sym_far_kernel(SymArgs S)
         cdy[t] = dy;
         cmask[t] = msk;
     }
-    for (int c = t; c < (SYM_R / 64) * SYM_C; c += SYM_R) red[c / SYM_C][c % SYM_C] = 0.0;
     const bool valid = i < N;
     double x = 0.0, y = 0.0, dix = 0.0, diy = 0.0;
-    uint32_t rnear = 0; /* bit k: column panel SYM_CP J + k listed near row i */
+    uint32_t rnear = 0; /* bit 0: column panel J listed near row i */
     int kp = 0;         /* row panel within the block */
     if (valid) {
         x = A.sx[i];
@@ -708,23 +760,90 @@ __global__ __launch_bounds__(SYM_R) void sym_far_kernel(SymArgs S)
         dix = m * A.snx[i];
         diy = m * A.sny[i];
         kp = (int)(i / 16) - pb;
-        rnear = (S.bits[i * S.nw + (J >> 5)] >> (J & 31)) & 1u; /* column panel J */
+        rnear = (S.bits[i * S.nw + (J >> 5)] >> (J & 31)) & 1u;
     }
     const bool diag = SYM_CP * J < pb + SYM_RP; /* the chunk lies in the row block */
     __syncthreads();
     const FarConst fc = far_const(A.alpha);
     const int ncol = (int)min((int64_t)SYM_C, N - j0);
-    const double acc = diag ? sym_columns<true>(A, fc, ncol, i, j0, valid, x, y, dix, diy, rnear, kp, cx, cy, cdx, cdy,
-                                                cmask, red, wv, ln)
-                            : sym_columns<false>(A, fc, ncol, i, j0, valid, x, y, dix, diy, rnear, kp, cx, cy, cdx,
-                                                 cdy, cmask, red, wv, ln);
+    const int cw = S.cls[((int64_t)I * (SYM_R / 64) + wv) * A.Np + J];
+    const int pc = (cw & 0x7f) - 1;
+    const double acc = (diag || (cw & 0x80))
+                           ? sym_columns_pc<true>(pc, A, fc, ncol, i, j0, valid, diag, x, y, dix, diy, rnear, kp,
+                                                  cx, cy, cdx, cdy, cmask, colv)
+                           : sym_columns_pc<false>(pc, A, fc, ncol, i, j0, valid, diag, x, y, dix, diy, rnear, kp,
+                                                   cx, cy, cdx, cdy, cmask, colv);
     __syncthreads();
-    if (t < ncol) {
-        double sc = red[0][t];
-        for (int q = 1; q < SYM_R / 64; ++q) sc += red[q][t];
-        S.p2[(int64_t)I * N + j0 + t] = sc;
+    /* column c = t / 16: thread (c, g) adds rows g, g + 16, ..., g + 240, then the
+       16 lanes of the column combine */
+    {
+        const int c = t >> 4, g = t & 15;
+        double sc = 0.0;
+        if (c < ncol)
+            for (int r = g; r < SYM_R; r += 16) sc += colv[c][r];
+        for (int off = 8; off > 0; off >>= 1) sc += __shfl_xor(sc, off);
+        if (g == 0 && c < ncol) S.p2[(int64_t)I * N + j0 + c] = sc;
     }
     if (valid) S.p1[(int64_t)J * N + i] = acc;
+}
+
+/* Plan time, symmetric on-surface plans: for every (wave of 64 row nodes,
+   column panel) the fine piece that holds z for every pair the tile evaluates
+   (row i < column j, and not near on both sides; exact extreme distances; a
+   two-neighbour piece when they straddle one boundary, KQ_NP + 1 otherwise),
+   plus bit 7 when some such pair is near on either side (the row node lists
+   the column panel, or the column node lists the row node's panel).  Pairs
+   with j <= i are never evaluated by tile (row block of i, column panel of j),
+   which exists only for column panels from 16 x the row block on. */
+__global__ __launch_bounds__(256) void sym_class_kernel(const double *__restrict__ x, const double *__restrict__ y,
+                                                        int64_t N, int64_t Np, double alpha,
+                                                        const uint32_t *__restrict__ bits, int nw,
+                                                        uint8_t *__restrict__ cls)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const bool valid = i < N;
+    const int64_t iv = valid ? i : N - 1;
+    const int64_t w = i >> 6, pi = iv / 16;
+    const double xi = x[iv], yi = y[iv];
+    for (int64_t p = 0; p < Np; ++p) {
+        double r2lo = 1e300, r2hi = -1.0;
+        const bool rn = ((bits[iv * nw + (p >> 5)] >> (p & 31)) & 1u) != 0;
+        bool near = false;
+        for (int jj = 0; jj < 16; ++jj) {
+            const int64_t j = 16 * p + jj;
+            if (!valid || j <= i) continue;
+            const bool cn = ((bits[j * nw + (pi >> 5)] >> (pi & 31)) & 1u) != 0;
+            near = near || rn || cn;
+            if (rn && cn) continue; /* neither term is taken */
+            const double ex = xi - x[j], ey = yi - y[j];
+            const double r2 = fma(ex, ex, ey * ey);
+            r2lo = fmin(r2lo, r2);
+            r2hi = fmax(r2hi, r2);
+        }
+        int lo = KQ_NB + 1, hi = -1; /* lanes without pairs do not vote */
+        if (r2hi >= 0.0) {
+            const double zlo = alpha * sqrt(r2lo), zhi = alpha * sqrt(r2hi);
+            lo = 0;
+            hi = 0;
+            for (int b = 0; b < KQ_NB; ++b) {
+                lo += zlo > KQ_B[b] ? 1 : 0;
+                hi += zhi > KQ_B[b] ? 1 : 0;
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            lo = min(lo, __shfl_xor(lo, off));
+            hi = max(hi, __shfl_xor(hi, off));
+        }
+        int c = KQ_NP + 1;
+        if (hi < 0)
+            c = KQ_NP + 1;
+        else if (lo == hi)
+            c = lo; /* piece lo - 1 (0: z <= 2) */
+        else if (lo >= 1 && hi == lo + 1 && lo <= KQ_NB - 1)
+            c = KQ_NB + lo; /* pieces lo - 1 and lo */
+        if (__ballot(near) != 0) c |= 0x80;
+        if ((threadIdx.x & 63) == 0) cls[w * Np + p] = (uint8_t)c;
+    }
 }
 
 /* node n: row sums of the chunks from its block on, column sums of the blocks
@@ -2492,7 +2611,8 @@ extern "C" mhlp_status mhlp_plan_destroy(mhlp_plan *P)
     if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
     void *ptrs[] = {P->near_ptr, P->near_panel, P->near_tgt, P->near_ts, P->wslp,  P->wdlp,    P->ws,
                     P->hdev,     P->part,       P->gdev,     P->perm,    P->wgrad, P->wstk,    P->stk_flux,
-                    P->wstkg,    P->sym_tiles,  P->sym_p1,   P->sym_p2,  P->sym_bits, P->wcls, P->skpart};
+                    P->wstkg,    P->sym_tiles,  P->sym_p1,   P->sym_p2,  P->sym_bits, P->wcls, P->skpart,
+                    P->sym_cls};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete P->fmm;
@@ -2673,7 +2793,8 @@ static mhlp_status plan_create_impl(const mhlp_geometry *g, double alpha, const 
         P->sym_ntiles = (int32_t)tiles.size();
         P->sym_nw = (int32_t)((g->Np + 31) / 32);
         if ((s = dalloc(&P->sym_tiles, (int64_t)tiles.size())) || (s = dalloc(&P->sym_p1, ncc * g->N)) ||
-            (s = dalloc(&P->sym_p2, nrb * g->N)) || (s = dalloc(&P->sym_bits, (int64_t)P->sym_nw * g->N))) {
+            (s = dalloc(&P->sym_p2, nrb * g->N)) || (s = dalloc(&P->sym_bits, (int64_t)P->sym_nw * g->N)) ||
+            (s = dalloc(&P->sym_cls, nrb * (SYM_R / 64) * g->Np))) {
             mhlp_plan_destroy(P);
             return s;
         }
@@ -2757,6 +2878,8 @@ static mhlp_status plan_create_impl(const mhlp_geometry *g, double alpha, const 
     }
     if (P->sym_bits) {
         near_bits_kernel<<<nblocks(M, 256), 256, 0, st>>>(P->near_ptr, P->near_panel, M, P->sym_nw, P->sym_bits);
+        sym_class_kernel<<<nblocks(M, SYM_R), SYM_R, 0, st>>>(P->g->soa, P->g->soa + P->g->N, M, P->g->Np,
+                                                               P->alpha, P->sym_bits, P->sym_nw, P->sym_cls);
         hipError_t eb = hipGetLastError();
         if (eb == hipSuccess) eb = hipStreamSynchronize(st); /* later calls may come on other streams */
         if (eb != hipSuccess) {
@@ -2885,7 +3008,7 @@ static mhlp_status launch_far(const mhlp_plan *P, const double *sigma, const dou
     A.skpd = P->skpart + (int64_t)P->sk_S * P->M;
     A.wcls = P->wcls;
     if (P->sym_tiles && !sigma && mu && precision == MHLP_FP64) {
-        SymArgs S{A, P->sym_tiles, P->sym_p1, P->sym_p2, P->sym_bits, P->sym_nw};
+        SymArgs S{A, P->sym_tiles, P->sym_p1, P->sym_p2, P->sym_bits, P->sym_nw, P->sym_cls};
         sym_far_kernel<<<(unsigned)P->sym_ntiles, SYM_R, 0, st>>>(S);
         sym_finalize<<<nblocks(A.M, FZ_TG), FZ_TG * FZ_L, 0, st>>>(S, (int)((g->N + SYM_C - 1) / SYM_C));
         HIPCHECK(hipGetLastError());
