@@ -68,12 +68,12 @@ FLOP_PER_PAIR_STOKES_GRAD = 219
 # launch shapes (far-field source splits) chosen by the autotuner on MI355X for
 # the plans of this benchmark
 TUNED_SPLITS = os.path.join(ROOT, "paper_1908_07392_amd", "tuning", "mi355x_far_splits.json")
-# HBM bytes per fused FP64 evaluation (FETCH_SIZE + WRITE_SIZE, each scaled by
-# the same counter's reading for a plain 256 MiB copy), averaged over the three
-# alphas, for the current kernel and launch shape (one stream launch of 4 x the
-# resident blocks) (profiles/far_eval_fp64_starfish4096_grid512_hbm_bytes.txt);
-# None until taken for this kernel
-PROFILED_TRAFFIC = None
+# HBM bytes per fused FP64 evaluation (FETCH_SIZE + WRITE_SIZE of far_eval_fp64
+# and far_sk_finalize, each scaled by the same counter's reading for a plain
+# 256 MiB copy), averaged over the three alphas, for the current kernels and
+# launch shape (one stream launch of 4 x the resident blocks)
+# (profiles/far_eval_fp64_starfish4096_grid512_hbm_bytes.txt)
+PROFILED_TRAFFIC = 99033203
 
 
 def parse():
