@@ -84,11 +84,34 @@ typedef struct {
 
 const char *mhlp_last_error(void);
 
-/* Geometry from node data.  node_soa: device [6][N] float64, rows x, y,
-   dx/dt, dy/dt, d2x/dt2, d2y/dt2 (derivatives with respect to the panel
-   parameter t in [-1,1]; Sec. 3.2).  n_panels >= 1.  Synchronises the stream.
-   Errors: MHLP_INVALID_ARG (null pointers, n_panels < 1), MHLP_HIP_ERROR. */
-mhlp_status mhlp_geometry_create(const double *node_soa, int64_t n_panels, void *stream, mhlp_geometry **out);
+/* Geometry of the composite panel discretisation (Sec. 3.2: each of the
+   closed curves of the boundary is divided into panels carrying 16
+   Gauss-Legendre nodes; with the interpolation of Sec. 4.5.3 we take a
+   panel to be the degree-15 polynomial through its nodes, so node data
+   determine it).
+   n_curves >= 1 closed curves; curve_panel_offsets: HOST [n_curves + 1],
+   curve c owns panels offsets[c] .. offsets[c+1]-1 (offsets[0] = 0,
+   strictly increasing; Np = offsets[n_curves]).  nodes_per_panel: 16 (other
+   values MHLP_UNSUPPORTED).  node_soa: device [6][N], N = 16 Np, rows x, y,
+   dx/dt, dy/dt, d2x/dt2, d2y/dt2 with derivatives in the panel parameter
+   t in [-1,1], panels in curve order, each curve oriented with the domain
+   on its left.  panel_ends: device [4][Np] (xa, ya, xb, yb: the points
+   t = -1 and t = 1 of each panel) or NULL; when given they are checked, not
+   used: each must lie within 1e-6 of the panel's arclength of the node
+   polynomial's end, and the end of every panel within that of the start of
+   the next panel of its curve (the last panel of a curve is followed by
+   its first), else MHLP_INVALID_ARG naming the panel.  The library copies
+   everything it needs; the caller may free its arrays on return.
+   Synchronises the stream.  Errors: MHLP_INVALID_ARG (null pointers, bad
+   offsets, panel_ends inconsistent), MHLP_UNSUPPORTED, MHLP_HIP_ERROR,
+   MHLP_NO_MEMORY. */
+mhlp_status mhlp_geometry_create(int32_t n_curves, const int32_t *curve_panel_offsets, int32_t nodes_per_panel,
+                                 const double *node_soa, const double *panel_ends, void *stream,
+                                 mhlp_geometry **out);
+/* Sizes and curve offsets of a geometry (host outputs, any may be NULL;
+   curve_panel_offsets receives at most cap entries). */
+mhlp_status mhlp_geometry_info(const mhlp_geometry *geom, int64_t *n_nodes, int64_t *n_panels, int32_t *n_curves,
+                               int32_t *curve_panel_offsets, int32_t cap);
 mhlp_status mhlp_geometry_destroy(mhlp_geometry *geom);
 /* Device views (valid for the geometry's lifetime): per-node quadrature
    weight, unit normal (x, y) and signed curvature. Any output may be NULL. */
@@ -137,13 +160,24 @@ mhlp_status mhlp_plan_autotune(mhlp_plan *plan, int32_t layers, int32_t precisio
                                int32_t *best_nsplit, double *best_ms, int32_t *cand, double *cand_ms, int32_t cap,
                                int32_t *n_cand);
 
-/* S[sigma] and/or D[mu] at the plan's targets (sigma, mu: device [N];
+/* Layer potentials of the modified Helmholtz (Yukawa) kernel, the K0 part of
+   the paper's modified-biharmonic Green's function (Sec. 2, App. B):
+     S[sigma](x) = int_Gamma K0(alpha|x-y|)/(2 pi) sigma(y) dS_y,
+     D[mu](x)    = int_Gamma alpha K1(alpha r) (x-y).n_y / (2 pi r) mu(y) dS_y,
+   discretised by the composite 16-point Nystrom rule of Sec. 3.2, with the
+   near-boundary and on-boundary quadrature of Sec. 4.5 (kernel split of
+   Sec. 4.1, upsampling and subdivision of Sec. 4.5.3-4.5.4) replacing the
+   rule on the plan's near panels.
+   S[sigma] and/or D[mu] at the plan's targets (sigma, mu: device [N];
    u_slp, u_dlp: device [M], overwritten).  Either density/output pair may be
    NULL (then that potential is skipped), not both.  On an on-surface plan,
    D is the principal value (no 1/2 mu term) and S is the on-surface value.
    Far field in FP64 or mixed precision; near-field corrections FP64. */
 mhlp_status mhlp_eval_layer(const mhlp_plan *plan, const double *sigma, const double *mu, double *u_slp,
                             double *u_dlp, int32_t precision, void *stream);
+/* S[sigma] alone (eval_slp) and D[mu] alone (eval_dlp): the same sums as
+   mhlp_eval_layer with one density; u: device [M], overwritten.  Errors as
+   mhlp_eval_layer (MHLP_INVALID_ARG for NULL arrays or a stokes plan). */
 mhlp_status mhlp_eval_slp(const mhlp_plan *plan, const double *sigma, double *u, int32_t precision, void *stream);
 mhlp_status mhlp_eval_dlp(const mhlp_plan *plan, const double *mu, double *u, int32_t precision, void *stream);
 

@@ -76,6 +76,7 @@ struct mhlp_geometry {
     double *w = nullptr, *nx = nullptr, *ny = nullptr, *kappa = nullptr;
     double *pa = nullptr; /* [Np][16] complex Legendre coefficients of the panel relative to its node 7 */
     double *ph = nullptr, *pcx = nullptr, *pcy = nullptr, *prad = nullptr;
+    std::vector<int32_t> curve_off; /* host: first panel of each curve, then Np */
 };
 
 /* Device state of one GMRES cycle (see the GMRES section). */
@@ -130,6 +131,7 @@ struct mhlp_plan {
     double *part = nullptr;   /* [2][nsplit][M] partial sums ([4][..] off-surface, for gradients) */
     /* FP64 far field as a stream of (target block, panel) units (far_eval_fp64) */
     uint8_t *wcls = nullptr;  /* [M/64 waves][Np] fine piece + 1 of each (wave, panel) */
+    double *fqd = nullptr;    /* [2][KQ_NP] fine-piece scales at alpha (fine_scales) */
     int32_t sk_P[3] = {0, 0, 0}; /* blocks of the launch (resident blocks of the chip) for SLP+DLP, SLP, DLP */
     int32_t sk_S = 0;            /* partial slots per target block, the largest over the three */
     int32_t sk_stride = 1;       /* unit order within a target block (coprime to Np)            */
@@ -204,6 +206,40 @@ __host__ __device__ inline void geom_prep_body(int64_t p, const double *__restri
     pcx[p] = c.re;
     pcy[p] = c.im;
     prad[p] = r;
+}
+
+/* given panel ends must lie within this fraction of the panel's arclength of
+   the node polynomial's ends and of the next panel's start */
+constexpr double PANEL_ENDS_TOL = 1e-6;
+
+/* Checks given panel end points against the node data (Sec. 3.2: a panel is
+   the degree-15 polynomial through its 16 nodes, so its ends are tau(-1) and
+   tau(1)) and the chain of each closed curve (the end of a panel is the
+   start of the next panel of its curve).  ends: [4][Np] xa, ya, xb, yb.
+   flag[p]: bit 0 an end further than tol*h from the polynomial's end, bit 1
+   the end of p further than tol*h from the start of next[p]. */
+__global__ void panel_ends_kernel(const double *__restrict__ pa, const double *__restrict__ x,
+                                  const double *__restrict__ y, const double *__restrict__ ph,
+                                  const double *__restrict__ ends, const int32_t *__restrict__ next, int64_t Np,
+                                  double tol, int32_t *__restrict__ flag)
+{
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= Np) return;
+    double ax = x[16 * p + 7], ay = y[16 * p + 7], bx = ax, by = ay;
+    for (int m = 0; m < 16; ++m) {
+        const double cr = pa[(16 * p + m) * 2], ci = pa[(16 * p + m) * 2 + 1];
+        bx += cr;
+        by += ci;
+        ax += (m & 1) ? -cr : cr;
+        ay += (m & 1) ? -ci : ci;
+    }
+    const double lim = tol * ph[p];
+    const double xa = ends[p], ya = ends[Np + p], xb = ends[2 * Np + p], yb = ends[3 * Np + p];
+    int32_t f = 0;
+    if (!(hypot(xa - ax, ya - ay) <= lim && hypot(xb - bx, yb - by) <= lim)) f |= 1;
+    const int64_t q = next[p];
+    if (!(hypot(xb - ends[q], yb - ends[Np + q]) <= lim)) f |= 2;
+    flag[p] = f;
 }
 
 __global__ void geom_prep_kernel(const double *__restrict__ soa, int64_t N, int64_t Np, double *__restrict__ w,
@@ -469,7 +505,6 @@ struct FarArgs {
     int64_t jstride;
     const int32_t *perm; /* output index of internal target i (NULL: identity) */
     const double *pcx, *pcy, *prad; /* bounding circle of each panel */
-    FineConst fq;                   /* per-alpha constants of the fine pieces */
     /* FP64 far field as a stream of (target block, panel) units: the launch's
        skP blocks take equal contiguous ranges of the skU = TB Np units and
        leave one partial sum per target block they touch, slot = block - first
@@ -480,6 +515,7 @@ struct FarArgs {
     int32_t skStride; /* unit j of a target block is panel (j skStride) mod Np */
     double *skps, *skpd;
     const uint8_t *wcls;
+    const double *fq; /* [2][KQ_NP] scales of the fine pieces at the plan's alpha (fine_scales) */
 };
 
 
@@ -635,8 +671,9 @@ __device__ __forceinline__ double sym_columns(const FarArgs &A, const FarConst &
                                               double (*colv)[SYM_R])
 {
     constexpr int K = PC < 0 || PC >= KQ_NP ? 0 : PC;
-    const double qa = A.fq.qa[K], qk = A.fq.qk[K];
     const FarTab T = far_table();
+    double qa, qk;
+    fine_q<K>(A.fq, qa, qk);
     const int t = threadIdx.x;
     double acc = 0.0;
 #pragma unroll 1
@@ -890,10 +927,11 @@ __device__ __forceinline__ void far_panel_fp64(const FarArgs &A, const FarConst 
                                                double &accd)
 {
     constexpr int K = PC < 0 || PC >= KQ_NP ? 0 : PC;
-    const double qa = A.fq.qa[K], qk = A.fq.qk[K];
     /* the table pointer once per panel: the piece's coefficients stay in
        scalar registers for its 8 loop trips */
     const FarTab T = far_table();
+    double qa, qk;
+    fine_q<K>(A.fq, qa, qk);
 #pragma unroll 1
     for (int s = 0; s < 16; s += 2) {
         const int a0 = l0 + s, a1 = a0 + 1;
@@ -913,6 +951,18 @@ __device__ __forceinline__ void far_panel_fp64(const FarArgs &A, const FarConst 
 
 /* waves per SIMD the FP64 far kernel is compiled for (96 registers per lane) */
 constexpr int SK_WAVES = 5;
+
+/* The stream position of hardware block b of a P-block launch.  The chip's
+   dispatcher deals blocks to its 8 XCDs (each with its own L2) in turn, block b
+   to XCD b mod 8; numbering the stream XCD by XCD gives each XCD one
+   contiguous stretch of it, so the blocks that share a target block share an
+   L2 and read its targets and class rows from there.  A bijection of
+   [0, P) for every P. */
+__device__ __forceinline__ int64_t xcd_major(int64_t b, int64_t P)
+{
+    const int64_t q = P >> 3, r = P & 7, x = b & 7, k = b >> 3;
+    return x * q + (x < r ? x : r) + k;
+}
 
 /* first unit of block b of the stream decomposition, and the block that holds unit u */
 __host__ __device__ inline int64_t sk_start(int64_t U, int P, int64_t b) { return (U * b) / P; }
@@ -946,8 +996,9 @@ __global__ __launch_bounds__(FT_THREADS, SK_WAVES) void far_eval_fp64(FarArgs A)
     const double *mu;
     if (!far_density(A, mu)) return;
     const int64_t Np = A.Np;
-    int64_t u = sk_start(A.skU, A.skP, blockIdx.x);
-    const int64_t uend = sk_start(A.skU, A.skP, (int64_t)blockIdx.x + 1);
+    const int64_t blk = xcd_major(blockIdx.x, A.skP);
+    int64_t u = sk_start(A.skU, A.skP, blk);
+    const int64_t uend = sk_start(A.skU, A.skP, blk + 1);
     const FarConst fc = far_const(A.alpha);
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     while (u < uend) {
@@ -1018,7 +1069,7 @@ __global__ __launch_bounds__(FT_THREADS, SK_WAVES) void far_eval_fp64(FarArgs A)
                 }
             }
         }
-        const int64_t slot = (int64_t)blockIdx.x - sk_block_of(A.skU, A.skP, tb * Np);
+        const int64_t slot = blk - sk_block_of(A.skU, A.skP, tb * Np);
         if (valid) {
             if (SLP) A.skps[slot * A.M + i] = accs;
             if (DLP) A.skpd[slot * A.M + i] = accd;
@@ -2513,18 +2564,28 @@ static GeoView view(const mhlp_geometry *g)
 /* ------------------------------------------------------------------------ */
 /* geometry API                                                              */
 /* ------------------------------------------------------------------------ */
-extern "C" mhlp_status mhlp_geometry_create(const double *node_soa, int64_t n_panels, void *stream,
-                                            mhlp_geometry **out)
+extern "C" mhlp_status mhlp_geometry_create(int32_t n_curves, const int32_t *curve_panel_offsets,
+                                            int32_t nodes_per_panel, const double *node_soa,
+                                            const double *panel_ends, void *stream, mhlp_geometry **out)
 {
     if (!out) return fail(MHLP_INVALID_ARG, "out is NULL");
     *out = nullptr;
     if (!node_soa) return fail(MHLP_INVALID_ARG, "node_soa is NULL");
-    if (n_panels < 1 || n_panels > (INT_MAX / 16)) return fail(MHLP_INVALID_ARG, "n_panels out of range");
+    if (!curve_panel_offsets) return fail(MHLP_INVALID_ARG, "curve_panel_offsets is NULL");
+    if (n_curves < 1) return fail(MHLP_INVALID_ARG, "n_curves must be >= 1");
+    if (nodes_per_panel != 16) return fail(MHLP_UNSUPPORTED, "nodes_per_panel must be 16");
+    if (curve_panel_offsets[0] != 0) return fail(MHLP_INVALID_ARG, "curve_panel_offsets[0] must be 0");
+    for (int32_t c = 0; c < n_curves; ++c)
+        if (curve_panel_offsets[c + 1] <= curve_panel_offsets[c])
+            return fail(MHLP_INVALID_ARG, "curve_panel_offsets must increase (every curve has a panel)");
+    const int64_t n_panels = curve_panel_offsets[n_curves];
+    if (n_panels > (INT_MAX / 16)) return fail(MHLP_INVALID_ARG, "n_panels out of range");
     hipStream_t st = (hipStream_t)stream;
     mhlp_geometry *g = new mhlp_geometry();
     HIPCHECK(hipGetDevice(&g->device));
     g->Np = n_panels;
     g->N = 16 * n_panels;
+    g->curve_off.assign(curve_panel_offsets, curve_panel_offsets + n_curves + 1);
     const int64_t N = g->N, Np = g->Np;
     mhlp_status s;
     if ((s = dalloc(&g->soa, 6 * N)) || (s = dalloc(&g->w, N)) || (s = dalloc(&g->nx, N)) || (s = dalloc(&g->ny, N)) ||
@@ -2539,12 +2600,56 @@ extern "C" mhlp_status mhlp_geometry_create(const double *node_soa, int64_t n_pa
                                                           g->pcx, g->pcy, g->prad);
         e = hipGetLastError();
     }
+    std::vector<int32_t> flags;
+    int32_t *dnext = nullptr;
+    if (e == hipSuccess && panel_ends) {
+        std::vector<int32_t> next((size_t)Np);
+        for (int32_t c = 0; c < n_curves; ++c)
+            for (int32_t p = curve_panel_offsets[c]; p < curve_panel_offsets[c + 1]; ++p)
+                next[p] = (p + 1 < curve_panel_offsets[c + 1]) ? p + 1 : curve_panel_offsets[c];
+        flags.resize((size_t)Np);
+        /* one buffer: next panels, then the flags */
+        if ((s = dalloc(&dnext, 2 * Np))) {
+            mhlp_geometry_destroy(g);
+            return s;
+        }
+        e = hipMemcpyAsync(dnext, next.data(), sizeof(int32_t) * Np, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) {
+            panel_ends_kernel<<<nblocks(Np, 64), 64, 0, st>>>(g->pa, g->soa, g->soa + N, g->ph, panel_ends, dnext, Np,
+                                                              PANEL_ENDS_TOL, dnext + Np);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(flags.data(), dnext + Np, sizeof(int32_t) * Np, hipMemcpyDeviceToHost, st);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (dnext) (void)hipFree(dnext);
     if (e != hipSuccess) {
         mhlp_geometry_destroy(g);
         return fail(MHLP_HIP_ERROR, std::string("geometry_create: ") + hipGetErrorString(e));
     }
+    for (int64_t p = 0; p < (int64_t)flags.size(); ++p)
+        if (flags[p]) {
+            mhlp_geometry_destroy(g);
+            return fail(MHLP_INVALID_ARG,
+                        std::string("panel_ends: panel ") + std::to_string(p) +
+                            ((flags[p] & 1) ? " does not end where its node polynomial ends"
+                                            : " does not end where the next panel of its curve starts"));
+        }
     *out = g;
+    return MHLP_OK;
+}
+
+extern "C" mhlp_status mhlp_geometry_info(const mhlp_geometry *g, int64_t *n_nodes, int64_t *n_panels,
+                                          int32_t *n_curves, int32_t *curve_panel_offsets, int32_t cap)
+{
+    if (!g) return fail(MHLP_INVALID_ARG, "geometry is NULL");
+    const int32_t nc = (int32_t)g->curve_off.size() - 1;
+    if (n_nodes) *n_nodes = g->N;
+    if (n_panels) *n_panels = g->Np;
+    if (n_curves) *n_curves = nc;
+    if (curve_panel_offsets)
+        for (int32_t c = 0; c <= nc && c < cap; ++c) curve_panel_offsets[c] = g->curve_off[c];
     return MHLP_OK;
 }
 
@@ -2612,7 +2717,7 @@ extern "C" mhlp_status mhlp_plan_destroy(mhlp_plan *P)
     void *ptrs[] = {P->near_ptr, P->near_panel, P->near_tgt, P->near_ts, P->wslp,  P->wdlp,    P->ws,
                     P->hdev,     P->part,       P->gdev,     P->perm,    P->wgrad, P->wstk,    P->stk_flux,
                     P->wstkg,    P->sym_tiles,  P->sym_p1,   P->sym_p2,  P->sym_bits, P->wcls, P->skpart,
-                    P->sym_cls};
+                    P->sym_cls,  P->fqd};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete P->fmm;
@@ -2669,6 +2774,10 @@ static mhlp_status far_stream_setup(mhlp_plan *P, hipStream_t st)
     }
     TRY(dalloc(&P->skpart, 2 * (int64_t)smax * M));
     TRY(dalloc(&P->wcls, TB * (FT_THREADS / 64) * Np));
+    double fq[2 * KQ_NP];
+    fine_scales(P->alpha, fq);
+    TRY(dalloc(&P->fqd, 2 * KQ_NP));
+    HIPCHECK(hipMemcpyAsync(P->fqd, fq, sizeof(fq), hipMemcpyHostToDevice, st)); /* fq lives until the sync below */
     far_class_kernel<<<(unsigned)TB, FT_THREADS, 0, st>>>(P->tx, P->ty, M, P->g->soa, P->g->soa + P->g->N, Np,
                                                           P->alpha, P->near_ptr, P->near_panel, P->wcls);
     HIPCHECK(hipGetLastError());
@@ -2798,7 +2907,13 @@ static mhlp_status plan_create_impl(const mhlp_geometry *g, double alpha, const 
             mhlp_plan_destroy(P);
             return s;
         }
-        HIPCHECK(hipMemcpy(P->sym_tiles, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice));
+        hipError_t e = hipMemcpyAsync(P->sym_tiles, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice,
+                                      st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);  /* tiles is freed at the end of this block */
+        if (e != hipSuccess) {
+            mhlp_plan_destroy(P);
+            return fail(MHLP_HIP_ERROR, std::string("plan_create tile copy: ") + hipGetErrorString(e));
+        }
     }
     int32_t *cnt = nullptr;
     if ((s = dalloc(&cnt, M + 1)) || (s = dalloc(&P->near_ptr, M + 1))) {
@@ -2999,7 +3114,6 @@ static mhlp_status launch_far(const mhlp_plan *P, const double *sigma, const dou
     A.pcx = g->pcx;
     A.pcy = g->pcy;
     A.prad = g->prad;
-    A.fq = fine_const(P->alpha);
     A.skU = (int64_t)((P->M + FT_THREADS - 1) / FT_THREADS) * g->Np;
     A.skP = P->sk_P[0];
     A.skS = P->sk_S;
@@ -3007,6 +3121,7 @@ static mhlp_status launch_far(const mhlp_plan *P, const double *sigma, const dou
     A.skps = P->skpart;
     A.skpd = P->skpart + (int64_t)P->sk_S * P->M;
     A.wcls = P->wcls;
+    A.fq = P->fqd;
     if (P->sym_tiles && !sigma && mu && precision == MHLP_FP64) {
         SymArgs S{A, P->sym_tiles, P->sym_p1, P->sym_p2, P->sym_bits, P->sym_nw, P->sym_cls};
         sym_far_kernel<<<(unsigned)P->sym_ntiles, SYM_R, 0, st>>>(S);

@@ -414,22 +414,28 @@ __device__ __forceinline__ void k01_far2_big(FarTab T, const FarConst &c, double
 }
 
 /* The fine piece K at 1/r = ri: value and, with both layers, (4/alpha^2) dP/du
-   as far_finish<.., K1R> takes it.  v = qa ri + qb with
-   qa = (4/alpha) w, w = 2/(uhi - ulo), and qk = (4/alpha^2) w (per-launch values
-   of FineConst). */
-struct FineConst {
-    double qa[KQ_NP], qk[KQ_NP];
-};
-
-__host__ __device__ inline FineConst fine_const(double alpha)
+   as far_finish<.., K1R> takes it.  v = qa ri + qb with qa = (4/alpha) w,
+   w = 2/(uhi - ulo), and qk = (4/alpha^2) w.  A plan keeps the qa of every
+   piece, then every qk, in device memory (fine_scales); fine_q reads the two
+   of piece K through an opaque pointer, once per panel, into scalar
+   registers (the compiler cannot hoist the reads of all pieces out of the
+   loops, where they would stay live). */
+__host__ inline void fine_scales(double alpha, double *q)
 {
-    FineConst f;
     for (int k = 0; k < KQ_NP; ++k) {
         const double w = 2.0 / (KQ_UHI[k] - KQ_ULO[k]);
-        f.qa[k] = 4.0 / alpha * w;
-        f.qk[k] = 4.0 / (alpha * alpha) * w;
+        q[k] = 4.0 / alpha * w;
+        q[KQ_NP + k] = 4.0 / (alpha * alpha) * w;
     }
-    return f;
+}
+
+template <int K>
+__device__ __forceinline__ void fine_q(const double *fq, double &qa, double &qk)
+{
+    const MHLP_CAS double *q = (const MHLP_CAS double *)fq;
+    asm volatile("" : "+s"(q));
+    qa = q[K];
+    qk = q[KQ_NP + K];
 }
 
 template <bool SLP, bool DLP, int K>
@@ -451,7 +457,7 @@ __device__ __forceinline__ double far_piece_fine(FarTab T, double qa, double qk,
    one piece: PC = 0..KQ_NP-1 the fine pieces, PC = -1 z <= 2 (k01_far_small).  The
    arithmetic of k01_far2's z > 2 form with the fine piece's polynomial and
    without any per-pair selection: for launches that classify a whole wave
-   against a panel beforehand (qa, qk: the piece's FineConst entries). */
+   against a panel beforehand (qa, qk: the piece's scales from fine_q). */
 template <bool SLP, bool DLP, int PC>
 __device__ __forceinline__ void k01_far2_fixed(FarTab T, const FarConst &c, double qa, double qk, double r2a,
                                                double r2b, K01 &oa, K01 &ob)

@@ -52,7 +52,11 @@ class GmresInfo(ctypes.Structure):
 _V = ctypes.c_void_p
 _SIGS = {
     "mhlp_last_error": ([], ctypes.c_char_p),
-    "mhlp_geometry_create": ([_V, ctypes.c_int64, _V, ctypes.POINTER(_V)], ctypes.c_int32),
+    "mhlp_geometry_create": ([ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, _V, _V, _V,
+                              ctypes.POINTER(_V)], ctypes.c_int32),
+    "mhlp_geometry_info": ([_V, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                            ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), ctypes.c_int32],
+                           ctypes.c_int32),
     "mhlp_geometry_destroy": ([_V], ctypes.c_int32),
     "mhlp_geometry_arrays": ([_V, ctypes.POINTER(_V), ctypes.POINTER(_V), ctypes.POINTER(_V), ctypes.POINTER(_V)],
                              ctypes.c_int32),
@@ -167,19 +171,43 @@ def _stream():
 
 
 class Geometry:
-    """Panel geometry on the device from a ``[6][N]`` float64 node array."""
+    """Panel geometry on the device from a ``[6][N]`` float64 node array.
 
-    def __init__(self, node_soa: torch.Tensor):
+    curve_panel_offsets: first panel of each closed curve, then the panel
+    count (host sequence; default: one curve).  panel_ends: optional device
+    ``[4][Np]`` float64 (xa, ya, xb, yb), checked by the library against the
+    node data and the curve chain."""
+
+    def __init__(self, node_soa: torch.Tensor, curve_panel_offsets=None, panel_ends: torch.Tensor | None = None):
         L = load()
         if node_soa.dim() != 2 or node_soa.shape[0] != 6 or node_soa.shape[1] % 16:
             raise MhlpError("node_soa must be [6][16*n_panels]")
         self.n_nodes = int(node_soa.shape[1])
         self.n_panels = self.n_nodes // 16
         self.device = node_soa.device
+        if curve_panel_offsets is None:
+            curve_panel_offsets = [0, self.n_panels]
+        offs = [int(v) for v in curve_panel_offsets]
+        if len(offs) < 2 or offs[-1] != self.n_panels:
+            raise MhlpError("curve_panel_offsets must end with the panel count of node_soa")
+        if panel_ends is not None and tuple(panel_ends.shape) != (4, self.n_panels):
+            raise MhlpError("panel_ends must be [4][n_panels]")
+        self.curve_panel_offsets = offs
+        c_offs = (ctypes.c_int32 * len(offs))(*offs)
         h = ctypes.c_void_p()
-        _check(L.mhlp_geometry_create(_dev(node_soa, "node_soa"), self.n_panels, _stream(), ctypes.byref(h)),
-               "geometry_create")
+        ends = _dev(panel_ends, "panel_ends") if panel_ends is not None else None
+        _check(L.mhlp_geometry_create(len(offs) - 1, c_offs, 16, _dev(node_soa, "node_soa"), ends, _stream(),
+                                      ctypes.byref(h)), "geometry_create")
         self._h = h
+
+    def info(self):
+        """(n_nodes, n_panels, curve_panel_offsets) as the library holds them."""
+        n, np_, nc = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+        _check(load().mhlp_geometry_info(self._h, ctypes.byref(n), ctypes.byref(np_), ctypes.byref(nc), None, 0),
+               "geometry_info")
+        offs = (ctypes.c_int32 * (nc.value + 1))()
+        _check(load().mhlp_geometry_info(self._h, None, None, None, offs, nc.value + 1), "geometry_info")
+        return n.value, np_.value, list(offs)
 
     @property
     def handle(self):

@@ -163,6 +163,7 @@ class Geometry:
     gl_w: np.ndarray           # 16 Gauss-Legendre weights
     lengths: np.ndarray        # arclength of each curve
     theta_w: np.ndarray = None  # quadrature weight in theta (half panel span in theta x GL weight)
+    panel_theta: np.ndarray = None  # [Np][2] curve parameter at the panel ends (t = -1, t = 1)
 
     @property
     def n_nodes(self) -> int:
@@ -200,6 +201,17 @@ class Geometry:
         """``[6][N]`` float64: x, y, dx/dt, dy/dt, d2x/dt2, d2y/dt2."""
         return np.ascontiguousarray(np.stack([self.x, self.y, self.dx, self.dy, self.d2x, self.d2y]))
 
+    def panel_ends(self) -> np.ndarray:
+        """``[4][Np]`` float64: xa, ya, xb, yb, the curve points at the panel ends."""
+        offs = self.curve_panel_offsets
+        out = np.empty((4, self.n_panels))
+        for c, curve in enumerate(self.curves):
+            sl = slice(offs[c], offs[c + 1])
+            za, _, _ = curve.eval(self.panel_theta[sl, 0])
+            zb, _, _ = curve.eval(self.panel_theta[sl, 1])
+            out[:, sl] = [za.real, za.imag, zb.real, zb.imag]
+        return out
+
     def contains(self, x, y):
         """Inside the domain: inside the outer curve (index 0) and outside every hole."""
         inside = self.curves[0].contains(x, y)
@@ -215,7 +227,7 @@ def discretize(curves, panels_per_curve) -> Geometry:
     if np.isscalar(panels_per_curve):
         panels_per_curve = [int(panels_per_curve)] * len(curves)
     t, lam = _gl(NODES_PER_PANEL)
-    xs, ys, dxs, dys, d2xs, d2ys, ths, cid, lens, thw = [], [], [], [], [], [], [], [], [], []
+    xs, ys, dxs, dys, d2xs, d2ys, ths, cid, lens, thw, pth = [], [], [], [], [], [], [], [], [], [], []
     for ci, (c, npan) in enumerate(zip(curves, panels_per_curve)):
         bps, L = _arclength_breakpoints(c, int(npan))
         a, b = bps[:-1], bps[1:]
@@ -229,10 +241,11 @@ def discretize(curves, panels_per_curve) -> Geometry:
         d2xs.append(d2zt.real.ravel()); d2ys.append(d2zt.imag.ravel())
         ths.append(th.ravel()); cid.append(np.full(th.size, ci, dtype=np.int32))
         thw.append((half[:, None] * lam[None, :]).ravel())
+        pth.append(np.stack([a, b], axis=1))
         lens.append(L)
     cat = np.concatenate
     return Geometry(list(curves), [int(p) for p in panels_per_curve], cat(xs), cat(ys), cat(dxs), cat(dys),
-                    cat(d2xs), cat(d2ys), cat(ths), cat(cid), t, lam, np.asarray(lens), cat(thw))
+                    cat(d2xs), cat(d2ys), cat(ths), cat(cid), t, lam, np.asarray(lens), cat(thw), cat(pth))
 
 
 # --------------------------------------------------------------------------------------

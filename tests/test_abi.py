@@ -37,3 +37,30 @@ def test_binding_signatures_cover_header():
     assert set(declared_symbols()) <= set(mhlp._SIGS)
     lib = mhlp.load()
     assert lib.mhlp_last_error() is not None
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libmhlp.so not built (run __graft_entry__.build())")
+def test_geometry_create_validates_before_any_device_work():
+    """Argument checks of mhlp_geometry_create return before the library touches
+    the device (the node pointer is a placeholder and is never read)."""
+    lib = ctypes.CDLL(LIB)
+    lib.mhlp_geometry_create.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.POINTER(ctypes.c_void_p)]
+    lib.mhlp_last_error.restype = ctypes.c_char_p
+    fake = ctypes.c_void_p(4096)
+    out = ctypes.c_void_p()
+
+    def call(nc, offs, npp, soa=fake):
+        arr = (ctypes.c_int32 * len(offs))(*offs) if offs is not None else None
+        return lib.mhlp_geometry_create(nc, arr, npp, soa, None, None, ctypes.byref(out))
+
+    assert call(1, [0, 8], 8) == -3            # MHLP_UNSUPPORTED: 16 nodes per panel only
+    assert b"16" in lib.mhlp_last_error()
+    assert call(0, [0], 16) == -1              # no curve
+    assert call(1, [1, 8], 16) == -1           # offsets must start at 0
+    assert call(2, [0, 4, 4], 16) == -1        # an empty curve
+    assert call(2, [0, 6, 5], 16) == -1        # decreasing
+    assert call(1, None, 16) == -1             # no offsets
+    assert call(1, [0, 8], 16, soa=None) == -1  # no node data
+    assert out.value is None
