@@ -11,8 +11,11 @@ targets (fused kernel, near-field corrections included).  Plans (near lists
 and correction weights) are built once before timing, as the paper
 precomputes them; their build time is reported separately.
 
-value = far-field pair evaluations (GMRES mat-vecs + target evaluation) per
-second of the whole step.  Prints one JSON line.
+value = far-field kernel evaluations per second of the whole step: M N for
+each target evaluation and N (N - 1) / 2 for each GMRES operator application
+(the FP64 on-surface operator evaluates each unordered pair once and uses it
+for both of its terms); pair_terms_per_s counts the N^2 terms of each
+application instead.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -82,7 +85,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--grid", type=int, default=512)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle CPU baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=8.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched, volume, warm-start and gradient legs")
     ap.add_argument("--legs", default="batched,volume,warm,gradient,stokes,fmm,step",
@@ -114,6 +117,39 @@ def cpu_baseline(cfg, alpha, budget_s):
     return dict(value=pairs / t_used / 1e9, unit="GPair-evals/s", cores=oracle.max_threads(), kind="oracle",
                 sample=f"{done} random targets of the {len(cfg['tx'])} x {g.n_nodes} SLP+DLP evaluation at "
                        f"alpha={alpha:g} ({pairs:.3g} pairs, {t_used:.1f} s)")
+
+
+def cpu_baseline_legs(cfg2, wl):
+    """The oracle on the other workloads, each in full or on its stated sample:
+    the circle evaluation (all 2828 targets), GMRES to 1e-10 on the circle and
+    on the starfish at alpha = 50 (dense oracle operator, assembly and solve
+    timed separately), and the volume sum at the 2048-target sample."""
+    import oracle
+    legs = {}
+    c1 = wl.config1()
+    g1 = c1["geom"]
+    t0 = time.perf_counter()
+    oracle.eval_potentials(g1.x, g1.y, c1["alpha"], c1["tx"], c1["ty"], sigma=c1["sigma"], mu=c1["sigma"])
+    dt = time.perf_counter() - t0
+    legs["circle_eval"] = {"gpair_per_s": round(len(c1["tx"]) * g1.n_nodes / dt / 1e9, 5), "s": round(dt, 3),
+                           "pairs": len(c1["tx"]) * g1.n_nodes}
+    for name, geom, alpha, rhs in (("circle_gmres", g1, c1["alpha"], c1["sigma"]),
+                                   ("starfish_gmres_alpha50", cfg2["geom"], 50.0, cfg2["data"][50.0]["g"])):
+        t0 = time.perf_counter()
+        _, D = oracle.onsurface_matrices(geom.x, geom.y, alpha)
+        A = D + 0.5 * np.eye(geom.n_nodes)
+        t1 = time.perf_counter()
+        _, info = oracle.gmres(A, rhs, tol=1e-10)
+        t2 = time.perf_counter()
+        legs[name] = {"n": geom.n_nodes, "alpha": alpha, "assembly_s": round(t1 - t0, 3), "gmres_ms": round((t2 - t1) * 1e3, 2),
+                      "iters": info["iters"], "residual": info["relres"]}
+    c3 = wl.config3()
+    t0 = time.perf_counter()
+    oracle.volume_eval(c3["x"], c3["y"], c3["w"], c3["f"], c3["alpha"], c3["h"], c3["sample"])
+    dt = time.perf_counter() - t0
+    pairs3 = len(c3["sample"]) * c3["x"].size
+    legs["volume_sample"] = {"gpair_per_s": round(pairs3 / dt / 1e9, 5), "s": round(dt, 3), "pairs": pairs3}
+    return legs
 
 
 def main():
@@ -164,7 +200,7 @@ def main():
     events = []  # (alpha, start, end) around every fused evaluation of the timed region
 
     def step(record=False):
-        pairs = 0
+        pairs = [0, 0]  # kernel evaluations, pair terms
         for a in cfg["alphas"]:
             on, off = plans[a]
             if record:
@@ -182,8 +218,12 @@ def main():
                 stats.setdefault(a, []).append(dict(gmres_ms=(t2 - t1) * 1e3, iters=info["iters"],
                                                     residual=info["rel_residual"]))
             # operator applications of a zero-guess solve: one per Arnoldi step and
-            # one true-residual check per cycle (the first residual is g itself)
-            pairs += (info["iters"] + info["restarts"]) * N * N + M * N
+            # one true-residual check per cycle (the first residual is g itself);
+            # the FP64 operator evaluates each unordered pair once (N(N-1)/2
+            # kernel evaluations give its N^2 terms)
+            napp = info["iters"] + info["restarts"]
+            pairs[0] += napp * (N * (N - 1) // 2) + M * N
+            pairs[1] += napp * N * N + M * N
         return pairs
 
     for _ in range(args.warmup):
@@ -191,9 +231,11 @@ def main():
         step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    total_pairs = 0
+    total_pairs, total_terms = 0, 0
     for _ in range(args.steps):
-        total_pairs += step(record=True)
+        p_ev, p_terms = step(record=True)
+        total_pairs += p_ev
+        total_terms += p_terms
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = elapsed * 1e3 / args.steps
@@ -245,6 +287,7 @@ def main():
            "config": {"workload": f"starfish 256x16 (N={N}), alpha 5/50/500, GMRES to 1e-10 + SLP+DLP at {M} "
                                   f"interior targets of a {args.grid}^2 grid",
                       "n_sources": N, "n_targets": M, "alphas": list(cfg["alphas"]), "precision": "fp64"},
+           "pair_terms_per_s": round(total_terms / elapsed / 1e9, 4),
            "gmres": gm, "plan_build_ms": round(plan_ms, 1), "autotune": tuned, "roofline": roofline}
     # ---- mixed precision (FP32 far field, FP64 near/identity/Arnoldi, GMRES-IR) on the same step
     def mixed_step():
@@ -311,6 +354,7 @@ def main():
         out["implicit_step"] = bench_step(mhlp, wl, cfg, G, t, torch)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, 50.0, args.cpu_seconds)
+        out["cpu_baseline"]["legs"] = cpu_baseline_legs(cfg, wl)
     print(json.dumps(out), flush=True)
 
 

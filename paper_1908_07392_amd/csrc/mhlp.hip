@@ -153,7 +153,8 @@ struct mhlp_plan {
         hipGraphExec_t exec = nullptr;
         const void *ws = nullptr, *part = nullptr, *gdev = nullptr;
         int R = 0, nsplit = 0, S = 0;
-    } graphs[2][2][4]; /* [precision][Gram-Schmidt in one block, over slices][chunk length 1, 2, 4, 8] */
+    } graphs[2][9][4]; /* [precision][steps of the chunk whose Gram-Schmidt runs in one block: 0..8]
+                          [chunk length 1, 2, 4, 8] */
 };
 
 /* ------------------------------------------------------------------------ */
@@ -885,13 +886,11 @@ __global__ __launch_bounds__(256) void sym_class_kernel(const double *__restrict
 
 /* node n: row sums of the chunks from its block on, column sums of the blocks
    up to its own, then the near corrections, 1/(2 pi) and the identity term;
-   FZ_L lanes per node as in far_finalize */
-__global__ __launch_bounds__(FZ_TG *FZ_L) void sym_finalize(SymArgs S, int nchunk)
+   FZ_L lanes per node as in far_finalize.  Every thread of the block returns. */
+__device__ __forceinline__ void sym_finalize_body(const SymArgs &S, const double *mu, int nchunk,
+                                                  double (&red)[2][FZ_L][FZ_TG])
 {
     const FarArgs &A = S.A;
-    __shared__ double red[2][FZ_L][FZ_TG];
-    const double *mu;
-    if (!far_density(A, mu)) return;
     const int g = threadIdx.x % FZ_TG, l = threadIdx.x / FZ_TG;
     const int64_t n = blockIdx.x * (int64_t)FZ_TG + g;
     double fd = 0.0, nd = 0.0;
@@ -908,14 +907,23 @@ __global__ __launch_bounds__(FZ_TG *FZ_L) void sym_finalize(SymArgs S, int nchun
     red[0][l][g] = fd;
     red[1][l][g] = nd;
     __syncthreads();
-    if (l != 0 || n >= A.N) return;
-    for (int q = 1; q < FZ_L; ++q) {
-        fd += red[0][q][g];
-        nd += red[1][q][g];
+    if (l == 0 && n < A.N) {
+        for (int q = 1; q < FZ_L; ++q) {
+            fd += red[0][q][g];
+            nd += red[1][q][g];
+        }
+        double v = fma(INV_2PI, fd, nd);
+        if (A.half_term != 0.0) v = fma(A.half_term, mu[n], v);
+        A.ud[n] = v;
     }
-    double v = fma(INV_2PI, fd, nd);
-    if (A.half_term != 0.0) v = fma(A.half_term, mu[n], v);
-    A.ud[n] = v;
+}
+
+__global__ __launch_bounds__(FZ_TG *FZ_L) void sym_finalize(SymArgs S, int nchunk)
+{
+    __shared__ double red[2][FZ_L][FZ_TG];
+    const double *mu;
+    if (!far_density(S.A, mu)) return;
+    sym_finalize_body(S, mu, nchunk, red);
 }
 
 /* the 16 sources of one LDS panel (offset l0) against the lane's target: PC the
@@ -1966,79 +1974,197 @@ __device__ void gs_finish_block(GState *__restrict__ gs, double *__restrict__ H,
     for (int c = threadIdx.x; c <= k + 1; c += blockDim.x) H[(int64_t)c * R + k] = col[c];
 }
 
-/* The whole Gram-Schmidt part of an Arnoldi step in one block (small N):
-   both CGS passes, the norm, the Hessenberg column with its rotations and the
-   stopping test, the next basis vector and the advance.  Dot products: each
-   thread sums its strided elements, waves reduce by a fixed butterfly, the
-   wave sums are added in wave order. */
 constexpr int GSF_T = 1024, GSF_W = GSF_T / 64, GSF_RMAX = 256;
-/* the one-block form serves vectors up to GSF_NMAX long for the first
-   GSF_STEPS Arnoldi steps of a cycle: its cost grows with the number of basis
-   columns, while the slice form below costs a few short launches per step */
-constexpr int64_t GSF_NMAX = 4096;
-constexpr int GSF_STEPS = 3;
 
+/* The whole Gram-Schmidt part of an Arnoldi step in one block with the new
+   vector held in registers (vectors up to GSR_NMAX long, any step): thread t
+   owns elements t, t + GSF_T, ... (E of them).  The basis columns go through
+   registers in chunks of C = 32 / E; while all columns fit in one chunk they
+   are loaded once, together with the new vector, and serve both CGS passes.
+   A pass forms the thread's partial dot products, sums them over the wave by
+   a fixed butterfly and over the waves in wave order, then subtracts the
+   projection in column order.  Then the norm, the Hessenberg column
+   (gs_finish_block), and the next basis vector from the registers. */
+constexpr int64_t GSR_NMAX = 8 * GSF_T;
+/* basis columns the one-block form keeps in registers for vectors of length N;
+   it serves the steps whose columns all fit, the slice form the later ones */
+__host__ __device__ inline int gsr_cols(int64_t N) { return N <= GSF_T ? 32 : N <= 2 * GSF_T ? 16 : N <= 4 * GSF_T ? 8 : 4; }
 
-/* hs[c] = V_c . w for c < ncol (LDS) */
-__device__ void gsf_dots(const double *__restrict__ V, int64_t ld, const double *__restrict__ w, int64_t N, int ncol,
-                         double (*red)[GSF_RMAX], double *hs)
+/* Sum over the 64 lanes of a wave with DPP moves (no LDS traffic): adds of
+   the value 1, 2, 4, 8 lanes lower within each row of 16 lanes, then the last
+   lane of each row carried into the next row (row_bcast15) and lane 31 into
+   the upper half (row_bcast31): lane 63 then holds the sum, a fixed tree, and
+   readlane returns it to every lane.  Lanes with no source add zero. */
+__device__ __forceinline__ double dpp_add(double v, int ctrl_sel)
 {
-    const int t = threadIdx.x, wv = t >> 6, ln = t & 63;
-    for (int c = 0; c < ncol; ++c) {
-        const double *v = V + (int64_t)c * ld;
-        double sacc = 0.0;
-        for (int64_t i = t; i < N; i += GSF_T) sacc = fma(v[i], w[i], sacc);
-        sacc = gsf_wave_sum(sacc);
-        if (ln == 0) red[wv][c] = sacc;
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    int rlo, rhi;
+    switch (ctrl_sel) {
+    case 0: rlo = __builtin_amdgcn_update_dpp(0, lo, 0x111, 0xf, 0xf, false);
+            rhi = __builtin_amdgcn_update_dpp(0, hi, 0x111, 0xf, 0xf, false); break;
+    case 1: rlo = __builtin_amdgcn_update_dpp(0, lo, 0x112, 0xf, 0xf, false);
+            rhi = __builtin_amdgcn_update_dpp(0, hi, 0x112, 0xf, 0xf, false); break;
+    case 2: rlo = __builtin_amdgcn_update_dpp(0, lo, 0x114, 0xf, 0xf, false);
+            rhi = __builtin_amdgcn_update_dpp(0, hi, 0x114, 0xf, 0xf, false); break;
+    case 3: rlo = __builtin_amdgcn_update_dpp(0, lo, 0x118, 0xf, 0xf, false);
+            rhi = __builtin_amdgcn_update_dpp(0, hi, 0x118, 0xf, 0xf, false); break;
+    case 4: rlo = __builtin_amdgcn_update_dpp(0, lo, 0x142, 0xa, 0xf, false);
+            rhi = __builtin_amdgcn_update_dpp(0, hi, 0x142, 0xa, 0xf, false); break;
+    default: rlo = __builtin_amdgcn_update_dpp(0, lo, 0x143, 0xc, 0xf, false);
+             rhi = __builtin_amdgcn_update_dpp(0, hi, 0x143, 0xc, 0xf, false); break;
     }
+    return v + __hiloint2double(rhi, rlo);
+}
+
+__device__ __forceinline__ double wave_sum_dpp(double v)
+{
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v = dpp_add(v, k);
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
+}
+
+/* v[c][k] = V_{c0+c}[t + k GSF_T] for the chunk's columns below ncol (0 elsewhere) */
+template <int C, int E>
+__device__ __forceinline__ void gsr_load(const double *__restrict__ V, int64_t ld, int64_t N, int c0, int ncol,
+                                         double (&v)[C][E])
+{
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            const int64_t i = t + (int64_t)k * GSF_T;
+            v[c][k] = (c0 + c < ncol && i < N) ? V[(int64_t)(c0 + c) * ld + i] : 0.0;
+        }
+}
+
+/* the chunk's dot products with x: wave sums (wave_sum_dpp) into
+   red[wave][c0 + c] */
+template <int C, int E>
+__device__ __forceinline__ void gsr_dots(const double (&v)[C][E], const double (&x)[E], int c0, int ncol,
+                                         double (*red)[GSF_RMAX])
+{
+    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    double p[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        p[c] = 0.0;
+#pragma unroll
+        for (int k = 0; k < E; ++k) p[c] = fma(v[c][k], x[k], p[c]);
+        p[c] = wave_sum_dpp(p[c]);
+    }
+    if (ln == 0)
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            if (c0 + c < ncol) red[wv][c0 + c] = p[c];
+}
+
+/* hp[c] = sum over the waves of red[.][c], in wave order (after a barrier) */
+__device__ __forceinline__ void gsr_collect(double (*red)[GSF_RMAX], int ncol, double *hp)
+{
     __syncthreads();
-    for (int c = t; c < ncol; c += GSF_T) {
+    for (int c = threadIdx.x; c < ncol; c += GSF_T) {
         double sacc = red[0][c];
         for (int q = 1; q < GSF_W; ++q) sacc += red[q][c];
-        hs[c] = sacc;
+        hp[c] = sacc;
     }
     __syncthreads();
 }
 
-__global__ __launch_bounds__(GSF_T) void gs_fused_kernel(GState *__restrict__ gs, double *__restrict__ V, int64_t ld,
-                                                         double *__restrict__ w, int64_t N, double *__restrict__ H,
-                                                         int R, double *__restrict__ cs, double *__restrict__ sn,
-                                                         double *__restrict__ gv)
+template <int C, int E>
+__device__ __forceinline__ void gsr_sub(const double (&v)[C][E], double (&x)[E], int c0, int ncol, const double *hp)
 {
-    __shared__ double red[GSF_W][GSF_RMAX];
-    __shared__ double hs[2][GSF_RMAX];
-    __shared__ double nrm[GSF_W], hnl[1];
-    __shared__ double col[GSF_RMAX + 2], rot[2 * GSF_RMAX];
-    if (gs->done) return; /* the whole block */
-    const int t = threadIdx.x;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        if (c0 + c >= ncol) break;
+        const double h = hp[c0 + c];
+#pragma unroll
+        for (int k = 0; k < E; ++k) x[k] = fma(-h, v[c][k], x[k]);
+    }
+}
+
+/* LDS of the one-block Gram-Schmidt */
+struct GsrShared {
+    double red[GSF_W][GSF_RMAX];
+    double hs[2][GSF_RMAX];
+    double nrm[GSF_W], hnl[1];
+    double col[GSF_RMAX + 2], rot[2 * GSF_RMAX];
+};
+
+/* The one-block CGS2 step on w (length N), by every thread of a GSF_T block. */
+template <int E>
+__device__ __forceinline__ void gsr_body(GState *__restrict__ gs, double *__restrict__ V, int64_t ld,
+                                         const double *__restrict__ w, int64_t N, double *__restrict__ H, int R,
+                                         double *__restrict__ cs, double *__restrict__ sn, double *__restrict__ gv,
+                                         GsrShared &sh)
+{
+    constexpr int C = 32 / E;
+    const int t = threadIdx.x, wv = t >> 6, ln = t & 63;
     const int j = gs->j, ncol = j + 1;
-    /* each thread owns the elements t, t + GSF_T, ... of w and of the new column */
-    for (int pass = 0; pass < 2; ++pass) {
-        double *hp = hs[pass];
-        gsf_dots(V, ld, w, N, ncol, red, hp);
-        for (int64_t i = t; i < N; i += GSF_T) {
-            double v = w[i];
-            for (int c = 0; c < ncol; ++c) v = fma(-hp[c], V[(int64_t)c * ld + i], v);
-            w[i] = v;
+    double x[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        const int64_t i = t + (int64_t)k * GSF_T;
+        x[k] = i < N ? w[i] : 0.0;
+    }
+    if (ncol <= C) {
+        double v[C][E];
+        gsr_load<C, E>(V, ld, N, 0, ncol, v);
+        for (int pass = 0; pass < 2; ++pass) {
+            gsr_dots<C, E>(v, x, 0, ncol, sh.red);
+            gsr_collect(sh.red, ncol, sh.hs[pass]);
+            gsr_sub<C, E>(v, x, 0, ncol, sh.hs[pass]);
+        }
+    } else {
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int c0 = 0; c0 < ncol; c0 += C) {
+                double v[C][E];
+                gsr_load<C, E>(V, ld, N, c0, ncol, v);
+                gsr_dots<C, E>(v, x, c0, ncol, sh.red);
+            }
+            gsr_collect(sh.red, ncol, sh.hs[pass]);
+            for (int c0 = 0; c0 < ncol; c0 += C) {
+                double v[C][E];
+                gsr_load<C, E>(V, ld, N, c0, ncol, v);
+                gsr_sub<C, E>(v, x, c0, ncol, sh.hs[pass]);
+            }
         }
     }
     double sacc = 0.0;
-    for (int64_t i = t; i < N; i += GSF_T) sacc = fma(w[i], w[i], sacc);
-    sacc = gsf_wave_sum(sacc);
-    if ((t & 63) == 0) nrm[t >> 6] = sacc;
+#pragma unroll
+    for (int k = 0; k < E; ++k) sacc = fma(x[k], x[k], sacc);
+    sacc = wave_sum_dpp(sacc);
+    if (ln == 0) sh.nrm[wv] = sacc;
     __syncthreads();
     if (t == 0) {
-        double s2 = nrm[0];
-        for (int q = 1; q < GSF_W; ++q) s2 += nrm[q];
-        hnl[0] = s2;
+        double s2 = sh.nrm[0];
+        for (int q = 1; q < GSF_W; ++q) s2 += sh.nrm[q];
+        sh.hnl[0] = s2;
     }
     __syncthreads();
-    gs_finish_block(gs, H, R, cs, sn, gv, hs[0], hs[1], hnl[0], col, rot);
+    gs_finish_block(gs, H, R, cs, sn, gv, sh.hs[0], sh.hs[1], sh.hnl[0], sh.col, sh.rot);
     if (gs->done) return; /* written by thread 0 before the block's last barrier */
     const double inv = gs->inv;
-    for (int64_t i = t; i < N; i += GSF_T) V[(int64_t)(j + 1) * ld + i] = inv * w[i];
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        const int64_t i = t + (int64_t)k * GSF_T;
+        if (i < N) V[(int64_t)(j + 1) * ld + i] = inv * x[k];
+    }
     __syncthreads(); /* every thread has read gs->j and gs->done */
     if (t == 0) gs->j = j + 1;
+}
+
+template <int E>
+__global__ __launch_bounds__(GSF_T) void gs_reg_kernel(GState *__restrict__ gs, double *__restrict__ V, int64_t ld,
+                                                       const double *__restrict__ w, int64_t N,
+                                                       double *__restrict__ H, int R, double *__restrict__ cs,
+                                                       double *__restrict__ sn, double *__restrict__ gv)
+{
+    __shared__ GsrShared sh;
+    if (gs->done) return; /* the whole block */
+    gsr_body<E>(gs, V, ld, w, N, H, R, cs, sn, gv, sh);
 }
 
 /* The Gram-Schmidt part of an Arnoldi step over many blocks (CGS2), for
@@ -3075,15 +3201,11 @@ static void launch_far_t(FarArgs A, const mhlp_plan *P, int nsplit, int32_t prec
         far_finalize<SLP, DLP, 1><<<nblocks(A.M, 256), 256, 0, st>>>(A, nsplit);
 }
 
-static mhlp_status launch_far(const mhlp_plan *P, const double *sigma, const double *mu, double *us, double *ud,
-                              double half_term, int32_t precision, hipStream_t st, const GState *gs = nullptr,
-                              int64_t jstride = 0)
+/* The far-field launch arguments of plan P for the given densities and outputs. */
+static FarArgs far_args(const mhlp_plan *P, const double *sigma, const double *mu, double *us, double *ud,
+                        double half_term, const GState *gs, int64_t jstride)
 {
-    if (precision != MHLP_FP64 && precision != MHLP_MIXED) return fail(MHLP_INVALID_ARG, "unknown precision");
-    if (P->stokes) return fail(MHLP_INVALID_ARG, "a stokes plan evaluates with the mhlp_stokes_* calls");
     const mhlp_geometry *g = P->g;
-    if (half_term != 0.0 && (!P->onsurf || P->M != g->N))
-        return fail(MHLP_INVALID_ARG, "identity term needs an on-surface plan");
     FarArgs A;
     A.sx = g->soa;
     A.sy = g->soa + g->N;
@@ -3122,8 +3244,28 @@ static mhlp_status launch_far(const mhlp_plan *P, const double *sigma, const dou
     A.skpd = P->skpart + (int64_t)P->sk_S * P->M;
     A.wcls = P->wcls;
     A.fq = P->fqd;
+    return A;
+}
+
+/* The symmetric on-surface operator's launches (FP64, scalar plan with
+   symmetric tiles) */
+static SymArgs sym_args(const mhlp_plan *P, const FarArgs &A)
+{
+    return SymArgs{A, P->sym_tiles, P->sym_p1, P->sym_p2, P->sym_bits, P->sym_nw, P->sym_cls};
+}
+
+static mhlp_status launch_far(const mhlp_plan *P, const double *sigma, const double *mu, double *us, double *ud,
+                              double half_term, int32_t precision, hipStream_t st, const GState *gs = nullptr,
+                              int64_t jstride = 0)
+{
+    if (precision != MHLP_FP64 && precision != MHLP_MIXED) return fail(MHLP_INVALID_ARG, "unknown precision");
+    if (P->stokes) return fail(MHLP_INVALID_ARG, "a stokes plan evaluates with the mhlp_stokes_* calls");
+    const mhlp_geometry *g = P->g;
+    if (half_term != 0.0 && (!P->onsurf || P->M != g->N))
+        return fail(MHLP_INVALID_ARG, "identity term needs an on-surface plan");
+    const FarArgs A = far_args(P, sigma, mu, us, ud, half_term, gs, jstride);
     if (P->sym_tiles && !sigma && mu && precision == MHLP_FP64) {
-        SymArgs S{A, P->sym_tiles, P->sym_p1, P->sym_p2, P->sym_bits, P->sym_nw, P->sym_cls};
+        const SymArgs S = sym_args(P, A);
         sym_far_kernel<<<(unsigned)P->sym_ntiles, SYM_R, 0, st>>>(S);
         sym_finalize<<<nblocks(A.M, FZ_TG), FZ_TG * FZ_L, 0, st>>>(S, (int)((g->N + SYM_C - 1) / SYM_C));
         HIPCHECK(hipGetLastError());
@@ -3601,7 +3743,23 @@ static mhlp_status ensure_gdev(mhlp_plan *P, int R)
     return MHLP_OK;
 }
 
-/* One Arnoldi step of the device-driven GMRES, enqueued on st. */
+/* Arnoldi steps of the first captured chunk of a GMRES cycle (later chunks
+   follow the observed convergence rate); measured on the config-2 solves, 4
+   saves a replay at alpha = 50 and 500 against 2 and costs nothing at 5 */
+constexpr int GMRES_FIRST_CHUNK = 4;
+
+/* Waits for the stream by polling it: the chunk reads of GMRES are a few tens
+   of microseconds apart, shorter than a blocking wait takes to wake. */
+static hipError_t spin_sync(hipStream_t st)
+{
+    hipError_t e;
+    while ((e = hipStreamQuery(st)) == hipErrorNotReady) {
+    }
+    return e;
+}
+
+/* One Arnoldi step of the device-driven GMRES, enqueued on st (one_block: the
+   Gram-Schmidt part in one block, else over element slices). */
 static mhlp_status enqueue_step(mhlp_plan *P, int32_t prec, bool one_block, hipStream_t st)
 {
     const int64_t N = vlen(P);
@@ -3610,7 +3768,14 @@ static mhlp_status enqueue_step(mhlp_plan *P, int32_t prec, bool one_block, hipS
     const GmresDev d = gdev_view(P);
     TRY(apply_op(P, V, w, prec, st, d.gs, N));
     if (one_block) {
-        gs_fused_kernel<<<1, GSF_T, 0, st>>>(d.gs, V, N, w, N, d.H, R, d.cs, d.sn, d.gv);
+        if (N <= GSF_T)
+            gs_reg_kernel<1><<<1, GSF_T, 0, st>>>(d.gs, V, N, w, N, d.H, R, d.cs, d.sn, d.gv);
+        else if (N <= 2 * GSF_T)
+            gs_reg_kernel<2><<<1, GSF_T, 0, st>>>(d.gs, V, N, w, N, d.H, R, d.cs, d.sn, d.gv);
+        else if (N <= 4 * GSF_T)
+            gs_reg_kernel<4><<<1, GSF_T, 0, st>>>(d.gs, V, N, w, N, d.H, R, d.cs, d.sn, d.gv);
+        else
+            gs_reg_kernel<8><<<1, GSF_T, 0, st>>>(d.gs, V, N, w, N, d.H, R, d.cs, d.sn, d.gv);
         HIPCHECK(hipGetLastError());
         return MHLP_OK;
     }
@@ -3625,12 +3790,13 @@ static mhlp_status enqueue_step(mhlp_plan *P, int32_t prec, bool one_block, hipS
     return MHLP_OK;
 }
 
-/* Executable graph of S consecutive Arnoldi steps (S = 1, 2, 4, 8), captured
-   once per plan state (workspace, split and restart) on a private stream. */
-static mhlp_status step_graph(mhlp_plan *P, int32_t prec, bool one_block, int si, hipGraphExec_t *out)
+/* Executable graph of S consecutive Arnoldi steps (S = 1, 2, 4, 8), the first
+   m of them with the one-block Gram-Schmidt, captured once per plan state
+   (workspace, split and restart) on a private stream. */
+static mhlp_status step_graph(mhlp_plan *P, int32_t prec, int m, int si, hipGraphExec_t *out)
 {
     const int S = 1 << si;
-    mhlp_plan::StepGraph &G = P->graphs[prec == MHLP_MIXED ? 1 : 0][one_block ? 0 : 1][si];
+    mhlp_plan::StepGraph &G = P->graphs[prec == MHLP_MIXED ? 1 : 0][m][si];
     if (G.exec && G.ws == P->ws && G.part == P->part && G.gdev == P->gdev && G.R == P->gdev_R &&
         G.nsplit == P->nsplit && G.S == S) {
         *out = G.exec;
@@ -3643,7 +3809,7 @@ static mhlp_status step_graph(mhlp_plan *P, int32_t prec, bool one_block, int si
     if (!P->cap_stream) HIPCHECK(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
     HIPCHECK(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
     mhlp_status s = MHLP_OK;
-    for (int k = 0; k < S && s == MHLP_OK; ++k) s = enqueue_step(P, prec, one_block, P->cap_stream);
+    for (int k = 0; k < S && s == MHLP_OK; ++k) s = enqueue_step(P, prec, k < m, P->cap_stream);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(P->cap_stream, &graph);
     if (s != MHLP_OK) {
@@ -3720,18 +3886,21 @@ static mhlp_status gmres_core(mhlp_plan *P, const double *b, double bnorm, doubl
             gs_init_kernel<<<1, 256, 0, st>>>(d.gs, d.gv, R, kmax, beta, 0.5 * tol * bnorm);
         }
         HIPCHECK(hipGetLastError());
-        int done_steps = 0, chunk = 2;
+        int done_steps = 0, chunk = GMRES_FIRST_CHUNK;
         double last_est = beta, thresh = 0.5 * tol * bnorm;
         for (;;) {
             int si = 0;
             while ((1 << si) < chunk && si < 3) ++si;
-            /* Gram-Schmidt in one block while the chunk stays within its first steps */
-            const bool one_block = N <= GSF_NMAX && R <= GSF_RMAX && done_steps + (1 << si) <= GSF_STEPS;
+            /* Gram-Schmidt in one block for the steps whose basis columns fit
+               its registers (step j has j + 1), over slices after them */
+            const int m = (N <= GSR_NMAX && R <= GSF_RMAX)
+                              ? std::max(0, std::min(1 << si, gsr_cols(N) - done_steps))
+                              : 0;
             hipGraphExec_t ex;
-            TRY(step_graph(P, prec, one_block, si, &ex));
+            TRY(step_graph(P, prec, m, si, &ex));
             HIPCHECK(hipGraphLaunch(ex, st));
             HIPCHECK(hipMemcpyAsync(P->gstate_host, d.gs, sizeof(GState), hipMemcpyDeviceToHost, st));
-            HIPCHECK(hipStreamSynchronize(st));
+            HIPCHECK(spin_sync(st));
             const GState gsh = *P->gstate_host;
             if (first_dev && done_steps == 0) {
                 bnorm = gsh.bnorm;
