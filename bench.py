@@ -668,8 +668,9 @@ def bench_volume(mhlp, wl, t, torch):
 def bench_warm(mhlp, wl, t, torch):
     """Multiply connected time series (outer circle + 3 starfish holes, 14,336 nodes,
     alpha 30, 200 steps): train the learned initial guess on the densities of steps
-    1-100, then solve steps 101-200 to 1e-10 from four initial guesses (zero, the
-    previous density, cubic extrapolation of the last four, learned)."""
+    1-100, then solve steps 101-200 to 1e-10 from five initial guesses (zero, the
+    previous density, cubic extrapolation of the last four, the fitted recurrence
+    alone, and the recurrence with the trained network)."""
     print("# warm-start leg", file=sys.stderr, flush=True)
     cfg = wl.config5()
     geom = cfg["geom"]
@@ -682,12 +683,19 @@ def bench_warm(mhlp, wl, t, torch):
         mu, _ = mhlp.gmres_solve(plan, g[s], x0=x0, **kw)
         mus.append(mu)
         x0 = mu
-    W = mhlp.WarmStart(t(geom.theta), t(geom.theta_w), geom.curve_node_ptr, n_modes=128, n_hist=4, base_order=3,
-                       width=256, seed=5)
+    # the model: per-coefficient recurrence fitted to the training densities
+    # (base) and the network trained on what the recurrence leaves
+    W = mhlp.WarmStart(t(geom.theta), t(geom.theta_w), geom.curve_node_ptr, n_modes=128, n_hist=4,
+                       base_order=mhlp.WARM_RECURRENCE, width=256, seed=5)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     losses = W.train(torch.stack(mus).contiguous(), iters=2000, lr=1e-3)
     train_ms = (time.perf_counter() - t0) * 1e3
+    # the same recurrence with a zero network: what the network itself adds
+    R = mhlp.WarmStart(t(geom.theta), t(geom.theta_w), geom.curve_node_ptr, n_modes=128, n_hist=4,
+                       base_order=mhlp.WARM_RECURRENCE, width=256, seed=5)
+    R.train(torch.stack(mus).contiguous(), iters=0)
+    R.mlp.set_params(torch.zeros(R.mlp.n_params, dtype=torch.float32, device=mus[0].device))
     hist = torch.stack(mus[-4:]).contiguous()
 
     def guess(kind):
@@ -697,9 +705,11 @@ def bench_warm(mhlp, wl, t, torch):
             return hist[-1]
         if kind == "cubic":
             return 4 * hist[-1] - 6 * hist[-2] + 4 * hist[-3] - hist[-4]
+        if kind == "recurrence":
+            return R.predict(hist)
         return W.predict(hist)
 
-    kinds = ("zero", "previous", "cubic", "learned")
+    kinds = ("zero", "previous", "cubic", "recurrence", "learned")
     rec = {k: dict(iters=[], ms=[], res=[], x0res=[], used=[]) for k in kinds}
     pred_ms = []
     for s in range(100, 200):

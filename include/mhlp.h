@@ -465,16 +465,28 @@ mhlp_status mhlp_gemm_bf16(int32_t m, int32_t n, int32_t k, const float *A, int6
    the last n_hist densities (newest last) the network input is, for
    h = 0..n_hist-1, the h-th backward difference of the newest coefficients,
    each group scaled to unit RMS over the training samples.  The network
-   predicts the error of the order-p polynomial extrapolation of the history,
-   sum_{i<=p} (-1)^i C(p+1, i+1) c_{s-i}  (p = base_order; 0 = the last
-   density, 1 = linear, 2 = quadratic, 3 = cubic), in units of its RMS over
-   the training samples; the initial guess is the same extrapolation of the
-   densities plus the synthesis of the predicted correction.
+   predicts the error of a base prediction of the next coefficients, in units
+   of its RMS over the training samples:
+   * base_order = p >= 0: the order-p polynomial extrapolation of the history,
+     sum_{i<=p} (-1)^i C(p+1, i+1) c_{s-i} (0 = the last density, 1 = linear,
+     2 = quadratic, 3 = cubic); the initial guess is the same extrapolation of
+     the densities plus the synthesis of the predicted correction;
+   * base_order = -1 (MHLP_WARM_RECURRENCE): a linear recurrence of order
+     n_hist for each complex coefficient, c_k(s) = sum_i a_{k,i} c_k(s-1-i),
+     fitted by mhlp_warm_train (least squares over the training windows with a
+     relative Tikhonov term of 1e-14, complex normal equations solved by
+     Cholesky); the initial guess is the cubic extrapolation of the densities
+     (quadratic or lower when n_hist < 4) plus the synthesis of (recurrence -
+     cubic extrapolation) of the coefficients plus the predicted correction.
+     A coefficient that rotates, c_k(s) = b e^{i w s} (a drifting mode on a
+     curve the operator maps to itself), or sums up to n_hist such terms,
+     satisfies such a recurrence exactly.
    theta, omega: device [N] float64, curve parameter and theta-quadrature
    weight of each node (copied); curve_ptr: host [n_curves+1], node ranges of
    the curves (0 = curve_ptr[0] < ... < curve_ptr[n_curves] = N).
-   1 <= n_hist <= 8, 0 <= base_order <= min(3, n_hist - 1).  The network is
-   n_hist*F -> width -> width -> F.  Synchronises the stream. */
+   1 <= n_hist <= 8, base_order = -1 or 0 <= base_order <= min(3, n_hist - 1).
+   The network is n_hist*F -> width -> width -> F.  Synchronises the stream. */
+#define MHLP_WARM_RECURRENCE (-1)
 typedef struct mhlp_warm mhlp_warm;
 mhlp_status mhlp_warm_create(const double *theta, const double *omega, const int64_t *curve_ptr, int32_t n_curves,
                              int32_t n_modes, int32_t n_hist, int32_t base_order, int32_t width, uint64_t seed,

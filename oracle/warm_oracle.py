@@ -12,8 +12,9 @@ the benchmark.
   be rounded to BF16 (round to nearest even) before use, as the matrix cores
   see them; everything else is FP64.
 * The warm-start data: network inputs are the backward differences of a
-  window of coefficient rows, targets the error of polynomial extrapolation
-  of the window one step ahead.
+  window of coefficient rows, targets the error of a base prediction of the
+  next row: polynomial extrapolation of the window, or a per-coefficient
+  linear recurrence fitted by regularised least squares over the series.
 
 Parameter layout (shared convention with the library): for l = 0, 1, 2 the
 weight W_l as a row-major [n_{l+1}][n_l] block followed by the bias b_l.
@@ -167,10 +168,53 @@ def extrapolation_coeffs(p):
     return np.array([(-1) ** i * math.comb(p + 1, i + 1) for i in range(p + 1)], dtype=np.float64)
 
 
-def warm_features(coef, n_hist, order):
+def as_complex(coef):
+    """Rows of real coefficients [..][F] ordered (Re, Im) as complex rows [..][F/2]."""
+    c = np.asarray(coef, dtype=np.float64)
+    return c[..., 0::2] + 1j * c[..., 1::2]
+
+
+def as_real(z):
+    z = np.asarray(z)
+    out = np.empty(z.shape[:-1] + (2 * z.shape[-1],))
+    out[..., 0::2] = z.real
+    out[..., 1::2] = z.imag
+    return out
+
+
+REC_LAMBDA = 1e-14
+
+
+def recurrence_fit(coef, n_hist):
+    """Per complex coefficient k, the order-n_hist linear recurrence
+    c_k(s) = sum_i a_i c_k(s-1-i) that minimises, over the windows j of the
+    series, sum_j |c_k(j+H) - sum_i a_i c_k(j+H-1-i)|^2 + lam |a|^2 with
+    lam = 1e-14 tr(G)/H (plus the smallest normal number), G = sum_j conj(h_j) h_j^T:
+    the solution of the regularised normal equations.  Returns a [F/2][H] complex."""
+    z = as_complex(coef)
+    S = z.shape[0] - n_hist
+    out = np.zeros((z.shape[1], n_hist), dtype=complex)
+    for k in range(z.shape[1]):
+        Hm = np.array([[z[j + n_hist - 1 - i, k] for i in range(n_hist)] for j in range(S)])
+        y = z[n_hist:n_hist + S, k]
+        G = Hm.conj().T @ Hm
+        lam = REC_LAMBDA * np.trace(G).real / n_hist + np.finfo(float).tiny
+        out[k] = np.linalg.solve(G + lam * np.eye(n_hist), Hm.conj().T @ y)
+    return out
+
+
+def recurrence_predict(window, rec):
+    """Next coefficients [F] (real layout) of a window [H][F] (newest last)."""
+    z = as_complex(window)
+    H = z.shape[0]
+    return as_real(sum(rec[:, i] * z[H - 1 - i] for i in range(H)))
+
+
+def warm_features(coef, n_hist, order, rec=None):
     """Network input groups [S][n_hist][F] (backward differences 0..n_hist-1 of
-    the newest row of each window) and targets [S][F] (next row minus the
-    order-p extrapolation of the window)."""
+    the newest row of each window) and targets [S][F] (next row minus the base
+    prediction: the order-p extrapolation of the window, or the recurrence rec
+    when given)."""
     coef = np.asarray(coef, dtype=np.float64)
     S = coef.shape[0] - n_hist
     grp = np.zeros((S, n_hist, coef.shape[1]))
@@ -180,23 +224,26 @@ def warm_features(coef, n_hist, order):
         for h in range(1, n_hist):  # repeated first differences of the window
             cur = cur[1:] - cur[:-1]
             grp[j, h] = cur[-1]
-    b = extrapolation_coeffs(order)
-    tgt = np.stack([coef[j + n_hist] - sum(b[i] * coef[j + n_hist - 1 - i] for i in range(order + 1))
-                    for j in range(S)])
+    if rec is not None:
+        tgt = np.stack([coef[j + n_hist] - recurrence_predict(coef[j:j + n_hist], rec) for j in range(S)])
+    else:
+        b = extrapolation_coeffs(order)
+        tgt = np.stack([coef[j + n_hist] - sum(b[i] * coef[j + n_hist - 1 - i] for i in range(order + 1))
+                        for j in range(S)])
     return grp, tgt
 
 
-def warm_scales(coef, n_hist, order):
+def warm_scales(coef, n_hist, order, rec=None):
     """(1 / RMS of each input group over the samples, RMS of the targets)."""
-    grp, tgt = warm_features(coef, n_hist, order)
+    grp, tgt = warm_features(coef, n_hist, order, rec)
     gx = [math.sqrt(np.mean(grp[:, h] ** 2)) for h in range(n_hist)]
     ry = math.sqrt(np.mean(tgt ** 2))
     return [1.0 / r if r > 0 else 1.0 for r in gx], (ry if ry > 0 else 1.0)
 
 
-def warm_samples(coef, n_hist, order, scales):
+def warm_samples(coef, n_hist, order, scales, rec=None):
     """Network inputs [S][n_hist F] and targets [S][F] of a training series."""
-    grp, tgt = warm_features(coef, n_hist, order)
+    grp, tgt = warm_features(coef, n_hist, order, rec)
     X = (grp * np.asarray(scales[0])[None, :, None]).reshape(grp.shape[0], -1)
     return X, tgt / scales[1]
 

@@ -559,6 +559,8 @@ struct WarmMap {
     int H, p;
     double diff[MAX_HIST][MAX_HIST]; /* diff[h][i] = (-1)^i C(h, i), i <= h */
     double b[4];
+    const double *rec; /* learned recurrence [F/2][H] complex (Re, Im) of each coefficient, or NULL:
+                          the base is then the order-p extrapolation */
 };
 
 static WarmMap make_map(int H, int p)
@@ -566,6 +568,7 @@ static WarmMap make_map(int H, int p)
     WarmMap w{};
     w.H = H;
     w.p = p;
+    w.rec = nullptr;
     double C[MAX_HIST + 1][MAX_HIST + 1] = {};
     for (int n = 0; n <= MAX_HIST; ++n) {
         C[n][0] = 1.0;
@@ -622,6 +625,9 @@ struct mhlp_warm {
     int64_t *cptr = nullptr;
     mhlp_mlp *net = nullptr;
     double *scales = nullptr; /* device [H+1]: input group factors, output unit */
+    bool recurrence = false;  /* base: learned per-coefficient recurrence (else polynomial extrapolation) */
+    double *rec = nullptr;    /* device [F/2][H] complex recurrence coefficients */
+    double *D = nullptr;      /* device [F] correction of one prediction */
     double *coef = nullptr;
     int64_t coef_rows = 0;
     float *X = nullptr, *T = nullptr, *Y = nullptr, *losses = nullptr;
@@ -641,9 +647,124 @@ __device__ __forceinline__ void warm_features(const WarmMap &w, const double *__
     }
     if (with_target) {
         double e = c[(int64_t)w.H * F];
-        for (int i = 0; i <= w.p; ++i) e -= w.b[i] * c[(int64_t)(w.H - 1 - i) * F];
+        if (w.rec) {
+            /* complex coefficient k = f / 2: e = c_next - sum_i a_i c_{next-1-i} (Re or Im part) */
+            const int64_t k = f >> 1;
+            const double *cc = coef + j * F + 2 * k; /* its (Re, Im) in row j */
+            const double *a = w.rec + k * 2 * (int64_t)w.H;
+            for (int i = 0; i < w.H; ++i) {
+                const double cr = cc[(int64_t)(w.H - 1 - i) * F], ci = cc[(int64_t)(w.H - 1 - i) * F + 1];
+                const double ar = a[2 * i], ai = a[2 * i + 1];
+                e -= (f & 1) ? fma(ar, ci, ai * cr) : fma(ar, cr, -ai * ci);
+            }
+        } else {
+            for (int i = 0; i <= w.p; ++i) e -= w.b[i] * c[(int64_t)(w.H - 1 - i) * F];
+        }
         *tgt = e;
     }
+}
+
+/* Least-squares recurrence of each complex coefficient k over the training
+   windows j < S: a = argmin sum_j |c_k(j + H) - sum_i a_i c_k(j + H - 1 - i)|^2
+   + lam |a|^2 with lam = REC_LAMBDA tr(G) / H + the smallest normal number,
+   G = sum_j conj(h_j) h_j^T, h_j = (c_k(j + H - 1 - i))_i; from the normal
+   equations (G + lam I) a = sum_j conj(h_j) c_k(j + H) by a complex Cholesky
+   factorisation, one thread per coefficient (sums in sample order). */
+constexpr double REC_LAMBDA = 1e-14;
+__global__ void warm_rec_fit_kernel(const double *__restrict__ coef, int64_t S, int H, int64_t F,
+                                    double *__restrict__ rec)
+{
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= F / 2) return;
+    double gr[MAX_HIST][MAX_HIST], gi[MAX_HIST][MAX_HIST], rr[MAX_HIST], ri[MAX_HIST];
+    for (int i = 0; i < H; ++i) {
+        rr[i] = ri[i] = 0.0;
+        for (int l = 0; l < H; ++l) gr[i][l] = gi[i][l] = 0.0;
+    }
+    for (int64_t j = 0; j < S; ++j) {
+        const double *c = coef + j * F + 2 * k;
+        double hr[MAX_HIST], hi[MAX_HIST];
+        for (int i = 0; i < H; ++i) {
+            hr[i] = c[(int64_t)(H - 1 - i) * F];
+            hi[i] = c[(int64_t)(H - 1 - i) * F + 1];
+        }
+        const double yr = c[(int64_t)H * F], yi = c[(int64_t)H * F + 1];
+        for (int i = 0; i < H; ++i) {
+            /* conj(h_i) h_l and conj(h_i) y */
+            for (int l = 0; l < H; ++l) {
+                gr[i][l] += fma(hr[i], hr[l], hi[i] * hi[l]);
+                gi[i][l] += fma(hr[i], hi[l], -hi[i] * hr[l]);
+            }
+            rr[i] += fma(hr[i], yr, hi[i] * yi);
+            ri[i] += fma(hr[i], yi, -hi[i] * yr);
+        }
+    }
+    double tr = 0.0;
+    for (int i = 0; i < H; ++i) tr += gr[i][i];
+    const double lam = REC_LAMBDA * tr / H + 2.2250738585072014e-308;
+    for (int i = 0; i < H; ++i) gr[i][i] += lam;
+    /* G = L L^H: L lower triangular, real positive diagonal */
+    for (int i = 0; i < H; ++i) {
+        for (int l = 0; l <= i; ++l) {
+            double sr = gr[i][l], si = gi[i][l];
+            for (int m = 0; m < l; ++m) { /* - L_im conj(L_lm) */
+                sr -= fma(gr[i][m], gr[l][m], gi[i][m] * gi[l][m]);
+                si -= fma(gi[i][m], gr[l][m], -gr[i][m] * gi[l][m]);
+            }
+            if (l == i) {
+                gr[i][i] = sqrt(fmax(sr, lam));
+                gi[i][i] = 0.0;
+            } else {
+                gr[i][l] = sr / gr[l][l];
+                gi[i][l] = si / gr[l][l];
+            }
+        }
+    }
+    /* L z = r, then L^H a = z */
+    for (int i = 0; i < H; ++i) {
+        double sr = rr[i], si = ri[i];
+        for (int m = 0; m < i; ++m) {
+            sr -= fma(gr[i][m], rr[m], -gi[i][m] * ri[m]);
+            si -= fma(gr[i][m], ri[m], gi[i][m] * rr[m]);
+        }
+        rr[i] = sr / gr[i][i];
+        ri[i] = si / gr[i][i];
+    }
+    for (int i = H - 1; i >= 0; --i) {
+        double sr = rr[i], si = ri[i];
+        for (int m = i + 1; m < H; ++m) { /* - conj(L_mi) a_m */
+            sr -= fma(gr[m][i], rr[m], gi[m][i] * ri[m]);
+            si -= fma(gr[m][i], ri[m], -gi[m][i] * rr[m]);
+        }
+        rr[i] = sr / gr[i][i];
+        ri[i] = si / gr[i][i];
+    }
+    for (int i = 0; i < H; ++i) {
+        rec[(k * H + i) * 2] = rr[i];
+        rec[(k * H + i) * 2 + 1] = ri[i];
+    }
+}
+
+/* D[f] = (recurrence prediction - order-p extrapolation of the window)[f]
+   + scale * Y[f]: the correction the synthesis adds to the extrapolated
+   densities (rows of coef: the window, newest last) */
+__global__ void warm_combine_kernel(WarmMap w, const double *__restrict__ coef, int64_t F,
+                                    const float *__restrict__ Y, const double *__restrict__ scale,
+                                    double *__restrict__ D)
+{
+    const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (f >= F) return;
+    const int64_t k = f >> 1;
+    const double *cc = coef + 2 * k;
+    const double *a = w.rec + k * 2 * (int64_t)w.H;
+    double v = 0.0;
+    for (int i = 0; i < w.H; ++i) {
+        const double cr = cc[(int64_t)(w.H - 1 - i) * F], ci = cc[(int64_t)(w.H - 1 - i) * F + 1];
+        const double ar = a[2 * i], ai = a[2 * i + 1];
+        v += (f & 1) ? fma(ar, ci, ai * cr) : fma(ar, cr, -ai * ci);
+    }
+    for (int i = 0; i <= w.p; ++i) v -= w.b[i] * coef[(int64_t)(w.H - 1 - i) * F + f];
+    D[f] = fma(scale[0], (double)Y[f], v);
 }
 
 /* scales[h] = 1 / RMS of input group h, scales[H] = RMS of the target, over
@@ -698,6 +819,8 @@ extern "C" mhlp_status mhlp_warm_destroy(mhlp_warm *W)
     free_dev(W->cid);
     free_dev(W->cptr);
     free_dev(W->scales);
+    free_dev(W->rec);
+    free_dev(W->D);
     free_dev(W->coef);
     free_dev(W->X);
     free_dev(W->T);
@@ -717,8 +840,8 @@ extern "C" mhlp_status mhlp_warm_create(const double *theta, const double *omega
     if (n_curves < 1 || n_modes < 1 || n_hist < 1 || width < 1)
         return mfail(MHLP_INVALID_ARG, "n_curves, n_modes, n_hist and width must be >= 1");
     if (n_hist > MAX_HIST) return mfail(MHLP_INVALID_ARG, "n_hist > 8");
-    if (base_order < 0 || base_order > 3 || base_order >= n_hist)
-        return mfail(MHLP_INVALID_ARG, "base_order must be in [0, min(3, n_hist - 1)]");
+    if (base_order < -1 || base_order > 3 || base_order >= n_hist)
+        return mfail(MHLP_INVALID_ARG, "base_order must be -1 (learned recurrence) or in [0, min(3, n_hist - 1)]");
     if ((int64_t)n_curves * n_modes > 65535) return mfail(MHLP_INVALID_ARG, "n_curves * n_modes > 65535");
     if (curve_ptr[0] != 0) return mfail(MHLP_INVALID_ARG, "curve_ptr[0] must be 0");
     for (int c = 0; c < n_curves; ++c)
@@ -732,8 +855,11 @@ extern "C" mhlp_status mhlp_warm_create(const double *theta, const double *omega
     W->n_curves = n_curves;
     W->K = n_modes;
     W->H = n_hist;
-    W->order = base_order;
-    W->map = make_map(n_hist, base_order);
+    W->recurrence = base_order < 0;
+    /* the densities beyond the modes follow the polynomial extrapolation:
+       with the recurrence base, the cubic one (or the highest the history allows) */
+    W->order = base_order < 0 ? std::min(3, n_hist - 1) : base_order;
+    W->map = make_map(n_hist, W->order);
     W->F = F;
     std::vector<int32_t> cid(n);
     for (int c = 0; c < n_curves; ++c)
@@ -741,7 +867,8 @@ extern "C" mhlp_status mhlp_warm_create(const double *theta, const double *omega
     mhlp_status s;
     if ((s = malloc_dev(&W->theta, n)) || (s = malloc_dev(&W->omega, n)) || (s = malloc_dev(&W->cid, n)) ||
         (s = malloc_dev(&W->cptr, n_curves + 1)) || (s = malloc_dev(&W->scales, n_hist + 1)) ||
-        (s = malloc_dev(&W->Y, F))) {
+        (s = malloc_dev(&W->Y, F)) || (s = malloc_dev(&W->D, F)) ||
+        (W->recurrence && (s = malloc_dev(&W->rec, F * n_hist)))) {
         mhlp_warm_destroy(W);
         return s;
     }
@@ -842,6 +969,10 @@ extern "C" mhlp_status mhlp_warm_train(mhlp_warm *W, const double *mus, int32_t 
         W->loss_cap = lc;
     }
     analysis(W, mus, n_steps, W->coef, st);
+    if (W->recurrence) {
+        warm_rec_fit_kernel<<<nb(W->F / 2, 64), 64, 0, st>>>(W->coef, S, W->H, W->F, W->rec);
+        W->map.rec = W->rec;
+    }
     warm_scales_kernel<<<1, 256, 0, st>>>(W->map, W->coef, S, W->F, W->scales);
     warm_samples_kernel<<<nb(S * W->F, 256), 256, 0, st>>>(W->map, W->coef, S, W->F, W->scales, W->X, W->T);
     MHIP(hipGetLastError());
@@ -868,8 +999,16 @@ extern "C" mhlp_status mhlp_warm_predict(mhlp_warm *W, const double *hist, doubl
     if (mhlp_status s = mhlp_mlp_forward(W->net, W->X, 1, W->Y, stream)) return s;
     dim3 grid(nb(W->n, 256), 1);
     const WarmMap &w = W->map;
-    fourier_synthesis_kernel<float><<<grid, 256, 0, st>>>(W->theta, W->cid, W->n, W->K, W->F, W->Y, W->scales + W->H,
-                                                          hist, 0, W->H - 1, w.p, w.b[0], w.b[1], w.b[2], w.b[3], x0);
+    if (W->recurrence) {
+        warm_combine_kernel<<<nb(W->F, 256), 256, 0, st>>>(w, W->coef, W->F, W->Y, W->scales + W->H, W->D);
+        fourier_synthesis_kernel<double><<<grid, 256, 0, st>>>(W->theta, W->cid, W->n, W->K, W->F, W->D, nullptr,
+                                                               hist, 0, W->H - 1, w.p, w.b[0], w.b[1], w.b[2], w.b[3],
+                                                               x0);
+    } else {
+        fourier_synthesis_kernel<float><<<grid, 256, 0, st>>>(W->theta, W->cid, W->n, W->K, W->F, W->Y,
+                                                              W->scales + W->H, hist, 0, W->H - 1, w.p, w.b[0],
+                                                              w.b[1], w.b[2], w.b[3], x0);
+    }
     MHIP(hipGetLastError());
     return MHLP_OK;
 }

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libmhlp.so")
 
 FP64 = 0
 MIXED = 1
+WARM_RECURRENCE = -1  # warm-start base: learned per-coefficient recurrence
 
 OK = 0
 NOT_CONVERGED = 1

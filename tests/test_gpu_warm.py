@@ -148,6 +148,39 @@ def test_warm_predict_vs_oracle(M, geo5, n_hist, order):
     assert _rel(x0 - base, corr) < 1e-2
 
 
+def test_warm_recurrence_vs_oracle(M, geo5):
+    """Learned recurrence base (base_order = -1): the per-coefficient least-squares
+    recurrence fitted by the library, seen through a prediction with a zero
+    network (x0 = cubic extrapolation + synthesis of recurrence - cubic in the
+    coefficients), and the target scale, against the oracle's fit (FP64)."""
+    geom = geo5
+    W = _warm(M, geom, n_modes=32, n_hist=4, base_order=-1, width=64)
+    rng = np.random.default_rng(41)
+    steps = np.arange(16)
+    th = geom.theta
+    series = np.zeros((16, geom.n_nodes))
+    for m in range(1, 9):  # drifting modes plus a little noise
+        b, w = rng.standard_normal(2), rng.uniform(-0.3, 0.3)
+        series += (b[0] * np.cos(m * th[None, :] + w * steps[:, None]) / m
+                   + b[1] * np.sin(m * th[None, :] - 0.5 * w * steps[:, None]) / m)
+    series += 1e-3 * rng.standard_normal(series.shape)
+    W.train(_t(series, torch.float64), iters=0)
+    W.mlp.set_params(torch.zeros(W.mlp.n_params, dtype=torch.float32, device=DEV))
+    hist = series[-4:]
+    x0 = W.predict(_t(hist, torch.float64)).cpu().numpy()
+    coef_r = wo.fourier_coefficients(geom.theta, geom.theta_w, geom.curve_node_ptr, series, 32)
+    rec = wo.recurrence_fit(coef_r, 4)
+    sx, sy = wo.warm_scales(coef_r, 4, 3, rec)
+    gsx, gsy = W.scales()
+    assert np.max(np.abs(np.array(gsx) / np.array(sx) - 1)) < 1e-12 and abs(gsy / sy - 1) < 1e-6
+    b = wo.extrapolation_coeffs(3)
+    ccub = sum(b[i] * coef_r[-1 - i] for i in range(4))
+    corr = wo.recurrence_predict(coef_r[-4:], rec) - ccub
+    expect = sum(b[i] * hist[-1 - i] for i in range(4)) + wo.fourier_synthesis(geom.theta, geom.curve_node_ptr,
+                                                                                corr[None], 32)[0]
+    assert np.max(np.abs(x0 - expect)) < 1e-9 * np.max(np.abs(expect))
+
+
 def test_warm_requires_training_and_validates(M, geo5):
     W = _warm(M, geo5, n_modes=8, n_hist=2, base_order=1, width=16)
     with pytest.raises(M.MhlpError):
@@ -178,26 +211,38 @@ def series5(M):
 
 
 def test_learned_warm_start_reduces_gmres_iterations(M, series5):
+    """The model trained on the first 100 solved densities (recurrence base and
+    network) against zero, previous-density and cubic-extrapolation guesses on
+    the next 16 steps: every solve reaches 1e-10; the learned guess starts at
+    least 10 times closer (true residual of the guess) than the cubic
+    extrapolation and needs fewer iterations."""
     d = series5
-    W = _warm(M, d["geom"], seed=5)
+    W = _warm(M, d["geom"], seed=5, base_order=-1)
     losses = W.train(d["mus"], iters=2000, lr=1e-3)
-    assert np.isfinite(losses).all() and losses[-1] < 0.05 * losses[0]
+    assert np.isfinite(losses).all() and losses[-1] < 0.5 * losses[0]
     hist = list(d["mus"][-4:])
-    its = {"zero": [], "previous": [], "learned": []}
+    its = {"zero": [], "previous": [], "cubic": [], "learned": []}
+    x0res = {"cubic": [], "learned": []}
     for s in range(100, 116):
         g = d["g"][s]
         mu, iz = M.gmres_solve(d["plan"], g, tol=1e-10, restart=100)
         _, ip = M.gmres_solve(d["plan"], g, x0=hist[-1], tol=1e-10, restart=100)
+        _, ic = M.gmres_solve(d["plan"], g, x0=4 * hist[-1] - 6 * hist[-2] + 4 * hist[-3] - hist[-4], tol=1e-10,
+                              restart=100)
         x0 = W.predict(torch.stack(hist[-4:]).contiguous())
         _, il = M.gmres_solve(d["plan"], g, x0=x0, tol=1e-10, restart=100)
-        for k, inf in (("zero", iz), ("previous", ip), ("learned", il)):
+        for k, inf in (("zero", iz), ("previous", ip), ("cubic", ic), ("learned", il)):
             assert inf["converged"] and inf["rel_residual"] <= 1e-10, (s, k, inf)
             its[k].append(inf["iters"])
         assert il["used_x0"] == 1
+        x0res["cubic"].append(ic["x0_residual"])
+        x0res["learned"].append(il["x0_residual"])
         hist = hist[1:] + [mu]
     mean = {k: float(np.mean(v)) for k, v in its.items()}
-    print("mean GMRES iterations to 1e-10:", mean)
-    assert mean["learned"] < mean["zero"]
+    med = {k: float(np.median(v)) for k, v in x0res.items()}
+    print("mean GMRES iterations to 1e-10:", mean, "median x0 residual:", med)
+    assert mean["learned"] < mean["cubic"] < mean["zero"]
+    assert med["learned"] <= 0.1 * med["cubic"]
 
 
 def test_bad_initial_guess_falls_back_to_zero(M, series5):

@@ -176,3 +176,41 @@ def test_warm_samples_shapes_and_scales():
     assert abs(np.sqrt(np.mean(T ** 2)) - 1.0) < 1e-12
     Xi = wo.warm_input(coef[2:6], (sx, sy))
     assert np.allclose(Xi, X[2:3])
+
+
+def test_recurrence_exact_on_sums_of_rotations():
+    """A coefficient series that is a sum of H rotations b_m e^{i w_m s} obeys a
+    linear recurrence of order H (its characteristic roots are e^{i w_m}); the
+    least-squares fit recovers it and predicts the next value to rounding, for
+    each coefficient separately.  Fewer terms than H are also exact."""
+    rng = np.random.default_rng(5)
+    H, S = 4, 40
+    s = np.arange(S + H + 1)
+    cols = []
+    for n_terms in (1, 2, 3, 4):
+        w = rng.uniform(-1.5, 1.5, n_terms) + np.arange(n_terms) * 0.7  # distinct frequencies
+        b = rng.standard_normal(n_terms) + 1j * rng.standard_normal(n_terms)
+        cols.append((b[None, :] * np.exp(1j * np.outer(s, w))).sum(axis=1))
+    Z = np.stack(cols, axis=1)                       # [steps][4 coefficients]
+    coef = wo.as_real(Z)
+    rec = wo.recurrence_fit(coef[:-1], H)             # fitted on all but the last row
+    pred = wo.recurrence_predict(coef[-1 - H:-1], rec)
+    assert np.max(np.abs(pred - coef[-1])) < 1e-9 * np.max(np.abs(coef))
+    # the exact recurrence of one rotation: a_0 = e^{i w}
+    z1 = 0.7 * np.exp(1j * 0.37 * s)
+    r1 = wo.recurrence_fit(wo.as_real(z1[:, None]), 1)
+    assert abs(r1[0, 0] - np.exp(1j * 0.37)) < 1e-12
+
+
+def test_recurrence_normal_equations_vs_lstsq():
+    """On noisy data the regularised normal equations give the least-squares
+    solution of numpy's lstsq (the Tikhonov term is 1e-14 of the trace)."""
+    rng = np.random.default_rng(6)
+    H = 3
+    coef = rng.standard_normal((30, 6))
+    rec = wo.recurrence_fit(coef, H)
+    Z = wo.as_complex(coef)
+    for k in range(Z.shape[1]):
+        Hm = np.array([[Z[j + H - 1 - i, k] for i in range(H)] for j in range(Z.shape[0] - H)])
+        a = np.linalg.lstsq(Hm, Z[H:, k], rcond=None)[0]
+        assert np.max(np.abs(a - rec[k])) < 1e-10 * np.max(np.abs(a))
