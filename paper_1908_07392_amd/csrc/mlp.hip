@@ -50,16 +50,22 @@ static inline unsigned nb(int64_t n, int t) { return (unsigned)((n + t - 1) / t)
 /* BF16 GEMM on the matrix cores                                              */
 /*   C_z[m][n] = sum_{k in chunk z} A(m,k) B(k,n)                             */
 /*   A(m,k) = A[m*sam + k*sak], B(k,n) = B[k*sbk + n*sbn] (FP32 in memory,    */
-/*   rounded to nearest-even BF16 on load).  One wave per 16x16 output tile;  */
-/*   blockIdx.z splits K into chunks of Kc (a multiple of 16) whose partial    */
-/*   tiles go to C + z*split_stride and are summed by the consumer.           */
-/* v_mfma_f32_16x16x16_bf16 operand layout (lane l of 64):                    */
-/*   A: row l%16, k = 4(l/16)..4(l/16)+3;  B: column l%16, same k;            */
+/*   rounded to nearest-even BF16 as they are staged).  A block of four waves */
+/*   owns a 32x32 output tile (each wave a 16x16 quarter); per step of 32 k   */
+/*   its threads stage the tile's A rows and B columns in LDS as BF16 (each   */
+/*   element read from global memory once per block) and every wave issues    */
+/*   one v_mfma_f32_16x16x32_bf16.  blockIdx.z splits K into chunks of Kc (a  */
+/*   multiple of 32) whose partial tiles go to C + z*split_stride and are     */
+/*   summed by the consumer.                                                  */
+/* v_mfma_f32_16x16x32_bf16 operand layout (lane l of 64):                    */
+/*   A: row l%16, k = 8(l/16)..8(l/16)+7;  B: column l%16, same k;            */
 /*   D: column l%16, rows 4(l/16)..4(l/16)+3.                                 */
 /* AV / BV: the operand is contiguous along k and 16-byte aligned, so the     */
-/* four k values of a lane come in one load.                                  */
+/* four k values a thread stages come in one load.                            */
 /* ------------------------------------------------------------------------ */
 typedef short short4_t __attribute__((ext_vector_type(4)));
+typedef short short8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ short f32_to_bf16(float f)
@@ -87,44 +93,58 @@ __device__ __forceinline__ short4_t load_k4(const float *__restrict__ P, int64_t
     return r;
 }
 
+constexpr int GT = 32;       /* output tile edge and k step */
+constexpr int GT_PAD = 8;    /* LDS row padding (BF16 elements): rows of 80 bytes */
+
 template <bool AV, bool BV>
-__global__ __launch_bounds__(64) void gemm_bf16_kernel(int M, int N, int K, int Kc, const float *__restrict__ A,
-                                                       int64_t sam, int64_t sak, const float *__restrict__ B,
-                                                       int64_t sbk, int64_t sbn, float *__restrict__ C, int64_t ldc,
-                                                       int64_t split_stride)
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, int Kc, const float *__restrict__ A,
+                                                        int64_t sam, int64_t sak, const float *__restrict__ B,
+                                                        int64_t sbk, int64_t sbn, float *__restrict__ C, int64_t ldc,
+                                                        int64_t split_stride)
 {
-    const int tm = blockIdx.y * 16, tn = blockIdx.x * 16;
+    __shared__ __attribute__((aligned(16))) short la[GT][GT + GT_PAD]; /* [m][k] */
+    __shared__ __attribute__((aligned(16))) short lb[GT][GT + GT_PAD]; /* [n][k] */
+    const int tm = blockIdx.y * GT, tn = blockIdx.x * GT;
     const int kbeg = blockIdx.z * Kc, kend = min(K, kbeg + Kc);
-    const int lane = threadIdx.x;
-    const int r = lane & 15, kg = (lane >> 4) * 4;
-    const int am = tm + r, bn_ = tn + r;
-    const bool va = am < M, vb = bn_ < N;
-    const int64_t aoff = (int64_t)am * sam, boff = (int64_t)bn_ * sbn;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int wm = (wv >> 1) * 16, wn = (wv & 1) * 16; /* the wave's quarter of the tile */
+    /* staging: thread t takes row (column) t / 8 of the tile and k = 4 (t % 8) .. + 3 */
+    const int sr = t >> 3, sk4 = (t & 7) * 4;
+    const bool va = tm + sr < M, vb = tn + sr < N;
+    const int64_t aoff = (int64_t)(tm + sr) * sam, boff = (int64_t)(tn + sr) * sbn;
+    const int r = lane & 15, kg = lane >> 4;
     float4_t acc = {0.f, 0.f, 0.f, 0.f};
-    for (int k0 = kbeg; k0 < kend; k0 += 16) {
-        const short4_t a = load_k4<AV>(A, aoff, sak, k0 + kg, kend, va);
-        const short4_t b = load_k4<BV>(B, boff, sbk, k0 + kg, kend, vb);
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    for (int k0 = kbeg; k0 < kend; k0 += GT) {
+        const short4_t a = load_k4<AV>(A, aoff, sak, k0 + sk4, kend, va);
+        const short4_t b = load_k4<BV>(B, boff, sbk, k0 + sk4, kend, vb);
+        __syncthreads(); /* the previous step's operands are read */
+        *reinterpret_cast<short4_t *>(&la[sr][sk4]) = a;
+        *reinterpret_cast<short4_t *>(&lb[sr][sk4]) = b;
+        __syncthreads();
+        const short8_t av = *reinterpret_cast<const short8_t *>(&la[wm + r][8 * kg]);
+        const short8_t bv = *reinterpret_cast<const short8_t *>(&lb[wn + r][8 * kg]);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, av),
+                                                      __builtin_bit_cast(bf16x8_t, bv), acc, 0, 0, 0);
     }
     C += blockIdx.z * split_stride;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const int row = tm + kg + t, col = tn + r;
-        if (row < M && col < N) C[(int64_t)row * ldc + col] = acc[t];
+    for (int q = 0; q < 4; ++q) {
+        const int row = tm + wm + 4 * kg + q, col = tn + wn + r;
+        if (row < M && col < N) C[(int64_t)row * ldc + col] = acc[q];
     }
 }
 
-/* K chunking: enough waves to fill the chip (about 1024), chunks of at least
-   64 and a multiple of 16; at most MAX_SPLITS chunks */
+/* K chunking: enough blocks to fill the chip (about 256 blocks of four
+   waves), chunks of at least 64 and a multiple of GT; at most MAX_SPLITS */
 constexpr int MAX_SPLITS = 32;
 
 static int splitk_chunk(int M, int N, int K)
 {
-    const int64_t tiles = (int64_t)nb(M, 16) * nb(N, 16);
-    int splits = (int)std::min<int64_t>(MAX_SPLITS, std::max<int64_t>(1, (1024 + tiles - 1) / tiles));
+    const int64_t tiles = (int64_t)nb(M, GT) * nb(N, GT);
+    int splits = (int)std::min<int64_t>(MAX_SPLITS, std::max<int64_t>(1, (256 + tiles - 1) / tiles));
     splits = std::max(1, std::min(splits, K / 64));
     int Kc = (int)nb(K, splits);
-    Kc = (Kc + 15) / 16 * 16;
+    Kc = (Kc + GT - 1) / GT * GT;
     return Kc;
 }
 
@@ -137,19 +157,21 @@ static bool kvec(const float *P, int64_t srow, int64_t sk, int K)
 static int gemm_bf16(hipStream_t st, int M, int N, int K, const float *A, int64_t sam, int64_t sak, const float *B,
                      int64_t sbk, int64_t sbn, float *C, int64_t ldc, int64_t split_stride, bool allow_split)
 {
-    const int Kc = allow_split ? splitk_chunk(M, N, K) : (K + 15) / 16 * 16;
+    const int Kc = allow_split ? splitk_chunk(M, N, K) : (K + GT - 1) / GT * GT;
     const int splits = (int)nb(K, Kc);
-    dim3 grid(nb(N, 16), nb(M, 16), (unsigned)splits);
+    dim3 grid(nb(N, GT), nb(M, GT), (unsigned)splits);
     const bool av = kvec(A, sam, sak, K), bv = kvec(B, sbn, sbk, K);
     if (av && bv)
-        gemm_bf16_kernel<true, true><<<grid, 64, 0, st>>>(M, N, K, Kc, A, sam, sak, B, sbk, sbn, C, ldc, split_stride);
+        gemm_bf16_kernel<true, true><<<grid, 256, 0, st>>>(M, N, K, Kc, A, sam, sak, B, sbk, sbn, C, ldc, split_stride);
     else if (av)
-        gemm_bf16_kernel<true, false><<<grid, 64, 0, st>>>(M, N, K, Kc, A, sam, sak, B, sbk, sbn, C, ldc, split_stride);
-    else if (bv)
-        gemm_bf16_kernel<false, true><<<grid, 64, 0, st>>>(M, N, K, Kc, A, sam, sak, B, sbk, sbn, C, ldc, split_stride);
-    else
-        gemm_bf16_kernel<false, false><<<grid, 64, 0, st>>>(M, N, K, Kc, A, sam, sak, B, sbk, sbn, C, ldc,
+        gemm_bf16_kernel<true, false><<<grid, 256, 0, st>>>(M, N, K, Kc, A, sam, sak, B, sbk, sbn, C, ldc,
                                                             split_stride);
+    else if (bv)
+        gemm_bf16_kernel<false, true><<<grid, 256, 0, st>>>(M, N, K, Kc, A, sam, sak, B, sbk, sbn, C, ldc,
+                                                            split_stride);
+    else
+        gemm_bf16_kernel<false, false><<<grid, 256, 0, st>>>(M, N, K, Kc, A, sam, sak, B, sbk, sbn, C, ldc,
+                                                             split_stride);
     return splits;
 }
 
