@@ -494,6 +494,7 @@ def bench_batched(mhlp, wl, t, torch):
     plan_ms = (time.perf_counter() - t0) * 1e3
     B = mhlp.Batch(plans, 4)
     target, _ = B.autotune(reps=3)
+    tile = B.tile()
     rhs = [t(it["rhs"][r]) for it in items for r in range(4)]
     gb = B.pack(rhs)
     B.gmres(gb, tol=1e-10)  # warm-up
@@ -514,6 +515,8 @@ def bench_batched(mhlp, wl, t, torch):
     seq_ms = (time.perf_counter() - t0) * 1e3
     n_nodes = sum(it["geom"].n_nodes for it in items)
     return {"systems": len(infos), "total_nodes": n_nodes, "plan_build_ms": round(plan_ms, 1), "block_target": target,
+            "targets_per_lane": tile["targets_per_lane"], "sources_per_stage": tile["sources_per_stage"],
+            "tile_candidates_ms": {f"{c[1]}x{c[2]}@{c[0]}": round(c[3], 3) for c in tile["candidates"]},
             "batched_ms": round(batched_ms, 2), "sequential_ms": round(seq_ms, 2),
             "speedup_vs_sequential": round(seq_ms / batched_ms, 2),
             "all_converged": all(i["converged"] for i in infos),

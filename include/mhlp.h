@@ -403,11 +403,25 @@ mhlp_status mhlp_batch_info(const mhlp_batch *batch, int64_t *total_len, int32_t
    shared by the right-hand sides of a geometry); FP64.  The launch runs a
    work list of (geometry, 256 targets, source split) items, longest first. */
 mhlp_status mhlp_batch_apply_bie(const mhlp_batch *batch, const double *mu, double *out, void *stream);
-/* Rebuild the work list for a total of 512, 1024, ..., 16384 blocks, time the
-   grouped operator for each (reps launches after a warm-up, HIP events on
-   `stream`) and keep the fewest blocks within 1% of the fastest; best_target
-   and best_ms (host) may be NULL.  Synchronises the stream. */
+/* Autotuner of the grouped operator's launch shape: for every tile shape
+   (1 or 2 targets per lane, i.e. target tiles of 256 or 512 nodes; 128 or
+   256 sources staged in LDS per step) and a total of 512, 1024, ..., 16384
+   blocks, rebuild the work list and time the operator (reps launches after a
+   warm-up, HIP events on `stream`); keep the fewest blocks within 1% of the
+   fastest.  best_target and best_ms (host) may be NULL.  Synchronises the
+   stream. */
 mhlp_status mhlp_batch_autotune(mhlp_batch *batch, int32_t reps, void *stream, int64_t *best_target, double *best_ms);
+/* The batch's launch shape (block target, targets per lane, sources per LDS
+   stage) and the autotuner's candidates: cand [cap][3] rows {block target,
+   targets per lane, sources per stage}, cand_ms [cap] ms per application;
+   n_cand receives the number measured (0 before autotuning).  Host outputs,
+   any may be NULL. */
+mhlp_status mhlp_batch_tile(const mhlp_batch *batch, int64_t *target, int32_t *tpl, int32_t *src, int64_t *cand,
+                            double *cand_ms, int32_t cap, int32_t *n_cand);
+/* Set the launch shape directly: target blocks in total (>= 1), tpl targets per
+   lane (1 or 2), src sources per LDS stage (128 or 256); rebuilds the work
+   list (synchronises the stream).  Errors: MHLP_INVALID_ARG. */
+mhlp_status mhlp_batch_set_tile(mhlp_batch *batch, int64_t target, int32_t tpl, int32_t src, void *stream);
 /* Lockstep restarted GMRES on every system (FP64, CGS2, restart <= 64),
    converged systems frozen (their geometries drop out of the operator
    launches of the cycle); each judged by its own true residual.  infos:

@@ -4723,39 +4723,55 @@ __device__ __forceinline__ bool batch_density(const BState *bs, int64_t jstride,
     return true;
 }
 
-template <int R>
+/* The batched far field of one work item (geometry g, target tile tb, source
+   split): TPL targets per lane (tile of FT_THREADS * TPL targets; lane t takes
+   t, t + FT_THREADS, ...), sources staged in LDS SRC at a time (a multiple of
+   16), R right-hand sides sharing every kernel value; a target skips the
+   panels it lists as near.  Partial sums per (split, right-hand side, node). */
+template <int R, int TPL, int SRC>
 __global__ __launch_bounds__(FT_THREADS) void batch_far_dlp(const BatchGeo *__restrict__ G,
                                                             const BatchWork *__restrict__ W,
                                                             const double *__restrict__ mu, double *__restrict__ part,
                                                             const double *__restrict__ gate, const BState *bs,
                                                             int64_t jstride)
 {
+    static_assert(SRC % 16 == 0 && SRC <= FT_THREADS, "whole panels, one source per thread");
     if (batch_gated_off<R>(gate, W[blockIdx.x].g) || !batch_density(bs, jstride, mu)) return;
-    __shared__ double lx[FT_SRC], ly[FT_SRC];
-    __shared__ double ldx[R][FT_SRC], ldy[R][FT_SRC];
+    __shared__ double lx[SRC], ly[SRC];
+    __shared__ double ldx[R][SRC], ldy[R][SRC];
     const BatchWork wk = W[blockIdx.x];
     const BatchGeo geo = G[wk.g];
-    const int64_t i = (int64_t)wk.tb * FT_THREADS + threadIdx.x;
-    const bool valid = i < geo.N;
-    const double x = valid ? geo.x[i] : 0.0, y = valid ? geo.y[i] : 0.0;
     const int64_t pb = (int64_t)wk.split * geo.pps;
     const int64_t pe = min(geo.Np, pb + geo.pps);
-    int32_t k = 0, kend = 0;
-    if (valid) {
-        k = geo.nptr[i];
-        kend = geo.nptr[i + 1];
-        while (k < kend && geo.npan[k] >= 0 && geo.npan[k] < pb) ++k;
+    int64_t i[TPL];
+    bool valid[TPL];
+    double x[TPL], y[TPL];
+    int32_t k[TPL], kend[TPL], nxt[TPL];
+#pragma unroll
+    for (int q = 0; q < TPL; ++q) {
+        i[q] = (int64_t)wk.tb * (FT_THREADS * TPL) + q * FT_THREADS + threadIdx.x;
+        valid[q] = i[q] < geo.N;
+        x[q] = valid[q] ? geo.x[i[q]] : 0.0;
+        y[q] = valid[q] ? geo.y[i[q]] : 0.0;
+        k[q] = kend[q] = 0;
+        if (valid[q]) {
+            k[q] = geo.nptr[i[q]];
+            kend[q] = geo.nptr[i[q] + 1];
+            while (k[q] < kend[q] && geo.npan[k[q]] >= 0 && geo.npan[k[q]] < pb) ++k[q];
+        }
+        nxt[q] = (k[q] < kend[q]) ? geo.npan[k[q]] : INT_MAX;
     }
-    int32_t nxt = (k < kend) ? geo.npan[k] : INT_MAX;
     const FarConst fc = far_const(geo.alpha);
     const double *mug = mu + geo.voff;
-    double acc[R];
+    double acc[TPL][R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) acc[r] = 0.0;
-    for (int64_t base = 16 * pb; base < 16 * pe; base += FT_SRC) {
+    for (int q = 0; q < TPL; ++q)
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[q][r] = 0.0;
+    for (int64_t base = 16 * pb; base < 16 * pe; base += SRC) {
         __syncthreads();
         const int64_t j = base + threadIdx.x;
-        if (j < 16 * pe) {
+        if (threadIdx.x < SRC && j < 16 * pe) {
             const double wj = geo.w[j];
             lx[threadIdx.x] = geo.x[j];
             ly[threadIdx.x] = geo.y[j];
@@ -4769,31 +4785,46 @@ __global__ __launch_bounds__(FT_THREADS) void batch_far_dlp(const BatchGeo *__re
         }
         __syncthreads();
         const int32_t p0 = (int32_t)(base / 16);
-        const int npl = (pe - p0) < 16 ? (int)(pe - p0) : 16;
+        const int npl = (pe - p0) < SRC / 16 ? (int)(pe - p0) : SRC / 16;
         for (int pl = 0; pl < npl; ++pl) {
-            if (p0 + pl == nxt) {
-                ++k;
-                nxt = (k < kend) ? geo.npan[k] : INT_MAX;
-                continue;
+            bool use[TPL];
+            bool any = false;
+#pragma unroll
+            for (int q = 0; q < TPL; ++q) {
+                use[q] = p0 + pl != nxt[q];
+                if (!use[q]) {
+                    ++k[q];
+                    nxt[q] = (k[q] < kend[q]) ? geo.npan[k[q]] : INT_MAX;
+                }
+                any = any || use[q];
             }
+            if (!any) continue;
 #pragma unroll 1
             for (int s = 0; s < 16; s += 2) {
                 const FarTab T = far_table();
                 const int l0 = pl * 16 + s, l1 = l0 + 1;
-                const double ex0 = x - lx[l0], ey0 = y - ly[l0];
-                const double ex1 = x - lx[l1], ey1 = y - ly[l1];
-                K01 o0, o1;
-                k01_far2<false, true, true, true>(T, fc, fma(ex0, ex0, ey0 * ey0), fma(ex1, ex1, ey1 * ey1), o0, o1);
 #pragma unroll
-                for (int r = 0; r < R; ++r)
-                    acc[r] = fma(o1.ak1r, fma(ex1, ldx[r][l1], ey1 * ldy[r][l1]),
-                                 fma(o0.ak1r, fma(ex0, ldx[r][l0], ey0 * ldy[r][l0]), acc[r]));
+                for (int q = 0; q < TPL; ++q) {
+                    if (!use[q]) continue;
+                    const double ex0 = x[q] - lx[l0], ey0 = y[q] - ly[l0];
+                    const double ex1 = x[q] - lx[l1], ey1 = y[q] - ly[l1];
+                    K01 o0, o1;
+                    k01_far2<false, true, true, true>(T, fc, fma(ex0, ex0, ey0 * ey0), fma(ex1, ex1, ey1 * ey1), o0,
+                                                      o1);
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        acc[q][r] = fma(o1.ak1r, fma(ex1, ldx[r][l1], ey1 * ldy[r][l1]),
+                                        fma(o0.ak1r, fma(ex0, ldx[r][l0], ey0 * ldy[r][l0]), acc[q][r]));
+                }
             }
         }
     }
-    if (!valid) return;
 #pragma unroll
-    for (int r = 0; r < R; ++r) part[geo.poff + ((int64_t)wk.split * R + r) * geo.N + i] = acc[r];
+    for (int q = 0; q < TPL; ++q) {
+        if (!valid[q]) continue;
+#pragma unroll
+        for (int r = 0; r < R; ++r) part[geo.poff + ((int64_t)wk.split * R + r) * geo.N + i[q]] = acc[q][r];
+    }
 }
 
 /* out = (1/2 I + D) mu for every system: split partials + corrections + identity */
@@ -5032,6 +5063,14 @@ struct mhlp_batch {
     int ldh = 0;
     std::vector<BatchGeo> hgeo; /* host copy of the per-geometry descriptors */
     int64_t target = 0;         /* block target of the current work list    */
+    int tpl = 1, src = FT_SRC;  /* tile shape of the far launch: targets per lane, sources per LDS stage */
+    uint64_t version = 0;       /* bumped by every work-list build (keys the captured graphs) */
+    struct TuneRec {
+        int64_t target;
+        int tpl, src;
+        double ms;
+    };
+    std::vector<TuneRec> tune; /* the autotuner's candidates */
     /* device-driven GMRES: state, per-system Hessenberg data, step graphs */
     char *gd = nullptr;         /* BState, H, cs, sn, gv, y, thresh, resest  */
     char *hpin = nullptr;       /* pinned: BState + resest (down), gv + thresh (up) */
@@ -5040,10 +5079,11 @@ struct mhlp_batch {
         hipGraphExec_t exec = nullptr;
         const void *V = nullptr, *work = nullptr, *part = nullptr, *gd = nullptr;
         int m = 0, S = 0;
+        uint64_t version = 0;
     } graphs[4];
 };
 
-static mhlp_status batch_build_work(mhlp_batch *B, int64_t target, hipStream_t st);
+static mhlp_status batch_build_work(mhlp_batch *B, int64_t target, int tpl, int src, hipStream_t st);
 
 extern "C" mhlp_status mhlp_batch_destroy(mhlp_batch *B)
 {
@@ -5114,7 +5154,7 @@ extern "C" mhlp_status mhlp_batch_create(int32_t n_geom, const mhlp_plan *const 
         mhlp_batch_destroy(B);
         return fail(MHLP_HIP_ERROR, std::string("batch_create: ") + hipGetErrorString(e));
     }
-    if ((s = batch_build_work(B, 2048, st))) {
+    if ((s = batch_build_work(B, 2048, 1, FT_SRC, st))) {
         mhlp_batch_destroy(B);
         return s;
     }
@@ -5126,7 +5166,7 @@ extern "C" mhlp_status mhlp_batch_create(int32_t n_geom, const mhlp_plan *const 
    each geometry gets blocks in proportion to its share of the pair work
    (N_g^2), as source splits of its target blocks (at least 4 panels per
    split); items are ordered by decreasing cost so the longest start first. */
-static mhlp_status batch_build_work(mhlp_batch *B, int64_t target, hipStream_t st)
+static mhlp_status batch_build_work(mhlp_batch *B, int64_t target, int tpl, int src, hipStream_t st)
 {
     const int n_geom = B->n_geom, n_rhs = B->R;
     double tot_work = 0;
@@ -5135,21 +5175,21 @@ static mhlp_status batch_build_work(mhlp_batch *B, int64_t target, hipStream_t s
     int64_t poff = 0;
     for (int g = 0; g < n_geom; ++g) {
         BatchGeo &b = B->hgeo[g];
-        const int64_t tb = (b.N + FT_THREADS - 1) / FT_THREADS;
+        const int64_t tb = (b.N + FT_THREADS - 1) / FT_THREADS;            /* finalize tiles */
+        const int64_t tbf = (b.N + FT_THREADS * tpl - 1) / (FT_THREADS * tpl); /* far tiles */
         const int64_t want = (int64_t)std::ceil((double)target * (double)b.N * b.N / tot_work);
-        int64_t ns = (want + tb - 1) / tb;
+        int64_t ns = (want + tbf - 1) / tbf;
         if (ns > b.Np / 4) ns = b.Np / 4;
         if (ns < 1) ns = 1;
         b.pps = (int32_t)((b.Np + ns - 1) / ns);
         b.nsplit = (int32_t)((b.Np + b.pps - 1) / b.pps);
         b.poff = poff;
         poff += (int64_t)b.nsplit * n_rhs * b.N;
-        for (int64_t t = 0; t < tb; ++t) {
+        for (int64_t t = 0; t < tbf; ++t)
             for (int sp = 0; sp < b.nsplit; ++sp) hw.push_back(BatchWork{g, (int32_t)t, sp, 0});
-            hf.push_back(BatchWork{g, (int32_t)t, 0, 0});
-        }
+        for (int64_t t = 0; t < tb; ++t) hf.push_back(BatchWork{g, (int32_t)t, 0, 0});
     }
-    /* cost of an item ~ panels it sums over (all items have 256 targets) */
+    /* cost of an item ~ panels it sums over (all items have the same target tile) */
     std::stable_sort(hw.begin(), hw.end(), [&](const BatchWork &a, const BatchWork &c) {
         return B->hgeo[a.g].pps > B->hgeo[c.g].pps;
     });
@@ -5162,6 +5202,9 @@ static mhlp_status batch_build_work(mhlp_batch *B, int64_t target, hipStream_t s
     B->nwork = (int64_t)hw.size();
     B->nfin = (int64_t)hf.size();
     B->target = target;
+    B->tpl = tpl;
+    B->src = src;
+    ++B->version;
     TRY(dalloc(&B->dwork, B->nwork));
     TRY(dalloc(&B->dfin, B->nfin));
     TRY(dalloc(&B->part, poff));
@@ -5190,7 +5233,15 @@ template <int R>
 static void batch_apply_t(const mhlp_batch *B, const double *mu, double *out, const double *gate,
                           const BState *bs, int64_t jstride, hipStream_t st)
 {
-    batch_far_dlp<R><<<(unsigned)B->nwork, FT_THREADS, 0, st>>>(B->dgeo, B->dwork, mu, B->part, gate, bs, jstride);
+    const unsigned nw = (unsigned)B->nwork;
+    if (B->tpl == 2 && B->src == 128)
+        batch_far_dlp<R, 2, 128><<<nw, FT_THREADS, 0, st>>>(B->dgeo, B->dwork, mu, B->part, gate, bs, jstride);
+    else if (B->tpl == 2)
+        batch_far_dlp<R, 2, FT_SRC><<<nw, FT_THREADS, 0, st>>>(B->dgeo, B->dwork, mu, B->part, gate, bs, jstride);
+    else if (B->src == 128)
+        batch_far_dlp<R, 1, 128><<<nw, FT_THREADS, 0, st>>>(B->dgeo, B->dwork, mu, B->part, gate, bs, jstride);
+    else
+        batch_far_dlp<R, 1, FT_SRC><<<nw, FT_THREADS, 0, st>>>(B->dgeo, B->dwork, mu, B->part, gate, bs, jstride);
     batch_finalize<R><<<(unsigned)B->nfin, FT_THREADS, 0, st>>>(B->dgeo, B->dfin, B->part, mu, out, gate, bs,
                                                                   jstride);
 }
@@ -5231,20 +5282,28 @@ extern "C" mhlp_status mhlp_batch_autotune(mhlp_batch *B, int32_t reps, void *st
     if (s == MHLP_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
         s = fail(MHLP_HIP_ERROR, "hipEventCreate");
     if (s == MHLP_OK) fill_kernel<<<nblocks(B->total, 256), 256, 0, st>>>(mu, 1.0, B->total);
-    std::vector<std::pair<int64_t, double>> tim;
-    for (int64_t tg : {512LL, 1024LL, 2048LL, 4096LL, 8192LL, 16384LL}) {
-        if (s) break;
-        if ((s = batch_build_work(B, tg, st))) break;
-        if ((s = batch_apply_impl(B, mu, out, st))) break;
-        float ms = 0.f;
-        hipError_t e = hipEventRecord(e0, st);
-        for (int r = 0; r < reps && e == hipSuccess && s == MHLP_OK; ++r) s = batch_apply_impl(B, mu, out, st);
-        if (e == hipSuccess) e = hipEventRecord(e1, st);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e != hipSuccess && s == MHLP_OK) s = fail(MHLP_HIP_ERROR, std::string("batch autotune: ") + hipGetErrorString(e));
-        if (s == MHLP_OK) tim.emplace_back(tg, (double)ms / reps);
-    }
+    struct Cand {
+        int64_t target;
+        int tpl, src;
+        double ms;
+    };
+    std::vector<Cand> tim;
+    for (int tpl : {1, 2})
+        for (int src : {128, FT_SRC})
+            for (int64_t tg : {512LL, 1024LL, 2048LL, 4096LL, 8192LL, 16384LL}) {
+                if (s) break;
+                if ((s = batch_build_work(B, tg, tpl, src, st))) break;
+                if ((s = batch_apply_impl(B, mu, out, st))) break;
+                float ms = 0.f;
+                hipError_t e = hipEventRecord(e0, st);
+                for (int r = 0; r < reps && e == hipSuccess && s == MHLP_OK; ++r) s = batch_apply_impl(B, mu, out, st);
+                if (e == hipSuccess) e = hipEventRecord(e1, st);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e != hipSuccess && s == MHLP_OK)
+                    s = fail(MHLP_HIP_ERROR, std::string("batch autotune: ") + hipGetErrorString(e));
+                if (s == MHLP_OK) tim.push_back(Cand{tg, tpl, src, (double)ms / reps});
+            }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     (void)hipStreamSynchronize(st);
@@ -5252,14 +5311,50 @@ extern "C" mhlp_status mhlp_batch_autotune(mhlp_batch *B, int32_t reps, void *st
     if (out) (void)hipFree(out);
     if (s) return s;
     double bms = 1e300;
-    for (const auto &t : tim) bms = std::min(bms, t.second);
-    int64_t best = 0;
-    double bt = 0.0;
-    for (const auto &t : tim) /* fewest blocks within 1% of the fastest */
-        if (t.second <= 1.01 * bms && (best == 0 || t.first < best)) best = t.first, bt = t.second;
-    TRY(batch_build_work(B, best, st));
-    if (best_target) *best_target = best;
-    if (best_ms) *best_ms = bt;
+    for (const auto &t : tim) bms = std::min(bms, t.ms);
+    /* fewest blocks within 1% of the fastest (the first such in the search
+       order: one target per lane and the larger stage first) */
+    const Cand *best = nullptr;
+    for (const auto &t : tim)
+        if (t.ms <= 1.01 * bms && (!best || t.target < best->target)) best = &t;
+    B->tune.clear();
+    for (const auto &t : tim) B->tune.push_back(mhlp_batch::TuneRec{t.target, t.tpl, t.src, t.ms});
+    TRY(batch_build_work(B, best->target, best->tpl, best->src, st));
+    if (best_target) *best_target = best->target;
+    if (best_ms) *best_ms = best->ms;
+    return MHLP_OK;
+}
+
+extern "C" mhlp_status mhlp_batch_set_tile(mhlp_batch *B, int64_t target, int32_t tpl, int32_t src, void *stream)
+{
+    if (!B) return fail(MHLP_INVALID_ARG, "batch is NULL");
+    if (target < 1 || target > (1LL << 24)) return fail(MHLP_INVALID_ARG, "block target must be in [1, 2^24]");
+    if (tpl != 1 && tpl != 2) return fail(MHLP_INVALID_ARG, "targets per lane must be 1 or 2");
+    if (src != 128 && src != FT_SRC) return fail(MHLP_INVALID_ARG, "sources per stage must be 128 or 256");
+    return batch_build_work(B, target, tpl, src, (hipStream_t)stream);
+}
+
+/* The tile shape chosen for a batch (targets per lane, sources per LDS stage)
+   and the autotuner's measured candidates (host outputs, may be NULL; up to
+   cap rows of {block target, targets per lane, sources per stage} and their
+   ms per operator application). */
+extern "C" mhlp_status mhlp_batch_tile(const mhlp_batch *B, int64_t *target, int32_t *tpl, int32_t *src,
+                                       int64_t *cand, double *cand_ms, int32_t cap, int32_t *n_cand)
+{
+    if (!B) return fail(MHLP_INVALID_ARG, "batch is NULL");
+    if (target) *target = B->target;
+    if (tpl) *tpl = B->tpl;
+    if (src) *src = B->src;
+    const int32_t n = (int32_t)B->tune.size();
+    if (n_cand) *n_cand = n;
+    for (int32_t c = 0; c < n && c < cap; ++c) {
+        if (cand) {
+            cand[3 * c] = B->tune[c].target;
+            cand[3 * c + 1] = B->tune[c].tpl;
+            cand[3 * c + 2] = B->tune[c].src;
+        }
+        if (cand_ms) cand_ms[c] = B->tune[c].ms;
+    }
     return MHLP_OK;
 }
 
@@ -5321,7 +5416,7 @@ static mhlp_status bstep_graph(mhlp_batch *B, int si, hipGraphExec_t *out)
     const int S = 1 << si;
     mhlp_batch::StepGraph &G = B->graphs[si];
     if (G.exec && G.V == B->V && G.work == B->dwork && G.part == B->part && G.gd == B->gd && G.m == B->m &&
-        G.S == S) {
+        G.S == S && G.version == B->version) {
         *out = G.exec;
         return MHLP_OK;
     }
@@ -5352,6 +5447,7 @@ static mhlp_status bstep_graph(mhlp_batch *B, int si, hipGraphExec_t *out)
     G.gd = B->gd;
     G.m = B->m;
     G.S = S;
+    G.version = B->version;
     *out = G.exec;
     return MHLP_OK;
 }

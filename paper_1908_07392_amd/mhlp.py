@@ -105,6 +105,10 @@ _SIGS = {
                          ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int32),
     "mhlp_batch_apply_bie": ([_V, _V, _V, _V], ctypes.c_int32),
     "mhlp_batch_autotune": ([_V, ctypes.c_int32, _V, ctypes.POINTER(ctypes.c_int64), _c_double_p], ctypes.c_int32),
+    "mhlp_batch_set_tile": ([_V, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _V], ctypes.c_int32),
+    "mhlp_batch_tile": ([_V, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
+                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64), _c_double_p, ctypes.c_int32,
+                         ctypes.POINTER(ctypes.c_int32)], ctypes.c_int32),
     "mhlp_batch_gmres_solve": ([_V, _V, _V, ctypes.POINTER(GmresOpts), ctypes.POINTER(GmresInfo), _V],
                                ctypes.c_int32),
     "mhlp_volume_eval": ([_V, _V, _V, _V, ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_int32, _V,
@@ -567,11 +571,29 @@ class Batch:
         return out
 
     def autotune(self, reps: int = 3):
-        """Pick the block target of the grouped launch; returns (target, ms)."""
+        """Pick the launch shape of the grouped operator (block target, targets
+        per lane, sources per LDS stage); returns (target, ms)."""
         tg, ms = ctypes.c_int64(), ctypes.c_double()
         _check(load().mhlp_batch_autotune(self._h, int(reps), _stream(), ctypes.byref(tg), ctypes.byref(ms)),
                "batch_autotune")
         return tg.value, ms.value
+
+    def set_tile(self, target: int, targets_per_lane: int = 1, sources_per_stage: int = 256):
+        _check(load().mhlp_batch_set_tile(self._h, int(target), int(targets_per_lane), int(sources_per_stage),
+                                          _stream()), "batch_set_tile")
+
+    def tile(self):
+        """{'target', 'targets_per_lane', 'sources_per_stage', 'candidates': [(target, tpl, src, ms), ...]}"""
+        L = load()
+        tg, tpl, src, n = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(L.mhlp_batch_tile(self._h, ctypes.byref(tg), ctypes.byref(tpl), ctypes.byref(src), None, None, 0,
+                                 ctypes.byref(n)), "batch_tile")
+        cand = (ctypes.c_int64 * (3 * max(n.value, 1)))()
+        cms = (ctypes.c_double * max(n.value, 1))()
+        _check(L.mhlp_batch_tile(self._h, None, None, None, cand, cms, n.value, None), "batch_tile")
+        rows = [(cand[3 * c], cand[3 * c + 1], cand[3 * c + 2], cms[c]) for c in range(n.value)]
+        return {"target": tg.value, "targets_per_lane": tpl.value, "sources_per_stage": src.value,
+                "candidates": rows}
 
     def gmres(self, g, x0=None, tol=1e-10, max_iter=500, restart=64):
         mu = torch.zeros(self.total, dtype=torch.float64, device=self.device) if x0 is None else x0.clone()

@@ -305,9 +305,20 @@ def test_batch_apply_matches_single():
             refs.append(ref.cpu().numpy())
             assert _relerr(out[k].cpu().numpy(), refs[-1]) < 1e-12
             k += 1
-    # every work-list shape the autotuner may pick gives the same operator
+    # every launch shape the autotuner may pick gives the same operator: block
+    # targets, 1 or 2 targets per lane, 128 or 256 sources per LDS stage
+    for tpl in (1, 2):
+        for src in (128, 256):
+            for target in (512, 16384):
+                B.set_tile(target, tpl, src)
+                out2 = B.unpack(B.apply(B.pack(vecs)))
+                for k in range(len(vecs)):
+                    assert _relerr(out2[k].cpu().numpy(), refs[k]) < 1e-12, (tpl, src, target, k)
     target, ms = B.autotune(reps=2)
     assert target in (512, 1024, 2048, 4096, 8192, 16384) and ms > 0
+    tile = B.tile()
+    assert len(tile["candidates"]) == 24 and tile["targets_per_lane"] in (1, 2)
+    assert tile["sources_per_stage"] in (128, 256) and tile["target"] == target
     out2 = B.unpack(B.apply(B.pack(vecs)))
     for k in range(len(vecs)):
         assert _relerr(out2[k].cpu().numpy(), refs[k]) < 1e-12
