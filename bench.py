@@ -47,7 +47,7 @@ FLOP_PER_PAIR_FP64 = {5.0: 125.0, 50.0: 103.2, 500.0: 99.6}
 # VALU instructions per pair (all types, same counters), and the issue rate
 # they are bound by: 256 CUs x 2.4 GHz, one 64-lane VALU instruction per CU
 # per clock
-VALU_PER_PAIR_FP64 = {5.0: 82.6, 50.0: 69.1, 500.0: 67.3}
+VALU_PER_PAIR_FP64 = {5.0: 81.1, 50.0: 67.2, 500.0: 65.0}
 VALU_ISSUE_PER_S = 256 * 2.4e9 * 64
 # the gradient kernel (grad S and grad D of the same densities) evaluates K0
 # and K1(z)/r per pair as the potentials' tiles do (alpha carried by the staged
@@ -74,9 +74,9 @@ TUNED_SPLITS = os.path.join(ROOT, "paper_1908_07392_amd", "tuning", "mi355x_far_
 # HBM bytes per fused FP64 evaluation (FETCH_SIZE + WRITE_SIZE of far_eval_fp64
 # and far_sk_finalize, each scaled by the same counter's reading for a plain
 # 256 MiB copy), averaged over the three alphas, for the current kernels and
-# launch shape (one stream launch of 4 x the resident blocks)
-# (profiles/far_eval_fp64_starfish4096_grid512_hbm_bytes.txt)
-PROFILED_TRAFFIC = 99033203
+# launch shape (one stream launch of 4 x the resident blocks, numbered XCD by
+# XCD) (profiles/far_eval_fp64_starfish4096_grid512_hbm_bytes.txt)
+PROFILED_TRAFFIC = 73943808
 
 
 def parse():
