@@ -32,6 +32,7 @@
 #include <cstring>
 #include <string>
 #include <vector>
+#include <map>
 #include <mutex>
 #include <numeric>
 
@@ -89,7 +90,10 @@ struct GState {
     double inv;    /* 1 / h_{j+1,j}: scaling of the next basis vector      */
     double resest; /* |g_{j+1}| after the last step                        */
     double bnorm;  /* ||b|| when the solve left it on the device (first cycle) */
+    double rn2;    /* ||b - A x||^2 after the end of the cycle (its last chunk) */
+    double *xout;  /* caller's array that receives x at the end of each cycle (or NULL) */
 };
+static_assert(sizeof(GState) <= 64, "the state and the tail state share the first 128 bytes of gdev");
 
 namespace mhlp {
 struct FmmTree;
@@ -151,10 +155,13 @@ struct mhlp_plan {
     hipStream_t cap_stream = nullptr;
     struct StepGraph {
         hipGraphExec_t exec = nullptr;
-        const void *ws = nullptr, *part = nullptr, *gdev = nullptr;
-        int R = 0, nsplit = 0, S = 0;
-    } graphs[2][9][4]; /* [precision][steps of the chunk whose Gram-Schmidt runs in one block: 0..8]
-                          [chunk length 1, 2, 4, 8] */
+        const void *ws = nullptr, *part = nullptr, *gdev = nullptr, *x = nullptr, *b = nullptr;
+        int R = 0, nsplit = 0;
+    };
+    /* keyed by (precision, chunk length S = 0..GMRES_MAX_CHUNK, steps m <= S
+       whose Gram-Schmidt runs in one block, end-of-cycle tail or not) */
+    std::map<int, StepGraph> graphs;
+    int gm_first_steps[2] = {0, 0}; /* steps of the last solve's first cycle, per precision */
 };
 
 /* ------------------------------------------------------------------------ */
@@ -1989,6 +1996,10 @@ constexpr int64_t GSR_NMAX = 8 * GSF_T;
 /* basis columns the one-block form keeps in registers for vectors of length N;
    it serves the steps whose columns all fit, the slice form the later ones */
 __host__ __device__ inline int gsr_cols(int64_t N) { return N <= GSF_T ? 32 : N <= 2 * GSF_T ? 16 : N <= 4 * GSF_T ? 8 : 4; }
+/* GMRES steps take the one-block form while their basis columns fill at most
+   this many register groups of gsr_cols(N) columns (later groups are reloaded
+   for each pass); beyond that the element slices */
+constexpr int GSR_GROUPS = 1;
 
 /* Sum over the 64 lanes of a wave with DPP moves (no LDS traffic): adds of
    the value 1, 2, 4, 8 lanes lower within each row of 16 lanes, then the last
@@ -2282,7 +2293,7 @@ __global__ __launch_bounds__(GSF_T) void gsm_finish_kernel(GState *__restrict__ 
 
 /* start of a cycle: state, g = beta e_1 */
 __global__ void gs_init_kernel(GState *__restrict__ gs, double *__restrict__ gv, int R, int kmax, double beta,
-                               double thresh)
+                               double thresh, double *xout)
 {
     for (int i = threadIdx.x; i <= R; i += blockDim.x) gv[i] = i == 0 ? beta : 0.0;
     if (threadIdx.x == 0) {
@@ -2293,6 +2304,7 @@ __global__ void gs_init_kernel(GState *__restrict__ gs, double *__restrict__ gv,
         gs->thresh = thresh;
         gs->inv = 0.0;
         gs->resest = beta;
+        gs->xout = xout;
     }
 }
 
@@ -2302,7 +2314,7 @@ __global__ void gs_init_kernel(GState *__restrict__ gs, double *__restrict__ gv,
    the state for the host's first read (a zero b ends the cycle at once) */
 __global__ void gs_init_dev_kernel(GState *__restrict__ gs, double *__restrict__ gv, int R, int kmax,
                                    double half_tol, const double *__restrict__ bn2, const double *__restrict__ b,
-                                   double *__restrict__ V0, int64_t N)
+                                   double *__restrict__ V0, int64_t N, double *xout)
 {
     const double beta = sqrt(bn2[0]);
     const double sc = beta > 0.0 ? 1.0 / beta : 0.0;
@@ -2319,14 +2331,24 @@ __global__ void gs_init_dev_kernel(GState *__restrict__ gs, double *__restrict__
         gs->inv = 0.0;
         gs->resest = beta;
         gs->bnorm = beta;
+        gs->xout = xout;
     }
 }
 
+/* ---- end of a cycle, enqueued after its last chunk of steps; every kernel
+   does nothing unless the cycle has ended (gs->done) ---- */
 /* y = R_k^{-1} g_k for the k = steps leading columns (upper triangular back
-   substitution), one wave: the row sums are split over the 64 lanes */
-__global__ __launch_bounds__(64) void gs_solve_kernel(const GState *__restrict__ gs, const double *__restrict__ H,
-                                                      int R, const double *__restrict__ gv, double *__restrict__ y)
+   substitution), one wave: the row sums are split over the 64 lanes.  Also
+   arms the tail state for the operator application that follows: density
+   x (column 0, stride 0), active only when the cycle has ended. */
+__global__ __launch_bounds__(64) void gs_solve_kernel(const GState *__restrict__ gs, GState *__restrict__ tail,
+                                                      const double *__restrict__ H, int R,
+                                                      const double *__restrict__ gv, double *__restrict__ y)
 {
+    if (!gs->done) {
+        if (threadIdx.x == 0) tail->done = 1;
+        return;
+    }
     const int k = gs->steps;
     for (int i = k - 1; i >= 0; --i) {
         double s = 0.0;
@@ -2335,6 +2357,10 @@ __global__ __launch_bounds__(64) void gs_solve_kernel(const GState *__restrict__
         if (threadIdx.x == 0) y[i] = (gv[i] - s) / H[(int64_t)i * R + i];
         __syncthreads();
     }
+    if (threadIdx.x == 0) {
+        tail->j = 0;
+        tail->done = 0;
+    }
 }
 
 /* x += sum_{c < steps} y[c] V_c */
@@ -2342,11 +2368,90 @@ __global__ void gs_addcols_kernel(const GState *__restrict__ gs, const double *_
                                   const double *__restrict__ y, double *__restrict__ x, int64_t N)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= N) return;
+    if (i >= N || !gs->done) return;
     const int k = gs->steps;
     double v = x[i];
     for (int c = 0; c < k; ++c) v = fma(y[c], V[c * ld + i], v);
     x[i] = v;
+}
+
+/* r = b - a and gs->rn2 = ||r||^2 (the true residual of the cycle's new
+   iterate x, a = A x), and x copied to gs->xout when set; one block; the sum
+   runs in a fixed order (each thread's strided elements, wave sums, waves in
+   order) */
+__global__ __launch_bounds__(GSF_T) void tail_residual_kernel(const GState *__restrict__ tail,
+                                                              const double *__restrict__ b,
+                                                              const double *__restrict__ a,
+                                                              const double *__restrict__ x, double *__restrict__ r,
+                                                              int64_t N, GState *__restrict__ gs)
+{
+    __shared__ double red[GSF_W];
+    if (tail->done) return;
+    const int t = threadIdx.x;
+    double *xout = gs->xout;
+    double s = 0.0;
+    for (int64_t i = t; i < N; i += GSF_T) {
+        const double v = b[i] - a[i];
+        r[i] = v;
+        s = fma(v, v, s);
+        if (xout) xout[i] = x[i];
+    }
+    s = wave_sum_dpp(s);
+    if ((t & 63) == 0) red[t >> 6] = s;
+    __syncthreads();
+    if (t == 0) {
+        double q = red[0];
+        for (int k = 1; k < GSF_W; ++k) q += red[k];
+        gs->rn2 = q;
+    }
+}
+
+/* Start of a zero-guess FP64 solve in one block (vectors up to
+   GS_START_NMAX): beta = ||bsrc||, b = bsrc (the solve's own copy), x = 0,
+   V_0 = b / beta (zero when b is), g = beta e_1, the stopping threshold
+   half_tol * beta, and beta kept in the state for the host's first read (a
+   zero b ends the cycle at once).  The sum runs in a fixed order. */
+constexpr int64_t GS_START_NMAX = 64 * GSF_T;
+__global__ __launch_bounds__(GSF_T) void gs_start_kernel(GState *__restrict__ gs, double *__restrict__ gv, int R,
+                                                         int kmax, double half_tol, const double *__restrict__ bsrc,
+                                                         double *__restrict__ b, double *__restrict__ x,
+                                                         double *__restrict__ V0, int64_t N, double *xout)
+{
+    __shared__ double red[GSF_W];
+    __shared__ double bsh;
+    const int t = threadIdx.x;
+    double s = 0.0;
+    for (int64_t i = t; i < N; i += GSF_T) {
+        const double v = bsrc[i];
+        b[i] = v;
+        x[i] = 0.0;
+        s = fma(v, v, s);
+    }
+    s = wave_sum_dpp(s);
+    if ((t & 63) == 0) red[t >> 6] = s;
+    __syncthreads();
+    if (t == 0) {
+        double q = red[0];
+        for (int k = 1; k < GSF_W; ++k) q += red[k];
+        bsh = sqrt(q);
+    }
+    __syncthreads();
+    const double beta = bsh;
+    const double sc = beta > 0.0 ? 1.0 / beta : 0.0;
+    for (int64_t i = t; i < N; i += GSF_T) V0[i] = sc * bsrc[i];
+    for (int k = t; k <= R; k += GSF_T) gv[k] = k == 0 ? beta : 0.0;
+    if (t == 0) {
+        gs->j = 0;
+        gs->kmax = kmax;
+        gs->done = beta > 0.0 ? 0 : 1;
+        gs->steps = 0;
+        gs->thresh = half_tol * beta;
+        gs->inv = 0.0;
+        gs->resest = beta;
+        gs->bnorm = beta;
+        gs->rn2 = 0.0;
+        gs->xout = xout;
+    }
 }
 
 __global__ void fill_i32_kernel(int32_t *__restrict__ x, int32_t v, int64_t N)
@@ -2836,9 +2941,7 @@ extern "C" mhlp_status mhlp_plan_destroy(mhlp_plan *P)
         if (P->ty) (void)hipFree(P->ty);
     }
     for (auto &gp : P->graphs)
-        for (auto &gv : gp)
-            for (auto &gr : gv)
-                if (gr.exec) (void)hipGraphExecDestroy(gr.exec);
+        if (gp.second.exec) (void)hipGraphExecDestroy(gp.second.exec);
     if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
     void *ptrs[] = {P->near_ptr, P->near_panel, P->near_tgt, P->near_ts, P->wslp,  P->wdlp,    P->ws,
                     P->hdev,     P->part,       P->gdev,     P->perm,    P->wgrad, P->wstk,    P->stk_flux,
@@ -3665,7 +3768,7 @@ static mhlp_status ensure_ws(mhlp_plan *P, int64_t cols)
     if (P->ws && P->ws_cols >= cols) return MHLP_OK;
     if (P->ws) (void)hipFree(P->ws);
     P->ws = nullptr;
-    TRY(dalloc(&P->ws, (cols + 4) * vlen(P)));
+    TRY(dalloc(&P->ws, (cols + 6) * vlen(P)));
     P->ws_cols = cols;
     if (!P->hdev) {
         TRY(dalloc(&P->hdev, 4 * 1024));
@@ -3690,6 +3793,7 @@ static mhlp_status dnorm(mhlp_plan *P, const double *v, int64_t N, hipStream_t s
 /* Device data of the device-driven GMRES for restart length R. */
 struct GmresDev {
     GState *gs;
+    GState *tail; /* density selector of the end-of-cycle operator: j = 0, done unless gs->done */
     double *H, *cs, *sn, *gv, *y, *h1, *h2, *hn;
     double *p1, *p2, *pn; /* multi-block Gram-Schmidt partials: [nb][R+1], [nb][R+1], [nb] */
 };
@@ -3697,9 +3801,10 @@ struct GmresDev {
 static GmresDev gdev_view(const mhlp_plan *P)
 {
     const int R = P->gdev_R;
-    double *d = reinterpret_cast<double *>(P->gdev + 64);
+    double *d = reinterpret_cast<double *>(P->gdev + 128);
     GmresDev v;
     v.gs = reinterpret_cast<GState *>(P->gdev);
+    v.tail = reinterpret_cast<GState *>(P->gdev + 64);
     v.H = d;
     d += (int64_t)(R + 1) * R;
     v.cs = d;
@@ -3736,7 +3841,7 @@ static mhlp_status ensure_gdev(mhlp_plan *P, int R)
     const int64_t nb = (vlen(P) + gsm_slice(vlen(P)) - 1) / gsm_slice(vlen(P));
     const int64_t nd = (int64_t)(R + 1) * R + 3 * R + 3 * (R + 1) + 1 + nb * (2 * (R + 1) + 1);
     char *g = nullptr;
-    TRY(dalloc(&g, 64 + 8 * nd));
+    TRY(dalloc(&g, 128 + 8 * nd));
     P->gdev = g;
     P->gdev_R = R;
     if (!P->gstate_host) HIPCHECK(hipHostMalloc((void **)&P->gstate_host, sizeof(GState), hipHostMallocDefault));
@@ -3790,15 +3895,40 @@ static mhlp_status enqueue_step(mhlp_plan *P, int32_t prec, bool one_block, hipS
     return MHLP_OK;
 }
 
-/* Executable graph of S consecutive Arnoldi steps (S = 1, 2, 4, 8), the first
-   m of them with the one-block Gram-Schmidt, captured once per plan state
-   (workspace, split and restart) on a private stream. */
-static mhlp_status step_graph(mhlp_plan *P, int32_t prec, int m, int si, hipGraphExec_t *out)
+/* End of a cycle (each kernel a no-op unless the state says done): y from
+   the rotated Hessenberg system, x += V y, and the true residual r = b - A x
+   with its squared norm in the state, so that the host reads the outcome of
+   the cycle with the state itself.  x and b are the solve's own vectors. */
+static mhlp_status enqueue_tail(mhlp_plan *P, int32_t prec, const double *b, double *x, hipStream_t st)
 {
-    const int S = 1 << si;
-    mhlp_plan::StepGraph &G = P->graphs[prec == MHLP_MIXED ? 1 : 0][m][si];
+    const int64_t N = vlen(P);
+    const int R = P->gdev_R;
+    double *V = P->ws, *w = P->ws + (int64_t)(R + 1) * N, *r = w + N;
+    const GmresDev d = gdev_view(P);
+    gs_solve_kernel<<<1, 64, 0, st>>>(d.gs, d.tail, d.H, R, d.gv, d.y);
+    gs_addcols_kernel<<<nblocks(N, 256), 256, 0, st>>>(d.gs, V, N, d.y, x, N);
+    HIPCHECK(hipGetLastError());
+    TRY(apply_op(P, x, w, prec, st, d.tail, 0));
+    tail_residual_kernel<<<1, GSF_T, 0, st>>>(d.tail, b, w, x, r, N, d.gs);
+    HIPCHECK(hipGetLastError());
+    return MHLP_OK;
+}
+
+/* longest chunk of Arnoldi steps captured in one graph */
+constexpr int GMRES_MAX_CHUNK = 16;
+
+/* Executable graph of S consecutive Arnoldi steps (0 <= S <= GMRES_MAX_CHUNK),
+   the first m of them with the one-block Gram-Schmidt, followed by the end of
+   the cycle when `tail` is set; captured once per plan state (workspace,
+   split, restart, the solve's x and b) on a private stream. */
+static mhlp_status step_graph(mhlp_plan *P, int32_t prec, int m, int S, bool tail, const double *b, double *x,
+                              hipGraphExec_t *out)
+{
+    const int key = (((prec == MHLP_MIXED ? 1 : 0) * (GMRES_MAX_CHUNK + 1) + S) * (GMRES_MAX_CHUNK + 1) + m) * 2 +
+                    (tail ? 1 : 0);
+    mhlp_plan::StepGraph &G = P->graphs[key];
     if (G.exec && G.ws == P->ws && G.part == P->part && G.gdev == P->gdev && G.R == P->gdev_R &&
-        G.nsplit == P->nsplit && G.S == S) {
+        G.nsplit == P->nsplit && G.x == x && G.b == b) {
         *out = G.exec;
         return MHLP_OK;
     }
@@ -3810,6 +3940,7 @@ static mhlp_status step_graph(mhlp_plan *P, int32_t prec, int m, int si, hipGrap
     HIPCHECK(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
     mhlp_status s = MHLP_OK;
     for (int k = 0; k < S && s == MHLP_OK; ++k) s = enqueue_step(P, prec, k < m, P->cap_stream);
+    if (tail && s == MHLP_OK) s = enqueue_tail(P, prec, b, x, P->cap_stream);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(P->cap_stream, &graph);
     if (s != MHLP_OK) {
@@ -3828,25 +3959,30 @@ static mhlp_status step_graph(mhlp_plan *P, int32_t prec, int m, int si, hipGrap
     G.gdev = P->gdev;
     G.R = P->gdev_R;
     G.nsplit = P->nsplit;
-    G.S = S;
+    G.x = x;
+    G.b = b;
     *out = G.exec;
     return MHLP_OK;
 }
 
 /* One restarted-GMRES solve of A x = b to relative tolerance `tol` (relative
-   to bnorm), FP64 Arnoldi with CGS2, operator in `prec`.  x is updated in
-   place.  The Arnoldi steps, the Givens rotations and the stopping test run
-   on the device; the host replays captured chunks of steps and reads the
-   state once per chunk.  The chunk length follows the observed convergence
-   rate (the steps still needed, rounded up to a power of two, at most 8);
-   steps after the stopping point do nothing. */
-static mhlp_status gmres_core(mhlp_plan *P, const double *b, double bnorm, double *x, double tol, int restart,
+   to bnorm), FP64 Arnoldi with CGS2, operator in `prec`.  x and b belong to
+   the plan's workspace (captured graphs refer to them); x is updated in
+   place.  The Arnoldi steps, the Givens rotations, the stopping test and the
+   end of each cycle (x += V y, the true residual, and a copy of x into xout
+   when given) run on the device; the
+   host replays captured chunks of steps and reads the state once per chunk.
+   The first chunk of a solve is as long as the first cycle of the previous
+   solve on this plan (GMRES_FIRST_CHUNK the first time), later chunks follow
+   the observed convergence rate; a chunk expected to end the cycle carries
+   its end, and steps after the stopping point do nothing.  With first_dev
+   the solve starts from x = 0 with ||b|| formed on the device from bsrc,
+   which is copied into b. */
+static mhlp_status gmres_core(mhlp_plan *P, double *b, double bnorm, double *x, double tol, int restart,
                               int max_iter, int32_t prec, hipStream_t st, int *iters, int *cycles, double *relres,
-                              const double *r_first, double beta_first, bool bnorm_dev = false)
+                              const double *r_first, double beta_first, bool first_dev_in = false,
+                              const double *bsrc = nullptr, double *xout = nullptr)
 {
-    /* bnorm_dev: a zero-guess solve (tol < 1) whose ||b||^2 the caller left in
-       P->hdev[0]; the first cycle starts from it on the device and ||b|| comes
-       back with the first read of the state */
     const int64_t N = vlen(P);
     TRY(ensure_gdev(P, restart));
     const int R = P->gdev_R;
@@ -3855,22 +3991,30 @@ static mhlp_status gmres_core(mhlp_plan *P, const double *b, double bnorm, doubl
     double *r = w + N;
     const GmresDev d = gdev_view(P);
     const unsigned nbN = nblocks(N, 256);
+    const int pi = prec == MHLP_MIXED ? 1 : 0;
     int it = 0;
     *cycles = 0;
+    double beta_tail = 0.0;
     for (;;) {
-        /* r = b - A x; the caller may hand over the first cycle's residual and
-           its norm (b itself for a zero initial guess) */
+        /* residual at the start of the cycle: handed over by the caller for
+           the first cycle (b itself for a zero initial guess), left in r by
+           the previous cycle's end otherwise */
         double beta;
-        const double *rr = r_first;
-        const bool first_dev = bnorm_dev && *cycles == 0;
+        const double *rr;
+        const bool first_dev = first_dev_in && *cycles == 0;
         if (first_dev) {
             beta = 0.0; /* known after the first read of the state */
-        } else if (r_first && *cycles == 0) {
+            rr = nullptr;
+        } else if (*cycles == 0 && r_first) {
             beta = beta_first;
-        } else {
+            rr = r_first;
+        } else if (*cycles == 0) {
             TRY(apply_op(P, x, w, prec, st));
             residual_kernel<<<nbN, 256, 0, st>>>(b, w, r, N);
             TRY(dnorm(P, r, N, st, &beta));
+            rr = r;
+        } else {
+            beta = beta_tail;
             rr = r;
         }
         if (!first_dev) {
@@ -3880,31 +4024,44 @@ static mhlp_status gmres_core(mhlp_plan *P, const double *b, double bnorm, doubl
         ++*cycles;
         const int kmax = std::min(restart, max_iter - it);
         if (first_dev) {
-            gs_init_dev_kernel<<<nbN, 256, 0, st>>>(d.gs, d.gv, R, kmax, 0.5 * tol, P->hdev, b, V, N);
+            if (N <= GS_START_NMAX) {
+                gs_start_kernel<<<1, GSF_T, 0, st>>>(d.gs, d.gv, R, kmax, 0.5 * tol, bsrc, b, x, V, N, xout);
+            } else {
+                HIPCHECK(hipMemcpyAsync(b, bsrc, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+                fill_kernel<<<nbN, 256, 0, st>>>(x, 0.0, N);
+                multi_dot_kernel<<<1, 256, 0, st>>>(b, N, b, N, P->hdev); /* ||b||^2 */
+                gs_init_dev_kernel<<<nbN, 256, 0, st>>>(d.gs, d.gv, R, kmax, 0.5 * tol, P->hdev, b, V, N, xout);
+            }
         } else {
             scale_kernel<<<nbN, 256, 0, st>>>(rr, 1.0 / beta, V, N);
-            gs_init_kernel<<<1, 256, 0, st>>>(d.gs, d.gv, R, kmax, beta, 0.5 * tol * bnorm);
+            gs_init_kernel<<<1, 256, 0, st>>>(d.gs, d.gv, R, kmax, beta, 0.5 * tol * bnorm, xout);
         }
         HIPCHECK(hipGetLastError());
-        int done_steps = 0, chunk = GMRES_FIRST_CHUNK;
+        int done_steps = 0;
+        /* the first cycle starts with the previous solve's count and its end
+           appended; otherwise GMRES_FIRST_CHUNK steps */
+        const bool hist = *cycles == 1 && P->gm_first_steps[pi] > 0;
+        int chunk = hist ? P->gm_first_steps[pi] : GMRES_FIRST_CHUNK;
+        bool expect_end = hist;
         double last_est = beta, thresh = 0.5 * tol * bnorm;
+        GState gsh;
         for (;;) {
-            int si = 0;
-            while ((1 << si) < chunk && si < 3) ++si;
+            const int S = std::max(1, std::min({chunk, GMRES_MAX_CHUNK, kmax - done_steps}));
+            const bool tail = expect_end || S == kmax - done_steps;
             /* Gram-Schmidt in one block for the steps whose basis columns fit
                its registers (step j has j + 1), over slices after them */
             const int m = (N <= GSR_NMAX && R <= GSF_RMAX)
-                              ? std::max(0, std::min(1 << si, gsr_cols(N) - done_steps))
+                              ? std::max(0, std::min(S, GSR_GROUPS * gsr_cols(N) - done_steps))
                               : 0;
             hipGraphExec_t ex;
-            TRY(step_graph(P, prec, m, si, &ex));
+            TRY(step_graph(P, prec, m, S, tail, b, x, &ex));
             HIPCHECK(hipGraphLaunch(ex, st));
             HIPCHECK(hipMemcpyAsync(P->gstate_host, d.gs, sizeof(GState), hipMemcpyDeviceToHost, st));
             HIPCHECK(spin_sync(st));
-            const GState gsh = *P->gstate_host;
+            gsh = *P->gstate_host;
             if (first_dev && done_steps == 0) {
                 bnorm = gsh.bnorm;
-                if (bnorm == 0.0) { /* b = 0: x = 0 (the caller's zero guess) */
+                if (bnorm == 0.0) { /* b = 0: x = 0 (set by the start kernel) */
                     *relres = 0.0;
                     *iters = 0;
                     *cycles = 0;
@@ -3913,22 +4070,35 @@ static mhlp_status gmres_core(mhlp_plan *P, const double *b, double bnorm, doubl
                 last_est = bnorm;
                 thresh = 0.5 * tol * bnorm;
             }
-            if (gsh.done) break;
+            if (gsh.done) {
+                if (!tail) { /* the cycle ended before its end was enqueued */
+                    TRY(step_graph(P, prec, 0, 0, true, b, x, &ex));
+                    HIPCHECK(hipGraphLaunch(ex, st));
+                    HIPCHECK(hipMemcpyAsync(P->gstate_host, d.gs, sizeof(GState), hipMemcpyDeviceToHost, st));
+                    HIPCHECK(spin_sync(st));
+                    gsh = *P->gstate_host;
+                }
+                break;
+            }
             /* steps still needed at the rate observed over this chunk */
             const int ran = gsh.steps - done_steps;
             done_steps = gsh.steps;
-            int need = 8;
+            expect_end = false;
+            int need = GMRES_MAX_CHUNK;
             if (ran > 0 && gsh.resest > 0.0 && gsh.resest < last_est) {
                 const double rate = std::pow(gsh.resest / last_est, 1.0 / ran);
-                need = (int)std::ceil(std::log(thresh / gsh.resest) / std::log(rate));
+                const double est = std::ceil(std::log(thresh / gsh.resest) / std::log(rate));
+                if (est <= GMRES_MAX_CHUNK) {
+                    need = std::max(1, (int)est);
+                    expect_end = true;
+                }
             }
             last_est = gsh.resest;
-            chunk = std::max(1, std::min(need, 8));
+            chunk = need;
         }
-        it += P->gstate_host->steps;
-        gs_solve_kernel<<<1, 64, 0, st>>>(d.gs, d.H, R, d.gv, d.y);
-        gs_addcols_kernel<<<nbN, 256, 0, st>>>(d.gs, V, N, d.y, x, N);
-        HIPCHECK(hipGetLastError());
+        it += gsh.steps;
+        if (*cycles == 1) P->gm_first_steps[pi] = std::max(1, gsh.steps);
+        beta_tail = std::sqrt(gsh.rn2);
     }
     *iters = it;
     return MHLP_OK;
@@ -3951,21 +4121,20 @@ static mhlp_status gmres_solve_impl(const mhlp_plan *Pc, const double *g, double
     hipStream_t st = (hipStream_t)stream;
     const int64_t N = vlen(P);
     std::memset(info, 0, sizeof(*info));
-    /* workspace columns: basis V_0..V_R, w, r (cycle residual), and the two
-       refinement vectors; R >= restart is the largest restart seen */
+    /* workspace columns: basis V_0..V_R, w, r (cycle residual), the two
+       refinement vectors, and the FP64 solve's own x and b; R >= restart is
+       the largest restart seen */
     TRY(ensure_gdev(P, opts->restart));
     const int R = P->gdev_R;
     TRY(ensure_ws(P, R + 1));
-    /* an FP64 solve from zero keeps ||g|| on the device until the first read
-       of the GMRES state (one host round trip fewer); the others need it now */
-    const bool bnorm_dev = opts->precision == MHLP_FP64 && !opts->use_x0 && opts->tol < 1.0;
+    const bool fp64 = opts->precision == MHLP_FP64;
+    double *xw = P->ws + (int64_t)(R + 5) * N, *bw = P->ws + (int64_t)(R + 6) * N;
+    /* an FP64 solve from zero forms ||g|| on the device and reads it with the
+       first read of the GMRES state (one host round trip fewer); the others
+       need it now */
+    const bool bnorm_dev = fp64 && !opts->use_x0 && opts->tol < 1.0;
     double bnorm = 0.0;
-    if (bnorm_dev) {
-        multi_dot_kernel<<<1, 256, 0, st>>>(g, N, g, N, P->hdev); /* ||g||^2 */
-        HIPCHECK(hipGetLastError());
-    } else {
-        TRY(dnorm(P, g, N, st, &bnorm));
-    }
+    if (!bnorm_dev) TRY(dnorm(P, g, N, st, &bnorm));
     info->used_x0 = opts->use_x0 ? 1 : 0;
     if (!bnorm_dev && bnorm == 0.0) {
         fill_kernel<<<nblocks(N, 256), 256, 0, st>>>(mu, 0.0, N);
@@ -3984,18 +4153,28 @@ static mhlp_status gmres_solve_impl(const mhlp_plan *Pc, const double *g, double
         TRY(dnorm(P, r0, N, st, &r0n));
         info->x0_residual = r0n / bnorm;
         if (!(info->x0_residual < 1.0)) {
-            fill_kernel<<<nblocks(N, 256), 256, 0, st>>>(mu, 0.0, N);
+            fill_kernel<<<nblocks(N, 256), 256, 0, st>>>(fp64 ? xw : mu, 0.0, N);
             info->used_x0 = 0;
+        } else if (fp64) {
+            HIPCHECK(hipMemcpyAsync(xw, mu, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
         }
     } else {
-        fill_kernel<<<nblocks(N, 256), 256, 0, st>>>(mu, 0.0, N);
+        if (!bnorm_dev) fill_kernel<<<nblocks(N, 256), 256, 0, st>>>(fp64 ? xw : mu, 0.0, N);
         info->x0_residual = 1.0;
     }
     int iters = 0, cycles = 0;
     double rel = 1.0;
-    if (opts->precision == MHLP_FP64) {
-        TRY(gmres_core(P, g, bnorm, mu, opts->tol, opts->restart, opts->max_iter, MHLP_FP64, st, &iters, &cycles, &rel,
-                       info->used_x0 ? r0 : g, info->used_x0 ? r0n : bnorm, bnorm_dev));
+    if (fp64) {
+        /* the solve runs on its own copies of g and mu (xw, bw), which the
+           captured graphs refer to; the start kernel of a device-normed solve
+           makes them, else they are copied here */
+        if (!bnorm_dev) HIPCHECK(hipMemcpyAsync(bw, g, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+        const mhlp_status s = gmres_core(P, bw, bnorm, xw, opts->tol, opts->restart, opts->max_iter, MHLP_FP64, st,
+                                         &iters, &cycles, &rel, info->used_x0 ? r0 : bw,
+                                         info->used_x0 ? r0n : bnorm, bnorm_dev, g, mu);
+        if (s) return s;
+        /* every cycle's end copies x into mu; without a cycle x is the start */
+        if (cycles == 0) HIPCHECK(hipMemcpyAsync(mu, xw, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
     } else {
         /* iterative refinement: FP64 residual r = g - A mu (FP64 operator), inner
            GMRES on the mixed-precision operator for A d = r to 1e-6 relative (the
