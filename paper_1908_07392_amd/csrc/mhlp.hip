@@ -893,16 +893,20 @@ __global__ __launch_bounds__(256) void sym_class_kernel(const double *__restrict
 
 /* node n: row sums of the chunks from its block on, column sums of the blocks
    up to its own, then the near corrections, 1/(2 pi) and the identity term;
-   FZ_L lanes per node as in far_finalize.  Every thread of the block returns. */
+   FZ_L lanes per node as in far_finalize, SFZ_TG nodes per block (small
+   blocks: the vectors are short, and more blocks spread the reads of the
+   partials over more CUs).  Every thread of the block returns. */
+constexpr int SFZ_TG = 16;
 __device__ __forceinline__ void sym_finalize_body(const SymArgs &S, const double *mu, int nchunk,
-                                                  double (&red)[2][FZ_L][FZ_TG])
+                                                  double (&red)[2][FZ_L][SFZ_TG])
 {
     const FarArgs &A = S.A;
-    const int g = threadIdx.x % FZ_TG, l = threadIdx.x / FZ_TG;
-    const int64_t n = blockIdx.x * (int64_t)FZ_TG + g;
+    const int g = threadIdx.x % SFZ_TG, l = threadIdx.x / SFZ_TG;
+    const int64_t n = blockIdx.x * (int64_t)SFZ_TG + g;
     double fd = 0.0, nd = 0.0;
     if (n < A.N) {
         const int B = (int)(n / SYM_R);
+#pragma unroll 4
         for (int c = SYM_RP * B / SYM_CP + l; c < nchunk; c += FZ_L) fd += S.p1[(int64_t)c * A.N + n];
         for (int b = l; b <= B; b += FZ_L) fd += S.p2[(int64_t)b * A.N + n];
         for (int32_t q = A.nptr[n]; q < A.nptr[n + 1]; ++q) {
@@ -925,9 +929,9 @@ __device__ __forceinline__ void sym_finalize_body(const SymArgs &S, const double
     }
 }
 
-__global__ __launch_bounds__(FZ_TG *FZ_L) void sym_finalize(SymArgs S, int nchunk)
+__global__ __launch_bounds__(SFZ_TG *FZ_L) void sym_finalize(SymArgs S, int nchunk)
 {
-    __shared__ double red[2][FZ_L][FZ_TG];
+    __shared__ double red[2][FZ_L][SFZ_TG];
     const double *mu;
     if (!far_density(S.A, mu)) return;
     sym_finalize_body(S, mu, nchunk, red);
@@ -1996,11 +2000,6 @@ constexpr int64_t GSR_NMAX = 8 * GSF_T;
 /* basis columns the one-block form keeps in registers for vectors of length N;
    it serves the steps whose columns all fit, the slice form the later ones */
 __host__ __device__ inline int gsr_cols(int64_t N) { return N <= GSF_T ? 32 : N <= 2 * GSF_T ? 16 : N <= 4 * GSF_T ? 8 : 4; }
-/* GMRES steps take the one-block form while their basis columns fill at most
-   this many register groups of gsr_cols(N) columns (later groups are reloaded
-   for each pass); beyond that the element slices */
-constexpr int GSR_GROUPS = 1;
-
 /* Sum over the 64 lanes of a wave with DPP moves (no LDS traffic): adds of
    the value 1, 2, 4, 8 lanes lower within each row of 16 lanes, then the last
    lane of each row carried into the next row (row_bcast15) and lane 31 into
@@ -3370,7 +3369,7 @@ static mhlp_status launch_far(const mhlp_plan *P, const double *sigma, const dou
     if (P->sym_tiles && !sigma && mu && precision == MHLP_FP64) {
         const SymArgs S = sym_args(P, A);
         sym_far_kernel<<<(unsigned)P->sym_ntiles, SYM_R, 0, st>>>(S);
-        sym_finalize<<<nblocks(A.M, FZ_TG), FZ_TG * FZ_L, 0, st>>>(S, (int)((g->N + SYM_C - 1) / SYM_C));
+        sym_finalize<<<nblocks(A.M, SFZ_TG), SFZ_TG * FZ_L, 0, st>>>(S, (int)((g->N + SYM_C - 1) / SYM_C));
         HIPCHECK(hipGetLastError());
         return MHLP_OK;
     }
@@ -4051,7 +4050,7 @@ static mhlp_status gmres_core(mhlp_plan *P, double *b, double bnorm, double *x, 
             /* Gram-Schmidt in one block for the steps whose basis columns fit
                its registers (step j has j + 1), over slices after them */
             const int m = (N <= GSR_NMAX && R <= GSF_RMAX)
-                              ? std::max(0, std::min(S, GSR_GROUPS * gsr_cols(N) - done_steps))
+                              ? std::max(0, std::min(S, gsr_cols(N) - done_steps))
                               : 0;
             hipGraphExec_t ex;
             TRY(step_graph(P, prec, m, S, tail, b, x, &ex));
