@@ -565,12 +565,14 @@ __device__ __forceinline__ void far_epilogue(const FarArgs &A, const double *__r
 
 /* Sum of the source-split partials, near corrections, 1/(2 pi) scaling and
    identity term.  A block takes FZ_TG consecutive targets with L lanes each
-   (lane l is wave l, so every partial load is a coalesced row segment): lane
+   (lane l is the l-th group of FZ_TG threads, so the partial loads of a lane
+   are row segments of FZ_TG consecutive values; small blocks spread short
+   lists over many CUs): lane
    l adds the partials l, l + L, ... and the correction terms of node l, l + L,
    ... of each near panel; the lane sums are then added in lane order.  L = 16
    for short target lists (many splits, few targets: the on-surface operator),
    L = 1 (one thread per target, 256 targets a block) otherwise. */
-constexpr int FZ_TG = 64, FZ_L = 16, FZ_SHORT = 16384;
+constexpr int FZ_TG = 16, FZ_L = 16, FZ_SHORT = 16384;
 
 template <bool SLP, bool DLP, int L>
 __global__ __launch_bounds__(L == 1 ? 256 : FZ_TG * L) void far_finalize(FarArgs A, int nsplit)
@@ -893,16 +895,14 @@ __global__ __launch_bounds__(256) void sym_class_kernel(const double *__restrict
 
 /* node n: row sums of the chunks from its block on, column sums of the blocks
    up to its own, then the near corrections, 1/(2 pi) and the identity term;
-   FZ_L lanes per node as in far_finalize, SFZ_TG nodes per block (small
-   blocks: the vectors are short, and more blocks spread the reads of the
-   partials over more CUs).  Every thread of the block returns. */
-constexpr int SFZ_TG = 16;
+   FZ_L lanes per node and FZ_TG nodes per block as in far_finalize.  Every
+   thread of the block returns. */
 __device__ __forceinline__ void sym_finalize_body(const SymArgs &S, const double *mu, int nchunk,
-                                                  double (&red)[2][FZ_L][SFZ_TG])
+                                                  double (&red)[2][FZ_L][FZ_TG])
 {
     const FarArgs &A = S.A;
-    const int g = threadIdx.x % SFZ_TG, l = threadIdx.x / SFZ_TG;
-    const int64_t n = blockIdx.x * (int64_t)SFZ_TG + g;
+    const int g = threadIdx.x % FZ_TG, l = threadIdx.x / FZ_TG;
+    const int64_t n = blockIdx.x * (int64_t)FZ_TG + g;
     double fd = 0.0, nd = 0.0;
     if (n < A.N) {
         const int B = (int)(n / SYM_R);
@@ -929,9 +929,9 @@ __device__ __forceinline__ void sym_finalize_body(const SymArgs &S, const double
     }
 }
 
-__global__ __launch_bounds__(SFZ_TG *FZ_L) void sym_finalize(SymArgs S, int nchunk)
+__global__ __launch_bounds__(FZ_TG *FZ_L) void sym_finalize(SymArgs S, int nchunk)
 {
-    __shared__ double red[2][FZ_L][SFZ_TG];
+    __shared__ double red[2][FZ_L][FZ_TG];
     const double *mu;
     if (!far_density(S.A, mu)) return;
     sym_finalize_body(S, mu, nchunk, red);
@@ -3369,7 +3369,7 @@ static mhlp_status launch_far(const mhlp_plan *P, const double *sigma, const dou
     if (P->sym_tiles && !sigma && mu && precision == MHLP_FP64) {
         const SymArgs S = sym_args(P, A);
         sym_far_kernel<<<(unsigned)P->sym_ntiles, SYM_R, 0, st>>>(S);
-        sym_finalize<<<nblocks(A.M, SFZ_TG), SFZ_TG * FZ_L, 0, st>>>(S, (int)((g->N + SYM_C - 1) / SYM_C));
+        sym_finalize<<<nblocks(A.M, FZ_TG), FZ_TG * FZ_L, 0, st>>>(S, (int)((g->N + SYM_C - 1) / SYM_C));
         HIPCHECK(hipGetLastError());
         return MHLP_OK;
     }
