@@ -465,3 +465,37 @@ def test_gmres_long_vectors_circle_modal():
     print(info)
     assert g.n_nodes == 36864 and info["converged"] and info["iters"] >= 5
     assert np.max(np.abs(mu.cpu().numpy() - exact)) < 1e-9 * np.max(np.abs(exact))
+
+
+def test_gmres_chunk_history_does_not_change_results():
+    """A plan sizes the first chunk of a solve from its previous solve (which
+    may have needed more or fewer steps) and appends the end of the cycle to
+    chunks expected to finish it.  Solving a harder, an easier and the harder
+    system again on one plan, restarted and unrestarted, in FP64 and mixed
+    precision, gives bit for bit the results and counts of the same solves on
+    fresh plans, and the FP64 solutions meet the oracle's dense solve."""
+    alpha = 5.0
+    g = wl.discretize(wl.starfish_curve(), 40)
+    _, D = oracle.onsurface_matrices(g.x, g.y, alpha)
+    A = 0.5 * np.eye(g.n_nodes) + D
+    zs = np.array([2.0 * np.exp(0.4j), 2.0 * np.exp(2.9j), 1.6 * np.exp(4.4j)])
+    hard, _ = wl.point_source_data(g.x, g.y, alpha, zs, np.array([1.0, -0.7, 0.5]))
+    hard = hard / np.max(np.abs(hard))
+    easy = np.cos(g.theta)
+    G = _geom(g)
+    for precision in (mhlp.FP64, mhlp.MIXED):
+        for restart in (200, 4):
+            P = mhlp.Plan(G, alpha)
+            counts = []
+            for b in (hard, easy, hard, easy):
+                mu, info = mhlp.gmres_solve(P, _t(b), tol=1e-10, restart=restart, precision=precision)
+                ref, rinfo = mhlp.gmres_solve(mhlp.Plan(G, alpha), _t(b), tol=1e-10, restart=restart,
+                                              precision=precision)
+                assert info["converged"] and info["rel_residual"] <= 1e-10
+                assert (info["iters"], info["restarts"]) == (rinfo["iters"], rinfo["restarts"])
+                assert torch.equal(mu, ref)
+                if precision == mhlp.FP64:
+                    assert _relerr(mu.cpu().numpy(), np.linalg.solve(A, b)) < 1e-8
+                counts.append(info["iters"])
+            print(precision, restart, counts)
+            assert counts[0] > counts[1]  # the history both over- and undershoots
