@@ -622,6 +622,41 @@ __global__ __launch_bounds__(L == 1 ? 256 : FZ_TG * L) void far_finalize(FarArgs
     }
 }
 
+/* Sum over the 64 lanes of a wave with DPP moves (no LDS traffic): adds of
+   the value 1, 2, 4, 8 lanes lower within each row of 16 lanes, then the last
+   lane of each row carried into the next row (row_bcast15) and lane 31 into
+   the upper half (row_bcast31): lane 63 then holds the sum, a fixed tree, and
+   readlane returns it to every lane.  Lanes with no source add zero. */
+__device__ __forceinline__ double dpp_add(double v, int ctrl_sel)
+{
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    int rlo, rhi;
+    switch (ctrl_sel) {
+    case 0: rlo = __builtin_amdgcn_update_dpp(0, lo, 0x111, 0xf, 0xf, false);
+            rhi = __builtin_amdgcn_update_dpp(0, hi, 0x111, 0xf, 0xf, false); break;
+    case 1: rlo = __builtin_amdgcn_update_dpp(0, lo, 0x112, 0xf, 0xf, false);
+            rhi = __builtin_amdgcn_update_dpp(0, hi, 0x112, 0xf, 0xf, false); break;
+    case 2: rlo = __builtin_amdgcn_update_dpp(0, lo, 0x114, 0xf, 0xf, false);
+            rhi = __builtin_amdgcn_update_dpp(0, hi, 0x114, 0xf, 0xf, false); break;
+    case 3: rlo = __builtin_amdgcn_update_dpp(0, lo, 0x118, 0xf, 0xf, false);
+            rhi = __builtin_amdgcn_update_dpp(0, hi, 0x118, 0xf, 0xf, false); break;
+    case 4: rlo = __builtin_amdgcn_update_dpp(0, lo, 0x142, 0xa, 0xf, false);
+            rhi = __builtin_amdgcn_update_dpp(0, hi, 0x142, 0xa, 0xf, false); break;
+    default: rlo = __builtin_amdgcn_update_dpp(0, lo, 0x143, 0xc, 0xf, false);
+             rhi = __builtin_amdgcn_update_dpp(0, hi, 0x143, 0xc, 0xf, false); break;
+    }
+    return v + __hiloint2double(rhi, rlo);
+}
+
+__device__ __forceinline__ double wave_sum_dpp(double v)
+{
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v = dpp_add(v, k);
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
+}
+
 /* ---- on-surface double layer, each unordered far pair once ----
    K1(z)/r depends on the pair only through r, so one evaluation serves the
    term of source j at node i and of source i at node j.  Tiles pair a block of
@@ -1697,6 +1732,203 @@ __global__ void stkg_finalize(StkGArgs A, int nsplit)
     stkg_epilogue(A, i, acc);
 }
 
+/* ---- on-surface stresslet double layer, each unordered far pair once ----
+   The far term of source j at node i is -F(e; n_j, m_j), e = x_i - x_j, m = w mu,
+   F(e; n, m) = A1 (n (e.m) + e (n.m) + m (e.n)) + (A2 (e.m)(e.n) + A3 (n.m)) e
+   with A1, A2, A3 = alpha^2 T1, alpha^4 T2, alpha^2 T3 of |e| (App. B), the
+   contraction of far_stokes_fp64.  F is odd in e, so one evaluation of the A_k
+   serves both terms of the pair: source j at node i and +F(e; n_i, m_i) for
+   source i at node j.  Tiles, near bit set and order rules as sym_far_kernel;
+   the column terms of a tile are summed over each row of 16 lanes by DPP
+   moves, then the 16 row sums of a column in order through LDS. */
+struct StkSymArgs {
+    StkArgs A;
+    const int2 *tiles;
+    double *p1, *p2; /* [column panel][2][N], [row block][2][N] */
+    const uint32_t *bits;
+    int nw;
+};
+
+/* inclusive sums within each row of 16 lanes: lane 15 of a row holds its sum */
+__device__ __forceinline__ double row16_sum_dpp(double v)
+{
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v = dpp_add(v, k);
+    return v;
+}
+
+__global__ __launch_bounds__(SYM_R) void stk_sym_kernel(StkSymArgs S)
+{
+    const StkArgs &A = S.A;
+    __shared__ double cx[SYM_C], cy[SYM_C], cnx[SYM_C], cny[SYM_C], cm1[SYM_C], cm2[SYM_C], cnm[SYM_C];
+    __shared__ uint32_t cmask[SYM_C];
+    __shared__ double colv[2][SYM_C][SYM_R / 16];
+    const double *mu;
+    if (!stk_density(A, mu)) return; /* the same for the whole launch */
+    const int2 tl = S.tiles[blockIdx.x];
+    const int I = tl.x, J = tl.y, t = threadIdx.x;
+    const int64_t N = A.N, i = (int64_t)I * SYM_R + t, j0 = (int64_t)J * SYM_C;
+    const int pb = SYM_RP * I; /* first panel of the row block */
+    if (t < SYM_C) {
+        const int64_t j = j0 + t;
+        double xj = 0.0, yj = 0.0, nxj = 0.0, nyj = 0.0, m1 = 0.0, m2 = 0.0;
+        uint32_t msk = 0;
+        if (j < N) {
+            xj = A.sx[j];
+            yj = A.sy[j];
+            nxj = A.snx[j];
+            nyj = A.sny[j];
+            const double wj = A.sw[j];
+            m1 = wj * mu[j];
+            m2 = wj * mu[N + j];
+            msk = (S.bits[j * S.nw + (pb >> 5)] >> (pb & 31)) & 0xFFFFu; /* the block's 16 panels */
+        }
+        cx[t] = xj;
+        cy[t] = yj;
+        cnx[t] = nxj;
+        cny[t] = nyj;
+        cm1[t] = m1;
+        cm2[t] = m2;
+        cnm[t] = fma(nxj, m1, nyj * m2);
+        cmask[t] = msk;
+    }
+    const bool valid = i < N;
+    double x = 0.0, y = 0.0, nxi = 0.0, nyi = 0.0, mi1 = 0.0, mi2 = 0.0;
+    uint32_t rnear = 0; /* bit 0: column panel J listed near row i */
+    int kp = 0;         /* row panel within the block */
+    if (valid) {
+        x = A.sx[i];
+        y = A.sy[i];
+        nxi = A.snx[i];
+        nyi = A.sny[i];
+        const double wi = A.sw[i];
+        mi1 = wi * mu[i];
+        mi2 = wi * mu[N + i];
+        kp = (int)(i / 16) - pb;
+        rnear = (S.bits[i * S.nw + (J >> 5)] >> (J & 31)) & 1u;
+    }
+    const double nmi = fma(nxi, mi1, nyi * mi2);
+    const bool diag = SYM_CP * J < pb + SYM_RP; /* the chunk lies in the row block */
+    const bool rfar = valid && !(rnear & 1u);
+    __syncthreads();
+    const FarConst fc = far_const(A.alpha);
+    const double al2 = A.alpha * A.alpha, ial2 = fc.ia * fc.ia;
+    const int ncol = (int)min((int64_t)SYM_C, N - j0);
+    const int slot = t >> 4; /* row of 16 lanes: 4 per wave */
+    double a1 = 0.0, a2 = 0.0;
+#pragma unroll 1
+    for (int s = 0; s < ncol; s += 2) {
+        const FarTab T = far_table();
+        double ex[2], ey[2], r2[2];
+        bool rw[2], cl[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int c = s + u;
+            const bool order = !diag || i < j0 + c; /* on the diagonal block only row < column */
+            ex[u] = x - cx[c];
+            ey[u] = y - cy[c];
+            rw[u] = rfar && order;
+            cl[u] = valid && order && !((cmask[c] >> kp) & 1u);
+            const double d2 = fma(ex[u], ex[u], ey[u] * ey[u]);
+            r2[u] = (rw[u] || cl[u]) ? d2 : 1.0; /* unused pairs (the node itself among them) */
+        }
+        double Ak[2][3];
+        stk_far2(T, fc, al2, ial2, r2[0], r2[1], Ak[0], Ak[1]);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int c = s + u;
+            const double *K = Ak[u];
+            if (rw[u]) {
+                const double rn = fma(ex[u], cnx[c], ey[u] * cny[c]), rm = fma(ex[u], cm1[c], ey[u] * cm2[c]);
+                const double nm = cnm[c], cf = fma(K[1] * rm, rn, K[2] * nm);
+                a1 -= fma(K[0], fma(cnx[c], rm, fma(ex[u], nm, cm1[c] * rn)), cf * ex[u]);
+                a2 -= fma(K[0], fma(cny[c], rm, fma(ey[u], nm, cm2[c] * rn)), cf * ey[u]);
+            }
+            double v1 = 0.0, v2 = 0.0;
+            if (cl[u]) {
+                const double rn = fma(ex[u], nxi, ey[u] * nyi), rm = fma(ex[u], mi1, ey[u] * mi2);
+                const double cf = fma(K[1] * rm, rn, K[2] * nmi);
+                v1 = fma(K[0], fma(nxi, rm, fma(ex[u], nmi, mi1 * rn)), cf * ex[u]);
+                v2 = fma(K[0], fma(nyi, rm, fma(ey[u], nmi, mi2 * rn)), cf * ey[u]);
+            }
+            v1 = row16_sum_dpp(v1);
+            v2 = row16_sum_dpp(v2);
+            if ((t & 15) == 15) {
+                colv[0][c][slot] = v1;
+                colv[1][c][slot] = v2;
+            }
+        }
+    }
+    __syncthreads();
+    if (t < 2 * SYM_C) {
+        const int comp = t / SYM_C, c = t % SYM_C;
+        if (c < ncol) {
+            double sc = 0.0;
+            for (int r = 0; r < SYM_R / 16; ++r) sc += colv[comp][c][r];
+            S.p2[((int64_t)I * 2 + comp) * N + j0 + c] = sc;
+        }
+    }
+    if (valid) {
+        S.p1[(int64_t)J * 2 * N + i] = a1;
+        S.p1[((int64_t)J * 2 + 1) * N + i] = a2;
+    }
+}
+
+/* node n: both components of the row sums of the chunks from its block on and
+   of the column sums of the blocks up to its own, the near corrections, and
+   on the BIE operator the flux term and mu/2; FZ_L lanes per node, FZ_TG
+   nodes per block, lane sums added in lane order. */
+__global__ __launch_bounds__(FZ_TG *FZ_L) void stk_sym_finalize(StkSymArgs S, int nchunk)
+{
+    const StkArgs &A = S.A;
+    __shared__ double red[4][FZ_L][FZ_TG]; /* far 1, near 1, far 2, near 2 */
+    const double *mu;
+    if (!stk_density(A, mu)) return; /* the same for every thread of the launch */
+    const int g = threadIdx.x % FZ_TG, l = threadIdx.x / FZ_TG;
+    const int64_t N = A.N, n = blockIdx.x * (int64_t)FZ_TG + g;
+    double f1 = 0.0, n1 = 0.0, f2 = 0.0, n2 = 0.0;
+    if (n < N) {
+        const int B = (int)(n / SYM_R);
+        for (int c = SYM_RP * B / SYM_CP + l; c < nchunk; c += FZ_L) {
+            f1 += S.p1[(int64_t)c * 2 * N + n];
+            f2 += S.p1[((int64_t)c * 2 + 1) * N + n];
+        }
+        for (int b = l; b <= B; b += FZ_L) {
+            f1 += S.p2[(int64_t)b * 2 * N + n];
+            f2 += S.p2[((int64_t)b * 2 + 1) * N + n];
+        }
+        for (int32_t q = A.nptr[n]; q < A.nptr[n + 1]; ++q) {
+            const int64_t p = A.npan[q];
+            if (p < 0) continue;
+            const int64_t o = 16 * (int64_t)q + l;
+            const double m1 = mu[16 * p + l], m2 = mu[N + 16 * p + l];
+            n1 = fma(A.wst[o], m1, fma(A.wst[A.nnz * 16 + o], m2, n1));
+            n2 = fma(A.wst[2 * A.nnz * 16 + o], m1, fma(A.wst[3 * A.nnz * 16 + o], m2, n2));
+        }
+    }
+    red[0][l][g] = f1;
+    red[1][l][g] = n1;
+    red[2][l][g] = f2;
+    red[3][l][g] = n2;
+    __syncthreads();
+    if (l != 0 || n >= N) return;
+    for (int q = 1; q < FZ_L; ++q) {
+        f1 += red[0][q][g];
+        n1 += red[1][q][g];
+        f2 += red[2][q][g];
+        n2 += red[3][q][g];
+    }
+    double a1 = f1 + n1, a2 = f2 + n2;
+    if (A.bie) {
+        const double f = A.flux[0];
+        a1 = fma(0.5, mu[n], fma(A.snx[n], f, a1));
+        a2 = fma(0.5, mu[N + n], fma(A.sny[n], f, a2));
+    }
+    const int64_t o = A.perm ? (int64_t)A.perm[n] : n;
+    A.u[o] = a1;
+    A.u[A.ustride + o] = a2;
+}
+
 template <bool SPLIT>
 __global__ __launch_bounds__(FT_THREADS) void far_stokes_grad_fp64(StkGArgs A)
 {
@@ -2000,40 +2232,6 @@ constexpr int64_t GSR_NMAX = 8 * GSF_T;
 /* basis columns the one-block form keeps in registers for vectors of length N;
    it serves the steps whose columns all fit, the slice form the later ones */
 __host__ __device__ inline int gsr_cols(int64_t N) { return N <= GSF_T ? 32 : N <= 2 * GSF_T ? 16 : N <= 4 * GSF_T ? 8 : 4; }
-/* Sum over the 64 lanes of a wave with DPP moves (no LDS traffic): adds of
-   the value 1, 2, 4, 8 lanes lower within each row of 16 lanes, then the last
-   lane of each row carried into the next row (row_bcast15) and lane 31 into
-   the upper half (row_bcast31): lane 63 then holds the sum, a fixed tree, and
-   readlane returns it to every lane.  Lanes with no source add zero. */
-__device__ __forceinline__ double dpp_add(double v, int ctrl_sel)
-{
-    const int lo = __double2loint(v), hi = __double2hiint(v);
-    int rlo, rhi;
-    switch (ctrl_sel) {
-    case 0: rlo = __builtin_amdgcn_update_dpp(0, lo, 0x111, 0xf, 0xf, false);
-            rhi = __builtin_amdgcn_update_dpp(0, hi, 0x111, 0xf, 0xf, false); break;
-    case 1: rlo = __builtin_amdgcn_update_dpp(0, lo, 0x112, 0xf, 0xf, false);
-            rhi = __builtin_amdgcn_update_dpp(0, hi, 0x112, 0xf, 0xf, false); break;
-    case 2: rlo = __builtin_amdgcn_update_dpp(0, lo, 0x114, 0xf, 0xf, false);
-            rhi = __builtin_amdgcn_update_dpp(0, hi, 0x114, 0xf, 0xf, false); break;
-    case 3: rlo = __builtin_amdgcn_update_dpp(0, lo, 0x118, 0xf, 0xf, false);
-            rhi = __builtin_amdgcn_update_dpp(0, hi, 0x118, 0xf, 0xf, false); break;
-    case 4: rlo = __builtin_amdgcn_update_dpp(0, lo, 0x142, 0xa, 0xf, false);
-            rhi = __builtin_amdgcn_update_dpp(0, hi, 0x142, 0xa, 0xf, false); break;
-    default: rlo = __builtin_amdgcn_update_dpp(0, lo, 0x143, 0xc, 0xf, false);
-             rhi = __builtin_amdgcn_update_dpp(0, hi, 0x143, 0xc, 0xf, false); break;
-    }
-    return v + __hiloint2double(rhi, rlo);
-}
-
-__device__ __forceinline__ double wave_sum_dpp(double v)
-{
-#pragma unroll
-    for (int k = 0; k < 6; ++k) v = dpp_add(v, k);
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
-    return __hiloint2double(hi, lo);
-}
 
 /* v[c][k] = V_{c0+c}[t + k GSF_T] for the chunk's columns below ncol (0 elsewhere) */
 template <int C, int E>
@@ -3120,18 +3318,21 @@ static mhlp_status plan_create_impl(const mhlp_geometry *g, double alpha, const 
             return s;
         }
     }
-    if (P->onsurf && !P->stokes && g->N <= SYM_NMAX && g->N % 16 == 0) {
-        /* tiles of the symmetric on-surface double layer (row block I, column
-           chunk J from the block's first panel on) */
+    if (P->onsurf && g->N <= SYM_NMAX && g->N % 16 == 0) {
+        /* tiles of the symmetric on-surface double layer, scalar or stresslet
+           (row block I, column chunk J from the block's first panel on); the
+           stresslet keeps two components per partial sum and no piece table */
+        const int64_t ncomp = P->stokes ? 2 : 1;
         const int64_t nrb = (g->N + SYM_R - 1) / SYM_R, ncc = (g->N + SYM_C - 1) / SYM_C;
         std::vector<int2> tiles;
         for (int64_t I = 0; I < nrb; ++I)
             for (int64_t J = SYM_RP * I / SYM_CP; J < ncc; ++J) tiles.push_back(make_int2((int)I, (int)J));
         P->sym_ntiles = (int32_t)tiles.size();
         P->sym_nw = (int32_t)((g->Np + 31) / 32);
-        if ((s = dalloc(&P->sym_tiles, (int64_t)tiles.size())) || (s = dalloc(&P->sym_p1, ncc * g->N)) ||
-            (s = dalloc(&P->sym_p2, nrb * g->N)) || (s = dalloc(&P->sym_bits, (int64_t)P->sym_nw * g->N)) ||
-            (s = dalloc(&P->sym_cls, nrb * (SYM_R / 64) * g->Np))) {
+        if ((s = dalloc(&P->sym_tiles, (int64_t)tiles.size())) || (s = dalloc(&P->sym_p1, ncomp * ncc * g->N)) ||
+            (s = dalloc(&P->sym_p2, ncomp * nrb * g->N)) ||
+            (s = dalloc(&P->sym_bits, (int64_t)P->sym_nw * g->N)) ||
+            (!P->stokes && (s = dalloc(&P->sym_cls, nrb * (SYM_R / 64) * g->Np)))) {
             mhlp_plan_destroy(P);
             return s;
         }
@@ -3221,8 +3422,9 @@ static mhlp_status plan_create_impl(const mhlp_geometry *g, double alpha, const 
     }
     if (P->sym_bits) {
         near_bits_kernel<<<nblocks(M, 256), 256, 0, st>>>(P->near_ptr, P->near_panel, M, P->sym_nw, P->sym_bits);
-        sym_class_kernel<<<nblocks(M, SYM_R), SYM_R, 0, st>>>(P->g->soa, P->g->soa + P->g->N, M, P->g->Np,
-                                                               P->alpha, P->sym_bits, P->sym_nw, P->sym_cls);
+        if (P->sym_cls)
+            sym_class_kernel<<<nblocks(M, SYM_R), SYM_R, 0, st>>>(P->g->soa, P->g->soa + P->g->N, M, P->g->Np,
+                                                                   P->alpha, P->sym_bits, P->sym_nw, P->sym_cls);
         hipError_t eb = hipGetLastError();
         if (eb == hipSuccess) eb = hipStreamSynchronize(st); /* later calls may come on other streams */
         if (eb != hipSuccess) {
@@ -3654,6 +3856,13 @@ static mhlp_status launch_stokes(const mhlp_plan *P, const double *mu, double *u
     A.gs = gs;
     A.jstride = jstride;
     if (bie) stk_flux_kernel<<<1, 256, 0, st>>>(A, P->inv_len, P->stk_flux);
+    if (P->sym_tiles) { /* on-surface: each unordered far pair once */
+        const StkSymArgs S{A, P->sym_tiles, P->sym_p1, P->sym_p2, P->sym_bits, P->sym_nw};
+        stk_sym_kernel<<<(unsigned)P->sym_ntiles, SYM_R, 0, st>>>(S);
+        stk_sym_finalize<<<nblocks(g->N, FZ_TG), FZ_TG * FZ_L, 0, st>>>(S, (int)((g->N + SYM_C - 1) / SYM_C));
+        HIPCHECK(hipGetLastError());
+        return MHLP_OK;
+    }
     const unsigned nb = nblocks(A.M, FT_THREADS);
     if (P->nsplit <= 1) {
         far_stokes_fp64<false><<<nb, FT_THREADS, 0, st>>>(A);

@@ -68,8 +68,11 @@ def test_stokes_near_targets_vs_oracle(alpha):
 
 
 @pytest.mark.parametrize("alpha", [5.0, 50.0, 500.0])
-def test_stokes_onsurface_operator_vs_oracle(alpha):
-    g = wl.discretize(wl.starfish_curve(), 32)
+@pytest.mark.parametrize("n_panels", [32, 33])
+def test_stokes_onsurface_operator_vs_oracle(alpha, n_panels):
+    """The on-surface operator (each unordered far pair evaluated once) against
+    the oracle's dense matrices; 33 panels leave a ragged last row block."""
+    g = wl.discretize(wl.starfish_curve(), n_panels)
     mu = _density(g, 5)
     Dm = oracle.stokes_matrix(g.x, g.y, alpha)
     nx, ny = g.normals
@@ -181,3 +184,29 @@ def test_stokes_config2_full_size_sampled():
         e = _rel(u, ref)
         print(f"config2 stokes alpha={alpha} pairs={P.n_near_pairs} err {e:.2e}")
         assert e < 1e-11
+
+
+def test_stokes_onsurface_config2_full_size_sampled():
+    """The on-surface stresslet operator on the config-2 boundary (N = 4096,
+    the size its GMRES runs at): principal-value D mu at sampled nodes (random,
+    and the first and last node of panels) against the oracle, and the BIE
+    operator with mu/2 and the flux term n(x) (integral of mu.n dS)/|Gamma|."""
+    cfg = wl.config2()
+    g = cfg["geom"]
+    G = mhlp.Geometry(_t(g.node_soa()))
+    mu = _density(g, 12, nmax=12)
+    rng = np.random.default_rng(15)
+    idx = np.unique(np.concatenate([rng.choice(g.n_nodes, 120, replace=False), np.arange(0, g.n_nodes, 16)[::9],
+                                    np.arange(15, g.n_nodes, 16)[::9]]))
+    nx, ny = g.normals
+    flux = np.sum(g.weights * (mu[0] * nx + mu[1] * ny)) / np.sum(g.weights)
+    for alpha in cfg["alphas"]:
+        P = mhlp.Plan(G, alpha, stokes=True)
+        pv = mhlp.stokes_eval(P, _t(mu)).cpu().numpy()[:, idx]
+        bie = mhlp.stokes_apply_bie(P, _t(mu)).cpu().numpy().reshape(2, -1)[:, idx]
+        ref = oracle.stokes_eval(g.x, g.y, alpha, g.x[idx], g.y[idx], mu, tgt_node=idx)
+        refb = ref + 0.5 * mu[:, idx] + flux * np.stack([nx[idx], ny[idx]])
+        e1 = float(np.max(np.abs(pv - ref)) / np.max(np.abs(mu)))
+        e2 = float(np.max(np.abs(bie - refb)) / np.max(np.abs(mu)))
+        print(f"config2 on-surface stokes alpha={alpha} D_pv {e1:.2e} bie {e2:.2e}")
+        assert e1 < 1e-11 and e2 < 1e-11
