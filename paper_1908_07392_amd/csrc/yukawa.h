@@ -79,8 +79,9 @@ __host__ __device__ __forceinline__ K01 k01_fp64(double r2, double a, double a2q
 /* Same regimes and coefficients as k01_fp64 with lean elementary functions: */
 /*  * 1/sqrt and 1/x: hardware v_rsq_f64 / v_rcp_f64 estimates refined by    */
 /*    one Newton-type step (third order for rsq, two steps for rcp);         */
-/*  * e^{-z}: Cody-Waite reduction z = n ln2 - r, |r| <= ln2/2, degree-13    */
-/*    Taylor polynomial (truncation 4e-18), scaling by 2^-n (ldexp);         */
+/*  * e^{-z}, z >= 0: Cody-Waite reduction z = k ln2/32 - r, |r| <= ln2/64, */
+/*    a table of 2^{-j/32} (Tang's table-driven method), degree-6 Taylor     */
+/*    polynomial (truncation 4e-18), scaling by 2^-(k/32) (ldexp);           */
 /*  * log q, 0 < q <= 1: q = m 2^e with m in [sqrt(1/2), sqrt(2)),           */
 /*    log m = 2 atanh(s), s = (m-1)/(m+1), |s| <= 0.1716, series to s^21.     */
 /* ---------------------------------------------------------------------- */
@@ -115,6 +116,7 @@ constexpr int KQ_N1[KQ_NP] = {11, 10, 10, 9, 8, 8, 7, 7, 13, 13, 12, 11, 10, 9, 
 struct FarTable {
     double kp0n[17], kp0f[16], kp1n[15], kp1f[14], kl0[23], expt[14], atanh[11], ks_i0[12], ks_r0[13], ks_i1z[12],
         ks_r1[13];
+    double exp2nj[32]; /* 2^(-j/32) */
     double kp0m[13], kp0x[10], kp1m[11], kp1x[9]; /* the z > 6 piece split at z = 20 */
     double kq0[15][16], kq1[15][13];               /* the fine pieces (KQ0_k, KQ1_k), zero padded */
     double kqb[15];                                /* their constant v offsets (-2 - ulo - uhi)/(uhi - ulo) */
@@ -143,6 +145,7 @@ constexpr FarTable make_far_table()
         t.kqb[k] = (-2.0 - KQ_ULO[k] - KQ_UHI[k]) / (KQ_UHI[k] - KQ_ULO[k]);
     }
     for (int i = 0; i < 14; ++i) t.expt[i] = EXP_T[i];
+    for (int i = 0; i < 32; ++i) t.exp2nj[i] = EXP2_NJ[i];
     for (int i = 0; i < 11; ++i) t.atanh[i] = ATANH_T[i];
     for (int i = 0; i < 12; ++i) t.ks_i0[i] = KS_I0[i], t.ks_i1z[i] = KS_I1Z[i];
     for (int i = 0; i < 13; ++i) t.ks_r0[i] = KS_R0[i], t.ks_r1[i] = KS_R1[i];
@@ -205,16 +208,22 @@ __device__ __forceinline__ double lean_rcp(double x)
     return fma(y, e, y);
 }
 
-/* e^{-z} = 2^m e^r, m = round(-z log2 e), |r| <= ln2/2 (+ rounding): m comes
-   from adding 1.5 * 2^52, whose low word then holds m as an integer */
+/* e^{-z} for z >= 0: k = round(32 z log2 e), r = k ln2/32 - z with
+   |r| <= ln2/64 (+ rounding), e^{-z} = 2^{-(k >> 5)} 2^{-(k & 31)/32} e^r
+   (Tang's table-driven reduction: the table entry is a per-lane load, and the
+   polynomial is 7 terms instead of 14).  k comes from adding 1.5 * 2^52,
+   whose low word then holds it as an integer; k ln2/32 is exact in its high
+   part (LN2_HI has 21 trailing zero bits, k < 2^21 for z < 3e4, and e^{-z}
+   underflows to zero long before). */
 __device__ __forceinline__ double lean_exp_neg(FarTab T, double z)
 {
     constexpr double SHIFT = 6755399441055744.0; /* 1.5 * 2^52 */
-    const double t = fma(z, -LOG2E, SHIFT);
-    const double m = t - SHIFT;
-    double r = fma(m, -LN2_HI, -z);
-    r = fma(m, -LN2_LO, r);
-    return ldexp(hornerc<14>(T->expt, r), __double2loint(t));
+    const double t = fma(z, 32.0 * LOG2E, SHIFT);
+    const double kd = t - SHIFT;
+    double r = fma(kd, LN2_HI / 32.0, -z);
+    r = fma(kd, LN2_LO / 32.0, r);
+    const int k = __double2loint(t);
+    return ldexp(T->exp2nj[k & 31] * hornerc<7>(T->expt, r), -(k >> 5));
 }
 
 __device__ __forceinline__ double lean_log01(FarTab T, double q)
