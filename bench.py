@@ -41,13 +41,14 @@ FP64_PEAK_TFLOPS = 78.6        # MI355X vector FP64 (published)
 # profiles/far_eval_fp64_starfish4096_grid512_valu_f64.txt.  The pairs take
 # the fitted piece of their z: at alpha = 500 nearly all z > 100 (K0 with its
 # derivative to degree 6), at alpha = 5 z of 2..14 (degrees 9-12, the z <= 2
-# series for the nearest).  Static count of the z > 100 loop: 40 v_fma (x2),
-# 14 v_mul, 3 v_add, 2 v_rsq = 99 per pair.
-FLOP_PER_PAIR_FP64 = {5.0: 125.0, 50.0: 103.2, 500.0: 99.6}
+# series for the nearest).  Static count of the z > 100 loop: 33 v_fma (x2),
+# 15 v_mul, 3 v_add, 2 v_rsq = 86 per pair (e^{-z} by a table of 2^(-j/32)
+# and a 7-term polynomial).
+FLOP_PER_PAIR_FP64 = {5.0: 112.7, 50.0: 90.1, 500.0: 86.6}
 # VALU instructions per pair (all types, same counters), and the issue rate
 # they are bound by: 256 CUs x 2.4 GHz, one 64-lane VALU instruction per CU
 # per clock
-VALU_PER_PAIR_FP64 = {5.0: 81.1, 50.0: 67.2, 500.0: 65.0}
+VALU_PER_PAIR_FP64 = {5.0: 78.0, 50.0: 64.2, 500.0: 62.2}
 VALU_ISSUE_PER_S = 256 * 2.4e9 * 64
 # the gradient kernel (grad S and grad D of the same densities) evaluates K0
 # and K1(z)/r per pair as the potentials' tiles do (alpha carried by the staged
@@ -76,7 +77,7 @@ TUNED_SPLITS = os.path.join(ROOT, "paper_1908_07392_amd", "tuning", "mi355x_far_
 # 256 MiB copy), averaged over the three alphas, for the current kernels and
 # launch shape (one stream launch of 4 x the resident blocks, numbered XCD by
 # XCD) (profiles/far_eval_fp64_starfish4096_grid512_hbm_bytes.txt)
-PROFILED_TRAFFIC = 73943808
+PROFILED_TRAFFIC = 49040000
 
 
 def parse():

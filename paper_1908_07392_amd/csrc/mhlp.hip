@@ -1004,7 +1004,7 @@ __device__ __forceinline__ void far_panel_fp64(const FarArgs &A, const FarConst 
 }
 
 /* waves per SIMD the FP64 far kernel is compiled for (96 registers per lane) */
-constexpr int SK_WAVES = 5;
+constexpr int SK_WAVES = 4;
 
 /* The stream position of hardware block b of a P-block launch.  The chip's
    dispatcher deals blocks to its 8 XCDs (each with its own L2) in turn, block b
