@@ -52,23 +52,23 @@ VALU_PER_PAIR_FP64 = {5.0: 78.0, 50.0: 64.2, 500.0: 62.2}
 VALU_ISSUE_PER_S = 256 * 2.4e9 * 64
 # the gradient kernel (grad S and grad D of the same densities) evaluates K0
 # and K1(z)/r per pair as the potentials' tiles do (alpha carried by the staged
-# densities; 105 of their 112 on the z > 20 piece, without their accumulation),
-# then 1/r^2, (x-y).d, (alpha K0 + 2 K1/r)/r^2 and the four accumulations:
-# counted from the built kernel's loop, 51 v_fma (x2), 19 v_mul, 4 v_add,
-# 2 v_rsq = 127 per pair on the z > 20 piece
-FLOP_PER_PAIR_GRAD = 127
+# densities; e^{-z} by a table of 2^(-j/32) and a 7-term polynomial), then
+# 1/r^2, (x-y).d, (alpha K0 + 2 K1/r)/r^2 and the four accumulations: counted
+# from the built kernel's loop, 44 v_fma (x2), 20 v_mul, 4 v_add, 2 v_rsq =
+# 114 per pair on the z > 20 piece (counters 114.5 at alpha = 500)
+FLOP_PER_PAIR_GRAD = 114
 # modified-Stokes double layer (2x2 stresslet per pair): K0 and K1(z)/r from
 # the three-piece fits, alpha K1/r, 1/r^2, the closed forms of alpha^2 T1,
 # alpha^4 T2, alpha^2 T3 (App. B) and the contraction D_ij w mu_j into two
-# accumulators: counted from the built kernel's loop on the z > 20 piece, 60
-# v_fma (x2), 36 v_mul, 6 v_add, 2 v_rsq = 164 (counters 164.7 at alpha = 500)
-FLOP_PER_PAIR_STOKES = 164
+# accumulators: counted from the built kernel's loop on the z > 20 piece, 53
+# v_fma (x2), 37 v_mul, 6 v_add, 2 v_rsq = 151 (counters 151.6 at alpha = 500)
+FLOP_PER_PAIR_STOKES = 151
 # target gradient of the stresslet double layer (velocity gradient, 4 outputs):
 # the same K0, K1(z)/r, 1/r^2 and A_k, B_k = A_k'(r)/r from K0 and A_k, and the
 # contraction d_l D_ij w mu_j into four accumulators: counted from the built
-# kernel's loop on the z > 20 piece, 77 v_fma (x2), 52 v_mul, 11 v_add,
-# 2 v_rsq = 219 (counters 219.8 at alpha = 500)
-FLOP_PER_PAIR_STOKES_GRAD = 219
+# kernel's loop on the z > 20 piece, 70 v_fma (x2), 53 v_mul, 11 v_add,
+# 2 v_rsq = 206 (counters 206.8 at alpha = 500)
+FLOP_PER_PAIR_STOKES_GRAD = 206
 # launch shapes (far-field source splits) chosen by the autotuner on MI355X for
 # the plans of this benchmark
 TUNED_SPLITS = os.path.join(ROOT, "paper_1908_07392_amd", "tuning", "mi355x_far_splits.json")
