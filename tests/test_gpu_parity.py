@@ -444,13 +444,17 @@ def test_zero_rhs_and_loose_tolerance_paths():
     assert info["converged"] and info["iters"] == 0 and float(mu.abs().max()) == 0.0
 
 
-def test_gmres_long_vectors_circle_modal():
+@pytest.mark.parametrize("n_panels,restart", [(2304, 100), (4160, 100), (4160, 4)])
+def test_gmres_long_vectors_circle_modal(n_panels, restart):
     """N = 36,864 nodes: Gram-Schmidt over element slices of 512 (several
-    elements per thread, 72 slices) from the first step; a right-hand side with
+    elements per thread, 72 slices) from the first step; N = 66,560: also the
+    multi-kernel start of a zero-guess solve (vectors beyond the one-block
+    start kernel), unrestarted and restarted every 4 steps (each cycle's end
+    on the device, the next cycle from its residual).  A right-hand side with
     sixteen Fourier modes on the circle, whose exact solution divides each mode
     by its eigenvalue of 1/2 I + D."""
     R, alpha = 1.0, 10.0
-    g = wl.discretize(wl.Curve("circle", R=R), 2304)
+    g = wl.discretize(wl.Curve("circle", R=R), n_panels)
     x = alpha * R
 
     def lam(n):
@@ -461,9 +465,12 @@ def test_gmres_long_vectors_circle_modal():
     b = sum(a[n] * np.cos(n * g.theta) + c[n] * np.sin(n * g.theta) for n in range(16))
     exact = sum((a[n] * np.cos(n * g.theta) + c[n] * np.sin(n * g.theta)) / lam(n) for n in range(16))
     P = mhlp.Plan(_geom(g), alpha)
-    mu, info = mhlp.gmres_solve(P, _t(b), tol=1e-12)
-    print(info)
-    assert g.n_nodes == 36864 and info["converged"] and info["iters"] >= 5
+    mu, info = mhlp.gmres_solve(P, _t(b), tol=1e-12, restart=restart, max_iter=400)
+    print(n_panels, restart, info)
+    assert g.n_nodes == 16 * n_panels and info["converged"] and info["iters"] >= 5
+    assert info["rel_residual"] <= 1e-12
+    if restart < info["iters"]:
+        assert info["restarts"] >= 2
     assert np.max(np.abs(mu.cpu().numpy() - exact)) < 1e-9 * np.max(np.abs(exact))
 
 
