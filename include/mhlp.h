@@ -257,10 +257,14 @@ mhlp_status mhlp_eval_grad(const mhlp_plan *plan, const double *sigma, const dou
    with reorthogonalisation in FP64, judged by the true FP64 residual.  g, mu:
    device [N].  With opts->use_x0, mu holds the initial guess; a guess whose
    true relative residual is >= 1 is replaced by zero (info->used_x0 = 0).
-   The Arnoldi steps, Givens rotations and the stopping test run on the
-   device; chunks of steps are replayed from HIP graphs captured on a private
-   stream of the plan (the host reads the state once per chunk).  The plan's
-   GMRES state is shared: concurrent solves on one plan are not allowed.
+   The Arnoldi steps, Givens rotations, the stopping test and the end of each
+   cycle (the update of mu and its true residual) run on the device; chunks of
+   steps are replayed from HIP graphs captured on a private stream of the plan
+   (the host reads the state once per chunk).  The first chunk of a solve is
+   as long as the first cycle of the plan's previous solve, which only changes
+   how the steps are grouped, never the result.  The plan's GMRES state and
+   workspace (with its own copies of g and mu) are shared: concurrent solves on
+   one plan are not allowed.
    opts, info: host.  Synchronises the stream.  Returns MHLP_NOT_CONVERGED
    (mu = last iterate, info filled) if max_iter is reached. */
 mhlp_status mhlp_gmres_solve(const mhlp_plan *onsurf, const double *g, double *mu, const mhlp_gmres_opts *opts,
