@@ -2144,16 +2144,6 @@ __global__ __launch_bounds__(256) void multi_dot_kernel(const double *__restrict
     if (threadIdx.x == 0) out[c] = red[0];
 }
 
-/* x[i] += sum_{c<ncol} y[c] V[c*ld + i] */
-__global__ void add_combo_kernel(const double *__restrict__ V, int64_t ld, int ncol, const double *__restrict__ yv,
-                                 double *__restrict__ x, int64_t N)
-{
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    double s = x[i];
-    for (int c = 0; c < ncol; ++c) s = fma(yv[c], V[c * ld + i], s);
-    x[i] = s;
-}
 
 /* out = s * in */
 __global__ void scale_kernel(const double *__restrict__ in, double s, double *__restrict__ out, int64_t N)
@@ -3978,11 +3968,7 @@ static mhlp_status ensure_ws(mhlp_plan *P, int64_t cols)
     P->ws = nullptr;
     TRY(dalloc(&P->ws, (cols + 6) * vlen(P)));
     P->ws_cols = cols;
-    if (!P->hdev) {
-        TRY(dalloc(&P->hdev, 4 * 1024));
-        fill_kernel<<<1, 64, 0, 0>>>(P->hdev + 4000, 1.0, 1); /* constant 1 for x += d */
-        HIPCHECK(hipDeviceSynchronize());
-    }
+    if (!P->hdev) TRY(dalloc(&P->hdev, 4 * 1024));
     if (!P->hhost) HIPCHECK(hipHostMalloc((void **)&P->hhost, sizeof(double) * 4 * 1024, hipHostMallocDefault));
     return MHLP_OK;
 }
@@ -4105,9 +4091,11 @@ static mhlp_status enqueue_step(mhlp_plan *P, int32_t prec, bool one_block, hipS
 
 /* End of a cycle (each kernel a no-op unless the state says done): y from
    the rotated Hessenberg system, x += V y, and the true residual r = b - A x
-   with its squared norm in the state, so that the host reads the outcome of
-   the cycle with the state itself.  x and b are the solve's own vectors. */
-static mhlp_status enqueue_tail(mhlp_plan *P, int32_t prec, const double *b, double *x, hipStream_t st)
+   with the FP64 operator (whatever the precision of the cycle's Arnoldi
+   steps) and its squared norm in the state, so that the host reads the
+   outcome of the cycle with the state itself.  x and b are the solve's own
+   vectors. */
+static mhlp_status enqueue_tail(mhlp_plan *P, const double *b, double *x, hipStream_t st)
 {
     const int64_t N = vlen(P);
     const int R = P->gdev_R;
@@ -4116,7 +4104,7 @@ static mhlp_status enqueue_tail(mhlp_plan *P, int32_t prec, const double *b, dou
     gs_solve_kernel<<<1, 64, 0, st>>>(d.gs, d.tail, d.H, R, d.gv, d.y);
     gs_addcols_kernel<<<nblocks(N, 256), 256, 0, st>>>(d.gs, V, N, d.y, x, N);
     HIPCHECK(hipGetLastError());
-    TRY(apply_op(P, x, w, prec, st, d.tail, 0));
+    TRY(apply_op(P, x, w, MHLP_FP64, st, d.tail, 0));
     tail_residual_kernel<<<1, GSF_T, 0, st>>>(d.tail, b, w, x, r, N, d.gs);
     HIPCHECK(hipGetLastError());
     return MHLP_OK;
@@ -4148,7 +4136,7 @@ static mhlp_status step_graph(mhlp_plan *P, int32_t prec, int m, int S, bool tai
     HIPCHECK(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
     mhlp_status s = MHLP_OK;
     for (int k = 0; k < S && s == MHLP_OK; ++k) s = enqueue_step(P, prec, k < m, P->cap_stream);
-    if (tail && s == MHLP_OK) s = enqueue_tail(P, prec, b, x, P->cap_stream);
+    if (tail && s == MHLP_OK) s = enqueue_tail(P, b, x, P->cap_stream);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(P->cap_stream, &graph);
     if (s != MHLP_OK) {
@@ -4174,7 +4162,13 @@ static mhlp_status step_graph(mhlp_plan *P, int32_t prec, int m, int S, bool tai
 }
 
 /* One restarted-GMRES solve of A x = b to relative tolerance `tol` (relative
-   to bnorm), FP64 Arnoldi with CGS2, operator in `prec`.  x and b belong to
+   to bnorm), FP64 Arnoldi with CGS2 on the operator in `prec`, each cycle
+   ended by the true residual with the FP64 operator.  A cycle stops once its
+   residual estimate is below 0.5 tol bnorm or, when larger, cycle_rel times
+   the residual it started from: with the mixed-precision operator (cycle_rel
+   = 0.5e-6, the FP32 far field resolving the operator to ~1e-7) this is
+   iterative refinement, each cycle an inner solve of A d = r corrected by the
+   FP64 residual.  x and b belong to
    the plan's workspace (captured graphs refer to them); x is updated in
    place.  The Arnoldi steps, the Givens rotations, the stopping test and the
    end of each cycle (x += V y, the true residual, and a copy of x into xout
@@ -4189,8 +4183,9 @@ static mhlp_status step_graph(mhlp_plan *P, int32_t prec, int m, int S, bool tai
 static mhlp_status gmres_core(mhlp_plan *P, double *b, double bnorm, double *x, double tol, int restart,
                               int max_iter, int32_t prec, hipStream_t st, int *iters, int *cycles, double *relres,
                               const double *r_first, double beta_first, bool first_dev_in = false,
-                              const double *bsrc = nullptr, double *xout = nullptr)
+                              const double *bsrc = nullptr, double *xout = nullptr, double cycle_rel = 0.0)
 {
+    const double half_tol = std::max(0.5 * tol, cycle_rel); /* first cycle of a device-normed solve */
     const int64_t N = vlen(P);
     TRY(ensure_gdev(P, restart));
     const int R = P->gdev_R;
@@ -4217,7 +4212,7 @@ static mhlp_status gmres_core(mhlp_plan *P, double *b, double bnorm, double *x, 
             beta = beta_first;
             rr = r_first;
         } else if (*cycles == 0) {
-            TRY(apply_op(P, x, w, prec, st));
+            TRY(apply_op(P, x, w, MHLP_FP64, st));
             residual_kernel<<<nbN, 256, 0, st>>>(b, w, r, N);
             TRY(dnorm(P, r, N, st, &beta));
             rr = r;
@@ -4233,16 +4228,17 @@ static mhlp_status gmres_core(mhlp_plan *P, double *b, double bnorm, double *x, 
         const int kmax = std::min(restart, max_iter - it);
         if (first_dev) {
             if (N <= GS_START_NMAX) {
-                gs_start_kernel<<<1, GSF_T, 0, st>>>(d.gs, d.gv, R, kmax, 0.5 * tol, bsrc, b, x, V, N, xout);
+                gs_start_kernel<<<1, GSF_T, 0, st>>>(d.gs, d.gv, R, kmax, half_tol, bsrc, b, x, V, N, xout);
             } else {
                 HIPCHECK(hipMemcpyAsync(b, bsrc, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
                 fill_kernel<<<nbN, 256, 0, st>>>(x, 0.0, N);
                 multi_dot_kernel<<<1, 256, 0, st>>>(b, N, b, N, P->hdev); /* ||b||^2 */
-                gs_init_dev_kernel<<<nbN, 256, 0, st>>>(d.gs, d.gv, R, kmax, 0.5 * tol, P->hdev, b, V, N, xout);
+                gs_init_dev_kernel<<<nbN, 256, 0, st>>>(d.gs, d.gv, R, kmax, half_tol, P->hdev, b, V, N, xout);
             }
         } else {
             scale_kernel<<<nbN, 256, 0, st>>>(rr, 1.0 / beta, V, N);
-            gs_init_kernel<<<1, 256, 0, st>>>(d.gs, d.gv, R, kmax, beta, 0.5 * tol * bnorm, xout);
+            gs_init_kernel<<<1, 256, 0, st>>>(d.gs, d.gv, R, kmax, beta,
+                                              std::max(0.5 * tol * bnorm, cycle_rel * beta), xout);
         }
         HIPCHECK(hipGetLastError());
         int done_steps = 0;
@@ -4251,7 +4247,7 @@ static mhlp_status gmres_core(mhlp_plan *P, double *b, double bnorm, double *x, 
         const bool hist = *cycles == 1 && P->gm_first_steps[pi] > 0;
         int chunk = hist ? P->gm_first_steps[pi] : GMRES_FIRST_CHUNK;
         bool expect_end = hist;
-        double last_est = beta, thresh = 0.5 * tol * bnorm;
+        double last_est = beta, thresh = std::max(0.5 * tol * bnorm, cycle_rel * beta);
         GState gsh;
         for (;;) {
             const int S = std::max(1, std::min({chunk, GMRES_MAX_CHUNK, kmax - done_steps}));
@@ -4276,7 +4272,7 @@ static mhlp_status gmres_core(mhlp_plan *P, double *b, double bnorm, double *x, 
                     return MHLP_OK;
                 }
                 last_est = bnorm;
-                thresh = 0.5 * tol * bnorm;
+                thresh = half_tol * bnorm;
             }
             if (gsh.done) {
                 if (!tail) { /* the cycle ended before its end was enqueued */
@@ -4329,18 +4325,18 @@ static mhlp_status gmres_solve_impl(const mhlp_plan *Pc, const double *g, double
     hipStream_t st = (hipStream_t)stream;
     const int64_t N = vlen(P);
     std::memset(info, 0, sizeof(*info));
-    /* workspace columns: basis V_0..V_R, w, r (cycle residual), the two
-       refinement vectors, and the FP64 solve's own x and b; R >= restart is
-       the largest restart seen */
+    /* workspace columns: basis V_0..V_R, w, r (cycle residual), two spare
+       vectors, and the solve's own x and b; R >= restart is the largest
+       restart seen */
     TRY(ensure_gdev(P, opts->restart));
     const int R = P->gdev_R;
     TRY(ensure_ws(P, R + 1));
-    const bool fp64 = opts->precision == MHLP_FP64;
+    const bool mixed = opts->precision == MHLP_MIXED;
     double *xw = P->ws + (int64_t)(R + 5) * N, *bw = P->ws + (int64_t)(R + 6) * N;
-    /* an FP64 solve from zero forms ||g|| on the device and reads it with the
-       first read of the GMRES state (one host round trip fewer); the others
-       need it now */
-    const bool bnorm_dev = fp64 && !opts->use_x0 && opts->tol < 1.0;
+    /* a solve from zero forms ||g|| on the device and reads it with the first
+       read of the GMRES state (one host round trip fewer); the others need it
+       now */
+    const bool bnorm_dev = !opts->use_x0 && opts->tol < 1.0;
     double bnorm = 0.0;
     if (!bnorm_dev) TRY(dnorm(P, g, N, st, &bnorm));
     info->used_x0 = opts->use_x0 ? 1 : 0;
@@ -4350,8 +4346,9 @@ static mhlp_status gmres_solve_impl(const mhlp_plan *Pc, const double *g, double
         info->converged = 1;
         return MHLP_OK;
     }
-    /* residual of the initial guess, kept in the residual slot of the first
-       GMRES cycle (basis V_0..V_R, then w, r) so the cycle does not recompute it */
+    /* residual of the initial guess (FP64 operator), kept in the residual slot
+       of the first GMRES cycle (basis V_0..V_R, then w, r) so the cycle does
+       not recompute it */
     double *r0 = P->ws + (int64_t)(R + 2) * N;
     double r0n = 0.0;
     if (opts->use_x0) {
@@ -4361,60 +4358,28 @@ static mhlp_status gmres_solve_impl(const mhlp_plan *Pc, const double *g, double
         TRY(dnorm(P, r0, N, st, &r0n));
         info->x0_residual = r0n / bnorm;
         if (!(info->x0_residual < 1.0)) {
-            fill_kernel<<<nblocks(N, 256), 256, 0, st>>>(fp64 ? xw : mu, 0.0, N);
+            fill_kernel<<<nblocks(N, 256), 256, 0, st>>>(xw, 0.0, N);
             info->used_x0 = 0;
-        } else if (fp64) {
+        } else {
             HIPCHECK(hipMemcpyAsync(xw, mu, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
         }
     } else {
-        if (!bnorm_dev) fill_kernel<<<nblocks(N, 256), 256, 0, st>>>(fp64 ? xw : mu, 0.0, N);
+        if (!bnorm_dev) fill_kernel<<<nblocks(N, 256), 256, 0, st>>>(xw, 0.0, N);
         info->x0_residual = 1.0;
     }
     int iters = 0, cycles = 0;
     double rel = 1.0;
-    if (fp64) {
-        /* the solve runs on its own copies of g and mu (xw, bw), which the
-           captured graphs refer to; the start kernel of a device-normed solve
-           makes them, else they are copied here */
-        if (!bnorm_dev) HIPCHECK(hipMemcpyAsync(bw, g, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
-        const mhlp_status s = gmres_core(P, bw, bnorm, xw, opts->tol, opts->restart, opts->max_iter, MHLP_FP64, st,
-                                         &iters, &cycles, &rel, info->used_x0 ? r0 : bw,
-                                         info->used_x0 ? r0n : bnorm, bnorm_dev, g, mu);
-        if (s) return s;
-        /* every cycle's end copies x into mu; without a cycle x is the start */
-        if (cycles == 0) HIPCHECK(hipMemcpyAsync(mu, xw, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
-    } else {
-        /* iterative refinement: FP64 residual r = g - A mu (FP64 operator), inner
-           GMRES on the mixed-precision operator for A d = r to 1e-6 relative (the
-           FP32 far field resolves the operator to ~1e-7), mu += d. */
-        double *r = P->ws + (int64_t)(R + 3) * N, *d = P->ws + (int64_t)(R + 4) * N;
-        double *w = P->ws + (int64_t)(R + 1) * N;
-        const unsigned nbN = nblocks(N, 256);
-        for (int outer = 0; outer < 20; ++outer) {
-            double rn;
-            if (outer == 0 && !info->used_x0) {
-                rn = bnorm; /* zero initial guess: r = g */
-                HIPCHECK(hipMemcpyAsync(r, g, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
-            } else if (outer == 0) {
-                rn = r0n;
-                HIPCHECK(hipMemcpyAsync(r, r0, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
-            } else {
-                TRY(apply_op(P, mu, w, MHLP_FP64, st));
-                residual_kernel<<<nbN, 256, 0, st>>>(g, w, r, N);
-                TRY(dnorm(P, r, N, st, &rn));
-            }
-            rel = rn / bnorm;
-            if (rel <= opts->tol || iters >= opts->max_iter) break;
-            fill_kernel<<<nbN, 256, 0, st>>>(d, 0.0, N);
-            int it_in = 0, cyc_in = 0;
-            double rel_in = 1.0;
-            TRY(gmres_core(P, r, rn, d, 1e-6, opts->restart, opts->max_iter - iters, MHLP_MIXED, st, &it_in, &cyc_in,
-                           &rel_in, r, rn));
-            iters += it_in;
-            cycles += 1;
-            add_combo_kernel<<<nbN, 256, 0, st>>>(d, N, 1, P->hdev + 4000, mu, N);
-        }
-    }
+    /* the solve runs on its own copies of g and mu (xw, bw), which the captured
+       graphs refer to; the start kernel of a device-normed solve makes them,
+       else they are copied here.  Mixed precision: Arnoldi steps on the FP32
+       far field, each cycle an inner solve to 1e-6 of the residual it started
+       from, its end the FP64 true residual (iterative refinement). */
+    if (!bnorm_dev) HIPCHECK(hipMemcpyAsync(bw, g, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+    TRY(gmres_core(P, bw, bnorm, xw, opts->tol, opts->restart, opts->max_iter, mixed ? MHLP_MIXED : MHLP_FP64, st,
+                   &iters, &cycles, &rel, info->used_x0 ? r0 : bw, info->used_x0 ? r0n : bnorm, bnorm_dev, g, mu,
+                   mixed ? 0.5e-6 : 0.0));
+    /* every cycle's end copies x into mu; without a cycle x is the start */
+    if (cycles == 0) HIPCHECK(hipMemcpyAsync(mu, xw, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
     info->iters = iters;
     info->restarts = cycles;
     info->rel_residual = rel;
