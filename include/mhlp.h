@@ -69,7 +69,10 @@ typedef struct {
     int32_t max_iter;   /* total Arnoldi steps                                        */
     int32_t restart;    /* Krylov dimension before a restart (<= 512)                 */
     int32_t precision;  /* MHLP_FP64 or MHLP_MIXED (mixed: FP32 far-field inner solves
-                           inside FP64 iterative refinement)                          */
+                           inside FP64 iterative refinement: each cycle's Arnoldi steps
+                           use the FP32 far field and stop at 0.5e-6 of the residual
+                           the cycle started from; each cycle ends with the FP64 true
+                           residual, from which the next starts)                      */
     int32_t use_x0;     /* 1: mu holds the initial guess on entry; 0: zero guess      */
 } mhlp_gmres_opts;
 
