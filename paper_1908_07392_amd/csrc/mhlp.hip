@@ -2222,6 +2222,9 @@ constexpr int64_t GSR_NMAX = 8 * GSF_T;
 /* basis columns the one-block form keeps in registers for vectors of length N;
    it serves the steps whose columns all fit, the slice form the later ones */
 __host__ __device__ inline int gsr_cols(int64_t N) { return N <= GSF_T ? 32 : N <= 2 * GSF_T ? 16 : N <= 4 * GSF_T ? 8 : 4; }
+/* steps take the one-block form while their basis columns exceed the register
+   capacity by at most this many (read one at a time), the slice form after */
+constexpr int GSR_EXTRA = 8;
 
 /* v[c][k] = V_{c0+c}[t + k GSF_T] for the chunk's columns below ncol (0 elsewhere) */
 template <int C, int E>
@@ -2316,17 +2319,23 @@ __device__ __forceinline__ void gsr_body(GState *__restrict__ gs, double *__rest
             gsr_sub<C, E>(v, x, 0, ncol, sh.hs[pass]);
         }
     } else {
+        /* the first C columns stay in registers for both passes; the others
+           are read one at a time, twice per pass */
+        double v[C][E];
+        gsr_load<C, E>(V, ld, N, 0, ncol, v);
         for (int pass = 0; pass < 2; ++pass) {
-            for (int c0 = 0; c0 < ncol; c0 += C) {
-                double v[C][E];
-                gsr_load<C, E>(V, ld, N, c0, ncol, v);
-                gsr_dots<C, E>(v, x, c0, ncol, sh.red);
+            gsr_dots<C, E>(v, x, 0, ncol, sh.red);
+            for (int c = C; c < ncol; ++c) {
+                double u[1][E];
+                gsr_load<1, E>(V, ld, N, c, ncol, u);
+                gsr_dots<1, E>(u, x, c, ncol, sh.red);
             }
             gsr_collect(sh.red, ncol, sh.hs[pass]);
-            for (int c0 = 0; c0 < ncol; c0 += C) {
-                double v[C][E];
-                gsr_load<C, E>(V, ld, N, c0, ncol, v);
-                gsr_sub<C, E>(v, x, c0, ncol, sh.hs[pass]);
+            gsr_sub<C, E>(v, x, 0, ncol, sh.hs[pass]);
+            for (int c = C; c < ncol; ++c) {
+                double u[1][E];
+                gsr_load<1, E>(V, ld, N, c, ncol, u);
+                gsr_sub<1, E>(u, x, c, ncol, sh.hs[pass]);
             }
         }
     }
@@ -4253,9 +4262,10 @@ static mhlp_status gmres_core(mhlp_plan *P, double *b, double bnorm, double *x, 
             const int S = std::max(1, std::min({chunk, GMRES_MAX_CHUNK, kmax - done_steps}));
             const bool tail = expect_end || S == kmax - done_steps;
             /* Gram-Schmidt in one block for the steps whose basis columns fit
-               its registers (step j has j + 1), over slices after them */
+               its registers, or exceed them by at most GSR_EXTRA (step j has
+               j + 1), over slices after them */
             const int m = (N <= GSR_NMAX && R <= GSF_RMAX)
-                              ? std::max(0, std::min(S, gsr_cols(N) - done_steps))
+                              ? std::max(0, std::min(S, gsr_cols(N) + GSR_EXTRA - done_steps))
                               : 0;
             hipGraphExec_t ex;
             TRY(step_graph(P, prec, m, S, tail, b, x, &ex));
