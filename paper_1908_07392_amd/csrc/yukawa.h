@@ -480,6 +480,18 @@ __device__ __forceinline__ void k01_far2_fixed(FarTab T, const FarConst &c, doub
     const double ria = lean_rsq(r2a), rib = lean_rsq(r2b);
     const double za = c.a * (r2a * ria), zb = c.a * (r2b * rib);
     const double ea = lean_exp_neg(T, za) * lean_rsq(za), eb = lean_exp_neg(T, zb) * lean_rsq(zb);
+    if constexpr (SLP && DLP) {
+        /* both layers: the piece's K0 and K1 fits as two independent chains
+           (N0 + N1 - 2 FMA; K1 from the K0 fit's derivative takes 2 N0 - 3
+           and a combining step) */
+        const double va = fma(qa, ria, T->kqb[P]), vb = fma(qa, rib, T->kqb[P]);
+        const double p0a = hornerc<KQ_N0[P]>(T->kq0[P], va), p0b = hornerc<KQ_N0[P]>(T->kq0[P], vb);
+        const double p1a = hornerc<KQ_N1[P]>(T->kq1[P], va), p1b = hornerc<KQ_N1[P]>(T->kq1[P], vb);
+        oa = K01{ea * p0a, (ea * ria) * p1a, ria * ria};
+        ob = K01{eb * p0b, (eb * rib) * p1b, rib * rib};
+        (void)qk;
+        return;
+    }
     double da = 0.0, db = 0.0;
     const double pa = far_piece_fine<SLP, DLP, P>(T, qa, qk, ria, da);
     const double pb = far_piece_fine<SLP, DLP, P>(T, qa, qk, rib, db);
