@@ -247,8 +247,10 @@ __device__ __forceinline__ double lean_log01(FarTab T, double q)
      z <= 2: K1 = I0/z + (z/4) log(q) I0'(q) - (z/2) R0'(q), q = z^2/4.
    Max rel. error of the z > 2 pieces 1.2e-16 for K0 and K1 (40-digit check).
    The K1R form (the potentials' tiles) splits the z > 6 piece again at
-   z = 20: degree 12 / 9 for K0 with its derivative, 10 / 8 for K1 alone
-   (1.7e-16), which shortens the polynomials of the far pairs.
+   z = 20 (degree 12 / 9 for K0, 10 / 8 for K1; 1.7e-16), which shortens the
+   polynomials of the far pairs, and takes K1 from its own fits with both
+   layers too: two independent chains of N0 + N1 - 2 FMA against 2 N0 - 3 and
+   a combining step for K1 from the K0 fit's derivative.
    k01_far_small is the z <= 2 form.  k01_far2 takes two sources: the z > 2
    forms straight-line for both (independent instruction streams the
    scheduler interleaves) on lanes where either needs it, with the common
@@ -256,34 +258,28 @@ __device__ __forceinline__ double lean_log01(FarTab T, double q)
    the lanes that need it, overwriting the other values. */
 struct FarConst {
     double a, a2q, a4, ia; /* alpha, alpha^2/4, 4/alpha, 1/alpha */
-    double vf, vn;         /* 12/alpha, 6/alpha: piece variables from 1/r */
-    double kf, kn;         /* 12/alpha^2, 6/alpha^2: (4/alpha^2) dv/du     */
-    double ha;             /* 1/(2 alpha) */
+    double vn;             /* 6/alpha: v = vn/r - 2 on 2 < z <= 6 */
     /* pieces 6 < z <= 20 (v = vm/r + om) and z > 20 (v = vx/r - 1): with
        u = 4/z - 1 on [-0.8, -1/3] and [-1, -0.8], v = (30u + 17)/7 and 10u + 9 */
-    double vm, om, km, vx, kx;
+    double vm, om, vx;
 };
 
 __device__ __forceinline__ FarConst far_const(double alpha)
 {
     const double ia = 1.0 / alpha;
-    return FarConst{alpha,          0.25 * alpha * alpha, 4.0 / alpha,         ia,      12.0 * ia,
-                    6.0 * ia,       12.0 * ia * ia,       6.0 * ia * ia,       0.5 * ia, 120.0 / 7.0 * ia,
-                    -13.0 / 7.0,    120.0 / 7.0 * ia * ia, 40.0 * ia,          40.0 * ia * ia};
+    return FarConst{alpha, 0.25 * alpha * alpha, 4.0 / alpha, ia, 6.0 * ia, 120.0 / 7.0 * ia, -13.0 / 7.0, 40.0 * ia};
 }
 
-/* polynomial of the piece (value and d/du) at 1/r = ri.  K1R: the derivative
-   comes back as (4/alpha^2) dP/du, the form far_finish<.., K1R> takes. */
-template <bool SLP, bool DLP, bool FAR, bool K1R = false>
+/* polynomial of the two-piece form (value and d/du) at 1/r = ri */
+template <bool SLP, bool DLP, bool FAR>
 __device__ __forceinline__ double far_piece(FarTab T, const FarConst &c, double ri, double &dpdu)
 {
     /* v = 3u + 2 = (12/alpha) ri - 1 (far);  v = 1.5u - 0.5 = (6/alpha) ri - 2 (near) */
-    const double v = K1R ? (FAR ? fma(c.vf, ri, -1.0) : fma(c.vn, ri, -2.0))
-                         : (FAR ? fma(3.0 * c.a4, ri, -1.0) : fma(1.5 * c.a4, ri, -2.0));
+    const double v = FAR ? fma(3.0 * c.a4, ri, -1.0) : fma(1.5 * c.a4, ri, -2.0);
     if (SLP && DLP) {
         double d;
         const double p = FAR ? hornercd<16>(T->kp0f, v, d) : hornercd<17>(T->kp0n, v, d);
-        dpdu = K1R ? d * (FAR ? c.kf : c.kn) : d * (FAR ? 3.0 : 1.5);
+        dpdu = d * (FAR ? 3.0 : 1.5);
         return p;
     }
     dpdu = 0.0;
@@ -292,27 +288,25 @@ __device__ __forceinline__ double far_piece(FarTab T, const FarConst &c, double 
 }
 
 /* the K1R pieces: P = 0 for 2 < z <= 6, 1 for 6 < z <= 20, 2 for z > 20;
-   value (and (4/alpha^2) dP/du with both layers) at 1/r = ri */
+   the K0 fit's value at 1/r = ri and, with both layers, the K1 fit's value in
+   p1 (two independent chains: fewer FMA than K1 from the K0 fit's derivative) */
 template <bool SLP, bool DLP, int P>
-__device__ __forceinline__ double far_piece3(FarTab T, const FarConst &c, double ri, double &dpdu)
+__device__ __forceinline__ double far_piece3(FarTab T, const FarConst &c, double ri, double &p1)
 {
     const double v = P == 0 ? fma(c.vn, ri, -2.0) : P == 1 ? fma(c.vm, ri, c.om) : fma(c.vx, ri, -1.0);
     if (SLP && DLP) {
-        double d;
-        const double p = P == 0   ? hornercd<17>(T->kp0n, v, d)
-                         : P == 1 ? hornercd<13>(T->kp0m, v, d)
-                                  : hornercd<10>(T->kp0x, v, d);
-        dpdu = d * (P == 0 ? c.kn : P == 1 ? c.km : c.kx);
-        return p;
+        p1 = P == 0 ? hornerc<15>(T->kp1n, v) : P == 1 ? hornerc<11>(T->kp1m, v) : hornerc<9>(T->kp1x, v);
+        return P == 0 ? hornerc<17>(T->kp0n, v) : P == 1 ? hornerc<13>(T->kp0m, v) : hornerc<10>(T->kp0x, v);
     }
-    dpdu = 0.0;
+    p1 = 0.0;
     if (SLP) return P == 0 ? hornerc<17>(T->kp0n, v) : P == 1 ? hornerc<13>(T->kp0m, v) : hornerc<10>(T->kp0x, v);
     return P == 0 ? hornerc<15>(T->kp1n, v) : P == 1 ? hornerc<11>(T->kp1m, v) : hornerc<9>(T->kp1x, v);
 }
 
-/* K1R = false: out.ak1r = alpha K1(z)/r.  K1R = true: out.ak1r = K1(z)/r (the
-   caller scales its dipoles by alpha), with K1/E = P + (1/z)(P/2 + (4/z) dP/du)
-   written as P + ri (P/(2 alpha) + ri (4/alpha^2) dP/du). */
+/* K1R = false: out.ak1r = alpha K1(z)/r, with both layers from the K0 piece
+   as K1/E = P (1 + 1/(2z)) + (4/z^2) dP/du.  K1R = true: out.ak1r = K1(z)/r
+   (the caller scales its dipoles by alpha); with both layers dpdu then holds
+   the K1 fit's value at the pair. */
 template <bool SLP, bool DLP, bool K1R = false>
 __device__ __forceinline__ K01 far_finish(const FarConst &c, double ri, double z, double e, double p, double dpdu)
 {
@@ -320,8 +314,7 @@ __device__ __forceinline__ K01 far_finish(const FarConst &c, double ri, double z
     if (SLP && DLP) {
         o.k0 = e * p;
         if (K1R) {
-            const double g = fma(p, c.ha, ri * dpdu);
-            o.ak1r = (e * ri) * fma(ri, g, p);
+            o.ak1r = (e * ri) * dpdu; /* dpdu: the piece's K1 fit value */
         } else {
             const double iz = c.ia * ri; /* 1/z */
             const double k1 = e * fma(4.0 * iz * iz, dpdu, p * fma(0.5, iz, 1.0));
@@ -403,27 +396,27 @@ __device__ __forceinline__ void k01_far2_big(FarTab T, const FarConst &c, double
                 pb = far_piece3<SLP, DLP, 0>(T, c, rib, db);
         }
     } else if (fa && fb) {
-        pa = far_piece<SLP, DLP, true, K1R>(T, c, ria, da);
-        pb = far_piece<SLP, DLP, true, K1R>(T, c, rib, db);
+        pa = far_piece<SLP, DLP, true>(T, c, ria, da);
+        pb = far_piece<SLP, DLP, true>(T, c, rib, db);
     } else if (!fa && !fb) {
-        pa = far_piece<SLP, DLP, false, K1R>(T, c, ria, da);
-        pb = far_piece<SLP, DLP, false, K1R>(T, c, rib, db);
+        pa = far_piece<SLP, DLP, false>(T, c, ria, da);
+        pb = far_piece<SLP, DLP, false>(T, c, rib, db);
     } else {
         if (fa)
-            pa = far_piece<SLP, DLP, true, K1R>(T, c, ria, da);
+            pa = far_piece<SLP, DLP, true>(T, c, ria, da);
         else
-            pa = far_piece<SLP, DLP, false, K1R>(T, c, ria, da);
+            pa = far_piece<SLP, DLP, false>(T, c, ria, da);
         if (fb)
-            pb = far_piece<SLP, DLP, true, K1R>(T, c, rib, db);
+            pb = far_piece<SLP, DLP, true>(T, c, rib, db);
         else
-            pb = far_piece<SLP, DLP, false, K1R>(T, c, rib, db);
+            pb = far_piece<SLP, DLP, false>(T, c, rib, db);
     }
     oa = far_finish<SLP, DLP, K1R>(c, ria, za, ea, pa, da);
     ob = far_finish<SLP, DLP, K1R>(c, rib, zb, eb, pb, db);
 }
 
-/* The fine piece K at 1/r = ri: value and, with both layers, (4/alpha^2) dP/du
-   as far_finish<.., K1R> takes it.  v = qa ri + qb with qa = (4/alpha) w,
+/* The fine piece K at 1/r = ri: the K0 (SLP) or K1 (DLP) fit's value and,
+   with both layers, the K1 fit's value in dpdu as far_finish<.., K1R> takes it.  v = qa ri + qb with qa = (4/alpha) w,
    w = 2/(uhi - ulo), and qk = (4/alpha^2) w.  A plan keeps the qa of every
    piece, then every qk, in device memory (fine_scales); fine_q reads the two
    of piece K through an opaque pointer, once per panel, into scalar
@@ -451,11 +444,10 @@ template <bool SLP, bool DLP, int K>
 __device__ __forceinline__ double far_piece_fine(FarTab T, double qa, double qk, double ri, double &dpdu)
 {
     const double v = fma(qa, ri, T->kqb[K]);
-    if (SLP && DLP) {
-        double d;
-        const double p = hornercd<KQ_N0[K]>(T->kq0[K], v, d);
-        dpdu = d * qk;
-        return p;
+    if (SLP && DLP) { /* both layers: the K1 fit's value in dpdu, as far_finish<.., K1R> takes it */
+        dpdu = hornerc<KQ_N1[K]>(T->kq1[K], v);
+        (void)qk;
+        return hornerc<KQ_N0[K]>(T->kq0[K], v);
     }
     dpdu = 0.0;
     if (SLP) return hornerc<KQ_N0[K]>(T->kq0[K], v);
@@ -480,18 +472,6 @@ __device__ __forceinline__ void k01_far2_fixed(FarTab T, const FarConst &c, doub
     const double ria = lean_rsq(r2a), rib = lean_rsq(r2b);
     const double za = c.a * (r2a * ria), zb = c.a * (r2b * rib);
     const double ea = lean_exp_neg(T, za) * lean_rsq(za), eb = lean_exp_neg(T, zb) * lean_rsq(zb);
-    if constexpr (SLP && DLP) {
-        /* both layers: the piece's K0 and K1 fits as two independent chains
-           (N0 + N1 - 2 FMA; K1 from the K0 fit's derivative takes 2 N0 - 3
-           and a combining step) */
-        const double va = fma(qa, ria, T->kqb[P]), vb = fma(qa, rib, T->kqb[P]);
-        const double p0a = hornerc<KQ_N0[P]>(T->kq0[P], va), p0b = hornerc<KQ_N0[P]>(T->kq0[P], vb);
-        const double p1a = hornerc<KQ_N1[P]>(T->kq1[P], va), p1b = hornerc<KQ_N1[P]>(T->kq1[P], vb);
-        oa = K01{ea * p0a, (ea * ria) * p1a, ria * ria};
-        ob = K01{eb * p0b, (eb * rib) * p1b, rib * rib};
-        (void)qk;
-        return;
-    }
     double da = 0.0, db = 0.0;
     const double pa = far_piece_fine<SLP, DLP, P>(T, qa, qk, ria, da);
     const double pb = far_piece_fine<SLP, DLP, P>(T, qa, qk, rib, db);
