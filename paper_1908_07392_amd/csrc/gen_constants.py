@@ -17,9 +17,12 @@ Device K0/K1 (modified Bessel functions of the second kind):
   local v = 1.5 u - 0.5) and z >= 6 (u in (-1, -1/3], v = 3 u + 2); K0 to degree
   16 / 15 so that K1 = -K0' taken from the derivative of the fit is also
   accurate, K1 alone to degree 14 / 13.
+* z > 6 split again at z = 20 (KP0M / KP0X, KP1M / KP1X): each of K0 and K1
+  fitted on its own (the kernels that take these pieces evaluate K1 from its
+  fit, not from K0's derivative), degree 11 / 9 and 10 / 8.
 * z > 2, eight finer pieces split at z = 3, 4.5, 7, 12, 20, 40, 100 and the
-  seven pieces spanning two neighbours (KQ0_k, K0 with its derivative; KQ1_k,
-  K1 alone), degrees 15 down to 6.
+  seven pieces spanning two neighbours (KQ0_k for K0, KQ1_k for K1, each a fit
+  of its own), degrees 12 down to 6 from the 1.2e-16 requirement on the value.
 """
 import os
 
@@ -271,7 +274,7 @@ def main():
     # split again at z = 20 (M: 6 < z <= 20, X: z > 20) for shorter polynomials
     for name, nu, deg, lo, hi, der in (("KP0N", 0, 16, us, 1, True), ("KP0F", 0, 15, -1, us, True),
                                        ("KP1N", 1, 14, us, 1, False), ("KP1F", 1, 13, -1, us, False),
-                                       ("KP0M", 0, 12, ux, us, True), ("KP0X", 0, 9, -1, ux, True),
+                                       ("KP0M", 0, 11, ux, us, False), ("KP0X", 0, 9, -1, ux, False),
                                        ("KP1M", 1, 10, ux, us, False), ("KP1X", 1, 8, -1, ux, False)):
         c = cheb_fit_mono(large_fn(nu), deg, lo, hi)
         e0, e1 = check_piece(c, nu, lo, hi, der)
@@ -282,11 +285,11 @@ def main():
     # finer pieces for launches that classify whole waves against a panel: eight
     # pieces z in (B_k, B_k+1] (k = 0..7) and seven pieces spanning two of them,
     # z in (B_s, B_s+2] (k = 8 + s), for waves whose pairs straddle one boundary;
-    # u in [4/B_hi - 1, 4/B_lo - 1]; K0 with its derivative (KQ0_k) and K1 alone
-    # (KQ1_k), degrees from the 1.2e-16 requirement
+    # u in [4/B_hi - 1, 4/B_lo - 1]; K0 (KQ0_k) and K1 (KQ1_k) each fitted on its
+    # own, degrees from the 1.2e-16 requirement on the value
     bnd = [mp.mpf(2), mp.mpf(3), mp.mpf("4.5"), mp.mpf(7), mp.mpf(12), mp.mpf(20), mp.mpf(40), mp.mpf(100), mp.inf]
     spans = [(k, k + 1) for k in range(8)] + [(k, k + 2) for k in range(7)]
-    d0 = [12, 11, 10, 9, 8, 7, 6, 6, 15, 14, 13, 11, 10, 9, 7]
+    d0 = [10, 9, 9, 8, 7, 7, 6, 6, 12, 12, 11, 10, 9, 8, 7]
     d1 = [10, 9, 9, 8, 7, 7, 6, 6, 12, 12, 11, 10, 9, 8, 7]
     ulo_all, uhi_all = [], []
     for k, (a, b) in enumerate(spans):
@@ -294,7 +297,7 @@ def main():
         lo = 4 / bnd[b] - 1 if bnd[b] != mp.inf else mp.mpf(-1)
         ulo_all.append(lo)
         uhi_all.append(hi)
-        for nu, deg, der in ((0, d0[k], True), (1, d1[k], False)):
+        for nu, deg, der in ((0, d0[k], False), (1, d1[k], False)):
             name = f"KQ{nu}_{k}"
             c = cheb_fit_mono(large_fn(nu), deg, lo, hi)
             e0, e1 = check_piece(c, nu, lo, hi, der)

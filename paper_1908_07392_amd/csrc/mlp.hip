@@ -15,7 +15,7 @@
  * Network.  n_in -> width -> width -> n_out with GELU (tanh form) after the
  * two hidden layers.  Master weights and Adam state are FP32; every product
  * runs on the matrix cores with operands rounded to BF16 and FP32
- * accumulation (v_mfma_f32_16x16x16_bf16).
+ * accumulation (v_mfma_f32_16x16x32_bf16).
  *
  * Warm start.  Input: the backward differences 0..H-1 of the coefficients of
  * the last H densities (an invertible linear map of the history that keeps

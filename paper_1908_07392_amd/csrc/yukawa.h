@@ -108,17 +108,32 @@ static constexpr double ATANH_T[11] = {1.0, 1.0 / 3.0, 1.0 / 5.0, 1.0 / 7.0, 1.0
 #define MHLP_CAS __attribute__((address_space(4)))
 /* the fine pieces: KQ_NB single pieces z in (KQ_B[k], KQ_B[k+1]] (k < KQ_NB,
    the last unbounded) and KQ_NB - 1 pieces spanning two neighbours,
-   z in (KQ_B[s], KQ_B[s+2]] (k = KQ_NB + s); coefficient counts of K0 with its
-   derivative and of K1 alone */
+   z in (KQ_B[s], KQ_B[s+2]] (k = KQ_NB + s); coefficient counts of the K0 and
+   K1 fits */
 constexpr int KQ_NB = 8, KQ_NP = 2 * KQ_NB - 1;
-constexpr int KQ_N0[KQ_NP] = {13, 12, 11, 10, 9, 8, 7, 7, 16, 15, 14, 12, 11, 10, 8};
+constexpr int KQ_N0[KQ_NP] = {11, 10, 10, 9, 8, 8, 7, 7, 13, 13, 12, 11, 10, 9, 8};
 constexpr int KQ_N1[KQ_NP] = {11, 10, 10, 9, 8, 8, 7, 7, 13, 13, 12, 11, 10, 9, 8};
+/* the coefficient counts above against the generated tables */
+template <int K, size_t N0, size_t N1>
+constexpr bool kq_sizes(const double (&)[N0], const double (&)[N1])
+{
+    return N0 == (size_t)KQ_N0[K] && N1 == (size_t)KQ_N1[K];
+}
+static_assert(kq_sizes<0>(KQ0_0, KQ1_0) && kq_sizes<1>(KQ0_1, KQ1_1) && kq_sizes<2>(KQ0_2, KQ1_2) &&
+                  kq_sizes<3>(KQ0_3, KQ1_3) && kq_sizes<4>(KQ0_4, KQ1_4) && kq_sizes<5>(KQ0_5, KQ1_5) &&
+                  kq_sizes<6>(KQ0_6, KQ1_6) && kq_sizes<7>(KQ0_7, KQ1_7) && kq_sizes<8>(KQ0_8, KQ1_8) &&
+                  kq_sizes<9>(KQ0_9, KQ1_9) && kq_sizes<10>(KQ0_10, KQ1_10) && kq_sizes<11>(KQ0_11, KQ1_11) &&
+                  kq_sizes<12>(KQ0_12, KQ1_12) && kq_sizes<13>(KQ0_13, KQ1_13) && kq_sizes<14>(KQ0_14, KQ1_14),
+              "fine-piece coefficient counts differ from the generated tables");
+static_assert(sizeof(KP0M) == 12 * sizeof(double) && sizeof(KP0X) == 10 * sizeof(double) &&
+                  sizeof(KP1M) == 11 * sizeof(double) && sizeof(KP1X) == 9 * sizeof(double),
+              "middle and far piece lengths differ from the generated tables");
 struct FarTable {
     double kp0n[17], kp0f[16], kp1n[15], kp1f[14], kl0[23], expt[14], atanh[11], ks_i0[12], ks_r0[13], ks_i1z[12],
         ks_r1[13];
     double exp2nj[32]; /* 2^(-j/32) */
-    double kp0m[13], kp0x[10], kp1m[11], kp1x[9]; /* the z > 6 piece split at z = 20 */
-    double kq0[15][16], kq1[15][13];               /* the fine pieces (KQ0_k, KQ1_k), zero padded */
+    double kp0m[12], kp0x[10], kp1m[11], kp1x[9]; /* the z > 6 piece split at z = 20 */
+    double kq0[15][13], kq1[15][13];               /* the fine pieces (KQ0_k, KQ1_k), zero padded */
     double kqb[15];                                /* their constant v offsets (-2 - ulo - uhi)/(uhi - ulo) */
     double stk[6][14]; /* stresslet smooth parts T1S, T2S, T3S, T1L, T2L, T3L in q = z^2/4 <= 1 */
 };
@@ -131,7 +146,7 @@ constexpr FarTable make_far_table()
     for (int i = 0; i < 16; ++i) t.kp0f[i] = KP0F[i];
     for (int i = 0; i < 15; ++i) t.kp1n[i] = KP1N[i];
     for (int i = 0; i < 14; ++i) t.kp1f[i] = KP1F[i];
-    for (int i = 0; i < 13; ++i) t.kp0m[i] = KP0M[i];
+    for (int i = 0; i < 12; ++i) t.kp0m[i] = KP0M[i];
     for (int i = 0; i < 10; ++i) t.kp0x[i] = KP0X[i];
     for (int i = 0; i < 11; ++i) t.kp1m[i] = KP1M[i];
     for (int i = 0; i < 9; ++i) t.kp1x[i] = KP1X[i];
@@ -247,7 +262,7 @@ __device__ __forceinline__ double lean_log01(FarTab T, double q)
      z <= 2: K1 = I0/z + (z/4) log(q) I0'(q) - (z/2) R0'(q), q = z^2/4.
    Max rel. error of the z > 2 pieces 1.2e-16 for K0 and K1 (40-digit check).
    The K1R form (the potentials' tiles) splits the z > 6 piece again at
-   z = 20 (degree 12 / 9 for K0, 10 / 8 for K1; 1.7e-16), which shortens the
+   z = 20 (degree 11 / 9 for K0, 10 / 8 for K1; 1.7e-16), which shortens the
    polynomials of the far pairs, and takes K1 from its own fits with both
    layers too: two independent chains of N0 + N1 - 2 FMA against 2 N0 - 3 and
    a combining step for K1 from the K0 fit's derivative.
@@ -296,10 +311,10 @@ __device__ __forceinline__ double far_piece3(FarTab T, const FarConst &c, double
     const double v = P == 0 ? fma(c.vn, ri, -2.0) : P == 1 ? fma(c.vm, ri, c.om) : fma(c.vx, ri, -1.0);
     if (SLP && DLP) {
         p1 = P == 0 ? hornerc<15>(T->kp1n, v) : P == 1 ? hornerc<11>(T->kp1m, v) : hornerc<9>(T->kp1x, v);
-        return P == 0 ? hornerc<17>(T->kp0n, v) : P == 1 ? hornerc<13>(T->kp0m, v) : hornerc<10>(T->kp0x, v);
+        return P == 0 ? hornerc<17>(T->kp0n, v) : P == 1 ? hornerc<12>(T->kp0m, v) : hornerc<10>(T->kp0x, v);
     }
     p1 = 0.0;
-    if (SLP) return P == 0 ? hornerc<17>(T->kp0n, v) : P == 1 ? hornerc<13>(T->kp0m, v) : hornerc<10>(T->kp0x, v);
+    if (SLP) return P == 0 ? hornerc<17>(T->kp0n, v) : P == 1 ? hornerc<12>(T->kp0m, v) : hornerc<10>(T->kp0x, v);
     return P == 0 ? hornerc<15>(T->kp1n, v) : P == 1 ? hornerc<11>(T->kp1m, v) : hornerc<9>(T->kp1x, v);
 }
 
