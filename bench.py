@@ -39,36 +39,36 @@ FP64_PEAK_TFLOPS = 78.6        # MI355X vector FP64 (published)
 # masked off in divergent code are counted, but the kernel classifies whole
 # waves against each panel, so few are):
 # profiles/far_eval_fp64_starfish4096_grid512_valu_f64.txt.  The pairs take
-# the fitted piece of their z: at alpha = 500 nearly all z > 100 (K0 with its
-# derivative to degree 6), at alpha = 5 z of 2..14 (degrees 9-12, the z <= 2
-# series for the nearest).  Static count of the z > 100 loop: 33 v_fma (x2),
-# 15 v_mul, 3 v_add, 2 v_rsq = 86 per pair (e^{-z} by a table of 2^(-j/32)
-# and a 7-term polynomial).
-FLOP_PER_PAIR_FP64 = {5.0: 112.7, 50.0: 90.1, 500.0: 86.6}
+# the fitted piece of their z, K0 and K1 each from a fit of its own: at
+# alpha = 500 nearly all z > 100 (degree 6 each; the counters read 32.2 v_fma
+# (x2), 13.1 v_mul, 3.0 v_add, 2.0 v_rsq = 82.5 per pair), at alpha = 5 z of
+# 2..14 (degrees 7-12, the z <= 2 series for the nearest); e^{-z} by a table
+# of 2^(-j/32) and a 7-term polynomial.
+FLOP_PER_PAIR_FP64 = {5.0: 103.7, 50.0: 85.4, 500.0: 82.5}
 # VALU instructions per pair (all types, same counters), and the issue rate
 # they are bound by: 256 CUs x 2.4 GHz, one 64-lane VALU instruction per CU
 # per clock
-VALU_PER_PAIR_FP64 = {5.0: 78.0, 50.0: 64.2, 500.0: 62.2}
+VALU_PER_PAIR_FP64 = {5.0: 74.1, 50.0: 62.1, 500.0: 60.1}
 VALU_ISSUE_PER_S = 256 * 2.4e9 * 64
 # the gradient kernel (grad S and grad D of the same densities) evaluates K0
 # and K1(z)/r per pair as the potentials' tiles do (alpha carried by the staged
 # densities; e^{-z} by a table of 2^(-j/32) and a 7-term polynomial), then
-# 1/r^2, (x-y).d, (alpha K0 + 2 K1/r)/r^2 and the four accumulations: counted
-# from the built kernel's loop, 44 v_fma (x2), 20 v_mul, 4 v_add, 2 v_rsq =
-# 114 per pair on the z > 20 piece (counters 114.5 at alpha = 500)
-FLOP_PER_PAIR_GRAD = 114
+# 1/r^2, (x-y).d, (alpha K0 + 2 K1/r)/r^2 and the four accumulations: at
+# alpha = 500, where nearly every pair is on the z > 20 piece, the counters
+# read 42.2 v_fma (x2), 18.1 v_mul, 4.0 v_add, 2.0 v_rsq = 108.5 per pair
+FLOP_PER_PAIR_GRAD = 108
 # modified-Stokes double layer (2x2 stresslet per pair): K0 and K1(z)/r from
 # the three-piece fits, alpha K1/r, 1/r^2, the closed forms of alpha^2 T1,
 # alpha^4 T2, alpha^2 T3 (App. B) and the contraction D_ij w mu_j into two
-# accumulators: counted from the built kernel's loop on the z > 20 piece, 53
-# v_fma (x2), 37 v_mul, 6 v_add, 2 v_rsq = 151 (counters 151.6 at alpha = 500)
-FLOP_PER_PAIR_STOKES = 151
+# accumulators: at alpha = 500 (the z > 20 piece) the counters read 51.2 v_fma
+# (x2), 35.1 v_mul, 6.0 v_add, 2.0 v_rsq = 145.6 per pair
+FLOP_PER_PAIR_STOKES = 145
 # target gradient of the stresslet double layer (velocity gradient, 4 outputs):
 # the same K0, K1(z)/r, 1/r^2 and A_k, B_k = A_k'(r)/r from K0 and A_k, and the
-# contraction d_l D_ij w mu_j into four accumulators: counted from the built
-# kernel's loop on the z > 20 piece, 70 v_fma (x2), 53 v_mul, 11 v_add,
-# 2 v_rsq = 206 (counters 206.8 at alpha = 500)
-FLOP_PER_PAIR_STOKES_GRAD = 206
+# contraction d_l D_ij w mu_j into four accumulators: at alpha = 500 (the
+# z > 20 piece) the counters read 68.3 v_fma (x2), 51.2 v_mul, 11.0 v_add,
+# 2.0 v_rsq = 200.7 per pair
+FLOP_PER_PAIR_STOKES_GRAD = 200
 # launch shapes (far-field source splits) chosen by the autotuner on MI355X for
 # the plans of this benchmark
 TUNED_SPLITS = os.path.join(ROOT, "paper_1908_07392_amd", "tuning", "mi355x_far_splits.json")
@@ -77,7 +77,7 @@ TUNED_SPLITS = os.path.join(ROOT, "paper_1908_07392_amd", "tuning", "mi355x_far_
 # 256 MiB copy), averaged over the three alphas, for the current kernels and
 # launch shape (one stream launch of 4 x the resident blocks, numbered XCD by
 # XCD) (profiles/far_eval_fp64_starfish4096_grid512_hbm_bytes.txt)
-PROFILED_TRAFFIC = 49040000
+PROFILED_TRAFFIC = 49100000
 
 
 def parse():
