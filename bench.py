@@ -43,7 +43,7 @@ FP64_PEAK_TFLOPS = 78.6        # MI355X vector FP64 (published)
 # alpha = 500 nearly all z > 100 (degree 6 each; the counters read 32.2 v_fma
 # (x2), 13.1 v_mul, 3.0 v_add, 2.0 v_rsq = 82.5 per pair), at alpha = 5 z of
 # 2..14 (degrees 7-12, the z <= 2 series for the nearest); e^{-z} by a table
-# of 2^(-j/32) and a 7-term polynomial.
+# of 2^(-j/64) and a 6-term polynomial.
 FLOP_PER_PAIR_FP64 = {5.0: 103.7, 50.0: 85.4, 500.0: 82.5}
 # VALU instructions per pair (all types, same counters), and the issue rate
 # they are bound by: 256 CUs x 2.4 GHz, one 64-lane VALU instruction per CU
@@ -52,7 +52,7 @@ VALU_PER_PAIR_FP64 = {5.0: 74.1, 50.0: 62.1, 500.0: 60.1}
 VALU_ISSUE_PER_S = 256 * 2.4e9 * 64
 # the gradient kernel (grad S and grad D of the same densities) evaluates K0
 # and K1(z)/r per pair as the potentials' tiles do (alpha carried by the staged
-# densities; e^{-z} by a table of 2^(-j/32) and a 7-term polynomial), then
+# densities; e^{-z} by a table of 2^(-j/64) and a 6-term polynomial), then
 # 1/r^2, (x-y).d, (alpha K0 + 2 K1/r)/r^2 and the four accumulations: at
 # alpha = 500, where nearly every pair is on the z > 20 piece, the counters
 # read 42.2 v_fma (x2), 18.1 v_mul, 4.0 v_add, 2.0 v_rsq = 108.5 per pair

@@ -314,10 +314,10 @@ def main():
         report.append((nm, check_abs(c, f), 0.0))
         out.append(f"/* {nm}(q), q = z^2/4 in [0, 1]: smooth part of the stresslet function (max-abs fit) */")
         out.append(fmt(nm, c))
-    # 2^(-j/32), j = 0..31, correctly rounded: the table of the exponential's
-    # reduction by ln2/32 (Tang's table-driven method)
-    out.append("/* 2^(-j/32), j = 0..31 (correctly rounded) */")
-    out.append(fmt("EXP2_NJ", [mp.mpf(2) ** (-mp.mpf(j) / 32) for j in range(32)]))
+    # 2^(-j/64), j = 0..63, correctly rounded: the table of the exponential's
+    # reduction by ln2/64 (Tang's table-driven method)
+    out.append("/* 2^(-j/64), j = 0..63 (correctly rounded) */")
+    out.append(fmt("EXP2_NJ", [mp.mpf(2) ** (-mp.mpf(j) / 64) for j in range(64)]))
     with open(os.path.join(HERE, "constants.h"), "w") as fh:
         fh.write("\n".join(out) + "\n")
     for r in report:

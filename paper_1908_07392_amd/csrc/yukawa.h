@@ -79,9 +79,9 @@ __host__ __device__ __forceinline__ K01 k01_fp64(double r2, double a, double a2q
 /* Same regimes and coefficients as k01_fp64 with lean elementary functions: */
 /*  * 1/sqrt and 1/x: hardware v_rsq_f64 / v_rcp_f64 estimates refined by    */
 /*    one Newton-type step (third order for rsq, two steps for rcp);         */
-/*  * e^{-z}, z >= 0: Cody-Waite reduction z = k ln2/32 - r, |r| <= ln2/64, */
-/*    a table of 2^{-j/32} (Tang's table-driven method), degree-6 Taylor     */
-/*    polynomial (truncation 4e-18), scaling by 2^-(k/32) (ldexp);           */
+/*  * e^{-z}, z >= 0: Cody-Waite reduction z = k ln2/64 - r, |r| <= ln2/128,*/
+/*    a table of 2^{-j/64} (Tang's table-driven method), degree-5 Taylor     */
+/*    polynomial (truncation 4e-17), scaling by 2^-(k/64) (ldexp);           */
 /*  * log q, 0 < q <= 1: q = m 2^e with m in [sqrt(1/2), sqrt(2)),           */
 /*    log m = 2 atanh(s), s = (m-1)/(m+1), |s| <= 0.1716, series to s^21.     */
 /* ---------------------------------------------------------------------- */
@@ -89,10 +89,8 @@ constexpr double LN2_HI = 6.93147180369123816490e-01; /* ln 2 split: hi has 32 b
 constexpr double LN2_LO = 1.90821492927058770002e-10;
 constexpr double LOG2E = 1.44269504088896338700e+00;
 constexpr double SQRT_HALF = 0.707106781186547524401;
-/* 1/k!, k = 0..13 */
-static constexpr double EXP_T[14] = {1.0, 1.0, 0.5, 1.0 / 6.0, 1.0 / 24.0, 1.0 / 120.0, 1.0 / 720.0, 1.0 / 5040.0,
-                                     1.0 / 40320.0, 1.0 / 362880.0, 1.0 / 3628800.0, 1.0 / 39916800.0,
-                                     1.0 / 479001600.0, 1.0 / 6227020800.0};
+/* 1/k!, k = 0..5 */
+static constexpr double EXP_T[6] = {1.0, 1.0, 0.5, 1.0 / 6.0, 1.0 / 24.0, 1.0 / 120.0};
 /* 1/(2k+1), k = 0..10 */
 static constexpr double ATANH_T[11] = {1.0, 1.0 / 3.0, 1.0 / 5.0, 1.0 / 7.0, 1.0 / 9.0, 1.0 / 11.0,
                                        1.0 / 13.0, 1.0 / 15.0, 1.0 / 17.0, 1.0 / 19.0, 1.0 / 21.0};
@@ -129,9 +127,9 @@ static_assert(sizeof(KP0M) == 12 * sizeof(double) && sizeof(KP0X) == 10 * sizeof
                   sizeof(KP1M) == 11 * sizeof(double) && sizeof(KP1X) == 9 * sizeof(double),
               "middle and far piece lengths differ from the generated tables");
 struct FarTable {
-    double kp0n[17], kp0f[16], kp1n[15], kp1f[14], kl0[23], expt[14], atanh[11], ks_i0[12], ks_r0[13], ks_i1z[12],
+    double kp0n[17], kp0f[16], kp1n[15], kp1f[14], kl0[23], expt[6], atanh[11], ks_i0[12], ks_r0[13], ks_i1z[12],
         ks_r1[13];
-    double exp2nj[32]; /* 2^(-j/32) */
+    double exp2nj[64]; /* 2^(-j/64) */
     double kp0m[12], kp0x[10], kp1m[11], kp1x[9]; /* the z > 6 piece split at z = 20 */
     double kq0[15][13], kq1[15][13];               /* the fine pieces (KQ0_k, KQ1_k), zero padded */
     double kqb[15];                                /* their constant v offsets (-2 - ulo - uhi)/(uhi - ulo) */
@@ -159,8 +157,8 @@ constexpr FarTable make_far_table()
         for (int i = 0; i < KQ_N1[k]; ++i) t.kq1[k][i] = q1[k][i];
         t.kqb[k] = (-2.0 - KQ_ULO[k] - KQ_UHI[k]) / (KQ_UHI[k] - KQ_ULO[k]);
     }
-    for (int i = 0; i < 14; ++i) t.expt[i] = EXP_T[i];
-    for (int i = 0; i < 32; ++i) t.exp2nj[i] = EXP2_NJ[i];
+    for (int i = 0; i < 6; ++i) t.expt[i] = EXP_T[i];
+    for (int i = 0; i < 64; ++i) t.exp2nj[i] = EXP2_NJ[i];
     for (int i = 0; i < 11; ++i) t.atanh[i] = ATANH_T[i];
     for (int i = 0; i < 12; ++i) t.ks_i0[i] = KS_I0[i], t.ks_i1z[i] = KS_I1Z[i];
     for (int i = 0; i < 13; ++i) t.ks_r0[i] = KS_R0[i], t.ks_r1[i] = KS_R1[i];
@@ -223,22 +221,23 @@ __device__ __forceinline__ double lean_rcp(double x)
     return fma(y, e, y);
 }
 
-/* e^{-z} for z >= 0: k = round(32 z log2 e), r = k ln2/32 - z with
-   |r| <= ln2/64 (+ rounding), e^{-z} = 2^{-(k >> 5)} 2^{-(k & 31)/32} e^r
+/* e^{-z} for z >= 0: k = round(64 z log2 e), r = k ln2/64 - z with
+   |r| <= ln2/128 (+ rounding), e^{-z} = 2^{-(k >> 6)} 2^{-(k & 63)/64} e^r
    (Tang's table-driven reduction: the table entry is a per-lane load, and the
-   polynomial is 7 terms instead of 14).  k comes from adding 1.5 * 2^52,
-   whose low word then holds it as an integer; k ln2/32 is exact in its high
-   part (LN2_HI has 21 trailing zero bits, k < 2^21 for z < 3e4, and e^{-z}
+   Taylor polynomial of e^r needs 6 terms, truncation below 4e-17 relative;
+   the reduction by ln 2 alone needs 14).  k comes from adding 1.5 * 2^52,
+   whose low word then holds it as an integer; k ln2/64 is exact in its high
+   part (LN2_HI has 21 trailing zero bits, k < 2^21 for z < 2e4, and e^{-z}
    underflows to zero long before). */
 __device__ __forceinline__ double lean_exp_neg(FarTab T, double z)
 {
     constexpr double SHIFT = 6755399441055744.0; /* 1.5 * 2^52 */
-    const double t = fma(z, 32.0 * LOG2E, SHIFT);
+    const double t = fma(z, 64.0 * LOG2E, SHIFT);
     const double kd = t - SHIFT;
-    double r = fma(kd, LN2_HI / 32.0, -z);
-    r = fma(kd, LN2_LO / 32.0, r);
+    double r = fma(kd, LN2_HI / 64.0, -z);
+    r = fma(kd, LN2_LO / 64.0, r);
     const int k = __double2loint(t);
-    return ldexp(T->exp2nj[k & 31] * hornerc<7>(T->expt, r), -(k >> 5));
+    return ldexp(T->exp2nj[k & 63] * hornerc<6>(T->expt, r), -(k >> 6));
 }
 
 __device__ __forceinline__ double lean_log01(FarTab T, double q)
