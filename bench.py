@@ -40,35 +40,35 @@ FP64_PEAK_TFLOPS = 78.6        # MI355X vector FP64 (published)
 # waves against each panel, so few are):
 # profiles/far_eval_fp64_starfish4096_grid512_valu_f64.txt.  The pairs take
 # the fitted piece of their z, K0 and K1 each from a fit of its own: at
-# alpha = 500 nearly all z > 100 (degree 6 each; the counters read 32.2 v_fma
-# (x2), 13.1 v_mul, 3.0 v_add, 2.0 v_rsq = 82.5 per pair), at alpha = 5 z of
+# alpha = 500 nearly all z > 100 (degree 6 each; the counters read 31.2 v_fma
+# (x2), 13.1 v_mul, 3.0 v_add, 2.0 v_rsq = 80.5 per pair), at alpha = 5 z of
 # 2..14 (degrees 7-12, the z <= 2 series for the nearest); e^{-z} by a table
 # of 2^(-j/64) and a 6-term polynomial.
-FLOP_PER_PAIR_FP64 = {5.0: 103.7, 50.0: 85.4, 500.0: 82.5}
+FLOP_PER_PAIR_FP64 = {5.0: 101.8, 50.0: 83.4, 500.0: 80.5}
 # VALU instructions per pair (all types, same counters), and the issue rate
 # they are bound by: 256 CUs x 2.4 GHz, one 64-lane VALU instruction per CU
 # per clock
-VALU_PER_PAIR_FP64 = {5.0: 74.1, 50.0: 62.1, 500.0: 60.1}
+VALU_PER_PAIR_FP64 = {5.0: 73.0, 50.0: 61.1, 500.0: 59.1}
 VALU_ISSUE_PER_S = 256 * 2.4e9 * 64
 # the gradient kernel (grad S and grad D of the same densities) evaluates K0
 # and K1(z)/r per pair as the potentials' tiles do (alpha carried by the staged
 # densities; e^{-z} by a table of 2^(-j/64) and a 6-term polynomial), then
 # 1/r^2, (x-y).d, (alpha K0 + 2 K1/r)/r^2 and the four accumulations: at
 # alpha = 500, where nearly every pair is on the z > 20 piece, the counters
-# read 42.2 v_fma (x2), 18.1 v_mul, 4.0 v_add, 2.0 v_rsq = 108.5 per pair
-FLOP_PER_PAIR_GRAD = 108
+# read 41.2 v_fma (x2), 18.1 v_mul, 4.0 v_add, 2.0 v_rsq = 106.5 per pair
+FLOP_PER_PAIR_GRAD = 106
 # modified-Stokes double layer (2x2 stresslet per pair): K0 and K1(z)/r from
 # the three-piece fits, alpha K1/r, 1/r^2, the closed forms of alpha^2 T1,
 # alpha^4 T2, alpha^2 T3 (App. B) and the contraction D_ij w mu_j into two
-# accumulators: at alpha = 500 (the z > 20 piece) the counters read 51.2 v_fma
-# (x2), 35.1 v_mul, 6.0 v_add, 2.0 v_rsq = 145.6 per pair
-FLOP_PER_PAIR_STOKES = 145
+# accumulators: at alpha = 500 (the z > 20 piece) the counters read 50.2 v_fma
+# (x2), 35.1 v_mul, 6.0 v_add, 2.0 v_rsq = 143.6 per pair
+FLOP_PER_PAIR_STOKES = 143
 # target gradient of the stresslet double layer (velocity gradient, 4 outputs):
 # the same K0, K1(z)/r, 1/r^2 and A_k, B_k = A_k'(r)/r from K0 and A_k, and the
 # contraction d_l D_ij w mu_j into four accumulators: at alpha = 500 (the
-# z > 20 piece) the counters read 68.3 v_fma (x2), 51.2 v_mul, 11.0 v_add,
-# 2.0 v_rsq = 200.7 per pair
-FLOP_PER_PAIR_STOKES_GRAD = 200
+# z > 20 piece) the counters read 67.3 v_fma (x2), 51.2 v_mul, 11.0 v_add,
+# 2.0 v_rsq = 198.7 per pair
+FLOP_PER_PAIR_STOKES_GRAD = 198
 # launch shapes (far-field source splits) chosen by the autotuner on MI355X for
 # the plans of this benchmark
 TUNED_SPLITS = os.path.join(ROOT, "paper_1908_07392_amd", "tuning", "mi355x_far_splits.json")
