@@ -1337,6 +1337,8 @@ struct GradArgs {
     int32_t pps;
     double *part;      /* [4][nsplit][M] when split */
     double *out[4];    /* d/dx1 S, d/dx2 S, d/dx1 D, d/dx2 D (caller order) */
+    const uint8_t *wcls; /* the plan's (wave, panel) fine-piece classes */
+    const double *fq;    /* the fine pieces' scales at the plan's alpha */
 };
 
 template <bool GS, bool GD>
@@ -1383,23 +1385,66 @@ __global__ void grad_finalize(GradArgs A, int nsplit)
     grad_epilogue<GS, GD>(A, i, acc);
 }
 
+/* the 16 sources of one LDS panel (offset l0) against the lane's target for
+   the gradients: PC the fine piece of the plan's class table (-1: z <= 2;
+   KQ_NP: per-pair selection over the three-piece fits) */
+template <bool GS, bool GD, int PC>
+__device__ __forceinline__ void grad_panel_fp64(const GradArgs &A, const FarConst &fc, double x, double y,
+                                                const double *lx, const double *ly, const double *lq,
+                                                const double *ldx, const double *ldy, int l0, double &sx,
+                                                double &sy, double &dx, double &dy)
+{
+    constexpr int K = PC < 0 || PC >= KQ_NP ? 0 : PC;
+    const FarTab T = far_table();
+    double qa, qk;
+    fine_q<K>(A.fq, qa, qk);
+#pragma unroll 1
+    for (int s = 0; s < 16; s += 2) {
+        const int l0s = l0 + s, l1 = l0s + 1;
+        const double ex0 = x - lx[l0s], ey0 = y - ly[l0s];
+        const double ex1 = x - lx[l1], ey1 = y - ly[l1];
+        const double r20 = fma(ex0, ex0, ey0 * ey0), r21 = fma(ex1, ex1, ey1 * ey1);
+        K01 o0, o1; /* ak1r holds K1(z)/r; the staged densities carry alpha */
+        if constexpr (PC >= KQ_NP)
+            k01_far2<GD, true, true, true>(T, fc, r20, r21, o0, o1);
+        else
+            k01_far2_fixed<GD, true, PC>(T, fc, qa, qk, r20, r21, o0, o1);
+        if (GS) {
+            const double c0 = o0.ak1r * lq[l0s], c1 = o1.ak1r * lq[l1];
+            sx = fma(c1, ex1, fma(c0, ex0, sx));
+            sy = fma(c1, ey1, fma(c0, ey0, sy));
+        }
+        if (GD) {
+            /* (alpha^2 K0 + 2 alpha K1/r) (x-y).d / r^2, alpha from the dipole */
+            const double n0 = fma(ex0, ldx[l0s], ey0 * ldy[l0s]), n1 = fma(ex1, ldx[l1], ey1 * ldy[l1]);
+            const double b0 = n0 * fma(A.alpha, o0.k0, 2.0 * o0.ak1r) * o0.ri2;
+            const double b1 = n1 * fma(A.alpha, o1.k0, 2.0 * o1.ak1r) * o1.ri2;
+            dx = fma(-b1, ex1, fma(o1.ak1r, ldx[l1], fma(-b0, ex0, fma(o0.ak1r, ldx[l0s], dx))));
+            dy = fma(-b1, ey1, fma(o1.ak1r, ldy[l1], fma(-b0, ey0, fma(o0.ak1r, ldy[l0s], dy))));
+        }
+    }
+}
+
+/* Each panel takes the fine piece of the plan's (wave, panel) class table, the
+   one the fused evaluation uses (targets in the same order, waves of 64);
+   lanes past the last target repeat it, as the table assumes. */
 template <bool GS, bool GD, bool SPLIT>
 __global__ __launch_bounds__(FT_THREADS) void far_grad_fp64(GradArgs A)
 {
     __shared__ double lx[FT_SRC], ly[FT_SRC], lq[FT_SRC], ldx[FT_SRC], ldy[FT_SRC];
     const int64_t i = blockIdx.x * (int64_t)FT_THREADS + threadIdx.x;
     const bool valid = i < A.M;
-    const double x = valid ? A.tx[i] : 0.0, y = valid ? A.ty[i] : 0.0;
+    const int64_t iv = valid ? i : A.M - 1;
+    const double x = A.tx[iv], y = A.ty[iv];
     const int64_t pb = SPLIT ? (int64_t)blockIdx.y * A.pps : 0;
     const int64_t pe = SPLIT ? min(A.Np, pb + A.pps) : A.Np;
-    int32_t k = 0, kend = 0;
-    if (valid) {
-        k = A.nptr[i];
-        kend = A.nptr[i + 1];
-        while (k < kend && A.npan[k] >= 0 && A.npan[k] < pb) ++k;
-    }
+    int32_t k = A.nptr[iv];
+    const int32_t kend = A.nptr[iv + 1];
+    while (k < kend && A.npan[k] >= 0 && A.npan[k] < pb) ++k;
     int32_t nxt = (k < kend) ? A.npan[k] : INT_MAX;
     const FarConst fc = far_const(A.alpha);
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint8_t *cls = A.wcls ? A.wcls + ((int64_t)blockIdx.x * (FT_THREADS / 64) + wv) * A.Np : nullptr;
     double sx = 0.0, sy = 0.0, dx = 0.0, dy = 0.0;
     for (int64_t base = 16 * pb; base < 16 * pe; base += FT_SRC) {
         __syncthreads();
@@ -1425,28 +1470,32 @@ __global__ __launch_bounds__(FT_THREADS) void far_grad_fp64(GradArgs A)
                 nxt = (k < kend) ? A.npan[k] : INT_MAX;
                 continue;
             }
-#pragma unroll 1
-            for (int s = 0; s < 16; s += 2) {
-                const FarTab T = far_table();
-                const int l0 = pl * 16 + s, l1 = l0 + 1;
-                const double ex0 = x - lx[l0], ey0 = y - ly[l0];
-                const double ex1 = x - lx[l1], ey1 = y - ly[l1];
-                const double r20 = fma(ex0, ex0, ey0 * ey0), r21 = fma(ex1, ex1, ey1 * ey1);
-                K01 o0, o1; /* ak1r holds K1(z)/r; the staged densities carry alpha */
-                k01_far2<GD, true, true, true>(T, fc, r20, r21, o0, o1);
-                if (GS) {
-                    const double c0 = o0.ak1r * lq[l0], c1 = o1.ak1r * lq[l1];
-                    sx = fma(c1, ex1, fma(c0, ex0, sx));
-                    sy = fma(c1, ey1, fma(c0, ey0, sy));
-                }
-                if (GD) {
-                    /* (alpha^2 K0 + 2 alpha K1/r) (x-y).d / r^2, alpha from the dipole */
-                    const double n0 = fma(ex0, ldx[l0], ey0 * ldy[l0]), n1 = fma(ex1, ldx[l1], ey1 * ldy[l1]);
-                    const double b0 = n0 * fma(A.alpha, o0.k0, 2.0 * o0.ak1r) * o0.ri2;
-                    const double b1 = n1 * fma(A.alpha, o1.k0, 2.0 * o1.ak1r) * o1.ri2;
-                    dx = fma(-b1, ex1, fma(o1.ak1r, ldx[l1], fma(-b0, ex0, fma(o0.ak1r, ldx[l0], dx))));
-                    dy = fma(-b1, ey1, fma(o1.ak1r, ldy[l1], fma(-b0, ey0, fma(o0.ak1r, ldy[l0], dy))));
-                }
+            const int pc = cls ? (cls[p0 + pl] & 0x7f) - 1 : KQ_NP;
+            const int l0 = pl * 16;
+            switch (pc) {
+#define MHLP_GRAD_PANEL(PCV)                                                                              \
+    case PCV:                                                                                              \
+        grad_panel_fp64<GS, GD, PCV>(A, fc, x, y, lx, ly, lq, ldx, ldy, l0, sx, sy, dx, dy);               \
+        break;
+                MHLP_GRAD_PANEL(-1)
+                MHLP_GRAD_PANEL(0)
+                MHLP_GRAD_PANEL(1)
+                MHLP_GRAD_PANEL(2)
+                MHLP_GRAD_PANEL(3)
+                MHLP_GRAD_PANEL(4)
+                MHLP_GRAD_PANEL(5)
+                MHLP_GRAD_PANEL(6)
+                MHLP_GRAD_PANEL(7)
+                MHLP_GRAD_PANEL(8)
+                MHLP_GRAD_PANEL(9)
+                MHLP_GRAD_PANEL(10)
+                MHLP_GRAD_PANEL(11)
+                MHLP_GRAD_PANEL(12)
+                MHLP_GRAD_PANEL(13)
+                MHLP_GRAD_PANEL(14)
+#undef MHLP_GRAD_PANEL
+            default:
+                grad_panel_fp64<GS, GD, KQ_NP>(A, fc, x, y, lx, ly, lq, ldx, ldy, l0, sx, sy, dx, dy);
             }
         }
     }
@@ -3807,6 +3856,8 @@ extern "C" mhlp_status mhlp_eval_grad(const mhlp_plan *Pc, const double *sigma, 
     A.alpha = P->alpha;
     A.pps = P->pps;
     A.part = P->part;
+    A.wcls = P->wcls;
+    A.fq = P->fqd;
     A.out[0] = gs_x;
     A.out[1] = gs_y;
     A.out[2] = gd_x;
