@@ -1337,8 +1337,8 @@ struct GradArgs {
     int32_t pps;
     double *part;      /* [4][nsplit][M] when split */
     double *out[4];    /* d/dx1 S, d/dx2 S, d/dx1 D, d/dx2 D (caller order) */
-    const uint8_t *wcls; /* the plan's (wave, panel) fine-piece classes */
-    const double *fq;    /* the fine pieces' scales at the plan's alpha */
+    const uint8_t *wcls = nullptr; /* the plan's (wave, panel) fine-piece classes, if any */
+    const double *fq = nullptr;    /* the fine pieces' scales at the plan's alpha */
 };
 
 template <bool GS, bool GD>
@@ -1536,6 +1536,8 @@ struct StkArgs {
     const double *flux; /* sum_j w_j mu_j.n_j / |Gamma| (bie) */
     const GState *gs;
     int64_t jstride;
+    const uint8_t *wcls = nullptr; /* the plan's (wave, panel) fine-piece classes, if any */
+    const double *fq = nullptr;    /* the fine pieces' scales at the plan's alpha */
 };
 
 __device__ __forceinline__ bool stk_density(const StkArgs &A, const double *&mu)
@@ -1651,6 +1653,46 @@ __global__ __launch_bounds__(256) void stk_flux_kernel(StkArgs A, double inv_len
     if (threadIdx.x == 0) flux[0] = red[0] * inv_len;
 }
 
+/* the classes -1 .. KQ_NP - 1 of the plan's (wave, panel) table, for a switch */
+#define MHLP_PC_CASES(X) X(-1) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14)
+static_assert(KQ_NP == 15, "MHLP_PC_CASES lists the fine pieces");
+
+/* the 16 sources of one LDS panel (offset l0) against the lane's target for
+   the stresslet double layer, in piece PC of the class table */
+template <int PC>
+__device__ __forceinline__ void stk_panel_fp64(const double *fq, const FarConst &fc, double al2, double ial2, double x,
+                                               double y, const double *lx, const double *ly, const double *lm1,
+                                               const double *lm2, const double *lnx, const double *lny, int l0,
+                                               double &a1, double &a2)
+{
+    constexpr int K = PC < 0 || PC >= KQ_NP ? 0 : PC;
+    const FarTab T = far_table();
+    double qa, qk;
+    fine_q<K>(fq, qa, qk);
+#pragma unroll 1
+    for (int s = 0; s < 16; s += 2) {
+        const int l0s = l0 + s;
+        const double ex0 = x - lx[l0s], ey0 = y - ly[l0s];
+        const double ex1 = x - lx[l0s + 1], ey1 = y - ly[l0s + 1];
+        const double r20 = fma(ex0, ex0, ey0 * ey0), r21 = fma(ex1, ex1, ey1 * ey1);
+        double Ak2[2][3];
+        stk_far2_pc<PC>(T, fc, qa, qk, al2, ial2, r20, r21, Ak2[0], Ak2[1]);
+        const double ex[2] = {ex0, ex1}, ey[2] = {ey0, ey1};
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int l = l0s + u;
+            const double *Ak = Ak2[u];
+            const double nx = lnx[l], ny = lny[l], m1 = lm1[l], m2 = lm2[l];
+            const double rn = fma(ex[u], nx, ey[u] * ny);
+            const double rm = fma(ex[u], m1, ey[u] * m2);
+            const double nm = fma(nx, m1, ny * m2);
+            const double c = fma(Ak[1] * rm, rn, Ak[2] * nm);
+            a1 -= fma(Ak[0], fma(nx, rm, fma(ex[u], nm, m1 * rn)), c * ex[u]);
+            a2 -= fma(Ak[0], fma(ny, rm, fma(ey[u], nm, m2 * rn)), c * ey[u]);
+        }
+    }
+}
+
 template <bool SPLIT>
 __global__ __launch_bounds__(FT_THREADS) void far_stokes_fp64(StkArgs A)
 {
@@ -1659,18 +1701,18 @@ __global__ __launch_bounds__(FT_THREADS) void far_stokes_fp64(StkArgs A)
     if (!stk_density(A, mu)) return;
     const int64_t i = blockIdx.x * (int64_t)FT_THREADS + threadIdx.x;
     const bool valid = i < A.M;
-    const double x = valid ? A.tx[i] : 0.0, y = valid ? A.ty[i] : 0.0;
+    const int64_t iv = valid ? i : A.M - 1; /* lanes past the last target repeat it */
+    const double x = A.tx[iv], y = A.ty[iv];
     const int64_t pb = SPLIT ? (int64_t)blockIdx.y * A.pps : 0;
     const int64_t pe = SPLIT ? min(A.Np, pb + A.pps) : A.Np;
-    int32_t k = 0, kend = 0;
-    if (valid) {
-        k = A.nptr[i];
-        kend = A.nptr[i + 1];
-        while (k < kend && A.npan[k] >= 0 && A.npan[k] < pb) ++k;
-    }
+    int32_t k = A.nptr[iv];
+    const int32_t kend = A.nptr[iv + 1];
+    while (k < kend && A.npan[k] >= 0 && A.npan[k] < pb) ++k;
     int32_t nxt = (k < kend) ? A.npan[k] : INT_MAX;
     const FarConst fc = far_const(A.alpha);
     const double al2 = A.alpha * A.alpha, ial2 = fc.ia * fc.ia;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint8_t *cls = A.wcls ? A.wcls + ((int64_t)blockIdx.x * (FT_THREADS / 64) + wv) * A.Np : nullptr;
     double a1 = 0.0, a2 = 0.0;
     for (int64_t base = 16 * pb; base < 16 * pe; base += FT_SRC) {
         __syncthreads();
@@ -1693,28 +1735,17 @@ __global__ __launch_bounds__(FT_THREADS) void far_stokes_fp64(StkArgs A)
                 nxt = (k < kend) ? A.npan[k] : INT_MAX;
                 continue;
             }
-#pragma unroll 1
-            for (int s = 0; s < 16; s += 2) {
-                const FarTab T = far_table();
-                const int l0 = pl * 16 + s;
-                const double ex0 = x - lx[l0], ey0 = y - ly[l0];
-                const double ex1 = x - lx[l0 + 1], ey1 = y - ly[l0 + 1];
-                const double r20 = fma(ex0, ex0, ey0 * ey0), r21 = fma(ex1, ex1, ey1 * ey1);
-                double Ak2[2][3];
-                stk_far2(T, fc, al2, ial2, r20, r21, Ak2[0], Ak2[1]);
-                const double ex[2] = {ex0, ex1}, ey[2] = {ey0, ey1};
-#pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    const int l = l0 + u;
-                    const double *Ak = Ak2[u];
-                    const double nx = lnx[l], ny = lny[l], m1 = lm1[l], m2 = lm2[l];
-                    const double rn = fma(ex[u], nx, ey[u] * ny);
-                    const double rm = fma(ex[u], m1, ey[u] * m2);
-                    const double nm = fma(nx, m1, ny * m2);
-                    const double c = fma(Ak[1] * rm, rn, Ak[2] * nm);
-                    a1 -= fma(Ak[0], fma(nx, rm, fma(ex[u], nm, m1 * rn)), c * ex[u]);
-                    a2 -= fma(Ak[0], fma(ny, rm, fma(ey[u], nm, m2 * rn)), c * ey[u]);
-                }
+            const int pc = cls ? (cls[p0 + pl] & 0x7f) - 1 : KQ_NP;
+            const int l0 = pl * 16;
+            switch (pc) {
+#define MHLP_STK_PANEL(PCV)                                                                                \
+    case PCV:                                                                                              \
+        stk_panel_fp64<PCV>(A.fq, fc, al2, ial2, x, y, lx, ly, lm1, lm2, lnx, lny, l0, a1, a2);           \
+        break;
+                MHLP_PC_CASES(MHLP_STK_PANEL)
+#undef MHLP_STK_PANEL
+            default:
+                stk_panel_fp64<KQ_NP>(A.fq, fc, al2, ial2, x, y, lx, ly, lm1, lm2, lnx, lny, l0, a1, a2);
             }
         }
     }
@@ -1750,6 +1781,8 @@ struct StkGArgs {
     int32_t pps;
     double *part;     /* [4][nsplit][M] */
     double *g;        /* [4][M] */
+    const uint8_t *wcls = nullptr; /* the plan's (wave, panel) fine-piece classes, if any */
+    const double *fq = nullptr;    /* the fine pieces' scales at the plan's alpha */
 };
 
 __device__ __forceinline__ void stkg_epilogue(const StkGArgs &A, int64_t i, const double *acc)
@@ -1978,24 +2011,68 @@ __global__ __launch_bounds__(FZ_TG *FZ_L) void stk_sym_finalize(StkSymArgs S, in
     A.u[A.ustride + o] = a2;
 }
 
+/* the 16 sources of one LDS panel (offset l0) against the lane's target for
+   the stresslet target gradient, in piece PC of the class table; g: the
+   lane's four accumulators */
+template <int PC>
+__device__ __forceinline__ void stkg_panel_fp64(const double *fq, const FarConst &fc, double al2, double ial2, double x,
+                                                double y, const double *lx, const double *ly, const double *lm1,
+                                                const double *lm2, const double *lnx, const double *lny, int l0,
+                                                double *g)
+{
+    constexpr int K = PC < 0 || PC >= KQ_NP ? 0 : PC;
+    const FarTab T = far_table();
+    double qa, qk;
+    fine_q<K>(fq, qa, qk);
+#pragma unroll 1
+    for (int s = 0; s < 16; s += 2) {
+        const int l0s = l0 + s;
+        const double ex0 = x - lx[l0s], ey0 = y - ly[l0s];
+        const double ex1 = x - lx[l0s + 1], ey1 = y - ly[l0s + 1];
+        const double r20 = fma(ex0, ex0, ey0 * ey0), r21 = fma(ex1, ex1, ey1 * ey1);
+        double Ak[2][3], Bk[2][3];
+        stk_far2_ab_pc<PC>(T, fc, qa, qk, al2, ial2, r20, r21, Ak[0], Bk[0], Ak[1], Bk[1]);
+        const double ex[2] = {ex0, ex1}, ey[2] = {ey0, ey1};
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int l = l0s + u;
+            const double *a = Ak[u], *b = Bk[u];
+            const double nx = lnx[l], ny = lny[l], m1 = lm1[l], m2 = lm2[l];
+            const double rn = fma(ex[u], nx, ey[u] * ny);
+            const double rm = fma(ex[u], m1, ey[u] * m2);
+            const double nm = fma(nx, m1, ny * m2);
+            const double sr = fma(b[1] * rn, rm, (b[0] + b[2]) * nm);
+            const double p1 = fma(b[0], fma(nx, rm, m1 * rn), ex[u] * sr);
+            const double p2 = fma(b[0], fma(ny, rm, m2 * rn), ey[u] * sr);
+            const double a1 = fma(a[0], m1, a[1] * rm * ex[u]), a2 = fma(a[0], m2, a[1] * rm * ey[u]);
+            const double c1 = fma(a[0], nx, a[1] * rn * ex[u]), c2 = fma(a[0], ny, a[1] * rn * ey[u]);
+            const double d = fma(a[0] + a[2], nm, a[1] * rn * rm);
+            g[0] -= fma(ex[u], p1, fma(nx, a1, fma(m1, c1, d)));
+            g[1] -= fma(ey[u], p1, fma(ny, a1, m2 * c1));
+            g[2] -= fma(ex[u], p2, fma(nx, a2, m1 * c2));
+            g[3] -= fma(ey[u], p2, fma(ny, a2, fma(m2, c2, d)));
+        }
+    }
+}
+
 template <bool SPLIT>
 __global__ __launch_bounds__(FT_THREADS) void far_stokes_grad_fp64(StkGArgs A)
 {
     __shared__ double lx[FT_SRC], ly[FT_SRC], lm1[FT_SRC], lm2[FT_SRC], lnx[FT_SRC], lny[FT_SRC];
     const int64_t i = blockIdx.x * (int64_t)FT_THREADS + threadIdx.x;
     const bool valid = i < A.M;
-    const double x = valid ? A.tx[i] : 0.0, y = valid ? A.ty[i] : 0.0;
+    const int64_t iv = valid ? i : A.M - 1; /* lanes past the last target repeat it */
+    const double x = A.tx[iv], y = A.ty[iv];
     const int64_t pb = SPLIT ? (int64_t)blockIdx.y * A.pps : 0;
     const int64_t pe = SPLIT ? min(A.Np, pb + A.pps) : A.Np;
-    int32_t k = 0, kend = 0;
-    if (valid) {
-        k = A.nptr[i];
-        kend = A.nptr[i + 1];
-        while (k < kend && A.npan[k] >= 0 && A.npan[k] < pb) ++k;
-    }
+    int32_t k = A.nptr[iv];
+    const int32_t kend = A.nptr[iv + 1];
+    while (k < kend && A.npan[k] >= 0 && A.npan[k] < pb) ++k;
     int32_t nxt = (k < kend) ? A.npan[k] : INT_MAX;
     const FarConst fc = far_const(A.alpha);
     const double al2 = A.alpha * A.alpha, ial2 = fc.ia * fc.ia;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint8_t *cls = A.wcls ? A.wcls + ((int64_t)blockIdx.x * (FT_THREADS / 64) + wv) * A.Np : nullptr;
     double g11 = 0.0, g12 = 0.0, g21 = 0.0, g22 = 0.0;
     for (int64_t base = 16 * pb; base < 16 * pe; base += FT_SRC) {
         __syncthreads();
@@ -2018,36 +2095,23 @@ __global__ __launch_bounds__(FT_THREADS) void far_stokes_grad_fp64(StkGArgs A)
                 nxt = (k < kend) ? A.npan[k] : INT_MAX;
                 continue;
             }
-#pragma unroll 1
-            for (int s = 0; s < 16; s += 2) {
-                const FarTab T = far_table();
-                const int l0 = pl * 16 + s;
-                const double ex0 = x - lx[l0], ey0 = y - ly[l0];
-                const double ex1 = x - lx[l0 + 1], ey1 = y - ly[l0 + 1];
-                const double r20 = fma(ex0, ex0, ey0 * ey0), r21 = fma(ex1, ex1, ey1 * ey1);
-                double Ak[2][3], Bk[2][3];
-                stk_far2_ab(T, fc, al2, ial2, r20, r21, Ak[0], Bk[0], Ak[1], Bk[1]);
-                const double ex[2] = {ex0, ex1}, ey[2] = {ey0, ey1};
-#pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    const int l = l0 + u;
-                    const double *a = Ak[u], *b = Bk[u];
-                    const double nx = lnx[l], ny = lny[l], m1 = lm1[l], m2 = lm2[l];
-                    const double rn = fma(ex[u], nx, ey[u] * ny);
-                    const double rm = fma(ex[u], m1, ey[u] * m2);
-                    const double nm = fma(nx, m1, ny * m2);
-                    const double sr = fma(b[1] * rn, rm, (b[0] + b[2]) * nm);
-                    const double p1 = fma(b[0], fma(nx, rm, m1 * rn), ex[u] * sr);
-                    const double p2 = fma(b[0], fma(ny, rm, m2 * rn), ey[u] * sr);
-                    const double a1 = fma(a[0], m1, a[1] * rm * ex[u]), a2 = fma(a[0], m2, a[1] * rm * ey[u]);
-                    const double c1 = fma(a[0], nx, a[1] * rn * ex[u]), c2 = fma(a[0], ny, a[1] * rn * ey[u]);
-                    const double d = fma(a[0] + a[2], nm, a[1] * rn * rm);
-                    g11 -= fma(ex[u], p1, fma(nx, a1, fma(m1, c1, d)));
-                    g12 -= fma(ey[u], p1, fma(ny, a1, m2 * c1));
-                    g21 -= fma(ex[u], p2, fma(nx, a2, m1 * c2));
-                    g22 -= fma(ey[u], p2, fma(ny, a2, fma(m2, c2, d)));
-                }
+            const int pc = cls ? (cls[p0 + pl] & 0x7f) - 1 : KQ_NP;
+            const int l0 = pl * 16;
+            double gg[4] = {g11, g12, g21, g22};
+            switch (pc) {
+#define MHLP_STKG_PANEL(PCV)                                                                               \
+    case PCV:                                                                                              \
+        stkg_panel_fp64<PCV>(A.fq, fc, al2, ial2, x, y, lx, ly, lm1, lm2, lnx, lny, l0, gg);              \
+        break;
+                MHLP_PC_CASES(MHLP_STKG_PANEL)
+#undef MHLP_STKG_PANEL
+            default:
+                stkg_panel_fp64<KQ_NP>(A.fq, fc, al2, ial2, x, y, lx, ly, lm1, lm2, lnx, lny, l0, gg);
             }
+            g11 = gg[0];
+            g12 = gg[1];
+            g21 = gg[2];
+            g22 = gg[3];
         }
     }
     if (!valid) return;
@@ -3213,6 +3277,26 @@ static mhlp_status far_resident_blocks(int *out)
     return MHLP_OK;
 }
 
+/* The (wave of 64 targets, panel) class table of the far-field tiles and the
+   fine pieces' scales at the plan's alpha (built on the stream after the near
+   lists, which it reads); the fused evaluation, the gradients and the
+   stresslet kernels read it. */
+static mhlp_status far_class_setup(mhlp_plan *P, hipStream_t st)
+{
+    const int64_t M = P->M, Np = P->g->Np;
+    const int64_t TB = (M + FT_THREADS - 1) / FT_THREADS;
+    TRY(dalloc(&P->wcls, TB * (FT_THREADS / 64) * Np));
+    double fq[2 * KQ_NP];
+    fine_scales(P->alpha, fq);
+    TRY(dalloc(&P->fqd, 2 * KQ_NP));
+    HIPCHECK(hipMemcpyAsync(P->fqd, fq, sizeof(fq), hipMemcpyHostToDevice, st)); /* fq lives until the sync below */
+    far_class_kernel<<<(unsigned)TB, FT_THREADS, 0, st>>>(P->tx, P->ty, M, P->g->soa, P->g->soa + P->g->N, Np,
+                                                          P->alpha, P->near_ptr, P->near_panel, P->wcls);
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(st)); /* later calls may come on other streams */
+    return MHLP_OK;
+}
+
 /* The FP64 far field's launch shape: one block per resident slot of the chip
    for each layer variant (at most one per unit), the partial slots a target
    block can need, their buffer, and the (wave, panel) class table (built on the
@@ -3247,16 +3331,7 @@ static mhlp_status far_stream_setup(mhlp_plan *P, hipStream_t st)
         P->sk_stride = (int32_t)(st_ % Np == 0 ? 1 : st_ % Np);
     }
     TRY(dalloc(&P->skpart, 2 * (int64_t)smax * M));
-    TRY(dalloc(&P->wcls, TB * (FT_THREADS / 64) * Np));
-    double fq[2 * KQ_NP];
-    fine_scales(P->alpha, fq);
-    TRY(dalloc(&P->fqd, 2 * KQ_NP));
-    HIPCHECK(hipMemcpyAsync(P->fqd, fq, sizeof(fq), hipMemcpyHostToDevice, st)); /* fq lives until the sync below */
-    far_class_kernel<<<(unsigned)TB, FT_THREADS, 0, st>>>(P->tx, P->ty, M, P->g->soa, P->g->soa + P->g->N, Np,
-                                                          P->alpha, P->near_ptr, P->near_panel, P->wcls);
-    HIPCHECK(hipGetLastError());
-    HIPCHECK(hipStreamSynchronize(st)); /* later calls may come on other streams */
-    return MHLP_OK;
+    return far_class_setup(P, st);
 }
 
 static mhlp_status plan_create_impl(const mhlp_geometry *g, double alpha, const double *tx, const double *ty,
@@ -3464,7 +3539,7 @@ static mhlp_status plan_create_impl(const mhlp_geometry *g, double alpha, const 
         P->fill_mismatch = mism;
     }
     (void)hipFree(cnt);
-    if (!stokes && (s = far_stream_setup(P, st))) {
+    if ((s = stokes ? far_class_setup(P, st) : far_stream_setup(P, st))) {
         mhlp_plan_destroy(P);
         return s;
     }
@@ -3905,6 +3980,8 @@ static mhlp_status launch_stokes(const mhlp_plan *P, const double *mu, double *u
     A.flux = P->stk_flux;
     A.gs = gs;
     A.jstride = jstride;
+    A.wcls = P->wcls;
+    A.fq = P->fqd;
     if (bie) stk_flux_kernel<<<1, 256, 0, st>>>(A, P->inv_len, P->stk_flux);
     if (P->sym_tiles) { /* on-surface: each unordered far pair once */
         const StkSymArgs S{A, P->sym_tiles, P->sym_p1, P->sym_p2, P->sym_bits, P->sym_nw};
@@ -3995,6 +4072,8 @@ extern "C" mhlp_status mhlp_stokes_eval_grad(const mhlp_plan *Pc, const double *
     A.pps = P->pps;
     A.part = P->part;
     A.g = g;
+    A.wcls = P->wcls;
+    A.fq = P->fqd;
     const unsigned nb = nblocks(A.M, FT_THREADS);
     if (P->nsplit <= 1) {
         far_stokes_grad_fp64<false><<<nb, FT_THREADS, 0, st>>>(A);

@@ -551,6 +551,29 @@ __device__ __forceinline__ void stk_far2(FarTab T, const FarConst &c, double al2
     }
 }
 
+/* stk_far2 for two sources of a panel whose pairs all fall in piece PC of the
+   plan's (wave, panel) class table: a fine piece (the closed forms from its
+   K0 and K1 fits), -1 (every z <= 2: the fitted smooth parts) or KQ_NP (the
+   per-pair selection of stk_far2) */
+template <int PC>
+__device__ __forceinline__ void stk_far2_pc(FarTab T, const FarConst &c, double qa, double qk, double al2,
+                                            double ial2, double r2a, double r2b, double *Aa, double *Ab)
+{
+    if constexpr (PC < 0) {
+        stk_small(T, c, al2, r2a, Aa);
+        stk_small(T, c, al2, r2b, Ab);
+    } else if constexpr (PC >= KQ_NP) {
+        stk_far2(T, c, al2, ial2, r2a, r2b, Aa, Ab);
+    } else {
+        K01 oa, ob; /* K1(z)/r; alpha K1/r for the closed forms */
+        k01_far2_fixed<true, true, PC>(T, c, qa, qk, r2a, r2b, oa, ob);
+        stk_closed(al2, ial2, r2a, oa.ri2, oa.k0, c.a * oa.ak1r, Aa);
+        stk_closed(al2, ial2, r2b, ob.ri2, ob.k0, c.a * ob.ak1r, Ab);
+    }
+    (void)qa;
+    (void)qk;
+}
+
 /* A_k and B_k = A_k'(r)/r of the stresslet (target gradient) for two
    sources of a far tile.  z > 2: B from K0, alpha K1/r and A,
      B1 = (alpha^2 K0/(2 pi) - 4 A1)/r^2, B2 = -(alpha^2 K0 + 2 alpha K1/r)/(pi r^4) - 6 A2/r^2,
@@ -600,6 +623,28 @@ __device__ __forceinline__ void stk_far2_ab(FarTab T, const FarConst &c, double 
         if (sa) stk_small_ab(T, c, al2, r2a, Aa, Ba);
         if (sb) stk_small_ab(T, c, al2, r2b, Ab, Bb);
     }
+}
+
+/* stk_far2_ab for two sources of a panel in piece PC of the class table (as
+   stk_far2_pc) */
+template <int PC>
+__device__ __forceinline__ void stk_far2_ab_pc(FarTab T, const FarConst &c, double qa, double qk, double al2,
+                                               double ial2, double r2a, double r2b, double *Aa, double *Ba,
+                                               double *Ab, double *Bb)
+{
+    if constexpr (PC < 0) {
+        stk_small_ab(T, c, al2, r2a, Aa, Ba);
+        stk_small_ab(T, c, al2, r2b, Ab, Bb);
+    } else if constexpr (PC >= KQ_NP) {
+        stk_far2_ab(T, c, al2, ial2, r2a, r2b, Aa, Ba, Ab, Bb);
+    } else {
+        K01 oa, ob;
+        k01_far2_fixed<true, true, PC>(T, c, qa, qk, r2a, r2b, oa, ob);
+        stk_closed_ab(al2, ial2, r2a, oa.ri2, oa.k0, c.a * oa.ak1r, Aa, Ba);
+        stk_closed_ab(al2, ial2, r2b, ob.ri2, ob.k0, c.a * ob.ak1r, Ab, Bb);
+    }
+    (void)qa;
+    (void)qk;
 }
 
 /* ---------------------------------------------------------------------- */
