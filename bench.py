@@ -51,24 +51,24 @@ FLOP_PER_PAIR_FP64 = {5.0: 101.8, 50.0: 83.4, 500.0: 80.5}
 VALU_PER_PAIR_FP64 = {5.0: 73.0, 50.0: 61.1, 500.0: 59.1}
 VALU_ISSUE_PER_S = 256 * 2.4e9 * 64
 # the gradient kernel (grad S and grad D of the same densities) evaluates K0
-# and K1(z)/r per pair as the potentials' tiles do (alpha carried by the staged
-# densities; e^{-z} by a table of 2^(-j/64) and a 6-term polynomial), then
-# 1/r^2, (x-y).d, (alpha K0 + 2 K1/r)/r^2 and the four accumulations: at
-# alpha = 500, where nearly every pair is on the z > 20 piece, the counters
-# read 41.2 v_fma (x2), 18.1 v_mul, 4.0 v_add, 2.0 v_rsq = 106.5 per pair
-FLOP_PER_PAIR_GRAD = 106
+# and K1(z)/r per pair as the fused evaluation does (the fine piece of the
+# plan's (wave, panel) class table; alpha carried by the staged densities),
+# then 1/r^2, (x-y).d, (alpha K0 + 2 K1/r)/r^2 and the four accumulations:
+# FLOP per pair from the FP64 VALU counters of each alpha (2 FMA + MUL + ADD +
+# TRANS; at alpha = 500 36.3 v_fma, 17.1 v_mul, 4.0 v_add, 2.0 v_rsq),
+# profiles/far_grad_fp64_starfish4096_grid512_valu_f64.txt
+FLOP_PER_PAIR_GRAD = {5.0: 116.8, 50.0: 98.5, 500.0: 95.6}
 # modified-Stokes double layer (2x2 stresslet per pair): K0 and K1(z)/r from
-# the three-piece fits, alpha K1/r, 1/r^2, the closed forms of alpha^2 T1,
-# alpha^4 T2, alpha^2 T3 (App. B) and the contraction D_ij w mu_j into two
-# accumulators: at alpha = 500 (the z > 20 piece) the counters read 50.2 v_fma
-# (x2), 35.1 v_mul, 6.0 v_add, 2.0 v_rsq = 143.6 per pair
-FLOP_PER_PAIR_STOKES = 143
+# the class table's fine piece, alpha K1/r, 1/r^2, the closed forms of
+# alpha^2 T1, alpha^4 T2, alpha^2 T3 (App. B) and the contraction D_ij w mu_j
+# into two accumulators (z <= 2: the fitted smooth parts with log z): counted
+# per alpha (at alpha = 500 45.3 v_fma, 34.1 v_mul, 6.0 v_add, 2.0 v_rsq)
+FLOP_PER_PAIR_STOKES = {5.0: 158.7, 50.0: 135.8, 500.0: 132.7}
 # target gradient of the stresslet double layer (velocity gradient, 4 outputs):
 # the same K0, K1(z)/r, 1/r^2 and A_k, B_k = A_k'(r)/r from K0 and A_k, and the
-# contraction d_l D_ij w mu_j into four accumulators: at alpha = 500 (the
-# z > 20 piece) the counters read 67.3 v_fma (x2), 51.2 v_mul, 11.0 v_add,
-# 2.0 v_rsq = 198.7 per pair
-FLOP_PER_PAIR_STOKES_GRAD = 198
+# contraction d_l D_ij w mu_j into four accumulators: counted per alpha (at
+# alpha = 500 64.3 v_fma, 49.2 v_mul, 9.0 v_add, 2.0 v_rsq)
+FLOP_PER_PAIR_STOKES_GRAD = {5.0: 228.4, 50.0: 192.3, 500.0: 188.8}
 # launch shapes (far-field source splits) chosen by the autotuner on MI355X for
 # the plans of this benchmark
 TUNED_SPLITS = os.path.join(ROOT, "paper_1908_07392_amd", "tuning", "mi355x_far_splits.json")
@@ -534,7 +534,7 @@ def bench_grad(mhlp, plans, gdev, cfg, args, torch):
     (builds the 64 gradient weights per near pair) and the steady launch."""
     print("# gradient leg", file=sys.stderr, flush=True)
     from paper_1908_07392_amd import autotune
-    res = {"flop_per_pair": FLOP_PER_PAIR_GRAD}
+    res = {"flop_per_pair_by_alpha": {f"alpha={a:g}": f for a, f in FLOP_PER_PAIR_GRAD.items()}}
     launch = {}
     for a in cfg["alphas"]:
         on, off = plans[a]
@@ -558,7 +558,9 @@ def bench_grad(mhlp, plans, gdev, cfg, args, torch):
                                   "nsplit": r["nsplit"], "near_pairs": off.n_near_pairs}
     ms = float(np.mean([v["launch_ms"] for v in launch.values()]))
     pairs = off.n_targets * off.n_sources
-    tf = pairs * FLOP_PER_PAIR_GRAD / (ms * 1e-3) / 1e12
+    # the counted FLOPs of every alpha's launch over their summed durations
+    tf = pairs * sum(FLOP_PER_PAIR_GRAD[a] for a in cfg["alphas"]) / (
+        sum(launch[f"alpha={a:g}"]["launch_ms"] for a in cfg["alphas"]) * 1e-3) / 1e12
     res.update({"by_alpha": launch, "pairs_per_launch": pairs, "launch_ms": round(ms, 4),
                 "gpair_per_s": round(pairs / (ms * 1e-3) / 1e9, 3), "achieved_tflops": round(tf, 3),
                 "frac_of_fp64_peak": round(tf / FP64_PEAK_TFLOPS, 4),
@@ -577,7 +579,7 @@ def bench_stokes(mhlp, wl, cfg, G, tx, ty, t, args, torch):
     from paper_1908_07392_amd import autotune
     g = cfg["geom"]
     sources = [(2.2 + 0.4j, (1.0, 0.3)), (-0.5 - 2.1j, (-0.4, 0.8))]
-    res = {"flop_per_pair": FLOP_PER_PAIR_STOKES}
+    res = {"flop_per_pair_by_alpha": {f"alpha={a:g}": f for a, f in FLOP_PER_PAIR_STOKES.items()}}
     by = {}
     for a in cfg["alphas"]:
         gb = np.zeros((2, g.n_nodes))
@@ -636,13 +638,16 @@ def bench_stokes(mhlp, wl, cfg, G, tx, ty, t, args, torch):
     ms = float(np.mean([v["eval_launch_ms"] for v in by.values()]))
     gms = float(np.mean([v["grad_launch_ms"] for v in by.values()]))
     pairs = off.n_targets * off.n_sources
-    tf = pairs * FLOP_PER_PAIR_STOKES / (ms * 1e-3) / 1e12
-    gtf = pairs * FLOP_PER_PAIR_STOKES_GRAD / (gms * 1e-3) / 1e12
+    al = [float(k.split("=")[1]) for k in by]
+    tf = pairs * sum(FLOP_PER_PAIR_STOKES[a] for a in al) / (sum(v["eval_launch_ms"] for v in by.values()) * 1e-3) / 1e12
+    gtf = pairs * sum(FLOP_PER_PAIR_STOKES_GRAD[a] for a in al) / (
+        sum(v["grad_launch_ms"] for v in by.values()) * 1e-3) / 1e12
     res.update({"by_alpha": by, "pairs_per_launch": pairs, "eval_launch_ms": round(ms, 4),
                 "eval_gpair_per_s": round(pairs / (ms * 1e-3) / 1e9, 3), "achieved_tflops": round(tf, 3),
                 "frac_of_fp64_peak": round(tf / FP64_PEAK_TFLOPS, 4),
                 "kernel": "far_stokes_fp64 (+ stk_finalize when split)",
-                "grad": {"flop_per_pair": FLOP_PER_PAIR_STOKES_GRAD, "launch_ms": round(gms, 4),
+                "grad": {"flop_per_pair_by_alpha": {f"alpha={a:g}": f for a, f in FLOP_PER_PAIR_STOKES_GRAD.items()},
+                         "launch_ms": round(gms, 4),
                          "gpair_per_s": round(pairs / (gms * 1e-3) / 1e9, 3), "achieved_tflops": round(gtf, 3),
                          "frac_of_fp64_peak": round(gtf / FP64_PEAK_TFLOPS, 4),
                          "kernel": "far_stokes_grad_fp64 (+ stkg_finalize when split)"}})
