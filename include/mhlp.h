@@ -195,8 +195,10 @@ mhlp_status mhlp_apply_bie_operator(const mhlp_plan *onsurf, const double *mu, d
      D[mu]_i(x) = int_Gamma D_ij(x,y) mu_j(y) dS_y,  D_ij = -T_jik(x,y) n_k(y),
      T_ijk = alpha^2 T1 (d_jk r_i + d_ik r_j + d_ij r_k) + alpha^4 T2 r_i r_j r_k
              + alpha^2 T3 d_ik r_j,   r = x - y, n into the domain.
-   A stokes plan has the near lists of mhlp_plan_create and 64 stresslet
-   correction weights per near pair (2x2 blocks on the panel's 16 nodes); it
+   A stokes plan has the near lists of mhlp_plan_create, 64 stresslet
+   correction weights per near pair (2x2 blocks on the panel's 16 nodes) and,
+   like a scalar plan, one byte per (64 targets, panel) naming the far-field
+   fit that serves those pairs; it
    serves only the mhlp_stokes_* calls (the scalar calls reject it and vice
    versa).  Densities and outputs are component-major: mu [2][N] (mu_1 at
    mu[0..N), mu_2 at mu[N..2N)), u [2][M].  FP64 throughout.
