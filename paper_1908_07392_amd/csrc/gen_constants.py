@@ -22,7 +22,8 @@ Device K0/K1 (modified Bessel functions of the second kind):
   fit, not from K0's derivative), degree 11 / 9 and 10 / 8.
 * z > 2, eight finer pieces split at z = 3, 4.5, 7, 12, 20, 40, 100 and the
   seven pieces spanning two neighbours (KQ0_k for K0, KQ1_k for K1, each a fit
-  of its own), degrees 12 down to 6 from the 1.2e-16 requirement on the value.
+  of its own), degrees 12 down to 6 from the 1.2e-16 requirement on the value;
+  KQF0 / KQF1 the same pieces in FP32 (degrees 5 down to 2, about 1e-7).
 """
 import os
 
@@ -188,6 +189,22 @@ def check_piece(coef, nu, lo, hi, with_derivative):
     return e0, e1
 
 
+def check_piece32(coef, nu, lo, hi):
+    """max rel. error of a fine-piece fit evaluated in float32 over its v range"""
+    vs = np.linspace(-1.0, 1.0, 301)
+    cc = np.array([float(c) for c in coef], dtype=np.float32)
+    p = np.zeros_like(vs, dtype=np.float32)
+    for a in cc[::-1]:
+        p = (p * vs.astype(np.float32) + a).astype(np.float32)
+    worst = 0.0
+    for v, pv in zip(vs, p):
+        u = (mp.mpf(v) * (mp.mpf(hi) - lo) + lo + hi) / 2
+        if u <= -1:
+            u = mp.mpf(-1) + mp.mpf("1e-6")
+        worst = max(worst, abs(float(pv) / float(large_fn(nu)(u)) - 1))
+    return worst
+
+
 def fmt(name, vals, ctype="double"):
     suffix = "" if ctype == "double" else "f"
     body = ",\n    ".join(f"{mp.nstr(v, 20, min_fixed=-1, max_fixed=-1)}{suffix}" if ctype == "double" else
@@ -305,6 +322,23 @@ def main():
             out.append(f"/* e^z sqrt(z) K{nu}(z) on u in [{float(lo):.6f}, {float(hi):.6f}] (u = 4/z - 1), piece {k} of the"
                        f" fine set, as a polynomial in v = (2u - lo - hi)/(hi - lo) */")
             out.append(fmt(name, c))
+    # FP32 fits of the same pieces for the mixed-precision far field, degrees
+    # from about 1e-7 relative error in float32 evaluation (the whole-range
+    # FP32 fits reach 8.7e-8 / 6.6e-8 at degree 9), zero padded to 6 coefficients
+    d0f = [4, 4, 3, 3, 3, 2, 2, 2, 5, 5, 4, 3, 3, 3, 3]
+    d1f = [4, 3, 3, 3, 3, 3, 2, 2, 4, 4, 4, 4, 3, 3, 2]
+    for nu, dd in ((0, d0f), (1, d1f)):
+        rows = []
+        for k, (a, b) in enumerate(spans):
+            hi = 4 / bnd[a] - 1
+            lo = 4 / bnd[b] - 1 if bnd[b] != mp.inf else mp.mpf(-1)
+            c = cheb_fit_mono(large_fn(nu), dd[k], lo, hi)
+            report.append((f"KQF{nu}_{k}", check_piece32(c, nu, lo, hi), 0.0))
+            rows.append([float(x) for x in c] + [0.0] * (6 - len(c)))
+        out.append(f"/* FP32 e^z sqrt(z) K{nu}(z) on the fine pieces (as KQ{nu}_k), degrees "
+                   + ", ".join(str(d) for d in dd) + ", zero padded */")
+        body = ",\n    ".join("{" + ", ".join(f"{v:.9e}f" for v in r) + "}" for r in rows)
+        out.append(f"static constexpr float KQF{nu}[15][6] = {{\n    {body}}};\n")
     out.append("/* fine pieces: the z boundaries, and the u range of each piece (0..7 single, 8..14 double) */")
     out.append(fmt("KQ_B", bnd[:8]))
     out.append(fmt("KQ_ULO", ulo_all))

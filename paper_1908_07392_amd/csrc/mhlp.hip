@@ -522,8 +522,8 @@ struct FarArgs {
     int32_t skP, skS;
     int32_t skStride; /* unit j of a target block is panel (j skStride) mod Np */
     double *skps, *skpd;
-    const uint8_t *wcls;
-    const double *fq; /* [2][KQ_NP] scales of the fine pieces at the plan's alpha (fine_scales) */
+    const uint8_t *wcls = nullptr;
+    const double *fq = nullptr; /* [2][KQ_NP] scales of the fine pieces at the plan's alpha (fine_scales) */
 };
 
 
@@ -1247,6 +1247,28 @@ __global__ __launch_bounds__(256) void far_class_kernel(const double *__restrict
 /* x - y formed exactly in FP64 then rounded, FP32 partial sums over each     */
 /* 16-node panel accumulated in FP64; corrections and identity term in FP64. */
 /* ------------------------------------------------------------------------ */
+/* the classes -1 .. KQ_NP - 1 of the plan's (wave, panel) table, for a switch */
+#define MHLP_PC_CASES(X) X(-1) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14)
+static_assert(KQ_NP == 15, "MHLP_PC_CASES lists the fine pieces");
+
+/* the 16 sources of one LDS panel (offset l0) against the lane's target in
+   FP32, in piece PC of the plan's class table (k01_fp32_pc) */
+template <bool SLP, bool DLP, int PC>
+__device__ __forceinline__ void mixed_panel(double x, double y, const double *lx, const double *ly, const float *lq,
+                                            const float *ldx, const float *ldy, int l0, float alpha, float a2q,
+                                            float a4, float &ps, float &pd)
+{
+#pragma unroll 4
+    for (int s = 0; s < 16; ++s) {
+        const int l = l0 + s;
+        const float ex = (float)(x - lx[l]), ey = (float)(y - ly[l]);
+        const float r2 = fmaf(ex, ex, ey * ey);
+        const K01f o = k01_fp32_pc<SLP, DLP, PC>(r2, alpha, a2q, a4);
+        if (SLP) ps = fmaf(o.k0, lq[l], ps);
+        if (DLP) pd = fmaf(o.ak1r, fmaf(ex, ldx[l], ey * ldy[l]), pd);
+    }
+}
+
 template <bool SLP, bool DLP, bool SPLIT>
 __global__ __launch_bounds__(FT_THREADS) void far_eval_mixed(FarArgs A)
 {
@@ -1267,6 +1289,8 @@ __global__ __launch_bounds__(FT_THREADS) void far_eval_mixed(FarArgs A)
     }
     int32_t nxt = (k < kend) ? A.npan[k] : INT_MAX;
     const float alpha = (float)A.alpha, a2q = 0.25f * alpha * alpha, a4 = 4.0f / alpha;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint8_t *cls = A.wcls ? A.wcls + ((int64_t)blockIdx.x * (FT_THREADS / 64) + wv) * A.Np : nullptr;
     double accs = 0.0, accd = 0.0;
     for (int64_t base = 16 * pb; base < 16 * pe; base += FT_SRC) {
         __syncthreads();
@@ -1292,14 +1316,16 @@ __global__ __launch_bounds__(FT_THREADS) void far_eval_mixed(FarArgs A)
                 continue;
             }
             float ps = 0.0f, pd = 0.0f;
-#pragma unroll 4
-            for (int s = 0; s < 16; ++s) {
-                const int l = pl * 16 + s;
-                const float ex = (float)(x - lx[l]), ey = (float)(y - ly[l]);
-                const float r2 = fmaf(ex, ex, ey * ey);
-                const K01f o = k01_fp32<SLP, DLP>(r2, alpha, a2q, a4);
-                if (SLP) ps = fmaf(o.k0, lq[l], ps);
-                if (DLP) pd = fmaf(o.ak1r, fmaf(ex, ldx[l], ey * ldy[l]), pd);
+            const int pc = cls ? (cls[p0 + pl] & 0x7f) - 1 : KQ_NP;
+            switch (pc) {
+#define MHLP_MIXED_PANEL(PCV)                                                                              \
+    case PCV:                                                                                              \
+        mixed_panel<SLP, DLP, PCV>(x, y, lx, ly, lq, ldx, ldy, pl * 16, alpha, a2q, a4, ps, pd);           \
+        break;
+                MHLP_PC_CASES(MHLP_MIXED_PANEL)
+#undef MHLP_MIXED_PANEL
+            default:
+                mixed_panel<SLP, DLP, KQ_NP>(x, y, lx, ly, lq, ldx, ldy, pl * 16, alpha, a2q, a4, ps, pd);
             }
             if (SLP) accs += (double)ps;
             if (DLP) accd += (double)pd;
@@ -1652,10 +1678,6 @@ __global__ __launch_bounds__(256) void stk_flux_kernel(StkArgs A, double inv_len
     }
     if (threadIdx.x == 0) flux[0] = red[0] * inv_len;
 }
-
-/* the classes -1 .. KQ_NP - 1 of the plan's (wave, panel) table, for a switch */
-#define MHLP_PC_CASES(X) X(-1) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14)
-static_assert(KQ_NP == 15, "MHLP_PC_CASES lists the fine pieces");
 
 /* the 16 sources of one LDS panel (offset l0) against the lane's target for
    the stresslet double layer, in piece PC of the class table */

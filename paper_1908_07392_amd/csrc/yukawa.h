@@ -123,6 +123,8 @@ static_assert(kq_sizes<0>(KQ0_0, KQ1_0) && kq_sizes<1>(KQ0_1, KQ1_1) && kq_sizes
                   kq_sizes<9>(KQ0_9, KQ1_9) && kq_sizes<10>(KQ0_10, KQ1_10) && kq_sizes<11>(KQ0_11, KQ1_11) &&
                   kq_sizes<12>(KQ0_12, KQ1_12) && kq_sizes<13>(KQ0_13, KQ1_13) && kq_sizes<14>(KQ0_14, KQ1_14),
               "fine-piece coefficient counts differ from the generated tables");
+static_assert(sizeof(KQF0[0]) == 6 * sizeof(float) && sizeof(KQF1[0]) == 6 * sizeof(float),
+              "FP32 fine pieces are padded to 6 coefficients");
 static_assert(sizeof(KP0M) == 12 * sizeof(double) && sizeof(KP0X) == 10 * sizeof(double) &&
                   sizeof(KP1M) == 11 * sizeof(double) && sizeof(KP1X) == 9 * sizeof(double),
               "middle and far piece lengths differ from the generated tables");
@@ -680,6 +682,68 @@ __device__ __forceinline__ K01f k01_fp32(float r2, float a, float a2q, float a4)
         if (DLP) o.ak1r = a * e * horner(KLF1, u) * ri;
     }
     return o;
+}
+
+/* The FP32 fits of the fine pieces (coefficient counts of KQF0 / KQF1) for
+   the mixed-precision far field on the plan's (wave, panel) class table:
+   PC a fine piece (z > 2: e^{-z} z^{-1/2} times the piece's fit in
+   v = (2u - ulo - uhi)/(uhi - ulo), u = 4/z - 1), -1 (every pair z <= 2: the
+   series form), KQ_NP (the per-pair choice of k01_fp32). */
+constexpr int KQF_N0[KQ_NP] = {5, 5, 4, 4, 4, 3, 3, 3, 6, 6, 5, 4, 4, 4, 4};
+constexpr int KQF_N1[KQ_NP] = {5, 4, 4, 4, 4, 4, 3, 3, 5, 5, 5, 5, 4, 4, 3};
+
+constexpr bool kqf_counts_ok()
+{
+    for (int k = 0; k < KQ_NP; ++k) {
+        if (KQF0[k][KQF_N0[k] - 1] == 0.0f || KQF1[k][KQF_N1[k] - 1] == 0.0f) return false;
+        for (int i = KQF_N0[k]; i < 6; ++i)
+            if (KQF0[k][i] != 0.0f) return false;
+        for (int i = KQF_N1[k]; i < 6; ++i)
+            if (KQF1[k][i] != 0.0f) return false;
+    }
+    return true;
+}
+static_assert(kqf_counts_ok(), "KQF_N0 / KQF_N1 differ from the generated FP32 fine pieces");
+
+template <int N>
+__device__ __forceinline__ float horner_f(const float *c, float x)
+{
+    float v = c[N - 1];
+#pragma unroll
+    for (int i = N - 2; i >= 0; --i) v = fmaf(v, x, c[i]);
+    return v;
+}
+
+template <bool SLP, bool DLP, int PC>
+__device__ __forceinline__ K01f k01_fp32_pc(float r2, float a, float a2q, float a4)
+{
+    if constexpr (PC < 0 || PC >= KQ_NP) {
+        if constexpr (PC < 0) {
+            K01f o{0.0f, 0.0f};
+            const float q = a2q * r2;
+            const float lq = __logf(q);
+            if (SLP) o.k0 = fmaf(-0.5f * lq, horner(KSF_I0, q), horner(KSF_R0, q));
+            if (DLP) {
+                const float t = fmaf(0.5f * lq, horner(KSF_I1Z, q), -0.25f * horner(KSF_R1, q));
+                o.ak1r = fmaf(4.0f * a2q, t, __frcp_rn(r2));
+            }
+            return o;
+        } else {
+            return k01_fp32<SLP, DLP>(r2, a, a2q, a4);
+        }
+    } else {
+        /* v = (4/alpha) w ri + b, w = 2/(uhi - ulo), b = -(2 + ulo + uhi)/(uhi - ulo) */
+        constexpr float w = (float)(2.0 / (KQ_UHI[PC] - KQ_ULO[PC]));
+        constexpr float b = (float)((-2.0 - KQ_ULO[PC] - KQ_UHI[PC]) / (KQ_UHI[PC] - KQ_ULO[PC]));
+        K01f o{0.0f, 0.0f};
+        const float ri = __frsqrt_rn(r2);
+        const float z = a * (r2 * ri);
+        const float v = fmaf(a4 * w, ri, b);
+        const float e = __expf(-z) * __frsqrt_rn(z);
+        if (SLP) o.k0 = e * horner_f<KQF_N0[PC]>(KQF0[PC], v);
+        if (DLP) o.ak1r = a * e * horner_f<KQF_N1[PC]>(KQF1[PC], v) * ri;
+        return o;
+    }
 }
 
 /* ---------------------------------------------------------------------- */

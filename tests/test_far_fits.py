@@ -86,6 +86,32 @@ def test_fine_piece_matches_scaled_bessel(name, nu, urange, der):
     test_piece_matches_scaled_bessel(name, nu, urange, der)
 
 
+def table2d(name, rows, cols):
+    text = open(HEADER).read()
+    m = re.search(r"static constexpr float " + name + r"\[(\d+)\]\[(\d+)\] = \{(.*?)\};\n", text, re.S)
+    assert (int(m.group(1)), int(m.group(2))) == (rows, cols)
+    vals = [float(x.strip().rstrip("f")) for x in m.group(3).replace("{", " ").replace("}", " ").split(",") if x.strip()]
+    return np.array(vals, dtype=np.float32).reshape(rows, cols)
+
+
+@pytest.mark.parametrize("nu", [0, 1])
+def test_fp32_fine_pieces_match_scaled_bessel(nu):
+    """the FP32 fits of the fifteen fine pieces (mixed-precision far field),
+    evaluated in float32 by Horner: within 1.2e-7 of e^z sqrt(z) K_nu(z)"""
+    ulo, uhi = table("KQ_ULO"), table("KQ_UHI")
+    c = table2d(f"KQF{nu}", 15, 6)
+    for k in range(15):
+        lo, hi = ulo[k], uhi[k]
+        u = np.linspace(lo, hi, 801)[1:] if lo == -1.0 else np.linspace(lo, hi, 801)
+        v = ((2 * u - lo - hi) / (hi - lo)).astype(np.float32)
+        p = np.zeros_like(v)
+        for a in c[k][::-1]:
+            p = (p * v + a).astype(np.float32)
+        z = 4.0 / (u + 1.0)
+        ref = np.sqrt(z) * sp.kve(nu, z)
+        assert np.max(np.abs(p.astype(np.float64) / ref - 1)) < 1.2e-7, (nu, k)
+
+
 def test_fine_pieces_tile_the_axis():
     """single pieces k cover z in (B_k, B_k+1], the double pieces (B_s, B_s+2]"""
     b = table("KQ_B")
